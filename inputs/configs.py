@@ -1,0 +1,184 @@
+"""The workloads: seeded synthetic problems with the shapes of the method's test cases.
+
+Sizes follow the 1D first-order ODE, the multilevel 2D Poisson problems, the
+batched ragged Poisson instances and the parameterised warm-start families.
+Every random draw is seeded here; nothing in this module evaluates the method.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .problems import ProblemSpec, grid_points
+from . import families as fam
+
+
+# ---------------------------------------------------------------- single problems
+
+def ode1d() -> ProblemSpec:
+    """du/dx = cos(15x) on [-2pi, 2pi], u(0)=0; 20 subdomains, width ratio 1.3, K=64, 2000 points."""
+    return ProblemSpec(
+        name="ode1d", dim=1, op="d1", ansatz="tanh_origin", ansatz_omega=15.0,
+        lo=(-2 * math.pi,), hi=(2 * math.pi,), n_points=(2000,), levels=((20,),),
+        delta=1.3, K=64, w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=0,
+        meta={"family": "ode_cos", "omega": 15.0, "n_test": (1000,)},
+    )
+
+
+def poisson3l() -> ProblemSpec:
+    """-Lap u = f on [0,1]^2, u = sum_{k in 1,4,16} sin(k pi x) sin(k pi y)/k; levels 1,4,16; K=96; 400^2."""
+    return ProblemSpec(
+        name="poisson3l", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=16.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(400, 400),
+        levels=((1, 1), (4, 4), (16, 16)), delta=2.9, K=96,
+        w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=0,
+        meta={"family": "sines", "freqs": (1.0, 4.0, 16.0), "amps": (1.0, 0.25, 1.0 / 16.0),
+              "n_test": (480, 480), "n_check": (128, 128)},
+    )
+
+
+def poisson5l() -> ProblemSpec:
+    """u = sum_{k=1..5} sin(2^k pi x) sin(2^k pi y); levels 1,8,16,32,64; K=256; 1024^2 points."""
+    return ProblemSpec(
+        name="poisson5l", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=32.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(1024, 1024),
+        levels=((1, 1), (8, 8), (16, 16), (32, 32), (64, 64)), delta=2.9, K=256,
+        w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=0,
+        meta={"family": "sines", "freqs": tuple(float(2 ** k) for k in range(1, 6)),
+              "amps": (1.0,) * 5, "n_test": (1228, 1228), "n_check": (256, 256)},
+    )
+
+
+def laplace_baseline(levels=((16, 16),), seed=0) -> ProblemSpec:
+    """The method's 2D multiscale Laplace baseline: n_omega=4 (4,8,12,16), K=16, 80^2 points, R=1."""
+    a = 1.0 / math.sqrt(2.0)          # LeCun uniform bound R*sqrt(1/dim(z)) with R=1, dim(z)=2
+    return ProblemSpec(
+        name="laplace_baseline", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=16.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(80, 80), levels=tuple(levels), delta=2.9, K=16,
+        w_range=(-a, a), b_range=(-a, a), seed=seed,
+        meta={"family": "sines", "freqs": (4.0, 8.0, 12.0, 16.0), "amps": (0.25,) * 4,
+              "n_test": (96, 96)},
+    )
+
+
+# ---------------------------------------------------------------- small parity cases
+
+def tiny1d(K=4, J=3, n=50, delta=1.5, seed=1) -> ProblemSpec:
+    return ProblemSpec(
+        name="tiny1d", dim=1, op="d1", ansatz="tanh_origin", ansatz_omega=3.0,
+        lo=(-1.0,), hi=(1.0,), n_points=(n,), levels=((J,),), delta=delta, K=K,
+        w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=seed,
+        meta={"family": "ode_cos", "omega": 3.0, "n_test": (97,)},
+    )
+
+
+def small1d_multilevel(seed=2) -> ProblemSpec:
+    return ProblemSpec(
+        name="small1d_ml", dim=1, op="d1", ansatz="tanh_origin", ansatz_omega=6.0,
+        lo=(-2.0,), hi=(3.0,), n_points=(301,), levels=((1,), (4,), (9,)), delta=2.2, K=12,
+        w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=seed,
+        meta={"family": "ode_cos", "omega": 6.0, "n_test": (333,)},
+    )
+
+
+def small2d(seed=4) -> ProblemSpec:
+    """Several tiles and ragged tails: 3 levels, non-square grid, K not a multiple of 16."""
+    return ProblemSpec(
+        name="small2d", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=6.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.5), n_points=(61, 83), levels=((1, 1), (2, 3), (5, 6)),
+        delta=2.9, K=20, w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=seed,
+        meta={"family": "sines", "freqs": (1.0, 3.0), "amps": (1.0, 0.3), "n_test": (71, 77)},
+    )
+
+
+def medium2d(seed=5) -> ProblemSpec:
+    """A multilevel case big enough to span many workgroups, small enough for the oracle."""
+    return ProblemSpec(
+        name="medium2d", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=8.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(150, 150), levels=((1, 1), (4, 4), (8, 8)),
+        delta=2.9, K=48, w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=seed,
+        meta={"family": "sines", "freqs": (1.0, 4.0, 8.0), "amps": (1.0, 0.25, 0.125),
+              "n_test": (180, 180), "n_check": (64, 64)},
+    )
+
+
+# ---------------------------------------------------------------- problem data
+
+def forcing(spec: ProblemSpec, pts=None) -> np.ndarray:
+    pts = grid_points(spec) if pts is None else pts
+    m = spec.meta
+    if m["family"] == "ode_cos":
+        return fam.ode_cos_forcing(pts, m["omega"])
+    if m["family"] == "ode_modes":
+        return fam.ode_modes_forcing(pts, m["freqs"], m["amps"])
+    if m["family"] == "sines":
+        return fam.sines_forcing(pts, m["freqs"], m["amps"])
+    raise ValueError(m["family"])
+
+
+def exact(spec: ProblemSpec, pts) -> np.ndarray:
+    m = spec.meta
+    if m["family"] == "ode_cos":
+        return fam.ode_cos_exact(pts, m["omega"])
+    if m["family"] == "ode_modes":
+        return fam.ode_modes_exact(pts, m["freqs"], m["amps"])
+    if m["family"] == "sines":
+        return fam.sines_exact(pts, m["freqs"], m["amps"])
+    raise ValueError(m["family"])
+
+
+def test_grid(spec: ProblemSpec, which="n_test") -> np.ndarray:
+    return grid_points(spec, spec.meta[which])
+
+
+# ---------------------------------------------------------------- batched ragged instances
+
+def batch_instances(n=512, seed=3, n_rhs=8):
+    """Ragged 2D Poisson instances: J~U{4..24} square, K~U{64..128}, 20..60 grid points per
+    subdomain cell, 3 integer modes k~U{1..20}, per-RHS amplitudes N(0,1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs, amps = [], []
+    for i in range(n):
+        J = int(rng.integers(4, 25))
+        K = int(rng.integers(64, 129))
+        p = float(rng.uniform(20.0, 60.0))
+        g = int(round(J * math.sqrt(p)))
+        ks = tuple(float(v) for v in rng.integers(1, 21, size=3))
+        A = rng.standard_normal((n_rhs, 3))
+        specs.append(ProblemSpec(
+            name=f"batch{i}", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=max(ks),
+            lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(g, g), levels=((J, J),), delta=2.9, K=K,
+            w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=10_000 + i,
+            meta={"family": "sines", "freqs": ks, "amps": tuple(A[0]), "rhs_amps": A},
+        ))
+        amps.append(A)
+    return specs, amps
+
+
+def batch_forcing(spec: ProblemSpec) -> np.ndarray:
+    """[n_rhs, N] forcing for every right-hand side of one batched instance."""
+    pts = grid_points(spec)
+    A = spec.meta["rhs_amps"]
+    return np.stack([fam.sines_forcing(pts, spec.meta["freqs"], A[r]) for r in range(A.shape[0])])
+
+
+# ---------------------------------------------------------------- warm-start families
+
+def warm_family_1d(omega: float, coeffs) -> ProblemSpec:
+    """du/dx = sum_{m=1..3} c_m cos(m omega x/3) on [-2pi,2pi], ansatz tanh(omega x); J=64, K=32."""
+    freqs = tuple(m * omega / 3.0 for m in (1, 2, 3))
+    return ProblemSpec(
+        name="warm1d", dim=1, op="d1", ansatz="tanh_origin", ansatz_omega=float(omega),
+        lo=(-2 * math.pi,), hi=(2 * math.pi,), n_points=(6000,), levels=((64,),), delta=2.9,
+        K=32, w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=0,
+        meta={"family": "ode_modes", "freqs": freqs, "amps": tuple(coeffs), "n_test": (1000,)},
+    )
+
+
+def warm_draws(n, seed):
+    """Problem parameters (omega ~ U[5,50], c ~ N(0,1)^3) for n instances."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    om = rng.uniform(5.0, 50.0, size=n)
+    c = rng.standard_normal((n, 3))
+    return om, c

@@ -1,0 +1,49 @@
+"""Manufactured problems: exact solutions and forcing terms.
+
+These are problem statements, not the method: the caller evaluates the forcing
+term f at the collocation points and hands the values to the solver.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def ode_cos_exact(x: np.ndarray, omega: float = 15.0) -> np.ndarray:
+    """du/dx = cos(omega x), u(0) = 0  =>  u = sin(omega x)/omega."""
+    return np.sin(omega * x[..., 0]) / omega
+
+
+def ode_cos_forcing(x: np.ndarray, omega: float = 15.0) -> np.ndarray:
+    return np.cos(omega * x[..., 0])
+
+
+def ode_modes_forcing(x: np.ndarray, freqs, amps) -> np.ndarray:
+    """du/dx = sum_m c_m cos(w_m x)."""
+    s = np.zeros(x.shape[0])
+    for w, c in zip(freqs, amps):
+        s = s + c * np.cos(w * x[:, 0])
+    return s
+
+
+def ode_modes_exact(x: np.ndarray, freqs, amps) -> np.ndarray:
+    s = np.zeros(x.shape[0])
+    for w, c in zip(freqs, amps):
+        s = s + c * np.sin(w * x[:, 0]) / w
+    return s
+
+
+def sines_exact(x: np.ndarray, freqs, amps) -> np.ndarray:
+    """u = sum_m a_m sin(k_m pi x) sin(k_m pi y)  (Sec. 4.3, multiscale Laplace family)."""
+    u = np.zeros(x.shape[0])
+    for k, a in zip(freqs, amps):
+        u = u + a * np.sin(k * np.pi * x[:, 0]) * np.sin(k * np.pi * x[:, 1])
+    return u
+
+
+def sines_forcing(x: np.ndarray, freqs, amps) -> np.ndarray:
+    """f = -Laplace(u) = sum_m a_m 2 (k_m pi)^2 sin(k_m pi x) sin(k_m pi y)."""
+    f = np.zeros(x.shape[0])
+    for k, a in zip(freqs, amps):
+        kp = k * np.pi
+        f = f + a * 2.0 * kp * kp * np.sin(kp * x[:, 0]) * np.sin(kp * x[:, 1])
+    return f

@@ -1,0 +1,94 @@
+"""Problem specifications and the seeded draws of the random feature parameters.
+
+A ProblemSpec fixes everything a caller decides before the method runs: the
+domain box, the regular collocation grid, the decomposition sizes per level,
+the width ratio, the number of random features per subdomain and the ranges
+and seed of their uniform initialisation (Sec. 4.1, "Neural network
+architecture and weight initialisation").
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class ProblemSpec:
+    name: str
+    dim: int                      # 1 or 2
+    op: str                       # "d1" (d/dx, dim 1) | "neg_laplace" (-Laplacian, dim 2) | "identity"
+    ansatz: str                   # "none" | "tanh_origin" | "tanh_box"
+    ansatz_omega: float           # sharpness of the hard-constraint factor
+    lo: Tuple[float, ...]
+    hi: Tuple[float, ...]
+    n_points: Tuple[int, ...]     # regular grid, endpoints included, per axis
+    levels: Tuple[Tuple[int, ...], ...]   # subdomains per axis, per level (coarse first)
+    delta: float                  # width ratio
+    K: int                        # random features per subdomain
+    w_range: Tuple[float, float] = (-1.0, 1.0)
+    b_range: Tuple[float, float] = (-1.0, 1.0)
+    seed: int = 0
+    meta: dict = field(default_factory=dict, compare=False, hash=False)
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.levels)
+
+    @property
+    def n_rows(self) -> int:
+        return int(np.prod(self.n_points))
+
+    def n_subdomains(self) -> int:
+        return int(sum(int(np.prod(J)) for J in self.levels))
+
+
+def n_phi(spec: ProblemSpec) -> int:
+    """Total number of random features over all levels (N_Phi = sum_l J_l K)."""
+    return spec.n_subdomains() * spec.K
+
+
+def feature_params(spec: ProblemSpec):
+    """Seeded uniform draws of the fixed hidden weights W [N_Phi, dim] and biases b [N_Phi].
+
+    Rows follow the global column order q (level, then subdomain j in x-major
+    order, then feature k).  W is drawn first, then b, from one PCG64 stream.
+    """
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    n = n_phi(spec)
+    W = rng.uniform(spec.w_range[0], spec.w_range[1], size=(n, spec.dim))
+    b = rng.uniform(spec.b_range[0], spec.b_range[1], size=n)
+    return np.ascontiguousarray(W, dtype=np.float64), np.ascontiguousarray(b, dtype=np.float64)
+
+
+def grid_axes(spec: ProblemSpec, n_points=None):
+    """Per-axis coordinates of the regular grid: x_m = lo + m*step, last point = hi.
+
+    step = (hi - lo)/(n - 1), each operation rounded separately (no fused
+    multiply-add), so that every implementation reproduces the same doubles.
+    """
+    n_points = spec.n_points if n_points is None else n_points
+    axes = []
+    for a in range(spec.dim):
+        n = int(n_points[a])
+        lo, hi = float(spec.lo[a]), float(spec.hi[a])
+        if n == 1:
+            axes.append(np.array([lo]))
+            continue
+        step = (hi - lo) / (n - 1)
+        m = np.arange(n, dtype=np.float64)
+        x = m * step
+        x = x + lo
+        x[-1] = hi
+        axes.append(x)
+    return axes
+
+
+def grid_points(spec: ProblemSpec, n_points=None) -> np.ndarray:
+    """All grid points [N, dim], x-major order (row n = ix*ny + iy)."""
+    axes = grid_axes(spec, n_points)
+    if spec.dim == 1:
+        return axes[0][:, None].copy()
+    X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)

@@ -1,0 +1,102 @@
+"""Assembly of the least-squares system min ||M a - h|| (Sec. 3, eq. multilevel_ls).
+
+Entries (Sec. 3 "Definition of the system matrices"):
+    M_{n,q} = Op[omega_j phi_q C](x_n) / (sqrt(N_I) L),     h_n = f(x_n) / sqrt(N_I)
+with all grid points taken as interior rows (the hard-constraint ansatz carries the
+boundary condition, Sec. 4.3).  The block form follows eq. multilevel_domain_decomp:
+M = sum_l sum_j V_j^T M_j W_j, with M_j = M restricted to I_j x K_j.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import basis
+from . import geometry as geo
+
+
+@dataclass
+class Block:
+    sd: geo.Subdomain
+    rows: np.ndarray      # I_j: sorted global row indices
+    M: np.ndarray         # M_j [len(rows), K]
+
+
+def assemble_blocks(prob, W, b, x=None):
+    """All blocks M_j of the system matrix.  W [N_Phi, d], b [N_Phi] in global column order."""
+    x = geo.points(prob) if x is None else x
+    N = x.shape[0]
+    L = len(prob.levels)
+    scale = 1.0 / (np.sqrt(float(N)) * L)
+    subs = geo.subdomains(prob)
+    ans = basis.ansatz(x, prob)
+    blocks = []
+    for l in range(L):
+        level = [sd for sd in subs if sd.level == l]
+        sums = basis.level_sum(x, level)
+        for sd in level:
+            rows = np.nonzero(geo.in_support(x, sd))[0]
+            xs = x[rows]
+            sums_r = tuple(s[rows] for s in sums)
+            ans_r = tuple(a[rows] for a in ans)
+            q = slice(sd.q0, sd.q0 + prob.K)
+            val, grad, lap = basis.localized_function(xs, prob, sd, W[q], b[q], sums_r, ans_r)
+            blocks.append(Block(sd, rows, basis.apply_operator(prob, val, grad, lap) * scale))
+    return blocks
+
+
+def rhs(prob, f):
+    """h = f(x_n) / sqrt(N_I)."""
+    N = int(np.prod(prob.n_points))
+    return np.asarray(f, dtype=np.float64) / np.sqrt(float(N))
+
+
+def dense_from_blocks(blocks, n_rows, n_cols):
+    M = np.zeros((n_rows, n_cols))
+    for blk in blocks:
+        K = blk.M.shape[1]
+        M[np.ix_(blk.rows, np.arange(blk.sd.q0, blk.sd.q0 + K))] = blk.M
+    return M
+
+
+def assemble_dense(prob, W, b, x=None):
+    """M as a dense array, each entry computed directly at every point (no block loop): the
+    localised function of every subdomain is evaluated at all N points, where it is zero off
+    the support."""
+    x = geo.points(prob) if x is None else x
+    N = x.shape[0]
+    L = len(prob.levels)
+    scale = 1.0 / (np.sqrt(float(N)) * L)
+    subs = geo.subdomains(prob)
+    M = np.zeros((N, len(subs) * prob.K))
+    for l in range(L):
+        level = [sd for sd in subs if sd.level == l]
+        sums = basis.level_sum(x, level)
+        safe = tuple(np.where(np.abs(s) > 0, s, 1.0) if i == 0 else s
+                     for i, s in enumerate(sums))
+        for sd in level:
+            q = slice(sd.q0, sd.q0 + prob.K)
+            val, grad, lap = basis.localized_function(x, prob, sd, W[q], b[q], safe)
+            ent = basis.apply_operator(prob, val, grad, lap) * scale
+            ent[~geo.in_support(x, sd)] = 0.0
+            M[:, q] = ent
+    return M
+
+
+def matvec(blocks, v, n_rows):
+    """y = M v = sum_j V_j^T (M_j (W_j v))."""
+    y = np.zeros(n_rows)
+    for blk in blocks:
+        K = blk.M.shape[1]
+        y[blk.rows] += blk.M @ v[blk.sd.q0:blk.sd.q0 + K]
+    return y
+
+
+def rmatvec(blocks, u, n_cols):
+    """x = M^T u = sum_j W_j^T (M_j^T (V_j u))."""
+    x = np.zeros(n_cols)
+    for blk in blocks:
+        K = blk.M.shape[1]
+        x[blk.sd.q0:blk.sd.q0 + K] += blk.M.T @ u[blk.rows]
+    return x

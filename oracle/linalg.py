@@ -1,0 +1,279 @@
+"""Least-squares solvers for min ||M a - h|| (Sec. 3 eq. multilevel_ls; Sec. 4.1 "Optimisation
+and solvers": the method solves it with the LSQR algorithm).
+
+  * householder_lstsq  dense Householder QR and back substitution (tiny full-rank systems)
+  * lsqr               Paige & Saunders (1982), damp = 0, stopping tests on ||r|| and ||A^T r||
+  * cgls               conjugate gradients on the normal equations in factored form (CGLS)
+  * gram_blocks        G_ij = M_i^T M_j over the shared rows I_i and I_j, for overlapping pairs
+  * normal_cg          CG on G a = M^T h with G held as its upper blocks
+  * refine             FP64 residual refinement around a low-precision normal-equation solve
+
+The matrix enters through callables matvec(v) -> M v and rmatvec(u) -> M^T u.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- dense QR
+
+def householder_lstsq(M: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """Minimiser of ||M a - h|| for full column rank M via Householder QR."""
+    A = np.array(M, dtype=np.float64, copy=True)
+    y = np.array(h, dtype=np.float64, copy=True)
+    m, n = A.shape
+    if m < n:
+        raise ValueError("householder_lstsq needs rows >= cols")
+    for k in range(n):
+        col = A[k:, k]
+        alpha = np.linalg.norm(col)
+        if alpha == 0.0:
+            continue
+        sign = 1.0 if col[0] >= 0 else -1.0
+        vk = col.copy()
+        vk[0] += sign * alpha
+        vk /= np.linalg.norm(vk)
+        A[k:, k:] -= 2.0 * np.outer(vk, vk @ A[k:, k:])
+        y[k:] -= 2.0 * vk * (vk @ y[k:])
+    R = np.triu(A[:n, :n])
+    x = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - R[i, i + 1:] @ x[i + 1:]) / R[i, i]
+    return x
+
+
+# ---------------------------------------------------------------- LSQR
+
+@dataclass
+class LsqrResult:
+    x: np.ndarray
+    istop: int
+    itn: int
+    rnorm: float
+    arnorm: float
+    anorm: float
+    xnorm: float
+    snapshots: Dict[int, np.ndarray] = field(default_factory=dict)
+    history: List[tuple] = field(default_factory=list)
+
+
+def lsqr(matvec: Callable, rmatvec: Callable, h: np.ndarray, n: int, atol=1e-8, btol=1e-8,
+         iter_lim=15000, x0: Optional[np.ndarray] = None, snapshot_at=(), callback=None,
+         record=False) -> LsqrResult:
+    """Paige-Saunders LSQR with damp = 0 and no condition-number limit.
+
+    Golub-Kahan bidiagonalisation
+        beta_1 u_1 = h - M x0,  alpha_1 v_1 = M^T u_1,
+        beta_{i+1} u_{i+1} = M v_i - alpha_i u_i,  alpha_{i+1} v_{i+1} = M^T u_{i+1} - beta_{i+1} v_i,
+    a plane rotation per step, x_i = x_{i-1} + (phi_i/rho_i) w_i, w_{i+1} = v_{i+1} - (theta_{i+1}/rho_i) w_i.
+    Stop codes: 0 x0 solves exactly, 1 ||r|| <= btol ||h|| + atol ||A|| ||x||,
+    2 ||A^T r|| <= atol ||A|| ||r||, 4/5 the same tests at machine precision, 7 iteration limit.
+    """
+    eps = np.finfo(np.float64).eps
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    u = np.array(h, dtype=np.float64, copy=True)
+    bnorm = np.linalg.norm(u)
+    if x0 is not None:
+        u = u - matvec(x)
+    beta = np.linalg.norm(u)
+    snaps = {}
+    hist = []
+    if beta > 0:
+        u = u / beta
+        v = rmatvec(u)
+        alpha = np.linalg.norm(v)
+    else:
+        v = np.zeros(n)
+        alpha = 0.0
+    if alpha > 0:
+        v = v / alpha
+    w = v.copy()
+    phibar, rhobar = beta, alpha
+    anorm = 0.0
+    rnorm, arnorm = beta, alpha * beta
+    if arnorm == 0.0:
+        return LsqrResult(x, 0, 0, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist)
+    if bnorm == 0.0:
+        bnorm = beta
+    istop, itn = 0, 0
+    while itn < iter_lim:
+        itn += 1
+        u = matvec(v) - alpha * u
+        beta = np.linalg.norm(u)
+        if beta > 0:
+            u = u / beta
+            anorm = np.sqrt(anorm * anorm + alpha * alpha + beta * beta)
+            v = rmatvec(u) - beta * v
+            alpha = np.linalg.norm(v)
+            if alpha > 0:
+                v = v / alpha
+        rho = np.sqrt(rhobar * rhobar + beta * beta)
+        c = rhobar / rho
+        s = beta / rho
+        theta = s * alpha
+        rhobar = -c * alpha
+        phi = c * phibar
+        phibar = s * phibar
+        x = x + (phi / rho) * w
+        w = v - (theta / rho) * w
+        xnorm = float(np.linalg.norm(x))
+        rnorm = phibar
+        arnorm = alpha * abs(c) * phibar
+        test1 = rnorm / bnorm
+        test2 = arnorm / (anorm * rnorm + eps)
+        t1 = test1 / (1.0 + anorm * xnorm / bnorm)
+        rtol = btol + atol * anorm * xnorm / bnorm
+        if record:
+            hist.append((itn, rnorm, arnorm, anorm, xnorm))
+        if itn in snapshot_at:
+            snaps[itn] = x.copy()
+        if callback is not None and callback(itn, x):
+            istop = 8
+            break
+        if 1.0 + test2 <= 1.0:
+            istop = 5
+        if 1.0 + t1 <= 1.0:
+            istop = 4
+        if test2 <= atol:
+            istop = 2
+        if test1 <= rtol:
+            istop = 1
+        if istop != 0:
+            break
+    else:
+        istop = 7
+    return LsqrResult(x, istop, itn, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist)
+
+
+# ---------------------------------------------------------------- CGLS
+
+@dataclass
+class CglsResult:
+    x: np.ndarray
+    istop: int
+    itn: int
+    rnorm: float
+    snorm: float
+    snapshots: Dict[int, np.ndarray] = field(default_factory=dict)
+
+
+def cgls(matvec, rmatvec, h, n, anorm_f, atol=1e-8, btol=1e-8, iter_lim=15000, x0=None,
+         snapshot_at=(), callback=None) -> CglsResult:
+    """CGLS (Bjorck, Numerical Methods for Least Squares Problems, sec. 7.4):
+        r = h - M x, s = M^T r, p = s, gamma = ||s||^2;
+        t = M p, a = gamma/||t||^2, x += a p, r -= a t, s = M^T r, p = s + (||s||^2/gamma) p.
+    Stop: 1 if ||r|| <= btol ||h||, 2 if ||s|| <= atol ||M||_F ||r||, 7 at the iteration limit."""
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = np.array(h, dtype=np.float64, copy=True)
+    bnorm = np.linalg.norm(r)
+    if x0 is not None:
+        r = r - matvec(x)
+    s = rmatvec(r)
+    p = s.copy()
+    gamma = float(s @ s)
+    snaps = {}
+    istop, itn = 0, 0
+    rnorm = float(np.linalg.norm(r))
+    if gamma == 0.0:
+        return CglsResult(x, 0, 0, rnorm, 0.0, snaps)
+    while itn < iter_lim:
+        itn += 1
+        t = matvec(p)
+        a = gamma / float(t @ t)
+        x = x + a * p
+        r = r - a * t
+        s = rmatvec(r)
+        gnew = float(s @ s)
+        p = s + (gnew / gamma) * p
+        gamma = gnew
+        rnorm = float(np.linalg.norm(r))
+        if itn in snapshot_at:
+            snaps[itn] = x.copy()
+        if callback is not None and callback(itn, x):
+            istop = 8
+            break
+        if np.sqrt(gamma) <= atol * anorm_f * rnorm:
+            istop = 2
+        if rnorm <= btol * bnorm:
+            istop = 1
+        if istop:
+            break
+    else:
+        istop = 7
+    return CglsResult(x, istop, itn, rnorm, float(np.sqrt(gamma)), snaps)
+
+
+# ---------------------------------------------------------------- Gram blocks
+
+def gram_blocks(blocks, pairs=None, entry_map=None):
+    """{(i, j): M_i^T M_j over rows in I_i and I_j} for i <= j with a shared row.
+
+    entry_map, if given, is applied to every block's entries first (e.g. rounding to a lower
+    precision); the products are then formed in float64."""
+    mats = [blk.M if entry_map is None else entry_map(blk.M) for blk in blocks]
+    G = {}
+    n = len(blocks)
+    if pairs is None:
+        pairs = [(i, j) for i in range(n) for j in range(i, n)]
+    for i, j in pairs:
+        shared, ii, jj = np.intersect1d(blocks[i].rows, blocks[j].rows, assume_unique=True,
+                                        return_indices=True)
+        if shared.size == 0:
+            continue
+        G[(i, j)] = mats[i][ii].T @ mats[j][jj]
+    return G
+
+
+def gram_apply(G, blocks, p, dtype=np.float64):
+    """y = G p with G given by its upper blocks (i <= j): y_i += G_ij p_j, y_j += G_ij^T p_i."""
+    y = np.zeros(p.shape, dtype=dtype)
+    for (i, j), g in G.items():
+        qi = slice(blocks[i].sd.q0, blocks[i].sd.q0 + g.shape[0])
+        qj = slice(blocks[j].sd.q0, blocks[j].sd.q0 + g.shape[1])
+        y[qi] += (g @ p[qj]).astype(dtype)
+        if i != j:
+            y[qj] += (g.T @ p[qi]).astype(dtype)
+    return y
+
+
+def normal_cg(apply_G, g, n_iter, dtype=np.float64):
+    """Hestenes-Stiefel CG on G d = g from d = 0 for n_iter steps, vectors and scalars in dtype."""
+    d = np.zeros(g.shape, dtype=dtype)
+    r = np.array(g, dtype=dtype, copy=True)
+    p = r.copy()
+    rr = r @ r
+    for _ in range(n_iter):
+        if rr == 0:
+            break
+        q = np.asarray(apply_G(p), dtype=dtype)
+        pq = p @ q
+        if not pq > 0:
+            break
+        a = rr / pq
+        d = d + a * p
+        r = r - a * q
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return d
+
+
+def refine(matvec, rmatvec, h, n, apply_G_lo, n_outer, n_inner, x0=None, lo_dtype=np.float32,
+           callback=None):
+    """Iterative refinement (BJ-style mixed precision): per outer step
+         r = h - M c (float64), g = M^T r (float64), d ~ G_lo^{-1} g by n_inner CG steps in lo_dtype,
+         c = c + d (float64)."""
+    c = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    hist = []
+    for it in range(n_outer):
+        r = h - matvec(c)
+        g = rmatvec(r)
+        hist.append((float(np.linalg.norm(r)), float(np.linalg.norm(g))))
+        d = normal_cg(apply_G_lo, g.astype(lo_dtype), n_inner, dtype=lo_dtype)
+        c = c + d.astype(np.float64)
+        if callback is not None and callback(it, c):
+            break
+    return c, hist

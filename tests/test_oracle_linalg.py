@@ -1,0 +1,195 @@
+"""Pins of the oracle's solvers, Gram blocks, refinement, rounding and evaluation against
+textbook facts: QR vs LAPACK, LSQR finite termination, LSQR = CGLS in exact arithmetic,
+SciPy's LSQR iterates, Gram = M^T M, refinement convergence, bfloat16 rounding."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from inputs import configs, feature_params
+from oracle import assemble as asm
+from oracle import evaluate as ev
+from oracle import geometry as geo
+from oracle import linalg
+from oracle import lowprec
+
+
+def _tiny_system():
+    spec = configs.tiny1d()
+    W, b = feature_params(spec)
+    blocks = asm.assemble_blocks(spec, W, b)
+    M = asm.dense_from_blocks(blocks, spec.n_rows, len(blocks) * spec.K)
+    h = asm.rhs(spec, configs.forcing(spec))
+    return spec, W, b, blocks, M, h
+
+
+def _well_conditioned(m=60, n=20, cond=10.0, seed=0):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.geomspace(1.0, 1.0 / cond, n)
+    return (U * s) @ V.T, rng.standard_normal(m)
+
+
+def test_householder_matches_lapack():
+    _, _, _, _, M, h = _tiny_system()
+    x = linalg.householder_lstsq(M, h)
+    ref = np.linalg.lstsq(M, h, rcond=None)[0]
+    cond = np.linalg.cond(M)
+    assert np.linalg.norm(x - ref) <= cond * 1e-15 * 10 * np.linalg.norm(ref)
+
+
+def test_lsqr_orthonormal_columns_one_step():
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(rng.standard_normal((30, 8)))
+    h = rng.standard_normal(30)
+    r = linalg.lsqr(lambda v: Q @ v, lambda u: Q.T @ u, h, 8, atol=1e-14, btol=1e-14, iter_lim=1)
+    assert np.allclose(r.x, Q.T @ h, atol=1e-14)
+    # the stopping test recognises the exact least-squares solution after one step
+    r = linalg.lsqr(lambda v: Q @ v, lambda u: Q.T @ u, h, 8, atol=1e-12, btol=1e-12)
+    assert r.itn == 1 and r.istop in (2, 5)
+
+
+def test_lsqr_diagonal_finite_termination():
+    """A diagonal matrix with n distinct singular values: the Krylov space is exhausted after n
+    steps, so LSQR returns the exact solution at step n."""
+    d = np.array([3.0, 1.5, 0.7, 0.2, 0.05])
+    A = np.vstack([np.diag(d), np.zeros((3, 5))])
+    rng = np.random.default_rng(2)
+    h = rng.standard_normal(8)
+    r = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, 5, atol=0, btol=0, iter_lim=5)
+    assert np.allclose(r.x, h[:5] / d, rtol=1e-10)
+    r4 = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, 5, atol=0, btol=0, iter_lim=4)
+    assert not np.allclose(r4.x, h[:5] / d, rtol=1e-3)
+
+
+def test_lsqr_equals_cgls_iterates():
+    """LSQR and CGLS generate the same iterates in exact arithmetic (Paige & Saunders 1982);
+    compared over the first 10 steps, before the residual reaches rounding level and the two
+    recurrences' rounding errors take over."""
+    A, h = _well_conditioned()
+    ks = tuple(range(1, 11))
+    r1 = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], atol=0, btol=0,
+                     iter_lim=10, snapshot_at=ks)
+    r2 = linalg.cgls(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], np.linalg.norm(A),
+                     atol=0, btol=0, iter_lim=10, snapshot_at=ks)
+    for k in ks:
+        assert np.linalg.norm(r1.snapshots[k] - r2.snapshots[k]) <= 1e-12 * np.linalg.norm(r1.snapshots[k])
+
+
+def test_lsqr_matches_scipy_iterates():
+    """Same iterates as SciPy's LSQR over the first steps; later, where the residual nearly
+    stagnates and the iterates become sensitive to rounding, the residual norms still agree."""
+    A, h = _well_conditioned(cond=1e3, seed=3)
+    for k in (1, 2, 3, 4, 5):
+        ours = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], atol=0, btol=0,
+                           iter_lim=k).x
+        theirs = spla.lsqr(A, h, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+        assert np.linalg.norm(ours - theirs) <= 1e-12 * np.linalg.norm(theirs)
+    for k in (12, 20):
+        ours = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], atol=0, btol=0,
+                           iter_lim=k).x
+        theirs = spla.lsqr(A, h, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+        assert abs(np.linalg.norm(A @ ours - h) - np.linalg.norm(A @ theirs - h)) <= \
+            1e-3 * np.linalg.norm(h)
+
+
+def test_lsqr_converges_to_qr_solution():
+    _, _, _, blocks, M, h = _tiny_system()
+    n = M.shape[1]
+    r = linalg.lsqr(lambda v: asm.matvec(blocks, v, M.shape[0]),
+                    lambda u: asm.rmatvec(blocks, u, n), h, n, atol=1e-14, btol=1e-14,
+                    iter_lim=2000)
+    ref = linalg.householder_lstsq(M, h)
+    cond = np.linalg.cond(M)
+    assert np.linalg.norm(r.x - ref) <= 1e-14 * cond * np.linalg.norm(ref)
+    assert abs(r.rnorm - np.linalg.norm(M @ ref - h)) <= 1e-10
+
+
+def test_lsqr_warm_start():
+    """Starting from x0 solves for the correction of h - M x0; a converged x0 stops at once."""
+    A, h = _well_conditioned(seed=4)
+    full = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], atol=1e-14, btol=1e-14)
+    again = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, h, A.shape[1], atol=1e-10,
+                        btol=1e-10, x0=full.x)
+    assert again.itn <= 1
+    assert np.allclose(again.x, full.x, atol=1e-12)
+
+
+def test_gram_blocks_equal_dense_normal_matrix():
+    spec = configs.small2d()
+    W, b = feature_params(spec)
+    blocks = asm.assemble_blocks(spec, W, b)
+    n = len(blocks) * spec.K
+    M = asm.dense_from_blocks(blocks, spec.n_rows, n)
+    pairs = geo.overlap_pairs(spec, [blk.rows for blk in blocks])
+    G = linalg.gram_blocks(blocks, pairs)
+    assert set(G.keys()) == set(pairs)
+    D = np.zeros((n, n))
+    for (i, j), g in G.items():
+        qi, qj = blocks[i].sd.q0, blocks[j].sd.q0
+        D[qi:qi + spec.K, qj:qj + spec.K] = g
+        D[qj:qj + spec.K, qi:qi + spec.K] = g.T
+    ref = M.T @ M
+    assert np.abs(D - ref).max() <= 1e-14 * np.abs(ref).max()
+    for (i, j), g in G.items():
+        if i == j:
+            assert np.array_equal(g, g.T) or np.abs(g - g.T).max() <= 1e-15 * np.abs(g).max()
+    lam = np.linalg.eigvalsh(ref)
+    assert lam.min() >= -1e-12 * lam.max()
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(n)
+    assert np.allclose(linalg.gram_apply(G, blocks, p), ref @ p, rtol=0,
+                       atol=1e-13 * np.abs(ref @ p).max())
+
+
+def test_normal_cg_solves_spd():
+    A, _ = _well_conditioned(m=40, n=12, cond=5.0, seed=6)
+    G = A.T @ A
+    g = np.random.default_rng(7).standard_normal(12)
+    d = linalg.normal_cg(lambda p: G @ p, g, 12)
+    assert np.allclose(d, np.linalg.solve(G, g), rtol=1e-10)
+
+
+def test_refinement_reaches_working_precision():
+    """With kappa(G) u_32 << 1, refinement around a float32 inner solve converges to the float64
+    least-squares solution (classical iterative refinement)."""
+    A, h = _well_conditioned(m=80, n=24, cond=20.0, seed=8)
+    G32 = (A.T @ A).astype(np.float32)
+    c, hist = linalg.refine(lambda v: A @ v, lambda u: A.T @ u, h, 24,
+                            lambda p: G32 @ p, n_outer=12, n_inner=24)
+    ref = np.linalg.lstsq(A, h, rcond=None)[0]
+    assert np.linalg.norm(c - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert hist[-1][1] < 1e-10 * hist[0][1]
+
+
+def test_bf16_rounding_against_torch_and_ties():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    x32 = (rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))).astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(lowprec.to_bf16(x32.astype(np.float64)), ref)
+    # ties and double-rounding cases, decided from the definition
+    assert lowprec.to_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0            # tie -> even
+    assert lowprec.to_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2 ** -6  # tie -> even (up)
+    assert lowprec.to_bf16(np.array([1.0 + 2.0 ** -8 + 2.0 ** -30]))[0] == 1.0 + 2.0 ** -7
+    assert lowprec.to_bf16(np.array([-(1.0 + 2.0 ** -8 + 2.0 ** -30)]))[0] == -(1.0 + 2.0 ** -7)
+    assert np.isinf(lowprec.to_bf16(np.array([3.5e38]))[0])
+    assert lowprec.to_f32(np.array([1.0 + 2.0 ** -24]))[0] == 1.0
+
+
+def test_evaluate_single_feature_closed_form():
+    """One level, one subdomain, one feature: u = C(x) a tanh(W xbar + b)."""
+    spec = configs.tiny1d(K=1, J=1, n=10)
+    W, b = feature_params(spec)
+    x = np.linspace(-1, 1, 13)[:, None]
+    u = ev.evaluate(spec, W, b, np.array([2.5]), x)
+    ref = np.tanh(spec.ansatz_omega * x[:, 0]) * 2.5 * np.tanh(W[0, 0] * x[:, 0] + b[0])
+    assert np.allclose(u, ref, rtol=1e-15, atol=1e-15)
+
+
+def test_metrics():
+    u = np.array([1.0, 2.0, 3.0, 4.0])
+    ue = np.array([1.0, 2.0, 3.0, 5.0])
+    assert ev.e_l1(u, ue) == pytest.approx(0.25 / np.std(ue))
+    assert np.std(ue) == pytest.approx(np.sqrt(np.mean((ue - ue.mean()) ** 2)))
+    assert ev.rel_l2(u, ue) == pytest.approx(1.0 / np.linalg.norm(ue))
