@@ -1,0 +1,203 @@
+/*
+ * elmfb.h -- C ABI of the MI355X (gfx950) multilevel ELM-FBPINN least-squares library.
+ *
+ * The library assembles and solves the structured linear least-squares system of a
+ * multilevel ELM-FBPINN (Sec. 3 of "ELM-FBPINNs: An Efficient Multilevel Random Feature
+ * Method"):   min_a || M a - h ||,   M = sum_l sum_j V_j^T M_j W_j   (eq. multilevel_ls,
+ * eq. multilevel_domain_decomp), for a linear operator on a box domain with a regular
+ * collocation grid, L levels of overlapping subdomains with partition-of-unity windows
+ * (Sec. 4.1, eq. window_func) and K fixed random tanh features per subdomain.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an elmfb_status; 0 is success.  No C++ exception crosses the ABI.
+ *     On failure elmfb_last_error(handle) (or elmfb_last_error(NULL) for calls that failed
+ *     before a handle existed) returns a message; the message lives until the next failing
+ *     call on the same thread.
+ *   - Pointers named *_dev are device pointers (hipMalloc'ed or any device allocation, for
+ *     example a torch tensor's data pointer) owned by the caller.  They must stay valid until
+ *     the work enqueued on the given stream has completed.  The library never frees them.
+ *   - Pointers named *_host are host pointers owned by the caller, read during the call only.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.  Calls enqueue
+ *     their device work on that stream.  elmfb_solve blocks the host at its check points
+ *     (it reads the stopping state back), every other call is asynchronous.
+ *   - Arguments are checked before any device work is enqueued; a rejected call changes
+ *     nothing.  Device failures map to ELMFB_E_DEVICE with the HIP error text.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Row order of every vector over collocation points is x-major (row n = ix*ny + iy);
+ *     column (coefficient) order is q = sum_{m<l} J_m K + j K + k with the subdomain index
+ *     j = jx*Jy + jy (Sec. 3 "Indexing conventions", 0-based here).
+ */
+#ifndef ELMFB_H_
+#define ELMFB_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELMFB_ABI_VERSION 1
+#define ELMFB_MAX_LEVELS 8
+
+typedef int32_t elmfb_status;
+enum {
+  ELMFB_OK = 0,
+  ELMFB_E_INVALID = 1,     /* bad argument or descriptor                                    */
+  ELMFB_E_NOMEM = 2,       /* device footprint does not fit (checked before allocating)      */
+  ELMFB_E_DEVICE = 3,      /* HIP runtime failure or no usable gfx950 device                 */
+  ELMFB_E_STATE = 4,       /* call out of order (e.g. solve before assemble)                 */
+  ELMFB_E_NUMERIC = 5,     /* non-finite input values                                        */
+  ELMFB_E_UNSUPPORTED = 6  /* valid but not implemented combination                          */
+};
+
+/* Linear operators N of the PDE N[u] = f (Sec. 3 "Problem and model definition"). */
+enum {
+  ELMFB_OP_D1 = 1,          /* du/dx, dim = 1                                                */
+  ELMFB_OP_NEG_LAPLACE = 2, /* -Laplace(u), dim = 2                                          */
+  ELMFB_OP_IDENTITY = 3     /* u itself (evaluation / projection matrices), dim 1 or 2       */
+};
+
+/* Hard-constraint factor C(x) multiplying the network (Sec. 4.3 "Hard boundary constraints"). */
+enum {
+  ELMFB_ANSATZ_NONE = 0,        /* C = 1                                                     */
+  ELMFB_ANSATZ_TANH_ORIGIN = 1, /* C = tanh(w x), dim 1: u(0) = 0                            */
+  ELMFB_ANSATZ_TANH_BOX = 2     /* C = prod_i tanh(w (x_i - lo_i)) tanh(w (hi_i - x_i))      */
+};
+
+enum { ELMFB_FP64 = 0, ELMFB_FP32 = 1, ELMFB_BF16 = 2 };
+
+/* Solvers (Sec. 4.1 "Optimisation and solvers": LSQR; the others are alternatives on the
+ * same matrix). */
+enum {
+  ELMFB_LSQR = 0,       /* Paige-Saunders LSQR on block-sparse A v / A^T u, FP64 recurrences  */
+  ELMFB_CGLS = 1        /* CG on the normal equations in factored form, FP64                 */
+};
+
+typedef struct elmfb_problem_s* elmfb_problem;
+
+/* Problem descriptor.  The grid has n_points[a] points per axis, endpoints included:
+ * x_m = lo + m*((hi-lo)/(n-1)), last point = hi.  Level l has J[l][a] subdomains along axis a
+ * with centres lo + j*h, h = (hi-lo)/(J-1), and half-width delta*h/2 (J = 1: the whole axis,
+ * window factor 1).  For dim = 1 the second entries of lo/hi/n_points/J are ignored.
+ * W_host [n_phi][dim] and b_host [n_phi] are the fixed hidden weights and biases of the
+ * random features tanh(W_q . xbar + b_q), xbar = (x - mu_j)/sigma_l, in column order q. */
+typedef struct {
+  int32_t abi_version;               /* must be ELMFB_ABI_VERSION                            */
+  int32_t dim;                       /* 1 or 2                                               */
+  int32_t op;                        /* ELMFB_OP_*                                           */
+  int32_t ansatz;                    /* ELMFB_ANSATZ_*                                       */
+  double ansatz_omega;               /* w of the hard-constraint factor                      */
+  double lo[2], hi[2];               /* domain box, lo < hi                                  */
+  int32_t n_points[2];               /* >= 2 per used axis                                   */
+  int32_t n_levels;                  /* 1..ELMFB_MAX_LEVELS                                  */
+  int32_t J[ELMFB_MAX_LEVELS][2];    /* subdomains per axis per level, >= 1                  */
+  double delta;                      /* width ratio, > 0                                     */
+  int32_t K;                         /* features per subdomain, 1..256                       */
+  int32_t store_prec;                /* precision of the stored matrix: ELMFB_FP64/FP32/BF16 */
+  const double* W_host;              /* [n_phi][dim]                                         */
+  const double* b_host;              /* [n_phi]                                              */
+} elmfb_problem_desc;
+
+typedef struct {
+  int64_t n_rows;          /* collocation points N_I                                        */
+  int64_t n_phi;           /* columns N_Phi = K * sum_l prod_a J[l][a]                       */
+  int64_t nnz;             /* stored entries = K * sum_j |I_j|                               */
+  int64_t n_blocks;        /* subdomains over all levels                                    */
+  int64_t n_block_points;  /* sum_j |I_j|                                                   */
+  int64_t bytes_device;    /* device memory held by the handle                              */
+} elmfb_sizes;
+
+typedef struct {
+  int32_t method;          /* ELMFB_LSQR | ELMFB_CGLS                                       */
+  int32_t iter_lim;        /* maximum iterations (>= 0)                                     */
+  int32_t check_every;     /* iterations per captured graph replay / host check, >= 1       */
+  int32_t use_graph;       /* 1: capture the iteration loop in a hipGraph and replay it     */
+  double atol, btol;       /* Paige-Saunders stopping tolerances (>= 0); conlim is off      */
+  const double* x0_dev;    /* optional warm start [n_phi] (NULL: zero)                      */
+  /* optional stop on the solution error: every check_every iterations u_tilde is evaluated
+   * at check_pts_dev [n_check][dim] and the solve stops once
+   * ||u - check_ref|| / ||check_ref|| <= target_rel_l2.  n_check = 0 disables it. */
+  const double* check_pts_dev;
+  const double* check_ref_dev;
+  int64_t n_check;
+  double target_rel_l2;
+} elmfb_solve_opts;
+
+typedef struct {
+  int32_t istop;           /* 0 x0 exact, 1 ||r|| test, 2 ||A^T r|| test, 4/5 the same at
+                              machine precision, 7 iteration limit, 8 rel-L2 target reached */
+  int32_t iters;
+  double rnorm;            /* ||h - A x|| (LSQR estimate / CGLS recurrence)                  */
+  double arnorm;           /* ||A^T (h - A x)||                                              */
+  double anorm;            /* LSQR Frobenius-norm estimate; CGLS: exact ||A||_F              */
+  double xnorm;            /* ||x||                                                          */
+  double rel_l2;           /* last rel-L2 check value (-1 if none ran)                      */
+  double ms_solve;         /* host wall time of the call                                    */
+} elmfb_solve_info;
+
+/* Validate the descriptor, plan the decomposition (subdomain boxes on the grid, offsets),
+ * check the device footprint against free memory (ELMFB_E_NOMEM before any allocation),
+ * allocate the handle's device memory and upload W, b and the tables.  Needs a gfx950
+ * device (ELMFB_E_DEVICE otherwise).  Sec. 3, Sec. 4.1. */
+elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out);
+
+/* Sizes of the planned system. */
+elmfb_status elmfb_query(elmfb_problem h, elmfb_sizes* out_host);
+
+/* Collocation points [n_rows][dim] in row order, computed on the device. */
+elmfb_status elmfb_points(elmfb_problem h, double* xy_dev, void* stream);
+
+/* Assemble every block M_j [K][|I_j|] (feature-major) of the system matrix in the stored
+ * precision and the right-hand side h = f/sqrt(N_I) from f_dev [n_rows] (Sec. 3 "Definition
+ * of the vectors" and "Definition of the system matrices"):
+ *     M_{n,q} = Op[C omega_j phi_q](x_n) / (sqrt(N_I) L).
+ * Entries are computed in FP64 and rounded once (round-to-nearest-even) to the stored
+ * precision.  ELMFB_E_NUMERIC if f holds a non-finite value (checked on the device; the
+ * call then synchronises the stream). */
+elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream);
+
+/* y_dev [n_rows] = M v_dev [n_phi] (block-sparse, Sec. 3 eq. multilevel_domain_decomp). */
+elmfb_status elmfb_matvec(elmfb_problem h, const double* v_dev, double* y_dev, void* stream);
+
+/* x_dev [n_phi] = M^T u_dev [n_rows]. */
+elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, void* stream);
+
+/* Copy the assembled right-hand side h [n_rows] (FP64). */
+elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
+
+/* Copy the stored blocks (in the stored precision, raw bytes, blocks in column order, each
+ * [K][|I_j|] with the block's points in row-major order of its box) into dst_dev, and the
+ * block table into table_host [n_blocks][8] as int64: level, jx, jy, ix0, nx, iy0, ny,
+ * element offset of the block. */
+elmfb_status elmfb_copy_blocks(elmfb_problem h, void* dst_dev, int64_t* table_host,
+                               void* stream);
+
+/* Solve min ||M x - h|| (Sec. 3 eq. multilevel_ls) into coef_dev [n_phi].  LSQR follows
+ * Paige & Saunders (damp 0, no condition limit, stop tests on ||r|| and ||A^T r||), as the
+ * method's reference solver does (Sec. 4.1).  Non-convergence is not an error: istop = 7.
+ * info_host may be NULL. */
+elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
+                         elmfb_solve_info* info_host, void* stream);
+
+/* u_dev [n_pts] = C(x) (1/L) sum_l sum_j omega_j(x) sum_k coef_q phi_q(x) at arbitrary points
+ * pts_dev [n_pts][dim] (Sec. 3 eq. multilevel_solution with the hard-constraint factor). */
+elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,
+                            int64_t n_pts, double* u_dev, void* stream);
+
+/* Time the two matrix-streaming kernels of one LSQR/CGLS iteration on `stream` with HIP
+ * events: the per-block-point pass of y = M v and the per-chunk pass of x = M^T u, each
+ * launched `reps` times back to back on the stored matrix (with v = 1, u = 1).  Writes the
+ * average duration of one launch in milliseconds to ms_host[0] (M v) and ms_host[1]
+ * (M^T u).  Blocks the host until the timing completes. */
+elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t reps, double* ms_host, void* stream);
+
+/* Release everything the handle owns.  NULL is a no-op. */
+void elmfb_destroy(elmfb_problem h);
+
+/* Message of the last failing call on this handle (NULL: of the calling thread). */
+const char* elmfb_last_error(elmfb_problem h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELMFB_H_ */

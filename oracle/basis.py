@@ -48,6 +48,12 @@ def window_hat(x, sd: geo.Subdomain):
     f = [raw_window(t[a]) for a in range(d)]
     f1 = [raw_window_dt(t[a]) / sd.sigma[a] for a in range(d)]
     f2 = [raw_window_dtt(t[a]) / sd.sigma[a] ** 2 for a in range(d)]
+    for a in range(d):
+        if sd.single_axes and sd.single_axes[a]:
+            # one subdomain along this axis: factor 1 (its normalisation would be 0/0 at the ends)
+            f[a] = np.ones(N, dtype=np.result_type(x, float))
+            f1[a] = np.zeros(N, dtype=f[a].dtype)
+            f2[a] = np.zeros(N, dtype=f[a].dtype)
     val = np.ones(N, dtype=np.result_type(x, float))
     for a in range(d):
         val = val * f[a]
@@ -82,8 +88,8 @@ def level_sum(x, subs_of_level):
 def window(x, sd: geo.Subdomain, level_sums):
     """Normalised window omega_j = omega_hat_j / S with gradient and Laplacian (quotient rule).
 
-    A level with a single subdomain has omega == 1 (the normalisation would be 0/0 on the
-    boundary otherwise)."""
+    Along an axis with a single subdomain the factor is 1, so a level with one subdomain has
+    omega == 1."""
     N, d = x.shape
     if sd.single:
         return np.ones(N), np.zeros((N, d)), np.zeros(N)

@@ -11,8 +11,8 @@ Readings of the paper used here:
   * every subdomain, the two end ones included, has half-width sigma = delta*h/2
     (bounds mu -/+ (delta/2)*h, sigma = half their distance); supports are cut at the
     domain boundary;
-  * a single subdomain (J = 1) is the whole axis: mu = midpoint, sigma = (hi-lo)/2,
-    and its window is identically one;
+  * a single subdomain along an axis (J = 1) is the whole axis: mu = midpoint,
+    sigma = (hi-lo)/2, and its window factor along that axis is identically one;
   * a point belongs to the support I_j when |x_i - mu_i| < sigma_i on every axis (strict).
 """
 from __future__ import annotations
@@ -63,6 +63,7 @@ class Subdomain:
     sigma: np.ndarray     # half-width [dim]
     q0: int               # first global column: sum_{m<l} J_m K + j K
     single: bool          # level with a single subdomain (window == 1)
+    single_axes: tuple = ()   # per axis: the level has one subdomain along that axis
 
 
 def subdomains(prob) -> List[Subdomain]:
@@ -77,17 +78,18 @@ def subdomains(prob) -> List[Subdomain]:
             mu = np.array([per_axis[a][0][jj[a]] for a in range(prob.dim)])
             sig = np.array([per_axis[a][1] for a in range(prob.dim)])
             j = int(np.ravel_multi_index(jj, [int(J[a]) for a in range(prob.dim)]))
-            out.append(Subdomain(l, j, tuple(int(v) for v in jj), mu, sig, q0, single))
+            out.append(Subdomain(l, j, tuple(int(v) for v in jj), mu, sig, q0, single,
+                                 tuple(int(J[a]) == 1 for a in range(prob.dim))))
             q0 += prob.K
     return out
 
 
 def in_support(x: np.ndarray, sd: Subdomain) -> np.ndarray:
     """Boolean mask over points x [N, dim]: omega_j(x) != 0."""
-    if sd.single:
-        return np.ones(x.shape[0], dtype=bool)
     m = np.ones(x.shape[0], dtype=bool)
     for a in range(x.shape[1]):
+        if sd.single_axes and sd.single_axes[a]:
+            continue                   # one subdomain along this axis: it covers the whole axis
         m &= np.abs(x[:, a] - sd.mu[a]) < sd.sigma[a]
     return m
 

@@ -1,0 +1,99 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include "common.h"
+
+namespace elmfb {
+
+// Grid coordinate x_m = lo + m*step (last point = hi), each operation rounded on its own (the
+// multiply and add must not be contracted into a fused multiply-add).
+__device__ __forceinline__ double grid_coord(const Geo& g, int a, int m) {
+#pragma clang fp contract(off)
+  const int n = (a == 0) ? g.nx : g.ny;
+  if (n == 1) return g.lo[a];
+  if (m == n - 1) return g.hi[a];
+  const double t = (double)m * g.step[a];
+  return t + g.lo[a];
+}
+
+// Centre of subdomain j of level l along axis a: lo + j*h (J > 1) or the midpoint (J = 1).
+__device__ __forceinline__ double centre(const Geo& g, int l, int a, int j) {
+#pragma clang fp contract(off)
+  if (g.J[l][a] == 1) return g.mid[l][a];
+  const double t = (double)j * g.cen_h[l][a];
+  return t + g.lo[a];
+}
+
+// Raw window factor (1 + cos(pi t))^2, t = (x - mu)/sigma, and its first two x-derivatives.
+__device__ __forceinline__ void raw_window(double x, double mu, double sigma, double& w,
+                                           double& w1, double& w2) {
+  const double t = (x - mu) / sigma;
+  if (!(fabs(t) < 1.0)) { w = 0.0; w1 = 0.0; w2 = 0.0; return; }
+  double s, c;
+  sincospi(t, &s, &c);
+  const double oc = 1.0 + c;
+  w = oc * oc;
+  w1 = (-2.0 * M_PI * s * oc) / sigma;
+  w2 = (2.0 * M_PI * M_PI * (s * s - c * oc)) / (sigma * sigma);
+}
+
+// Hard-constraint factor along one axis: value and two derivatives.
+__device__ __forceinline__ void ansatz_axis(const Geo& g, int a, double x, double& v, double& v1,
+                                            double& v2) {
+  const double w = g.ansatz_omega;
+  if (g.ansatz == ELMFB_ANSATZ_TANH_BOX && a < g.dim) {
+    const double p = tanh(w * (x - g.lo[a]));
+    const double r = tanh(w * (g.hi[a] - x));
+    const double dp = w * (1.0 - p * p);
+    const double dr = -w * (1.0 - r * r);
+    const double ddp = -2.0 * w * p * dp;
+    const double ddr = 2.0 * w * r * dr;
+    v = p * r;
+    v1 = dp * r + p * dr;
+    v2 = ddp * r + 2.0 * dp * dr + p * ddr;
+  } else if (g.ansatz == ELMFB_ANSATZ_TANH_ORIGIN && a == 0) {
+    const double c = tanh(w * x);
+    v = c;
+    v1 = w * (1.0 - c * c);
+    v2 = -2.0 * w * w * c * (1.0 - c * c);
+  } else {
+    v = 1.0; v1 = 0.0; v2 = 0.0;
+  }
+}
+
+// Fixed-order (deterministic) sum over a wavefront of 64 lanes.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order sum over a workgroup of 256 threads; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double* sh /* >= 4 doubles */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+template <int PREC>
+__device__ __forceinline__ double load_entry(const void* A, int64_t i);
+
+template <>
+__device__ __forceinline__ double load_entry<ELMFB_FP64>(const void* A, int64_t i) {
+  return static_cast<const double*>(A)[i];
+}
+template <>
+__device__ __forceinline__ double load_entry<ELMFB_FP32>(const void* A, int64_t i) {
+  return (double)static_cast<const float*>(A)[i];
+}
+template <>
+__device__ __forceinline__ double load_entry<ELMFB_BF16>(const void* A, int64_t i) {
+  return bf16_to_f64(static_cast<const uint16_t*>(A)[i]);
+}
+
+}  // namespace elmfb

@@ -1,0 +1,209 @@
+// Fused assembly of the block-sparse least-squares system (Sec. 3 "Definition of the system
+// matrices"; windows Sec. 4.1 eq. window_func; features Sec. 3 with h = 1; hard constraint
+// Sec. 4.3).
+//
+// On a tensor grid the windowed, hard-constrained envelope P = C * omega_j of a subdomain is a
+// product of one factor per axis: C = a_x(x) a_y(y) and omega_j = g_jx(x) g_jy(y), where
+// g_j = w_j / sum_{j'} w_{j'} along that axis (the level sum of the 2D windows factorises into
+// the product of the per-axis sums).  So the envelope and its derivatives up to second order
+// are tabulated once per (level, axis, subdomain, grid index): E = a g, E' = a'g + a g',
+// E'' = a''g + 2a'g' + a g''.  The entry kernel then combines one x-entry and one y-entry per
+// point with the K features of the block: phi = tanh(W1 xbar + W2 ybar + b),
+//   -Lap(P phi) = -(Lap P phi + 2 (1-phi^2)(P_x W1/sx + P_y W2/sy)
+//                   - 2 P phi (1-phi^2)((W1/sx)^2 + (W2/sy)^2)),
+//   d/dx(P phi) = P_x phi + P (1-phi^2) W1/sx,    identity: P phi,
+// scaled by 1/(sqrt(N) L), in FP64, stored feature-major per block (A_blk[k][p]) so that a
+// wavefront writes 64 consecutive points of one feature.
+#include "device.h"
+#include "kernels.h"
+
+namespace elmfb {
+
+// One workgroup per axis segment (level, axis, subdomain j): entries for grid indices
+// m0..m1-1.  cov gives, per (level, axis, grid index), the covering subdomain range.
+__global__ void __launch_bounds__(256) k_axis_tables(Geo g, const AxisSeg* __restrict__ segs,
+                                                     const int32_t* __restrict__ cov,
+                                                     double* __restrict__ tab) {
+  const AxisSeg sg = segs[blockIdx.x];
+  const int l = sg.level, a = sg.axis;
+  const int J = g.J[l][a];
+  const double sigma = g.sigma[l][a];
+  const double muj = centre(g, l, a, sg.j);
+  for (int m = sg.m0 + threadIdx.x; m < sg.m1; m += blockDim.x) {
+    double e = 1.0, e1 = 0.0, e2 = 0.0;
+    if (a < g.dim) {
+      const double x = grid_coord(g, a, m);
+      double gv = 1.0, g1 = 0.0, g2 = 0.0;
+      if (J > 1) {
+        double w, w1, w2;
+        raw_window(x, muj, sigma, w, w1, w2);
+        const int jlo = cov[g.cov_off[l][a] + 2 * m], jhi = cov[g.cov_off[l][a] + 2 * m + 1];
+        double S = 0.0, S1 = 0.0, S2 = 0.0;
+        for (int jj = jlo; jj <= jhi; ++jj) {
+          double v, v1, v2;
+          raw_window(x, centre(g, l, a, jj), sigma, v, v1, v2);
+          S += v; S1 += v1; S2 += v2;
+        }
+        gv = w / S;
+        g1 = (w1 - gv * S1) / S;
+        g2 = (w2 - 2.0 * g1 * S1 - gv * S2) / S;
+      }
+      double c, c1, c2;
+      ansatz_axis(g, a, x, c, c1, c2);
+      e = c * gv;
+      e1 = c1 * gv + c * g1;
+      e2 = c2 * gv + 2.0 * c1 * g1 + c * g2;
+    }
+    const int64_t o = 3 * (int64_t)(sg.tab_off + (m - sg.m0));
+    tab[o] = e;
+    tab[o + 1] = e1;
+    tab[o + 2] = e2;
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void store_entry(void* A, int64_t i, double v);
+template <>
+__device__ __forceinline__ void store_entry<ELMFB_FP64>(void* A, int64_t i, double v) {
+  static_cast<double*>(A)[i] = v;
+}
+template <>
+__device__ __forceinline__ void store_entry<ELMFB_FP32>(void* A, int64_t i, double v) {
+  static_cast<float*>(A)[i] = (float)v;   // IEEE round-to-nearest-even
+}
+template <>
+__device__ __forceinline__ void store_entry<ELMFB_BF16>(void* A, int64_t i, double v) {
+  static_cast<uint16_t*>(A)[i] = f64_to_bf16_rne(v);
+}
+
+// One workgroup per tile of <= 256 points of one block; one thread per point, looping over K.
+template <int PREC, int OP>
+__global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restrict__ blocks,
+                                                  const Tile* __restrict__ tiles,
+                                                  const double* __restrict__ tab,
+                                                  const double* __restrict__ W,
+                                                  const double* __restrict__ bias,
+                                                  void* __restrict__ A) {
+  __shared__ double w1s[256], w2s[256], c1s[256], c2s[256], c3s[256], bs[256];
+  const Tile t = tiles[blockIdx.x];
+  const DevBlock B = blocks[t.blk];
+  const int K = g.K;
+  const int l = B.level;
+  const double sx = g.sigma[l][0], sy = g.sigma[l][1];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double w1 = W[2 * (int64_t)(B.q0 + k)];
+    const double w2 = (g.dim == 2) ? W[2 * (int64_t)(B.q0 + k) + 1] : 0.0;
+    const double c1 = w1 / sx, c2 = (g.dim == 2) ? w2 / sy : 0.0;
+    w1s[k] = w1;
+    w2s[k] = w2;
+    c1s[k] = c1;
+    c2s[k] = c2;
+    c3s[k] = c1 * c1 + c2 * c2;
+    bs[k] = bias[B.q0 + k];
+  }
+  __syncthreads();
+  const int p = t.p0 + threadIdx.x;
+  if (p >= B.n) return;
+  const int lx = p / B.ny, ly = p - lx * B.ny;
+  const double* tx = tab + 3 * (int64_t)(B.tabx + lx);
+  const double* ty = tab + 3 * (int64_t)(B.taby + ly);
+  const double X0 = tx[0], X1 = tx[1], X2 = tx[2];
+  const double Y0 = ty[0], Y1 = ty[1], Y2 = ty[2];
+  const double P = X0 * Y0, Px = X1 * Y0, Py = X0 * Y1, LP = X2 * Y0 + X0 * Y2;
+  // subdomain-local inputs xbar = (x - mu)/sigma
+  const int jx = (t.blk - g.bbase[l]) / g.J[l][1];
+  const int jy = (t.blk - g.bbase[l]) - jx * g.J[l][1];
+  const double xb = (grid_coord(g, 0, B.ix0 + lx) - centre(g, l, 0, jx)) / sx;
+  const double yb = (g.dim == 2) ? (grid_coord(g, 1, B.iy0 + ly) - centre(g, l, 1, jy)) / sy : 0.0;
+  const double scale = g.inv_scale;
+  const int64_t base = B.a_off + p;
+  const int n = B.n;
+  for (int k = 0; k < K; ++k) {
+    const double z = w1s[k] * xb + w2s[k] * yb + bs[k];
+    const double ph = tanh(z);
+    const double sd = 1.0 - ph * ph;
+    double v;
+    if (OP == ELMFB_OP_NEG_LAPLACE) {
+      v = -(LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k]);
+    } else if (OP == ELMFB_OP_D1) {
+      v = Px * ph + P * sd * c1s[k];
+    } else {
+      v = P * ph;
+    }
+    store_entry<PREC>(A, base + (int64_t)k * n, v * scale);
+  }
+}
+
+__global__ void k_rhs(Geo g, const double* __restrict__ f, double* __restrict__ h,
+                      int32_t* __restrict__ bad) {
+  const double sq = sqrt((double)g.n_rows);
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < g.n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const double v = f[r];
+    if (!isfinite(v)) atomicOr(bad, 1);
+    h[r] = v / sq;
+  }
+}
+
+__global__ void k_points(Geo g, double* __restrict__ xy) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < g.n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(r / g.ny), iy = (int)(r - (int64_t)ix * g.ny);
+    xy[r * g.dim] = grid_coord(g, 0, ix);
+    if (g.dim == 2) xy[r * g.dim + 1] = grid_coord(g, 1, iy);
+  }
+}
+
+hipError_t launch_axis_tables(const Geo& g, const AxisSeg* segs, int n_segs, const int32_t* cov,
+                              double* tab, hipStream_t s) {
+  if (n_segs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axis_tables, dim3(n_segs), dim3(256), 0, s, g, segs, cov, tab);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_assemble_p(const Geo& g, const DevBlock* blocks, const Tile* tiles,
+                                    int64_t n_tiles, const double* tab, const double* W,
+                                    const double* b, void* A, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), blk(256);
+  switch (g.op) {
+    case ELMFB_OP_NEG_LAPLACE:
+      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_NEG_LAPLACE>), grid, blk, 0, s, g, blocks,
+                         tiles, tab, W, b, A);
+      break;
+    case ELMFB_OP_D1:
+      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_D1>), grid, blk, 0, s, g, blocks, tiles, tab,
+                         W, b, A);
+      break;
+    default:
+      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_IDENTITY>), grid, blk, 0, s, g, blocks, tiles,
+                         tab, W, b, A);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+                           int64_t n_tiles, const double* tab, const double* W, const double* b,
+                           void* A, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  if (prec == ELMFB_FP32) return launch_assemble_p<ELMFB_FP32>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
+  if (prec == ELMFB_BF16) return launch_assemble_p<ELMFB_BF16>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
+  return launch_assemble_p<ELMFB_FP64>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
+}
+
+hipError_t launch_rhs(const Geo& g, const double* f, double* h, int32_t* bad, hipStream_t s) {
+  int64_t nb = (g.n_rows + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, g, f, h, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_points(const Geo& g, double* xy, hipStream_t s) {
+  int64_t nb = (g.n_rows + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_points, dim3((unsigned)nb), dim3(256), 0, s, g, xy);
+  return hipGetLastError();
+}
+
+}  // namespace elmfb

@@ -1,0 +1,239 @@
+// Block-sparse products with the assembled matrix M = sum_j V_j^T M_j W_j (Sec. 3
+// eq. multilevel_domain_decomp), each block M_j stored feature-major [K][n_j].
+//
+// y = M v runs in two passes that stream the matrix exactly once:
+//   1. per block point (one thread each, consecutive points on consecutive lanes):
+//      t_j[p] = sum_k M_j[k][p] v[q0_j + k] -- the K coefficients of the block are
+//      wavefront-uniform, so they come from the scalar cache;
+//   2. per row (grid point): y_r = sum over the blocks covering it of t_j[p_j(r)], the covering
+//      blocks found arithmetically from per-axis index ranges; no atomics, fixed order.
+// x = M^T u also streams the matrix once:
+//   1. per chunk of <= 2048 consecutive points of one block: each thread holds 8 gathered
+//      u values; for every feature k the 256 lanes form their dot products and a fixed-order
+//      wavefront reduction (cross-lane shuffles) plus a 4-wave LDS sum gives the chunk partial;
+//   2. per column: sum of the chunk partials of its block in chunk order.
+// All reductions are deterministic (fixed order, no floating-point atomics).
+#include "device.h"
+#include "kernels.h"
+
+namespace elmfb {
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __restrict__ blocks,
+                                                   const Tile* __restrict__ tiles,
+                                                   const void* __restrict__ A,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ vscale,
+                                                   double* __restrict__ tpart,
+                                                   const SolveState* __restrict__ st) {
+  if (st && st->done) return;
+  const Tile t = tiles[blockIdx.x];
+  const DevBlock B = blocks[t.blk];
+  const int p = t.p0 + threadIdx.x;
+  if (p >= B.n) return;
+  const double* vb = v + B.q0;
+  const int K = g.K;
+  const int n = B.n;
+  const int64_t base = B.a_off + p;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= K; k += 4) {
+    acc0 += load_entry<PREC>(A, base + (int64_t)(k + 0) * n) * vb[k + 0];
+    acc1 += load_entry<PREC>(A, base + (int64_t)(k + 1) * n) * vb[k + 1];
+    acc2 += load_entry<PREC>(A, base + (int64_t)(k + 2) * n) * vb[k + 2];
+    acc3 += load_entry<PREC>(A, base + (int64_t)(k + 3) * n) * vb[k + 3];
+  }
+  for (; k < K; ++k) acc0 += load_entry<PREC>(A, base + (int64_t)k * n) * vb[k];
+  const double sc = vscale ? *vscale : 1.0;
+  tpart[B.p_off + p] = ((acc0 + acc1) + (acc2 + acc3)) * sc;
+}
+
+__global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __restrict__ blocks,
+                                                     const int32_t* __restrict__ cov,
+                                                     const double* __restrict__ tpart, int mode,
+                                                     double* __restrict__ out,
+                                                     const double* __restrict__ bvec,
+                                                     const SolveState* __restrict__ st,
+                                                     double* __restrict__ red) {
+  __shared__ double sh[4];
+  if (st && st->done) return;
+  double coef_u = 0.0;
+  if (mode == ROW_LSQR_U) coef_u = st->alpha * st->su;
+  double acc = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < g.n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(r / g.ny), iy = (int)(r - (int64_t)ix * g.ny);
+    double y = 0.0;
+    for (int l = 0; l < g.n_levels; ++l) {
+      const int jx0 = cov[g.cov_off[l][0] + 2 * ix], jx1 = cov[g.cov_off[l][0] + 2 * ix + 1];
+      const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
+      const int Jy = g.J[l][1];
+      for (int jx = jx0; jx <= jx1; ++jx) {
+        for (int jy = jy0; jy <= jy1; ++jy) {
+          const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
+          const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
+          y += tpart[B.p_off + p];
+        }
+      }
+    }
+    if (mode == ROW_STORE) {
+      out[r] = y;
+    } else if (mode == ROW_LSQR_U) {
+      const double u = y - coef_u * out[r];
+      out[r] = u;
+      acc += u * u;
+    } else if (mode == ROW_RESID) {
+      const double u = bvec[r] - y;
+      out[r] = u;
+      acc += u * u;
+    } else {
+      out[r] = y;
+      acc += y * y;
+    }
+  }
+  if (mode != ROW_STORE) {
+    const double s = block_sum256(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __restrict__ blocks,
+                                                    const Tile* __restrict__ chunks,
+                                                    const void* __restrict__ A,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ uscale,
+                                                    double* __restrict__ part,
+                                                    const SolveState* __restrict__ st) {
+  constexpr int PPT = kChunkPts / 256;
+  __shared__ double sred[4][256];
+  if (st && st->done) return;
+  const Tile c = chunks[blockIdx.x];
+  const DevBlock B = blocks[c.blk];
+  const int K = g.K;
+  const double sc = uscale ? *uscale : 1.0;
+  double uv[PPT];
+  int64_t idx[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int p = c.p0 + i * 256 + threadIdx.x;
+    if (p < B.n) {
+      const int lx = p / B.ny, ly = p - lx * B.ny;
+      const int64_t r = (int64_t)(B.ix0 + lx) * g.ny + (B.iy0 + ly);
+      uv[i] = u[r] * sc;
+      idx[i] = B.a_off + p;
+    } else {
+      uv[i] = 0.0;
+      idx[i] = -1;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int n = B.n;
+  for (int k = 0; k < K; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      if (idx[i] >= 0) acc += load_entry<PREC>(A, idx[i] + (int64_t)k * n) * uv[i];
+    acc = wave_sum(acc);
+    if (lane == 0) sred[wid][k] = acc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += 256)
+    part[(int64_t)blockIdx.x * K + k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
+}
+
+__global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __restrict__ cstart,
+                                                    const double* __restrict__ part, int mode,
+                                                    double* __restrict__ out,
+                                                    const SolveState* __restrict__ st,
+                                                    double* __restrict__ red) {
+  __shared__ double sh[4];
+  if (st && st->done) return;
+  const int K = g.K;
+  double coef_v = 0.0;
+  bool keep = false;
+  if (mode == COL_LSQR_V) {
+    coef_v = st->beta * st->sv;
+    keep = !(st->beta > 0.0);   // beta == 0: v and alpha stay as they are
+  }
+  double acc = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < g.n_phi;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(q / K), k = (int)(q - (int64_t)b * K);
+    double x = 0.0;
+    for (int c = cstart[b]; c < cstart[b + 1]; ++c) x += part[(int64_t)c * K + k];
+    if (mode == COL_STORE) {
+      out[q] = x;
+    } else if (mode == COL_LSQR_V) {
+      double v = out[q];
+      if (!keep) {
+        v = x - coef_v * v;
+        out[q] = v;
+      }
+      acc += v * v;
+    } else {
+      out[q] = x;
+      acc += x * x;
+    }
+  }
+  if (mode != COL_STORE) {
+    const double s = block_sum256(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+  }
+}
+
+int rows_wg(const Geo& g) {
+  int64_t nb = (g.n_rows + 255) / 256;
+  return (int)(nb < kRedBlocks ? nb : kRedBlocks);
+}
+int cols_wg(const Geo& g) {
+  int64_t nb = (g.n_phi + 255) / 256;
+  return (int)(nb < kRedBlocks ? nb : kRedBlocks);
+}
+
+hipError_t launch_mv_blocks(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+                            int64_t n_tiles, const void* A, const double* v, const double* vscale,
+                            double* tpart, const SolveState* st, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)n_tiles), blk(256);
+  if (prec == ELMFB_FP32)
+    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
+  else if (prec == ELMFB_BF16)
+    hipLaunchKernelGGL(k_mv_blocks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
+  else
+    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const Geo& g, const DevBlock* blocks, const int32_t* cov,
+                              const double* tpart, int mode, double* out, const double* bvec,
+                              const SolveState* st, double* red, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(n_wg), dim3(256), 0, s, g, blocks, cov, tpart, mode, out,
+                     bvec, st, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, const Tile* chunks,
+                             int64_t n_chunks, const void* A, const double* u,
+                             const double* uscale, double* part, const SolveState* st,
+                             hipStream_t s) {
+  if (n_chunks == 0) return hipSuccess;
+  const dim3 grid((unsigned)n_chunks), blk(256);
+  if (prec == ELMFB_FP32)
+    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
+  else if (prec == ELMFB_BF16)
+    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
+  else
+    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
+                             int mode, double* out, const SolveState* st, double* red, int n_wg,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rmv_finish, dim3(n_wg), dim3(256), 0, s, g, chunk_start, part, mode, out,
+                     st, red);
+  return hipGetLastError();
+}
+
+}  // namespace elmfb

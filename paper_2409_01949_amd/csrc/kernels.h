@@ -1,0 +1,81 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.h"
+
+namespace elmfb {
+
+// Axis segment: the grid range one subdomain covers along one axis of one level.
+struct AxisSeg {
+  int32_t level, axis, j, m0, m1, tab_off;
+};
+
+// ---- assembly (k_assemble.hip)
+hipError_t launch_axis_tables(const Geo& g, const AxisSeg* segs, int n_segs, const int32_t* cov,
+                              double* tab, hipStream_t s);
+hipError_t launch_assemble(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+                           int64_t n_tiles, const double* tab, const double* W, const double* b,
+                           void* A, hipStream_t s);
+hipError_t launch_rhs(const Geo& g, const double* f, double* h, int32_t* bad, hipStream_t s);
+hipError_t launch_points(const Geo& g, double* xy, hipStream_t s);
+
+// ---- block-sparse products (k_matvec.hip)
+enum RowMode { ROW_STORE = 0, ROW_LSQR_U = 1, ROW_RESID = 2, ROW_STORE_SQ = 3 };
+enum ColMode { COL_STORE = 0, COL_LSQR_V = 1, COL_STORE_SQ = 2 };
+
+// stage 1 of y = A v: per block point t[p] = sum_k A[k][p] v[q0+k] * (*vscale)
+hipError_t launch_mv_blocks(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+                            int64_t n_tiles, const void* A, const double* v, const double* vscale,
+                            double* tpart, const SolveState* st, hipStream_t s);
+// stage 2: y[r] = sum over covering blocks of t, then the row epilogue; partial sums of squares
+// into red[0..n_wg)
+hipError_t launch_gather_rows(const Geo& g, const DevBlock* blocks, const int32_t* cov,
+                              const double* tpart, int mode, double* out, const double* bvec,
+                              const SolveState* st, double* red, int n_wg, hipStream_t s);
+// stage 1 of x = A^T u: per chunk partial dot products [n_chunks][K]
+hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, const Tile* chunks,
+                             int64_t n_chunks, const void* A, const double* u,
+                             const double* uscale, double* part, const SolveState* st,
+                             hipStream_t s);
+// stage 2: x[q] = sum over the block's chunks, then the column epilogue
+hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
+                             int mode, double* out, const SolveState* st, double* red, int n_wg,
+                             hipStream_t s);
+int rows_wg(const Geo& g);
+int cols_wg(const Geo& g);
+
+// ---- Krylov recurrences (k_solver.hip)
+hipError_t launch_sumsq(const double* x, int64_t n, double* red, int n_wg, hipStream_t s);
+hipError_t launch_lsqr_init(SolveState* st, const double* red_b, int nb, const double* red_u,
+                            int nu, hipStream_t s);
+hipError_t launch_lsqr_init_alpha(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_init_xw(const Geo& g, const double* x0, double* x, double* w, const double* v,
+                          const SolveState* st, hipStream_t s);
+hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_lsqr_update(const Geo& g, double* x, double* w, const double* v,
+                              const SolveState* st, double* red, int n_wg, hipStream_t s);
+hipError_t launch_lsqr_stop(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_cgls_init(SolveState* st, const double* red_b, int nb, const double* red_r,
+                            int nr, const double* red_s, int ns, double anorm_f, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+hipError_t launch_cgls_step_a(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_cgls_update_x(const Geo& g, double* x, const double* p, const SolveState* st,
+                                hipStream_t s);
+hipError_t launch_cgls_update_r(const Geo& g, double* r, const double* t, const SolveState* st,
+                                double* red, int n_wg, hipStream_t s);
+hipError_t launch_cgls_step_b(SolveState* st, const double* red_r, int nr, const double* red_s,
+                              int ns, hipStream_t s);
+hipError_t launch_cgls_update_p(const Geo& g, double* p, const double* sv, const SolveState* st,
+                                hipStream_t s);
+hipError_t launch_sumsq_entries(int prec, const void* A, int64_t n, double* red, int n_wg,
+                                hipStream_t s);
+hipError_t launch_reduce_to(const double* red, int n, double* out, hipStream_t s);
+
+// ---- evaluation (k_evaluate.hip)
+hipError_t launch_evaluate(const Geo& g, const double* W, const double* b, const double* coef,
+                           const double* pts, int64_t n_pts, double* u, hipStream_t s);
+hipError_t launch_check_rel_l2(const double* u, const double* ref, int64_t n, SolveState* st,
+                               double* red, int n_wg, hipStream_t s);
+
+}  // namespace elmfb

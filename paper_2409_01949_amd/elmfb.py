@@ -1,0 +1,288 @@
+"""ctypes binding of libelmfb.so: the C ABI of include/elmfb.h with the same names.
+
+Argument marshalling only: every step of the computation runs in the library's HIP kernels.
+Device buffers are torch CUDA (HIP) tensors; their data pointers are handed to the library and
+the current torch stream is used unless a stream handle is given.  There is no fallback: if the
+library is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libelmfb.so")
+
+ABI_VERSION = 1
+MAX_LEVELS = 8
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = range(7)
+OP_D1, OP_NEG_LAPLACE, OP_IDENTITY = 1, 2, 3
+ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
+FP64, FP32, BF16 = 0, 1, 2
+LSQR, CGLS = 0, 1
+
+_OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY}
+_ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_METHOD = {"lsqr": LSQR, "cgls": CGLS}
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("ansatz", ctypes.c_int32),
+        ("ansatz_omega", ctypes.c_double),
+        ("lo", ctypes.c_double * 2),
+        ("hi", ctypes.c_double * 2),
+        ("n_points", ctypes.c_int32 * 2),
+        ("n_levels", ctypes.c_int32),
+        ("J", (ctypes.c_int32 * 2) * MAX_LEVELS),
+        ("delta", ctypes.c_double),
+        ("K", ctypes.c_int32),
+        ("store_prec", ctypes.c_int32),
+        ("W_host", ctypes.POINTER(ctypes.c_double)),
+        ("b_host", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_rows", "n_phi", "nnz", "n_blocks", "n_block_points", "bytes_device")]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("iter_lim", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("atol", ctypes.c_double),
+        ("btol", ctypes.c_double),
+        ("x0_dev", ctypes.c_void_p),
+        ("check_pts_dev", ctypes.c_void_p),
+        ("check_ref_dev", ctypes.c_void_p),
+        ("n_check", ctypes.c_int64),
+        ("target_rel_l2", ctypes.c_double),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("istop", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rnorm", ctypes.c_double),
+        ("arnorm", ctypes.c_double),
+        ("anorm", ctypes.c_double),
+        ("xnorm", ctypes.c_double),
+        ("rel_l2", ctypes.c_double),
+        ("ms_solve", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ElmfbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"elmfb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libelmfb.so (built in-tree by build.py) and declare the ABI signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2409_01949_amd/build.py")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7); load it first
+    # so that the library and torch's device allocations share one runtime in this process.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "elmfb_define_problem": (i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]),
+        "elmfb_query": (i32, [P, ctypes.POINTER(Sizes)]),
+        "elmfb_points": (i32, [P, P, P]),
+        "elmfb_assemble": (i32, [P, P, P]),
+        "elmfb_matvec": (i32, [P, P, P, P]),
+        "elmfb_rmatvec": (i32, [P, P, P, P]),
+        "elmfb_copy_rhs": (i32, [P, P, P]),
+        "elmfb_copy_blocks": (i32, [P, P, ctypes.POINTER(i64), P]),
+        "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
+        "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
+        "elmfb_time_kernels": (i32, [P, i32, ctypes.POINTER(dbl), P]),
+        "elmfb_destroy": (None, [P]),
+        "elmfb_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_cuda:
+            raise ValueError("device tensor required")
+        if not t.is_contiguous():
+            raise ValueError("contiguous tensor required")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(stream):
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(code, handle=None):
+    if code != OK:
+        msg = _lib.elmfb_last_error(handle)
+        raise ElmfbError(code, msg.decode() if msg else "")
+
+
+def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K, W, b,
+              store_prec="fp64"):
+    """Descriptor from plain values.  W [n_phi, dim] and b [n_phi] are float64 host arrays;
+    the returned tuple keeps them alive for the duration of the define call."""
+    d = ProblemDesc()
+    d.abi_version = ABI_VERSION
+    d.dim = int(dim)
+    d.op = _OPS[op] if isinstance(op, str) else int(op)
+    d.ansatz = _ANSATZ[ansatz] if isinstance(ansatz, str) else int(ansatz)
+    d.ansatz_omega = float(ansatz_omega)
+    for a in range(2):
+        d.lo[a] = float(lo[a]) if a < len(lo) else 0.0
+        d.hi[a] = float(hi[a]) if a < len(hi) else 1.0
+        d.n_points[a] = int(n_points[a]) if a < len(n_points) else 1
+    d.n_levels = len(levels)
+    for l, J in enumerate(levels[:MAX_LEVELS]):
+        for a in range(2):
+            d.J[l][a] = int(J[a]) if a < len(J) else 1
+    d.delta = float(delta)
+    d.K = int(K)
+    d.store_prec = _PREC[store_prec] if isinstance(store_prec, str) else int(store_prec)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    d.W_host = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.b_host = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, (W, b)
+
+
+def desc_from_spec(spec, W, b, store_prec="fp64"):
+    """Descriptor from any object with the problem-specification attributes."""
+    return make_desc(spec.dim, spec.op, spec.ansatz, spec.ansatz_omega, spec.lo, spec.hi,
+                     spec.n_points, spec.levels, spec.delta, spec.K, W, b, store_prec)
+
+
+def define_problem(desc_and_keep) -> "Problem":
+    lib = load_library()
+    desc, keep = desc_and_keep
+    h = ctypes.c_void_p()
+    code = lib.elmfb_define_problem(ctypes.byref(desc), ctypes.byref(h))
+    del keep
+    if code != OK:
+        msg = lib.elmfb_last_error(None)
+        raise ElmfbError(code, msg.decode() if msg else "")
+    return Problem(h)
+
+
+class Problem:
+    """Owns one elmfb_problem handle."""
+
+    def __init__(self, handle):
+        self.h = handle
+        self.sizes = self.query()
+
+    @classmethod
+    def from_spec(cls, spec, W, b, store_prec="fp64"):
+        return define_problem(desc_from_spec(spec, W, b, store_prec))
+
+    def query(self):
+        s = Sizes()
+        _check(_lib.elmfb_query(self.h, ctypes.byref(s)), self.h)
+        return {n: getattr(s, n) for n, _ in Sizes._fields_}
+
+    def points(self, xy, stream=None):
+        _check(_lib.elmfb_points(self.h, _ptr(xy), _stream(stream)), self.h)
+
+    def assemble(self, f, stream=None):
+        _check(_lib.elmfb_assemble(self.h, _ptr(f), _stream(stream)), self.h)
+
+    def matvec(self, v, y, stream=None):
+        _check(_lib.elmfb_matvec(self.h, _ptr(v), _ptr(y), _stream(stream)), self.h)
+
+    def rmatvec(self, u, x, stream=None):
+        _check(_lib.elmfb_rmatvec(self.h, _ptr(u), _ptr(x), _stream(stream)), self.h)
+
+    def copy_rhs(self, hvec, stream=None):
+        _check(_lib.elmfb_copy_rhs(self.h, _ptr(hvec), _stream(stream)), self.h)
+
+    def copy_blocks(self, dst=None, stream=None):
+        """Returns the block table [n_blocks, 8] (int64); copies raw blocks into dst if given."""
+        nb = self.sizes["n_blocks"]
+        table = np.zeros((nb, 8), dtype=np.int64)
+        _check(_lib.elmfb_copy_blocks(self.h, _ptr(dst) if dst is not None else None,
+                                      table.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      _stream(stream)), self.h)
+        return table
+
+    def solve(self, coef, method="lsqr", iter_lim=15000, atol=1e-8, btol=1e-8, check_every=50,
+              use_graph=True, x0=None, check_pts=None, check_ref=None, target_rel_l2=0.0,
+              stream=None):
+        o = SolveOpts()
+        o.method = _METHOD[method] if isinstance(method, str) else int(method)
+        o.iter_lim = int(iter_lim)
+        o.check_every = int(check_every)
+        o.use_graph = 1 if use_graph else 0
+        o.atol = float(atol)
+        o.btol = float(btol)
+        o.x0_dev = _ptr(x0)
+        o.check_pts_dev = _ptr(check_pts)
+        o.check_ref_dev = _ptr(check_ref)
+        o.n_check = int(check_ref.numel()) if check_ref is not None else 0
+        o.target_rel_l2 = float(target_rel_l2)
+        info = SolveInfo()
+        _check(_lib.elmfb_solve(self.h, ctypes.byref(o), _ptr(coef), ctypes.byref(info),
+                                _stream(stream)), self.h)
+        return info.as_dict()
+
+    def evaluate(self, coef, pts, u, stream=None):
+        n = pts.shape[0]
+        _check(_lib.elmfb_evaluate(self.h, _ptr(coef), _ptr(pts), int(n), _ptr(u),
+                                   _stream(stream)), self.h)
+
+    def time_kernels(self, reps=20, stream=None):
+        """Average duration (ms) of one launch of the M v and M^T u streaming kernels."""
+        out = (ctypes.c_double * 2)()
+        _check(_lib.elmfb_time_kernels(self.h, int(reps), out, _stream(stream)), self.h)
+        return float(out[0]), float(out[1])
+
+    def destroy(self):
+        if self.h is not None and _lib is not None:
+            _lib.elmfb_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

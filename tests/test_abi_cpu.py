@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every entry point that include/elmfb.h declares, and rejects
+bad descriptors before touching the device (no compute calls here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from inputs import configs, feature_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elmfb.h")
+
+
+def _declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(elmfb_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    names = _declared_symbols()
+    assert "elmfb_define_problem" in names and "elmfb_solve" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", elmfb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\s([A-Za-z_][A-Za-z_0-9]*)$", out, flags=re.M))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def _spec_desc(**over):
+    from paper_2409_01949_amd import elmfb
+    spec = configs.small2d()
+    W, b = feature_params(spec)
+    d, keep = elmfb.desc_from_spec(spec, W, b)
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("dim", 3), ("op", 1), ("op", 7), ("ansatz", 5), ("delta", 0.9),
+    ("delta", 7.5), ("K", 0), ("K", 257), ("n_levels", 0), ("n_levels", 9), ("store_prec", 3),
+])
+def test_invalid_descriptors_are_rejected(field, value):
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    d, keep = _spec_desc(**{field: value})
+    h = ctypes.c_void_p()
+    code = lib.elmfb_define_problem(ctypes.byref(d), ctypes.byref(h))
+    assert code == elmfb.E_INVALID
+    assert h.value is None
+    assert lib.elmfb_last_error(None)
+
+
+def test_missing_feature_arrays_rejected():
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    d, keep = _spec_desc()
+    d.W_host = None
+    h = ctypes.c_void_p()
+    assert lib.elmfb_define_problem(ctypes.byref(d), ctypes.byref(h)) == elmfb.E_INVALID
+
+
+def test_memory_cap_gives_nomem_before_any_allocation(monkeypatch):
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    monkeypatch.setenv("ELMFB_MEM_CAP", "1000")
+    d, keep = _spec_desc()
+    h = ctypes.c_void_p()
+    assert lib.elmfb_define_problem(ctypes.byref(d), ctypes.byref(h)) == elmfb.E_NOMEM
+    assert b"ELMFB_MEM_CAP" in lib.elmfb_last_error(None)
+
+
+def test_null_arguments():
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    assert lib.elmfb_define_problem(None, None) == elmfb.E_INVALID
+    assert lib.elmfb_query(None, None) == elmfb.E_INVALID
+    lib.elmfb_destroy(None)
+
+
+def test_no_device_gives_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2409_01949_amd import elmfb
+    lib = elmfb.load_library()
+    d, keep = _spec_desc()
+    h = ctypes.c_void_p()
+    assert lib.elmfb_define_problem(ctypes.byref(d), ctypes.byref(h)) == elmfb.E_DEVICE
