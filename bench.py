@@ -33,7 +33,12 @@ def parse():
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="poisson3l")
-    p.add_argument("--method", default="lsqr", choices=["lsqr", "cgls"])
+    p.add_argument("--method", default="lsqr", choices=["lsqr", "cgls", "mixed_ir"])
+    p.add_argument("--precond", action="store_true", help="block-Jacobi from diagonal Gram blocks")
+    p.add_argument("--shift", type=float, default=1e-12)
+    p.add_argument("--store", default="fp64", choices=["fp64", "fp32", "bf16"],
+                   help="low-precision stored copy for the inner solves of mixed_ir")
+    p.add_argument("--inner", type=int, default=200)
     p.add_argument("--iters", type=int, default=15000)
     p.add_argument("--target", type=float, default=1e-6)
     p.add_argument("--check-every", type=int, default=100)
@@ -125,7 +130,7 @@ def main():
     spec = getattr(configs, args.workload)()
     W, b = feature_params(spec)
     f = configs.forcing(spec)
-    P = Problem.from_spec(spec, W, b, "fp64")
+    P = Problem.from_spec(spec, W, b, args.store)
     fd = torch.as_tensor(f).cuda()
     xc = torch.as_tensor(grid_points(spec, spec.meta["n_check"])).cuda()
     uc_np = configs.exact(spec, grid_points(spec, spec.meta["n_check"]))
@@ -139,9 +144,17 @@ def main():
 
     def step():
         P.assemble(fd)
-        info = P.solve(coef, method=args.method, iter_lim=args.iters, atol=0.0, btol=0.0,
-                       check_every=args.check_every, check_pts=xc, check_ref=uc,
-                       target_rel_l2=args.target)
+        if args.precond:
+            P.precondition(args.shift)
+        if args.method == "mixed_ir":
+            info = P.solve(coef, method="mixed_ir", inner_iters=args.inner,
+                           outer_lim=max(1, args.iters // args.inner), atol=0.0, btol=0.0,
+                           check_every=min(args.check_every, args.inner), check_pts=xc,
+                           check_ref=uc, target_rel_l2=args.target, precond=args.precond)
+        else:
+            info = P.solve(coef, method=args.method, iter_lim=args.iters, atol=0.0, btol=0.0,
+                           check_every=args.check_every, check_pts=xc, check_ref=uc,
+                           target_rel_l2=args.target, precond=args.precond)
         P.evaluate(coef, xt, u_test)
         return info
 
@@ -176,16 +189,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.method != "mixed_ir" else f"f64+{args.store}",
         "data": "synthetic",
         "config": {"workload": spec.name, "rows": spec.n_rows, "cols": n, "nnz": nnz,
                    "levels": [list(J) for J in spec.levels], "K": spec.K,
-                   "grid": list(spec.n_points), "method": f"{args.method}-fp64",
+                   "grid": list(spec.n_points),
+                   "method": (f"{args.method}" + ("+block-jacobi" if args.precond else "") +
+                              (f" (inner {args.store} x{args.inner})" if args.method == "mixed_ir"
+                               else "-fp64")),
                    "iter_budget": args.iters, "target_rel_l2": args.target,
                    "reference": "exact solution on the 128x128 check grid"},
         "time_to_solution_s": dt,
         "reached_target": bool(info["istop"] == 8),
         "iters": info["iters"],
+        "outer_iters": info["outer_iters"],
         "rel_l2_check_at_stop": info["rel_l2"],
         "rel_l2_test_vs_exact": rel_test,
         "e_l1_test": e_l1,

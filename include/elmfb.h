@@ -70,7 +70,10 @@ enum { ELMFB_FP64 = 0, ELMFB_FP32 = 1, ELMFB_BF16 = 2 };
  * same matrix). */
 enum {
   ELMFB_LSQR = 0,       /* Paige-Saunders LSQR on block-sparse A v / A^T u, FP64 recurrences  */
-  ELMFB_CGLS = 1        /* CG on the normal equations in factored form, FP64                 */
+  ELMFB_CGLS = 1,       /* CG on the normal equations in factored form, FP64                 */
+  ELMFB_MIXED_IR = 2    /* FP64 iterative refinement: r = h - A c with the FP64 matrix, the
+                           correction from inner_iters LSQR steps on the stored FP32/BF16 copy
+                           (FP64 vectors and recurrences), c += d in FP64                     */
 };
 
 typedef struct elmfb_problem_s* elmfb_problem;
@@ -93,7 +96,10 @@ typedef struct {
   int32_t J[ELMFB_MAX_LEVELS][2];    /* subdomains per axis per level, >= 1                  */
   double delta;                      /* width ratio, > 0                                     */
   int32_t K;                         /* features per subdomain, 1..256                       */
-  int32_t store_prec;                /* precision of the stored matrix: ELMFB_FP64/FP32/BF16 */
+  int32_t store_prec;                /* extra low-precision copy of the matrix for inner
+                                        solves: ELMFB_FP32 or ELMFB_BF16 (rounded to nearest
+                                        even from FP64); ELMFB_FP64 = no copy.  The FP64
+                                        matrix is always stored.                            */
   const double* W_host;              /* [n_phi][dim]                                         */
   const double* b_host;              /* [n_phi]                                              */
 } elmfb_problem_desc;
@@ -105,6 +111,7 @@ typedef struct {
   int64_t n_blocks;        /* subdomains over all levels                                    */
   int64_t n_block_points;  /* sum_j |I_j|                                                   */
   int64_t bytes_device;    /* device memory held by the handle                              */
+  int64_t n_pairs;         /* overlapping subdomain pairs (i <= j), all levels               */
 } elmfb_sizes;
 
 typedef struct {
@@ -112,6 +119,10 @@ typedef struct {
   int32_t iter_lim;        /* maximum iterations (>= 0)                                     */
   int32_t check_every;     /* iterations per captured graph replay / host check, >= 1       */
   int32_t use_graph;       /* 1: capture the iteration loop in a hipGraph and replay it     */
+  int32_t precond;         /* 1: right block-Jacobi preconditioning (LSQR and MIXED_IR);
+                              needs elmfb_precondition first                               */
+  int32_t inner_iters;     /* MIXED_IR: LSQR steps per refinement step (>= 1)               */
+  int32_t outer_lim;       /* MIXED_IR: maximum refinement steps (>= 0)                     */
   double atol, btol;       /* Paige-Saunders stopping tolerances (>= 0); conlim is off      */
   const double* x0_dev;    /* optional warm start [n_phi] (NULL: zero)                      */
   /* optional stop on the solution error: every check_every iterations u_tilde is evaluated
@@ -126,7 +137,8 @@ typedef struct {
 typedef struct {
   int32_t istop;           /* 0 x0 exact, 1 ||r|| test, 2 ||A^T r|| test, 4/5 the same at
                               machine precision, 7 iteration limit, 8 rel-L2 target reached */
-  int32_t iters;
+  int32_t iters;           /* Krylov iterations (MIXED_IR: inner iterations in total)       */
+  int32_t outer_iters;     /* MIXED_IR refinement steps                                     */
   double rnorm;            /* ||h - A x|| (LSQR estimate / CGLS recurrence)                  */
   double arnorm;           /* ||A^T (h - A x)||                                              */
   double anorm;            /* LSQR Frobenius-norm estimate; CGLS: exact ||A||_F              */
@@ -165,11 +177,12 @@ elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, 
 /* Copy the assembled right-hand side h [n_rows] (FP64). */
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
 
-/* Copy the stored blocks (in the stored precision, raw bytes, blocks in column order, each
- * [K][|I_j|] with the block's points in row-major order of its box) into dst_dev, and the
- * block table into table_host [n_blocks][8] as int64: level, jx, jy, ix0, nx, iy0, ny,
- * element offset of the block. */
-elmfb_status elmfb_copy_blocks(elmfb_problem h, void* dst_dev, int64_t* table_host,
+/* Copy the stored blocks of the FP64 matrix (prec = ELMFB_FP64) or of its low-precision copy
+ * (prec = the descriptor's store_prec) as raw values, blocks in column order, each [K][|I_j|]
+ * with the block's points in row-major order of its box, into dst_dev; and the block table
+ * into table_host [n_blocks][8] as int64: level, jx, jy, ix0, nx, iy0, ny, element offset.
+ * Either pointer may be NULL. */
+elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int64_t* table_host,
                                void* stream);
 
 /* Solve min ||M x - h|| (Sec. 3 eq. multilevel_ls) into coef_dev [n_phi].  LSQR follows
@@ -178,6 +191,29 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, void* dst_dev, int64_t* table_ho
  * info_host may be NULL. */
 elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
                          elmfb_solve_info* info_host, void* stream);
+
+/* Gram blocks G_ij = M_i^T M_j over the rows shared by subdomains i and j (the normal
+ * equations of Sec. 3 eq. multilevel_ls restricted by eq. multilevel_domain_decomp), computed
+ * on the matrix cores from the matrix copy of precision `prec` (ELMFB_FP64: the FP64 matrix,
+ * FP64 products; ELMFB_FP32 / ELMFB_BF16: the stored low-precision copy, FP32 accumulation).
+ * which = 0: diagonal blocks only; 1: every overlapping pair i <= j.  The blocks are held by
+ * the handle (FP64 or FP32) until the next elmfb_gram call. */
+elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stream);
+
+/* Copy the Gram blocks of the last elmfb_gram call (n_pairs x K x K values, FP64 for
+ * prec = FP64 else FP32, row index = feature of i) into dst_dev and the pair table
+ * [n_pairs][3] (bi, bj, element offset) into pairs_host; *n_pairs_host receives the count.
+ * Either pointer may be NULL. */
+elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host,
+                             int64_t* n_pairs_host, void* stream);
+
+/* Build the block-Jacobi preconditioner used by opts.precond: for every subdomain the upper
+ * Cholesky factor R_j of G_jj + lambda_j I, lambda_j = shift * trace(G_jj)/K, from FP64 Gram
+ * blocks, and R_j^{-1}.  A block that does not factor is retried with 100x the shift up to 8
+ * times, then replaced by the identity; *n_fallback_host (may be NULL) receives that count.
+ * shift must be > 0.  Blocks until done. */
+elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback_host,
+                                void* stream);
 
 /* u_dev [n_pts] = C(x) (1/L) sum_l sum_j omega_j(x) sum_k coef_q phi_q(x) at arbitrary points
  * pts_dev [n_pts][dim] (Sec. 3 eq. multilevel_solution with the hard-constraint factor). */

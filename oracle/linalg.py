@@ -277,3 +277,74 @@ def refine(matvec, rmatvec, h, n, apply_G_lo, n_outer, n_inner, x0=None, lo_dtyp
         if callback is not None and callback(it, c):
             break
     return c, hist
+
+
+# ---------------------------------------------------------------- block-Jacobi preconditioning
+
+def block_jacobi_factors(blocks, shift):
+    """Per subdomain the upper Cholesky factor R_j of G_jj + lambda_j I, lambda_j =
+    shift * trace(G_jj)/K (G_jj = M_j^T M_j).  A factorisation that fails is retried with 100x
+    the shift up to 8 times, then R_j = I; an all-zero block gets R_j = I."""
+    out = []
+    for blk in blocks:
+        K = blk.M.shape[1]
+        G = blk.M.T @ blk.M
+        lam = shift * np.trace(G) / K
+        R = np.eye(K)
+        if lam > 0:
+            for _ in range(8):
+                try:
+                    R = np.linalg.cholesky(G + lam * np.eye(K)).T
+                    break
+                except np.linalg.LinAlgError:
+                    lam *= 100.0
+            else:
+                R = np.eye(K)
+        out.append(R)
+    return out
+
+
+def block_apply(blocks, factors, v, transpose=False, inverse=True):
+    """Apply blockdiag(R_j)^{-1} (or its transpose) to a coefficient vector."""
+    y = np.zeros_like(v)
+    for blk, R in zip(blocks, factors):
+        K = R.shape[0]
+        q = slice(blk.sd.q0, blk.sd.q0 + K)
+        if inverse:
+            y[q] = np.linalg.solve(R.T, v[q]) if transpose else np.linalg.solve(R, v[q])
+        else:
+            y[q] = (R.T @ v[q]) if transpose else (R @ v[q])
+    return y
+
+
+def preconditioned_lsqr(matvec, rmatvec, blocks, factors, h, n, x0=None, **kw):
+    """LSQR on M R^{-1} (right block-Jacobi preconditioning); returns (x, result) with
+    x = x0 + R^{-1} y, y the LSQR solution for the residual h - M x0."""
+    rhs = h if x0 is None else h - matvec(x0)
+    res = lsqr(lambda y: matvec(block_apply(blocks, factors, y)),
+               lambda u: block_apply(blocks, factors, rmatvec(u), transpose=True), rhs, n, **kw)
+    x = block_apply(blocks, factors, res.x)
+    if x0 is not None:
+        x = x + x0
+    return x, res
+
+
+def refine_lsqr(matvec, rmatvec, matvec_lo, rmatvec_lo, h, n, n_outer, n_inner, blocks=None,
+                factors=None, x0=None, callback=None):
+    """FP64 iterative refinement around inner LSQR on a low-precision copy of the matrix:
+    per outer step r = h - M c (float64), d = n_inner LSQR steps on M_lo d = r (float64 vectors,
+    optionally right block-Jacobi preconditioned), c = c + d."""
+    c = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    hist = []
+    for it in range(n_outer):
+        r = h - matvec(c)
+        hist.append(float(np.linalg.norm(r)))
+        if factors is None:
+            d = lsqr(matvec_lo, rmatvec_lo, r, n, atol=0, btol=0, iter_lim=n_inner).x
+        else:
+            d, _ = preconditioned_lsqr(matvec_lo, rmatvec_lo, blocks, factors, r, n, atol=0,
+                                       btol=0, iter_lim=n_inner)
+        c = c + d
+        if callback is not None and callback(it, c):
+            break
+    return c, hist

@@ -1,77 +1,26 @@
-// Host runtime behind the C ABI: descriptor checks, decomposition planner, device memory,
-// assembly, block-sparse products, LSQR/CGLS drivers with hipGraph-captured iteration loops,
-// and evaluation.
+// Host runtime behind the C ABI: descriptor checks, decomposition planner (subdomain boxes on
+// the grid, covering ranges, tiles, chunks, overlapping pairs), device memory, assembly,
+// block-sparse products, copies and evaluation.  The solvers live in solve.hip.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <map>
 #include <string>
 #include <utility>
 #include <vector>
 
-#include "common.h"
-#include "kernels.h"
+#include "handle.h"
 
 // Geometry decisions (grid coordinates, centres, support membership) must reproduce the same
 // doubles on every implementation: no contraction of a*b+c into fused multiply-adds here.
 #pragma clang fp contract(off)
 
-using namespace elmfb;
-
 static thread_local std::string g_thread_error;
 
-struct elmfb_problem_s {
-  elmfb_problem_desc desc{};
-  Geo geo{};
-  int prec = ELMFB_FP64;
-  std::string err;
-
-  // host tables
-  std::vector<DevBlock> blocks;
-  std::vector<Tile> tiles, chunks;
-  std::vector<int32_t> chunk_start, cov;
-  std::vector<AxisSeg> segs;
-  int64_t nnz = 0, n_block_points = 0, n_tab = 0;
-  int64_t bytes_device = 0;
-
-  // device memory
-  std::vector<void*> allocs;
-  DevBlock* d_blocks = nullptr;
-  Tile* d_tiles = nullptr;
-  Tile* d_chunks = nullptr;
-  int32_t* d_cstart = nullptr;
-  int32_t* d_cov = nullptr;
-  AxisSeg* d_segs = nullptr;
-  double* d_tab = nullptr;
-  double* d_W = nullptr;
-  double* d_b = nullptr;
-  void* d_A = nullptr;
-  double* d_h = nullptr;
-  double* d_tpart = nullptr;
-  double* d_part = nullptr;
-  double* d_red = nullptr;      // 4 * kRedBlocks * 2 partial sums
-  double* d_u = nullptr;        // LSQR u / CGLS r
-  double* d_t = nullptr;        // CGLS t = A p
-  double* d_v = nullptr;        // LSQR v / CGLS s
-  double* d_w = nullptr;        // LSQR w / CGLS p
-  double* d_x = nullptr;
-  double* d_scalar = nullptr;   // scratch scalar
-  SolveState* d_state = nullptr;
-  int32_t* d_flag = nullptr;
-  double* d_eval = nullptr;     // solution-check buffer
-  int64_t eval_cap = 0;
-
-  bool assembled = false;
-  double anorm_f = -1.0;        // exact Frobenius norm of the stored matrix (lazy)
-  hipStream_t stream = nullptr; // internal stream for captured solves
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (method, iterations) -> exec
-};
-
-namespace {
+namespace elmfb {
 
 elmfb_status fail(elmfb_problem h, elmfb_status code, const std::string& msg) {
   if (h) h->err = msg;
@@ -79,13 +28,28 @@ elmfb_status fail(elmfb_problem h, elmfb_status code, const std::string& msg) {
   return code;
 }
 
-#define HIP_OR_FAIL(h, expr)                                                             \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail((h), ELMFB_E_DEVICE,                                                   \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));                    \
-  } while (0)
+hipError_t dalloc_bytes(elmfb_problem h, void** p, int64_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)(bytes > 0 ? bytes : 16));
+  if (e != hipSuccess) return e;
+  h->allocs.push_back(q);
+  *p = q;
+  return hipSuccess;
+}
+
+void dfree(elmfb_problem h, void* p) {
+  if (!p) return;
+  for (auto it = h->allocs.begin(); it != h->allocs.end(); ++it)
+    if (*it == p) {
+      hipFree(p);
+      h->allocs.erase(it);
+      return;
+    }
+}
+
+}  // namespace elmfb
+
+namespace {
 
 double grid_x(double lo, double hi, int n, int m) {
   if (n == 1) return lo;
@@ -275,21 +239,55 @@ std::string plan(elmfb_problem h) {
   h->chunk_start.push_back((int32_t)h->chunks.size());
   h->nnz = a_off;
   h->n_block_points = p_off;
+
+  // overlapping pairs (i <= j) over all levels: on level l the subdomains meeting a box are the
+  // covering ranges of its first and last grid index (covering ranges are monotone)
+  h->pairs_all.clear();
+  h->diag_pair.assign(h->blocks.size(), -1);
+  for (size_t i = 0; i < h->blocks.size(); ++i) {
+    const DevBlock& Bi = h->blocks[i];
+    if (Bi.n == 0) continue;
+    const int ix1 = Bi.ix0 + Bi.nx, iy1 = Bi.iy0 + Bi.ny;
+    for (int l = Bi.level; l < d.n_levels; ++l) {
+      const int jx0 = h->cov[g.cov_off[l][0] + 2 * Bi.ix0];
+      const int jx1 = h->cov[g.cov_off[l][0] + 2 * (ix1 - 1) + 1];
+      const int jy0 = h->cov[g.cov_off[l][1] + 2 * Bi.iy0];
+      const int jy1 = h->cov[g.cov_off[l][1] + 2 * (iy1 - 1) + 1];
+      for (int jx = jx0; jx <= jx1; ++jx)
+        for (int jy = jy0; jy <= jy1; ++jy) {
+          const int j = g.bbase[l] + jx * g.J[l][1] + jy;
+          if (j < (int)i) continue;
+          const DevBlock& Bj = h->blocks[j];
+          if (Bj.n == 0) continue;
+          const int ox0 = std::max(Bi.ix0, Bj.ix0), ox1 = std::min(ix1, Bj.ix0 + Bj.nx);
+          const int oy0 = std::max(Bi.iy0, Bj.iy0), oy1 = std::min(iy1, Bj.iy0 + Bj.ny);
+          if (ox1 <= ox0 || oy1 <= oy0) continue;
+          GramPair pr{};
+          pr.bi = (int32_t)i;
+          pr.bj = j;
+          pr.ix0 = ox0;
+          pr.nx = ox1 - ox0;
+          pr.iy0 = oy0;
+          pr.ny = oy1 - oy0;
+          if (j == (int)i) h->diag_pair[i] = (int64_t)h->pairs_all.size();
+          h->pairs_all.push_back(pr);
+        }
+    }
+  }
   return "";
 }
-
-int64_t elem_size(int prec) { return prec == ELMFB_FP64 ? 8 : (prec == ELMFB_FP32 ? 4 : 2); }
 
 int64_t footprint(elmfb_problem h) {
   const Geo& g = h->geo;
   int64_t b = 0;
   auto add = [&](int64_t n) { b += (n + 255) / 256 * 256; };
-  add(h->nnz * elem_size(h->prec));                       // A
+  add(h->nnz * 8);                                        // FP64 matrix
+  if (h->lo_prec != ELMFB_FP64) add(h->nnz * elem_size(h->lo_prec));   // low-precision copy
   add(h->n_block_points * 8);                             // tpart
   add((int64_t)h->chunks.size() * g.K * 8);               // part
   add(4 * 2 * kRedBlocks * 8);                            // reductions
-  add(3 * g.n_rows * 8);                                  // h, u, t
-  add(4 * g.n_phi * 8);                                   // v, w, x + W-side
+  add(4 * g.n_rows * 8);                                  // h, u, t, r
+  add(7 * g.n_phi * 8);                                   // v, w, x, vt, xt, c
   add(g.n_phi * 2 * 8 + g.n_phi * 8);                     // W, b
   add(h->n_tab * 3 * 8);
   add((int64_t)h->blocks.size() * sizeof(DevBlock));
@@ -298,16 +296,6 @@ int64_t footprint(elmfb_problem h) {
   add((int64_t)h->segs.size() * sizeof(AxisSeg));
   add(sizeof(SolveState) + 64);
   return b;
-}
-
-template <typename T>
-hipError_t dalloc(elmfb_problem h, T** p, int64_t bytes) {
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)(bytes > 0 ? bytes : 16));
-  if (e != hipSuccess) return e;
-  h->allocs.push_back(q);
-  *p = static_cast<T*>(q);
-  return hipSuccess;
 }
 
 void release(elmfb_problem h) {
@@ -322,10 +310,6 @@ void release(elmfb_problem h) {
   h->stream = nullptr;
 }
 
-const double* state_field(elmfb_problem h, size_t off) {
-  return reinterpret_cast<const double*>(reinterpret_cast<const char*>(h->d_state) + off);
-}
-
 }  // namespace
 
 extern "C" {
@@ -338,7 +322,7 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   elmfb_problem h = new (std::nothrow) elmfb_problem_s();
   if (!h) return fail(nullptr, ELMFB_E_NOMEM, "host allocation failed");
   h->desc = *desc;
-  h->prec = desc->store_prec;
+  h->lo_prec = desc->store_prec;
   const std::string pe = plan(h);
   if (!pe.empty()) {
     delete h;
@@ -389,7 +373,8 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
                                               hipGetErrorString(e_));      \
     }                                                                       \
   } while (0)
-  ALLOC(h->d_A, h->nnz * elem_size(h->prec));
+  ALLOC(h->d_A, h->nnz * 8);
+  if (h->lo_prec != ELMFB_FP64) ALLOC(h->d_A_lo, h->nnz * elem_size(h->lo_prec));
   ALLOC(h->d_tpart, h->n_block_points * 8);
   ALLOC(h->d_part, (int64_t)h->chunks.size() * g.K * 8);
   ALLOC(h->d_red, 4 * 2 * kRedBlocks * 8);
@@ -399,6 +384,10 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_v, g.n_phi * 8);
   ALLOC(h->d_w, g.n_phi * 8);
   ALLOC(h->d_x, g.n_phi * 8);
+  ALLOC(h->d_vt, g.n_phi * 8);
+  ALLOC(h->d_xt, g.n_phi * 8);
+  ALLOC(h->d_c, g.n_phi * 8);
+  ALLOC(h->d_r, g.n_rows * 8);
   ALLOC(h->d_W, g.n_phi * 2 * 8);
   ALLOC(h->d_b, g.n_phi * 8);
   ALLOC(h->d_tab, h->n_tab * 3 * 8);
@@ -469,6 +458,7 @@ elmfb_status elmfb_query(elmfb_problem h, elmfb_sizes* out) {
   out->n_blocks = h->geo.n_blocks;
   out->n_block_points = h->n_block_points;
   out->bytes_device = h->bytes_device;
+  out->n_pairs = (int64_t)h->pairs_all.size();
   return ELMFB_OK;
 }
 
@@ -484,8 +474,9 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
   const Geo& g = h->geo;
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
   HIP_OR_FAIL(h, launch_rhs(g, f_dev, h->d_h, h->d_flag, s));
-  HIP_OR_FAIL(h, launch_assemble(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
-                                 h->d_tab, h->d_W, h->d_b, h->d_A, s));
+  HIP_OR_FAIL(h, launch_assemble(g, h->lo_prec, h->d_blocks, h->d_tiles,
+                                 (int64_t)h->tiles.size(), h->d_tab, h->d_W, h->d_b, h->d_A,
+                                 h->d_A_lo, s));
   int32_t bad = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&bad, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
@@ -495,6 +486,8 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
   }
   h->assembled = true;
   h->anorm_f = -1.0;
+  h->bj_ready = false;
+  h->gram_prec = -1;
   return ELMFB_OK;
 }
 
@@ -503,7 +496,7 @@ elmfb_status elmfb_matvec(elmfb_problem h, const double* v_dev, double* y_dev, v
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "matvec before assemble");
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->geo;
-  HIP_OR_FAIL(h, launch_mv_blocks(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
+  HIP_OR_FAIL(h, launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
                                   h->d_A, v_dev, nullptr, h->d_tpart, nullptr, s));
   HIP_OR_FAIL(h, launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE, y_dev,
                                     nullptr, nullptr, h->d_red, rows_wg(g), s));
@@ -515,7 +508,7 @@ elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, 
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "rmatvec before assemble");
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->geo;
-  HIP_OR_FAIL(h, launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks,
+  HIP_OR_FAIL(h, launch_rmv_chunks(g, ELMFB_FP64, h->d_blocks, h->d_chunks,
                                    (int64_t)h->chunks.size(), h->d_A, u_dev, nullptr, h->d_part,
                                    nullptr, s));
   HIP_OR_FAIL(h, launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, x_dev, nullptr,
@@ -531,7 +524,7 @@ elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream) {
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_copy_blocks(elmfb_problem h, void* dst_dev, int64_t* table_host,
+elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int64_t* table_host,
                                void* stream) {
   if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
   if (table_host) {
@@ -541,242 +534,25 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, void* dst_dev, int64_t* table_ho
       t[0] = B.level;
       t[1] = (b - (size_t)h->geo.bbase[B.level]) / h->geo.J[B.level][1];
       t[2] = (b - (size_t)h->geo.bbase[B.level]) % h->geo.J[B.level][1];
-      t[3] = B.ix0; t[4] = B.nx; t[5] = B.iy0; t[6] = B.ny; t[7] = B.a_off;
+      t[3] = B.ix0;
+      t[4] = B.nx;
+      t[5] = B.iy0;
+      t[6] = B.ny;
+      t[7] = B.a_off;
     }
   }
   if (dst_dev) {
     if (!h->assembled) return fail(h, ELMFB_E_STATE, "copy_blocks before assemble");
-    HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, h->d_A, (size_t)(h->nnz * elem_size(h->prec)),
+    const void* src = nullptr;
+    if (prec == ELMFB_FP64) src = h->d_A;
+    else if (prec == h->lo_prec && h->d_A_lo) src = h->d_A_lo;
+    else return fail(h, ELMFB_E_STATE, "no stored copy in that precision");
+    HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, src, (size_t)(h->nnz * elem_size(prec)),
                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
   }
   return ELMFB_OK;
 }
 
-}  // extern "C"
-
-// ------------------------------------------------------------------------- solve drivers
-namespace {
-
-hipError_t lsqr_iteration(elmfb_problem h, hipStream_t s) {
-  const Geo& g = h->geo;
-  SolveState* st = h->d_state;
-  double* red1 = h->d_red;
-  double* red2 = h->d_red + 2 * kRedBlocks;
-  double* red3 = h->d_red + 4 * kRedBlocks;
-  const int rw = rows_wg(g), cw = cols_wg(g);
-  hipError_t e;
-  if ((e = launch_mv_blocks(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), h->d_A,
-                            h->d_v, state_field(h, offsetof(SolveState, sv)), h->d_tpart, st, s)))
-    return e;
-  if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
-                              st, red1, rw, s)))
-    return e;
-  if ((e = launch_lsqr_beta(st, red1, rw, s))) return e;
-  if ((e = launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
-                             h->d_A, h->d_u, state_field(h, offsetof(SolveState, su)), h->d_part,
-                             st, s)))
-    return e;
-  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw, s)))
-    return e;
-  if ((e = launch_lsqr_alpha(st, red2, cw, s))) return e;
-  if ((e = launch_lsqr_update(g, h->d_x, h->d_w, h->d_v, st, red3, cw, s))) return e;
-  return launch_lsqr_stop(st, red3, cw, s);
-}
-
-hipError_t cgls_iteration(elmfb_problem h, hipStream_t s) {
-  const Geo& g = h->geo;
-  SolveState* st = h->d_state;
-  double* red1 = h->d_red;
-  double* red2 = h->d_red + 2 * kRedBlocks;
-  double* red3 = h->d_red + 4 * kRedBlocks;
-  const int rw = rows_wg(g), cw = cols_wg(g);
-  hipError_t e;
-  // t = A p
-  if ((e = launch_mv_blocks(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), h->d_A,
-                            h->d_w, nullptr, h->d_tpart, st, s)))
-    return e;
-  if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE_SQ, h->d_t, nullptr,
-                              st, red1, rw, s)))
-    return e;
-  if ((e = launch_cgls_step_a(st, red1, rw, s))) return e;
-  if ((e = launch_cgls_update_x(g, h->d_x, h->d_w, st, s))) return e;
-  if ((e = launch_cgls_update_r(g, h->d_u, h->d_t, st, red2, rw, s))) return e;
-  // s = A^T r
-  if ((e = launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
-                             h->d_A, h->d_u, nullptr, h->d_part, st, s)))
-    return e;
-  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, st, red3, cw, s)))
-    return e;
-  if ((e = launch_cgls_step_b(st, red2, rw, red3, cw, s))) return e;
-  return launch_cgls_update_p(g, h->d_w, h->d_v, st, s);
-}
-
-hipError_t solve_init(elmfb_problem h, int method, const double* x0, hipStream_t s) {
-  const Geo& g = h->geo;
-  double* red1 = h->d_red;
-  double* red2 = h->d_red + 2 * kRedBlocks;
-  double* red3 = h->d_red + 4 * kRedBlocks;
-  double* red4 = h->d_red + 6 * kRedBlocks;
-  const int rw = rows_wg(g), cw = cols_wg(g);
-  hipError_t e;
-  // u (LSQR) or r (CGLS) = h - A x0
-  if (x0) {
-    if ((e = launch_mv_blocks(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
-                              h->d_A, x0, nullptr, h->d_tpart, nullptr, s)))
-      return e;
-    if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_u, h->d_h,
-                                nullptr, red2, rw, s)))
-      return e;
-  } else {
-    if ((e = launch_copy(h->d_h, h->d_u, g.n_rows, s))) return e;
-    if ((e = launch_sumsq(h->d_u, g.n_rows, red2, rw, s))) return e;
-  }
-  if ((e = launch_sumsq(h->d_h, g.n_rows, red1, rw, s))) return e;
-  if (method == ELMFB_LSQR) {
-    if ((e = launch_lsqr_init(h->d_state, red1, rw, red2, rw, s))) return e;
-    if ((e = launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
-                               h->d_A, h->d_u, state_field(h, offsetof(SolveState, su)),
-                               h->d_part, nullptr, s)))
-      return e;
-    if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3, cw,
-                               s)))
-      return e;
-    if ((e = launch_lsqr_init_alpha(h->d_state, red3, cw, s))) return e;
-    return launch_init_xw(g, x0, h->d_x, h->d_w, h->d_v, h->d_state, s);
-  }
-  // CGLS: s = A^T r, p = s, x = x0
-  if ((e = launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
-                             h->d_A, h->d_u, nullptr, h->d_part, nullptr, s)))
-    return e;
-  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3, cw,
-                             s)))
-    return e;
-  (void)red4;
-  if ((e = launch_cgls_init(h->d_state, red1, rw, red2, rw, red3, cw, h->anorm_f, s))) return e;
-  if ((e = launch_copy(h->d_v, h->d_w, g.n_phi, s))) return e;
-  if (x0) return launch_copy(x0, h->d_x, g.n_phi, s);
-  return hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s);
-}
-
-hipError_t enqueue_iterations(elmfb_problem h, int method, int n, hipStream_t s) {
-  for (int i = 0; i < n; ++i) {
-    hipError_t e = method == ELMFB_LSQR ? lsqr_iteration(h, s) : cgls_iteration(h, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t get_graph(elmfb_problem h, int method, int n, hipGraphExec_t* out) {
-  auto key = std::make_pair(method, n);
-  auto it = h->graphs.find(key);
-  if (it != h->graphs.end()) { *out = it->second; return hipSuccess; }
-  hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  hipError_t e2 = enqueue_iterations(h, method, n, h->stream);
-  e = hipStreamEndCapture(h->stream, &graph);
-  if (e2 != hipSuccess) { if (graph) hipGraphDestroy(graph); return e2; }
-  if (e != hipSuccess) return e;
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  if (e != hipSuccess) return e;
-  h->graphs[key] = exec;
-  *out = exec;
-  return hipSuccess;
-}
-
-}  // namespace
-
-extern "C" {
-
-elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
-                         elmfb_solve_info* info, void* stream) {
-  const auto t0 = std::chrono::steady_clock::now();
-  if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
-  if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
-  if (opts->method != ELMFB_LSQR && opts->method != ELMFB_CGLS)
-    return fail(h, ELMFB_E_UNSUPPORTED, "unknown solve method");
-  if (opts->iter_lim < 0 || opts->check_every < 1 || opts->check_every > 100000)
-    return fail(h, ELMFB_E_INVALID, "iter_lim >= 0 and 1 <= check_every <= 100000 required");
-  if (!(opts->atol >= 0.0) || !(opts->btol >= 0.0))
-    return fail(h, ELMFB_E_INVALID, "atol and btol must be >= 0");
-  if (opts->n_check < 0 || (opts->n_check > 0 && (!opts->check_pts_dev || !opts->check_ref_dev)))
-    return fail(h, ELMFB_E_INVALID, "check points need check_pts_dev and check_ref_dev");
-  const Geo& g = h->geo;
-  hipStream_t caller = (hipStream_t)stream;
-  hipStream_t s = h->stream;
-  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, caller));
-  HIP_OR_FAIL(h, hipStreamWaitEvent(s, h->ev_in, 0));
-
-  if (opts->method == ELMFB_CGLS && h->anorm_f < 0.0) {
-    const int nw = kRedBlocks;
-    HIP_OR_FAIL(h, launch_sumsq_entries(h->prec, h->d_A, h->nnz, h->d_red, nw, s));
-    HIP_OR_FAIL(h, launch_reduce_to(h->d_red, nw, h->d_scalar, s));
-    double ss = 0.0;
-    HIP_OR_FAIL(h, hipMemcpyAsync(&ss, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(h, hipStreamSynchronize(s));
-    h->anorm_f = std::sqrt(ss);
-  }
-  if (opts->n_check > h->eval_cap) {
-    if (h->d_eval) {
-      for (auto it = h->allocs.begin(); it != h->allocs.end(); ++it)
-        if (*it == h->d_eval) { hipFree(*it); h->allocs.erase(it); break; }
-      h->d_eval = nullptr;
-      h->eval_cap = 0;
-    }
-    HIP_OR_FAIL(h, dalloc(h, &h->d_eval, opts->n_check * 8));
-    h->eval_cap = opts->n_check;
-  }
-
-  SolveState init{};
-  init.atol = opts->atol;
-  init.btol = opts->btol;
-  init.iter_lim = opts->iter_lim;
-  init.target = opts->n_check > 0 ? opts->target_rel_l2 : 0.0;
-  init.rel_l2 = -1.0;
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_state, &init, sizeof(init), hipMemcpyHostToDevice, s));
-  HIP_OR_FAIL(h, solve_init(h, opts->method, opts->x0_dev, s));
-
-  SolveState st{};
-  HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(h, hipStreamSynchronize(s));
-  const int chunk = opts->check_every;
-  while (!st.done) {
-    if (opts->use_graph) {
-      hipGraphExec_t exec = nullptr;
-      HIP_OR_FAIL(h, get_graph(h, opts->method, chunk, &exec));
-      HIP_OR_FAIL(h, hipGraphLaunch(exec, s));
-    } else {
-      HIP_OR_FAIL(h, enqueue_iterations(h, opts->method, chunk, s));
-    }
-    if (opts->n_check > 0) {
-      HIP_OR_FAIL(h, launch_evaluate(g, h->d_W, h->d_b, h->d_x, opts->check_pts_dev,
-                                     opts->n_check, h->d_eval, s));
-      int nw = (int)((opts->n_check + 255) / 256);
-      if (nw > kRedBlocks) nw = kRedBlocks;
-      HIP_OR_FAIL(h, launch_check_rel_l2(h->d_eval, opts->check_ref_dev, opts->n_check,
-                                         h->d_state, h->d_red + 6 * kRedBlocks, nw, s));
-    }
-    HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(h, hipStreamSynchronize(s));
-  }
-  HIP_OR_FAIL(h, hipMemcpyAsync(coef_dev, h->d_x, (size_t)g.n_phi * 8, hipMemcpyDeviceToDevice, s));
-  HIP_OR_FAIL(h, hipEventRecord(h->ev_out, s));
-  HIP_OR_FAIL(h, hipStreamWaitEvent(caller, h->ev_out, 0));
-  if (info) {
-    info->istop = st.istop;
-    info->iters = st.itn;
-    info->rnorm = st.rnorm;
-    info->arnorm = st.arnorm;
-    info->anorm = st.anorm;
-    info->xnorm = st.xnorm;
-    info->rel_l2 = st.rel_l2;
-    info->ms_solve =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  return ELMFB_OK;
-}
 
 elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,
                             int64_t n_pts, double* u_dev, void* stream) {
@@ -802,11 +578,11 @@ elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t reps, double* ms_host, 
   HIP_OR_FAIL(h, hipEventCreate(&e2));
   hipError_t e = hipEventRecord(e0, s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
-    e = launch_mv_blocks(g, h->prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), h->d_A,
+    e = launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), h->d_A,
                          h->d_x, nullptr, h->d_tpart, nullptr, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
-    e = launch_rmv_chunks(g, h->prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
+    e = launch_rmv_chunks(g, ELMFB_FP64, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
                           h->d_A, h->d_t, nullptr, h->d_part, nullptr, s);
   if (e == hipSuccess) e = hipEventRecord(e2, s);
   if (e == hipSuccess) e = hipEventSynchronize(e2);

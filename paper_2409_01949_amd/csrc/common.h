@@ -27,6 +27,22 @@ struct DevBlock {
   int32_t pad;
 };
 
+constexpr int kGramChunk = 4096;  // shared points per Gram chunk
+
+// One overlapping pair (bi <= bj) of subdomain blocks and its shared box of grid points.
+struct GramPair {
+  int32_t bi, bj;
+  int32_t ix0, nx, iy0, ny;   // shared box
+  int64_t g_off;              // element offset of G_ij [K][K] in the Gram storage
+  int32_t c0, nchunks;        // first global chunk, number of chunks
+  int64_t p_off;              // first partial slot (pairs with several chunks)
+};
+
+struct GramChunk {
+  int32_t pair;
+  int32_t s0;                 // first shared point of the chunk (box row-major)
+};
+
 struct Tile {       // a run of <= kTile consecutive points of one block
   int32_t blk;
   int32_t p0;
@@ -69,6 +85,8 @@ struct SolveState {
   double atol, btol;
   double target;           // rel-L2 target (0: off)
   int32_t itn, istop, done, iter_lim;
+  int32_t target_hit;      // the rel-L2 check met the target
+  int32_t pad_;
 };
 
 // Convert an FP64 value to bfloat16 bits with round-to-nearest-even (IEEE definition: keep

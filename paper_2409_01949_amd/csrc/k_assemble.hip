@@ -64,10 +64,6 @@ __global__ void __launch_bounds__(256) k_axis_tables(Geo g, const AxisSeg* __res
 template <int PREC>
 __device__ __forceinline__ void store_entry(void* A, int64_t i, double v);
 template <>
-__device__ __forceinline__ void store_entry<ELMFB_FP64>(void* A, int64_t i, double v) {
-  static_cast<double*>(A)[i] = v;
-}
-template <>
 __device__ __forceinline__ void store_entry<ELMFB_FP32>(void* A, int64_t i, double v) {
   static_cast<float*>(A)[i] = (float)v;   // IEEE round-to-nearest-even
 }
@@ -77,13 +73,15 @@ __device__ __forceinline__ void store_entry<ELMFB_BF16>(void* A, int64_t i, doub
 }
 
 // One workgroup per tile of <= 256 points of one block; one thread per point, looping over K.
-template <int PREC, int OP>
+// LO < 0: FP64 matrix only; LO = FP32 / BF16: also its rounded copy.
+template <int LO, int OP>
 __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restrict__ blocks,
                                                   const Tile* __restrict__ tiles,
                                                   const double* __restrict__ tab,
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ bias,
-                                                  void* __restrict__ A) {
+                                                  double* __restrict__ A,
+                                                  void* __restrict__ A_lo) {
   __shared__ double w1s[256], w2s[256], c1s[256], c2s[256], c3s[256], bs[256];
   const Tile t = tiles[blockIdx.x];
   const DevBlock B = blocks[t.blk];
@@ -130,7 +128,9 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
     } else {
       v = P * ph;
     }
-    store_entry<PREC>(A, base + (int64_t)k * n, v * scale);
+    const double e = v * scale;
+    A[base + (int64_t)k * n] = e;
+    if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * n, e);
   }
 }
 
@@ -161,35 +161,37 @@ hipError_t launch_axis_tables(const Geo& g, const AxisSeg* segs, int n_segs, con
   return hipGetLastError();
 }
 
-template <int PREC>
+template <int LO>
 static hipError_t launch_assemble_p(const Geo& g, const DevBlock* blocks, const Tile* tiles,
                                     int64_t n_tiles, const double* tab, const double* W,
-                                    const double* b, void* A, hipStream_t s) {
+                                    const double* b, double* A, void* A_lo, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), blk(256);
   switch (g.op) {
     case ELMFB_OP_NEG_LAPLACE:
-      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_NEG_LAPLACE>), grid, blk, 0, s, g, blocks,
-                         tiles, tab, W, b, A);
+      hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_NEG_LAPLACE>), grid, blk, 0, s, g, blocks,
+                         tiles, tab, W, b, A, A_lo);
       break;
     case ELMFB_OP_D1:
-      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_D1>), grid, blk, 0, s, g, blocks, tiles, tab,
-                         W, b, A);
+      hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_D1>), grid, blk, 0, s, g, blocks, tiles, tab,
+                         W, b, A, A_lo);
       break;
     default:
-      hipLaunchKernelGGL((k_assemble<PREC, ELMFB_OP_IDENTITY>), grid, blk, 0, s, g, blocks, tiles,
-                         tab, W, b, A);
+      hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_IDENTITY>), grid, blk, 0, s, g, blocks, tiles,
+                         tab, W, b, A, A_lo);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_assemble(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+hipError_t launch_assemble(const Geo& g, int lo_prec, const DevBlock* blocks, const Tile* tiles,
                            int64_t n_tiles, const double* tab, const double* W, const double* b,
-                           void* A, hipStream_t s) {
+                           double* A, void* A_lo, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  if (prec == ELMFB_FP32) return launch_assemble_p<ELMFB_FP32>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
-  if (prec == ELMFB_BF16) return launch_assemble_p<ELMFB_BF16>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
-  return launch_assemble_p<ELMFB_FP64>(g, blocks, tiles, n_tiles, tab, W, b, A, s);
+  if (lo_prec == ELMFB_FP32)
+    return launch_assemble_p<ELMFB_FP32>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
+  if (lo_prec == ELMFB_BF16)
+    return launch_assemble_p<ELMFB_BF16>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
+  return launch_assemble_p<-1>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
 }
 
 hipError_t launch_rhs(const Geo& g, const double* f, double* h, int32_t* bad, hipStream_t s) {

@@ -113,7 +113,8 @@ __global__ void __launch_bounds__(256) k_rel_l2_final(const double* __restrict__
   if (threadIdx.x == 0) {
     const double r = sqrt(sa) / sqrt(sb);
     st->rel_l2 = r;
-    if (!st->done && st->target > 0.0 && r <= st->target) {
+    if (st->target > 0.0 && r <= st->target) {
+      st->target_hit = 1;
       st->istop = 8;
       st->done = 1;
     }

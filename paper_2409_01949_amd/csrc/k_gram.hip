@@ -1,0 +1,219 @@
+// Gram blocks of the normal equations, G_ij = M_i^T M_j summed over the grid points the two
+// supports share (the block decomposition of Sec. 3, eq. multilevel_domain_decomp, gives
+// M^T M = sum_ij W_i^T M_i^T V_i V_j^T M_j W_j, nonzero only where I_i and I_j intersect).
+//
+// Each overlapping pair (i <= j) has a rectangular shared box; its points are split into chunks
+// of kGramChunk consecutive points (box row-major).  One workgroup per (chunk, group of <= 64
+// output tiles of 16 x 16) stages 32 points of both blocks ([K][32] each, feature-major) in LDS
+// and accumulates X Y^T on the matrix cores:
+//   FP64 blocks: v_mfma_f64_16x16x4_f64 (8 steps per stage),
+//   FP32 blocks: v_mfma_f32_16x16x4_f32 (8 steps),
+//   BF16 blocks: v_mfma_f32_16x16x32_bf16 (1 step), FP32 accumulation.
+// A pair with one chunk writes its block directly; a pair with several chunks writes chunk
+// partials that a second kernel sums in chunk order (deterministic, no atomics).
+#include "device.h"
+#include "kernels.h"
+
+namespace elmfb {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kStage = 32;        // points per LDS stage
+constexpr int kTilesPerGroup = 64; // 16 per wave
+
+template <int PREC> struct GramTypes;
+template <> struct GramTypes<ELMFB_FP64> { typedef double in_t; typedef double acc_t; typedef d4_t v4; };
+template <> struct GramTypes<ELMFB_FP32> { typedef float in_t; typedef float acc_t; typedef f4_t v4; };
+template <> struct GramTypes<ELMFB_BF16> { typedef __bf16 in_t; typedef float acc_t; typedef f4_t v4; };
+
+template <int PREC>
+__device__ __forceinline__ typename GramTypes<PREC>::in_t load_in(const void* A, int64_t i);
+template <>
+__device__ __forceinline__ double load_in<ELMFB_FP64>(const void* A, int64_t i) {
+  return static_cast<const double*>(A)[i];
+}
+template <>
+__device__ __forceinline__ float load_in<ELMFB_FP32>(const void* A, int64_t i) {
+  return static_cast<const float*>(A)[i];
+}
+template <>
+__device__ __forceinline__ __bf16 load_in<ELMFB_BF16>(const void* A, int64_t i) {
+  const uint16_t bits = static_cast<const uint16_t*>(A)[i];
+  return __builtin_bit_cast(__bf16, bits);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict__ blocks,
+                                              const GramPair* __restrict__ pairs,
+                                              const GramChunk* __restrict__ chunks,
+                                              const void* __restrict__ A,
+                                              typename GramTypes<PREC>::acc_t* __restrict__ G,
+                                              typename GramTypes<PREC>::acc_t* __restrict__ part) {
+  typedef typename GramTypes<PREC>::in_t in_t;
+  typedef typename GramTypes<PREC>::acc_t acc_t;
+  typedef typename GramTypes<PREC>::v4 v4;
+  constexpr int STR = (PREC == ELMFB_BF16) ? (kStage + 8) : (kStage + 1);   // LDS row stride
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int K = g.K;
+  const int Kp = (K + 15) & ~15;
+  in_t* X = reinterpret_cast<in_t*>(smem);
+  in_t* Y = X + (size_t)Kp * STR;
+  int* pidx = reinterpret_cast<int*>(Y + (size_t)Kp * STR);   // [2][kStage]
+
+  const GramChunk ck = chunks[blockIdx.x];
+  const GramPair pr = pairs[ck.pair];
+  const DevBlock Bi = blocks[pr.bi], Bj = blocks[pr.bj];
+  const int nshared = pr.nx * pr.ny;
+  const int s_end = min(ck.s0 + kGramChunk, nshared);
+  const int nT = Kp / 16;
+  const int ntiles = nT * nT;
+  const int t_base = blockIdx.y * kTilesPerGroup;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+
+  v4 acc[kTilesPerGroup / 4];
+#pragma unroll
+  for (int i = 0; i < kTilesPerGroup / 4; ++i) acc[i] = v4{0, 0, 0, 0};
+
+  for (int s0 = ck.s0; s0 < s_end; s0 += kStage) {
+    if (threadIdx.x < kStage) {
+      const int s = s0 + threadIdx.x;
+      int pi = -1, pj = -1;
+      if (s < s_end) {
+        const int sx = s / pr.ny, sy = s - sx * pr.ny;
+        const int ix = pr.ix0 + sx, iy = pr.iy0 + sy;
+        pi = (ix - Bi.ix0) * Bi.ny + (iy - Bi.iy0);
+        pj = (ix - Bj.ix0) * Bj.ny + (iy - Bj.iy0);
+      }
+      pidx[threadIdx.x] = pi;
+      pidx[kStage + threadIdx.x] = pj;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < Kp * kStage; e += 256) {
+      const int k = e / kStage, s = e - k * kStage;
+      const int pi = pidx[s], pj = pidx[kStage + s];
+      in_t xv = in_t(0.0f), yv = in_t(0.0f);
+      if (k < K && pi >= 0) {
+        xv = load_in<PREC>(A, Bi.a_off + (int64_t)k * Bi.n + pi);
+        yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.n + pj);
+      }
+      X[k * STR + s] = xv;
+      Y[k * STR + s] = yv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTilesPerGroup / 4; ++i) {
+      const int t = t_base + wid + 4 * i;
+      if (t < ntiles) {
+        const int I = t / nT, J = t - (t / nT) * nT;
+        const in_t* xr = X + (I * 16 + li) * STR;
+        const in_t* yr = Y + (J * 16 + li) * STR;
+        if constexpr (PREC == ELMFB_BF16) {
+          bf8_t a, b;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) { a[q] = xr[8 * lq + q]; b[q] = yr[8 * lq + q]; }
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+        } else if constexpr (PREC == ELMFB_FP32) {
+#pragma unroll
+          for (int q = 0; q < kStage; q += 4)
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q + lq], yr[q + lq], acc[i], 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int q = 0; q < kStage; q += 4)
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[q + lq], yr[q + lq], acc[i], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // accumulator layout of a 16 x 16 tile: lane holds column li; rows 4*lq + v for the FP32
+  // accumulating forms, rows lq + 4*v for v_mfma_f64_16x16x4_f64
+  acc_t* out = (pr.nchunks == 1) ? G + pr.g_off
+                                 : part + (int64_t)(blockIdx.x - pr.c0 + pr.p_off) * K * K;
+#pragma unroll
+  for (int i = 0; i < kTilesPerGroup / 4; ++i) {
+    const int t = t_base + wid + 4 * i;
+    if (t < ntiles) {
+      const int I = t / nT, J = t - (t / nT) * nT;
+      const int col = J * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = (PREC == ELMFB_FP64) ? I * 16 + lq + 4 * v : I * 16 + 4 * lq + v;
+        if (row < K && col < K) out[(int64_t)row * K + col] = acc[i][v];
+      }
+    }
+  }
+}
+
+// Sum the chunk partials of every multi-chunk pair in chunk order.
+template <typename acc_t>
+__global__ void __launch_bounds__(256) k_gram_reduce(Geo g, const GramPair* __restrict__ pairs,
+                                                     const int32_t* __restrict__ multi,
+                                                     const acc_t* __restrict__ part,
+                                                     acc_t* __restrict__ G) {
+  const GramPair pr = pairs[multi[blockIdx.x]];
+  const int KK = g.K * g.K;
+  for (int e = blockIdx.y * 256 + threadIdx.x; e < KK; e += 256 * gridDim.y) {
+    acc_t s = 0;
+    for (int c = 0; c < pr.nchunks; ++c) s += part[(int64_t)(pr.p_off + c) * KK + e];
+    G[pr.g_off + e] = s;
+  }
+}
+
+static size_t gram_smem(int prec, int K) {
+  const int Kp = (K + 15) & ~15;
+  const size_t es = prec == ELMFB_FP64 ? 8 : (prec == ELMFB_FP32 ? 4 : 2);
+  const int str = prec == ELMFB_BF16 ? kStage + 8 : kStage + 1;
+  return 2 * (size_t)Kp * str * es + 2 * kStage * sizeof(int) + 16;
+}
+
+hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const GramPair* pairs,
+                       const GramChunk* chunks, int64_t n_chunks, const int32_t* multi,
+                       int64_t n_multi, const void* A, void* G, void* part, hipStream_t s) {
+  if (n_chunks == 0) return hipSuccess;
+  const int Kp = (g.K + 15) & ~15;
+  const int nT = Kp / 16;
+  const int groups = (nT * nT + kTilesPerGroup - 1) / kTilesPerGroup;
+  const dim3 grid((unsigned)n_chunks, (unsigned)groups), blk(256);
+  const size_t sm = gram_smem(prec, g.K);
+  if (sm > 160 * 1024) return hipErrorInvalidValue;
+  if (sm > 64 * 1024) {
+    hipError_t ea = hipSuccess;
+    if (prec == ELMFB_FP64)
+      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP64>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    else if (prec == ELMFB_FP32)
+      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP32>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    else
+      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_BF16>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (ea != hipSuccess) return ea;
+  }
+  if (prec == ELMFB_FP64) {
+    hipLaunchKernelGGL(k_gram<ELMFB_FP64>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
+                       (double*)G, (double*)part);
+  } else if (prec == ELMFB_FP32) {
+    hipLaunchKernelGGL(k_gram<ELMFB_FP32>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
+                       (float*)G, (float*)part);
+  } else {
+    hipLaunchKernelGGL(k_gram<ELMFB_BF16>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
+                       (float*)G, (float*)part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_multi == 0) return e;
+  const dim3 rgrid((unsigned)n_multi, (unsigned)((g.K * g.K + 255) / 256 < 16 ? (g.K * g.K + 255) / 256 : 16));
+  if (prec == ELMFB_FP64)
+    hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, s, g, pairs, multi,
+                       (const double*)part, (double*)G);
+  else
+    hipLaunchKernelGGL(k_gram_reduce<float>, rgrid, dim3(256), 0, s, g, pairs, multi,
+                       (const float*)part, (float*)G);
+  return hipGetLastError();
+}
+
+size_t gram_smem_bytes(int prec, int K) { return gram_smem(prec, K); }
+
+}  // namespace elmfb

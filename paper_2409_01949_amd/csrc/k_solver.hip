@@ -282,6 +282,12 @@ __global__ void k_cgls_update_p(Geo g, double* __restrict__ p, const double* __r
     p[q] = s[q] + b * p[q];
 }
 
+__global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = y[i] + a * x[i];
+}
+
 __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -349,6 +355,10 @@ hipError_t launch_cgls_init(SolveState* st, const double* red_b, int nb, const d
                             int nr, const double* red_s, int ns, double anorm_f, hipStream_t s) {
   hipLaunchKernelGGL(k_cgls_init, dim3(1), dim3(256), 0, s, st, red_b, nb, red_r, nr, red_s, ns,
                      anorm_f);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, grid_for(n), dim3(256), 0, s, a, x, y, n);
   return hipGetLastError();
 }
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {

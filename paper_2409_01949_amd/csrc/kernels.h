@@ -13,9 +13,10 @@ struct AxisSeg {
 // ---- assembly (k_assemble.hip)
 hipError_t launch_axis_tables(const Geo& g, const AxisSeg* segs, int n_segs, const int32_t* cov,
                               double* tab, hipStream_t s);
-hipError_t launch_assemble(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
+// writes the FP64 matrix into A and, if lo_prec is FP32 or BF16, its rounded copy into A_lo
+hipError_t launch_assemble(const Geo& g, int lo_prec, const DevBlock* blocks, const Tile* tiles,
                            int64_t n_tiles, const double* tab, const double* W, const double* b,
-                           void* A, hipStream_t s);
+                           double* A, void* A_lo, hipStream_t s);
 hipError_t launch_rhs(const Geo& g, const double* f, double* h, int32_t* bad, hipStream_t s);
 hipError_t launch_points(const Geo& g, double* xy, hipStream_t s);
 
@@ -71,6 +72,25 @@ hipError_t launch_cgls_update_p(const Geo& g, double* p, const double* sv, const
 hipError_t launch_sumsq_entries(int prec, const void* A, int64_t n, double* red, int n_wg,
                                 hipStream_t s);
 hipError_t launch_reduce_to(const double* red, int n, double* out, hipStream_t s);
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
+
+// ---- Gram blocks (k_gram.hip)
+hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const GramPair* pairs,
+                       const GramChunk* chunks, int64_t n_chunks, const int32_t* multi,
+                       int64_t n_multi, const void* A, void* G, void* part, hipStream_t s);
+size_t gram_smem_bytes(int prec, int K);
+
+// ---- block-Jacobi preconditioner (k_precond.hip)
+int bj_wg(const Geo& g);
+hipError_t launch_bj_factor(const Geo& g, const double* G, const int64_t* diag_off, double shift,
+                            double* work, double* rinv, double* rinvT, int32_t* nfail,
+                            hipStream_t s);
+hipError_t launch_bj_apply(const Geo& g, const double* rinvT, const double* v,
+                           const double* scale, double* y, const SolveState* st, hipStream_t s);
+hipError_t launch_bj_apply_t(const Geo& g, const double* rinv, const double* x, int mode,
+                             double* out, const SolveState* st, double* red, hipStream_t s);
+hipError_t launch_bj_recover(const Geo& g, const double* rinvT, const double* y, const double* x0,
+                             double* x, hipStream_t s);
 
 // ---- evaluation (k_evaluate.hip)
 hipError_t launch_evaluate(const Geo& g, const double* W, const double* b, const double* coef,

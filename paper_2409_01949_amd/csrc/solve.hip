@@ -1,0 +1,515 @@
+// Solve drivers behind the C ABI: LSQR / CGLS on the block-sparse matrix with device-resident
+// recurrences captured in hipGraphs, right block-Jacobi preconditioning, FP64 iterative
+// refinement around low-precision inner LSQR, Gram blocks and the preconditioner factors.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "handle.h"
+
+namespace {
+
+// The matrix copy, right-hand side and preconditioning of one Krylov run.
+struct KCtx {
+  const void* A;
+  int prec;
+  const double* rhs;
+  bool bj;
+};
+
+double* red_slot(elmfb_problem h, int i) { return h->d_red + (int64_t)2 * kRedBlocks * i; }
+
+const double* state_field(elmfb_problem h, size_t off) {
+  return reinterpret_cast<const double*>(reinterpret_cast<const char*>(h->d_state) + off);
+}
+
+hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
+  const Geo& g = h->geo;
+  SolveState* st = h->d_state;
+  double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
+  const int rw = rows_wg(g), cw = cols_wg(g);
+  const int64_t nt = (int64_t)h->tiles.size(), nc = (int64_t)h->chunks.size();
+  hipError_t e;
+  // u = A v / alpha - ... (v scaled by 1/alpha as it is read)
+  if (c.bj) {
+    if ((e = launch_bj_apply(g, h->d_rinvT, h->d_v, state_field(h, offsetof(SolveState, sv)),
+                             h->d_vt, st, s)))
+      return e;
+    if ((e = launch_mv_blocks(g, c.prec, h->d_blocks, h->d_tiles, nt, c.A, h->d_vt, nullptr,
+                              h->d_tpart, st, s)))
+      return e;
+  } else {
+    if ((e = launch_mv_blocks(g, c.prec, h->d_blocks, h->d_tiles, nt, c.A, h->d_v,
+                              state_field(h, offsetof(SolveState, sv)), h->d_tpart, st, s)))
+      return e;
+  }
+  if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
+                              st, red1, rw, s)))
+    return e;
+  if ((e = launch_lsqr_beta(st, red1, rw, s))) return e;
+  if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, nc, c.A, h->d_u,
+                             state_field(h, offsetof(SolveState, su)), h->d_part, st, s)))
+    return e;
+  int na = cw;
+  if (c.bj) {
+    if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, h->d_xt, st, red2, cw, s)))
+      return e;
+    if ((e = launch_bj_apply_t(g, h->d_rinv, h->d_xt, COL_LSQR_V, h->d_v, st, red2, s))) return e;
+    na = bj_wg(g);
+  } else {
+    if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw, s)))
+      return e;
+  }
+  if ((e = launch_lsqr_alpha(st, red2, na, s))) return e;
+  if ((e = launch_lsqr_update(g, h->d_x, h->d_w, h->d_v, st, red3, cw, s))) return e;
+  return launch_lsqr_stop(st, red3, cw, s);
+}
+
+hipError_t cgls_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
+  const Geo& g = h->geo;
+  SolveState* st = h->d_state;
+  double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
+  const int rw = rows_wg(g), cw = cols_wg(g);
+  hipError_t e;
+  if ((e = launch_mv_blocks(g, c.prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), c.A,
+                            h->d_w, nullptr, h->d_tpart, st, s)))
+    return e;
+  if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE_SQ, h->d_t, nullptr,
+                              st, red1, rw, s)))
+    return e;
+  if ((e = launch_cgls_step_a(st, red1, rw, s))) return e;
+  if ((e = launch_cgls_update_x(g, h->d_x, h->d_w, st, s))) return e;
+  if ((e = launch_cgls_update_r(g, h->d_u, h->d_t, st, red2, rw, s))) return e;
+  if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), c.A,
+                             h->d_u, nullptr, h->d_part, st, s)))
+    return e;
+  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, st, red3, cw, s)))
+    return e;
+  if ((e = launch_cgls_step_b(st, red2, rw, red3, cw, s))) return e;
+  return launch_cgls_update_p(g, h->d_w, h->d_v, st, s);
+}
+
+// u (LSQR) or r (CGLS) = rhs - A x0, the first bidiagonalisation step, x = x0 (LSQR without
+// preconditioning) or 0 (preconditioned LSQR solves for the correction y, x = x0 + R^{-1} y).
+hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* x0,
+                      hipStream_t s) {
+  const Geo& g = h->geo;
+  double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
+  const int rw = rows_wg(g), cw = cols_wg(g);
+  hipError_t e;
+  if (x0) {
+    if ((e = launch_mv_blocks(g, c.prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), c.A,
+                              x0, nullptr, h->d_tpart, nullptr, s)))
+      return e;
+    if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_u, c.rhs,
+                                nullptr, red2, rw, s)))
+      return e;
+  } else {
+    if ((e = launch_copy(c.rhs, h->d_u, g.n_rows, s))) return e;
+    if ((e = launch_sumsq(h->d_u, g.n_rows, red2, rw, s))) return e;
+  }
+  if ((e = launch_sumsq(c.rhs, g.n_rows, red1, rw, s))) return e;
+  if (method == ELMFB_LSQR) {
+    if ((e = launch_lsqr_init(h->d_state, red1, rw, red2, rw, s))) return e;
+    if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), c.A,
+                               h->d_u, state_field(h, offsetof(SolveState, su)), h->d_part,
+                               nullptr, s)))
+      return e;
+    int na = cw;
+    if (c.bj) {
+      if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, h->d_xt, nullptr, red3, cw,
+                                 s)))
+        return e;
+      if ((e = launch_bj_apply_t(g, h->d_rinv, h->d_xt, COL_STORE_SQ, h->d_v, nullptr, red3, s)))
+        return e;
+      na = bj_wg(g);
+    } else {
+      if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3,
+                                 cw, s)))
+        return e;
+    }
+    if ((e = launch_lsqr_init_alpha(h->d_state, red3, na, s))) return e;
+    return launch_init_xw(g, c.bj ? nullptr : x0, h->d_x, h->d_w, h->d_v, h->d_state, s);
+  }
+  // CGLS: s = A^T r, p = s, x = x0
+  if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), c.A,
+                             h->d_u, nullptr, h->d_part, nullptr, s)))
+    return e;
+  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3, cw,
+                             s)))
+    return e;
+  if ((e = launch_cgls_init(h->d_state, red1, rw, red2, rw, red3, cw, h->anorm_f, s))) return e;
+  if ((e = launch_copy(h->d_v, h->d_w, g.n_phi, s))) return e;
+  if (x0) return launch_copy(x0, h->d_x, g.n_phi, s);
+  return hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s);
+}
+
+hipError_t enqueue_iterations(elmfb_problem h, const KCtx& c, int method, int n, hipStream_t s) {
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = method == ELMFB_LSQR ? lsqr_iteration(h, c, s) : cgls_iteration(h, c, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t get_graph(elmfb_problem h, const KCtx& c, int method, int n, hipGraphExec_t* out) {
+  const std::vector<int64_t> key = {method, n, (int64_t)c.A, c.prec, (int64_t)c.rhs, c.bj};
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e2 = enqueue_iterations(h, c, method, n, h->stream);
+  e = hipStreamEndCapture(h->stream, &graph);
+  if (e2 != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return e2;
+  }
+  if (e != hipSuccess) return e;
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  h->graphs[key] = exec;
+  *out = exec;
+  return hipSuccess;
+}
+
+hipError_t run_iterations(elmfb_problem h, const KCtx& c, int method, int n, bool graph,
+                          hipStream_t s) {
+  if (!graph) return enqueue_iterations(h, c, method, n, s);
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = get_graph(h, c, method, n, &exec);
+  if (e != hipSuccess) return e;
+  return hipGraphLaunch(exec, s);
+}
+
+// Evaluate the current solution at the check points and update the rel-L2 stop state.
+hipError_t check_solution(elmfb_problem h, const elmfb_solve_opts* o, const double* x,
+                          hipStream_t s) {
+  hipError_t e = launch_evaluate(h->geo, h->d_W, h->d_b, x, o->check_pts_dev, o->n_check,
+                                 h->d_eval, s);
+  if (e != hipSuccess) return e;
+  int nw = (int)((o->n_check + 255) / 256);
+  if (nw > kRedBlocks) nw = kRedBlocks;
+  return launch_check_rel_l2(h->d_eval, o->check_ref_dev, o->n_check, h->d_state, red_slot(h, 3),
+                             nw, s);
+}
+
+// Plan the chunks of a set of Gram pairs, upload the tables, run the Gram kernel into G.
+elmfb_status run_gram(elmfb_problem h, int prec, std::vector<GramPair>& pairs, void* G,
+                      hipStream_t s) {
+  const Geo& g = h->geo;
+  const int64_t KK = (int64_t)g.K * g.K;
+  std::vector<GramChunk> chunks;
+  std::vector<int32_t> multi;
+  int64_t p_off = 0;
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    GramPair& pr = pairs[p];
+    const int64_t ns = (int64_t)pr.nx * pr.ny;
+    pr.g_off = (int64_t)p * KK;
+    pr.c0 = (int32_t)chunks.size();
+    pr.nchunks = (int32_t)((ns + kGramChunk - 1) / kGramChunk);
+    pr.p_off = 0;
+    if (pr.nchunks > 1) {
+      pr.p_off = p_off;
+      p_off += pr.nchunks;
+      multi.push_back((int32_t)p);
+    }
+    for (int64_t s0 = 0; s0 < ns; s0 += kGramChunk) chunks.push_back(GramChunk{(int32_t)p, (int32_t)s0});
+  }
+  const int64_t acc_es = prec == ELMFB_FP64 ? 8 : 4;
+  auto grow = [&](void** buf, int64_t* cap, int64_t need) -> hipError_t {
+    if (need <= *cap) return hipSuccess;
+    dfree(h, *buf);
+    *buf = nullptr;
+    *cap = 0;
+    hipError_t e = dalloc_bytes(h, buf, need);
+    if (e == hipSuccess) *cap = need;
+    return e;
+  };
+  HIP_OR_FAIL(h, grow((void**)&h->d_gpairs, &h->gpairs_cap, (int64_t)pairs.size() * sizeof(GramPair)));
+  HIP_OR_FAIL(h, grow((void**)&h->d_gchunks, &h->gchunks_cap, (int64_t)chunks.size() * sizeof(GramChunk)));
+  HIP_OR_FAIL(h, grow((void**)&h->d_gmulti, &h->gmulti_cap, (int64_t)multi.size() * 4 + 4));
+  HIP_OR_FAIL(h, grow(&h->d_gpart, &h->gpart_bytes, p_off * KK * acc_es));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_gpairs, pairs.data(), pairs.size() * sizeof(GramPair),
+                                hipMemcpyHostToDevice, s));
+  if (!chunks.empty())
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_gchunks, chunks.data(), chunks.size() * sizeof(GramChunk),
+                                  hipMemcpyHostToDevice, s));
+  if (!multi.empty())
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_gmulti, multi.data(), multi.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+  const void* A = prec == ELMFB_FP64 ? (const void*)h->d_A : h->d_A_lo;
+  HIP_OR_FAIL(h, launch_gram(g, prec, h->d_blocks, h->d_gpairs, h->d_gchunks,
+                             (int64_t)chunks.size(), h->d_gmulti, (int64_t)multi.size(), A, G,
+                             h->d_gpart, s));
+  // the host tables above must outlive the asynchronous copies
+  HIP_OR_FAIL(h, hipStreamSynchronize(s));
+  return ELMFB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stream) {
+  if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
+  if (!h->assembled) return fail(h, ELMFB_E_STATE, "gram before assemble");
+  if (which != 0 && which != 1) return fail(h, ELMFB_E_INVALID, "which must be 0 or 1");
+  if (prec != ELMFB_FP64 && !(prec == h->lo_prec && h->d_A_lo))
+    return fail(h, ELMFB_E_STATE, "no stored matrix copy in that precision");
+  std::vector<GramPair> pairs;
+  if (which == 1) {
+    pairs = h->pairs_all;
+  } else {
+    for (int64_t idx : h->diag_pair)
+      if (idx >= 0) pairs.push_back(h->pairs_all[idx]);
+  }
+  const int64_t KK = (int64_t)h->geo.K * h->geo.K;
+  const int64_t need = (int64_t)pairs.size() * KK * (prec == ELMFB_FP64 ? 8 : 4);
+  if (need > h->G_bytes) {
+    dfree(h, h->d_G);
+    h->d_G = nullptr;
+    h->G_bytes = 0;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)need > free_b)
+      return fail(h, ELMFB_E_NOMEM, "Gram blocks do not fit in free device memory");
+    HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_G, need));
+    h->G_bytes = need;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  elmfb_status st = run_gram(h, prec, pairs, h->d_G, s);
+  if (st != ELMFB_OK) return st;
+  h->gram_prec = prec;
+  h->gram_which = which;
+  h->gram_npairs = (int64_t)pairs.size();
+  h->gram_pairs_host = pairs;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host,
+                             int64_t* n_pairs_host, void* stream) {
+  if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
+  if (h->gram_prec < 0) return fail(h, ELMFB_E_STATE, "no Gram blocks computed");
+  if (n_pairs_host) *n_pairs_host = h->gram_npairs;
+  if (pairs_host)
+    for (int64_t p = 0; p < h->gram_npairs; ++p) {
+      pairs_host[3 * p] = h->gram_pairs_host[p].bi;
+      pairs_host[3 * p + 1] = h->gram_pairs_host[p].bj;
+      pairs_host[3 * p + 2] = h->gram_pairs_host[p].g_off;
+    }
+  if (dst_dev) {
+    const int64_t KK = (int64_t)h->geo.K * h->geo.K;
+    HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, h->d_G,
+                                  (size_t)(h->gram_npairs * KK * (h->gram_prec == ELMFB_FP64 ? 8 : 4)),
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  }
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback, void* stream) {
+  if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
+  if (!h->assembled) return fail(h, ELMFB_E_STATE, "precondition before assemble");
+  if (!(shift > 0.0) || !std::isfinite(shift)) return fail(h, ELMFB_E_INVALID, "shift must be > 0");
+  const Geo& g = h->geo;
+  const int64_t KK = (int64_t)g.K * g.K;
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->d_bj_work) {
+    HIP_OR_FAIL(h, dalloc(h, &h->d_bj_work, g.n_blocks * KK * 8 * 2));   // diagonal Gram + R
+    HIP_OR_FAIL(h, dalloc(h, &h->d_rinv, g.n_blocks * KK * 8));
+    HIP_OR_FAIL(h, dalloc(h, &h->d_rinvT, g.n_blocks * KK * 8));
+    HIP_OR_FAIL(h, dalloc(h, &h->d_diag_off, g.n_blocks * 8));
+  }
+  double* gdiag = h->d_bj_work;
+  double* rwork = h->d_bj_work + g.n_blocks * KK;
+  // FP64 diagonal Gram blocks, one slot per block (empty blocks stay zero)
+  std::vector<GramPair> pairs;
+  std::vector<int64_t> offs(g.n_blocks, 0);
+  for (int b = 0; b < g.n_blocks; ++b) offs[b] = (int64_t)b * KK;
+  HIP_OR_FAIL(h, hipMemsetAsync(gdiag, 0, (size_t)(g.n_blocks * KK * 8), s));
+  std::vector<int> owner;
+  for (int b = 0; b < g.n_blocks; ++b)
+    if (h->diag_pair[b] >= 0) {
+      pairs.push_back(h->pairs_all[h->diag_pair[b]]);
+      owner.push_back(b);
+    }
+  // run_gram places pair p at p*K*K; map through a compact buffer when blocks are empty
+  const bool dense_map = (int)pairs.size() == g.n_blocks;
+  double* target = gdiag;
+  if (!dense_map) {
+    void* tmp = nullptr;
+    HIP_OR_FAIL(h, dalloc_bytes(h, &tmp, (int64_t)pairs.size() * KK * 8));
+    target = (double*)tmp;
+  }
+  elmfb_status st = run_gram(h, ELMFB_FP64, pairs, target, s);
+  if (st != ELMFB_OK) return st;
+  if (!dense_map) {
+    for (size_t p = 0; p < pairs.size(); ++p)
+      HIP_OR_FAIL(h, hipMemcpyAsync(gdiag + (int64_t)owner[p] * KK, target + (int64_t)p * KK,
+                                    (size_t)KK * 8, hipMemcpyDeviceToDevice, s));
+    HIP_OR_FAIL(h, hipStreamSynchronize(s));
+    dfree(h, target);
+  }
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_diag_off, offs.data(), offs.size() * 8,
+                                hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
+  HIP_OR_FAIL(h, launch_bj_factor(g, gdiag, h->d_diag_off, shift, rwork, h->d_rinv, h->d_rinvT,
+                                  h->d_flag, s));
+  int32_t nf = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(&nf, h->d_flag, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(h, hipStreamSynchronize(s));
+  if (n_fallback) *n_fallback = nf;
+  h->bj_ready = true;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
+                         elmfb_solve_info* info, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
+  if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
+  const int method = opts->method;
+  if (method != ELMFB_LSQR && method != ELMFB_CGLS && method != ELMFB_MIXED_IR)
+    return fail(h, ELMFB_E_UNSUPPORTED, "unknown solve method");
+  if (opts->iter_lim < 0 || opts->check_every < 1 || opts->check_every > 100000)
+    return fail(h, ELMFB_E_INVALID, "iter_lim >= 0 and 1 <= check_every <= 100000 required");
+  if (!(opts->atol >= 0.0) || !(opts->btol >= 0.0))
+    return fail(h, ELMFB_E_INVALID, "atol and btol must be >= 0");
+  if (opts->n_check < 0 || (opts->n_check > 0 && (!opts->check_pts_dev || !opts->check_ref_dev)))
+    return fail(h, ELMFB_E_INVALID, "check points need check_pts_dev and check_ref_dev");
+  const bool bj = opts->precond != 0;
+  if (bj && method == ELMFB_CGLS) return fail(h, ELMFB_E_UNSUPPORTED, "CGLS has no preconditioner");
+  if (bj && !h->bj_ready) return fail(h, ELMFB_E_STATE, "precondition before solving with it");
+  if (method == ELMFB_MIXED_IR) {
+    if (opts->inner_iters < 1 || opts->outer_lim < 0)
+      return fail(h, ELMFB_E_INVALID, "MIXED_IR needs inner_iters >= 1 and outer_lim >= 0");
+    if (!h->d_A_lo) return fail(h, ELMFB_E_STATE, "MIXED_IR needs a low-precision stored copy");
+  }
+  const Geo& g = h->geo;
+  hipStream_t caller = (hipStream_t)stream;
+  hipStream_t s = h->stream;
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_in, caller));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(s, h->ev_in, 0));
+
+  if (method == ELMFB_CGLS && h->anorm_f < 0.0) {
+    HIP_OR_FAIL(h, launch_sumsq_entries(ELMFB_FP64, h->d_A, h->nnz, h->d_red, kRedBlocks, s));
+    HIP_OR_FAIL(h, launch_reduce_to(h->d_red, kRedBlocks, h->d_scalar, s));
+    double ss = 0.0;
+    HIP_OR_FAIL(h, hipMemcpyAsync(&ss, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(h, hipStreamSynchronize(s));
+    h->anorm_f = std::sqrt(ss);
+  }
+  if (opts->n_check > h->eval_cap) {
+    dfree(h, h->d_eval);
+    h->d_eval = nullptr;
+    h->eval_cap = 0;
+    HIP_OR_FAIL(h, dalloc(h, &h->d_eval, opts->n_check * 8));
+    h->eval_cap = opts->n_check;
+  }
+
+  SolveState init{};
+  init.atol = opts->atol;
+  init.btol = opts->btol;
+  init.iter_lim = method == ELMFB_MIXED_IR ? opts->inner_iters : opts->iter_lim;
+  init.target = opts->n_check > 0 ? opts->target_rel_l2 : 0.0;
+  init.rel_l2 = -1.0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_state, &init, sizeof(init), hipMemcpyHostToDevice, s));
+
+  SolveState st{};
+  int total_iters = 0, outer = 0;
+  double outer_rnorm = -1.0;
+  const double* result = h->d_x;
+  if (method != ELMFB_MIXED_IR) {
+    const KCtx c{h->d_A, ELMFB_FP64, h->d_h, bj};
+    HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
+    HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(h, hipStreamSynchronize(s));
+    while (!st.done) {
+      HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
+      if (opts->n_check > 0) {
+        const double* xcur = h->d_x;
+        if (bj) {
+          HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, opts->x0_dev, h->d_c, s));
+          xcur = h->d_c;
+        }
+        HIP_OR_FAIL(h, check_solution(h, opts, xcur, s));
+      }
+      HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(h, hipStreamSynchronize(s));
+    }
+    if (bj) {
+      HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, opts->x0_dev, h->d_c, s));
+      result = h->d_c;
+    }
+    total_iters = st.itn;
+    if (st.target_hit) st.istop = 8;
+  } else {
+    // FP64 refinement: c = x0; repeat r = h - A c (FP64), d = inner LSQR on the low copy, c += d
+    if (opts->x0_dev)
+      HIP_OR_FAIL(h, launch_copy(opts->x0_dev, h->d_c, g.n_phi, s));
+    else
+      HIP_OR_FAIL(h, hipMemsetAsync(h->d_c, 0, (size_t)g.n_phi * 8, s));
+    const KCtx inner{h->d_A_lo, h->lo_prec, h->d_r, bj};
+    const int rw = rows_wg(g);
+    int istop = 7;
+    for (outer = 0; outer < opts->outer_lim; ++outer) {
+      HIP_OR_FAIL(h, launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles,
+                                      (int64_t)h->tiles.size(), h->d_A, h->d_c, nullptr,
+                                      h->d_tpart, nullptr, s));
+      HIP_OR_FAIL(h, launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_r,
+                                        h->d_h, nullptr, red_slot(h, 3), rw, s));
+      HIP_OR_FAIL(h, launch_reduce_to(red_slot(h, 3), rw, h->d_scalar, s));
+      HIP_OR_FAIL(h, solve_init(h, inner, ELMFB_LSQR, nullptr, s));
+      int left = opts->inner_iters;
+      while (left > 0) {
+        const int n = std::min(left, opts->check_every);
+        HIP_OR_FAIL(h, run_iterations(h, inner, ELMFB_LSQR, n, opts->use_graph != 0, s));
+        left -= n;
+      }
+      if (bj)
+        HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_c, s));
+      else
+        HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_c, g.n_phi, s));
+      if (opts->n_check > 0) HIP_OR_FAIL(h, check_solution(h, opts, h->d_c, s));
+      double rr = 0.0;
+      HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(h, hipMemcpyAsync(&rr, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
+      HIP_OR_FAIL(h, hipStreamSynchronize(s));
+      outer_rnorm = std::sqrt(rr);
+      total_iters += st.itn;
+      if (st.target_hit) {
+        istop = 8;
+        ++outer;
+        break;
+      }
+    }
+    st.istop = istop;
+    result = h->d_c;
+  }
+  HIP_OR_FAIL(h, hipMemcpyAsync(coef_dev, result, (size_t)g.n_phi * 8, hipMemcpyDeviceToDevice, s));
+  HIP_OR_FAIL(h, hipEventRecord(h->ev_out, s));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(caller, h->ev_out, 0));
+  if (info) {
+    info->istop = st.istop;
+    info->iters = total_iters;
+    info->outer_iters = outer;
+    info->rnorm = method == ELMFB_MIXED_IR ? outer_rnorm : st.rnorm;
+    info->arnorm = st.arnorm;
+    info->anorm = st.anorm;
+    info->xnorm = st.xnorm;
+    info->rel_l2 = st.rel_l2;
+    info->ms_solve =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return ELMFB_OK;
+}
+
+}  // extern "C"

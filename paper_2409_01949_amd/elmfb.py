@@ -23,12 +23,12 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = range(7)
 OP_D1, OP_NEG_LAPLACE, OP_IDENTITY = 1, 2, 3
 ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
-LSQR, CGLS = 0, 1
+LSQR, CGLS, MIXED_IR = 0, 1, 2
 
 _OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY}
 _ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
-_METHOD = {"lsqr": LSQR, "cgls": CGLS}
+_METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR}
 
 
 class ProblemDesc(ctypes.Structure):
@@ -53,7 +53,8 @@ class ProblemDesc(ctypes.Structure):
 
 class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("n_rows", "n_phi", "nnz", "n_blocks", "n_block_points", "bytes_device")]
+                ("n_rows", "n_phi", "nnz", "n_blocks", "n_block_points", "bytes_device",
+                 "n_pairs")]
 
 
 class SolveOpts(ctypes.Structure):
@@ -62,6 +63,9 @@ class SolveOpts(ctypes.Structure):
         ("iter_lim", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("inner_iters", ctypes.c_int32),
+        ("outer_lim", ctypes.c_int32),
         ("atol", ctypes.c_double),
         ("btol", ctypes.c_double),
         ("x0_dev", ctypes.c_void_p),
@@ -76,6 +80,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("istop", ctypes.c_int32),
         ("iters", ctypes.c_int32),
+        ("outer_iters", ctypes.c_int32),
         ("rnorm", ctypes.c_double),
         ("arnorm", ctypes.c_double),
         ("anorm", ctypes.c_double),
@@ -119,7 +124,10 @@ def load_library(path: Optional[str] = None):
         "elmfb_matvec": (i32, [P, P, P, P]),
         "elmfb_rmatvec": (i32, [P, P, P, P]),
         "elmfb_copy_rhs": (i32, [P, P, P]),
-        "elmfb_copy_blocks": (i32, [P, P, ctypes.POINTER(i64), P]),
+        "elmfb_copy_blocks": (i32, [P, i32, P, ctypes.POINTER(i64), P]),
+        "elmfb_gram": (i32, [P, i32, i32, P]),
+        "elmfb_copy_gram": (i32, [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P]),
+        "elmfb_precondition": (i32, [P, dbl, ctypes.POINTER(i32), P]),
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
         "elmfb_time_kernels": (i32, [P, i32, ctypes.POINTER(dbl), P]),
@@ -236,23 +244,49 @@ class Problem:
     def copy_rhs(self, hvec, stream=None):
         _check(_lib.elmfb_copy_rhs(self.h, _ptr(hvec), _stream(stream)), self.h)
 
-    def copy_blocks(self, dst=None, stream=None):
+    def copy_blocks(self, dst=None, prec="fp64", stream=None):
         """Returns the block table [n_blocks, 8] (int64); copies raw blocks into dst if given."""
         nb = self.sizes["n_blocks"]
         table = np.zeros((nb, 8), dtype=np.int64)
-        _check(_lib.elmfb_copy_blocks(self.h, _ptr(dst) if dst is not None else None,
+        pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        _check(_lib.elmfb_copy_blocks(self.h, pr, _ptr(dst) if dst is not None else None,
                                       table.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       _stream(stream)), self.h)
         return table
 
+    def gram(self, prec="fp64", which="all", stream=None):
+        pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        w = {"diag": 0, "all": 1}[which] if isinstance(which, str) else int(which)
+        _check(_lib.elmfb_gram(self.h, pr, w, _stream(stream)), self.h)
+
+    def copy_gram(self, dst=None, stream=None):
+        """Pair table [n_pairs, 3] (bi, bj, offset); copies the blocks into dst if given."""
+        n = ctypes.c_int64()
+        _check(_lib.elmfb_copy_gram(self.h, None, None, ctypes.byref(n), _stream(stream)), self.h)
+        table = np.zeros((n.value, 3), dtype=np.int64)
+        _check(_lib.elmfb_copy_gram(self.h, _ptr(dst) if dst is not None else None,
+                                    table.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.byref(n), _stream(stream)), self.h)
+        return table
+
+    def precondition(self, shift=1e-12, stream=None):
+        """Block-Jacobi factors; returns the number of blocks that fell back to the identity."""
+        nf = ctypes.c_int32()
+        _check(_lib.elmfb_precondition(self.h, float(shift), ctypes.byref(nf), _stream(stream)),
+               self.h)
+        return nf.value
+
     def solve(self, coef, method="lsqr", iter_lim=15000, atol=1e-8, btol=1e-8, check_every=50,
               use_graph=True, x0=None, check_pts=None, check_ref=None, target_rel_l2=0.0,
-              stream=None):
+              precond=False, inner_iters=100, outer_lim=10, stream=None):
         o = SolveOpts()
         o.method = _METHOD[method] if isinstance(method, str) else int(method)
         o.iter_lim = int(iter_lim)
         o.check_every = int(check_every)
         o.use_graph = 1 if use_graph else 0
+        o.precond = 1 if precond else 0
+        o.inner_iters = int(inner_iters)
+        o.outer_lim = int(outer_lim)
         o.atol = float(atol)
         o.btol = float(btol)
         o.x0_dev = _ptr(x0)

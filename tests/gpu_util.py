@@ -38,7 +38,7 @@ def device_blocks(P, K, store_prec="fp64"):
     nnz = P.sizes["nnz"]
     dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16}[store_prec]
     buf = torch.empty(nnz, dtype=dt, device="cuda")
-    table = P.copy_blocks(buf)
+    table = P.copy_blocks(buf, prec=store_prec)
     torch.cuda.synchronize()
     host = buf.float().double().cpu().numpy() if store_prec == "bf16" else \
         buf.double().cpu().numpy()

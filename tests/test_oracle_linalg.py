@@ -193,3 +193,61 @@ def test_metrics():
     assert ev.e_l1(u, ue) == pytest.approx(0.25 / np.std(ue))
     assert np.std(ue) == pytest.approx(np.sqrt(np.mean((ue - ue.mean()) ** 2)))
     assert ev.rel_l2(u, ue) == pytest.approx(1.0 / np.linalg.norm(ue))
+
+
+def _tiny2d_blocks():
+    spec = configs.small2d()
+    W, b = feature_params(spec)
+    blocks = asm.assemble_blocks(spec, W, b)
+    return spec, blocks
+
+
+def test_block_jacobi_factors_reconstruct_shifted_gram():
+    """R_j^T R_j = G_jj + lambda_j I, and R_j upper triangular with a positive diagonal."""
+    spec, blocks = _tiny2d_blocks()
+    facs = linalg.block_jacobi_factors(blocks, 1e-10)
+    for blk, R in zip(blocks, facs):
+        G = blk.M.T @ blk.M
+        lam = 1e-10 * np.trace(G) / spec.K
+        assert np.allclose(np.triu(R), R)
+        assert np.all(np.diag(R) > 0)
+        E = R.T @ R - (G + lam * np.eye(spec.K))
+        assert np.abs(E).max() <= 1e-12 * np.abs(G).max()
+
+
+def test_preconditioned_lsqr_reaches_least_squares_solution():
+    """Right preconditioning changes the iteration, not the minimiser: on a full-rank system it
+    converges to the QR solution."""
+    _, _, _, blocks, M, h = _tiny_system()
+    n = M.shape[1]
+    facs = linalg.block_jacobi_factors(blocks, 1e-14)
+    x, res = linalg.preconditioned_lsqr(lambda v: M @ v, lambda u: M.T @ u, blocks, facs, h, n,
+                                        atol=1e-15, btol=1e-15, iter_lim=500)
+    ref = linalg.householder_lstsq(M, h)
+    assert np.linalg.norm(M @ x - h) <= np.linalg.norm(M @ ref - h) * (1 + 1e-9)
+    assert np.linalg.norm(x - ref) <= 1e-8 * np.linalg.norm(ref)
+    # warm start: the correction from x0 reaches the same minimiser
+    x2, _ = linalg.preconditioned_lsqr(lambda v: M @ v, lambda u: M.T @ u, blocks, facs, h, n,
+                                       x0=0.5 * ref, atol=1e-15, btol=1e-15, iter_lim=500)
+    assert np.linalg.norm(x2 - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_refine_lsqr_fp32_inner_fixed_points():
+    """Refinement with the residual in float64 and the correction from LSQR on the float32-rounded
+    matrix: on a consistent system it converges to the exact solution; on an inconsistent one
+    its fixed point satisfies M_lo^T (h - M c) = 0 (the correction of a converged step is zero),
+    which differs from the float64 minimiser by a term proportional to the optimal residual."""
+    A, h = _well_conditioned(m=90, n=30, cond=50.0, seed=10)
+    A32 = lowprec.to_f32(A)
+    x_true = np.random.default_rng(3).standard_normal(30)
+    hc = A @ x_true
+    run = lambda rhs: linalg.refine_lsqr(lambda v: A @ v, lambda u: A.T @ u, lambda v: A32 @ v,
+                                         lambda u: A32.T @ u, rhs, 30, n_outer=10, n_inner=60)
+    c, _ = run(hc)
+    assert np.linalg.norm(c - x_true) <= 1e-13 * np.linalg.norm(x_true)
+    c, _ = run(h)
+    g = A32.T @ (h - A @ c)
+    assert np.linalg.norm(g) <= 1e-12 * np.linalg.norm(A32.T @ h)
+    ref = np.linalg.lstsq(A, h, rcond=None)[0]
+    r_opt = np.linalg.norm(h - A @ ref)
+    assert np.linalg.norm(A @ (c - ref)) <= 1e-5 * r_opt
