@@ -5,9 +5,14 @@ three levels of 1x1, 4x4 and 16x16 subdomains (width ratio 2.9), 96 tanh random 
 subdomain, 400 x 400 collocation grid: 160,000 rows, 26,208 columns, 2.42e8 stored entries.
 
 One step = the whole hot path on one synthetic input already resident in HBM: assemble the
-block-sparse matrix and right-hand side, run the solver until the solution on a 128 x 128 check
-grid is within rel-L2 1e-6 of the reference (or the iteration budget of the method, 15,000
-LSQR iterations, is spent), evaluate the solution on the 480 x 480 test grid.
+block-sparse matrix (FP64, plus an FP32 copy) and right-hand side, build the block-Jacobi
+preconditioner from the FP64 diagonal Gram blocks, run the solver until the solution on a
+128 x 128 check grid is within rel-L2 1e-6 of the exact solution (or the iteration budget of
+15,000 iterations is spent), evaluate the solution on the 480 x 480 test grid.
+
+Default solver: FP64 iterative refinement (residual with the FP64 matrix) around block-Jacobi
+preconditioned LSQR on the FP32 copy.  For comparison the same step is also timed once with
+block-Jacobi LSQR in FP64 and with plain FP64 LSQR (the method's own solver and budget).
 
 Prints one JSON line.  value = collocation rows per second of time-to-solution.
 """
@@ -33,12 +38,14 @@ def parse():
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="poisson3l")
-    p.add_argument("--method", default="lsqr", choices=["lsqr", "cgls", "mixed_ir"])
-    p.add_argument("--precond", action="store_true", help="block-Jacobi from diagonal Gram blocks")
+    p.add_argument("--method", default="mixed_ir", choices=["lsqr", "cgls", "mixed_ir"])
+    p.add_argument("--no-precond", action="store_true", help="no block-Jacobi preconditioning")
     p.add_argument("--shift", type=float, default=1e-12)
-    p.add_argument("--store", default="fp64", choices=["fp64", "fp32", "bf16"],
+    p.add_argument("--store", default="fp32", choices=["fp64", "fp32", "bf16"],
                    help="low-precision stored copy for the inner solves of mixed_ir")
-    p.add_argument("--inner", type=int, default=200)
+    p.add_argument("--inner", type=int, default=2500)
+    p.add_argument("--no-compare", action="store_true",
+                   help="skip the FP64 comparison solves")
     p.add_argument("--iters", type=int, default=15000)
     p.add_argument("--target", type=float, default=1e-6)
     p.add_argument("--check-every", type=int, default=100)
@@ -130,6 +137,7 @@ def main():
     spec = getattr(configs, args.workload)()
     W, b = feature_params(spec)
     f = configs.forcing(spec)
+    precond = not args.no_precond
     P = Problem.from_spec(spec, W, b, args.store)
     fd = torch.as_tensor(f).cuda()
     xc = torch.as_tensor(grid_points(spec, spec.meta["n_check"])).cuda()
@@ -142,19 +150,19 @@ def main():
     coef = torch.empty(n, dtype=torch.float64, device="cuda")
     u_test = torch.empty(xt.shape[0], dtype=torch.float64, device="cuda")
 
-    def step():
+    def step(method=args.method, pre=precond):
         P.assemble(fd)
-        if args.precond:
+        if pre:
             P.precondition(args.shift)
-        if args.method == "mixed_ir":
+        if method == "mixed_ir":
             info = P.solve(coef, method="mixed_ir", inner_iters=args.inner,
                            outer_lim=max(1, args.iters // args.inner), atol=0.0, btol=0.0,
                            check_every=min(args.check_every, args.inner), check_pts=xc,
-                           check_ref=uc, target_rel_l2=args.target, precond=args.precond)
+                           check_ref=uc, target_rel_l2=args.target, precond=pre)
         else:
-            info = P.solve(coef, method=args.method, iter_lim=args.iters, atol=0.0, btol=0.0,
+            info = P.solve(coef, method=method, iter_lim=args.iters, atol=0.0, btol=0.0,
                            check_every=args.check_every, check_pts=xc, check_ref=uc,
-                           target_rel_l2=args.target, precond=args.precond)
+                           target_rel_l2=args.target, precond=pre)
         P.evaluate(coef, xt, u_test)
         return info
 
@@ -170,14 +178,34 @@ def main():
     e_l1 = float(np.mean(np.abs(u - ut_np)) / np.std(ut_np))
     rel_test = float(np.linalg.norm(u - ut_np) / np.linalg.norm(ut_np))
 
-    # roofline of the dominant kernel: the per-chunk pass of x = M^T u (streams the matrix)
-    ms_mv, ms_rmv = P.time_kernels(args.kernel_reps)
+    # roofline of the dominant kernel: the per-chunk pass of x = M^T u over the matrix copy the
+    # inner iterations stream (the FP32 copy for the mixed path)
+    kprec = args.store if args.method == "mixed_ir" else "fp64"
+    es = {"fp64": 8, "fp32": 4, "bf16": 2}[kprec]
+    ms_mv, ms_rmv = P.time_kernels(args.kernel_reps, prec=kprec)
+    ms_mv64, ms_rmv64 = P.time_kernels(args.kernel_reps, prec="fp64")
     nnz, nbp = P.sizes["nnz"], P.sizes["n_block_points"]
-    n_chunks = sum(-(-int(v) // 2048) for v in
-                   [r[4] * r[6] for r in P.copy_blocks()])
-    bytes_rmv = nnz * 8 + nbp * 8 + n_chunks * spec.K * 8
-    bytes_mv = nnz * 8 + nbp * 8
-    achieved = bytes_rmv / (ms_rmv * 1e-3) / 1e9
+    n_chunks = sum(-(-int(v) // 2048) for v in [r[4] * r[6] for r in P.copy_blocks()])
+    rmv_bytes = lambda e: nnz * e + nbp * 8 + n_chunks * spec.K * 8
+    mv_bytes = lambda e: nnz * e + nbp * 8
+    achieved = rmv_bytes(es) / (ms_rmv * 1e-3) / 1e9
+    kname = {"fp64": "FP64", "fp32": "FP32", "bf16": "BF16"}[kprec]
+
+    compare = {}
+    if not args.no_compare:
+        for label, meth, pre in (("fp64_block_jacobi_lsqr", "lsqr", True),
+                                 ("fp64_plain_lsqr", "lsqr", False)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ci = step(meth, pre)
+            torch.cuda.synchronize()
+            compare[label] = {"time_to_solution_s": time.perf_counter() - t1,
+                              "reached_target": bool(ci["istop"] == 8), "iters": ci["iters"],
+                              "rel_l2_check_at_stop": ci["rel_l2"]}
+        compare["speedup_vs_fp64_block_jacobi"] = \
+            compare["fp64_block_jacobi_lsqr"]["time_to_solution_s"] / dt
+        compare["speedup_vs_fp64_plain_lsqr"] = compare["fp64_plain_lsqr"]["time_to_solution_s"] / dt
+
     out = {
         "metric": METRIC,
         "value": spec.n_rows / dt,
@@ -194,7 +222,7 @@ def main():
         "config": {"workload": spec.name, "rows": spec.n_rows, "cols": n, "nnz": nnz,
                    "levels": [list(J) for J in spec.levels], "K": spec.K,
                    "grid": list(spec.n_points),
-                   "method": (f"{args.method}" + ("+block-jacobi" if args.precond else "") +
+                   "method": (f"{args.method}" + ("+block-jacobi" if precond else "") +
                               (f" (inner {args.store} x{args.inner})" if args.method == "mixed_ir"
                                else "-fp64")),
                    "iter_budget": args.iters, "target_rel_l2": args.target,
@@ -208,11 +236,17 @@ def main():
         "e_l1_test": e_l1,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rmv_chunks<FP64> (x = M^T u, per-chunk pass)",
-                     "ms_per_launch": ms_rmv, "algorithmic_bytes_per_launch": bytes_rmv,
-                     "also": {"kernel": "k_mv_blocks<FP64> (y = M v, per-block-point pass)",
-                              "ms_per_launch": ms_mv,
-                              "achieved_GBs": bytes_mv / (ms_mv * 1e-3) / 1e9}},
+                     "kernel": f"k_rmv_chunks<{kname}> (x = M^T u, per-chunk pass)",
+                     "ms_per_launch": ms_rmv, "algorithmic_bytes_per_launch": rmv_bytes(es),
+                     "also": [
+                         {"kernel": f"k_mv_blocks<{kname}> (y = M v, per-block-point pass)",
+                          "ms_per_launch": ms_mv,
+                          "achieved_GBs": mv_bytes(es) / (ms_mv * 1e-3) / 1e9},
+                         {"kernel": "k_rmv_chunks<FP64>", "ms_per_launch": ms_rmv64,
+                          "achieved_GBs": rmv_bytes(8) / (ms_rmv64 * 1e-3) / 1e9},
+                         {"kernel": "k_mv_blocks<FP64>", "ms_per_launch": ms_mv64,
+                          "achieved_GBs": mv_bytes(8) / (ms_mv64 * 1e-3) / 1e9}]},
+        "compare": compare,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, W, b, f, info["iters"])

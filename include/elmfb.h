@@ -222,10 +222,12 @@ elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const doubl
 
 /* Time the two matrix-streaming kernels of one LSQR/CGLS iteration on `stream` with HIP
  * events: the per-block-point pass of y = M v and the per-chunk pass of x = M^T u, each
- * launched `reps` times back to back on the stored matrix (with v = 1, u = 1).  Writes the
- * average duration of one launch in milliseconds to ms_host[0] (M v) and ms_host[1]
- * (M^T u).  Blocks the host until the timing completes. */
-elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t reps, double* ms_host, void* stream);
+ * launched `reps` times back to back on the stored matrix copy of precision `prec`
+ * (ELMFB_FP64 or the descriptor's store_prec), with v = 1, u = 1.  Writes the average duration
+ * of one launch in milliseconds to ms_host[0] (M v) and ms_host[1] (M^T u).  Blocks the host
+ * until the timing completes. */
+elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t prec, int32_t reps, double* ms_host,
+                                void* stream);
 
 /* Release everything the handle owns.  NULL is a no-op. */
 void elmfb_destroy(elmfb_problem h);

@@ -563,9 +563,14 @@ elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const doubl
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t reps, double* ms_host, void* stream) {
+elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t prec, int32_t reps, double* ms_host,
+                                void* stream) {
   if (!h || !ms_host || reps < 1) return fail(h, ELMFB_E_INVALID, "bad argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "time_kernels before assemble");
+  const void* A = nullptr;
+  if (prec == ELMFB_FP64) A = h->d_A;
+  else if (prec == h->lo_prec && h->d_A_lo) A = h->d_A_lo;
+  else return fail(h, ELMFB_E_STATE, "no stored copy in that precision");
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->geo;
   // v = 1 (in d_x), u = 1 (in d_t)
@@ -578,12 +583,12 @@ elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t reps, double* ms_host, 
   HIP_OR_FAIL(h, hipEventCreate(&e2));
   hipError_t e = hipEventRecord(e0, s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
-    e = launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), h->d_A,
-                         h->d_x, nullptr, h->d_tpart, nullptr, s);
+    e = launch_mv_blocks(g, prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), A, h->d_x,
+                         nullptr, h->d_tpart, nullptr, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
-    e = launch_rmv_chunks(g, ELMFB_FP64, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
-                          h->d_A, h->d_t, nullptr, h->d_part, nullptr, s);
+    e = launch_rmv_chunks(g, prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), A,
+                          h->d_t, nullptr, h->d_part, nullptr, s);
   if (e == hipSuccess) e = hipEventRecord(e2, s);
   if (e == hipSuccess) e = hipEventSynchronize(e2);
   float t01 = 0.f, t12 = 0.f;

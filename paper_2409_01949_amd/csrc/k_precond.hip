@@ -95,62 +95,89 @@ __global__ void __launch_bounds__(256) k_bj_factor(Geo g, const double* __restri
   }
 }
 
-// y = R^{-1} (v * scale), one block of K coefficients per iteration of the grid-stride loop.
+// The three applications below are batched upper-triangular matrix-vector products, one K x K
+// factor per subdomain.  Work is split into tasks of 32 output coefficients of one block; a
+// workgroup of 256 threads takes a task at a time (grid-stride), thread t owns output
+// coefficient t % 32 and sums every 8th term of its dot product (split t / 32), and the 8
+// partial sums are added in a fixed order through LDS.  Consecutive threads read consecutive
+// factor entries.
+constexpr int kBjRows = 32;
+constexpr int kBjSplit = 8;
+
+__device__ __forceinline__ int bj_tasks(const Geo& g) {
+  return g.n_blocks * ((g.K + kBjRows - 1) / kBjRows);
+}
+
+// y = R^{-1} (v * scale):  y_i = sum_{k >= i} Ri[i][k] v_k = sum_k T[k][i] v_k
 __global__ void __launch_bounds__(256) k_bj_apply(Geo g, const double* __restrict__ rinvT,
                                                   const double* __restrict__ v,
                                                   const double* __restrict__ scale,
                                                   double* __restrict__ y,
                                                   const SolveState* __restrict__ st) {
-  __shared__ double vs[256];
+  __shared__ double part[kBjSplit][kBjRows];
   if (st && st->done) return;
   const int K = g.K;
+  const int per = (K + kBjRows - 1) / kBjRows;
   const double sc = scale ? *scale : 1.0;
-  for (int b = blockIdx.x; b < g.n_blocks; b += gridDim.x) {
+  const int ro = threadIdx.x % kBjRows, sp = threadIdx.x / kBjRows;
+  for (int task = blockIdx.x; task < bj_tasks(g); task += gridDim.x) {
+    const int b = task / per, i = (task - b * per) * kBjRows + ro;
     const int64_t q0 = (int64_t)b * K;
-    for (int k = threadIdx.x; k < K; k += 256) vs[k] = v[q0 + k] * sc;
-    __syncthreads();
     const double* T = rinvT + (int64_t)b * K * K;
-    for (int i = threadIdx.x; i < K; i += 256) {
-      double s = 0.0;
-      for (int k = i; k < K; ++k) s += T[(int64_t)k * K + i] * vs[k];   // Ri[i][k] = T[k][i]
-      y[q0 + i] = s;
+    double s = 0.0;
+    if (i < K)
+      for (int k = i + sp; k < K; k += kBjSplit) s += T[(int64_t)k * K + i] * v[q0 + k];
+    part[sp][ro] = s;
+    __syncthreads();
+    if (sp == 0 && i < K) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kBjSplit; ++q) t += part[q][ro];
+      y[q0 + i] = t * sc;
     }
     __syncthreads();
   }
 }
 
-// z = R^{-T} x per block, then the LSQR epilogue on v (v = z - beta sv v, partial ||v||^2) or a
-// plain store (mode COL_STORE / COL_STORE_SQ).
+// z = R^{-T} x:  z_k = sum_{i <= k} Ri[i][k] x_i, then the LSQR epilogue on v
+// (v = z - beta sv v, partial ||v||^2) or a plain store (COL_STORE / COL_STORE_SQ).
 __global__ void __launch_bounds__(256) k_bj_apply_t(Geo g, const double* __restrict__ rinv,
                                                     const double* __restrict__ x, int mode,
                                                     double* __restrict__ out,
                                                     const SolveState* __restrict__ st,
                                                     double* __restrict__ red) {
-  __shared__ double xs[256];
+  __shared__ double part[kBjSplit][kBjRows];
   __shared__ double sh[4];
   if (st && st->done) return;
   const int K = g.K;
+  const int per = (K + kBjRows - 1) / kBjRows;
   double coef_v = 0.0;
   bool keep = false;
   if (mode == COL_LSQR_V) {
     coef_v = st->beta * st->sv;
     keep = !(st->beta > 0.0);
   }
+  const int ro = threadIdx.x % kBjRows, sp = threadIdx.x / kBjRows;
   double acc = 0.0;
-  for (int b = blockIdx.x; b < g.n_blocks; b += gridDim.x) {
+  for (int task = blockIdx.x; task < bj_tasks(g); task += gridDim.x) {
+    const int b = task / per, k = (task - b * per) * kBjRows + ro;
     const int64_t q0 = (int64_t)b * K;
-    for (int k = threadIdx.x; k < K; k += 256) xs[k] = x[q0 + k];
-    __syncthreads();
     const double* Ri = rinv + (int64_t)b * K * K;
-    for (int k = threadIdx.x; k < K; k += 256) {
+    double s = 0.0;
+    if (k < K)
+      for (int i = sp; i <= k; i += kBjSplit) s += Ri[(int64_t)i * K + k] * x[q0 + i];
+    part[sp][ro] = s;
+    __syncthreads();
+    if (sp == 0 && k < K) {
       double z = 0.0;
-      for (int i = 0; i <= k; ++i) z += Ri[(int64_t)i * K + k] * xs[i];  // (R^{-T} x)_k
+#pragma unroll
+      for (int q = 0; q < kBjSplit; ++q) z += part[q][ro];
       if (mode == COL_STORE) {
         out[q0 + k] = z;
       } else if (mode == COL_LSQR_V) {
-        double v = out[q0 + k];
-        if (!keep) { v = z - coef_v * v; out[q0 + k] = v; }
-        acc += v * v;
+        double vv = out[q0 + k];
+        if (!keep) { vv = z - coef_v * vv; out[q0 + k] = vv; }
+        acc += vv * vv;
       } else {
         out[q0 + k] = z;
         acc += z * z;
@@ -159,33 +186,43 @@ __global__ void __launch_bounds__(256) k_bj_apply_t(Geo g, const double* __restr
     __syncthreads();
   }
   if (mode != COL_STORE) {
-    const double s = block_sum256(acc, sh);
-    if (threadIdx.x == 0) red[blockIdx.x] = s;
+    const double t = block_sum256(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = t;
   }
 }
 
-// x = x0 + R^{-1} y  (x0 may be NULL)
-// x0 and x may be the same vector (each element is read and then written by one thread).
+// x = x0 + R^{-1} y  (x0 may be NULL).  x0 and x may be the same vector: each element is read
+// and then written by one thread, after every read of y.
 __global__ void __launch_bounds__(256) k_bj_recover(Geo g, const double* __restrict__ rinvT,
                                                     const double* __restrict__ yv,
                                                     const double* x0, double* x) {
-  __shared__ double vs[256];
+  __shared__ double part[kBjSplit][kBjRows];
   const int K = g.K;
-  for (int b = blockIdx.x; b < g.n_blocks; b += gridDim.x) {
+  const int per = (K + kBjRows - 1) / kBjRows;
+  const int ro = threadIdx.x % kBjRows, sp = threadIdx.x / kBjRows;
+  for (int task = blockIdx.x; task < bj_tasks(g); task += gridDim.x) {
+    const int b = task / per, i = (task - b * per) * kBjRows + ro;
     const int64_t q0 = (int64_t)b * K;
-    for (int k = threadIdx.x; k < K; k += 256) vs[k] = yv[q0 + k];
-    __syncthreads();
     const double* T = rinvT + (int64_t)b * K * K;
-    for (int i = threadIdx.x; i < K; i += 256) {
-      double s = 0.0;
-      for (int k = i; k < K; ++k) s += T[(int64_t)k * K + i] * vs[k];
-      x[q0 + i] = (x0 ? x0[q0 + i] : 0.0) + s;
+    double s = 0.0;
+    if (i < K)
+      for (int k = i + sp; k < K; k += kBjSplit) s += T[(int64_t)k * K + i] * yv[q0 + k];
+    part[sp][ro] = s;
+    __syncthreads();
+    if (sp == 0 && i < K) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kBjSplit; ++q) t += part[q][ro];
+      x[q0 + i] = (x0 ? x0[q0 + i] : 0.0) + t;
     }
     __syncthreads();
   }
 }
 
-int bj_wg(const Geo& g) { return g.n_blocks < kRedBlocks ? g.n_blocks : kRedBlocks; }
+int bj_wg(const Geo& g) {
+  const int tasks = g.n_blocks * ((g.K + kBjRows - 1) / kBjRows);
+  return tasks < kRedBlocks ? tasks : kRedBlocks;
+}
 
 hipError_t launch_bj_factor(const Geo& g, const double* G, const int64_t* diag_off, double shift,
                             double* work, double* rinv, double* rinvT, int32_t* nfail,

@@ -469,16 +469,36 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, launch_reduce_to(red_slot(h, 3), rw, h->d_scalar, s));
       HIP_OR_FAIL(h, solve_init(h, inner, ELMFB_LSQR, nullptr, s));
       int left = opts->inner_iters;
+      bool hit = false;
       while (left > 0) {
         const int n = std::min(left, opts->check_every);
         HIP_OR_FAIL(h, run_iterations(h, inner, ELMFB_LSQR, n, opts->use_graph != 0, s));
         left -= n;
+        if (opts->n_check > 0 && left > 0) {
+          // trial solution c + d after this part of the inner solve
+          if (bj)
+            HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_xt, s));
+          else {
+            HIP_OR_FAIL(h, launch_copy(h->d_c, h->d_xt, g.n_phi, s));
+            HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_xt, g.n_phi, s));
+          }
+          HIP_OR_FAIL(h, check_solution(h, opts, h->d_xt, s));
+          HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
+          HIP_OR_FAIL(h, hipStreamSynchronize(s));
+          if (st.target_hit) {
+            HIP_OR_FAIL(h, launch_copy(h->d_xt, h->d_c, g.n_phi, s));
+            hit = true;
+            break;
+          }
+        }
       }
-      if (bj)
-        HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_c, s));
-      else
-        HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_c, g.n_phi, s));
-      if (opts->n_check > 0) HIP_OR_FAIL(h, check_solution(h, opts, h->d_c, s));
+      if (!hit) {
+        if (bj)
+          HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_c, s));
+        else
+          HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_c, g.n_phi, s));
+        if (opts->n_check > 0) HIP_OR_FAIL(h, check_solution(h, opts, h->d_c, s));
+      }
       double rr = 0.0;
       HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
       HIP_OR_FAIL(h, hipMemcpyAsync(&rr, h->d_scalar, 8, hipMemcpyDeviceToHost, s));

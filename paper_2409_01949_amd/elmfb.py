@@ -130,7 +130,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_precondition": (i32, [P, dbl, ctypes.POINTER(i32), P]),
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
-        "elmfb_time_kernels": (i32, [P, i32, ctypes.POINTER(dbl), P]),
+        "elmfb_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(dbl), P]),
         "elmfb_destroy": (None, [P]),
         "elmfb_last_error": (ctypes.c_char_p, [P]),
     }
@@ -304,10 +304,11 @@ class Problem:
         _check(_lib.elmfb_evaluate(self.h, _ptr(coef), _ptr(pts), int(n), _ptr(u),
                                    _stream(stream)), self.h)
 
-    def time_kernels(self, reps=20, stream=None):
+    def time_kernels(self, reps=20, prec="fp64", stream=None):
         """Average duration (ms) of one launch of the M v and M^T u streaming kernels."""
         out = (ctypes.c_double * 2)()
-        _check(_lib.elmfb_time_kernels(self.h, int(reps), out, _stream(stream)), self.h)
+        pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        _check(_lib.elmfb_time_kernels(self.h, pr, int(reps), out, _stream(stream)), self.h)
         return float(out[0]), float(out[1])
 
     def destroy(self):
