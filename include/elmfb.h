@@ -229,6 +229,43 @@ elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const doubl
 elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t prec, int32_t reps, double* ms_host,
                                 void* stream);
 
+/* ---- batches: many independent problems solved together -------------------------------- */
+
+typedef struct elmfb_batch_s* elmfb_batch;
+
+/* Define n independent problems (descs[i] as for elmfb_define_problem, every instance with
+ * K <= 128 and the same store_prec), each with n_rhs (1..8) right-hand sides that share its
+ * matrix.  Every kernel of the assembly and of the Krylov iteration then processes all instances
+ * and right-hand sides in one launch (the instances are concatenated; row and column work comes
+ * in tiles of one instance).  The footprint is checked before allocating (ELMFB_E_NOMEM). */
+elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int32_t n_rhs,
+                                elmfb_batch* out);
+
+/* offsets_host [n+1][2]: first global row and column of every instance, then the totals;
+ * totals_host: summed sizes (n_pairs = 0).  Either may be NULL. */
+elmfb_status elmfb_batch_query(elmfb_batch b, int64_t* offsets_host, elmfb_sizes* totals_host);
+
+/* Assemble every instance (FP64 plus the store_prec copy) and h = f/sqrt(N_I) per right-hand
+ * side.  f_dev holds instance i at f_dev + n_rhs*row_off_i as [n_rhs][n_rows_i]. */
+elmfb_status elmfb_batch_assemble(elmfb_batch b, const double* f_dev, void* stream);
+
+/* Y = M V for every instance and right-hand side, V at n_rhs*col_off_i as [n_rhs][n_phi_i] and
+ * Y at n_rhs*row_off_i as [n_rhs][n_rows_i]; rmatvec: X = M^T U in the same layouts. */
+elmfb_status elmfb_batch_matvec(elmfb_batch b, const double* v_dev, double* y_dev, void* stream);
+elmfb_status elmfb_batch_rmatvec(elmfb_batch b, const double* u_dev, double* x_dev, void* stream);
+
+/* LSQR (FP64, Paige-Saunders, damp 0) on every (instance, right-hand side) with its own
+ * recurrence and stop tests (atol, btol, iter_lim, check_every, use_graph of opts; method must
+ * be ELMFB_LSQR, no preconditioner, no warm start, no check points).  The iteration loop over
+ * the whole batch is captured in a hipGraph; the host checks the number of pairs still running
+ * once per replay.  coef_dev in the V layout; info_host [n*n_rhs] (instance-major) may be
+ * NULL. */
+elmfb_status elmfb_batch_solve(elmfb_batch b, const elmfb_solve_opts* opts, double* coef_dev,
+                               elmfb_solve_info* info_host, void* stream);
+
+void elmfb_batch_destroy(elmfb_batch b);
+const char* elmfb_batch_last_error(elmfb_batch b);
+
 /* Release everything the handle owns.  NULL is a no-op. */
 void elmfb_destroy(elmfb_problem h);
 

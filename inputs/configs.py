@@ -134,15 +134,16 @@ def test_grid(spec: ProblemSpec, which="n_test") -> np.ndarray:
 
 # ---------------------------------------------------------------- batched ragged instances
 
-def batch_instances(n=512, seed=3, n_rhs=8):
+def batch_instances(n=512, seed=3, n_rhs=8, J_range=(4, 24), K_range=(64, 128),
+                    p_range=(20.0, 60.0)):
     """Ragged 2D Poisson instances: J~U{4..24} square, K~U{64..128}, 20..60 grid points per
     subdomain cell, 3 integer modes k~U{1..20}, per-RHS amplitudes N(0,1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     specs, amps = [], []
     for i in range(n):
-        J = int(rng.integers(4, 25))
-        K = int(rng.integers(64, 129))
-        p = float(rng.uniform(20.0, 60.0))
+        J = int(rng.integers(J_range[0], J_range[1] + 1))
+        K = int(rng.integers(K_range[0], K_range[1] + 1))
+        p = float(rng.uniform(p_range[0], p_range[1]))
         g = int(round(J * math.sqrt(p)))
         ks = tuple(float(v) for v in rng.integers(1, 21, size=3))
         A = rng.standard_normal((n_rhs, 3))

@@ -66,7 +66,7 @@ double centre_x(double lo, double hi, int J, int j) {
   return t + lo;
 }
 
-std::string validate(const elmfb_problem_desc* d) {
+std::string validate_impl(const elmfb_problem_desc* d) {
   if (!d) return "descriptor is NULL";
   if (d->abi_version != ELMFB_ABI_VERSION) return "abi_version mismatch";
   if (d->dim != 1 && d->dim != 2) return "dim must be 1 or 2";
@@ -98,7 +98,7 @@ std::string validate(const elmfb_problem_desc* d) {
 }
 
 // Build every host table of the decomposition.
-std::string plan(elmfb_problem h) {
+std::string plan_impl(elmfb_problem h) {
   const elmfb_problem_desc& d = h->desc;
   Geo& g = h->geo;
   std::memset(&g, 0, sizeof(g));
@@ -312,18 +312,23 @@ void release(elmfb_problem h) {
 
 }  // namespace
 
+namespace elmfb {
+std::string validate_desc(const elmfb_problem_desc* d) { return validate_impl(d); }
+std::string plan_problem(elmfb_problem h) { return plan_impl(h); }
+}  // namespace elmfb
+
 extern "C" {
 
 elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out) {
   if (!out) return fail(nullptr, ELMFB_E_INVALID, "out is NULL");
   *out = nullptr;
-  const std::string v = validate(desc);
+  const std::string v = validate_impl(desc);
   if (!v.empty()) return fail(nullptr, ELMFB_E_INVALID, v);
   elmfb_problem h = new (std::nothrow) elmfb_problem_s();
   if (!h) return fail(nullptr, ELMFB_E_NOMEM, "host allocation failed");
   h->desc = *desc;
   h->lo_prec = desc->store_prec;
-  const std::string pe = plan(h);
+  const std::string pe = plan_impl(h);
   if (!pe.empty()) {
     delete h;
     return fail(nullptr, ELMFB_E_INVALID, pe);

@@ -24,7 +24,7 @@ struct DevBlock {
   int32_t tabx;     // offset of the x-axis envelope table entries for ix0..ix0+nx-1
   int32_t taby;     // offset of the y-axis envelope table entries for iy0..iy0+ny-1
   int32_t level;
-  int32_t pad;
+  int32_t inst;     // instance of a batch (0 for a single problem)
 };
 
 constexpr int kGramChunk = 4096;  // shared points per Gram chunk
@@ -41,6 +41,27 @@ struct GramPair {
 struct GramChunk {
   int32_t pair;
   int32_t s0;                 // first shared point of the chunk (box row-major)
+};
+
+// ---- batches of independent instances with several right-hand sides
+constexpr int kMaxRhs = 8;
+constexpr int kBatchMaxK = 128;      // features per subdomain in a batch
+constexpr int kBChunkPts = 1024;     // points per batched A^T U chunk (4 per thread)
+
+struct RowTile {    // <= 256 consecutive rows of one instance
+  int32_t inst;
+  int32_t r0;       // first global row
+};
+
+struct ColTile {    // <= 256 consecutive columns of one instance
+  int32_t inst;
+  int32_t q0;       // first global column
+};
+
+struct InstInfo {
+  int64_t row_off, col_off;   // global offsets of the instance's rows and columns
+  int32_t rt0, rt1;           // its row tiles
+  int32_t ct0, ct1;           // its column tiles
 };
 
 struct Tile {       // a run of <= kTile consecutive points of one block

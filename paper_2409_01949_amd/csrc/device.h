@@ -80,6 +80,35 @@ __device__ __forceinline__ double block_sum256(double v, double* sh /* >= 4 doub
   return r;
 }
 
+// Sum 8 per-lane values over the 64 lanes of a wavefront with a transposing butterfly: after
+// the exchanges across lanes 32, 16 and 8 apart each lane holds one of the 8 features (index
+// 4*b5 + 2*b4 + b3 of its lane bits), then three plain steps finish the sums; 10 shuffles for
+// 8 features instead of 48.  Fixed order, so deterministic.
+__device__ __forceinline__ double butterfly8(const double a[8], int lane, int* feat) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double c[4], d[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = b5 ? a[i] : a[i + 4];
+    const double keep = b5 ? a[i + 4] : a[i];
+    c[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b4 ? c[i] : c[i + 2];
+    const double keep = b4 ? c[i + 2] : c[i];
+    d[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  const double send = b3 ? d[0] : d[1];
+  const double keep = b3 ? d[1] : d[0];
+  double v = keep + __shfl_xor(send, 8, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  *feat = (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+  return v;
+}
+
 template <int PREC>
 __device__ __forceinline__ double load_entry(const void* A, int64_t i);
 

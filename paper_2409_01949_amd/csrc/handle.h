@@ -112,4 +112,8 @@ hipError_t dalloc(elmfb_problem h, T** p, int64_t bytes) {
 }
 void dfree(elmfb_problem h, void* p);
 
+// Descriptor checks and the host-side decomposition plan of one problem (no device work).
+std::string validate_desc(const elmfb_problem_desc* d);
+std::string plan_problem(elmfb_problem h);
+
 }  // namespace elmfb

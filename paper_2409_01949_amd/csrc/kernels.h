@@ -92,6 +92,52 @@ hipError_t launch_bj_apply_t(const Geo& g, const double* rinv, const double* x, 
 hipError_t launch_bj_recover(const Geo& g, const double* rinvT, const double* y, const double* x0,
                              double* x, hipStream_t s);
 
+// ---- batches (k_batch.hip)
+struct BSeg {
+  AxisSeg s;
+  int32_t inst;
+  int32_t pad;
+};
+hipError_t launch_bt_tables(const Geo* geos, const BSeg* segs, int n_segs, const int32_t* cov,
+                            double* tab, hipStream_t s);
+hipError_t launch_bt_assemble(int lo_prec, const Geo* geos, const DevBlock* blocks,
+                              const Tile* tiles, int64_t n_tiles, const double* tab,
+                              const double* W, const double* b, double* A, void* A_lo,
+                              hipStream_t s);
+hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* rt, int64_t n_rt,
+                         int R, const double* f, double* h, int32_t* bad, hipStream_t s);
+hipError_t launch_bt_mv(int prec, const Geo* geos, const DevBlock* blocks, const Tile* tiles,
+                        int64_t n_tiles, const void* A, const double* v, int R,
+                        const SolveState* st, double* tpart, hipStream_t s);
+hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
+                            const int32_t* cov, const RowTile* rt, int64_t n_rt,
+                            const double* tpart, int mode, int R, double* out, const double* bvec,
+                            const SolveState* st, double* red, hipStream_t s);
+hipError_t launch_bt_rmv(int prec, const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
+                         const Tile* chunks, int64_t n_chunks, const void* A, const double* u,
+                         int R, const SolveState* st, double* part, hipStream_t s);
+hipError_t launch_bt_finish(const Geo* geos, const InstInfo* insts, const ColTile* ct,
+                            int64_t n_ct, const int32_t* cstart, const double* part, int mode,
+                            int R, double* out, const SolveState* st, double* red, hipStream_t s);
+hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,
+                               const double* red_b, const double* red_u, double atol, double btol,
+                               int iter_lim, hipStream_t s);
+hipError_t launch_bt_lsqr_init_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,
+                                     const double* red, hipStream_t s);
+hipError_t launch_bt_lsqr_beta(SolveState* st, const InstInfo* insts, int n_inst, int R,
+                               const double* red, hipStream_t s);
+hipError_t launch_bt_lsqr_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,
+                                const double* red, hipStream_t s);
+hipError_t launch_bt_update(const Geo* geos, const InstInfo* insts, const ColTile* ct, int64_t n_ct,
+                            int R, double* x, double* w, const double* v, const SolveState* st,
+                            double* red, hipStream_t s);
+hipError_t launch_bt_lsqr_stop(SolveState* st, const InstInfo* insts, int n_inst, int R,
+                               const double* red, hipStream_t s);
+hipError_t launch_bt_count_active(const SolveState* st, int n, int32_t* out, hipStream_t s);
+hipError_t launch_bt_pack(const InstInfo* insts, const int64_t* sizes, int n_inst, int R,
+                          int64_t total, const double* src, double* dst, int to_interleaved,
+                          int use_cols, hipStream_t s);
+
 // ---- evaluation (k_evaluate.hip)
 hipError_t launch_evaluate(const Geo& g, const double* W, const double* b, const double* coef,
                            const double* pts, int64_t n_pts, double* u, hipStream_t s);

@@ -131,6 +131,14 @@ def load_library(path: Optional[str] = None):
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
         "elmfb_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(dbl), P]),
+        "elmfb_define_batch": (i32, [ctypes.POINTER(ProblemDesc), i32, i32, ctypes.POINTER(P)]),
+        "elmfb_batch_query": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(Sizes)]),
+        "elmfb_batch_assemble": (i32, [P, P, P]),
+        "elmfb_batch_matvec": (i32, [P, P, P, P]),
+        "elmfb_batch_rmatvec": (i32, [P, P, P, P]),
+        "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
+        "elmfb_batch_destroy": (None, [P]),
+        "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
         "elmfb_destroy": (None, [P]),
         "elmfb_last_error": (ctypes.c_char_p, [P]),
     }
@@ -314,6 +322,73 @@ class Problem:
     def destroy(self):
         if self.h is not None and _lib is not None:
             _lib.elmfb_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns one elmfb_batch handle: many instances, n_rhs right-hand sides each."""
+
+    def __init__(self, specs, Ws, bs, n_rhs, store_prec="fp64"):
+        lib = load_library()
+        keep = []
+        arr = (ProblemDesc * len(specs))()
+        for i, (sp, W, b) in enumerate(zip(specs, Ws, bs)):
+            d, k = desc_from_spec(sp, W, b, store_prec)
+            arr[i] = d
+            keep.append(k)
+        h = ctypes.c_void_p()
+        code = lib.elmfb_define_batch(arr, len(specs), int(n_rhs), ctypes.byref(h))
+        if code != OK:
+            msg = lib.elmfb_last_error(None) or b""
+            msg2 = lib.elmfb_batch_last_error(None) or b""
+            raise ElmfbError(code, (msg2 or msg).decode())
+        self.h = h
+        self.n = len(specs)
+        self.n_rhs = int(n_rhs)
+        offs = np.zeros((self.n + 1, 2), dtype=np.int64)
+        tot = Sizes()
+        self._check(lib.elmfb_batch_query(self.h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          ctypes.byref(tot)))
+        self.offsets = offs
+        self.sizes = {n: getattr(tot, n) for n, _ in Sizes._fields_}
+
+    def _check(self, code):
+        if code != OK:
+            msg = _lib.elmfb_batch_last_error(self.h)
+            raise ElmfbError(code, msg.decode() if msg else "")
+
+    def assemble(self, f, stream=None):
+        self._check(_lib.elmfb_batch_assemble(self.h, _ptr(f), _stream(stream)))
+
+    def matvec(self, v, y, stream=None):
+        self._check(_lib.elmfb_batch_matvec(self.h, _ptr(v), _ptr(y), _stream(stream)))
+
+    def rmatvec(self, u, x, stream=None):
+        self._check(_lib.elmfb_batch_rmatvec(self.h, _ptr(u), _ptr(x), _stream(stream)))
+
+    def solve(self, coef, iter_lim=15000, atol=0.0, btol=1e-6, check_every=50, use_graph=True,
+              stream=None):
+        o = SolveOpts()
+        o.method = LSQR
+        o.iter_lim = int(iter_lim)
+        o.check_every = int(check_every)
+        o.use_graph = 1 if use_graph else 0
+        o.atol = float(atol)
+        o.btol = float(btol)
+        infos = (SolveInfo * (self.n * self.n_rhs))()
+        self._check(_lib.elmfb_batch_solve(self.h, ctypes.byref(o), _ptr(coef), infos,
+                                           _stream(stream)))
+        return [i.as_dict() for i in infos]
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.elmfb_batch_destroy(self.h)
         self.h = None
 
     def __del__(self):
