@@ -254,12 +254,45 @@ elmfb_status elmfb_batch_assemble(elmfb_batch b, const double* f_dev, void* stre
 elmfb_status elmfb_batch_matvec(elmfb_batch b, const double* v_dev, double* y_dev, void* stream);
 elmfb_status elmfb_batch_rmatvec(elmfb_batch b, const double* u_dev, double* x_dev, void* stream);
 
-/* LSQR (FP64, Paige-Saunders, damp 0) on every (instance, right-hand side) with its own
- * recurrence and stop tests (atol, btol, iter_lim, check_every, use_graph of opts; method must
- * be ELMFB_LSQR, no preconditioner, no warm start, no check points).  The iteration loop over
- * the whole batch is captured in a hipGraph; the host checks the number of pairs still running
- * once per replay.  coef_dev in the V layout; info_host [n*n_rhs] (instance-major) may be
- * NULL. */
+/* Right block-Jacobi preconditioner for every block of every instance, as elmfb_precondition
+ * does for one problem (Sec. 5 "Conditioning and redundancy" motivates it): the diagonal Gram
+ * block G_b = M_b^T M_b (FP64, matrix cores), the Cholesky factor R_b of
+ * G_b + shift trace(G_b)/K_b I and R_b^{-1}, then the preconditioned matrix M_b R_b^{-1} formed
+ * once (FP64, matrix cores; its store_prec rounding replaces the low-precision copy of M), so
+ * preconditioned Krylov steps cost what plain ones do.  shift in (0, 1).  n_fallback_host (may
+ * be NULL) receives the number of blocks whose factorisation failed at every retry (100x larger
+ * shift, 8 times) and got the identity.  Keeps 8 (nnz + sum_b K_b (K_b+1)/2) bytes on the device;
+ * temporary: 16 sum_b K_b^2 bytes.  A later elmfb_batch_assemble discards it.  Synchronises
+ * the stream. */
+elmfb_status elmfb_batch_precondition(elmfb_batch b, double shift, int32_t* n_fallback_host,
+                                      void* stream);
+
+/* Time the candidate point-tile sizes (16, 32, 64 points per LDS stage) of the batched M^T U
+ * pass on the assembled matrix copy of precision `prec` (ELMFB_FP64 or the batch's store_prec),
+ * `reps` launches each (1..1000), and keep the fastest for later solves of that precision.
+ * ms_host [3] (may be NULL) receives the average milliseconds per launch (-1: not available for
+ * this precision; FP64 has no 64-point variant); chosen_host (may be NULL) the tile kept.
+ * Overwrites the solver's work vectors; synchronises. */
+elmfb_status elmfb_batch_autotune(elmfb_batch b, int32_t prec, int32_t reps, double* ms_host,
+                                  int32_t* chosen_host, void* stream);
+
+/* Set the point tile of the batched M^T U pass for matrix precision `prec` by hand (16, 32, or
+ * 64 except for ELMFB_FP64), as elmfb_batch_autotune would keep it. */
+elmfb_status elmfb_batch_set_tile(elmfb_batch b, int32_t prec, int32_t tile);
+
+/* Solve every (instance, right-hand side) with its own recurrence and stop tests (Sec. 4.1:
+ * LSQR, Paige-Saunders, damp 0; FP64 recurrences).
+ *   method ELMFB_LSQR: LSQR on the FP64 matrix with atol, btol, iter_lim;
+ *   method ELMFB_MIXED_IR: FP64 refinement c += d with d from inner LSQR on the store_prec copy
+ *     (at most inner_iters steps; an inner solve also stops once its residual estimate is half
+ *     the outer target), the residual h - M c recomputed with the FP64 matrix after each step;
+ *     a pair stops when ||h - M c|| <= btol ||h|| (istop 1) or after outer_lim steps (istop 7).
+ * precond = 1 runs on the preconditioned matrix of elmfb_batch_precondition (M R^{-1}, and its
+ * low-precision rounding for MIXED_IR) and returns x = R^{-1} y.  After elmfb_batch_precondition
+ * an unpreconditioned MIXED_IR solve needs elmfb_batch_assemble again (ELMFB_E_STATE).  No warm start and no check points.  The iteration loop over the
+ * whole batch is captured in a hipGraph (use_graph) of check_every steps; the host reads the
+ * number of pairs still running after each replay.  coef_dev in the V layout; info_host
+ * [n*n_rhs] (instance-major) may be NULL; MIXED_IR reports the true FP64 residual as rnorm. */
 elmfb_status elmfb_batch_solve(elmfb_batch b, const elmfb_solve_opts* opts, double* coef_dev,
                                elmfb_solve_info* info_host, void* stream);
 

@@ -12,6 +12,7 @@ The matrix enters through callables matvec(v) -> M v and rmatvec(u) -> M^T u.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional
 
@@ -315,6 +316,15 @@ def block_apply(blocks, factors, v, transpose=False, inverse=True):
         else:
             y[q] = (R.T @ v[q]) if transpose else (R @ v[q])
     return y
+
+
+def fold_blocks(blocks, factors):
+    """The right-preconditioned blocks M_j R_j^{-1} (same rows), formed once; LSQR on them is
+    LSQR on M R^{-1}, and a coefficient vector y of the folded system maps back as R^{-1} y."""
+    out = []
+    for blk, R in zip(blocks, factors):
+        out.append(dataclasses.replace(blk, M=np.linalg.solve(R.T, blk.M.T).T))
+    return out
 
 
 def preconditioned_lsqr(matvec, rmatvec, blocks, factors, h, n, x0=None, **kw):

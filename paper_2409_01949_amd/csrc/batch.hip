@@ -22,34 +22,44 @@ struct elmfb_batch_s {
   std::vector<InstInfo> insts;
   std::vector<int64_t> nrows, nphis;
   std::vector<DevBlock> blocks;
-  std::vector<Tile> tiles, chunks;
-  std::vector<int32_t> cstart, cov;
+  std::vector<Tile> tiles, ftiles;
+  std::vector<int32_t> cov;
   std::vector<BSeg> segs;
   std::vector<RowTile> rtiles;
   std::vector<ColTile> ctiles;
-  int64_t n_rows = 0, n_phi = 0, nnz = 0, n_bp = 0, n_tab = 0, bytes = 0;
+  std::vector<int64_t> foff, goff;   // per block: packed-factor and square Gram offsets
+  int64_t n_rows = 0, n_phi = 0, nnz = 0, n_bp = 0, n_tab = 0, n_fac = 0, n_gsq = 0, bytes = 0;
+  int tp[3] = {32, 32, 32};          // points per LDS stage of A^T U, per matrix precision
+  bool tuned[3] = {false, false, false};
 
   std::vector<void*> allocs;
   Geo* d_geos = nullptr;
   InstInfo* d_insts = nullptr;
   int64_t *d_nrows = nullptr, *d_nphis = nullptr;
   DevBlock* d_blocks = nullptr;
-  Tile *d_tiles = nullptr, *d_chunks = nullptr;
-  int32_t *d_cstart = nullptr, *d_cov = nullptr;
+  Tile* d_tiles = nullptr;
+  int32_t* d_cov = nullptr;
   BSeg* d_segs = nullptr;
   RowTile* d_rtiles = nullptr;
   ColTile* d_ctiles = nullptr;
+  int64_t *d_foff = nullptr, *d_goff = nullptr;
   double *d_tab = nullptr, *d_W = nullptr, *d_b = nullptr, *d_A = nullptr;
   void* d_A_lo = nullptr;
-  double *d_h = nullptr, *d_u = nullptr, *d_v = nullptr, *d_w = nullptr, *d_x = nullptr;
-  double *d_tpart = nullptr, *d_part = nullptr;
-  double *d_red_r = nullptr, *d_red_r2 = nullptr, *d_red_c = nullptr, *d_red_c2 = nullptr;
+  double *d_h = nullptr, *d_u = nullptr, *d_v = nullptr, *d_w = nullptr, *d_x = nullptr,
+         *d_c = nullptr;
+  double* d_tpart = nullptr;
+  double *d_red_r = nullptr, *d_red_b = nullptr, *d_red_c = nullptr;
   SolveState* d_state = nullptr;
+  BtOuter* d_outer = nullptr;
   int32_t *d_flag = nullptr, *d_count = nullptr;
-  bool assembled = false;
+  double* d_rc = nullptr;      // block-Jacobi inverse factors R_b^{-1} (column-packed)
+  double* d_Ahat = nullptr;    // preconditioned matrix M_b R_b^{-1} (FP64)
+  Tile* d_ftiles = nullptr;    // 64-point runs of the blocks (forming M R^{-1})
+  bool assembled = false, bj_ready = false;
+  bool lo_hat = false;         // the low-precision copy holds M R^{-1} (else M)
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::map<int, hipGraphExec_t> graphs;
+  std::map<int64_t, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -77,6 +87,17 @@ hipError_t balloc(elmfb_batch b, T** p, int64_t bytes) {
   return hipSuccess;
 }
 
+void bfree(elmfb_batch b, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < b->allocs.size(); ++i) {
+    if (b->allocs[i] == p) {
+      hipFree(p);
+      b->allocs.erase(b->allocs.begin() + (long)i);
+      return;
+    }
+  }
+}
+
 void brelease(elmfb_batch b) {
   for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
   b->graphs.clear();
@@ -90,7 +111,7 @@ void brelease(elmfb_batch b) {
 }
 
 std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
-  int64_t row_off = 0, col_off = 0, a_off = 0, p_off = 0;
+  int64_t row_off = 0, col_off = 0, a_off = 0, p_off = 0, f_off = 0, g_off = 0;
   int32_t blk_off = 0, tab_off = 0, cov_off = 0;
   for (int i = 0; i < B->n; ++i) {
     elmfb_problem_s hp;
@@ -114,9 +135,12 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
     I.ct0 = (int32_t)B->ctiles.size();
     for (int64_t q0 = 0; q0 < g.n_phi; q0 += 256) B->ctiles.push_back(ColTile{i, (int32_t)(col_off + q0)});
     I.ct1 = (int32_t)B->ctiles.size();
+    I.b0 = blk_off;
+    I.b1 = blk_off + (int32_t)hp.blocks.size();
     B->insts.push_back(I);
     B->nrows.push_back(g.n_rows);
     B->nphis.push_back(g.n_phi);
+    const int64_t K = g.K;
     for (size_t b = 0; b < hp.blocks.size(); ++b) {
       DevBlock D = hp.blocks[b];
       D.a_off += a_off;
@@ -125,10 +149,12 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
       D.tabx += tab_off;
       D.taby += tab_off;
       D.inst = i;
-      const int gb = blk_off + (int)b;
-      B->cstart.push_back((int32_t)B->chunks.size());
-      for (int64_t p0 = 0; p0 < D.n; p0 += kBChunkPts) B->chunks.push_back(Tile{gb, (int32_t)p0});
       B->blocks.push_back(D);
+      for (int p0 = 0; p0 < D.n; p0 += 64) B->ftiles.push_back(Tile{blk_off + (int32_t)b, p0});
+      B->foff.push_back(f_off);
+      B->goff.push_back(g_off);
+      f_off += K * (K + 1) / 2;
+      g_off += K * K;
     }
     for (const Tile& t : hp.tiles) B->tiles.push_back(Tile{t.blk + blk_off, t.p0});
     for (const AxisSeg& s : hp.segs) {
@@ -146,38 +172,128 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
     cov_off += (int32_t)hp.cov.size();
     if (row_off > ((int64_t)1 << 31) || col_off > ((int64_t)1 << 31)) return "batch too large";
   }
-  B->cstart.push_back((int32_t)B->chunks.size());
   B->n_rows = row_off;
   B->n_phi = col_off;
   B->nnz = a_off;
   B->n_bp = p_off;
   B->n_tab = tab_off;
+  B->n_fac = f_off;
+  B->n_gsq = g_off;
   return "";
 }
 
-hipError_t bt_iteration(elmfb_batch B, hipStream_t s) {
+int prec_index(int prec) { return prec == ELMFB_FP32 ? 1 : (prec == ELMFB_BF16 ? 2 : 0); }
+
+// The matrix the Krylov steps run on: M, or with block-Jacobi the folded M R^{-1}; FP64 or the
+// low-precision copy.
+const void* matrix_of(elmfb_batch B, int prec, bool bj) {
+  if (prec == ELMFB_FP64) return bj ? (const void*)B->d_Ahat : (const void*)B->d_A;
+  return (const void*)B->d_A_lo;
+}
+
+// One LSQR step for every (instance, rhs) on the matrix of precision `prec` (M, or M R^{-1} with
+// block-Jacobi): u = A v sv - alpha su u, beta; v = A^T u su - beta sv v, alpha; rotation;
+// x, w update; stop tests.
+hipError_t bt_iteration(elmfb_batch B, int prec, bool bj, hipStream_t s) {
   const int n = B->n, R = B->R;
+  const int64_t nb = (int64_t)B->blocks.size();
+  const void* A = matrix_of(B, prec, bj);
   hipError_t e;
-  if ((e = launch_bt_mv(ELMFB_FP64, B->d_geos, B->d_blocks, B->d_tiles, (int64_t)B->tiles.size(),
-                        B->d_A, B->d_v, R, B->d_state, B->d_tpart, s)))
+  if ((e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, B->d_state, B->d_tpart,
+                         s)))
     return e;
   if ((e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                             (int64_t)B->rtiles.size(), B->d_tpart, ROW_LSQR_U, R, B->d_u, nullptr,
                             B->d_state, B->d_red_r, s)))
     return e;
   if ((e = launch_bt_lsqr_beta(B->d_state, B->d_insts, n, R, B->d_red_r, s))) return e;
-  if ((e = launch_bt_rmv(ELMFB_FP64, B->d_geos, B->d_insts, B->d_blocks, B->d_chunks,
-                         (int64_t)B->chunks.size(), B->d_A, B->d_u, R, B->d_state, B->d_part, s)))
-    return e;
-  if ((e = launch_bt_finish(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(),
-                            B->d_cstart, B->d_part, COL_LSQR_V, R, B->d_v, B->d_state, B->d_red_c,
-                            s)))
+  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
+                          B->d_u, R, B->d_state, COL_LSQR_V, B->d_v, B->d_red_c, s)))
     return e;
   if ((e = launch_bt_lsqr_alpha(B->d_state, B->d_insts, n, R, B->d_red_c, s))) return e;
   if ((e = launch_bt_update(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
-                            B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_c2, s)))
+                            B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_b, s)))
     return e;
-  return launch_bt_lsqr_stop(B->d_state, B->d_insts, n, R, B->d_red_c2, s);
+  return launch_bt_lsqr_stop(B->d_state, B->d_insts, n, R, B->d_red_b, s);
+}
+
+// LSQR start from the rows already in d_u (u = rhs) with their squared-norm partials in
+// d_red_r: beta, v = A^T u / beta, alpha, w = v / alpha, x = 0.
+hipError_t bt_lsqr_start(elmfb_batch B, int prec, bool bj, double atol, double btol, int iter_lim,
+                         const BtOuter* ot, double inner_rel, hipStream_t s) {
+  const int n = B->n, R = B->R;
+  hipError_t e;
+  if ((e = launch_bt_lsqr_init(B->d_state, B->d_insts, n, R, B->d_red_r, B->d_red_r, atol, btol,
+                               iter_lim, ot, inner_rel, s)))
+    return e;
+  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks,
+                          (int64_t)B->blocks.size(), matrix_of(B, prec, bj), B->d_u, R,
+                          B->d_state, COL_STORE_SQ, B->d_v, B->d_red_c, s)))
+    return e;
+  if ((e = launch_bt_lsqr_init_alpha(B->d_state, B->d_insts, n, R, B->d_red_c, s))) return e;
+  if ((e = hipMemsetAsync(B->d_x, 0, (size_t)(B->n_phi * R * 8), s))) return e;
+  if ((e = hipMemsetAsync(B->d_w, 0, (size_t)(B->n_phi * R * 8), s))) return e;
+  // with t1 = t2 = 0 (fresh state) the update leaves x = 0 and sets w = v sv
+  return launch_bt_update(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
+                          B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_b, s);
+}
+
+// u = h - A c with the FP64 matrix A (M, or M R^{-1} with block-Jacobi and c in preconditioned
+// coordinates), squared-norm partials in d_red_r; c = NULL means c = 0.
+hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s) {
+  const int R = B->R;
+  hipError_t e;
+  if (c) {
+    if ((e = launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(),
+                           matrix_of(B, ELMFB_FP64, bj), c, R, nullptr, B->d_tpart, s)))
+      return e;
+  } else if ((e = hipMemsetAsync(B->d_tpart, 0, (size_t)(B->n_bp * R * 8), s))) {
+    return e;
+  }
+  return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+                          (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u, B->d_h,
+                          nullptr, B->d_red_r, s);
+}
+
+// Run LSQR steps until every pair has stopped: replays of a captured graph of `chunk` steps (or
+// eager launches), the host reading the number of running pairs after each.
+elmfb_status bt_run(elmfb_batch B, int prec, bool bj, int chunk, bool use_graph, hipStream_t s) {
+  const int nR = B->n * B->R;
+  int32_t active = 1;
+  BHIP(B, launch_bt_count_active(B->d_state, nR, B->d_count, s));
+  BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
+  BHIP(B, hipStreamSynchronize(s));
+  const int64_t key = ((int64_t)chunk << 16) | (prec << 8) | (bj ? 128 : 0) | B->tp[prec_index(prec)];
+  while (active > 0) {
+    if (use_graph) {
+      auto it = B->graphs.find(key);
+      hipGraphExec_t exec = nullptr;
+      if (it != B->graphs.end()) {
+        exec = it->second;
+      } else {
+        hipGraph_t graph = nullptr;
+        BHIP(B, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e2 = hipSuccess;
+        for (int i = 0; i < chunk && e2 == hipSuccess; ++i) e2 = bt_iteration(B, prec, bj, s);
+        hipError_t e3 = hipStreamEndCapture(s, &graph);
+        if (e2 != hipSuccess || e3 != hipSuccess) {
+          if (graph) hipGraphDestroy(graph);
+          BHIP(B, e2 != hipSuccess ? e2 : e3);
+        }
+        hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        BHIP(B, e4);
+        B->graphs[key] = exec;
+      }
+      BHIP(B, hipGraphLaunch(exec, s));
+    } else {
+      for (int i = 0; i < chunk; ++i) BHIP(B, bt_iteration(B, prec, bj, s));
+    }
+    BHIP(B, launch_bt_count_active(B->d_state, nR, B->d_count, s));
+    BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
+    BHIP(B, hipStreamSynchronize(s));
+  }
+  return ELMFB_OK;
 }
 
 }  // namespace
@@ -209,12 +325,13 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   }
   const int R = n_rhs;
   const int64_t es_lo = B->lo_prec == ELMFB_FP32 ? 4 : (B->lo_prec == ELMFB_BF16 ? 2 : 0);
-  int64_t bytes = B->nnz * (8 + es_lo) + B->n_bp * R * 8 +
-                  (int64_t)B->chunks.size() * kBatchMaxK * R * 8 + B->n_rows * R * 8 * 2 +
-                  B->n_phi * R * 8 * 3 + B->n_phi * 24 + B->n_tab * 24 +
-                  (int64_t)(B->rtiles.size() + B->ctiles.size()) * 2 * kMaxRhs * 8 +
-                  (int64_t)B->blocks.size() * sizeof(DevBlock) +
-                  (int64_t)(B->tiles.size() + B->chunks.size()) * sizeof(Tile);
+  const int64_t nblk = (int64_t)B->blocks.size();
+  int64_t bytes = B->nnz * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
+                  B->n_phi * R * 8 * 4 + B->n_phi * 24 + B->n_tab * 24 +
+                  (int64_t)(B->rtiles.size() * 2 + B->ctiles.size() + nblk) * kMaxRhs * 8 +
+                  nblk * ((int64_t)sizeof(DevBlock) + 16) +
+                  (int64_t)(B->tiles.size() + B->ftiles.size()) * sizeof(Tile) +
+                  (int64_t)n * R * ((int64_t)sizeof(SolveState) + (int64_t)sizeof(BtOuter));
   B->bytes = bytes;
   if (const char* cap = std::getenv("ELMFB_MEM_CAP")) {
     const long long c = std::atoll(cap);
@@ -246,10 +363,10 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_insts, n * (int64_t)sizeof(InstInfo));
   BALLOC(B->d_nrows, n * 8);
   BALLOC(B->d_nphis, n * 8);
-  BALLOC(B->d_blocks, (int64_t)B->blocks.size() * sizeof(DevBlock));
+  BALLOC(B->d_blocks, nblk * (int64_t)sizeof(DevBlock));
+  BALLOC(B->d_foff, nblk * 8);
+  BALLOC(B->d_goff, nblk * 8);
   BALLOC(B->d_tiles, (int64_t)B->tiles.size() * sizeof(Tile));
-  BALLOC(B->d_chunks, (int64_t)B->chunks.size() * sizeof(Tile));
-  BALLOC(B->d_cstart, (int64_t)B->cstart.size() * 4);
   BALLOC(B->d_cov, (int64_t)B->cov.size() * 4);
   BALLOC(B->d_segs, (int64_t)B->segs.size() * sizeof(BSeg));
   BALLOC(B->d_rtiles, (int64_t)B->rtiles.size() * sizeof(RowTile));
@@ -264,13 +381,14 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_v, B->n_phi * R * 8);
   BALLOC(B->d_w, B->n_phi * R * 8);
   BALLOC(B->d_x, B->n_phi * R * 8);
+  BALLOC(B->d_c, B->n_phi * R * 8);
+  BALLOC(B->d_ftiles, (int64_t)B->ftiles.size() * sizeof(Tile));
   BALLOC(B->d_tpart, B->n_bp * R * 8);
-  BALLOC(B->d_part, (int64_t)B->chunks.size() * kBatchMaxK * R * 8);
   BALLOC(B->d_red_r, (int64_t)B->rtiles.size() * kMaxRhs * 8);
-  BALLOC(B->d_red_r2, (int64_t)B->rtiles.size() * kMaxRhs * 8);
-  BALLOC(B->d_red_c, (int64_t)B->ctiles.size() * kMaxRhs * 8);
-  BALLOC(B->d_red_c2, (int64_t)B->ctiles.size() * kMaxRhs * 8);
+  BALLOC(B->d_red_b, (int64_t)B->ctiles.size() * kMaxRhs * 8);
+  BALLOC(B->d_red_c, nblk * kMaxRhs * 8);
   BALLOC(B->d_state, (int64_t)n * R * sizeof(SolveState));
+  BALLOC(B->d_outer, (int64_t)n * R * sizeof(BtOuter));
   BALLOC(B->d_flag, 64);
   BALLOC(B->d_count, 64);
 #undef BALLOC
@@ -293,9 +411,10 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   up(B->d_nrows, B->nrows.data(), B->nrows.size() * 8);
   up(B->d_nphis, B->nphis.data(), B->nphis.size() * 8);
   up(B->d_blocks, B->blocks.data(), B->blocks.size() * sizeof(DevBlock));
+  up(B->d_foff, B->foff.data(), B->foff.size() * 8);
+  up(B->d_goff, B->goff.data(), B->goff.size() * 8);
   up(B->d_tiles, B->tiles.data(), B->tiles.size() * sizeof(Tile));
-  up(B->d_chunks, B->chunks.data(), B->chunks.size() * sizeof(Tile));
-  up(B->d_cstart, B->cstart.data(), B->cstart.size() * 4);
+  up(B->d_ftiles, B->ftiles.data(), B->ftiles.size() * sizeof(Tile));
   up(B->d_cov, B->cov.data(), B->cov.size() * 4);
   up(B->d_segs, B->segs.data(), B->segs.size() * sizeof(BSeg));
   up(B->d_rtiles, B->rtiles.data(), B->rtiles.size() * sizeof(RowTile));
@@ -346,6 +465,8 @@ elmfb_status elmfb_batch_assemble(elmfb_batch B, const double* f_dev, void* stre
   BHIP(B, hipMemsetAsync(B->d_flag, 0, 4, s));
   BHIP(B, launch_bt_rhs(B->d_geos, B->d_insts, B->d_rtiles, (int64_t)B->rtiles.size(), B->R,
                         f_dev, B->d_h, B->d_flag, s));
+  B->bj_ready = false;
+  B->lo_hat = false;
   BHIP(B, launch_bt_assemble(B->lo_prec, B->d_geos, B->d_blocks, B->d_tiles,
                              (int64_t)B->tiles.size(), B->d_tab, B->d_W, B->d_b, B->d_A,
                              B->d_A_lo, s));
@@ -366,8 +487,8 @@ elmfb_status elmfb_batch_matvec(elmfb_batch B, const double* v_dev, double* y_de
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, v_dev, B->d_w, 1, 1, s));
-  BHIP(B, launch_bt_mv(ELMFB_FP64, B->d_geos, B->d_blocks, B->d_tiles, (int64_t)B->tiles.size(),
-                       B->d_A, B->d_w, R, nullptr, B->d_tpart, s));
+  BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(), B->d_A,
+                        B->d_w, R, nullptr, B->d_tpart, s));
   BHIP(B, launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                            (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE, R, B->d_u, nullptr,
                            nullptr, B->d_red_r, s));
@@ -381,11 +502,118 @@ elmfb_status elmfb_batch_rmatvec(elmfb_batch B, const double* u_dev, double* x_d
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nrows, B->n, R, B->n_rows, u_dev, B->d_u, 1, 0, s));
-  BHIP(B, launch_bt_rmv(ELMFB_FP64, B->d_geos, B->d_insts, B->d_blocks, B->d_chunks,
-                        (int64_t)B->chunks.size(), B->d_A, B->d_u, R, nullptr, B->d_part, s));
-  BHIP(B, launch_bt_finish(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(),
-                           B->d_cstart, B->d_part, COL_STORE, R, B->d_w, nullptr, B->d_red_c, s));
+  BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], B->d_geos, B->d_insts, B->d_blocks,
+                         (int64_t)B->blocks.size(), B->d_A, B->d_u, R, nullptr, COL_STORE, B->d_w,
+                         B->d_red_c, s));
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, B->d_w, x_dev, 0, 1, s));
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fallback_host,
+                                      void* stream) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (!B->assembled) return bfail(B, ELMFB_E_STATE, "precondition before assemble");
+  if (!(shift > 0.0) || !(shift < 1.0)) return bfail(B, ELMFB_E_INVALID, "shift must be in (0, 1)");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nb = (int64_t)B->blocks.size();
+  if (!B->d_rc) {
+    hipError_t e1 = balloc(B, &B->d_rc, B->n_fac * 8);
+    hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_Ahat, B->nnz * 8) : e1;
+    if (e2 != hipSuccess) {
+      bfree(B, B->d_rc);
+      B->d_rc = nullptr;
+      return bfail(B, ELMFB_E_NOMEM, std::string("factor storage: ") + hipGetErrorString(e2));
+    }
+    B->bytes += B->n_fac * 8 + B->nnz * 8;
+  }
+  double *G = nullptr, *work = nullptr;
+  hipError_t e1 = balloc(B, &G, B->n_gsq * 8);
+  hipError_t e2 = e1 == hipSuccess ? balloc(B, &work, B->n_gsq * 8) : e1;
+  if (e2 != hipSuccess) {
+    bfree(B, G);
+    return bfail(B, ELMFB_E_NOMEM, std::string("Gram scratch: ") + hipGetErrorString(e2));
+  }
+  B->bj_ready = false;
+  hipError_t e = hipMemsetAsync(B->d_flag, 0, 4, s);
+  if (e == hipSuccess)
+    e = launch_bt_gram_diag(B->d_geos, B->d_blocks, nb, B->d_A, B->d_goff, G, s);
+  if (e == hipSuccess)
+    e = launch_bt_bj_factor(B->d_geos, B->d_blocks, nb, G, B->d_goff, work, B->d_foff, shift,
+                            B->d_rc, B->d_flag, s);
+  // M R^{-1} in FP64, and its rounded copy in place of the low-precision M
+  if (e == hipSuccess)
+    e = launch_bt_fold(B->lo_prec, B->d_geos, B->d_blocks, B->d_ftiles,
+                       (int64_t)B->ftiles.size(), B->d_A, B->d_rc, B->d_foff, B->d_Ahat,
+                       B->d_A_lo, s);
+  int32_t nfail = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nfail, B->d_flag, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  bfree(B, work);
+  bfree(B, G);
+  BHIP(B, e);
+  if (n_fallback_host) *n_fallback_host = nfail;
+  B->bj_ready = true;
+  B->lo_hat = B->lo_prec != ELMFB_FP64;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_autotune(elmfb_batch B, int32_t prec, int32_t reps, double* ms_host,
+                                  int32_t* chosen_host, void* stream) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (!B->assembled) return bfail(B, ELMFB_E_STATE, "autotune before assemble");
+  if (prec != ELMFB_FP64 && prec != B->lo_prec)
+    return bfail(B, ELMFB_E_INVALID, "no stored matrix copy of that precision");
+  if (reps < 1 || reps > 1000) return bfail(B, ELMFB_E_INVALID, "reps must be in 1..1000");
+  hipStream_t s = (hipStream_t)stream;
+  const int R = B->R;
+  const int64_t nb = (int64_t)B->blocks.size();
+  const void* A = matrix_of(B, prec, false);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  BHIP(B, hipEventCreate(&t0));
+  BHIP(B, hipEventCreate(&t1));
+  // u = 1 on every row and right-hand side (timing input only)
+  std::vector<double> ones((size_t)B->n_rows * R, 1.0);
+  hipError_t e = hipMemcpyAsync(B->d_u, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s);
+  double best = 1e300;
+  int best_tp = 32;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    const int tp = kBtTileChoices[c];
+    double ms = -1.0;
+    if (!(prec == ELMFB_FP64 && tp == 64)) {
+      e = launch_bt_rmvb(prec, tp, B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u, R, nullptr,
+                         COL_STORE, B->d_w, B->d_red_c, s);
+      if (e == hipSuccess) e = hipEventRecord(t0, s);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_bt_rmvb(prec, tp, B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u, R,
+                           nullptr, COL_STORE, B->d_w, B->d_red_c, s);
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float f = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
+      ms = (double)f / reps;
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_tp = tp;
+      }
+    }
+    if (ms_host) ms_host[c] = ms;
+  }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  BHIP(B, e);
+  B->tp[prec_index(prec)] = best_tp;
+  B->tuned[prec_index(prec)] = true;
+  if (chosen_host) *chosen_host = best_tp;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_set_tile(elmfb_batch B, int32_t prec, int32_t tile) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (prec != ELMFB_FP64 && prec != ELMFB_FP32 && prec != ELMFB_BF16)
+    return bfail(B, ELMFB_E_INVALID, "bad precision");
+  if (!(tile == 16 || tile == 32 || (tile == 64 && prec != ELMFB_FP64)))
+    return bfail(B, ELMFB_E_INVALID, "tile must be 16, 32 or (not FP64) 64");
+  B->tp[prec_index(prec)] = tile;
   return ELMFB_OK;
 }
 
@@ -394,86 +622,90 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   const auto t0 = std::chrono::steady_clock::now();
   if (!B || !opts || !coef_dev) return bfail(B, ELMFB_E_INVALID, "NULL argument");
   if (!B->assembled) return bfail(B, ELMFB_E_STATE, "solve before assemble");
-  if (opts->method != ELMFB_LSQR || opts->precond)
-    return bfail(B, ELMFB_E_UNSUPPORTED, "batches solve with unpreconditioned LSQR");
+  const bool mixed = opts->method == ELMFB_MIXED_IR;
+  if (opts->method != ELMFB_LSQR && !mixed)
+    return bfail(B, ELMFB_E_UNSUPPORTED, "batches solve with LSQR or MIXED_IR");
   if (opts->x0_dev || opts->n_check)
     return bfail(B, ELMFB_E_UNSUPPORTED, "batched solves take no warm start or check points");
+  if (opts->precond && !B->bj_ready)
+    return bfail(B, ELMFB_E_STATE, "precond requested before elmfb_batch_precondition");
+  if (mixed && B->lo_prec == ELMFB_FP64)
+    return bfail(B, ELMFB_E_INVALID, "MIXED_IR needs a store_prec copy (FP32 or BF16)");
+  if (mixed && !opts->precond && B->lo_hat)
+    return bfail(B, ELMFB_E_STATE,
+                 "the low-precision copy holds the preconditioned matrix: assemble again for "
+                 "unpreconditioned refinement");
   if (opts->iter_lim < 0 || opts->check_every < 1 || opts->check_every > 100000 ||
-      !(opts->atol >= 0.0) || !(opts->btol >= 0.0))
+      !(opts->atol >= 0.0) || !(opts->btol >= 0.0) ||
+      (mixed && (opts->inner_iters < 1 || opts->outer_lim < 0)))
     return bfail(B, ELMFB_E_INVALID, "bad solve options");
   const int n = B->n, R = B->R;
+  const int64_t nb = (int64_t)B->blocks.size();
+  const bool bj = opts->precond != 0;
   hipStream_t caller = (hipStream_t)stream;
   hipStream_t s = B->stream;
   BHIP(B, hipEventRecord(B->ev_in, caller));
   BHIP(B, hipStreamWaitEvent(s, B->ev_in, 0));
-  // u = h, beta; v = A^T u / beta, alpha; w = v / alpha, x = 0
-  // row partials of ||h||^2 (= ||u||^2 at the start): computed by a ROW_RESID pass with t = 0
-  BHIP(B, hipMemsetAsync(B->d_tpart, 0, (size_t)(B->n_bp * R * 8), s));
-  BHIP(B, launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
-                           (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u, B->d_h,
-                           nullptr, B->d_red_r, s));
-  BHIP(B, launch_bt_lsqr_init(B->d_state, B->d_insts, n, R, B->d_red_r, B->d_red_r, opts->atol,
-                              opts->btol, opts->iter_lim, s));
-  BHIP(B, launch_bt_rmv(ELMFB_FP64, B->d_geos, B->d_insts, B->d_blocks, B->d_chunks,
-                        (int64_t)B->chunks.size(), B->d_A, B->d_u, R, B->d_state, B->d_part, s));
-  BHIP(B, launch_bt_finish(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(),
-                           B->d_cstart, B->d_part, COL_STORE_SQ, R, B->d_v, nullptr, B->d_red_c,
-                           s));
-  BHIP(B, launch_bt_lsqr_init_alpha(B->d_state, B->d_insts, n, R, B->d_red_c, s));
-  // w = v / alpha (one update step with t1 = 0, t2 = 0 gives w = v sv)
-  BHIP(B, hipMemsetAsync(B->d_x, 0, (size_t)(B->n_phi * R * 8), s));
-  BHIP(B, hipMemsetAsync(B->d_w, 0, (size_t)(B->n_phi * R * 8), s));
-  BHIP(B, launch_bt_update(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
-                           B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_c2, s));
-  int32_t active = 1;
-  BHIP(B, launch_bt_count_active(B->d_state, n * R, B->d_count, s));
-  BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
-  BHIP(B, hipStreamSynchronize(s));
-  const int chunk = opts->check_every;
-  while (active > 0) {
-    if (opts->use_graph) {
-      auto it = B->graphs.find(chunk);
-      hipGraphExec_t exec = nullptr;
-      if (it != B->graphs.end()) {
-        exec = it->second;
-      } else {
-        hipGraph_t graph = nullptr;
-        BHIP(B, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e2 = hipSuccess;
-        for (int i = 0; i < chunk && e2 == hipSuccess; ++i) e2 = bt_iteration(B, s);
-        hipError_t e3 = hipStreamEndCapture(s, &graph);
-        if (e2 != hipSuccess || e3 != hipSuccess) {
-          if (graph) hipGraphDestroy(graph);
-          BHIP(B, e2 != hipSuccess ? e2 : e3);
-        }
-        hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        BHIP(B, e4);
-        B->graphs[chunk] = exec;
-      }
-      BHIP(B, hipGraphLaunch(exec, s));
-    } else {
-      for (int i = 0; i < chunk; ++i) BHIP(B, bt_iteration(B, s));
+  if (!mixed) {
+    BHIP(B, bt_residual(B, nullptr, false, s));   // u = h
+    BHIP(B, bt_lsqr_start(B, ELMFB_FP64, bj, opts->atol, opts->btol, opts->iter_lim, nullptr, 0.0,
+                          s));
+    const elmfb_status st = bt_run(B, ELMFB_FP64, bj, opts->check_every, opts->use_graph != 0, s);
+    if (st != ELMFB_OK) return st;
+    if (bj)
+      BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_x,
+                                   nullptr, B->d_c, s));
+    else
+      BHIP(B, hipMemcpyAsync(B->d_c, B->d_x, (size_t)(B->n_phi * R * 8), hipMemcpyDeviceToDevice, s));
+  } else {
+    // FP64 refinement: r = h - M c, inner LSQR on the stored low-precision copy, c += d
+    const int lo = B->lo_prec;
+    BHIP(B, hipMemsetAsync(B->d_c, 0, (size_t)(B->n_phi * R * 8), s));
+    BHIP(B, bt_residual(B, nullptr, false, s));
+    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 1,
+                                  opts->btol, opts->outer_lim, s));
+    for (;;) {
+      int32_t active = 0;
+      BHIP(B, launch_bt_count_outer(B->d_outer, n * R, B->d_count, s));
+      BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
+      BHIP(B, hipStreamSynchronize(s));
+      if (active == 0) break;
+      BHIP(B, bt_lsqr_start(B, lo, bj, 0.0, 0.0, opts->inner_iters, B->d_outer, 0.5, s));
+      const elmfb_status st = bt_run(B, lo, bj, opts->check_every, opts->use_graph != 0, s);
+      if (st != ELMFB_OK) return st;
+      // c += d (c in preconditioned coordinates with block-Jacobi)
+      BHIP(B, launch_bt_axpy(B->n_phi * R, B->d_x, B->d_c, s));
+      BHIP(B, bt_residual(B, B->d_c, bj, s));
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 0,
+                                    opts->btol, opts->outer_lim, s));
     }
-    BHIP(B, launch_bt_count_active(B->d_state, n * R, B->d_count, s));
-    BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
-    BHIP(B, hipStreamSynchronize(s));
   }
-  BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, n, R, B->n_phi, B->d_x, coef_dev, 0, 1, s));
+  const double* fin = B->d_c;
+  if (mixed && bj) {   // coefficients x = R^{-1} c
+    BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_c,
+                                 nullptr, B->d_x, s));
+    fin = B->d_x;
+  }
+  BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, n, R, B->n_phi, fin, coef_dev, 0, 1, s));
   BHIP(B, hipEventRecord(B->ev_out, s));
   BHIP(B, hipStreamWaitEvent(caller, B->ev_out, 0));
   if (info) {
     std::vector<SolveState> st((size_t)n * R);
+    std::vector<BtOuter> ot(mixed ? (size_t)n * R : 0);
     BHIP(B, hipMemcpyAsync(st.data(), B->d_state, st.size() * sizeof(SolveState),
                            hipMemcpyDeviceToHost, s));
+    if (mixed)
+      BHIP(B, hipMemcpyAsync(ot.data(), B->d_outer, ot.size() * sizeof(BtOuter),
+                             hipMemcpyDeviceToHost, s));
     BHIP(B, hipStreamSynchronize(s));
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     for (size_t k = 0; k < st.size(); ++k) {
       info[k] = elmfb_solve_info{};
-      info[k].istop = st[k].istop;
-      info[k].iters = st[k].itn;
-      info[k].rnorm = st[k].rnorm;
+      info[k].istop = mixed ? ot[k].istop : st[k].istop;
+      info[k].iters = mixed ? ot[k].iters : st[k].itn;
+      info[k].outer_iters = mixed ? ot[k].outer : 0;
+      info[k].rnorm = mixed ? ot[k].rnorm : st[k].rnorm;
       info[k].arnorm = st[k].arnorm;
       info[k].anorm = st[k].anorm;
       info[k].xnorm = st[k].xnorm;

@@ -46,7 +46,8 @@ struct GramChunk {
 // ---- batches of independent instances with several right-hand sides
 constexpr int kMaxRhs = 8;
 constexpr int kBatchMaxK = 128;      // features per subdomain in a batch
-constexpr int kBChunkPts = 1024;     // points per batched A^T U chunk (4 per thread)
+// Points per LDS stage of the batched A^T U pass; the autotuner picks one of these.
+constexpr int kBtTileChoices[3] = {16, 32, 64};
 
 struct RowTile {    // <= 256 consecutive rows of one instance
   int32_t inst;
@@ -62,6 +63,7 @@ struct InstInfo {
   int64_t row_off, col_off;   // global offsets of the instance's rows and columns
   int32_t rt0, rt1;           // its row tiles
   int32_t ct0, ct1;           // its column tiles
+  int32_t b0, b1;             // its blocks
 };
 
 struct Tile {       // a run of <= kTile consecutive points of one block
@@ -108,6 +110,14 @@ struct SolveState {
   int32_t itn, istop, done, iter_lim;
   int32_t target_hit;      // the rel-L2 check met the target
   int32_t pad_;
+};
+
+// FP64 outer state of an iteratively refined batched solve, one per (instance, rhs).
+struct BtOuter {
+  double hnorm;      // ||h||
+  double rnorm;      // ||h - M c|| at the last check
+  double btol;       // stop when rnorm <= btol hnorm
+  int32_t done, outer, iters, istop;
 };
 
 // Convert an FP64 value to bfloat16 bits with round-to-nearest-even (IEEE definition: keep

@@ -146,6 +146,11 @@ __global__ void __launch_bounds__(256) k_bt_rhs(const Geo* __restrict__ geos,
 }
 
 // ---------------------------------------------------------------- products
+//
+// Both matrix passes run one workgroup per subdomain block, so each workgroup's results belong
+// to one block of one instance.  Block-Jacobi preconditioning needs no extra work here: its
+// factors are folded into a preconditioned copy of the matrix once (k_bt_precond.hip), and the
+// same kernels run on that copy.
 
 // per (instance, rhs) scale of the vector being read: 1/alpha (v) or 1/beta (u); 0 once done
 __device__ __forceinline__ double pair_scale(const SolveState* st, int idx, bool use_v) {
@@ -155,33 +160,135 @@ __device__ __forceinline__ double pair_scale(const SolveState* st, int idx, bool
   return use_v ? s.sv : s.su;
 }
 
-template <int PREC>
-__global__ void __launch_bounds__(256) k_bt_mv(const Geo* __restrict__ geos,
-                                               const DevBlock* __restrict__ blocks,
-                                               const Tile* __restrict__ tiles,
-                                               const void* __restrict__ A,
-                                               const double* __restrict__ v, int R,
-                                               const SolveState* __restrict__ st,
-                                               double* __restrict__ tpart) {
-  const Tile t = tiles[blockIdx.x];
-  const DevBlock B = blocks[t.blk];
-  const int p = t.p0 + threadIdx.x;
-  if (p >= B.n) return;
-  const int K = geos[B.inst].K;
-  const int n = B.n;
-  const int64_t base = B.a_off + p;
+// Sum 8 per-thread values over the 256 threads: transposing butterfly in each wave, then the
+// four wave sums in fixed order.  Value j is returned in thread j (j < 8); every thread must
+// call it.
+__device__ __forceinline__ double block_sum8(const double a[kMaxRhs], double (*sh)[kMaxRhs]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int f;
+  const double v = butterfly8(a, lane, &f);
+  if ((lane & 7) == 0) sh[wid][f] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x < kMaxRhs) {
+    const int j = threadIdx.x;
+    r = (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t packed_col(int i, int k) { return (int64_t)k * (k + 1) / 2 + i; }
+
+// Load / store the R values of one row or column (R == 8: four 16-byte accesses; the vectors
+// are 64-byte aligned then).  Missing entries read as zero.
+__device__ __forceinline__ void load_r(const double* __restrict__ p, int R, double v[kMaxRhs]) {
+  if (R == kMaxRhs) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double2 t = q[m];
+      v[2 * m] = t.x;
+      v[2 * m + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j) v[j] = j < R ? p[j] : 0.0;
+  }
+}
+__device__ __forceinline__ void store_r(double* __restrict__ p, int R, const double v[kMaxRhs]) {
+  if (R == kMaxRhs) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q[m] = double2{v[2 * m], v[2 * m + 1]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j)
+      if (j < R) p[j] = v[j];
+  }
+}
+
+// y = R_b^{-1} c for the block's coefficients c in LDS (cs[k][rhs]); the result replaces cs.
+// The column-packed factor is streamed through LDS (fs, nfs doubles) in runs of whole columns
+// with coalesced loads; thread i < K accumulates output i over the staged columns k >= i.
+__device__ __forceinline__ void bj_apply_lds(const double* __restrict__ rc, int K,
+                                             double (*cs)[kMaxRhs], double* fs, int nfs) {
+  const int i = threadIdx.x;
   double acc[kMaxRhs];
 #pragma unroll
   for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double a = load_entry<PREC>(A, base + (int64_t)k * n);
-    const double* vk = v + (int64_t)(B.q0 + k) * R;
+  int k0 = 0;
+  while (k0 < K) {
+    const int64_t base = packed_col(0, k0);
+    int k1 = k0 + 1;
+    while (k1 < K && packed_col(0, k1 + 1) - base <= nfs) ++k1;
+    const int cnt = (int)(packed_col(0, k1) - base);
+    for (int e = threadIdx.x; e < cnt; e += 256) fs[e] = rc[base + e];
+    __syncthreads();
+    if (i < K) {
+      for (int k = (i > k0 ? i : k0); k < k1; ++k) {
+        const double r = fs[packed_col(i, k) - base];
 #pragma unroll
-    for (int j = 0; j < kMaxRhs; ++j)
-      if (j < R) acc[j] += a * vk[j];
+        for (int j = 0; j < kMaxRhs; ++j) acc[j] += r * cs[k][j];
+      }
+    }
+    __syncthreads();
+    k0 = k1;
   }
-  double* out = tpart + (B.p_off + p) * R;
-  for (int j = 0; j < R; ++j) out[j] = acc[j] * pair_scale(st, B.inst * R + j, true);
+  if (i < K) {
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j) cs[i][j] = acc[j];
+  }
+  __syncthreads();
+}
+
+constexpr int kFacStage = 2048;   // doubles of a packed factor staged per round in A.v
+
+// Partial rows of Y = A V: per block point, the block's contribution for every right-hand side,
+// tpart[(p_off + p) * R + rhs] (V scaled per pair by 1/alpha, or 0 once the pair is done).  The waves take 64-point runs of the block in
+// turn; each lane loads 8 feature entries ahead of their products.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
+                                                const DevBlock* __restrict__ blocks,
+                                                const void* __restrict__ A,
+                                                const double* __restrict__ v, int R,
+                                                const SolveState* __restrict__ st,
+                                                double* __restrict__ tpart) {
+  __shared__ double cs[kBatchMaxK][kMaxRhs];
+  const DevBlock B = blocks[blockIdx.x];
+  const int K = geos[B.inst].K;
+  for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
+    const int k = e >> 3, j = e & 7;
+    cs[k][j] = j < R ? v[(int64_t)(B.q0 + k) * R + j] * pair_scale(st, B.inst * R + j, true) : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int n = B.n;
+  for (int p0 = wid * 64; p0 < n; p0 += 256) {
+    const int p = p0 + lane;
+    if (p < n) {
+      double acc[kMaxRhs];
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
+      const int64_t base = B.a_off + p;
+      int k = 0;
+      for (; k + 8 <= K; k += 8) {
+        double a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = load_entry<PREC>(A, base + (int64_t)(k + q) * n);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int j = 0; j < kMaxRhs; ++j) acc[j] += a[q] * cs[k + q][j];
+      }
+      for (; k < K; ++k) {
+        const double a = load_entry<PREC>(A, base + (int64_t)k * n);
+#pragma unroll
+        for (int j = 0; j < kMaxRhs; ++j) acc[j] += a * cs[k][j];
+      }
+      store_r(tpart + (B.p_off + p) * R, R, acc);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
@@ -194,15 +301,15 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
                                                    const double* __restrict__ bvec,
                                                    const SolveState* __restrict__ st,
                                                    double* __restrict__ red) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][kMaxRhs];
   const RowTile t = rtiles[blockIdx.x];
   const Geo& g = geos[t.inst];
   const InstInfo I = insts[t.inst];
   const int64_t r = t.r0 + threadIdx.x;
   const bool valid = r < I.row_off + g.n_rows;
-  double y[kMaxRhs];
+  double y[kMaxRhs], acc[kMaxRhs];
 #pragma unroll
-  for (int j = 0; j < kMaxRhs; ++j) y[j] = 0.0;
+  for (int j = 0; j < kMaxRhs; ++j) { y[j] = 0.0; acc[j] = 0.0; }
   if (valid) {
     const int64_t rl = r - I.row_off;
     const int ix = (int)(rl / g.ny), iy = (int)(rl - (int64_t)ix * g.ny);
@@ -214,159 +321,222 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
         for (int jy = jy0; jy <= jy1; ++jy) {
           const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
           const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
-          const double* tp = tpart + (B.p_off + p) * R;
+          double tv[kMaxRhs];
+          load_r(tpart + (B.p_off + p) * R, R, tv);
 #pragma unroll
-          for (int j = 0; j < kMaxRhs; ++j)
-            if (j < R) y[j] += tp[j];
+          for (int j = 0; j < kMaxRhs; ++j) y[j] += tv[j];
         }
     }
-  }
-  for (int j = 0; j < R; ++j) {
-    double acc = 0.0;
-    if (valid) {
-      const int64_t o = r * R + j;
-      if (mode == ROW_STORE) {
-        out[o] = y[j];
-      } else if (mode == ROW_LSQR_U) {
-        const SolveState& s = st[t.inst * R + j];
-        const double c = s.done ? 0.0 : s.alpha * s.su;
-        const double u = y[j] - c * out[o];
-        out[o] = s.done ? 0.0 : u;
-        acc = s.done ? 0.0 : u * u;
-      } else if (mode == ROW_RESID) {
-        const double u = bvec[o] - y[j];
-        out[o] = u;
-        acc = u * u;
-      } else {
-        out[o] = y[j];
-        acc = y[j] * y[j];
+    double* o = out + r * R;
+    if (mode == ROW_STORE) {
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j)
+        if (j < R) o[j] = y[j];
+    } else if (mode == ROW_LSQR_U) {
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j) {
+        if (j < R) {
+          const SolveState& s = st[t.inst * R + j];
+          const double u = s.done ? 0.0 : y[j] - s.alpha * s.su * o[j];
+          o[j] = u;
+          acc[j] = u * u;
+        }
       }
-    }
-    if (mode != ROW_STORE) {
-      const double s = block_sum256(acc, sh);
-      if (threadIdx.x == 0) red[(int64_t)blockIdx.x * kMaxRhs + j] = s;
-    }
-  }
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(256) k_bt_rmv(const Geo* __restrict__ geos,
-                                                const InstInfo* __restrict__ insts,
-                                                const DevBlock* __restrict__ blocks,
-                                                const Tile* __restrict__ chunks,
-                                                const void* __restrict__ A,
-                                                const double* __restrict__ u, int R,
-                                                const SolveState* __restrict__ st,
-                                                double* __restrict__ part) {
-  constexpr int PPT = kBChunkPts / 256;
-  __shared__ double sred[4][kBatchMaxK][kMaxRhs];
-  const Tile c = chunks[blockIdx.x];
-  const DevBlock B = blocks[c.blk];
-  const Geo& g = geos[B.inst];
-  const InstInfo I = insts[B.inst];
-  const int K = g.K;
-  double sc[kMaxRhs];
+    } else if (mode == ROW_RESID) {
+      const double* bv = bvec + r * R;
 #pragma unroll
-  for (int j = 0; j < kMaxRhs; ++j) sc[j] = j < R ? pair_scale(st, B.inst * R + j, false) : 0.0;
-  double uv[PPT][kMaxRhs];
-  int64_t idx[PPT];
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int p = c.p0 + i * 256 + threadIdx.x;
-    if (p < B.n) {
-      const int lx = p / B.ny, ly = p - lx * B.ny;
-      const int64_t r = I.row_off + (int64_t)(B.ix0 + lx) * g.ny + (B.iy0 + ly);
-#pragma unroll
-      for (int j = 0; j < kMaxRhs; ++j) uv[i][j] = j < R ? u[r * R + j] * sc[j] : 0.0;
-      idx[i] = B.a_off + p;
+      for (int j = 0; j < kMaxRhs; ++j) {
+        if (j < R) {
+          const double u = bv[j] - y[j];
+          o[j] = u;
+          acc[j] = u * u;
+        }
+      }
     } else {
 #pragma unroll
-      for (int j = 0; j < kMaxRhs; ++j) uv[i][j] = 0.0;
-      idx[i] = B.a_off;   // in bounds; multiplied by zero weights
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int n = B.n;
-  const int K8 = (K + 7) & ~7;
-  for (int k0 = 0; k0 < K8; k0 += 8) {
-    double a[8][PPT];
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const int k = k0 + jj < K ? k0 + jj : K - 1;
-#pragma unroll
-      for (int i = 0; i < PPT; ++i) a[jj][i] = load_entry<PREC>(A, idx[i] + (int64_t)k * n);
-    }
-    for (int j = 0; j < R; ++j) {
-      double acc[8];
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) s += a[jj][i] * uv[i][j];
-        acc[jj] = s;
+      for (int j = 0; j < kMaxRhs; ++j) {
+        if (j < R) {
+          o[j] = y[j];
+          acc[j] = y[j] * y[j];
+        }
       }
-      int f;
-      const double v = butterfly8(acc, lane, &f);
-      if ((lane & 7) == 0) sred[wid][k0 + f][j] = v;
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < K * R; e += 256) {
-    const int k = e / R, j = e - (e / R) * R;
-    part[((int64_t)blockIdx.x * kBatchMaxK + k) * R + j] =
-        (sred[0][k][j] + sred[1][k][j]) + (sred[2][k][j] + sred[3][k][j]);
+  if (mode != ROW_STORE) {
+    const double sum = block_sum8(acc, sh);
+    if (threadIdx.x < kMaxRhs) red[(int64_t)blockIdx.x * kMaxRhs + threadIdx.x] = sum;
   }
 }
 
-__global__ void __launch_bounds__(256) k_bt_finish(const Geo* __restrict__ geos,
-                                                   const InstInfo* __restrict__ insts,
-                                                   const ColTile* __restrict__ ctiles,
-                                                   const int32_t* __restrict__ cstart,
-                                                   const double* __restrict__ part, int mode,
-                                                   int R, double* __restrict__ out,
-                                                   const SolveState* __restrict__ st,
-                                                   double* __restrict__ red) {
-  __shared__ double sh[4];
-  const ColTile t = ctiles[blockIdx.x];
-  const Geo& g = geos[t.inst];
-  const InstInfo I = insts[t.inst];
-  const int64_t q = t.q0 + threadIdx.x;
-  const bool valid = q < I.col_off + g.n_phi;
-  const int K = g.K;
-  int b = 0, k = 0;
-  if (valid) {
-    const int64_t ql = q - I.col_off;
-    b = g.bbase[0] + (int)(ql / K);
-    k = (int)(ql - (ql / K) * K);
-  }
-  for (int j = 0; j < R; ++j) {
-    double acc = 0.0;
-    if (valid) {
-      double x = 0.0;
-      for (int c = cstart[b]; c < cstart[b + 1]; ++c)
-        x += part[((int64_t)c * kBatchMaxK + k) * R + j];
-      const int64_t o = q * R + j;
-      if (mode == COL_STORE) {
-        out[o] = x;
-      } else if (mode == COL_LSQR_V) {
-        const SolveState& s = st[t.inst * R + j];
-        double v = out[o];
-        if (s.done) {
-          v = 0.0;
-        } else if (s.beta > 0.0) {
-          v = x - s.beta * s.sv * v;
+template <int PREC> struct StoreT;
+template <> struct StoreT<ELMFB_FP64> { typedef double t; };
+template <> struct StoreT<ELMFB_FP32> { typedef float t; };
+template <> struct StoreT<ELMFB_BF16> { typedef uint16_t t; };
+
+template <int PREC>
+__device__ __forceinline__ double to_f64(typename StoreT<PREC>::t x) {
+  if constexpr (PREC == ELMFB_BF16) return bf16_to_f64(x);
+  else return (double)x;
+}
+
+// Column epilogue of the A^T U passes for one block: thread with column kk >= 0 holds the
+// block's column kk in x; COL_STORE stores it, COL_LSQR_V applies v = x - beta sv v, COL_STORE_SQ
+// stores and squares; per-block partial squared norms go to red[block][rhs].  Every thread of
+// the workgroup must call it.
+__device__ __forceinline__ void col_epilogue(int q0, int inst, int R, int kk,
+                                             const double x[kMaxRhs], int mode,
+                                             const SolveState* __restrict__ st,
+                                             double* __restrict__ out, double* __restrict__ red,
+                                             double (*sh)[kMaxRhs]) {
+  double sq[kMaxRhs];
+#pragma unroll
+  for (int j = 0; j < kMaxRhs; ++j) sq[j] = 0.0;
+  if (kk >= 0) {
+    double* o = out + (int64_t)(q0 + kk) * R;
+    if (mode == COL_STORE) {
+      store_r(o, R, x);
+    } else if (mode == COL_LSQR_V) {
+      double vv[kMaxRhs];
+      load_r(o, R, vv);
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j) {
+        if (j < R) {
+          const SolveState& ps = st[inst * R + j];
+          if (ps.done) vv[j] = 0.0;
+          else if (ps.beta > 0.0) vv[j] = x[j] - ps.beta * ps.sv * vv[j];
+          sq[j] = vv[j] * vv[j];
         }
-        out[o] = v;
-        acc = v * v;
-      } else {
-        out[o] = x;
-        acc = x * x;
+      }
+      store_r(o, R, vv);
+    } else {
+      store_r(o, R, x);
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j) sq[j] = x[j] * x[j];
+    }
+  }
+  if (mode != COL_STORE) {
+    const double sum = block_sum8(sq, sh);
+    if (threadIdx.x < kMaxRhs) red[(int64_t)blockIdx.x * kMaxRhs + threadIdx.x] = sum;
+  }
+}
+
+// X = A^T U for one block and every right-hand side.  Tiles of TP points
+// are staged in LDS (the block's K feature rows, and U on the tile's rows gathered from the
+// grid), the next tile's loads in flight while the current one is reduced; thread (k, s) owns
+// feature k and half s of the tile's points, so no cross-lane reduction is needed.  The
+// epilogue stores the block's columns (COL_STORE), applies the LSQR step v = x - beta sv v
+// (COL_LSQR_V) or stores and squares (COL_STORE_SQ); per-block partial squared norms go to
+// red[block][rhs].
+template <int PREC, int TP>
+__global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
+                                                 const InstInfo* __restrict__ insts,
+                                                 const DevBlock* __restrict__ blocks,
+                                                 const void* __restrict__ A,
+                                                 const double* __restrict__ u, int R,
+                                                 const SolveState* __restrict__ st, int mode,
+                                                 double* __restrict__ out,
+                                                 double* __restrict__ red) {
+  typedef typename StoreT<PREC>::t in_t;
+  constexpr int NA = kBatchMaxK * TP / 256;          // A entries per thread per tile
+  constexpr int NU = (TP * kMaxRhs + 255) / 256;     // U entries per thread per tile
+  __shared__ __align__(16) in_t At[kBatchMaxK][TP + 1];
+  __shared__ double us[TP][kMaxRhs];
+  __shared__ double xs[kBatchMaxK][kMaxRhs];
+  __shared__ double sh[4][kMaxRhs];
+  const DevBlock B = blocks[blockIdx.x];
+  const Geo& g = geos[B.inst];
+  const int64_t row0 = insts[B.inst].row_off;
+  const int K = g.K, n = B.n, gny = g.ny;
+  const in_t* Ab = static_cast<const in_t*>(A) + B.a_off;
+
+  in_t ra[NA];
+  double ru[NU];
+  auto fetch = [&](int p0) {
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      const int k = e / TP, c = e - (e / TP) * TP;
+      const int p = p0 + c;
+      ra[m] = (k < K && p < n) ? Ab[(int64_t)k * n + p] : in_t(0);
+    }
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      const int c = e >> 3, j = e & 7;
+      const int p = p0 + c;
+      double val = 0.0;
+      if (c < TP && j < R && p < n) {
+        const int lx = p / B.ny, ly = p - (p / B.ny) * B.ny;
+        const int64_t r = row0 + (int64_t)(B.ix0 + lx) * gny + (B.iy0 + ly);
+        val = u[r * R + j] * pair_scale(st, B.inst * R + j, false);
+      }
+      ru[m] = val;
+    }
+  };
+
+  const int k = threadIdx.x & 127, s = threadIdx.x >> 7;
+  double acc[kMaxRhs];
+#pragma unroll
+  for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
+  fetch(0);
+  for (int p0 = 0; p0 < n; p0 += TP) {
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      At[e / TP][e - (e / TP) * TP] = ra[m];
+    }
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      if ((e >> 3) < TP) us[e >> 3][e & 7] = ru[m];
+    }
+    __syncthreads();
+    if (p0 + TP < n) fetch(p0 + TP);
+    if (k < K) {
+#pragma unroll
+      for (int cc = 0; cc < TP / 2; ++cc) {
+        const int c = s * (TP / 2) + cc;
+        const double a = to_f64<PREC>(At[k][c]);
+#pragma unroll
+        for (int j = 0; j < kMaxRhs; ++j) acc[j] += a * us[c][j];
       }
     }
-    if (mode != COL_STORE) {
-      const double s = block_sum256(acc, sh);
-      if (threadIdx.x == 0) red[(int64_t)blockIdx.x * kMaxRhs + j] = s;
-    }
+    __syncthreads();
+  }
+  // combine the two halves: thread (k, 0) ends with column k of the block
+  if (s == 1 && k < K) {
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j) xs[k][j] = acc[j];
+  }
+  __syncthreads();
+  if (s == 0 && k < K) {
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j) acc[j] += xs[k][j];
+  }
+  col_epilogue(B.q0, B.inst, R, s == 0 && k < K ? k : -1, acc, mode, st, out, red, sh);
+}
+
+// x = x0 + R^{-1} y per block and right-hand side (x0 may be NULL; x may alias x0).
+__global__ void __launch_bounds__(256) k_bt_bj_recover(const Geo* __restrict__ geos,
+                                                       const DevBlock* __restrict__ blocks,
+                                                       const double* __restrict__ rc,
+                                                       const int64_t* __restrict__ foff, int R,
+                                                       const double* __restrict__ y,
+                                                       const double* x0, double* x) {
+  __shared__ double cs[kBatchMaxK][kMaxRhs];
+  __shared__ double fs[kFacStage];
+  const DevBlock B = blocks[blockIdx.x];
+  const int K = geos[B.inst].K;
+  for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
+    const int k = e >> 3, j = e & 7;
+    cs[k][j] = j < R ? y[(int64_t)(B.q0 + k) * R + j] : 0.0;
+  }
+  __syncthreads();
+  bj_apply_lds(rc + foff[blockIdx.x], K, cs, fs, kFacStage);
+  for (int e = threadIdx.x; e < K * R; e += 256) {
+    const int k = e / R, j = e - (e / R) * R;
+    const int64_t o = (int64_t)(B.q0 + k) * R + j;
+    x[o] = (x0 ? x0[o] : 0.0) + cs[k][j];
   }
 }
 
@@ -383,7 +553,7 @@ __device__ __forceinline__ double seg_sum(const double* red, int t0, int t1, int
 __global__ void k_bt_lsqr_init(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
                                int R, const double* __restrict__ red_b,
                                const double* __restrict__ red_u, double atol, double btol,
-                               int iter_lim) {
+                               int iter_lim, const BtOuter* __restrict__ ot, double inner_rel) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_inst * R) return;
   const int i = idx / R, j = idx - (idx / R) * R;
@@ -397,7 +567,50 @@ __global__ void k_bt_lsqr_init(SolveState* st, const InstInfo* __restrict__ inst
   s.btol = btol;
   s.iter_lim = iter_lim;
   s.rel_l2 = -1.0;
+  if (ot) {
+    const BtOuter o = ot[idx];
+    if (o.done) {
+      s.done = 1;
+      s.istop = 1;
+    } else if (beta > 0.0) {
+      s.btol = inner_rel * o.btol * o.hnorm / beta;
+    }
+  }
   st[idx] = s;
+}
+
+// Outer FP64 residual check of a refined solve: ||h - M c|| from the row partials; the first
+// call (c = 0) records ||h||.  Later calls add the inner iterations of the step just taken.
+__global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
+                                 const InstInfo* __restrict__ insts, int n_inst, int R,
+                                 const double* __restrict__ red_r, int first, double btol,
+                                 int outer_lim) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_inst * R) return;
+  const InstInfo I = insts[idx / R];
+  const double rn = sqrt(seg_sum(red_r, I.rt0, I.rt1, idx - (idx / R) * R));
+  BtOuter o = first ? BtOuter{} : ot[idx];
+  if (first) {
+    o.hnorm = rn;
+    o.btol = btol;
+  } else if (!o.done) {
+    o.iters += st[idx].itn;
+    o.outer += 1;
+  }
+  o.rnorm = rn;
+  if (!o.done) {
+    if (o.hnorm == 0.0) {
+      o.done = 1;
+      o.istop = 0;
+    } else if (rn <= o.btol * o.hnorm) {
+      o.done = 1;
+      o.istop = 1;
+    } else if (o.outer >= outer_lim) {
+      o.done = 1;
+      o.istop = 7;
+    }
+  }
+  ot[idx] = o;
 }
 
 // alpha = ||A^T u||, phibar = beta, rhobar = alpha  (column partials)
@@ -409,7 +622,7 @@ __global__ void k_bt_lsqr_init_alpha(SolveState* st, const InstInfo* __restrict_
   const InstInfo I = insts[i];
   SolveState& s = st[idx];
   const double beta = s.beta;
-  const double alpha = beta > 0.0 ? sqrt(seg_sum(red, I.ct0, I.ct1, j)) : 0.0;
+  const double alpha = beta > 0.0 ? sqrt(seg_sum(red, I.b0, I.b1, j)) : 0.0;
   s.alpha = alpha;
   s.sv = alpha > 0.0 ? 1.0 / alpha : 0.0;
   s.phibar = beta;
@@ -446,7 +659,7 @@ __global__ void k_bt_lsqr_alpha(SolveState* st, const InstInfo* __restrict__ ins
   const double beta = s.beta;
   double alpha = s.alpha;
   if (beta > 0.0) {
-    alpha = sqrt(seg_sum(red, I.ct0, I.ct1, idx - (idx / R) * R));
+    alpha = sqrt(seg_sum(red, I.b0, I.b1, idx - (idx / R) * R));
     s.alpha = alpha;
     if (alpha > 0.0) s.sv = 1.0 / alpha;
   }
@@ -462,6 +675,8 @@ __global__ void k_bt_lsqr_alpha(SolveState* st, const InstInfo* __restrict__ ins
   s.arnorm = alpha * fabs(c) * s.phibar;
 }
 
+// x += t1 w, w = v sv + t2 w per (column, rhs) of a column tile: consecutive threads take
+// consecutive elements of the interleaved vectors; per-rhs partials of ||x||^2.
 __global__ void __launch_bounds__(256) k_bt_update(const Geo* __restrict__ geos,
                                                    const InstInfo* __restrict__ insts,
                                                    const ColTile* __restrict__ ctiles, int R,
@@ -470,28 +685,33 @@ __global__ void __launch_bounds__(256) k_bt_update(const Geo* __restrict__ geos,
                                                    const double* __restrict__ v,
                                                    const SolveState* __restrict__ st,
                                                    double* __restrict__ red) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][kMaxRhs];
   const ColTile t = ctiles[blockIdx.x];
   const InstInfo I = insts[t.inst];
-  const int64_t q = t.q0 + threadIdx.x;
-  const bool valid = q < I.col_off + geos[t.inst].n_phi;
-  for (int j = 0; j < R; ++j) {
-    const SolveState& s = st[t.inst * R + j];
-    double acc = 0.0;
-    if (valid) {
-      const int64_t o = q * R + j;
-      double xq = x[o];
+  const int64_t q_end = I.col_off + geos[t.inst].n_phi;
+  const int64_t ncol = (q_end - t.q0) < 256 ? (q_end - t.q0) : 256;
+  const int64_t e0 = (int64_t)t.q0 * R, ne = ncol * R;
+  double acc[kMaxRhs];
+#pragma unroll
+  for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
+  for (int m = 0; m < kMaxRhs; ++m) {
+    const int64_t e = threadIdx.x + 256 * (int64_t)m;
+    if (e < ne) {
+      const int j = (int)((e0 + e) % R);
+      const SolveState& s = st[t.inst * R + j];
+      double xv = x[e0 + e];
       if (!s.done) {
-        const double wq = w[o];
-        xq = xq + s.t1 * wq;
-        x[o] = xq;
-        w[o] = v[o] * s.sv + s.t2 * wq;
+        const double wv = w[e0 + e];
+        xv = xv + s.t1 * wv;
+        x[e0 + e] = xv;
+        w[e0 + e] = v[e0 + e] * s.sv + s.t2 * wv;
       }
-      acc = xq * xq;
+#pragma unroll
+      for (int jj = 0; jj < kMaxRhs; ++jj) acc[jj] += (jj == j) ? xv * xv : 0.0;
     }
-    const double sum = block_sum256(acc, sh);
-    if (threadIdx.x == 0) red[(int64_t)blockIdx.x * kMaxRhs + j] = sum;
   }
+  const double sum = block_sum8(acc, sh);
+  if (threadIdx.x < kMaxRhs) red[(int64_t)blockIdx.x * kMaxRhs + threadIdx.x] = sum;
 }
 
 __global__ void k_bt_lsqr_stop(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
@@ -526,6 +746,21 @@ __global__ void __launch_bounds__(256) k_bt_count_active(const SolveState* __res
   for (int i = threadIdx.x; i < n; i += 256) c += st[i].done ? 0.0 : 1.0;
   const double s = block_sum256(c, sh);
   if (threadIdx.x == 0) *out = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(256) k_bt_count_outer(const BtOuter* __restrict__ ot, int n,
+                                                        int32_t* __restrict__ out) {
+  __shared__ double sh[4];
+  double c = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) c += ot[i].done ? 0.0 : 1.0;
+  const double s = block_sum256(c, sh);
+  if (threadIdx.x == 0) *out = (int32_t)s;
+}
+
+__global__ void k_bt_axpy(int64_t n, const double* __restrict__ y, double* __restrict__ x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += y[i];
 }
 
 // pack / unpack between the ABI layout (per instance [R][n_i]) and the interleaved [global][R]
@@ -582,17 +817,17 @@ hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* 
   return hipGetLastError();
 }
 
-hipError_t launch_bt_mv(int prec, const Geo* geos, const DevBlock* blocks, const Tile* tiles,
-                        int64_t n_tiles, const void* A, const double* v, int R,
-                        const SolveState* st, double* tpart, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_tiles), blk(256);
+hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                         const void* A, const double* v, int R, const SolveState* st,
+                         double* tpart, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  const dim3 grid((unsigned)n_blocks), blk(256);
   if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_bt_mv<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, tiles, A, v, R, st, tpart);
+    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_bt_mv<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, tiles, A, v, R, st, tpart);
+    hipLaunchKernelGGL(k_bt_mvb<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   else
-    hipLaunchKernelGGL(k_bt_mv<ELMFB_FP64>, grid, blk, 0, s, geos, blocks, tiles, A, v, R, st, tpart);
+    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP64>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   return hipGetLastError();
 }
 
@@ -605,25 +840,44 @@ hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlo
   return hipGetLastError();
 }
 
-hipError_t launch_bt_rmv(int prec, const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
-                         const Tile* chunks, int64_t n_chunks, const void* A, const double* u,
-                         int R, const SolveState* st, double* part, hipStream_t s) {
-  if (n_chunks == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_chunks), blk(256);
-  if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_bt_rmv<ELMFB_FP32>, grid, blk, 0, s, geos, insts, blocks, chunks, A, u, R, st, part);
-  else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_bt_rmv<ELMFB_BF16>, grid, blk, 0, s, geos, insts, blocks, chunks, A, u, R, st, part);
-  else
-    hipLaunchKernelGGL(k_bt_rmv<ELMFB_FP64>, grid, blk, 0, s, geos, insts, blocks, chunks, A, u, R, st, part);
+hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* insts,
+                          const DevBlock* blocks, int64_t n_blocks, const void* A,
+                          const double* u, int R, const SolveState* st, int mode, double* out,
+                          double* red, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  const dim3 grid((unsigned)n_blocks), blk(256);
+#define RMVB(P, T)                                                                          \
+  hipLaunchKernelGGL((k_bt_rmvb<P, T>), grid, blk, 0, s, geos, insts, blocks, A, u, R, st, mode, \
+                     out, red)
+  if (prec == ELMFB_FP32) {
+    if (tp == 16) RMVB(ELMFB_FP32, 16); else if (tp == 32) RMVB(ELMFB_FP32, 32);
+    else if (tp == 64) RMVB(ELMFB_FP32, 64); else return hipErrorInvalidValue;
+  } else if (prec == ELMFB_BF16) {
+    if (tp == 16) RMVB(ELMFB_BF16, 16); else if (tp == 32) RMVB(ELMFB_BF16, 32);
+    else if (tp == 64) RMVB(ELMFB_BF16, 64); else return hipErrorInvalidValue;
+  } else {
+    // FP64 stages of 64 points exceed the static LDS limit
+    if (tp == 16) RMVB(ELMFB_FP64, 16); else if (tp == 32) RMVB(ELMFB_FP64, 32);
+    else return hipErrorInvalidValue;
+  }
+#undef RMVB
   return hipGetLastError();
 }
 
-hipError_t launch_bt_finish(const Geo* geos, const InstInfo* insts, const ColTile* ct,
-                            int64_t n_ct, const int32_t* cstart, const double* part, int mode,
-                            int R, double* out, const SolveState* st, double* red, hipStream_t s) {
-  hipLaunchKernelGGL(k_bt_finish, dim3((unsigned)n_ct), dim3(256), 0, s, geos, insts, ct, cstart,
-                     part, mode, R, out, st, red);
+hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                                const double* rc, const int64_t* foff, int R, const double* y,
+                                const double* x0, double* x, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bt_bj_recover, dim3((unsigned)n_blocks), dim3(256), 0, s, geos, blocks, rc,
+                     foff, R, y, x0, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_bt_axpy(int64_t n, const double* y, double* x, hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_bt_axpy, dim3((unsigned)nb), dim3(256), 0, s, n, y, x);
   return hipGetLastError();
 }
 
@@ -631,9 +885,20 @@ static dim3 pairs_grid(int n) { return dim3((unsigned)((n + 255) / 256)); }
 
 hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,
                                const double* red_b, const double* red_u, double atol, double btol,
-                               int iter_lim, hipStream_t s) {
+                               int iter_lim, const BtOuter* ot, double inner_rel, hipStream_t s) {
   hipLaunchKernelGGL(k_bt_lsqr_init, pairs_grid(n_inst * R), dim3(256), 0, s, st, insts, n_inst, R,
-                     red_b, red_u, atol, btol, iter_lim);
+                     red_b, red_u, atol, btol, iter_lim, ot, inner_rel);
+  return hipGetLastError();
+}
+hipError_t launch_bt_outer_check(BtOuter* ot, const SolveState* st, const InstInfo* insts,
+                                 int n_inst, int R, const double* red_r, int first, double btol,
+                                 int outer_lim, hipStream_t s) {
+  hipLaunchKernelGGL(k_bt_outer_check, pairs_grid(n_inst * R), dim3(256), 0, s, ot, st, insts,
+                     n_inst, R, red_r, first, btol, outer_lim);
+  return hipGetLastError();
+}
+hipError_t launch_bt_count_outer(const BtOuter* ot, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bt_count_outer, dim3(1), dim3(256), 0, s, ot, n, out);
   return hipGetLastError();
 }
 hipError_t launch_bt_lsqr_init_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,

@@ -106,22 +106,39 @@ hipError_t launch_bt_assemble(int lo_prec, const Geo* geos, const DevBlock* bloc
                               hipStream_t s);
 hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* rt, int64_t n_rt,
                          int R, const double* f, double* h, int32_t* bad, hipStream_t s);
-hipError_t launch_bt_mv(int prec, const Geo* geos, const DevBlock* blocks, const Tile* tiles,
-                        int64_t n_tiles, const void* A, const double* v, int R,
-                        const SolveState* st, double* tpart, hipStream_t s);
+hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                         const void* A, const double* v, int R, const SolveState* st,
+                         double* tpart, hipStream_t s);
 hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
                             const int32_t* cov, const RowTile* rt, int64_t n_rt,
                             const double* tpart, int mode, int R, double* out, const double* bvec,
                             const SolveState* st, double* red, hipStream_t s);
-hipError_t launch_bt_rmv(int prec, const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
-                         const Tile* chunks, int64_t n_chunks, const void* A, const double* u,
-                         int R, const SolveState* st, double* part, hipStream_t s);
-hipError_t launch_bt_finish(const Geo* geos, const InstInfo* insts, const ColTile* ct,
-                            int64_t n_ct, const int32_t* cstart, const double* part, int mode,
-                            int R, double* out, const SolveState* st, double* red, hipStream_t s);
+// tp: points per LDS stage, one of kBtTileChoices (64 not for FP64)
+hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* insts,
+                          const DevBlock* blocks, int64_t n_blocks, const void* A,
+                          const double* u, int R, const SolveState* st, int mode, double* out,
+                          double* red, hipStream_t s);
+hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                                const double* rc, const int64_t* foff, int R, const double* y,
+                                const double* x0, double* x, hipStream_t s);
+hipError_t launch_bt_axpy(int64_t n, const double* y, double* x, hipStream_t s);
+hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                               const double* A, const int64_t* goff, double* G, hipStream_t s);
+hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+                               double* G, const int64_t* goff, double* work, const int64_t* foff,
+                               double shift, double* rc, int32_t* nfail, hipStream_t s);
+hipError_t launch_bt_fold(int lo_prec, const Geo* geos, const DevBlock* blocks,
+                          const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
+                          const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s);
+// ot (may be NULL): outer state of a refined solve; pairs it marks done are frozen, the others
+// stop their inner LSQR once its residual estimate is inner_rel times the outer target
 hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,
                                const double* red_b, const double* red_u, double atol, double btol,
-                               int iter_lim, hipStream_t s);
+                               int iter_lim, const BtOuter* ot, double inner_rel, hipStream_t s);
+hipError_t launch_bt_outer_check(BtOuter* ot, const SolveState* st, const InstInfo* insts,
+                                 int n_inst, int R, const double* red_r, int first, double btol,
+                                 int outer_lim, hipStream_t s);
+hipError_t launch_bt_count_outer(const BtOuter* ot, int n, int32_t* out, hipStream_t s);
 hipError_t launch_bt_lsqr_init_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,
                                      const double* red, hipStream_t s);
 hipError_t launch_bt_lsqr_beta(SolveState* st, const InstInfo* insts, int n_inst, int R,

@@ -136,6 +136,10 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_assemble": (i32, [P, P, P]),
         "elmfb_batch_matvec": (i32, [P, P, P, P]),
         "elmfb_batch_rmatvec": (i32, [P, P, P, P]),
+        "elmfb_batch_precondition": (i32, [P, ctypes.c_double, ctypes.POINTER(i32), P]),
+        "elmfb_batch_autotune": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(i32), P]),
+        "elmfb_batch_set_tile": (i32, [P, i32, i32]),
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_batch_destroy": (None, [P]),
         "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
@@ -372,13 +376,34 @@ class Batch:
     def rmatvec(self, u, x, stream=None):
         self._check(_lib.elmfb_batch_rmatvec(self.h, _ptr(u), _ptr(x), _stream(stream)))
 
+    def precondition(self, shift=1e-12, stream=None):
+        """Block-Jacobi factors of every block; returns the number of identity fallbacks."""
+        nf = ctypes.c_int32(0)
+        self._check(_lib.elmfb_batch_precondition(self.h, float(shift), ctypes.byref(nf),
+                                                  _stream(stream)))
+        return int(nf.value)
+
+    def autotune(self, prec="fp64", reps=5, stream=None):
+        """Time the M^T U tile variants; returns ({tile: ms}, chosen tile)."""
+        ms = (ctypes.c_double * 3)()
+        ch = ctypes.c_int32(0)
+        self._check(_lib.elmfb_batch_autotune(self.h, _PREC[prec], int(reps), ms, ctypes.byref(ch),
+                                              _stream(stream)))
+        return {t: ms[i] for i, t in enumerate((16, 32, 64)) if ms[i] >= 0}, int(ch.value)
+
+    def set_tile(self, prec, tile):
+        self._check(_lib.elmfb_batch_set_tile(self.h, _PREC[prec], int(tile)))
+
     def solve(self, coef, iter_lim=15000, atol=0.0, btol=1e-6, check_every=50, use_graph=True,
-              stream=None):
+              method="lsqr", precond=False, inner_iters=500, outer_lim=20, stream=None):
         o = SolveOpts()
-        o.method = LSQR
+        o.method = {"lsqr": LSQR, "mixed_ir": MIXED_IR}[method]
         o.iter_lim = int(iter_lim)
         o.check_every = int(check_every)
         o.use_graph = 1 if use_graph else 0
+        o.precond = 1 if precond else 0
+        o.inner_iters = int(inner_iters)
+        o.outer_lim = int(outer_lim)
         o.atol = float(atol)
         o.btol = float(btol)
         infos = (SolveInfo * (self.n * self.n_rhs))()

@@ -6,7 +6,7 @@ import pytest
 
 from inputs import configs, feature_params
 from oracle import assemble as asm
-from oracle import linalg
+from oracle import linalg, lowprec
 
 from gpu_util import dev, torch_mod
 
@@ -28,20 +28,42 @@ def _forcing(spec, r):
     return np.stack([base * (1.0 + 0.5 * j) for j in range(r)])
 
 
-@pytest.fixture(scope="module")
-def batch():
+def _make(store_prec):
     from paper_2409_01949_amd import Batch
     specs = _batch_specs()
     feats = [feature_params(s) for s in specs]
-    B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R)
+    B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R, store_prec=store_prec)
     fs = [_forcing(s, R) for s in specs]
     B.assemble(dev(np.concatenate([f.ravel() for f in fs])))
     oracle = []
     for s, (W, b), f in zip(specs, feats, fs):
         blocks = asm.assemble_blocks(s, W, b)
         oracle.append((s, blocks, np.stack([asm.rhs(s, fj) for fj in f])))
+    return B, oracle
+
+
+@pytest.fixture(scope="module")
+def batch():
+    B, oracle = _make("fp64")
     yield B, oracle
     B.destroy()
+
+
+@pytest.fixture(scope="module")
+def batch32():
+    B, oracle = _make("fp32")
+    yield B, oracle
+    B.destroy()
+
+
+def _coefs(B, coef, oracle):
+    ch = coef.cpu().numpy()
+    out = []
+    for i, (s, bl, _) in enumerate(oracle):
+        n = len(bl) * s.K
+        c0 = B.offsets[i][1]
+        out.append(ch[R * c0:R * (c0 + n)].reshape(R, n))
+    return out
 
 
 def test_batch_offsets(batch):
@@ -120,3 +142,137 @@ def test_batch_solve_to_residual_tolerance(batch):
                 assert r <= 1.05e-6
             else:
                 assert info["istop"] in (2, 4, 5, 7)
+
+
+def test_batch_rmatvec_every_tile(batch):
+    """Every point-tile variant of the batched M^T U pass gives the oracle's product."""
+    B, oracle = batch
+    torch = torch_mod()
+    rng = np.random.default_rng(9)
+    U = [rng.standard_normal((R, s.n_rows)) for s, _, _ in oracle]
+    x = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    for tile in (16, 32):
+        B.set_tile("fp64", tile)
+        B.rmatvec(dev(np.concatenate([u.ravel() for u in U])), x)
+        xh = x.cpu().numpy()
+        for i, (s, bl, _) in enumerate(oracle):
+            n = len(bl) * s.K
+            c0 = B.offsets[i][1]
+            xi = xh[R * c0:R * (c0 + n)].reshape(R, n)
+            for j in range(R):
+                xo = asm.rmatvec(bl, U[i][j], n)
+                assert np.linalg.norm(xi[j] - xo) <= 1e-12 * np.linalg.norm(xo), (tile, i, j)
+    ms, chosen = B.autotune("fp64", reps=3)
+    print("fp64 tile timings (ms):", ms, "chosen", chosen)
+    assert chosen in ms and set(ms) == {16, 32}
+
+
+def test_batch_block_jacobi_iterates(batch):
+    """Block-Jacobi preconditioned LSQR per pair (factors of G_bb + 1e-6 trace/K I, accurate to
+    ~1e-10) equals the oracle's preconditioned LSQR after 1 and 5 steps."""
+    B, oracle = batch
+    torch = torch_mod()
+    shift = 1e-6
+    assert B.precondition(shift) == 0
+    for k in (1, 5):
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        infos = B.solve(coef, iter_lim=k, atol=0.0, btol=0.0, check_every=5, precond=True)
+        cs = _coefs(B, coef, oracle)
+        worst = 0.0
+        for i, (s, bl, h) in enumerate(oracle):
+            n = len(bl) * s.K
+            facs = linalg.block_jacobi_factors(bl, shift)
+            for j in range(R):
+                x_ref, res = linalg.preconditioned_lsqr(
+                    lambda v: asm.matvec(bl, v, s.n_rows), lambda u: asm.rmatvec(bl, u, n), bl,
+                    facs, h[j], n, atol=0, btol=0, iter_lim=k)
+                err = np.linalg.norm(cs[i][j] - x_ref) / np.linalg.norm(x_ref)
+                worst = max(worst, err)
+                assert infos[i * R + j]["iters"] == k
+                assert abs(infos[i * R + j]["rnorm"] - res.rnorm) <= 1e-8 * res.rnorm
+        print(f"bj-lsqr k={k}: worst coefficient rel diff {worst:.2e}")
+        assert worst <= 1e-8
+
+
+def test_batch_block_jacobi_beats_plain(batch):
+    """With the production shift 1e-12, 200 preconditioned steps leave a smaller residual than
+    200 plain steps on every pair that has not converged, and the oracle confirms the residual
+    of the returned coefficients."""
+    B, oracle = batch
+    torch = torch_mod()
+    B.precondition(1e-12)
+    coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    pre = B.solve(coef, iter_lim=200, atol=0.0, btol=0.0, check_every=50, precond=True)
+    cs = _coefs(B, coef, oracle)
+    plain = B.solve(torch.empty_like(coef), iter_lim=200, atol=0.0, btol=0.0, check_every=50)
+    for i, (s, bl, h) in enumerate(oracle):
+        for j in range(R):
+            p, q = pre[i * R + j], plain[i * R + j]
+            r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j])
+            print(f"instance {i} rhs {j}: ||r|| plain {q['rnorm']:.3e}, bj {p['rnorm']:.3e}, "
+                  f"oracle residual of bj coefficients {r:.3e}")
+            assert abs(r - p["rnorm"]) <= 1e-6 * np.linalg.norm(h[j]) + 1e-3 * r
+            assert p["rnorm"] <= q["rnorm"] * 1.01
+
+
+def test_batch_mixed_refinement_matches_oracle(batch32):
+    """FP64 refinement around inner LSQR on the FP32 copy of the block-Jacobi preconditioned
+    matrix M R^{-1} (formed in FP64, rounded to nearest even): after 1 and 2 outer steps of 5
+    inner steps every pair equals the oracle's refinement on its folded blocks, mapped back by
+    R^{-1}.  The FP32 copies come from FP64 products summed in different orders, so an entry
+    next to a rounding boundary may round differently: tolerance 1e-7."""
+    B, oracle = batch32
+    torch = torch_mod()
+    shift = 1e-6
+    B.precondition(shift)
+    inner = 5
+    for outer in (1, 2):
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        infos = B.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, check_every=5,
+                        precond=True, atol=0.0, btol=0.0)
+        cs = _coefs(B, coef, oracle)
+        worst = 0.0
+        for i, (s, bl, h) in enumerate(oracle):
+            n = len(bl) * s.K
+            facs = linalg.block_jacobi_factors(bl, shift)
+            fb = linalg.fold_blocks(bl, facs)
+            lo = [asm.Block(blk.sd, blk.rows, lowprec.to_f32(blk.M)) for blk in fb]
+            for j in range(R):
+                cy, hist = linalg.refine_lsqr(
+                    lambda v: asm.matvec(fb, v, s.n_rows), lambda u: asm.rmatvec(fb, u, n),
+                    lambda v: asm.matvec(lo, v, s.n_rows), lambda u: asm.rmatvec(lo, u, n), h[j],
+                    n, outer, inner)
+                c = linalg.block_apply(bl, facs, cy)
+                info = infos[i * R + j]
+                assert info["outer_iters"] == outer and info["iters"] == outer * inner
+                worst = max(worst, np.linalg.norm(cs[i][j] - c) / np.linalg.norm(c))
+                r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j])
+                assert abs(info["rnorm"] - r) <= 1e-9 * np.linalg.norm(h[j])
+        print(f"mixed outer={outer}: worst coefficient rel diff {worst:.2e}")
+        assert worst <= 1e-7
+
+
+def test_batch_mixed_solve_to_tolerance(batch32):
+    """Mixed refinement with the production shift stops each pair on its FP64 residual: pairs
+    reporting istop 1 satisfy ||h - M c|| <= btol ||h|| by the oracle's matvec."""
+    B, oracle = batch32
+    torch = torch_mod()
+    B.precondition(1e-12)
+    btol = 1e-6
+    coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    infos = B.solve(coef, method="mixed_ir", inner_iters=2000, outer_lim=6, check_every=50,
+                    precond=True, atol=0.0, btol=btol)
+    cs = _coefs(B, coef, oracle)
+    n_conv = 0
+    for i, (s, bl, h) in enumerate(oracle):
+        for j in range(R):
+            info = infos[i * R + j]
+            r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j]) / np.linalg.norm(h[j])
+            print(f"instance {i} rhs {j}: istop {info['istop']}, outer {info['outer_iters']}, "
+                  f"inner {info['iters']}, rel residual {r:.2e}")
+            if info["istop"] == 1:
+                n_conv += 1
+                assert r <= btol * (1 + 1e-2)
+            else:
+                assert info["istop"] == 7 and info["outer_iters"] == 6
+    assert n_conv >= 1

@@ -215,6 +215,34 @@ def test_block_jacobi_factors_reconstruct_shifted_gram():
         assert np.abs(E).max() <= 1e-12 * np.abs(G).max()
 
 
+def test_folded_blocks_are_orthonormalised_and_equal_the_product():
+    """M_j R_j^{-1} from fold_blocks: its Gram matrix is I - lambda_j R_j^{-T} R_j^{-1} (from
+    R_j^T R_j = G_jj + lambda_j I), i.e. orthonormal columns up to the shift, and the folded
+    system's products equal M (R^{-1} y) and R^{-T} (M^T u).  Shift 1e-6 keeps cond(G + lambda I)
+    near 1e6, so the identity holds to ~1e-10 in floating point."""
+    spec, blocks = _tiny2d_blocks()
+    shift = 1e-6
+    facs = linalg.block_jacobi_factors(blocks, shift)
+    folded = linalg.fold_blocks(blocks, facs)
+    for blk, fb, R in zip(blocks, folded, facs):
+        G = blk.M.T @ blk.M
+        lam = shift * np.trace(G) / spec.K
+        Ri = np.linalg.inv(R)
+        E = fb.M.T @ fb.M - (np.eye(spec.K) - lam * Ri.T @ Ri)
+        assert np.abs(E).max() <= 1e-8
+        assert np.array_equal(fb.rows, blk.rows)
+    n = len(blocks) * spec.K
+    N = spec.n_rows
+    rng = np.random.default_rng(4)
+    y, u = rng.standard_normal(n), rng.standard_normal(N)
+    a = asm.matvec(folded, y, N)
+    b = asm.matvec(blocks, linalg.block_apply(blocks, facs, y), N)
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+    a = asm.rmatvec(folded, u, n)
+    b = linalg.block_apply(blocks, facs, asm.rmatvec(blocks, u, n), transpose=True)
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
 def test_preconditioned_lsqr_reaches_least_squares_solution():
     """Right preconditioning changes the iteration, not the minimiser: on a full-rank system it
     converges to the QR solution."""
