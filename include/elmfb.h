@@ -299,6 +299,45 @@ elmfb_status elmfb_batch_solve(elmfb_batch b, const elmfb_solve_opts* opts, doub
 void elmfb_batch_destroy(elmfb_batch b);
 const char* elmfb_batch_last_error(elmfb_batch b);
 
+/* ---- learned warm start: a small MLP trained on the method's own solutions --------------- */
+
+/* A fully connected tanh network for predicting coefficient blocks from problem parameters
+ * (warm starts for the Krylov solve; not part of the paper's method, whose own optimiser
+ * settings it uses: Adam with learning rate 1e-3, Sec. 4.1).  Layers l = 0..n_layers-1 map
+ * dims[l] -> dims[l+1]: z = a W_l^T + b_l with W_l [dims[l+1]][dims[l]] row-major; hidden layers
+ * a = tanh(z), the last layer is linear.  Samples are rows: x [batch][dims[0]], y
+ * [batch][dims[n_layers]], FP32.  Products take bfloat16 operands (round to nearest even: the
+ * input, the weights, the hidden activations and the back-propagated gradients) with FP32
+ * accumulation on the matrix cores; master weights, biases and Adam moments are FP32.
+ * Parameters are one flat FP32 vector [W_0, b_0, W_1, b_1, ...]. */
+typedef struct elmfb_mlp_s* elmfb_mlp;
+
+typedef struct {
+  double lr, beta1, beta2, eps;   /* Adam (Kingma & Ba 2015); lr > 0, betas in [0,1), eps > 0 */
+} elmfb_adam;
+
+/* dims_host [n_layers+1] (1..65536 each), n_layers 1..16, max_batch 1..2^24.  Parameters start
+ * at zero; set them with elmfb_mlp_set_params. */
+elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t max_batch,
+                              elmfb_mlp* out);
+elmfb_status elmfb_mlp_query(elmfb_mlp m, int64_t* n_params_host);
+/* Copy the flat parameters in (also resets the Adam moments and step count) or out. */
+elmfb_status elmfb_mlp_set_params(elmfb_mlp m, const float* params_host);
+elmfb_status elmfb_mlp_get_params(elmfb_mlp m, float* params_host);
+/* Gradient of the last elmfb_mlp_train_step, same layout as the parameters. */
+elmfb_status elmfb_mlp_get_grads(elmfb_mlp m, float* grads_host);
+/* y_dev [batch][dims[n_layers]] = network(x_dev [batch][dims[0]]), 1 <= batch <= max_batch. */
+elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, int32_t batch, float* y_dev,
+                               void* stream);
+/* Loss = mean over the batch and outputs of (y - t)^2; gradient by back-propagation; then one
+ * Adam step when opt is not NULL (opt NULL: gradient only).  loss_host (may be NULL; then the
+ * call does not synchronise) receives the loss before the step. */
+elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* t_dev,
+                                  int32_t batch, const elmfb_adam* opt, double* loss_host,
+                                  void* stream);
+void elmfb_mlp_destroy(elmfb_mlp m);
+const char* elmfb_mlp_last_error(elmfb_mlp m);
+
 /* Release everything the handle owns.  NULL is a no-op. */
 void elmfb_destroy(elmfb_problem h);
 

@@ -13,6 +13,7 @@ from .problems import (  # noqa: F401
     feature_params,
     grid_axes,
     grid_points,
+    mlp_init,
     n_phi,
 )
 from .families import (  # noqa: F401

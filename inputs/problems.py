@@ -92,3 +92,15 @@ def grid_points(spec: ProblemSpec, n_points=None) -> np.ndarray:
         return axes[0][:, None].copy()
     X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
     return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def mlp_init(dims, seed):
+    """Flat FP32 parameters [W_0, b_0, W_1, b_1, ...] of a tanh network: W_l ~ U(-a, a) with
+    a = 1/sqrt(fan_in) (LeCun-uniform scale), b_l = 0; W_l [dims[l+1], dims[l]] row-major."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for n_in, n_out in zip(dims[:-1], dims[1:]):
+        a = 1.0 / np.sqrt(n_in)
+        parts.append(rng.uniform(-a, a, size=n_out * n_in))
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts).astype(np.float32)

@@ -10,6 +10,7 @@ from .elmfb import (  # noqa: F401
     FP32,
     FP64,
     LSQR,
+    MLP,
     ElmfbError,
     Problem,
     define_problem,

@@ -155,6 +155,30 @@ hipError_t launch_bt_pack(const InstInfo* insts, const int64_t* sizes, int n_ins
                           int64_t total, const double* src, double* dst, int to_interleaved,
                           int use_cols, hipStream_t s);
 
+// ---- warm-start MLP (k_mlp.hip)
+enum { MLP_EPI_F32 = 0, MLP_EPI_BIAS = 1, MLP_EPI_BIAS_TANH = 2, MLP_EPI_DTANH = 3 };
+struct MlpGemm {
+  int M, N, K;
+  const uint16_t* A;       // A(m, k) = A[m sam + k sak], bfloat16 bits
+  int64_t sam, sak;
+  const uint16_t* B;       // B(k, n) = B[k sbk + n sbn]
+  int64_t sbk, sbn;
+  int epi;
+  const float* bias;       // [N] (BIAS, BIAS_TANH)
+  const uint16_t* act;     // [M][ldo] activations (DTANH)
+  float* out_f32;          // F32, BIAS
+  uint16_t* out_bf16;      // BIAS_TANH, DTANH
+  int64_t ldo;
+};
+hipError_t launch_mlp_gemm(const MlpGemm& p, hipStream_t s);
+hipError_t launch_mlp_to_bf16(int64_t n, const float* x, uint16_t* y, hipStream_t s);
+hipError_t launch_mlp_loss(int64_t n, const float* y, const float* t, uint16_t* g, double* part,
+                           int n_part, double* loss, hipStream_t s);
+hipError_t launch_mlp_colsum(int M, int N, const uint16_t* g, float* db, hipStream_t s);
+hipError_t launch_mlp_adam(int64_t n, float* prm, const float* grad, float* m1, float* m2,
+                           uint16_t* pb, float lr, float b1, float b2, float eps, float c1,
+                           float c2, hipStream_t s);
+
 // ---- evaluation (k_evaluate.hip)
 hipError_t launch_evaluate(const Geo& g, const double* W, const double* b, const double* coef,
                            const double* pts, int64_t n_pts, double* u, hipStream_t s);

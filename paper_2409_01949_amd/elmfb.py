@@ -93,6 +93,11 @@ class SolveInfo(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 class ElmfbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"elmfb error {code}: {msg}")
@@ -143,6 +148,15 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_batch_destroy": (None, [P]),
         "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
+        "elmfb_mlp_create": (i32, [i32, ctypes.POINTER(i32), i32, ctypes.POINTER(P)]),
+        "elmfb_mlp_query": (i32, [P, ctypes.POINTER(i64)]),
+        "elmfb_mlp_set_params": (i32, [P, P]),
+        "elmfb_mlp_get_params": (i32, [P, P]),
+        "elmfb_mlp_get_grads": (i32, [P, P]),
+        "elmfb_mlp_forward": (i32, [P, P, i32, P, P]),
+        "elmfb_mlp_train_step": (i32, [P, P, P, i32, ctypes.POINTER(Adam), ctypes.POINTER(dbl), P]),
+        "elmfb_mlp_destroy": (None, [P]),
+        "elmfb_mlp_last_error": (ctypes.c_char_p, [P]),
         "elmfb_destroy": (None, [P]),
         "elmfb_last_error": (ctypes.c_char_p, [P]),
     }
@@ -414,6 +428,73 @@ class Batch:
     def destroy(self):
         if getattr(self, "h", None) is not None and _lib is not None:
             _lib.elmfb_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Owns one elmfb_mlp handle (tanh network, bfloat16 products, FP32 master weights)."""
+
+    def __init__(self, dims, max_batch):
+        lib = load_library()
+        d = (ctypes.c_int32 * len(dims))(*[int(v) for v in dims])
+        h = ctypes.c_void_p()
+        code = lib.elmfb_mlp_create(len(dims) - 1, d, int(max_batch), ctypes.byref(h))
+        if code != OK:
+            raise ElmfbError(code, (lib.elmfb_mlp_last_error(None) or b"").decode())
+        self.h = h
+        self.dims = list(dims)
+        self.max_batch = int(max_batch)
+        n = ctypes.c_int64(0)
+        self._check(lib.elmfb_mlp_query(self.h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+
+    def _check(self, code):
+        if code != OK:
+            msg = _lib.elmfb_mlp_last_error(self.h)
+            raise ElmfbError(code, msg.decode() if msg else "")
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        assert v.size == self.n_params
+        self._check(_lib.elmfb_mlp_set_params(self.h, v.ctypes.data))
+
+    def get_params(self):
+        v = np.empty(self.n_params, dtype=np.float32)
+        self._check(_lib.elmfb_mlp_get_params(self.h, v.ctypes.data))
+        return v
+
+    def get_grads(self):
+        v = np.empty(self.n_params, dtype=np.float32)
+        self._check(_lib.elmfb_mlp_get_grads(self.h, v.ctypes.data))
+        return v
+
+    def forward(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        self._check(_lib.elmfb_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y),
+                                           _stream(stream)))
+        return y
+
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, update=True,
+                   want_loss=True, stream=None):
+        opt = Adam(lr, beta1, beta2, eps)
+        loss = ctypes.c_double(0.0)
+        self._check(_lib.elmfb_mlp_train_step(self.h, _ptr(x), _ptr(t), int(x.shape[0]),
+                                              ctypes.byref(opt) if update else None,
+                                              ctypes.byref(loss) if want_loss else None,
+                                              _stream(stream)))
+        return float(loss.value) if want_loss else None
+
+    def destroy(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.elmfb_mlp_destroy(self.h)
         self.h = None
 
     def __del__(self):

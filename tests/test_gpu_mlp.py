@@ -1,0 +1,110 @@
+"""GPU parity of the warm-start MLP (BF16 products on the matrix cores, FP32 accumulation and
+master weights) against the reference MLP in its bfloat16-rounding mode (same rounding points,
+float64 sums), at the production width (3 hidden layers of 512) with ragged batch and layer
+sizes (several 64 x 64 tiles plus tails)."""
+import numpy as np
+import pytest
+
+from inputs import mlp_init
+from oracle import mlp as omlp
+
+from gpu_util import torch_mod
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [11, 512, 512, 512, 32]
+
+
+def _data(batch, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((batch, DIMS[0])).astype(np.float32),
+            rng.standard_normal((batch, DIMS[-1])).astype(np.float32))
+
+
+@pytest.fixture(scope="module")
+def net():
+    from paper_2409_01949_amd import MLP
+    m = MLP(DIMS, 4096)
+    yield m
+    m.destroy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_mlp_forward_matches_oracle(net):
+    """FP32 accumulation against float64 sums of the same bfloat16 operands: the rare operand
+    that rounds to the neighbouring bfloat16 value keeps the outputs within 2e-3 (norm-wise)."""
+    torch = torch_mod()
+    p = mlp_init(DIMS, 1)
+    net.set_params(p)
+    for batch in (1, 97, 300):
+        X, _ = _data(batch, batch)
+        y = net.forward(torch.as_tensor(X).cuda()).cpu().numpy()
+        yo, _ = omlp.forward(omlp.unflatten(p.astype(np.float64), DIMS), X.astype(np.float64),
+                             bf16=True)
+        err = _rel(y, yo)
+        print(f"batch {batch}: forward rel diff {err:.2e}")
+        assert err <= 2e-3
+
+
+def test_mlp_gradients_match_oracle(net):
+    torch = torch_mod()
+    p = mlp_init(DIMS, 2)
+    net.set_params(p)
+    X, T = _data(200, 7)
+    loss = net.train_step(torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda(), update=False)
+    g = net.get_grads()
+    params = omlp.unflatten(p.astype(np.float64), DIMS)
+    y, acts = omlp.forward(params, X.astype(np.float64), bf16=True)
+    lo, dy = omlp.mse(y, T.astype(np.float64))
+    go = omlp.flatten(omlp.backward(params, acts, dy, bf16=True))
+    assert abs(loss - lo) <= 1e-3 * lo
+    gl = omlp.unflatten(g.astype(np.float64), DIMS)
+    gol = omlp.unflatten(go, DIMS)
+    for l, ((gW, gb), (oW, ob)) in enumerate(zip(gl, gol)):
+        eW, eb = _rel(gW, oW), _rel(gb, ob)
+        print(f"layer {l}: dW rel diff {eW:.2e}, db rel diff {eb:.2e}")
+        assert eW <= 5e-3 and eb <= 5e-3
+    # and the gradient itself agrees with float64 central differences of the float64 loss
+    # along the gradient direction (the bfloat16 rounding is a small perturbation of it)
+    d = go / np.linalg.norm(go)
+    h = 1e-4
+
+    def f(vec):
+        yy, _ = omlp.forward(omlp.unflatten(vec, DIMS), X.astype(np.float64))
+        return omlp.mse(yy, T.astype(np.float64))[0]
+
+    fd = (f(p + h * d) - f(p - h * d)) / (2 * h)
+    assert abs(float(g @ d) - fd) <= 3e-2 * abs(fd) + 1e-6
+
+
+def test_mlp_adam_step_matches_formula(net):
+    """One Adam step from the GPU's own gradient: the FP32 update equals the float64 formula."""
+    torch = torch_mod()
+    p = mlp_init(DIMS, 3)
+    net.set_params(p)
+    X, T = _data(64, 9)
+    net.train_step(torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda(), lr=1e-3)
+    g = net.get_grads().astype(np.float64)
+    p1 = net.get_params().astype(np.float64)
+    step = 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.abs((p - p1) - step).max() <= 1e-6 * 1e-3 + 1e-7 * np.abs(p).max()
+
+
+def test_mlp_training_reduces_loss(net):
+    """A few hundred Adam steps on a smooth map of the inputs cut the loss by 10x."""
+    torch = torch_mod()
+    net.set_params(mlp_init(DIMS, 4))
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-1, 1, (2048, DIMS[0])).astype(np.float32)
+    M = rng.standard_normal((DIMS[0], DIMS[-1])) / np.sqrt(DIMS[0])
+    T = np.sin(X @ M).astype(np.float32)
+    xd, td = torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda()
+    l0 = net.train_step(xd, td, update=False)
+    for _ in range(300):
+        net.train_step(xd, td, lr=1e-3, want_loss=False)
+    l1 = net.train_step(xd, td, update=False)
+    print(f"loss {l0:.4e} -> {l1:.4e}")
+    assert l1 < 0.1 * l0
