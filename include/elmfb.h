@@ -280,6 +280,12 @@ elmfb_status elmfb_batch_autotune(elmfb_batch b, int32_t prec, int32_t reps, dou
  * 64 except for ELMFB_FP64), as elmfb_batch_autotune would keep it. */
 elmfb_status elmfb_batch_set_tile(elmfb_batch b, int32_t prec, int32_t tile);
 
+/* Coefficients in block-Jacobi coordinates: with preconditioned = 1, elmfb_batch_solve takes x0
+ * and returns its result as y = R x per block (the coordinates of M R^{-1}, whose block columns
+ * are orthonormal over each support up to the shift), which suits learned warm starts; such
+ * solves need precond = 1.  0 (the default) restores x. */
+elmfb_status elmfb_batch_set_coords(elmfb_batch b, int32_t preconditioned);
+
 /* Solve every (instance, right-hand side) with its own recurrence and stop tests (Sec. 4.1:
  * LSQR, Paige-Saunders, damp 0; FP64 recurrences).
  *   method ELMFB_LSQR: LSQR on the FP64 matrix with atol, btol, iter_lim;

@@ -183,3 +183,18 @@ def warm_draws(n, seed):
     om = rng.uniform(5.0, 50.0, size=n)
     c = rng.standard_normal((n, 3))
     return om, c
+
+
+def warm_groups(n_groups, seed, n_rhs=8):
+    """Parameters of the 1D warm-start family in groups that share omega (one matrix, n_rhs
+    source-coefficient vectors): omega ~ U[5, 50], c ~ N(0, 1)^3 per right-hand side."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    om = rng.uniform(5.0, 50.0, size=n_groups)
+    C = rng.standard_normal((n_groups, n_rhs, 3))
+    return om, C
+
+
+def warm_batch_forcing(spec: ProblemSpec, C) -> np.ndarray:
+    """[n_rhs, N] forcing of one warm-family instance for each coefficient vector C[r]."""
+    pts = grid_points(spec)
+    return np.stack([fam.ode_modes_forcing(pts, spec.meta["freqs"], c) for c in C])

@@ -48,7 +48,8 @@ struct elmfb_batch_s {
   double *d_h = nullptr, *d_u = nullptr, *d_v = nullptr, *d_w = nullptr, *d_x = nullptr,
          *d_c = nullptr;
   double* d_tpart = nullptr;
-  double *d_red_r = nullptr, *d_red_b = nullptr, *d_red_c = nullptr;
+  double *d_red_r = nullptr, *d_red_b = nullptr, *d_red_c = nullptr, *d_red_h = nullptr;
+  double *d_x0 = nullptr, *d_h0 = nullptr;   // warm start and h - M x0 (allocated on first use)
   SolveState* d_state = nullptr;
   BtOuter* d_outer = nullptr;
   int32_t *d_flag = nullptr, *d_count = nullptr;
@@ -57,6 +58,7 @@ struct elmfb_batch_s {
   Tile* d_ftiles = nullptr;    // 64-point runs of the blocks (forming M R^{-1})
   bool assembled = false, bj_ready = false;
   bool lo_hat = false;         // the low-precision copy holds M R^{-1} (else M)
+  bool coords_y = false;       // solve in/out coefficients are y = R x (block-Jacobi coordinates)
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<int64_t, hipGraphExec_t> graphs;
@@ -218,13 +220,15 @@ hipError_t bt_iteration(elmfb_batch B, int prec, bool bj, hipStream_t s) {
 }
 
 // LSQR start from the rows already in d_u (u = rhs) with their squared-norm partials in
-// d_red_r: beta, v = A^T u / beta, alpha, w = v / alpha, x = 0.
+// d_red_r: beta, v = A^T u / beta, alpha, w = v / alpha, x = 0.  red_b: partials of the norm
+// the stop tests are relative to (default: ||u||).
 hipError_t bt_lsqr_start(elmfb_batch B, int prec, bool bj, double atol, double btol, int iter_lim,
-                         const BtOuter* ot, double inner_rel, hipStream_t s) {
+                         const BtOuter* ot, double inner_rel, hipStream_t s,
+                         const double* red_b = nullptr) {
   const int n = B->n, R = B->R;
   hipError_t e;
-  if ((e = launch_bt_lsqr_init(B->d_state, B->d_insts, n, R, B->d_red_r, B->d_red_r, atol, btol,
-                               iter_lim, ot, inner_rel, s)))
+  if ((e = launch_bt_lsqr_init(B->d_state, B->d_insts, n, R, red_b ? red_b : B->d_red_r,
+                               B->d_red_r, atol, btol, iter_lim, ot, inner_rel, s)))
     return e;
   if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks,
                           (int64_t)B->blocks.size(), matrix_of(B, prec, bj), B->d_u, R,
@@ -238,9 +242,10 @@ hipError_t bt_lsqr_start(elmfb_batch B, int prec, bool bj, double atol, double b
                           B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_b, s);
 }
 
-// u = h - A c with the FP64 matrix A (M, or M R^{-1} with block-Jacobi and c in preconditioned
-// coordinates), squared-norm partials in d_red_r; c = NULL means c = 0.
-hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s) {
+// u = b - A c with the FP64 matrix A (M, or M R^{-1} with block-Jacobi and c in preconditioned
+// coordinates), squared-norm partials in d_red_r; c = NULL means c = 0; b = NULL means h.
+hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s,
+                       const double* b = nullptr) {
   const int R = B->R;
   hipError_t e;
   if (c) {
@@ -251,8 +256,8 @@ hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s) {
     return e;
   }
   return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
-                          (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u, B->d_h,
-                          nullptr, B->d_red_r, s);
+                          (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u,
+                          b ? b : B->d_h, nullptr, B->d_red_r, s);
 }
 
 // Run LSQR steps until every pair has stopped: replays of a captured graph of `chunk` steps (or
@@ -328,7 +333,7 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   const int64_t nblk = (int64_t)B->blocks.size();
   int64_t bytes = B->nnz * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
                   B->n_phi * R * 8 * 4 + B->n_phi * 24 + B->n_tab * 24 +
-                  (int64_t)(B->rtiles.size() * 2 + B->ctiles.size() + nblk) * kMaxRhs * 8 +
+                  (int64_t)(B->rtiles.size() * 3 + B->ctiles.size() + nblk) * kMaxRhs * 8 +
                   nblk * ((int64_t)sizeof(DevBlock) + 16) +
                   (int64_t)(B->tiles.size() + B->ftiles.size()) * sizeof(Tile) +
                   (int64_t)n * R * ((int64_t)sizeof(SolveState) + (int64_t)sizeof(BtOuter));
@@ -387,6 +392,7 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_red_r, (int64_t)B->rtiles.size() * kMaxRhs * 8);
   BALLOC(B->d_red_b, (int64_t)B->ctiles.size() * kMaxRhs * 8);
   BALLOC(B->d_red_c, nblk * kMaxRhs * 8);
+  BALLOC(B->d_red_h, (int64_t)B->rtiles.size() * kMaxRhs * 8);
   BALLOC(B->d_state, (int64_t)n * R * sizeof(SolveState));
   BALLOC(B->d_outer, (int64_t)n * R * sizeof(BtOuter));
   BALLOC(B->d_flag, 64);
@@ -617,6 +623,12 @@ elmfb_status elmfb_batch_set_tile(elmfb_batch B, int32_t prec, int32_t tile) {
   return ELMFB_OK;
 }
 
+elmfb_status elmfb_batch_set_coords(elmfb_batch B, int32_t preconditioned) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  B->coords_y = preconditioned != 0;
+  return ELMFB_OK;
+}
+
 elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, double* coef_dev,
                                elmfb_solve_info* info, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -625,8 +637,10 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   const bool mixed = opts->method == ELMFB_MIXED_IR;
   if (opts->method != ELMFB_LSQR && !mixed)
     return bfail(B, ELMFB_E_UNSUPPORTED, "batches solve with LSQR or MIXED_IR");
-  if (opts->x0_dev || opts->n_check)
-    return bfail(B, ELMFB_E_UNSUPPORTED, "batched solves take no warm start or check points");
+  if (opts->n_check)
+    return bfail(B, ELMFB_E_UNSUPPORTED, "batched solves take no check points");
+  if (B->coords_y && !opts->precond)
+    return bfail(B, ELMFB_E_STATE, "block-Jacobi coordinates need a preconditioned solve");
   if (opts->precond && !B->bj_ready)
     return bfail(B, ELMFB_E_STATE, "precond requested before elmfb_batch_precondition");
   if (mixed && B->lo_prec == ELMFB_FP64)
@@ -642,28 +656,55 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   const int n = B->n, R = B->R;
   const int64_t nb = (int64_t)B->blocks.size();
   const bool bj = opts->precond != 0;
+  const bool warm = opts->x0_dev != nullptr;
+  if (warm && !B->d_x0) {
+    hipError_t e1 = balloc(B, &B->d_x0, B->n_phi * R * 8);
+    hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_h0, B->n_rows * R * 8) : e1;
+    if (e2 != hipSuccess) {
+      bfree(B, B->d_x0);
+      B->d_x0 = nullptr;
+      return bfail(B, ELMFB_E_NOMEM, std::string("warm-start storage: ") + hipGetErrorString(e2));
+    }
+    B->bytes += (B->n_phi + B->n_rows) * R * 8;
+  }
   hipStream_t caller = (hipStream_t)stream;
   hipStream_t s = B->stream;
   BHIP(B, hipEventRecord(B->ev_in, caller));
   BHIP(B, hipStreamWaitEvent(s, B->ev_in, 0));
+  // ||h|| partials (d_red_h); with a warm start the solve runs on h0 = h - M x0 (FP64 M)
+  BHIP(B, bt_residual(B, nullptr, false, s));
+  BHIP(B, hipMemcpyAsync(B->d_red_h, B->d_red_r, B->rtiles.size() * kMaxRhs * 8,
+                         hipMemcpyDeviceToDevice, s));
+  const double* rhs = B->d_h;
+  if (warm) {
+    BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, n, R, B->n_phi, opts->x0_dev, B->d_x0, 1, 1, s));
+    BHIP(B, bt_residual(B, B->d_x0, B->coords_y, s));   // h - M x0, or h - (M R^{-1}) y0
+    BHIP(B, hipMemcpyAsync(B->d_h0, B->d_u, (size_t)(B->n_rows * R * 8), hipMemcpyDeviceToDevice,
+                           s));
+    rhs = B->d_h0;
+  }
   if (!mixed) {
-    BHIP(B, bt_residual(B, nullptr, false, s));   // u = h
+    // u holds the right-hand side (h, or h - M x0) and d_red_r its partials
     BHIP(B, bt_lsqr_start(B, ELMFB_FP64, bj, opts->atol, opts->btol, opts->iter_lim, nullptr, 0.0,
-                          s));
+                          s, B->d_red_h));
     const elmfb_status st = bt_run(B, ELMFB_FP64, bj, opts->check_every, opts->use_graph != 0, s);
     if (st != ELMFB_OK) return st;
-    if (bj)
+    if (bj && !B->coords_y)
       BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_x,
-                                   nullptr, B->d_c, s));
+                                   warm ? B->d_x0 : nullptr, B->d_c, s));
+    else if (warm)
+      BHIP(B, launch_bt_recover_plain(B->n_phi * R, B->d_x, B->d_x0, B->d_c, s));
     else
       BHIP(B, hipMemcpyAsync(B->d_c, B->d_x, (size_t)(B->n_phi * R * 8), hipMemcpyDeviceToDevice, s));
   } else {
-    // FP64 refinement: r = h - M c, inner LSQR on the stored low-precision copy, c += d
+    // FP64 refinement: r = rhs - A c, inner LSQR on the stored low-precision copy, c += d
     const int lo = B->lo_prec;
-    BHIP(B, hipMemsetAsync(B->d_c, 0, (size_t)(B->n_phi * R * 8), s));
-    BHIP(B, bt_residual(B, nullptr, false, s));
-    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 1,
+    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_h, 1,
                                   opts->btol, opts->outer_lim, s));
+    if (warm)   // the residual of x0 (in d_red_r) may already meet the target
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 2,
+                                    opts->btol, opts->outer_lim, s));
+    BHIP(B, hipMemsetAsync(B->d_c, 0, (size_t)(B->n_phi * R * 8), s));
     for (;;) {
       int32_t active = 0;
       BHIP(B, launch_bt_count_outer(B->d_outer, n * R, B->d_count, s));
@@ -675,15 +716,18 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
       if (st != ELMFB_OK) return st;
       // c += d (c in preconditioned coordinates with block-Jacobi)
       BHIP(B, launch_bt_axpy(B->n_phi * R, B->d_x, B->d_c, s));
-      BHIP(B, bt_residual(B, B->d_c, bj, s));
+      BHIP(B, bt_residual(B, B->d_c, bj, s, rhs));
       BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 0,
                                     opts->btol, opts->outer_lim, s));
     }
   }
   const double* fin = B->d_c;
-  if (mixed && bj) {   // coefficients x = R^{-1} c
-    BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_c,
-                                 nullptr, B->d_x, s));
+  if (mixed) {   // coefficients x = x0 + R^{-1} c (or x0 + c; y = y0 + c in block-Jacobi coordinates)
+    if (bj && !B->coords_y)
+      BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_c,
+                                   warm ? B->d_x0 : nullptr, B->d_x, s));
+    else
+      BHIP(B, launch_bt_recover_plain(B->n_phi * R, B->d_c, warm ? B->d_x0 : nullptr, B->d_x, s));
     fin = B->d_x;
   }
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, n, R, B->n_phi, fin, coef_dev, 0, 1, s));

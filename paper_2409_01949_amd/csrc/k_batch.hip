@@ -579,21 +579,23 @@ __global__ void k_bt_lsqr_init(SolveState* st, const InstInfo* __restrict__ inst
   st[idx] = s;
 }
 
-// Outer FP64 residual check of a refined solve: ||h - M c|| from the row partials; the first
-// call (c = 0) records ||h||.  Later calls add the inner iterations of the step just taken.
+// Outer FP64 residual check of a refined solve from the row partials of the current residual.
+// mode 1: the partials are those of h; record ||h|| (fresh state).  mode 2: the residual of a
+// warm start; no step is counted.  mode 0: after a refinement step, whose inner iterations are
+// added.  A pair stops once ||h - M c|| <= btol ||h|| or after outer_lim steps.
 __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
                                  const InstInfo* __restrict__ insts, int n_inst, int R,
-                                 const double* __restrict__ red_r, int first, double btol,
+                                 const double* __restrict__ red_r, int mode, double btol,
                                  int outer_lim) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_inst * R) return;
   const InstInfo I = insts[idx / R];
   const double rn = sqrt(seg_sum(red_r, I.rt0, I.rt1, idx - (idx / R) * R));
-  BtOuter o = first ? BtOuter{} : ot[idx];
-  if (first) {
+  BtOuter o = mode == 1 ? BtOuter{} : ot[idx];
+  if (mode == 1) {
     o.hnorm = rn;
     o.btol = btol;
-  } else if (!o.done) {
+  } else if (mode == 0 && !o.done) {
     o.iters += st[idx].itn;
     o.outer += 1;
   }
@@ -757,6 +759,14 @@ __global__ void __launch_bounds__(256) k_bt_count_outer(const BtOuter* __restric
   if (threadIdx.x == 0) *out = (int32_t)s;
 }
 
+// x = x0 + y (x0 may be NULL)
+__global__ void k_bt_recover_plain(int64_t n, const double* __restrict__ y,
+                                   const double* __restrict__ x0, double* __restrict__ x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (x0 ? x0[i] : 0.0) + y[i];
+}
+
 __global__ void k_bt_axpy(int64_t n, const double* __restrict__ y, double* __restrict__ x) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -870,6 +880,15 @@ hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bt_bj_recover, dim3((unsigned)n_blocks), dim3(256), 0, s, geos, blocks, rc,
                      foff, R, y, x0, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_bt_recover_plain(int64_t n, const double* y, const double* x0, double* x,
+                                   hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_bt_recover_plain, dim3((unsigned)nb), dim3(256), 0, s, n, y, x0, x);
   return hipGetLastError();
 }
 

@@ -122,6 +122,8 @@ hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t
                                 const double* rc, const int64_t* foff, int R, const double* y,
                                 const double* x0, double* x, hipStream_t s);
 hipError_t launch_bt_axpy(int64_t n, const double* y, double* x, hipStream_t s);
+hipError_t launch_bt_recover_plain(int64_t n, const double* y, const double* x0, double* x,
+                                   hipStream_t s);
 hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
                                const double* A, const int64_t* goff, double* G, hipStream_t s);
 hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
@@ -136,7 +138,7 @@ hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst
                                const double* red_b, const double* red_u, double atol, double btol,
                                int iter_lim, const BtOuter* ot, double inner_rel, hipStream_t s);
 hipError_t launch_bt_outer_check(BtOuter* ot, const SolveState* st, const InstInfo* insts,
-                                 int n_inst, int R, const double* red_r, int first, double btol,
+                                 int n_inst, int R, const double* red_r, int mode, double btol,
                                  int outer_lim, hipStream_t s);
 hipError_t launch_bt_count_outer(const BtOuter* ot, int n, int32_t* out, hipStream_t s);
 hipError_t launch_bt_lsqr_init_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,

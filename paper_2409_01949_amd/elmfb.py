@@ -145,6 +145,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_autotune": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i32), P]),
         "elmfb_batch_set_tile": (i32, [P, i32, i32]),
+        "elmfb_batch_set_coords": (i32, [P, i32]),
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_batch_destroy": (None, [P]),
         "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
@@ -405,12 +406,17 @@ class Batch:
                                               _stream(stream)))
         return {t: ms[i] for i, t in enumerate((16, 32, 64)) if ms[i] >= 0}, int(ch.value)
 
+    def set_coords(self, preconditioned):
+        """Solve coefficients (x0 and result) as y = R x per block when True."""
+        self._check(_lib.elmfb_batch_set_coords(self.h, 1 if preconditioned else 0))
+
     def set_tile(self, prec, tile):
         self._check(_lib.elmfb_batch_set_tile(self.h, _PREC[prec], int(tile)))
 
     def solve(self, coef, iter_lim=15000, atol=0.0, btol=1e-6, check_every=50, use_graph=True,
-              method="lsqr", precond=False, inner_iters=500, outer_lim=20, stream=None):
+              method="lsqr", precond=False, inner_iters=500, outer_lim=20, x0=None, stream=None):
         o = SolveOpts()
+        o.x0_dev = _ptr(x0)
         o.method = {"lsqr": LSQR, "mixed_ir": MIXED_IR}[method]
         o.iter_lim = int(iter_lim)
         o.check_every = int(check_every)

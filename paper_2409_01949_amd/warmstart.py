@@ -1,0 +1,152 @@
+"""Learned warm start for batched solves of a parameterised problem family.
+
+A tanh MLP (libelmfb's elmfb_mlp: bfloat16 products, FP32 master weights, Adam) is trained on
+coefficient vectors that the batched solver itself produced, and maps the problem parameters
+plus a subdomain's position to that subdomain's K coefficients; its prediction is the x0 of
+later batched solves.  Coefficients are taken in block-Jacobi coordinates y_j = R_j x_j (the
+subdomain's features orthonormalised over its support): there they are of the size of the
+local solution, whereas the raw coefficients of the redundant random features carry large,
+cancelling components that no regression reproduces.  This module only prepares inputs and standardises targets on the host;
+solves, training and inference run in the library.
+
+Family (1D, single level): du/dx = sum_{m=1..3} c_m cos(m omega x / 3) on [-2 pi, 2 pi] with the
+hard constraint tanh(omega x) (u(0) = 0), J subdomains of K features.  The exact solution is
+linear in c, and near a centre mu_j each mode is a combination of sin and cos of its phase
+phi_m = m omega mu_j / 3; per subdomain the network input is
+    [omega / 50, mu_j / L, c_m sin(phi_m), c_m cos(phi_m), sin(phi_m), cos(phi_m) (m = 1..3)],
+L = half the domain length.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from .elmfb import MLP, Batch
+
+N_IN = 14
+
+
+def subdomain_inputs(spec, omega, coeffs):
+    """[J, N_IN] inputs of one instance (single level, 1D) for one coefficient vector."""
+    lo, hi = spec.lo[0], spec.hi[0]
+    J = spec.levels[0][0]
+    mu = lo + (hi - lo) * np.arange(J) / (J - 1) if J > 1 else np.array([(lo + hi) / 2])
+    half = (hi - lo) / 2
+    c = np.asarray(coeffs, dtype=np.float64)
+    X = np.empty((J, N_IN))
+    X[:, 0] = omega / 50.0
+    X[:, 1] = mu / half
+    for m in range(3):
+        ph = (m + 1) * omega * mu / 3.0
+        X[:, 2 + 4 * m] = c[m] * np.sin(ph)
+        X[:, 3 + 4 * m] = c[m] * np.cos(ph)
+        X[:, 4 + 4 * m] = np.sin(ph)
+        X[:, 5 + 4 * m] = np.cos(ph)
+    return X
+
+
+def family_inputs(specs, omegas, C):
+    """Inputs for every (instance, rhs, subdomain), in the coefficient order of a batch solve."""
+    return np.concatenate([subdomain_inputs(s, om, c)
+                           for s, om, Cg in zip(specs, omegas, C) for c in Cg])
+
+
+def coef_blocks(coef, specs, n_rhs):
+    """Batch coefficients (per instance [n_rhs][J K]) as [(instance, rhs, subdomain), K]."""
+    out, o = [], 0
+    for s in specs:
+        n = s.levels[0][0] * s.K
+        out.append(coef[o:o + n_rhs * n].reshape(n_rhs * s.levels[0][0], s.K))
+        o += n_rhs * n
+    return np.concatenate(out)
+
+
+class WarmStart:
+    """MLP from subdomain inputs to standardised coefficient blocks."""
+
+    def __init__(self, K, hidden=512, depth=3, max_batch=4096, seed=0):
+        from inputs import mlp_init
+
+        self.dims = [N_IN] + [hidden] * depth + [K]
+        self.net = MLP(self.dims, max_batch)
+        self.net.set_params(mlp_init(self.dims, seed))
+        self.max_batch = max_batch
+        self.mean = np.zeros(K)
+        self.std = np.ones(K)
+
+    def fit(self, X, Y, epochs, lr=1e-3, seed=0, log=None):
+        """Adam on the mean-squared error of standardised targets; returns the loss history
+        (one value per epoch: the loss of the epoch's last mini-batch)."""
+        import torch
+
+        self.mean = Y.mean(axis=0)
+        self.std = Y.std(axis=0) + 1e-12
+        Z = ((Y - self.mean) / self.std).astype(np.float32)
+        Xf = X.astype(np.float32)
+        rng = np.random.default_rng(seed)
+        hist = []
+        bs = self.max_batch
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            perm = rng.permutation(len(X))
+            xd = torch.as_tensor(Xf[perm]).cuda()
+            zd = torch.as_tensor(Z[perm]).cuda()
+            nb = len(X) // bs
+            loss = None
+            for b in range(nb):
+                last = b == nb - 1
+                loss = self.net.train_step(xd[b * bs:(b + 1) * bs], zd[b * bs:(b + 1) * bs], lr=lr,
+                                           want_loss=last)
+            hist.append(loss)
+            if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+                log(f"epoch {ep}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
+        return hist
+
+    def predict(self, X):
+        import torch
+
+        out = []
+        for o in range(0, len(X), self.max_batch):
+            xd = torch.as_tensor(X[o:o + self.max_batch].astype(np.float32)).cuda()
+            out.append(self.net.forward(xd).cpu().numpy().astype(np.float64))
+        return np.concatenate(out) * self.std + self.mean
+
+    def destroy(self):
+        self.net.destroy()
+
+
+def family_batch(omegas, C, store_prec="fp32"):
+    """Batch of warm-family instances (one per omega, its rows of C as right-hand sides),
+    assembled, with their specs and per-pair ||h||."""
+    import torch
+
+    from inputs import configs, feature_params
+
+    specs = [configs.warm_family_1d(om, Cg[0]) for om, Cg in zip(omegas, C)]
+    feats = [feature_params(s) for s in specs]
+    R = C.shape[1]
+    B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R, store_prec=store_prec)
+    f = np.concatenate([configs.warm_batch_forcing(s, Cg).ravel() for s, Cg in zip(specs, C)])
+    B.assemble(torch.as_tensor(f).cuda())
+    hn = np.concatenate([np.linalg.norm(configs.warm_batch_forcing(s, Cg), axis=1)
+                         / np.sqrt(s.n_rows) for s, Cg in zip(specs, C)])
+    return B, specs, hn
+
+
+def solve_batch(B, x0=None, btol=1e-4, inner=1000, outer=8, shift=1e-12, precondition=True):
+    """Refined block-Jacobi solve of every pair to ||h - M c|| <= btol ||h||, coefficients in
+    block-Jacobi coordinates (x0 and result); returns (coefficients on the host, infos,
+    seconds)."""
+    import torch
+
+    if precondition:
+        B.precondition(shift)
+    B.set_coords(True)
+    coef = torch.empty(B.n_rhs * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = B.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, atol=0.0,
+                    btol=btol, check_every=50, precond=True, x0=x0)
+    torch.cuda.synchronize()
+    return coef.cpu().numpy(), infos, time.perf_counter() - t0

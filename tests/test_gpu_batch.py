@@ -276,3 +276,47 @@ def test_batch_mixed_solve_to_tolerance(batch32):
             else:
                 assert info["istop"] == 7 and info["outer_iters"] == 6
     assert n_conv >= 1
+
+
+def test_batch_warm_start(batch32):
+    """Warm starts: preconditioned LSQR from x0 equals the oracle's preconditioned LSQR from x0
+    after 5 steps (x = x0 + R^{-1} y, y for h - M x0), and refinement from a nearly converged x0
+    stops at once while meeting the same ||h - M c|| <= btol ||h|| target (oracle residual)."""
+    B, oracle = batch32
+    torch = torch_mod()
+    shift = 1e-6
+    B.precondition(shift)
+    rng = np.random.default_rng(21)
+    X0 = [rng.standard_normal((R, len(bl) * s.K)) for s, bl, _ in oracle]
+    x0 = dev(np.concatenate([x.ravel() for x in X0]))
+    coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    B.solve(coef, iter_lim=5, atol=0.0, btol=0.0, check_every=5, precond=True, x0=x0)
+    cs = _coefs(B, coef, oracle)
+    worst = 0.0
+    for i, (s, bl, h) in enumerate(oracle):
+        n = len(bl) * s.K
+        facs = linalg.block_jacobi_factors(bl, shift)
+        for j in range(R):
+            x_ref, _ = linalg.preconditioned_lsqr(
+                lambda v: asm.matvec(bl, v, s.n_rows), lambda u: asm.rmatvec(bl, u, n), bl, facs,
+                h[j], n, x0=X0[i][j], atol=0, btol=0, iter_lim=5)
+            worst = max(worst, np.linalg.norm(cs[i][j] - x_ref) / np.linalg.norm(x_ref))
+    print(f"warm bj-lsqr k=5: worst coefficient rel diff {worst:.2e}")
+    assert worst <= 1e-8
+    # refinement: cold to btol, then warm from the cold result
+    btol = 1e-4
+    cold = B.solve(coef, method="mixed_ir", inner_iters=2000, outer_lim=4, check_every=50,
+                   precond=True, atol=0.0, btol=btol)
+    warm_coef = torch.empty_like(coef)
+    warm = B.solve(warm_coef, method="mixed_ir", inner_iters=2000, outer_lim=4, check_every=50,
+                   precond=True, atol=0.0, btol=btol, x0=coef)
+    cs = _coefs(B, warm_coef, oracle)
+    for i, (s, bl, h) in enumerate(oracle):
+        for j in range(R):
+            c, w = cold[i * R + j], warm[i * R + j]
+            r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j]) / np.linalg.norm(h[j])
+            print(f"instance {i} rhs {j}: cold istop {c['istop']} after {c['iters']}, warm istop "
+                  f"{w['istop']} after {w['iters']}, rel residual {r:.2e}")
+            if c["istop"] == 1:
+                assert w["istop"] == 1 and w["iters"] == 0 and w["outer_iters"] == 0
+                assert r <= btol * (1 + 1e-2)
