@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=20)
     p.add_argument("--batch-n", type=int, default=512)
     p.add_argument("--batch-btol", type=float, default=1e-6)
+    p.add_argument("--epochs", type=int, default=300, help="warm workload: MLP training epochs")
+    p.add_argument("--copy-bytes", type=int, default=0,
+                   help="only run device copies of this many bytes (traffic-counter reference)")
     return p.parse_args()
 
 
@@ -127,7 +130,8 @@ def run_batch(args):
     """The ragged batch: 512 independent 2D Poisson instances (J~U{4..24}^2, K~U{64..128},
     20..60 points per subdomain cell), 8 right-hand sides each, every kernel one launch over the
     batch.  A step is assembly, block-Jacobi factors and the solve of every (instance, rhs) pair
-    until ||h - M c|| <= btol ||h|| or the iteration budget."""
+    until ||h - M c|| <= btol ||h|| (istop 1), least-squares optimality ||M^T r|| <= btol ||M|| ||r||
+    (istop 2; pairs whose features cannot represent the solution) or the iteration budget."""
     import numpy as np
     import torch
 
@@ -160,10 +164,10 @@ def run_batch(args):
         tb = time.perf_counter()
         if mixed:
             inf = B.solve(coef, method="mixed_ir", inner_iters=args.inner,
-                          outer_lim=max(1, args.iters // args.inner), atol=0.0, btol=btol,
+                          outer_lim=max(1, args.iters // args.inner), atol=btol, btol=btol,
                           check_every=args.check_every, precond=precond)
         else:
-            inf = B.solve(coef, iter_lim=args.iters, atol=0.0, btol=btol,
+            inf = B.solve(coef, iter_lim=args.iters, atol=btol, btol=btol,
                           check_every=args.check_every, precond=precond)
         torch.cuda.synchronize()
         return inf, tb - ta, time.perf_counter() - tb
@@ -201,6 +205,7 @@ def run_batch(args):
         "autotune_ms": {p: v[0] for p, v in tune.items()},
         "tiles": {p: v[1] for p, v in tune.items()},
         "pairs_converged": int(np.sum(stops == 1)), "pairs": int(len(stops)),
+        "pairs_ls_optimal": int(np.sum(stops == 2)), "pairs_budget": int(np.sum(stops == 7)),
         "iters_max": int(its.max()), "iters_median": float(np.median(its)),
         "rel_residual_quantiles": {q: float(np.quantile(rel, float(q)))
                                    for q in ("0.5", "0.9", "0.99", "1.0")},
@@ -210,15 +215,128 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_warm(args):
+    """Learned warm start on the 1D parameterised family (omega ~ U[5,50], c ~ N(0,1)^3, J=64,
+    K=32, 6000 points): 4,096 training solves (512 omega x 8 c) by the batched solver, the MLP
+    (3 x 512 tanh, BF16 products) trained on them, then the 1,024 held-out pairs (128 x 8) solved
+    to ||h - M c|| <= btol ||h|| from its prediction.  A step is prediction + warm solve; the cold
+    solve of the same batch is reported beside it."""
+    import numpy as np
+    import torch
+
+    from inputs import configs
+    from paper_2409_01949_amd import warmstart as ws
+
+    def log(m):
+        print("# " + m, file=sys.stderr, flush=True)
+
+    om, C = configs.warm_groups(512, 5)
+    B, specs, _ = ws.family_batch(om, C)
+    coef, infos, t_data = ws.solve_batch(B, btol=args.batch_btol * 0.1, inner=2000, outer=6)
+    X = ws.family_inputs(specs, om, C)
+    Y = ws.coef_blocks(coef, specs, C.shape[1])
+    B.destroy()
+    log(f"training data: {len(X)} samples from {len(infos)} solves in {t_data:.1f} s")
+    W = ws.WarmStart(K=Y.shape[1], max_batch=4096, seed=0)
+    t0 = time.perf_counter()
+    hist = W.fit(X, Y, epochs=args.epochs, lr=1e-3, seed=0, log=log)
+    t_train = time.perf_counter() - t0
+    om2, C2 = configs.warm_groups(128, 6)
+    B2, specs2, hn2 = ws.family_batch(om2, C2)
+    X2 = ws.family_inputs(specs2, om2, C2)
+    btol = args.batch_btol
+    _, cold, t_cold = ws.solve_batch(B2, btol=btol, inner=2000, outer=10)
+
+    def step():
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        x0 = torch.as_tensor(np.ascontiguousarray(W.predict(X2)).reshape(-1)).cuda()
+        _, warm, _ = ws.solve_batch(B2, x0=x0, btol=btol, inner=2000, outer=10,
+                                    precondition=False)
+        torch.cuda.synchronize()
+        return warm, time.perf_counter() - ta
+
+    for _ in range(args.warmup):
+        step()
+    ts = []
+    for _ in range(args.steps):
+        warm, dt = step()
+        ts.append(dt)
+    dt = float(np.mean(ts))
+    itc = np.array([i["iters"] for i in cold])
+    itw = np.array([i["iters"] for i in warm])
+    rows_rhs = B2.sizes["n_rows"] * C2.shape[1]
+    out = {
+        "metric": METRIC, "value": rows_rhs / dt, "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+fp32",
+        "data": "synthetic",
+        "config": {"workload": "warm1d_128x8", "instances": 128, "n_rhs": 8,
+                   "train_solves": len(infos), "rows": B2.sizes["n_rows"],
+                   "cols": B2.sizes["n_phi"], "method": "bj-mixed-ir (fp32 inner), MLP x0",
+                   "btol": btol, "mlp": "14-512-512-512-32 tanh, bf16", "epochs": args.epochs},
+        "warm_s": dt, "cold_s": t_cold, "speedup_vs_cold": t_cold / dt,
+        "iters_mean": {"cold": float(itc.mean()), "warm": float(itw.mean())},
+        "iters_max": {"cold": int(itc.max()), "warm": int(itw.max())},
+        "converged": {"cold": int(sum(i["istop"] == 1 for i in cold)),
+                      "warm": int(sum(i["istop"] == 1 for i in warm)), "pairs": len(cold)},
+        "training": {"data_s": t_data, "train_s": t_train, "loss_first": hist[0],
+                     "loss_last": hist[-1]},
+    }
+    B2.destroy()
+    W.destroy()
+    print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.json: FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
+    the same counters on a plain copy of known size), or None when there is none or the kernel's
+    source changed since the counters were taken (its SHA-256 is recorded there)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        with open(os.path.join(ROOT, d["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != d["source_sha256"]:
+                return None
+        return float(d["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def run_copy(args):
+    """Plain device-to-device copies of a known size (the reference for scaling the HBM traffic
+    counters of the other kernels): prints bytes read and written per copy."""
+    import torch
+
+    n = args.copy_bytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                      "copies": args.steps}), flush=True)
+
+
 def main():
     args = parse()
-    if args.workload.startswith("batch"):
-        run_batch(args)
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the multi-GPU "
                                    "sharding is a design only)"}))
         sys.exit(2)
+    if args.copy_bytes:
+        run_copy(args)
+        return
+    if args.workload.startswith("batch"):
+        run_batch(args)
+        return
+    if args.workload == "warm":
+        run_warm(args)
+        return
     import numpy as np
     import torch
 
@@ -327,7 +445,8 @@ def main():
         "rel_l2_test_vs_exact": rel_test,
         "e_l1_test": e_l1,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"k_rmv_chunks_{kprec}", spec.name),
                      "kernel": f"k_rmv_chunks<{kname}> (x = M^T u, per-chunk pass)",
                      "ms_per_launch": ms_rmv, "algorithmic_bytes_per_launch": rmv_bytes(es),
                      "also": [

@@ -139,7 +139,8 @@ typedef struct {
                               machine precision, 7 iteration limit, 8 rel-L2 target reached */
   int32_t iters;           /* Krylov iterations (MIXED_IR: inner iterations in total)       */
   int32_t outer_iters;     /* MIXED_IR refinement steps                                     */
-  double rnorm;            /* ||h - A x|| (LSQR estimate / CGLS recurrence)                  */
+  double rnorm;            /* ||h - A x|| (LSQR estimate / CGLS recurrence; MIXED_IR: of the
+                              returned coefficients, recomputed with the FP64 matrix)         */
   double arnorm;           /* ||A^T (h - A x)||                                              */
   double anorm;            /* LSQR Frobenius-norm estimate; CGLS: exact ||A||_F              */
   double xnorm;            /* ||x||                                                          */
@@ -286,13 +287,20 @@ elmfb_status elmfb_batch_set_tile(elmfb_batch b, int32_t prec, int32_t tile);
  * solves need precond = 1.  0 (the default) restores x. */
 elmfb_status elmfb_batch_set_coords(elmfb_batch b, int32_t preconditioned);
 
+/* x_dev = R^{-1} y_dev per block (both in the V layout): coefficients from block-Jacobi
+ * coordinates.  Needs elmfb_batch_precondition; overwrites the solver's work vectors. */
+elmfb_status elmfb_batch_from_coords(elmfb_batch b, const double* y_dev, double* x_dev,
+                                     void* stream);
+
 /* Solve every (instance, right-hand side) with its own recurrence and stop tests (Sec. 4.1:
  * LSQR, Paige-Saunders, damp 0; FP64 recurrences).
  *   method ELMFB_LSQR: LSQR on the FP64 matrix with atol, btol, iter_lim;
  *   method ELMFB_MIXED_IR: FP64 refinement c += d with d from inner LSQR on the store_prec copy
  *     (at most inner_iters steps; an inner solve also stops once its residual estimate is half
- *     the outer target), the residual h - M c recomputed with the FP64 matrix after each step;
- *     a pair stops when ||h - M c|| <= btol ||h|| (istop 1) or after outer_lim steps (istop 7).
+ *     the outer target), the residual r = h - M c recomputed with the FP64 matrix after each
+ *     step; a pair stops when ||r|| <= btol ||h|| (istop 1), when atol > 0 and
+ *     ||M^T r|| <= atol ||M|| ||r|| (istop 2, least-squares optimality; FP64 products, ||M|| the
+ *     inner LSQR's estimate) or after outer_lim steps (istop 7).
  * precond = 1 runs on the preconditioned matrix of elmfb_batch_precondition (M R^{-1}, and its
  * low-precision rounding for MIXED_IR) and returns x = R^{-1} y.  After elmfb_batch_precondition
  * an unpreconditioned MIXED_IR solve needs elmfb_batch_assemble again (ELMFB_E_STATE).  No warm start and no check points.  The iteration loop over the

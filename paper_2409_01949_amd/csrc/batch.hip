@@ -629,6 +629,19 @@ elmfb_status elmfb_batch_set_coords(elmfb_batch B, int32_t preconditioned) {
   return ELMFB_OK;
 }
 
+elmfb_status elmfb_batch_from_coords(elmfb_batch B, const double* y_dev, double* x_dev,
+                                     void* stream) {
+  if (!B || !y_dev || !x_dev) return bfail(B, ELMFB_E_INVALID, "NULL argument");
+  if (!B->bj_ready) return bfail(B, ELMFB_E_STATE, "no block-Jacobi factors");
+  hipStream_t s = (hipStream_t)stream;
+  const int R = B->R;
+  BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, y_dev, B->d_w, 1, 1, s));
+  BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, (int64_t)B->blocks.size(), B->d_rc,
+                               B->d_foff, R, B->d_w, nullptr, B->d_v, s));
+  BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, B->d_v, x_dev, 0, 1, s));
+  return ELMFB_OK;
+}
+
 elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, double* coef_dev,
                                elmfb_solve_info* info, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -699,11 +712,11 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   } else {
     // FP64 refinement: r = rhs - A c, inner LSQR on the stored low-precision copy, c += d
     const int lo = B->lo_prec;
-    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_h, 1,
-                                  opts->btol, opts->outer_lim, s));
+    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_h, nullptr,
+                                  0.0, 1, opts->btol, opts->outer_lim, s));
     if (warm)   // the residual of x0 (in d_red_r) may already meet the target
-      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 2,
-                                    opts->btol, opts->outer_lim, s));
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r,
+                                    nullptr, 0.0, 2, opts->btol, opts->outer_lim, s));
     BHIP(B, hipMemsetAsync(B->d_c, 0, (size_t)(B->n_phi * R * 8), s));
     for (;;) {
       int32_t active = 0;
@@ -717,8 +730,15 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
       // c += d (c in preconditioned coordinates with block-Jacobi)
       BHIP(B, launch_bt_axpy(B->n_phi * R, B->d_x, B->d_c, s));
       BHIP(B, bt_residual(B, B->d_c, bj, s, rhs));
-      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, 0,
-                                    opts->btol, opts->outer_lim, s));
+      const double* red_a = nullptr;
+      if (opts->atol > 0.0) {   // ||A^T r|| per block with the FP64 matrix (v is free here)
+        BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], B->d_geos, B->d_insts, B->d_blocks, nb,
+                               matrix_of(B, ELMFB_FP64, bj), B->d_u, R, nullptr, COL_STORE_SQ,
+                               B->d_v, B->d_red_c, s));
+        red_a = B->d_red_c;
+      }
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, red_a,
+                                    opts->atol, 0, opts->btol, opts->outer_lim, s));
     }
   }
   const double* fin = B->d_c;

@@ -582,11 +582,14 @@ __global__ void k_bt_lsqr_init(SolveState* st, const InstInfo* __restrict__ inst
 // Outer FP64 residual check of a refined solve from the row partials of the current residual.
 // mode 1: the partials are those of h; record ||h|| (fresh state).  mode 2: the residual of a
 // warm start; no step is counted.  mode 0: after a refinement step, whose inner iterations are
-// added.  A pair stops once ||h - M c|| <= btol ||h|| or after outer_lim steps.
+// added.  A pair stops once ||h - M c|| <= btol ||h|| (istop 1), once ||A^T r|| <= atol ||A|| ||r||
+// (istop 2: least-squares optimality; red_a holds the per-block partials of ||A^T r||^2 and ||A||
+// is the inner LSQR's estimate), or after outer_lim steps (istop 7).
 __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
                                  const InstInfo* __restrict__ insts, int n_inst, int R,
-                                 const double* __restrict__ red_r, int mode, double btol,
-                                 int outer_lim) {
+                                 const double* __restrict__ red_r,
+                                 const double* __restrict__ red_a, double atol, int mode,
+                                 double btol, int outer_lim) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_inst * R) return;
   const InstInfo I = insts[idx / R];
@@ -607,6 +610,11 @@ __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
     } else if (rn <= o.btol * o.hnorm) {
       o.done = 1;
       o.istop = 1;
+    } else if (mode == 0 && red_a && atol > 0.0 &&
+               sqrt(seg_sum(red_a, I.b0, I.b1, idx - (idx / R) * R)) <=
+                   atol * st[idx].anorm * rn) {
+      o.done = 1;
+      o.istop = 2;
     } else if (o.outer >= outer_lim) {
       o.done = 1;
       o.istop = 7;
@@ -910,10 +918,11 @@ hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst
   return hipGetLastError();
 }
 hipError_t launch_bt_outer_check(BtOuter* ot, const SolveState* st, const InstInfo* insts,
-                                 int n_inst, int R, const double* red_r, int first, double btol,
-                                 int outer_lim, hipStream_t s) {
+                                 int n_inst, int R, const double* red_r, const double* red_a,
+                                 double atol, int mode, double btol, int outer_lim,
+                                 hipStream_t s) {
   hipLaunchKernelGGL(k_bt_outer_check, pairs_grid(n_inst * R), dim3(256), 0, s, ot, st, insts,
-                     n_inst, R, red_r, first, btol, outer_lim);
+                     n_inst, R, red_r, red_a, atol, mode, btol, outer_lim);
   return hipGetLastError();
 }
 hipError_t launch_bt_count_outer(const BtOuter* ot, int n, int32_t* out, hipStream_t s) {

@@ -138,8 +138,9 @@ hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst
                                const double* red_b, const double* red_u, double atol, double btol,
                                int iter_lim, const BtOuter* ot, double inner_rel, hipStream_t s);
 hipError_t launch_bt_outer_check(BtOuter* ot, const SolveState* st, const InstInfo* insts,
-                                 int n_inst, int R, const double* red_r, int mode, double btol,
-                                 int outer_lim, hipStream_t s);
+                                 int n_inst, int R, const double* red_r, const double* red_a,
+                                 double atol, int mode, double btol, int outer_lim,
+                                 hipStream_t s);
 hipError_t launch_bt_count_outer(const BtOuter* ot, int n, int32_t* out, hipStream_t s);
 hipError_t launch_bt_lsqr_init_alpha(SolveState* st, const InstInfo* insts, int n_inst, int R,
                                      const double* red, hipStream_t s);

@@ -499,11 +499,8 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
           HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_c, g.n_phi, s));
         if (opts->n_check > 0) HIP_OR_FAIL(h, check_solution(h, opts, h->d_c, s));
       }
-      double rr = 0.0;
       HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
-      HIP_OR_FAIL(h, hipMemcpyAsync(&rr, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
       HIP_OR_FAIL(h, hipStreamSynchronize(s));
-      outer_rnorm = std::sqrt(rr);
       total_iters += st.itn;
       if (st.target_hit) {
         istop = 8;
@@ -513,6 +510,17 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
     }
     st.istop = istop;
     result = h->d_c;
+    // the residual of the returned coefficients, in FP64
+    HIP_OR_FAIL(h, launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles,
+                                    (int64_t)h->tiles.size(), h->d_A, h->d_c, nullptr,
+                                    h->d_tpart, nullptr, s));
+    HIP_OR_FAIL(h, launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_r,
+                                      h->d_h, nullptr, red_slot(h, 3), rw, s));
+    HIP_OR_FAIL(h, launch_reduce_to(red_slot(h, 3), rw, h->d_scalar, s));
+    double rr = 0.0;
+    HIP_OR_FAIL(h, hipMemcpyAsync(&rr, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(h, hipStreamSynchronize(s));
+    outer_rnorm = std::sqrt(rr);
   }
   HIP_OR_FAIL(h, hipMemcpyAsync(coef_dev, result, (size_t)g.n_phi * 8, hipMemcpyDeviceToDevice, s));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_out, s));

@@ -146,6 +146,7 @@ def load_library(path: Optional[str] = None):
                                        ctypes.POINTER(i32), P]),
         "elmfb_batch_set_tile": (i32, [P, i32, i32]),
         "elmfb_batch_set_coords": (i32, [P, i32]),
+        "elmfb_batch_from_coords": (i32, [P, P, P, P]),
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_batch_destroy": (None, [P]),
         "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
@@ -409,6 +410,10 @@ class Batch:
     def set_coords(self, preconditioned):
         """Solve coefficients (x0 and result) as y = R x per block when True."""
         self._check(_lib.elmfb_batch_set_coords(self.h, 1 if preconditioned else 0))
+
+    def from_coords(self, y, x, stream=None):
+        """x = R^{-1} y per block (V layout)."""
+        self._check(_lib.elmfb_batch_from_coords(self.h, _ptr(y), _ptr(x), _stream(stream)))
 
     def set_tile(self, prec, tile):
         self._check(_lib.elmfb_batch_set_tile(self.h, _PREC[prec], int(tile)))

@@ -19,11 +19,11 @@ N_SAMPLE = 1500
 
 @pytest.fixture(scope="module", params=["poisson3l", "poisson5l"])
 def full(request):
-    from paper_2409_01949_amd import define_problem
+    from paper_2409_01949_amd import Problem
     spec = getattr(configs, request.param)()
     W, b = feature_params(spec)
     print(f"# {spec.name}: define + assemble", flush=True)
-    P = define_problem(spec, W, b, store_prec="fp32")
+    P = Problem.from_spec(spec, W, b, "fp32")
     f = configs.forcing(spec)
     P.assemble(dev(f))
     N = spec.n_rows
