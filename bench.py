@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=20)
     p.add_argument("--batch-n", type=int, default=512)
     p.add_argument("--batch-btol", type=float, default=1e-6)
-    p.add_argument("--epochs", type=int, default=300, help="warm workload: MLP training epochs")
+    p.add_argument("--epochs", type=int, default=100, help="warm workload: MLP training epochs")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run device copies of this many bytes (traffic-counter reference)")
     return p.parse_args()
@@ -233,24 +233,24 @@ def run_warm(args):
     om, C = configs.warm_groups(512, 5)
     B, specs, _ = ws.family_batch(om, C)
     coef, infos, t_data = ws.solve_batch(B, btol=args.batch_btol * 0.1, inner=2000, outer=6)
-    X = ws.family_inputs(specs, om, C)
+    X, F = ws.family_inputs(specs, om, C)
     Y = ws.coef_blocks(coef, specs, C.shape[1])
     B.destroy()
     log(f"training data: {len(X)} samples from {len(infos)} solves in {t_data:.1f} s")
-    W = ws.WarmStart(K=Y.shape[1], max_batch=4096, seed=0)
+    W = ws.WarmStart(n_in=X.shape[1], K=Y.shape[1], max_batch=4096, seed=0)
     t0 = time.perf_counter()
-    hist = W.fit(X, Y, epochs=args.epochs, lr=1e-3, seed=0, log=log)
+    hist = W.fit(X, F, Y, epochs=args.epochs, lr=1e-3, seed=0, log=log)
     t_train = time.perf_counter() - t0
     om2, C2 = configs.warm_groups(128, 6)
     B2, specs2, hn2 = ws.family_batch(om2, C2)
-    X2 = ws.family_inputs(specs2, om2, C2)
+    X2, F2 = ws.family_inputs(specs2, om2, C2)
     btol = args.batch_btol
     _, cold, t_cold = ws.solve_batch(B2, btol=btol, inner=2000, outer=10)
 
     def step():
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        x0 = torch.as_tensor(np.ascontiguousarray(W.predict(X2)).reshape(-1)).cuda()
+        x0 = torch.as_tensor(np.ascontiguousarray(W.predict(X2, F2)).reshape(-1)).cuda()
         _, warm, _ = ws.solve_batch(B2, x0=x0, btol=btol, inner=2000, outer=10,
                                     precondition=False)
         torch.cuda.synchronize()
@@ -274,7 +274,8 @@ def run_warm(args):
         "config": {"workload": "warm1d_128x8", "instances": 128, "n_rhs": 8,
                    "train_solves": len(infos), "rows": B2.sizes["n_rows"],
                    "cols": B2.sizes["n_phi"], "method": "bj-mixed-ir (fp32 inner), MLP x0",
-                   "btol": btol, "mlp": "14-512-512-512-32 tanh, bf16", "epochs": args.epochs},
+                   "btol": btol, "epochs": args.epochs,
+                   "mlp": "65-512-512-512-192 tanh, bf16, output modulated by 6 weights"},
         "warm_s": dt, "cold_s": t_cold, "speedup_vs_cold": t_cold / dt,
         "iters_mean": {"cold": float(itc.mean()), "warm": float(itw.mean())},
         "iters_max": {"cold": int(itc.max()), "warm": int(itw.max())},

@@ -330,25 +330,30 @@ typedef struct {
   double lr, beta1, beta2, eps;   /* Adam (Kingma & Ba 2015); lr > 0, betas in [0,1), eps > 0 */
 } elmfb_adam;
 
-/* dims_host [n_layers+1] (1..65536 each), n_layers 1..16, max_batch 1..2^24.  Parameters start
- * at zero; set them with elmfb_mlp_set_params. */
-elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t max_batch,
-                              elmfb_mlp* out);
+/* dims_host [n_layers+1] (1..65536 each), n_layers 1..16, max_batch 1..2^24.  n_mod = 1: the model
+ * output is the last layer z.  n_mod > 1 (dividing dims[n_layers] = n_mod K): the output is
+ * modulated by per-sample weights f [batch][n_mod], y[k] = sum_i f_i z[i K + k] (a model linear in
+ * f, for targets that are linear in some problem parameters).  Parameters start at zero; set them
+ * with elmfb_mlp_set_params. */
+elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t n_mod,
+                              int32_t max_batch, elmfb_mlp* out);
 elmfb_status elmfb_mlp_query(elmfb_mlp m, int64_t* n_params_host);
 /* Copy the flat parameters in (also resets the Adam moments and step count) or out. */
 elmfb_status elmfb_mlp_set_params(elmfb_mlp m, const float* params_host);
 elmfb_status elmfb_mlp_get_params(elmfb_mlp m, float* params_host);
 /* Gradient of the last elmfb_mlp_train_step, same layout as the parameters. */
 elmfb_status elmfb_mlp_get_grads(elmfb_mlp m, float* grads_host);
-/* y_dev [batch][dims[n_layers]] = network(x_dev [batch][dims[0]]), 1 <= batch <= max_batch. */
-elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, int32_t batch, float* y_dev,
-                               void* stream);
-/* Loss = mean over the batch and outputs of (y - t)^2; gradient by back-propagation; then one
- * Adam step when opt is not NULL (opt NULL: gradient only).  loss_host (may be NULL; then the
- * call does not synchronise) receives the loss before the step. */
-elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* t_dev,
-                                  int32_t batch, const elmfb_adam* opt, double* loss_host,
-                                  void* stream);
+/* y_dev [batch][K] = model(x_dev [batch][dims[0]], f_dev [batch][n_mod]) (f_dev ignored and may
+ * be NULL when n_mod = 1; K = dims[n_layers] / n_mod), 1 <= batch <= max_batch. */
+elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, const float* f_dev,
+                               int32_t batch, float* y_dev, void* stream);
+/* Loss = mean over the batch and the K outputs of (y - t)^2, t_dev [batch][K]; gradient by
+ * back-propagation; then one Adam step when opt is not NULL (opt NULL: gradient only).
+ * loss_host (may be NULL; then the call does not synchronise) receives the loss before the
+ * step. */
+elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* f_dev,
+                                  const float* t_dev, int32_t batch, const elmfb_adam* opt,
+                                  double* loss_host, void* stream);
 void elmfb_mlp_destroy(elmfb_mlp m);
 const char* elmfb_mlp_last_error(elmfb_mlp m);
 

@@ -6,6 +6,8 @@ mean-squared error and Adam (Kingma & Ba 2015) with the method's learning rate 1
 Test infrastructure only: nothing in the library imports this module.
 
 Layers l = 1..L:  z_l = a_{l-1} W_l^T + b_l,  a_l = tanh(z_l) (hidden), y = z_L (output);
+optionally modulated: with per-sample weights f [batch, n_mod] the last layer has n_mod K outputs
+and the model output is y[k] = sum_i f_i z_L[i K + k] (a network whose output is linear in f);
 W_l [n_l, n_{l-1}], row-major samples [batch, features].  Loss = mean over batch and outputs of
 (y - t)^2.  Arithmetic is float64.  With bf16=True the operands of every product are rounded to
 bfloat16 (round to nearest even) where a low-precision implementation stores them: the input,
@@ -43,17 +45,31 @@ def forward(params: Params, X: np.ndarray, bf16=False):
     return y, acts
 
 
+def modulate(z: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """y[b, k] = sum_i f[b, i] z[b, i K + k]."""
+    B, n_mod = f.shape
+    K = z.shape[1] // n_mod
+    return np.einsum("bi,bik->bk", f, z.reshape(B, n_mod, K))
+
+
+def demodulate_grad(dy: np.ndarray, f: np.ndarray, bf16=False) -> np.ndarray:
+    """dL/dz for y = modulate(z, f): dz[b, i K + k] = f[b, i] dy[b, k] (rounded like g_L)."""
+    g = (f[:, :, None] * dy[:, None, :]).reshape(dy.shape[0], -1)
+    return _r(g, bf16)
+
+
 def mse(y: np.ndarray, t: np.ndarray):
     """(loss, dL/dy)."""
     d = y - t
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
-def backward(params: Params, acts, dy: np.ndarray, bf16=False):
-    """Gradients [(dW_l, db_l)] of the loss whose output gradient is dy."""
+def backward(params: Params, acts, dy: np.ndarray, bf16=False, f=None):
+    """Gradients [(dW_l, db_l)] of the loss whose output gradient is dy (of the modulated
+    output when f is given)."""
     L = len(params)
     grads = [None] * L
-    g = _r(dy, bf16)
+    g = demodulate_grad(dy, f, bf16) if f is not None else _r(dy, bf16)
     for l in range(L - 1, -1, -1):
         W, _ = params[l]
         grads[l] = (g.T @ acts[l], g.sum(axis=0))

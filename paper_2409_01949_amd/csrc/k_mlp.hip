@@ -123,6 +123,45 @@ __global__ void __launch_bounds__(256) k_mlp_loss(int64_t n, const float* __rest
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Modulated output y[b][k] = sum_i f[b][i] z[b][i K + k] (FP32).
+__global__ void k_mlp_modulate(int64_t n, int K, int n_mod, const float* __restrict__ z,
+                               const float* __restrict__ f, float* __restrict__ y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / K;
+    const int k = (int)(e - b * K);
+    float s = 0.0f;
+    for (int i = 0; i < n_mod; ++i) s += f[b * n_mod + i] * z[(b * n_mod + i) * K + k];
+    y[e] = s;
+  }
+}
+
+// Loss of the modulated output: d = y - t, g = 2 d / n, gz[b][i K + k] = bf16(f[b][i] g);
+// per-workgroup partial sums of d^2 in FP64.
+__global__ void __launch_bounds__(256) k_mlp_mod_loss(int64_t n, int K, int n_mod,
+                                                      const float* __restrict__ z,
+                                                      const float* __restrict__ f,
+                                                      const float* __restrict__ t,
+                                                      uint16_t* __restrict__ gz,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const float sc = 2.0f / (float)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / K;
+    const int k = (int)(e - b * K);
+    float y = 0.0f;
+    for (int i = 0; i < n_mod; ++i) y += f[b * n_mod + i] * z[(b * n_mod + i) * K + k];
+    const float d = y - t[e];
+    const float g = sc * d;
+    for (int i = 0; i < n_mod; ++i) gz[(b * n_mod + i) * K + k] = f32_to_bf16(f[b * n_mod + i] * g);
+    acc += (double)d * (double)d;
+  }
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 __global__ void k_mlp_sum(int n, const double* __restrict__ part, double scale,
                           double* __restrict__ out) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -178,6 +217,19 @@ hipError_t launch_mlp_loss(int64_t n, const float* y, const float* t, uint16_t* 
                            int n_part, double* loss, hipStream_t s) {
   const unsigned nb = (unsigned)std::min<int64_t>(n_part, std::max<int64_t>(1, (n + 255) / 256));
   hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(256), 0, s, n, y, t, g, part);
+  hipLaunchKernelGGL(k_mlp_sum, dim3(1), dim3(64), 0, s, (int)nb, part, 1.0 / (double)n, loss);
+  return hipGetLastError();
+}
+hipError_t launch_mlp_modulate(int64_t n, int K, int n_mod, const float* z, const float* f,
+                               float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_modulate, dim3(flat_grid(n)), dim3(256), 0, s, n, K, n_mod, z, f, y);
+  return hipGetLastError();
+}
+hipError_t launch_mlp_mod_loss(int64_t n, int K, int n_mod, const float* z, const float* f,
+                               const float* t, uint16_t* gz, double* part, int n_part,
+                               double* loss, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<int64_t>(n_part, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_mlp_mod_loss, dim3(nb), dim3(256), 0, s, n, K, n_mod, z, f, t, gz, part);
   hipLaunchKernelGGL(k_mlp_sum, dim3(1), dim3(64), 0, s, (int)nb, part, 1.0 / (double)n, loss);
   return hipGetLastError();
 }

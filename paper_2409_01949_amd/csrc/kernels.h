@@ -178,6 +178,11 @@ hipError_t launch_mlp_to_bf16(int64_t n, const float* x, uint16_t* y, hipStream_
 hipError_t launch_mlp_loss(int64_t n, const float* y, const float* t, uint16_t* g, double* part,
                            int n_part, double* loss, hipStream_t s);
 hipError_t launch_mlp_colsum(int M, int N, const uint16_t* g, float* db, hipStream_t s);
+hipError_t launch_mlp_modulate(int64_t n, int K, int n_mod, const float* z, const float* f,
+                               float* y, hipStream_t s);
+hipError_t launch_mlp_mod_loss(int64_t n, int K, int n_mod, const float* z, const float* f,
+                               const float* t, uint16_t* gz, double* part, int n_part,
+                               double* loss, hipStream_t s);
 hipError_t launch_mlp_adam(int64_t n, float* prm, const float* grad, float* m1, float* m2,
                            uint16_t* pb, float lr, float b1, float b2, float eps, float c1,
                            float c2, hipStream_t s);

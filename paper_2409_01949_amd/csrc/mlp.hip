@@ -17,7 +17,7 @@ using namespace elmfb;
 static thread_local std::string g_mlp_error;
 
 struct elmfb_mlp_s {
-  int L = 0, max_batch = 0, max_dim = 0;
+  int L = 0, max_batch = 0, max_dim = 0, n_mod = 1;
   std::vector<int> dims;
   std::vector<int64_t> offW, offb;
   int64_t n_params = 0;
@@ -101,8 +101,8 @@ hipError_t run_forward(elmfb_mlp m, const float* x, int batch, float* y, hipStre
 
 extern "C" {
 
-elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t max_batch,
-                              elmfb_mlp* out) {
+elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t n_mod,
+                              int32_t max_batch, elmfb_mlp* out) {
   if (!out || !dims_host) return mfail(nullptr, ELMFB_E_INVALID, "NULL argument");
   *out = nullptr;
   if (n_layers < 1 || n_layers > 16) return mfail(nullptr, ELMFB_E_INVALID, "n_layers must be in 1..16");
@@ -111,12 +111,15 @@ elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_
   for (int l = 0; l <= n_layers; ++l)
     if (dims_host[l] < 1 || dims_host[l] > 65536)
       return mfail(nullptr, ELMFB_E_INVALID, "layer widths must be in 1..65536");
+  if (n_mod < 1 || n_mod > 64 || dims_host[n_layers] % n_mod != 0)
+    return mfail(nullptr, ELMFB_E_INVALID, "n_mod must be in 1..64 and divide the output width");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return mfail(nullptr, ELMFB_E_DEVICE, "no HIP device available");
   elmfb_mlp m = new (std::nothrow) elmfb_mlp_s();
   if (!m) return mfail(nullptr, ELMFB_E_NOMEM, "host allocation failed");
   m->L = n_layers;
+  m->n_mod = n_mod;
   m->max_batch = max_batch;
   m->dims.assign(dims_host, dims_host + n_layers + 1);
   int64_t o = 0;
@@ -193,18 +196,27 @@ elmfb_status elmfb_mlp_get_grads(elmfb_mlp m, float* grads_host) {
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, int32_t batch, float* y_dev,
-                               void* stream) {
+elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, const float* f_dev,
+                               int32_t batch, float* y_dev, void* stream) {
   if (!m || !x_dev || !y_dev) return mfail(m, ELMFB_E_INVALID, "NULL argument");
+  if (m->n_mod > 1 && !f_dev) return mfail(m, ELMFB_E_INVALID, "modulated network needs f");
   if (batch < 1 || batch > m->max_batch) return mfail(m, ELMFB_E_INVALID, "batch out of range");
-  MHIP(m, run_forward(m, x_dev, batch, y_dev, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  if (m->n_mod == 1) {
+    MHIP(m, run_forward(m, x_dev, batch, y_dev, s));
+  } else {
+    const int K = m->dims[m->L] / m->n_mod;
+    MHIP(m, run_forward(m, x_dev, batch, m->d_y, s));
+    MHIP(m, launch_mlp_modulate((int64_t)batch * K, K, m->n_mod, m->d_y, f_dev, y_dev, s));
+  }
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* t_dev,
-                                  int32_t batch, const elmfb_adam* opt, double* loss_host,
-                                  void* stream) {
+elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* f_dev,
+                                  const float* t_dev, int32_t batch, const elmfb_adam* opt,
+                                  double* loss_host, void* stream) {
   if (!m || !x_dev || !t_dev) return mfail(m, ELMFB_E_INVALID, "NULL argument");
+  if (m->n_mod > 1 && !f_dev) return mfail(m, ELMFB_E_INVALID, "modulated network needs f");
   if (batch < 1 || batch > m->max_batch) return mfail(m, ELMFB_E_INVALID, "batch out of range");
   if (opt && !(opt->lr > 0.0 && opt->beta1 >= 0.0 && opt->beta1 < 1.0 && opt->beta2 >= 0.0 &&
                opt->beta2 < 1.0 && opt->eps > 0.0))
@@ -212,8 +224,14 @@ elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* 
   hipStream_t s = (hipStream_t)stream;
   const int L = m->L;
   MHIP(m, run_forward(m, x_dev, batch, m->d_y, s));
-  MHIP(m, launch_mlp_loss((int64_t)batch * m->dims[L], m->d_y, t_dev, m->d_g1, m->d_part,
-                          kLossParts, m->d_loss, s));
+  if (m->n_mod == 1) {
+    MHIP(m, launch_mlp_loss((int64_t)batch * m->dims[L], m->d_y, t_dev, m->d_g1, m->d_part,
+                            kLossParts, m->d_loss, s));
+  } else {
+    const int K = m->dims[L] / m->n_mod;
+    MHIP(m, launch_mlp_mod_loss((int64_t)batch * K, K, m->n_mod, m->d_y, f_dev, t_dev, m->d_g1,
+                                m->d_part, kLossParts, m->d_loss, s));
+  }
   uint16_t* g = m->d_g1;
   uint16_t* g_next = m->d_g2;
   for (int l = L - 1; l >= 0; --l) {

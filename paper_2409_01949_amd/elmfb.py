@@ -150,13 +150,14 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_batch_destroy": (None, [P]),
         "elmfb_batch_last_error": (ctypes.c_char_p, [P]),
-        "elmfb_mlp_create": (i32, [i32, ctypes.POINTER(i32), i32, ctypes.POINTER(P)]),
+        "elmfb_mlp_create": (i32, [i32, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(P)]),
         "elmfb_mlp_query": (i32, [P, ctypes.POINTER(i64)]),
         "elmfb_mlp_set_params": (i32, [P, P]),
         "elmfb_mlp_get_params": (i32, [P, P]),
         "elmfb_mlp_get_grads": (i32, [P, P]),
-        "elmfb_mlp_forward": (i32, [P, P, i32, P, P]),
-        "elmfb_mlp_train_step": (i32, [P, P, P, i32, ctypes.POINTER(Adam), ctypes.POINTER(dbl), P]),
+        "elmfb_mlp_forward": (i32, [P, P, P, i32, P, P]),
+        "elmfb_mlp_train_step": (i32, [P, P, P, P, i32, ctypes.POINTER(Adam), ctypes.POINTER(dbl),
+                                       P]),
         "elmfb_mlp_destroy": (None, [P]),
         "elmfb_mlp_last_error": (ctypes.c_char_p, [P]),
         "elmfb_destroy": (None, [P]),
@@ -449,17 +450,20 @@ class Batch:
 
 
 class MLP:
-    """Owns one elmfb_mlp handle (tanh network, bfloat16 products, FP32 master weights)."""
+    """Owns one elmfb_mlp handle (tanh network, bfloat16 products, FP32 master weights); with
+    n_mod > 1 the output is modulated by per-sample weights f: y[k] = sum_i f_i z[i K + k]."""
 
-    def __init__(self, dims, max_batch):
+    def __init__(self, dims, max_batch, n_mod=1):
         lib = load_library()
         d = (ctypes.c_int32 * len(dims))(*[int(v) for v in dims])
         h = ctypes.c_void_p()
-        code = lib.elmfb_mlp_create(len(dims) - 1, d, int(max_batch), ctypes.byref(h))
+        code = lib.elmfb_mlp_create(len(dims) - 1, d, int(n_mod), int(max_batch), ctypes.byref(h))
         if code != OK:
             raise ElmfbError(code, (lib.elmfb_mlp_last_error(None) or b"").decode())
         self.h = h
         self.dims = list(dims)
+        self.n_mod = int(n_mod)
+        self.n_out = self.dims[-1] // self.n_mod
         self.max_batch = int(max_batch)
         n = ctypes.c_int64(0)
         self._check(lib.elmfb_mlp_query(self.h, ctypes.byref(n)))
@@ -485,19 +489,19 @@ class MLP:
         self._check(_lib.elmfb_mlp_get_grads(self.h, v.ctypes.data))
         return v
 
-    def forward(self, x, y=None, stream=None):
+    def forward(self, x, f=None, y=None, stream=None):
         import torch
         if y is None:
-            y = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
-        self._check(_lib.elmfb_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y),
+            y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        self._check(_lib.elmfb_mlp_forward(self.h, _ptr(x), _ptr(f), int(x.shape[0]), _ptr(y),
                                            _stream(stream)))
         return y
 
-    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, update=True,
+    def train_step(self, x, t, f=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, update=True,
                    want_loss=True, stream=None):
         opt = Adam(lr, beta1, beta2, eps)
         loss = ctypes.c_double(0.0)
-        self._check(_lib.elmfb_mlp_train_step(self.h, _ptr(x), _ptr(t), int(x.shape[0]),
+        self._check(_lib.elmfb_mlp_train_step(self.h, _ptr(x), _ptr(f), _ptr(t), int(x.shape[0]),
                                               ctypes.byref(opt) if update else None,
                                               ctypes.byref(loss) if want_loss else None,
                                               _stream(stream)))

@@ -10,11 +10,13 @@ cancelling components that no regression reproduces.  This module only prepares 
 solves, training and inference run in the library.
 
 Family (1D, single level): du/dx = sum_{m=1..3} c_m cos(m omega x / 3) on [-2 pi, 2 pi] with the
-hard constraint tanh(omega x) (u(0) = 0), J subdomains of K features.  The exact solution is
-linear in c, and near a centre mu_j each mode is a combination of sin and cos of its phase
-phi_m = m omega mu_j / 3; per subdomain the network input is
-    [omega / 50, mu_j / L, c_m sin(phi_m), c_m cos(phi_m), sin(phi_m), cos(phi_m) (m = 1..3)],
-L = half the domain length.
+hard constraint tanh(omega x) (u(0) = 0), J subdomains of K features.  The solution is linear in
+c, and near a centre mu_j each mode is a combination of sin and cos of its phase
+phi_m = m omega mu_j / 3.  The model uses that structure: the network maps (omega / 50, one-hot
+subdomain index) to six K-vectors G_i, and the prediction is sum_i f_i G_i with the per-sample
+weights f = (c_m sin phi_m, c_m cos phi_m), m = 1..3 (the library's modulated MLP output).  The
+subdomains have their own random features, so each needs its own function of omega: the one-hot
+index lets the first layer hold them.
 """
 from __future__ import annotations
 
@@ -24,32 +26,29 @@ import numpy as np
 
 from .elmfb import MLP, Batch
 
-N_IN = 14
+N_MOD = 6
 
 
 def subdomain_inputs(spec, omega, coeffs):
-    """[J, N_IN] inputs of one instance (single level, 1D) for one coefficient vector."""
+    """Network inputs [J, 1 + J] and modulation weights [J, N_MOD] of one instance (single
+    level, 1D) for one coefficient vector."""
     lo, hi = spec.lo[0], spec.hi[0]
     J = spec.levels[0][0]
     mu = lo + (hi - lo) * np.arange(J) / (J - 1) if J > 1 else np.array([(lo + hi) / 2])
-    half = (hi - lo) / 2
     c = np.asarray(coeffs, dtype=np.float64)
-    X = np.empty((J, N_IN))
-    X[:, 0] = omega / 50.0
-    X[:, 1] = mu / half
+    X = np.concatenate([np.full((J, 1), omega / 50.0), np.eye(J)], axis=1)
+    F = np.empty((J, N_MOD))
     for m in range(3):
         ph = (m + 1) * omega * mu / 3.0
-        X[:, 2 + 4 * m] = c[m] * np.sin(ph)
-        X[:, 3 + 4 * m] = c[m] * np.cos(ph)
-        X[:, 4 + 4 * m] = np.sin(ph)
-        X[:, 5 + 4 * m] = np.cos(ph)
-    return X
+        F[:, 2 * m] = c[m] * np.sin(ph)
+        F[:, 2 * m + 1] = c[m] * np.cos(ph)
+    return X, F
 
 
 def family_inputs(specs, omegas, C):
-    """Inputs for every (instance, rhs, subdomain), in the coefficient order of a batch solve."""
-    return np.concatenate([subdomain_inputs(s, om, c)
-                           for s, om, Cg in zip(specs, omegas, C) for c in Cg])
+    """(X, F) for every (instance, rhs, subdomain), in the coefficient order of a batch solve."""
+    parts = [subdomain_inputs(s, om, c) for s, om, Cg in zip(specs, omegas, C) for c in Cg]
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
 
 def coef_blocks(coef, specs, n_rhs):
@@ -63,54 +62,53 @@ def coef_blocks(coef, specs, n_rhs):
 
 
 class WarmStart:
-    """MLP from subdomain inputs to standardised coefficient blocks."""
+    """Modulated MLP from subdomain inputs to coefficient blocks (targets scaled per column)."""
 
-    def __init__(self, K, hidden=512, depth=3, max_batch=4096, seed=0):
+    def __init__(self, n_in, K, hidden=512, depth=3, max_batch=4096, seed=0):
         from inputs import mlp_init
 
-        self.dims = [N_IN] + [hidden] * depth + [K]
-        self.net = MLP(self.dims, max_batch)
+        self.dims = [n_in] + [hidden] * depth + [N_MOD * K]
+        self.net = MLP(self.dims, max_batch, n_mod=N_MOD)
         self.net.set_params(mlp_init(self.dims, seed))
         self.max_batch = max_batch
-        self.mean = np.zeros(K)
-        self.std = np.ones(K)
+        self.scale = np.ones(K)
 
-    def fit(self, X, Y, epochs, lr=1e-3, seed=0, log=None):
-        """Adam on the mean-squared error of standardised targets; returns the loss history
-        (one value per epoch: the loss of the epoch's last mini-batch)."""
+    def fit(self, X, F, Y, epochs, lr=1e-3, seed=0, log=None):
+        """Adam on the mean-squared error of the scaled targets (scaling only, so the model stays
+        linear in F); returns the loss history (the last mini-batch's loss of every epoch)."""
         import torch
 
-        self.mean = Y.mean(axis=0)
-        self.std = Y.std(axis=0) + 1e-12
-        Z = ((Y - self.mean) / self.std).astype(np.float32)
-        Xf = X.astype(np.float32)
+        self.scale = Y.std(axis=0) + 1e-12
+        T = (Y / self.scale).astype(np.float32)
+        Xf, Ff = X.astype(np.float32), F.astype(np.float32)
         rng = np.random.default_rng(seed)
         hist = []
-        bs = self.max_batch
+        bs = min(self.max_batch, len(X))
         t0 = time.perf_counter()
         for ep in range(epochs):
             perm = rng.permutation(len(X))
             xd = torch.as_tensor(Xf[perm]).cuda()
-            zd = torch.as_tensor(Z[perm]).cuda()
+            fd = torch.as_tensor(Ff[perm]).cuda()
+            td = torch.as_tensor(T[perm]).cuda()
             nb = len(X) // bs
             loss = None
             for b in range(nb):
-                last = b == nb - 1
-                loss = self.net.train_step(xd[b * bs:(b + 1) * bs], zd[b * bs:(b + 1) * bs], lr=lr,
-                                           want_loss=last)
+                sl = slice(b * bs, (b + 1) * bs)
+                loss = self.net.train_step(xd[sl], td[sl], f=fd[sl], lr=lr, want_loss=b == nb - 1)
             hist.append(loss)
             if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
                 log(f"epoch {ep}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
         return hist
 
-    def predict(self, X):
+    def predict(self, X, F):
         import torch
 
         out = []
         for o in range(0, len(X), self.max_batch):
             xd = torch.as_tensor(X[o:o + self.max_batch].astype(np.float32)).cuda()
-            out.append(self.net.forward(xd).cpu().numpy().astype(np.float64))
-        return np.concatenate(out) * self.std + self.mean
+            fd = torch.as_tensor(F[o:o + self.max_batch].astype(np.float32)).cuda()
+            out.append(self.net.forward(xd, fd).cpu().numpy().astype(np.float64))
+        return np.concatenate(out) * self.scale
 
     def destroy(self):
         self.net.destroy()

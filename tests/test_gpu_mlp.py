@@ -108,3 +108,32 @@ def test_mlp_training_reduces_loss(net):
     l1 = net.train_step(xd, td, update=False)
     print(f"loss {l0:.4e} -> {l1:.4e}")
     assert l1 < 0.1 * l0
+
+
+def test_mlp_modulated_output_matches_oracle():
+    """Output modulated by per-sample weights (y[k] = sum_i f_i z[i K + k], n_mod = 6): forward and
+    gradients against the oracle's bfloat16-rounding mode."""
+    torch = torch_mod()
+    from paper_2409_01949_amd import MLP
+    dims = [65, 512, 512, 512, 6 * 32]
+    m = MLP(dims, 512, n_mod=6)
+    p = mlp_init(dims, 5)
+    m.set_params(p)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((150, 65)).astype(np.float32)
+    F = rng.standard_normal((150, 6)).astype(np.float32)
+    T = rng.standard_normal((150, 32)).astype(np.float32)
+    xd, fd, td = (torch.as_tensor(a).cuda() for a in (X, F, T))
+    y = m.forward(xd, fd).cpu().numpy()
+    params = omlp.unflatten(p.astype(np.float64), dims)
+    z, acts = omlp.forward(params, X.astype(np.float64), bf16=True)
+    yo = omlp.modulate(z, F.astype(np.float64))
+    ef = _rel(y, yo)
+    loss = m.train_step(xd, td, f=fd, update=False)
+    lo, dy = omlp.mse(yo, T.astype(np.float64))
+    go = omlp.backward(params, acts, dy, bf16=True, f=F.astype(np.float64))
+    gl = omlp.unflatten(m.get_grads().astype(np.float64), dims)
+    eg = max(max(_rel(a, c), _rel(b, d)) for (a, b), (c, d) in zip(gl, go))
+    print(f"modulated: forward rel diff {ef:.2e}, worst gradient rel diff {eg:.2e}")
+    assert ef <= 2e-3 and eg <= 5e-3 and abs(loss - lo) <= 1e-3 * lo
+    m.destroy()

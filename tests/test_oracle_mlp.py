@@ -90,3 +90,27 @@ def test_training_reduces_loss():
         params, state = mlp.adam(params, mlp.backward(params, acts, dy), state, lr=1e-2)
     l1 = mlp.mse(mlp.forward(params, x)[0], t)[0]
     assert l1 < 0.05 * l0
+
+
+def test_modulated_output_gradients():
+    """Output linear in per-sample weights f: y[k] = sum_i f_i z[i K + k]; gradients against
+    central differences, and the output for one-hot f picks the matching slice of z."""
+    dims = [4, 9, 6]          # n_mod = 3, K = 2
+    params = _net(dims, 8)
+    rng = np.random.default_rng(9)
+    X, F, T = rng.standard_normal((5, 4)), rng.standard_normal((5, 3)), rng.standard_normal((5, 2))
+
+    def loss(vec):
+        z, _ = mlp.forward(mlp.unflatten(vec, dims), X)
+        return mlp.mse(mlp.modulate(z, F), T)[0]
+
+    z, acts = mlp.forward(params, X)
+    _, dy = mlp.mse(mlp.modulate(z, F), T)
+    g = mlp.flatten(mlp.backward(params, acts, dy, f=F))
+    v = mlp.flatten(params)
+    h = 1e-6
+    fd = np.array([(loss(v + h * e) - loss(v - h * e)) / (2 * h) for e in np.eye(v.size)])
+    assert np.abs(fd - g).max() <= 1e-8 * max(1.0, np.abs(g).max())
+    onehot = np.zeros((5, 3))
+    onehot[:, 1] = 1.0
+    assert np.array_equal(mlp.modulate(z, onehot), z[:, 2:4])
