@@ -212,7 +212,10 @@ elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host
  * Cholesky factor R_j of G_jj + lambda_j I, lambda_j = shift * trace(G_jj)/K, from FP64 Gram
  * blocks, and R_j^{-1}.  A block that does not factor is retried with 100x the shift up to 8
  * times, then replaced by the identity; *n_fallback_host (may be NULL) receives that count.
- * shift must be > 0.  Blocks until done. */
+ * With K <= 128 the preconditioned matrix M R^{-1} is also formed once (FP64 matrix cores) with
+ * its store_prec rounding, in 8 nnz (+ 4 or 2 nnz) bytes of extra device memory: preconditioned
+ * Krylov steps then run on it with no per-step R^{-1} products (M and its copy are unchanged).
+ * A later elmfb_assemble discards the factors.  shift must be > 0.  Blocks until done. */
 elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback_host,
                                 void* stream);
 

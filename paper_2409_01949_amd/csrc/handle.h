@@ -80,6 +80,13 @@ struct elmfb_problem_s {
   double* d_rinvT = nullptr;
   int64_t* d_diag_off = nullptr;
   bool bj_ready = false;
+  // the preconditioner folded into the matrix (K <= 128): M R^{-1} in FP64 and in store_prec
+  bool folded = false;
+  double* d_Ahat = nullptr;
+  void* d_Ahat_lo = nullptr;
+  Geo* d_geo1 = nullptr;
+  Tile* d_ftiles = nullptr;
+  int64_t n_ftiles = 0;
 
   bool assembled = false;
   double anorm_f = -1.0;        // exact Frobenius norm of the stored matrix (lazy)

@@ -317,15 +317,39 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
       const int jx0 = cov[g.cov_off[l][0] + 2 * ix], jx1 = cov[g.cov_off[l][0] + 2 * ix + 1];
       const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
       const int Jy = g.J[l][1];
-      for (int jx = jx0; jx <= jx1; ++jx)
-        for (int jy = jy0; jy <= jy1; ++jy) {
-          const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
-          const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
-          double tv[kMaxRhs];
-          load_r(tpart + (B.p_off + p) * R, R, tv);
+      const int ncx = jx1 - jx0 + 1, ncy = jy1 - jy0 + 1;
+      if (ncx <= 3 && ncy <= 3) {
+        // up to 3 x 3 covering blocks (width ratio < 3): block records first, then the
+        // partial rows, summed jx-major, jy-minor; absent slots read the first block, add 0
+        int64_t off[9];
 #pragma unroll
-          for (int j = 0; j < kMaxRhs; ++j) y[j] += tv[j];
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const bool ok = a < ncx && c < ncy;
+            const DevBlock& B = blocks[g.bbase[l] + (jx0 + (ok ? a : 0)) * Jy + jy0 + (ok ? c : 0)];
+            off[a * 3 + c] = ok ? (B.p_off + (ix - B.ix0) * B.ny + (iy - B.iy0)) * R : -1;
+          }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          if (off[q] >= 0) {
+            double tv[kMaxRhs];
+            load_r(tpart + off[q], R, tv);
+#pragma unroll
+            for (int j = 0; j < kMaxRhs; ++j) y[j] += tv[j];
+          }
         }
+      } else {
+        for (int jx = jx0; jx <= jx1; ++jx)
+          for (int jy = jy0; jy <= jy1; ++jy) {
+            const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
+            const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
+            double tv[kMaxRhs];
+            load_r(tpart + (B.p_off + p) * R, R, tv);
+#pragma unroll
+            for (int j = 0; j < kMaxRhs; ++j) y[j] += tv[j];
+          }
+      }
     }
     double* o = out + r * R;
     if (mode == ROW_STORE) {

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_bt_bj_factor(const Geo* __restrict__ ge
 
 // Fold the preconditioner into the matrix: Mhat_b = M_b R_b^{-1}, i.e. in the feature-major
 // block layout Mhat_b[k'][p] = sum_{k <= k'} Ri[k][k'] M_b[k][p] (R^{-T} times the block), on
-// v_mfma_f64_16x16x4_f64.  One workgroup per 64-point run of a block: the four waves own output
+// v_mfma_f64_16x16x4_f64 (K <= 128).  One workgroup per 64-point run of a block: the four waves own output
 // row tiles (16 features each) w and w + 4 and the four 16-point column tiles; the contraction
 // over k runs in LDS stages of 16 (R^{-T} columns from the column-packed factor, M_b rows), and
 // tiles entirely above the diagonal are skipped.  The FP64 result goes to Mhat and, rounded to
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) k_bt_bj_factor(const Geo* __restrict__ ge
 constexpr int kFoldK = 16;
 constexpr int kFoldP = 64;
 
-template <int LO>
+template <int LO, bool FULL>
 __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
                                                  const DevBlock* __restrict__ blocks,
                                                  const Tile* __restrict__ ftiles,
@@ -183,7 +183,8 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   const int K = geos[B.inst].K;
   const int n = B.n, p0 = t.p0;
   const double* Ab = A + B.a_off;
-  const double* Rb = rc + foff[t.blk];
+  // FULL: R^{-1} stored K x K row-major per block (single problems); else column-packed
+  const double* Rb = FULL ? rc + (int64_t)t.blk * K * K : rc + foff[t.blk];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nT = (K + 15) >> 4;
@@ -196,7 +197,8 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
     for (int e = threadIdx.x; e < kBatchMaxK * kFoldK; e += 256) {
       const int kp = e / kFoldK, kk = e - (e / kFoldK) * kFoldK;
       const int k = k0 + kk;
-      Rt[kp][kk] = (kp < K && k <= kp) ? Rb[(int64_t)kp * (kp + 1) / 2 + k] : 0.0;
+      const int64_t ri = FULL ? (int64_t)k * K + kp : (int64_t)kp * (kp + 1) / 2 + k;
+      Rt[kp][kk] = (kp < K && k <= kp) ? Rb[ri] : 0.0;
     }
     for (int e = threadIdx.x; e < kFoldK * kFoldP; e += 256) {
       const int kk = e / kFoldP, c = e - (e / kFoldP) * kFoldP;
@@ -243,20 +245,18 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   }
 }
 
-hipError_t launch_bt_fold(int lo_prec, const Geo* geos, const DevBlock* blocks,
+hipError_t launch_bt_fold(int lo_prec, bool full, const Geo* geos, const DevBlock* blocks,
                           const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
                           const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s) {
   if (n_ftiles == 0) return hipSuccess;
   const dim3 grid((unsigned)n_ftiles), blk(256);
-  if (lo_prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_bt_fold<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff,
-                       Ahat, Ahat_lo);
-  else if (lo_prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_bt_fold<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff,
-                       Ahat, Ahat_lo);
-  else
-    hipLaunchKernelGGL(k_bt_fold<-1>, grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff, Ahat,
-                       Ahat_lo);
+#define FOLD(L, F)                                                                            \
+  hipLaunchKernelGGL((k_bt_fold<L, F>), grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff, Ahat, \
+                     Ahat_lo)
+  if (lo_prec == ELMFB_FP32) { if (full) FOLD(ELMFB_FP32, true); else FOLD(ELMFB_FP32, false); }
+  else if (lo_prec == ELMFB_BF16) { if (full) FOLD(ELMFB_BF16, true); else FOLD(ELMFB_BF16, false); }
+  else { if (full) FOLD(-1, true); else FOLD(-1, false); }
+#undef FOLD
   return hipGetLastError();
 }
 

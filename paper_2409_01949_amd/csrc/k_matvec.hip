@@ -69,11 +69,31 @@ __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __re
       const int jx0 = cov[g.cov_off[l][0] + 2 * ix], jx1 = cov[g.cov_off[l][0] + 2 * ix + 1];
       const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
       const int Jy = g.J[l][1];
-      for (int jx = jx0; jx <= jx1; ++jx) {
-        for (int jy = jy0; jy <= jy1; ++jy) {
-          const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
-          const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
-          y += tpart[B.p_off + p];
+      const int ncx = jx1 - jx0 + 1, ncy = jy1 - jy0 + 1;
+      if (ncx <= 3 && ncy <= 3) {
+        // up to 3 x 3 covering blocks (width ratio < 3): every load issued before the sums,
+        // which keep the order jx-major, jy-minor; absent slots read the first block and add 0
+        double tv[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const bool ok = a < ncx && c < ncy;
+            const DevBlock& B = blocks[g.bbase[l] + (jx0 + (ok ? a : 0)) * Jy + jy0 + (ok ? c : 0)];
+            const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
+            const double t = tpart[B.p_off + p];
+            tv[a * 3 + c] = ok ? t : 0.0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) y += tv[q];
+      } else {
+        for (int jx = jx0; jx <= jx1; ++jx) {
+          for (int jy = jy0; jy <= jy1; ++jy) {
+            const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
+            const int p = (ix - B.ix0) * B.ny + (iy - B.iy0);
+            y += tpart[B.p_off + p];
+          }
         }
       }
     }
@@ -168,7 +188,16 @@ __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __rest
        q += (int64_t)gridDim.x * blockDim.x) {
     const int b = (int)(q / K), k = (int)(q - (int64_t)b * K);
     double x = 0.0;
-    for (int c = cstart[b]; c < cstart[b + 1]; ++c) x += part[(int64_t)c * K + k];
+    int c = cstart[b];
+    const int ce = cstart[b + 1];
+    for (; c + 8 <= ce; c += 8) {   // 8 partials in flight, summed in chunk order
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = part[(int64_t)(c + q) * K + k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x += t[q];
+    }
+    for (; c < ce; ++c) x += part[(int64_t)c * K + k];
     if (mode == COL_STORE) {
       out[q] = x;
     } else if (mode == COL_LSQR_V) {

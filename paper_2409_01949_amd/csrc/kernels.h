@@ -129,7 +129,8 @@ hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t 
 hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
                                double* G, const int64_t* goff, double* work, const int64_t* foff,
                                double shift, double* rc, int32_t* nfail, hipStream_t s);
-hipError_t launch_bt_fold(int lo_prec, const Geo* geos, const DevBlock* blocks,
+// full: rc holds R^{-1} as K x K row-major per block (foff unused); else column-packed at foff
+hipError_t launch_bt_fold(int lo_prec, bool full, const Geo* geos, const DevBlock* blocks,
                           const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
                           const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s);
 // ot (may be NULL): outer state of a refined solve; pairs it marks done are frozen, the others

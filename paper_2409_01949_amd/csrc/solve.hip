@@ -13,12 +13,17 @@
 
 namespace {
 
-// The matrix copy, right-hand side and preconditioning of one Krylov run.
+// The matrix copy, right-hand side and preconditioning of one Krylov run.  With block-Jacobi
+// (bj) the iterate is the correction in preconditioned coordinates; `apply` says whether R^{-1}
+// is applied in every step (else A is the folded M R^{-1}).  A_x is the FP64 matrix M, for the
+// residual of a warm start.
 struct KCtx {
   const void* A;
   int prec;
   const double* rhs;
   bool bj;
+  bool apply;
+  const double* A_x;
 };
 
 double* red_slot(elmfb_problem h, int i) { return h->d_red + (int64_t)2 * kRedBlocks * i; }
@@ -35,7 +40,7 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
   const int64_t nt = (int64_t)h->tiles.size(), nc = (int64_t)h->chunks.size();
   hipError_t e;
   // u = A v / alpha - ... (v scaled by 1/alpha as it is read)
-  if (c.bj) {
+  if (c.apply) {
     if ((e = launch_bj_apply(g, h->d_rinvT, h->d_v, state_field(h, offsetof(SolveState, sv)),
                              h->d_vt, st, s)))
       return e;
@@ -55,7 +60,7 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
                              state_field(h, offsetof(SolveState, su)), h->d_part, st, s)))
     return e;
   int na = cw;
-  if (c.bj) {
+  if (c.apply) {
     if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, h->d_xt, st, red2, cw, s)))
       return e;
     if ((e = launch_bj_apply_t(g, h->d_rinv, h->d_xt, COL_LSQR_V, h->d_v, st, red2, s))) return e;
@@ -101,9 +106,9 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
   double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
   const int rw = rows_wg(g), cw = cols_wg(g);
   hipError_t e;
-  if (x0) {
-    if ((e = launch_mv_blocks(g, c.prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), c.A,
-                              x0, nullptr, h->d_tpart, nullptr, s)))
+  if (x0) {   // x0 is in the coordinates of M
+    if ((e = launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
+                              c.A_x, x0, nullptr, h->d_tpart, nullptr, s)))
       return e;
     if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_u, c.rhs,
                                 nullptr, red2, rw, s)))
@@ -120,7 +125,7 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
                                nullptr, s)))
       return e;
     int na = cw;
-    if (c.bj) {
+    if (c.apply) {
       if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, h->d_xt, nullptr, red3, cw,
                                  s)))
         return e;
@@ -157,7 +162,8 @@ hipError_t enqueue_iterations(elmfb_problem h, const KCtx& c, int method, int n,
 }
 
 hipError_t get_graph(elmfb_problem h, const KCtx& c, int method, int n, hipGraphExec_t* out) {
-  const std::vector<int64_t> key = {method, n, (int64_t)c.A, c.prec, (int64_t)c.rhs, c.bj};
+  const std::vector<int64_t> key = {method, n, (int64_t)c.A, c.prec, (int64_t)c.rhs, c.bj,
+                                    c.apply};
   auto it = h->graphs.find(key);
   if (it != h->graphs.end()) {
     *out = it->second;
@@ -363,6 +369,29 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
   HIP_OR_FAIL(h, launch_bj_factor(g, gdiag, h->d_diag_off, shift, rwork, h->d_rinv, h->d_rinvT,
                                   h->d_flag, s));
+  // fold the preconditioner into the matrix (and its low-precision copy) when K <= 128
+  h->folded = false;
+  if (g.K <= kBatchMaxK) {
+    const int64_t es_lo = h->lo_prec == ELMFB_FP32 ? 4 : (h->lo_prec == ELMFB_BF16 ? 2 : 0);
+    if (!h->d_Ahat) {
+      std::vector<Tile> ft;
+      for (size_t b = 0; b < h->blocks.size(); ++b)
+        for (int p0 = 0; p0 < h->blocks[b].n; p0 += 64) ft.push_back(Tile{(int32_t)b, p0});
+      HIP_OR_FAIL(h, dalloc(h, &h->d_Ahat, h->nnz * 8));
+      if (es_lo) HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->nnz * es_lo));
+      HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_geo1, (int64_t)sizeof(Geo)));
+      HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_ftiles, (int64_t)(ft.size() * sizeof(Tile)) + 16));
+      HIP_OR_FAIL(h, hipMemcpy(h->d_geo1, &h->geo, sizeof(Geo), hipMemcpyHostToDevice));
+      if (!ft.empty())
+        HIP_OR_FAIL(h, hipMemcpy(h->d_ftiles, ft.data(), ft.size() * sizeof(Tile),
+                                 hipMemcpyHostToDevice));
+      h->n_ftiles = (int64_t)ft.size();
+    }
+    HIP_OR_FAIL(h, launch_bt_fold(h->lo_prec, true, h->d_geo1, h->d_blocks, h->d_ftiles,
+                                  h->n_ftiles, h->d_A, h->d_rinv, nullptr, h->d_Ahat,
+                                  h->d_Ahat_lo, s));
+    h->folded = true;
+  }
   int32_t nf = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&nf, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
@@ -428,7 +457,9 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   double outer_rnorm = -1.0;
   const double* result = h->d_x;
   if (method != ELMFB_MIXED_IR) {
-    const KCtx c{h->d_A, ELMFB_FP64, h->d_h, bj};
+    const bool fold = bj && h->folded;
+    const KCtx c{fold ? (const void*)h->d_Ahat : (const void*)h->d_A, ELMFB_FP64, h->d_h, bj,
+                 bj && !fold, h->d_A};
     HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
     HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(h, hipStreamSynchronize(s));
@@ -457,7 +488,9 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, launch_copy(opts->x0_dev, h->d_c, g.n_phi, s));
     else
       HIP_OR_FAIL(h, hipMemsetAsync(h->d_c, 0, (size_t)g.n_phi * 8, s));
-    const KCtx inner{h->d_A_lo, h->lo_prec, h->d_r, bj};
+    const bool fold = bj && h->folded;
+    const KCtx inner{fold ? (const void*)h->d_Ahat_lo : (const void*)h->d_A_lo, h->lo_prec, h->d_r,
+                     bj, bj && !fold, h->d_A};
     const int rw = rows_wg(g);
     int istop = 7;
     for (outer = 0; outer < opts->outer_lim; ++outer) {

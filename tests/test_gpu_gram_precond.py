@@ -157,9 +157,11 @@ def test_block_jacobi_small_shift(case32):
 
 
 def test_mixed_refinement_matches_oracle(case32):
-    """FP64 refinement around inner LSQR on the FP32 copy (block-Jacobi preconditioned): GPU and
-    oracle refinement agree after each of the first outer steps, and the FP64 outer residual
-    never grows."""
+    """FP64 refinement around inner LSQR on the FP32 copy of the block-Jacobi preconditioned
+    matrix: the inner solves run on the FP32 rounding of M R^{-1} (formed once in FP64; K <= 128
+    for all cases here), the FP64 residual on M, c += R^{-1} d.  GPU and oracle refinement agree
+    after each of the first outer steps.  The FP32 copies come from FP64 products summed in
+    different orders, so an entry next to a rounding boundary may round differently."""
     spec, P, W, b, f, blocks, h = case32
     torch = torch_mod()
     shift = 1e-6
@@ -167,20 +169,22 @@ def test_mixed_refinement_matches_oracle(case32):
     n = P.sizes["n_phi"]
     N = spec.n_rows
     facs = linalg.block_jacobi_factors(blocks, shift)
-    lo = [asm.Block(blk.sd, blk.rows, lowprec.to_f32(blk.M)) for blk in blocks]
+    fb = linalg.fold_blocks(blocks, facs)
+    lo = [asm.Block(blk.sd, blk.rows, lowprec.to_f32(blk.M)) for blk in fb]
     xt = grid_points(spec, spec.meta["n_test"])
     inner = 5
     for outer in (1, 2):
         coef = torch.empty(n, dtype=torch.float64, device="cuda")
         info = P.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, check_every=5,
                        precond=True, atol=0, btol=0)
-        c, hist = linalg.refine_lsqr(lambda v: asm.matvec(blocks, v, N),
-                                     lambda u: asm.rmatvec(blocks, u, n),
-                                     lambda v: asm.matvec(lo, v, N),
-                                     lambda u: asm.rmatvec(lo, u, n), h, n, outer, inner,
-                                     blocks=blocks, factors=facs)
+        # the same refinement in preconditioned coordinates: r = h - (M R^{-1}) c_y, x = R^{-1} c_y
+        cy, hist = linalg.refine_lsqr(lambda v: asm.matvec(fb, v, N),
+                                      lambda u: asm.rmatvec(fb, u, n),
+                                      lambda v: asm.matvec(lo, v, N),
+                                      lambda u: asm.rmatvec(lo, u, n), h, n, outer, inner)
+        c = linalg.block_apply(blocks, facs, cy)
         du = ev.rel_l2(ev.evaluate(spec, W, b, coef.cpu().numpy(), xt), ev.evaluate(spec, W, b, c, xt))
         print(f"{spec.name} mixed outer={outer}: u diff {du:.2e}, outer ||r|| {info['rnorm']:.4e} "
               f"(oracle last {hist[-1]:.4e}), inner iters {info['iters']}")
         assert info["outer_iters"] == outer and info["iters"] == outer * inner
-        assert du <= 1e-8
+        assert du <= 1e-7
