@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--check-every", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=20)
+    p.add_argument("--compare-iters", type=int, default=15000,
+                   help="iteration budget of the FP64 comparison solves")
     p.add_argument("--batch-n", type=int, default=512)
     p.add_argument("--batch-btol", type=float, default=1e-6)
     p.add_argument("--epochs", type=int, default=100, help="warm workload: MLP training epochs")
@@ -361,27 +363,34 @@ def main():
     coef = torch.empty(n, dtype=torch.float64, device="cuda")
     u_test = torch.empty(xt.shape[0], dtype=torch.float64, device="cuda")
 
-    def step(method=args.method, pre=precond):
+    def step(method=args.method, pre=precond, iters=args.iters):
         P.assemble(fd)
         if pre:
             P.precondition(args.shift)
         if method == "mixed_ir":
             info = P.solve(coef, method="mixed_ir", inner_iters=args.inner,
-                           outer_lim=max(1, args.iters // args.inner), atol=0.0, btol=0.0,
+                           outer_lim=max(1, iters // args.inner), atol=0.0, btol=0.0,
                            check_every=min(args.check_every, args.inner), check_pts=xc,
                            check_ref=uc, target_rel_l2=args.target, precond=pre)
         else:
-            info = P.solve(coef, method=method, iter_lim=args.iters, atol=0.0, btol=0.0,
+            info = P.solve(coef, method=method, iter_lim=iters, atol=0.0, btol=0.0,
                            check_every=args.check_every, check_pts=xc, check_ref=uc,
                            target_rel_l2=args.target, precond=pre)
         P.evaluate(coef, xt, u_test)
         return info
 
-    for _ in range(args.warmup):
-        step()
+    def note(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        wi = step()
+        note(f"warmup step {w}: {wi['iters']} iterations")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = [step() for _ in range(args.steps)]
+    infos = []
+    for k in range(args.steps):
+        infos.append(step())
+        note(f"step {k}: {infos[-1]['iters']} iterations, rel-L2 {infos[-1]['rel_l2']:.3e}")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     info = infos[-1]
@@ -408,11 +417,13 @@ def main():
                                  ("fp64_plain_lsqr", "lsqr", False)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ci = step(meth, pre)
+            ci = step(meth, pre, args.compare_iters)
             torch.cuda.synchronize()
             compare[label] = {"time_to_solution_s": time.perf_counter() - t1,
                               "reached_target": bool(ci["istop"] == 8), "iters": ci["iters"],
+                              "iter_budget": args.compare_iters,
                               "rel_l2_check_at_stop": ci["rel_l2"]}
+            note(f"{label}: {compare[label]['time_to_solution_s']:.2f} s, {ci['iters']} iterations")
         compare["speedup_vs_fp64_block_jacobi"] = \
             compare["fp64_block_jacobi_lsqr"]["time_to_solution_s"] / dt
         compare["speedup_vs_fp64_plain_lsqr"] = compare["fp64_plain_lsqr"]["time_to_solution_s"] / dt

@@ -212,9 +212,11 @@ elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host
  * Cholesky factor R_j of G_jj + lambda_j I, lambda_j = shift * trace(G_jj)/K, from FP64 Gram
  * blocks, and R_j^{-1}.  A block that does not factor is retried with 100x the shift up to 8
  * times, then replaced by the identity; *n_fallback_host (may be NULL) receives that count.
- * With K <= 128 the preconditioned matrix M R^{-1} is also formed once (FP64 matrix cores) with
- * its store_prec rounding, in 8 nnz (+ 4 or 2 nnz) bytes of extra device memory: preconditioned
- * Krylov steps then run on it with no per-step R^{-1} products (M and its copy are unchanged).
+ * The preconditioned matrix M R^{-1} is also formed once (FP64 matrix cores): its store_prec
+ * rounding (4 or 2 nnz bytes) for the inner solves of ELMFB_MIXED_IR and the FP64 matrix (8 nnz
+ * bytes) for FP64 solves, each when it fits in free device memory with an 8 GB margin;
+ * preconditioned steps on a folded copy need no per-step R^{-1} products, the others apply R^{-1}
+ * in every step.  M and its copy are unchanged.
  * A later elmfb_assemble discards the factors.  shift must be > 0.  Blocks until done. */
 elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback_host,
                                 void* stream);

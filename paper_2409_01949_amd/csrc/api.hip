@@ -478,7 +478,7 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->geo;
   h->bj_ready = false;   // factors and the folded matrix belong to the previous assembly
-  h->folded = false;
+  h->folded64 = h->folded_lo = false;
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
   HIP_OR_FAIL(h, launch_rhs(g, f_dev, h->d_h, h->d_flag, s));
   HIP_OR_FAIL(h, launch_assemble(g, h->lo_prec, h->d_blocks, h->d_tiles,

@@ -548,7 +548,7 @@ elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fa
                             B->d_rc, B->d_flag, s);
   // M R^{-1} in FP64, and its rounded copy in place of the low-precision M
   if (e == hipSuccess)
-    e = launch_bt_fold(B->lo_prec, false, B->d_geos, B->d_blocks, B->d_ftiles,
+    e = launch_bt_fold(B->lo_prec, false, kBatchMaxK, B->d_geos, B->d_blocks, B->d_ftiles,
                        (int64_t)B->ftiles.size(), B->d_A, B->d_rc, B->d_foff, B->d_Ahat,
                        B->d_A_lo, s);
   int32_t nfail = 0;

@@ -80,8 +80,9 @@ struct elmfb_problem_s {
   double* d_rinvT = nullptr;
   int64_t* d_diag_off = nullptr;
   bool bj_ready = false;
-  // the preconditioner folded into the matrix (K <= 128): M R^{-1} in FP64 and in store_prec
-  bool folded = false;
+  // the preconditioner folded into the matrix: M R^{-1} in FP64 (folded64) and its store_prec
+  // rounding (folded_lo), each formed when device memory allows
+  bool folded64 = false, folded_lo = false;
   double* d_Ahat = nullptr;
   void* d_Ahat_lo = nullptr;
   Geo* d_geo1 = nullptr;

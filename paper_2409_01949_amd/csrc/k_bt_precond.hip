@@ -159,15 +159,15 @@ __global__ void __launch_bounds__(256) k_bt_bj_factor(const Geo* __restrict__ ge
 
 // Fold the preconditioner into the matrix: Mhat_b = M_b R_b^{-1}, i.e. in the feature-major
 // block layout Mhat_b[k'][p] = sum_{k <= k'} Ri[k][k'] M_b[k][p] (R^{-T} times the block), on
-// v_mfma_f64_16x16x4_f64 (K <= 128).  One workgroup per 64-point run of a block: the four waves own output
-// row tiles (16 features each) w and w + 4 and the four 16-point column tiles; the contraction
+// v_mfma_f64_16x16x4_f64 (K <= 256).  One workgroup per 64-point run of a block: the four waves own output
+// row tiles (16 features each) w, w + 4, ... and the four 16-point column tiles; the contraction
 // over k runs in LDS stages of 16 (R^{-T} columns from the column-packed factor, M_b rows), and
-// tiles entirely above the diagonal are skipped.  The FP64 result goes to Mhat and, rounded to
-// nearest even, to the low-precision copy.
+// tiles entirely above the diagonal are skipped.  The FP64 result goes to Mhat (if not NULL) and,
+// rounded to nearest even, to the low-precision copy.
 constexpr int kFoldK = 16;
 constexpr int kFoldP = 64;
 
-template <int LO, bool FULL>
+template <int LO, bool FULL, int TPW>
 __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
                                                  const DevBlock* __restrict__ blocks,
                                                  const Tile* __restrict__ ftiles,
@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
                                                  const int64_t* __restrict__ foff,
                                                  double* __restrict__ Ahat,
                                                  void* __restrict__ Ahat_lo) {
-  __shared__ double Rt[kBatchMaxK][kFoldK + 1];   // Rt[k'][kk] = Ri[k0 + kk][k']
+  constexpr int KMAX = 64 * TPW;                  // TPW row tiles of 16 features per wave
+  __shared__ double Rt[KMAX][kFoldK + 1];         // Rt[k'][kk] = Ri[k0 + kk][k']
   __shared__ double At[kFoldK][kFoldP + 1];       // At[kk][c] = M_b[k0 + kk][p0 + c]
   const Tile t = ftiles[blockIdx.x];
   const DevBlock B = blocks[t.blk];
@@ -188,13 +189,13 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int nT = (K + 15) >> 4;
-  d4_t acc[2][4];
+  d4_t acc[TPW][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TPW; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
   for (int k0 = 0; k0 < K; k0 += kFoldK) {
-    for (int e = threadIdx.x; e < kBatchMaxK * kFoldK; e += 256) {
+    for (int e = threadIdx.x; e < KMAX * kFoldK; e += 256) {
       const int kp = e / kFoldK, kk = e - (e / kFoldK) * kFoldK;
       const int k = k0 + kk;
       const int64_t ri = FULL ? (int64_t)k * K + kp : (int64_t)kp * (kp + 1) / 2 + k;
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
     }
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < TPW; ++a) {
       const int I = wid + 4 * a;
       if (I < nT && 16 * I + 15 >= k0) {     // rows k' < k0 of R^{-T} vanish on this stage
 #pragma unroll
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   }
   // accumulator of v_mfma_f64_16x16x4_f64: lane holds column li, rows lq + 4 v
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < TPW; ++a) {
     const int I = wid + 4 * a;
     if (I >= nT) continue;
 #pragma unroll
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
         if (kp < K && p < n) {
           const int64_t o = B.a_off + (int64_t)kp * n + p;
           const double val = acc[a][b][v];
-          Ahat[o] = val;
+          if (Ahat) Ahat[o] = val;
           if constexpr (LO == ELMFB_FP32) static_cast<float*>(Ahat_lo)[o] = (float)val;
           if constexpr (LO == ELMFB_BF16) static_cast<uint16_t*>(Ahat_lo)[o] = f64_to_bf16_rne(val);
         }
@@ -245,17 +246,21 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   }
 }
 
-hipError_t launch_bt_fold(int lo_prec, bool full, const Geo* geos, const DevBlock* blocks,
-                          const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
-                          const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s) {
+hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const Geo* geos,
+                          const DevBlock* blocks, const Tile* ftiles, int64_t n_ftiles,
+                          const double* A, const double* rc, const int64_t* foff, double* Ahat,
+                          void* Ahat_lo, hipStream_t s) {
   if (n_ftiles == 0) return hipSuccess;
+  if (kmax > 256) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_ftiles), blk(256);
-#define FOLD(L, F)                                                                            \
-  hipLaunchKernelGGL((k_bt_fold<L, F>), grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff, Ahat, \
-                     Ahat_lo)
-  if (lo_prec == ELMFB_FP32) { if (full) FOLD(ELMFB_FP32, true); else FOLD(ELMFB_FP32, false); }
-  else if (lo_prec == ELMFB_BF16) { if (full) FOLD(ELMFB_BF16, true); else FOLD(ELMFB_BF16, false); }
-  else { if (full) FOLD(-1, true); else FOLD(-1, false); }
+#define FOLD(L, F, T)                                                                            \
+  hipLaunchKernelGGL((k_bt_fold<L, F, T>), grid, blk, 0, s, geos, blocks, ftiles, A, rc, foff,    \
+                     Ahat, Ahat_lo)
+#define FOLD_T(L, F) do { if (kmax > 128) FOLD(L, F, 4); else FOLD(L, F, 2); } while (0)
+  if (lo_prec == ELMFB_FP32) { if (full) FOLD_T(ELMFB_FP32, true); else FOLD_T(ELMFB_FP32, false); }
+  else if (lo_prec == ELMFB_BF16) { if (full) FOLD_T(ELMFB_BF16, true); else FOLD_T(ELMFB_BF16, false); }
+  else { if (full) FOLD_T(-1, true); else FOLD_T(-1, false); }
+#undef FOLD_T
 #undef FOLD
   return hipGetLastError();
 }

@@ -130,9 +130,11 @@ hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t 
                                double* G, const int64_t* goff, double* work, const int64_t* foff,
                                double shift, double* rc, int32_t* nfail, hipStream_t s);
 // full: rc holds R^{-1} as K x K row-major per block (foff unused); else column-packed at foff
-hipError_t launch_bt_fold(int lo_prec, bool full, const Geo* geos, const DevBlock* blocks,
-                          const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
-                          const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s);
+// kmax: largest K of the blocks (<= 256); Ahat may be NULL (low-precision result only)
+hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const Geo* geos,
+                          const DevBlock* blocks, const Tile* ftiles, int64_t n_ftiles,
+                          const double* A, const double* rc, const int64_t* foff, double* Ahat,
+                          void* Ahat_lo, hipStream_t s);
 // ot (may be NULL): outer state of a refined solve; pairs it marks done are frozen, the others
 // stop their inner LSQR once its residual estimate is inner_rel times the outer target
 hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,

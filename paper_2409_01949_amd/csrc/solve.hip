@@ -369,16 +369,25 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
   HIP_OR_FAIL(h, launch_bj_factor(g, gdiag, h->d_diag_off, shift, rwork, h->d_rinv, h->d_rinvT,
                                   h->d_flag, s));
-  // fold the preconditioner into the matrix (and its low-precision copy) when K <= 128
-  h->folded = false;
-  if (g.K <= kBatchMaxK) {
+  // fold the preconditioner into the matrix: the store_prec rounding of M R^{-1} (inner solves of
+  // the refinement) and M R^{-1} in FP64 (FP64 Krylov solves), each when it fits in free device
+  // memory with an 8 GB margin; otherwise those solves apply R^{-1} in every step
+  h->folded64 = h->folded_lo = false;
+  {
     const int64_t es_lo = h->lo_prec == ELMFB_FP32 ? 4 : (h->lo_prec == ELMFB_BF16 ? 2 : 0);
-    if (!h->d_Ahat) {
+    const int64_t margin = (int64_t)8 << 30;
+    auto fits = [&](int64_t bytes) {
+      size_t free_b = 0, total_b = 0;
+      return hipMemGetInfo(&free_b, &total_b) == hipSuccess && (int64_t)free_b > bytes + margin;
+    };
+    if (es_lo && !h->d_Ahat_lo && fits(h->nnz * es_lo))
+      HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->nnz * es_lo));
+    if (!h->d_Ahat && fits(h->nnz * 8)) HIP_OR_FAIL(h, dalloc(h, &h->d_Ahat, h->nnz * 8));
+    const bool lo_ok = es_lo && h->d_Ahat_lo;
+    if ((lo_ok || h->d_Ahat) && !h->d_ftiles) {
       std::vector<Tile> ft;
       for (size_t b = 0; b < h->blocks.size(); ++b)
         for (int p0 = 0; p0 < h->blocks[b].n; p0 += 64) ft.push_back(Tile{(int32_t)b, p0});
-      HIP_OR_FAIL(h, dalloc(h, &h->d_Ahat, h->nnz * 8));
-      if (es_lo) HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->nnz * es_lo));
       HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_geo1, (int64_t)sizeof(Geo)));
       HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_ftiles, (int64_t)(ft.size() * sizeof(Tile)) + 16));
       HIP_OR_FAIL(h, hipMemcpy(h->d_geo1, &h->geo, sizeof(Geo), hipMemcpyHostToDevice));
@@ -387,10 +396,13 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
                                  hipMemcpyHostToDevice));
       h->n_ftiles = (int64_t)ft.size();
     }
-    HIP_OR_FAIL(h, launch_bt_fold(h->lo_prec, true, h->d_geo1, h->d_blocks, h->d_ftiles,
-                                  h->n_ftiles, h->d_A, h->d_rinv, nullptr, h->d_Ahat,
-                                  h->d_Ahat_lo, s));
-    h->folded = true;
+    if (lo_ok || h->d_Ahat) {
+      HIP_OR_FAIL(h, launch_bt_fold(lo_ok ? h->lo_prec : ELMFB_FP64, true, g.K, h->d_geo1,
+                                    h->d_blocks, h->d_ftiles, h->n_ftiles, h->d_A, h->d_rinv,
+                                    nullptr, h->d_Ahat, lo_ok ? h->d_Ahat_lo : nullptr, s));
+      h->folded64 = h->d_Ahat != nullptr;
+      h->folded_lo = lo_ok;
+    }
   }
   int32_t nf = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&nf, h->d_flag, 4, hipMemcpyDeviceToHost, s));
@@ -457,7 +469,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   double outer_rnorm = -1.0;
   const double* result = h->d_x;
   if (method != ELMFB_MIXED_IR) {
-    const bool fold = bj && h->folded;
+    const bool fold = bj && h->folded64;
     const KCtx c{fold ? (const void*)h->d_Ahat : (const void*)h->d_A, ELMFB_FP64, h->d_h, bj,
                  bj && !fold, h->d_A};
     HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
@@ -488,7 +500,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, launch_copy(opts->x0_dev, h->d_c, g.n_phi, s));
     else
       HIP_OR_FAIL(h, hipMemsetAsync(h->d_c, 0, (size_t)g.n_phi * 8, s));
-    const bool fold = bj && h->folded;
+    const bool fold = bj && h->folded_lo;
     const KCtx inner{fold ? (const void*)h->d_Ahat_lo : (const void*)h->d_A_lo, h->lo_prec, h->d_r,
                      bj, bj && !fold, h->d_A};
     const int rw = rows_wg(g);
