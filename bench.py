@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--method", default="mixed_ir", choices=["lsqr", "cgls", "mixed_ir"])
     p.add_argument("--no-precond", action="store_true", help="no block-Jacobi preconditioning")
     p.add_argument("--shift", type=float, default=1e-12)
-    p.add_argument("--store", default="fp32", choices=["fp64", "fp32", "bf16"],
+    p.add_argument("--store", default="fp32", choices=["fp64", "fp32", "bf16", "fp16"],
                    help="low-precision stored copy for the inner solves of mixed_ir")
     p.add_argument("--inner", type=int, default=2500)
     p.add_argument("--no-compare", action="store_true",
@@ -401,7 +401,7 @@ def main():
     # roofline of the dominant kernel: the per-chunk pass of x = M^T u over the matrix copy the
     # inner iterations stream (the FP32 copy for the mixed path)
     kprec = args.store if args.method == "mixed_ir" else "fp64"
-    es = {"fp64": 8, "fp32": 4, "bf16": 2}[kprec]
+    es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kprec]
     ms_mv, ms_rmv = P.time_kernels(args.kernel_reps, prec=kprec)
     ms_mv64, ms_rmv64 = P.time_kernels(args.kernel_reps, prec="fp64")
     nnz, nbp = P.sizes["nnz"], P.sizes["n_block_points"]
@@ -409,7 +409,7 @@ def main():
     rmv_bytes = lambda e: nnz * e + nbp * 8 + n_chunks * spec.K * 8
     mv_bytes = lambda e: nnz * e + nbp * 8
     achieved = rmv_bytes(es) / (ms_rmv * 1e-3) / 1e9
-    kname = {"fp64": "FP64", "fp32": "FP32", "bf16": "BF16"}[kprec]
+    kname = {"fp64": "FP64", "fp32": "FP32", "bf16": "BF16", "fp16": "FP16"}[kprec]
 
     compare = {}
     if not args.no_compare:

@@ -64,7 +64,13 @@ enum {
   ELMFB_ANSATZ_TANH_BOX = 2     /* C = prod_i tanh(w (x_i - lo_i)) tanh(w (hi_i - x_i))      */
 };
 
-enum { ELMFB_FP64 = 0, ELMFB_FP32 = 1, ELMFB_BF16 = 2 };
+/* Storage precisions.  ELMFB_FP16 is IEEE binary16 (11 significant bits, finite range
+ * +-65504): meant for the block-Jacobi-folded matrix M R^{-1}, whose columns have norm <= 1. */
+enum { ELMFB_FP64 = 0, ELMFB_FP32 = 1, ELMFB_BF16 = 2, ELMFB_FP16 = 3 };
+
+/* Or'd into the precision argument of elmfb_copy_blocks / elmfb_batch_copy_blocks: copy the
+ * block-Jacobi-folded matrix M R^{-1} (FP64) or its low-precision rounding instead of M. */
+#define ELMFB_COPY_FOLDED 0x100
 
 /* Solvers (Sec. 4.1 "Optimisation and solvers": LSQR; the others are alternatives on the
  * same matrix). */
@@ -182,7 +188,8 @@ elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
  * (prec = the descriptor's store_prec) as raw values, blocks in column order, each [K][|I_j|]
  * with the block's points in row-major order of its box, into dst_dev; and the block table
  * into table_host [n_blocks][8] as int64: level, jx, jy, ix0, nx, iy0, ny, element offset.
- * Either pointer may be NULL. */
+ * prec | ELMFB_COPY_FOLDED copies the folded M R^{-1} of elmfb_precondition in that precision
+ * instead (ELMFB_E_STATE if it was not formed).  Either pointer may be NULL. */
 elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int64_t* table_host,
                                void* stream);
 
@@ -250,6 +257,16 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
 /* offsets_host [n+1][2]: first global row and column of every instance, then the totals;
  * totals_host: summed sizes (n_pairs = 0).  Either may be NULL. */
 elmfb_status elmfb_batch_query(elmfb_batch b, int64_t* offsets_host, elmfb_sizes* totals_host);
+
+/* Copy the stored blocks of every instance into dst_dev: prec = ELMFB_FP64 (M) or the batch's
+ * store_prec (its rounded copy, until elmfb_batch_precondition replaces it), or either or'd with
+ * ELMFB_COPY_FOLDED for the folded M_b R_b^{-1} in FP64 or its rounding (after
+ * elmfb_batch_precondition); ELMFB_E_STATE when that copy is not held.  Each block is
+ * [K][nx*ny], points in row-major order of its box.  The block table goes into table_host
+ * [n_blocks][8] as int64: instance, level, ix0, nx, iy0, ny, K, element offset; blocks are
+ * ordered by instance, then by column.  Either pointer may be NULL. */
+elmfb_status elmfb_batch_copy_blocks(elmfb_batch b, int32_t prec, void* dst_dev,
+                                     int64_t* table_host, void* stream);
 
 /* Assemble every instance (FP64 plus the store_prec copy) and h = f/sqrt(N_I) per right-hand
  * side.  f_dev holds instance i at f_dev + n_rhs*row_off_i as [n_rhs][n_rows_i]. */

@@ -5,6 +5,7 @@ package only marshals arguments.  It fails loudly when the library is missing.
 """
 from .elmfb import (  # noqa: F401
     BF16,
+    FP16,
     Batch,
     CGLS,
     FP32,

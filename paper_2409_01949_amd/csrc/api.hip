@@ -91,7 +91,8 @@ std::string validate_impl(const elmfb_problem_desc* d) {
   for (int l = 0; l < d->n_levels; ++l)
     for (int a = 0; a < d->dim; ++a)
       if (d->J[l][a] < 1 || d->J[l][a] > 4096) return "J out of range";
-  if (d->store_prec != ELMFB_FP64 && d->store_prec != ELMFB_FP32 && d->store_prec != ELMFB_BF16)
+  if (d->store_prec != ELMFB_FP64 && d->store_prec != ELMFB_FP32 && d->store_prec != ELMFB_BF16 &&
+      d->store_prec != ELMFB_FP16)
     return "unknown store precision";
   if (!d->W_host || !d->b_host) return "W_host and b_host are required";
   return "";
@@ -550,10 +551,21 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
   }
   if (dst_dev) {
     if (!h->assembled) return fail(h, ELMFB_E_STATE, "copy_blocks before assemble");
+    const bool folded = (prec & ELMFB_COPY_FOLDED) != 0;
+    prec &= ~ELMFB_COPY_FOLDED;
     const void* src = nullptr;
-    if (prec == ELMFB_FP64) src = h->d_A;
-    else if (prec == h->lo_prec && h->d_A_lo) src = h->d_A_lo;
-    else return fail(h, ELMFB_E_STATE, "no stored copy in that precision");
+    if (folded) {
+      if (prec == ELMFB_FP64 && h->bj_ready && h->folded64) src = h->d_Ahat;
+      else if (prec == h->lo_prec && prec != ELMFB_FP64 && h->bj_ready && h->folded_lo)
+        src = h->d_Ahat_lo;
+      else return fail(h, ELMFB_E_STATE, "no folded copy in that precision");
+    } else if (prec == ELMFB_FP64) {
+      src = h->d_A;
+    } else if (prec == h->lo_prec && h->d_A_lo) {
+      src = h->d_A_lo;
+    } else {
+      return fail(h, ELMFB_E_STATE, "no stored copy in that precision");
+    }
     HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, src, (size_t)(h->nnz * elem_size(prec)),
                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
   }

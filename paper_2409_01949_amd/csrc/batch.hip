@@ -29,8 +29,9 @@ struct elmfb_batch_s {
   std::vector<ColTile> ctiles;
   std::vector<int64_t> foff, goff;   // per block: packed-factor and square Gram offsets
   int64_t n_rows = 0, n_phi = 0, nnz = 0, n_bp = 0, n_tab = 0, n_fac = 0, n_gsq = 0, bytes = 0;
-  int tp[3] = {32, 32, 32};          // points per LDS stage of A^T U, per matrix precision
-  bool tuned[3] = {false, false, false};
+  int tp[4] = {32, 32, 32, 32};      // points per LDS stage of A^T U, per matrix precision
+  bool tuned[4] = {false, false, false, false};
+  bool lo_unsafe = false;            // FP16 fold over an identity-fallback block: not used
 
   std::vector<void*> allocs;
   Geo* d_geos = nullptr;
@@ -184,7 +185,9 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
   return "";
 }
 
-int prec_index(int prec) { return prec == ELMFB_FP32 ? 1 : (prec == ELMFB_BF16 ? 2 : 0); }
+int prec_index(int prec) {
+  return prec == ELMFB_FP32 ? 1 : (prec == ELMFB_BF16 ? 2 : (prec == ELMFB_FP16 ? 3 : 0));
+}
 
 // The matrix the Krylov steps run on: M, or with block-Jacobi the folded M R^{-1}; FP64 or the
 // low-precision copy.
@@ -329,7 +332,7 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
     return bfail(nullptr, ELMFB_E_INVALID, pe);
   }
   const int R = n_rhs;
-  const int64_t es_lo = B->lo_prec == ELMFB_FP32 ? 4 : (B->lo_prec == ELMFB_BF16 ? 2 : 0);
+  const int64_t es_lo = B->lo_prec == ELMFB_FP64 ? 0 : elem_size(B->lo_prec);
   const int64_t nblk = (int64_t)B->blocks.size();
   int64_t bytes = B->nnz * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
                   B->n_phi * R * 8 * 4 + B->n_phi * 24 + B->n_tab * 24 +
@@ -465,6 +468,41 @@ elmfb_status elmfb_batch_query(elmfb_batch B, int64_t* offsets_host, elmfb_sizes
   return ELMFB_OK;
 }
 
+elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
+                                     int64_t* table_host, void* stream) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (table_host) {
+    for (size_t i = 0; i < B->blocks.size(); ++i) {
+      const DevBlock& d = B->blocks[i];
+      int64_t* t = table_host + 8 * i;
+      t[0] = d.inst;
+      t[1] = d.level;
+      t[2] = d.ix0;
+      t[3] = d.nx;
+      t[4] = d.iy0;
+      t[5] = d.ny;
+      t[6] = B->geos[d.inst].K;
+      t[7] = d.a_off;
+    }
+  }
+  if (dst_dev) {
+    if (!B->assembled) return bfail(B, ELMFB_E_STATE, "copy_blocks before assemble");
+    const bool folded = (prec & ELMFB_COPY_FOLDED) != 0;
+    prec &= ~ELMFB_COPY_FOLDED;
+    const void* src = nullptr;
+    if (prec == ELMFB_FP64) {
+      src = folded ? (B->bj_ready ? (const void*)B->d_Ahat : nullptr) : (const void*)B->d_A;
+    } else if (prec == B->lo_prec && B->d_A_lo) {
+      // the low-precision buffer holds M until elmfb_batch_precondition, then M R^{-1}
+      src = folded == B->lo_hat ? B->d_A_lo : nullptr;
+    }
+    if (!src) return bfail(B, ELMFB_E_STATE, "no stored copy of that kind and precision");
+    BHIP(B, hipMemcpyAsync(dst_dev, src, (size_t)(B->nnz * elem_size(prec)),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  }
+  return ELMFB_OK;
+}
+
 elmfb_status elmfb_batch_assemble(elmfb_batch B, const double* f_dev, void* stream) {
   if (!B || !f_dev) return bfail(B, ELMFB_E_INVALID, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
@@ -473,6 +511,7 @@ elmfb_status elmfb_batch_assemble(elmfb_batch B, const double* f_dev, void* stre
                         f_dev, B->d_h, B->d_flag, s));
   B->bj_ready = false;
   B->lo_hat = false;
+  B->lo_unsafe = false;
   BHIP(B, launch_bt_assemble(B->lo_prec, B->d_geos, B->d_blocks, B->d_tiles,
                              (int64_t)B->tiles.size(), B->d_tab, B->d_W, B->d_b, B->d_A,
                              B->d_A_lo, s));
@@ -560,6 +599,8 @@ elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fa
   if (n_fallback_host) *n_fallback_host = nfail;
   B->bj_ready = true;
   B->lo_hat = B->lo_prec != ELMFB_FP64;
+  // an identity fallback leaves that block's columns unscaled; their FP16 rounding may overflow
+  B->lo_unsafe = B->lo_prec == ELMFB_FP16 && nfail > 0;
   return ELMFB_OK;
 }
 
@@ -615,7 +656,7 @@ elmfb_status elmfb_batch_autotune(elmfb_batch B, int32_t prec, int32_t reps, dou
 
 elmfb_status elmfb_batch_set_tile(elmfb_batch B, int32_t prec, int32_t tile) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
-  if (prec != ELMFB_FP64 && prec != ELMFB_FP32 && prec != ELMFB_BF16)
+  if (prec != ELMFB_FP64 && prec != ELMFB_FP32 && prec != ELMFB_BF16 && prec != ELMFB_FP16)
     return bfail(B, ELMFB_E_INVALID, "bad precision");
   if (!(tile == 16 || tile == 32 || (tile == 64 && prec != ELMFB_FP64)))
     return bfail(B, ELMFB_E_INVALID, "tile must be 16, 32 or (not FP64) 64");
@@ -657,7 +698,11 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   if (opts->precond && !B->bj_ready)
     return bfail(B, ELMFB_E_STATE, "precond requested before elmfb_batch_precondition");
   if (mixed && B->lo_prec == ELMFB_FP64)
-    return bfail(B, ELMFB_E_INVALID, "MIXED_IR needs a store_prec copy (FP32 or BF16)");
+    return bfail(B, ELMFB_E_INVALID, "MIXED_IR needs a store_prec copy (FP32, BF16 or FP16)");
+  if (mixed && B->lo_prec == ELMFB_FP16 && (!opts->precond || B->lo_unsafe))
+    return bfail(B, ELMFB_E_UNSUPPORTED,
+                 "FP16 inner solves run on the folded copy of M R^-1: precondition (no identity "
+                 "fallback) and set precond");
   if (mixed && !opts->precond && B->lo_hat)
     return bfail(B, ELMFB_E_STATE,
                  "the low-precision copy holds the preconditioned matrix: assemble again for "

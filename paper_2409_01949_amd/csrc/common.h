@@ -120,33 +120,35 @@ struct BtOuter {
   int32_t done, outer, iters, istop;
 };
 
-// Convert an FP64 value to bfloat16 bits with round-to-nearest-even (IEEE definition: keep
-// 8 significant bits, or the fixed 2^-133 spacing below 2^-126; overflow to infinity).
-__host__ __device__ inline uint16_t f64_to_bf16_rne(double x) {
-  // Integer rounding of the 53-bit significand to the bf16 spacing, half to even.
+// Convert an FP64 value to the bits of a 16-bit IEEE-style format with MB stored significand
+// bits and EB exponent bits (bias 2^(EB-1) - 1) by round-to-nearest-even in one step: keep
+// MB + 1 significant bits, or the fixed spacing 2^(emin - MB) below 2^emin; overflow to
+// infinity.  bfloat16 is <7, 8>, IEEE binary16 is <10, 5>.
+template <int MB, int EB>
+__host__ __device__ inline uint16_t f64_to_small_rne(double x) {
+  constexpr int kEmax = (1 << (EB - 1)) - 1;       // also the bias
+  constexpr int kEmin = 1 - kEmax;
+  constexpr int kSub = kEmin - MB;                 // exponent of the subnormal spacing
+  constexpr uint64_t kMant = (1ull << MB) - 1;
+  constexpr uint64_t kInf = ((1ull << EB) - 1) << MB;
   union { double d; uint64_t u; } dv;
   dv.d = x;
-  uint64_t sign = dv.u >> 63;
-  uint64_t mag = dv.u & 0x7fffffffffffffffull;
+  const uint64_t sign = (dv.u >> 63) << 15;
+  const uint64_t mag = dv.u & 0x7fffffffffffffffull;
   if (mag >= 0x7ff0000000000000ull) {               // inf or nan
-    if (mag > 0x7ff0000000000000ull) return (uint16_t)((sign << 15) | 0x7fc0);
-    return (uint16_t)((sign << 15) | 0x7f80);
+    if (mag > 0x7ff0000000000000ull) return (uint16_t)(sign | kInf | (1ull << (MB - 1)));
+    return (uint16_t)(sign | kInf);
   }
-  int e = (int)(mag >> 52);                          // biased exponent
-  uint64_t frac = mag & 0xfffffffffffffull;
-  // value = 1.frac * 2^(e-1023) (normal) ; doubles here are never subnormal in practice but
-  // handle them as zero-exponent values below.
-  int exp2v = (e == 0) ? -1022 : e - 1023;
-  uint64_t sig = (e == 0) ? frac : (frac | (1ull << 52));   // 53-bit significand
-  // target spacing exponent: normal bf16 keeps 8 bits -> ulp = 2^(exp2v-7); below 2^-126 the
-  // spacing is 2^-133.
-  int ulp_e = exp2v - 7;
-  if (ulp_e < -133) ulp_e = -133;
-  // sig * 2^(exp2v-52) / 2^ulp_e = sig >> (ulp_e - exp2v + 52)
-  int sh = ulp_e - exp2v + 52;
+  const int e = (int)(mag >> 52);                    // biased FP64 exponent
+  const uint64_t frac = mag & 0xfffffffffffffull;
+  const int exp2v = (e == 0) ? -1022 : e - 1023;
+  const uint64_t sig = (e == 0) ? frac : (frac | (1ull << 52));   // value = sig 2^(exp2v-52)
+  int ulp_e = exp2v - MB;                            // spacing of the target at this binade
+  if (ulp_e < kSub) ulp_e = kSub;
+  const int sh = ulp_e - exp2v + 52;                 // q = sig / 2^sh, rounded
   uint64_t q, rem, half;
   if (sh >= 64) {
-    return (uint16_t)(sign << 15);                   // far below half the smallest spacing
+    return (uint16_t)sign;                           // far below half the smallest spacing
   } else if (sh <= 0) {
     q = sig << (-sh); rem = 0; half = 1;
   } else {
@@ -155,27 +157,39 @@ __host__ __device__ inline uint16_t f64_to_bf16_rne(double x) {
     half = 1ull << (sh - 1);
   }
   if (rem > half || (rem == half && (q & 1))) q += 1;
-  // q is the integer multiple of 2^ulp_e; rebuild the bf16 bits
-  if (q == 0) return (uint16_t)(sign << 15);
-  // normalise: find the exponent of q * 2^ulp_e
-  int msb = 63 - __builtin_clzll(q);
-  int vexp = ulp_e + msb;                            // value in [2^vexp, 2^(vexp+1))
-  uint16_t bits;
-  if (vexp < -126) {
-    // subnormal bf16: mantissa = q (spacing 2^-133), exponent field 0
-    bits = (uint16_t)(q & 0x7f);
-  } else {
-    if (vexp > 127) return (uint16_t)((sign << 15) | 0x7f80);
-    uint64_t mant = (msb >= 7) ? (q >> (msb - 7)) : (q << (7 - msb));
-    bits = (uint16_t)(((uint64_t)(vexp + 127) << 7) | (mant & 0x7f));
-  }
-  return (uint16_t)((sign << 15) | bits);
+  if (q == 0) return (uint16_t)sign;
+  // q is an integer multiple of 2^ulp_e; find the binade of q 2^ulp_e and rebuild the bits
+  const int msb = 63 - __builtin_clzll(q);
+  const int vexp = ulp_e + msb;
+  if (vexp < kEmin) return (uint16_t)(sign | (q & kMant));     // subnormal: exponent field 0
+  if (vexp > kEmax) return (uint16_t)(sign | kInf);
+  const uint64_t mant = (msb >= MB) ? (q >> (msb - MB)) : (q << (MB - msb));
+  return (uint16_t)(sign | ((uint64_t)(vexp + kEmax) << MB) | (mant & kMant));
 }
+
+__host__ __device__ inline uint16_t f64_to_bf16_rne(double x) { return f64_to_small_rne<7, 8>(x); }
+__host__ __device__ inline uint16_t f64_to_fp16_rne(double x) { return f64_to_small_rne<10, 5>(x); }
 
 __host__ __device__ inline double bf16_to_f64(uint16_t b) {
   union { float f; uint32_t u; } v;
   v.u = ((uint32_t)b) << 16;
   return (double)v.f;
+}
+
+// Exact value of IEEE binary16 bits (subnormals included).
+__host__ __device__ inline double fp16_to_f64(uint16_t h) {
+  const int e = (h >> 10) & 0x1f;
+  const int m = h & 0x3ff;
+  union { double d; uint64_t u; } v;
+  if (e == 0x1f) {
+    v.u = 0x7ff0000000000000ull | (m ? 0x8000000000000ull : 0);
+  } else if (e == 0) {
+    v.d = (double)m * 0x1p-24;                    // m 2^-24, exact
+  } else {
+    v.u = ((uint64_t)(e - 15 + 1023) << 52) | ((uint64_t)m << 42);
+  }
+  if (h & 0x8000) v.u |= 0x8000000000000000ull;
+  return v.d;
 }
 
 }  // namespace elmfb

@@ -124,5 +124,10 @@ template <>
 __device__ __forceinline__ double load_entry<ELMFB_BF16>(const void* A, int64_t i) {
   return bf16_to_f64(static_cast<const uint16_t*>(A)[i]);
 }
+template <>
+__device__ __forceinline__ double load_entry<ELMFB_FP16>(const void* A, int64_t i) {
+  // hardware conversion; exact, subnormals kept (FP16 denormals are on by default on gfx950)
+  return (double)(float)static_cast<const _Float16*>(A)[i];
+}
 
 }  // namespace elmfb

@@ -71,9 +71,13 @@ template <>
 __device__ __forceinline__ void store_entry<ELMFB_BF16>(void* A, int64_t i, double v) {
   static_cast<uint16_t*>(A)[i] = f64_to_bf16_rne(v);
 }
+template <>
+__device__ __forceinline__ void store_entry<ELMFB_FP16>(void* A, int64_t i, double v) {
+  static_cast<uint16_t*>(A)[i] = f64_to_fp16_rne(v);
+}
 
 // One workgroup per tile of <= 256 points of one block; one thread per point, looping over K.
-// LO < 0: FP64 matrix only; LO = FP32 / BF16: also its rounded copy.
+// LO < 0: FP64 matrix only; LO = FP32 / BF16 / FP16: also its rounded copy.
 template <int LO, int OP>
 __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restrict__ blocks,
                                                   const Tile* __restrict__ tiles,
@@ -191,6 +195,8 @@ hipError_t launch_assemble(const Geo& g, int lo_prec, const DevBlock* blocks, co
     return launch_assemble_p<ELMFB_FP32>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
   if (lo_prec == ELMFB_BF16)
     return launch_assemble_p<ELMFB_BF16>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
+  if (lo_prec == ELMFB_FP16)
+    return launch_assemble_p<ELMFB_FP16>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
   return launch_assemble_p<-1>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
 }
 

@@ -122,6 +122,8 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
     if constexpr (LO == ELMFB_FP32) static_cast<float*>(A_lo)[base + (int64_t)k * n] = (float)e;
     if constexpr (LO == ELMFB_BF16)
       static_cast<uint16_t*>(A_lo)[base + (int64_t)k * n] = f64_to_bf16_rne(e);
+    if constexpr (LO == ELMFB_FP16)
+      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * n] = f64_to_fp16_rne(e);
   }
 }
 
@@ -396,6 +398,7 @@ template <int PREC> struct StoreT;
 template <> struct StoreT<ELMFB_FP64> { typedef double t; };
 template <> struct StoreT<ELMFB_FP32> { typedef float t; };
 template <> struct StoreT<ELMFB_BF16> { typedef uint16_t t; };
+template <> struct StoreT<ELMFB_FP16> { typedef _Float16 t; };
 
 template <int PREC>
 __device__ __forceinline__ double to_f64(typename StoreT<PREC>::t x) {
@@ -848,6 +851,8 @@ hipError_t launch_bt_assemble(int lo_prec, const Geo* geos, const DevBlock* bloc
     hipLaunchKernelGGL(k_bt_assemble<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, tiles, tab, W, b, A, A_lo);
   else if (lo_prec == ELMFB_BF16)
     hipLaunchKernelGGL(k_bt_assemble<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, tiles, tab, W, b, A, A_lo);
+  else if (lo_prec == ELMFB_FP16)
+    hipLaunchKernelGGL(k_bt_assemble<ELMFB_FP16>, grid, blk, 0, s, geos, blocks, tiles, tab, W, b, A, A_lo);
   else
     hipLaunchKernelGGL(k_bt_assemble<-1>, grid, blk, 0, s, geos, blocks, tiles, tab, W, b, A, A_lo);
   return hipGetLastError();
@@ -868,6 +873,8 @@ hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int6
     hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   else if (prec == ELMFB_BF16)
     hipLaunchKernelGGL(k_bt_mvb<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+  else if (prec == ELMFB_FP16)
+    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP16>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   else
     hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP64>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
   return hipGetLastError();
@@ -897,6 +904,9 @@ hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* ins
   } else if (prec == ELMFB_BF16) {
     if (tp == 16) RMVB(ELMFB_BF16, 16); else if (tp == 32) RMVB(ELMFB_BF16, 32);
     else if (tp == 64) RMVB(ELMFB_BF16, 64); else return hipErrorInvalidValue;
+  } else if (prec == ELMFB_FP16) {
+    if (tp == 16) RMVB(ELMFB_FP16, 16); else if (tp == 32) RMVB(ELMFB_FP16, 32);
+    else if (tp == 64) RMVB(ELMFB_FP16, 64); else return hipErrorInvalidValue;
   } else {
     // FP64 stages of 64 points exceed the static LDS limit
     if (tp == 16) RMVB(ELMFB_FP64, 16); else if (tp == 32) RMVB(ELMFB_FP64, 32);

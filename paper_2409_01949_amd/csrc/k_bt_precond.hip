@@ -240,6 +240,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
           if (Ahat) Ahat[o] = val;
           if constexpr (LO == ELMFB_FP32) static_cast<float*>(Ahat_lo)[o] = (float)val;
           if constexpr (LO == ELMFB_BF16) static_cast<uint16_t*>(Ahat_lo)[o] = f64_to_bf16_rne(val);
+          if constexpr (LO == ELMFB_FP16) static_cast<uint16_t*>(Ahat_lo)[o] = f64_to_fp16_rne(val);
         }
       }
     }
@@ -259,6 +260,7 @@ hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const Geo* geos,
 #define FOLD_T(L, F) do { if (kmax > 128) FOLD(L, F, 4); else FOLD(L, F, 2); } while (0)
   if (lo_prec == ELMFB_FP32) { if (full) FOLD_T(ELMFB_FP32, true); else FOLD_T(ELMFB_FP32, false); }
   else if (lo_prec == ELMFB_BF16) { if (full) FOLD_T(ELMFB_BF16, true); else FOLD_T(ELMFB_BF16, false); }
+  else if (lo_prec == ELMFB_FP16) { if (full) FOLD_T(ELMFB_FP16, true); else FOLD_T(ELMFB_FP16, false); }
   else { if (full) FOLD_T(-1, true); else FOLD_T(-1, false); }
 #undef FOLD_T
 #undef FOLD

@@ -8,7 +8,8 @@
 // and accumulates X Y^T on the matrix cores:
 //   FP64 blocks: v_mfma_f64_16x16x4_f64 (8 steps per stage),
 //   FP32 blocks: v_mfma_f32_16x16x4_f32 (8 steps),
-//   BF16 blocks: v_mfma_f32_16x16x32_bf16 (1 step), FP32 accumulation.
+//   BF16 blocks: v_mfma_f32_16x16x32_bf16 (1 step), FP32 accumulation,
+//   FP16 blocks: v_mfma_f32_16x16x32_f16 (1 step), FP32 accumulation.
 // A pair with one chunk writes its block directly; a pair with several chunks writes chunk
 // partials that a second kernel sums in chunk order (deterministic, no atomics).
 #include "device.h"
@@ -19,6 +20,7 @@ namespace elmfb {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kStage = 32;        // points per LDS stage
 constexpr int kTilesPerGroup = 64; // 16 per wave
@@ -27,6 +29,7 @@ template <int PREC> struct GramTypes;
 template <> struct GramTypes<ELMFB_FP64> { typedef double in_t; typedef double acc_t; typedef d4_t v4; };
 template <> struct GramTypes<ELMFB_FP32> { typedef float in_t; typedef float acc_t; typedef f4_t v4; };
 template <> struct GramTypes<ELMFB_BF16> { typedef __bf16 in_t; typedef float acc_t; typedef f4_t v4; };
+template <> struct GramTypes<ELMFB_FP16> { typedef _Float16 in_t; typedef float acc_t; typedef f4_t v4; };
 
 template <int PREC>
 __device__ __forceinline__ typename GramTypes<PREC>::in_t load_in(const void* A, int64_t i);
@@ -43,6 +46,10 @@ __device__ __forceinline__ __bf16 load_in<ELMFB_BF16>(const void* A, int64_t i) 
   const uint16_t bits = static_cast<const uint16_t*>(A)[i];
   return __builtin_bit_cast(__bf16, bits);
 }
+template <>
+__device__ __forceinline__ _Float16 load_in<ELMFB_FP16>(const void* A, int64_t i) {
+  return static_cast<const _Float16*>(A)[i];
+}
 
 template <int PREC>
 __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict__ blocks,
@@ -54,7 +61,8 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
   typedef typename GramTypes<PREC>::in_t in_t;
   typedef typename GramTypes<PREC>::acc_t acc_t;
   typedef typename GramTypes<PREC>::v4 v4;
-  constexpr int STR = (PREC == ELMFB_BF16) ? (kStage + 8) : (kStage + 1);   // LDS row stride
+  constexpr bool k16 = PREC == ELMFB_BF16 || PREC == ELMFB_FP16;
+  constexpr int STR = k16 ? (kStage + 8) : (kStage + 1);   // LDS row stride
   extern __shared__ __align__(16) unsigned char smem[];
   const int K = g.K;
   const int Kp = (K + 15) & ~15;
@@ -115,6 +123,11 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
 #pragma unroll
           for (int q = 0; q < 8; ++q) { a[q] = xr[8 * lq + q]; b[q] = yr[8 * lq + q]; }
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+        } else if constexpr (PREC == ELMFB_FP16) {
+          h8_t a, b;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) { a[q] = xr[8 * lq + q]; b[q] = yr[8 * lq + q]; }
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[i], 0, 0, 0);
         } else if constexpr (PREC == ELMFB_FP32) {
 #pragma unroll
           for (int q = 0; q < kStage; q += 4)
@@ -165,7 +178,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Geo g, const GramPair* __re
 static size_t gram_smem(int prec, int K) {
   const int Kp = (K + 15) & ~15;
   const size_t es = prec == ELMFB_FP64 ? 8 : (prec == ELMFB_FP32 ? 4 : 2);
-  const int str = prec == ELMFB_BF16 ? kStage + 8 : kStage + 1;
+  const int str = (prec == ELMFB_BF16 || prec == ELMFB_FP16) ? kStage + 8 : kStage + 1;
   return 2 * (size_t)Kp * str * es + 2 * kStage * sizeof(int) + 16;
 }
 
@@ -187,8 +200,11 @@ hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const Gra
     else if (prec == ELMFB_FP32)
       ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP32>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    else
+    else if (prec == ELMFB_BF16)
       ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_BF16>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    else
+      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP16>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (ea != hipSuccess) return ea;
   }
@@ -198,8 +214,11 @@ hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const Gra
   } else if (prec == ELMFB_FP32) {
     hipLaunchKernelGGL(k_gram<ELMFB_FP32>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
                        (float*)G, (float*)part);
-  } else {
+  } else if (prec == ELMFB_BF16) {
     hipLaunchKernelGGL(k_gram<ELMFB_BF16>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
+                       (float*)G, (float*)part);
+  } else {
+    hipLaunchKernelGGL(k_gram<ELMFB_FP16>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
                        (float*)G, (float*)part);
   }
   hipError_t e = hipGetLastError();

@@ -236,6 +236,8 @@ hipError_t launch_mv_blocks(const Geo& g, int prec, const DevBlock* blocks, cons
     hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
   else if (prec == ELMFB_BF16)
     hipLaunchKernelGGL(k_mv_blocks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
+  else if (prec == ELMFB_FP16)
+    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP16>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
   else
     hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
   return hipGetLastError();
@@ -259,6 +261,8 @@ hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, con
     hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
   else if (prec == ELMFB_BF16)
     hipLaunchKernelGGL(k_rmv_chunks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
+  else if (prec == ELMFB_FP16)
+    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP16>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
   else
     hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
   return hipGetLastError();

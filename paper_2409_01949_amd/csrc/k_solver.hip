@@ -312,6 +312,8 @@ hipError_t launch_sumsq_entries(int prec, const void* A, int64_t n, double* red,
     hipLaunchKernelGGL(k_sumsq_entries<ELMFB_FP32>, dim3(n_wg), dim3(256), 0, s, A, n, red);
   else if (prec == ELMFB_BF16)
     hipLaunchKernelGGL(k_sumsq_entries<ELMFB_BF16>, dim3(n_wg), dim3(256), 0, s, A, n, red);
+  else if (prec == ELMFB_FP16)
+    hipLaunchKernelGGL(k_sumsq_entries<ELMFB_FP16>, dim3(n_wg), dim3(256), 0, s, A, n, red);
   else
     hipLaunchKernelGGL(k_sumsq_entries<ELMFB_FP64>, dim3(n_wg), dim3(256), 0, s, A, n, red);
   return hipGetLastError();

@@ -374,7 +374,7 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
   // memory with an 8 GB margin; otherwise those solves apply R^{-1} in every step
   h->folded64 = h->folded_lo = false;
   {
-    const int64_t es_lo = h->lo_prec == ELMFB_FP32 ? 4 : (h->lo_prec == ELMFB_BF16 ? 2 : 0);
+    const int64_t es_lo = h->lo_prec == ELMFB_FP64 ? 0 : elem_size(h->lo_prec);
     const int64_t margin = (int64_t)8 << 30;
     auto fits = [&](int64_t bytes) {
       size_t free_b = 0, total_b = 0;
@@ -408,6 +408,9 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
   HIP_OR_FAIL(h, hipMemcpyAsync(&nf, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
   if (n_fallback) *n_fallback = nf;
+  // an identity fallback leaves that block's columns unscaled, and their FP16 rounding may
+  // overflow: such a copy is not used
+  if (nf > 0 && h->lo_prec == ELMFB_FP16) h->folded_lo = false;
   h->bj_ready = true;
   return ELMFB_OK;
 }
@@ -433,6 +436,10 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
     if (opts->inner_iters < 1 || opts->outer_lim < 0)
       return fail(h, ELMFB_E_INVALID, "MIXED_IR needs inner_iters >= 1 and outer_lim >= 0");
     if (!h->d_A_lo) return fail(h, ELMFB_E_STATE, "MIXED_IR needs a low-precision stored copy");
+    if (h->lo_prec == ELMFB_FP16 && !(bj && h->folded_lo))
+      return fail(h, ELMFB_E_UNSUPPORTED,
+                  "FP16 inner solves run on the folded copy of M R^-1: precondition (no identity "
+                  "fallback) and set precond");
   }
   const Geo& g = h->geo;
   hipStream_t caller = (hipStream_t)stream;

@@ -22,12 +22,13 @@ MAX_LEVELS = 8
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = range(7)
 OP_D1, OP_NEG_LAPLACE, OP_IDENTITY = 1, 2, 3
 ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, FP16 = 0, 1, 2, 3
+COPY_FOLDED = 0x100
 LSQR, CGLS, MIXED_IR = 0, 1, 2
 
 _OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY}
 _ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
-_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
 _METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR}
 
 
@@ -139,6 +140,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_define_batch": (i32, [ctypes.POINTER(ProblemDesc), i32, i32, ctypes.POINTER(P)]),
         "elmfb_batch_query": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(Sizes)]),
         "elmfb_batch_assemble": (i32, [P, P, P]),
+        "elmfb_batch_copy_blocks": (i32, [P, i32, P, ctypes.POINTER(i64), P]),
         "elmfb_batch_matvec": (i32, [P, P, P, P]),
         "elmfb_batch_rmatvec": (i32, [P, P, P, P]),
         "elmfb_batch_precondition": (i32, [P, ctypes.c_double, ctypes.POINTER(i32), P]),
@@ -273,11 +275,14 @@ class Problem:
     def copy_rhs(self, hvec, stream=None):
         _check(_lib.elmfb_copy_rhs(self.h, _ptr(hvec), _stream(stream)), self.h)
 
-    def copy_blocks(self, dst=None, prec="fp64", stream=None):
-        """Returns the block table [n_blocks, 8] (int64); copies raw blocks into dst if given."""
+    def copy_blocks(self, dst=None, prec="fp64", folded=False, stream=None):
+        """Returns the block table [n_blocks, 8] (int64); copies raw blocks into dst if given
+        (folded: the block-Jacobi-folded M R^-1 instead of M)."""
         nb = self.sizes["n_blocks"]
         table = np.zeros((nb, 8), dtype=np.int64)
         pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        if folded:
+            pr |= COPY_FOLDED
         _check(_lib.elmfb_copy_blocks(self.h, pr, _ptr(dst) if dst is not None else None,
                                       table.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       _stream(stream)), self.h)
@@ -386,6 +391,18 @@ class Batch:
 
     def assemble(self, f, stream=None):
         self._check(_lib.elmfb_batch_assemble(self.h, _ptr(f), _stream(stream)))
+
+    def copy_blocks(self, dst=None, prec="fp64", folded=False, stream=None):
+        """Block table [n_blocks, 8] (instance, level, ix0, nx, iy0, ny, K, element offset);
+        copies the raw blocks of M (or, folded, of M R^-1) in precision prec into dst if given."""
+        table = np.zeros((self.sizes["n_blocks"], 8), dtype=np.int64)
+        pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        if folded:
+            pr |= COPY_FOLDED
+        self._check(_lib.elmfb_batch_copy_blocks(
+            self.h, pr, _ptr(dst) if dst is not None else None,
+            table.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(stream)))
+        return table
 
     def matvec(self, v, y, stream=None):
         self._check(_lib.elmfb_batch_matvec(self.h, _ptr(v), _ptr(y), _stream(stream)))

@@ -32,13 +32,15 @@ def build(spec, store_prec="fp64", f=None):
     return P, W, b, f
 
 
-def device_blocks(P, K, store_prec="fp64"):
-    """[(table_row, M_j [n_j, K] float64)] from the device block storage."""
+def device_blocks(P, K, store_prec="fp64", folded=False):
+    """[(table_row, M_j [n_j, K] float64)] from the device block storage (folded: the
+    block-Jacobi-folded M R^-1)."""
     torch = torch_mod()
     nnz = P.sizes["nnz"]
-    dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16}[store_prec]
+    dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16,
+          "fp16": torch.float16}[store_prec]
     buf = torch.empty(nnz, dtype=dt, device="cuda")
-    table = P.copy_blocks(buf, prec=store_prec)
+    table = P.copy_blocks(buf, prec=store_prec, folded=folded)
     torch.cuda.synchronize()
     host = buf.float().double().cpu().numpy() if store_prec == "bf16" else \
         buf.double().cpu().numpy()
@@ -59,3 +61,57 @@ def block_rows(row, n_y):
 
 def n_y(spec):
     return spec.n_points[1] if spec.dim == 2 else 1
+
+
+def fold_tolerance(M_hat, K, shift):
+    """Entry tolerance between two FP64 evaluations of the folded block M_j R_j^{-1}: the Gram
+    block G + lambda I (lambda = shift trace(G)/K) has condition number up to about K/shift, so
+    rounding differences of the Gram products change R_j, and M_j R_j^{-1} with it, by a small
+    multiple of K eps / shift relative to the block's largest entry (measured: up to 0.8 of it
+    on the test problems; the factor 4 is the margin)."""
+    return 4.0 * K * np.finfo(np.float64).eps / shift * np.abs(M_hat).max()
+
+
+def n_ambiguous(ref, rounding, tol):
+    """Entries of ref that lie within tol of a rounding boundary of `rounding`."""
+    r = rounding(ref)
+    return int(np.sum((rounding(ref - tol) != r) | (rounding(ref + tol) != r)))
+
+
+def check_rounded_fold(got, ref, rounding, tol):
+    """The low-precision folded copy `got` is the rounding of an FP64 product within tol of the
+    oracle's `ref`: rounding is monotone, so got lies between the roundings of ref - tol and
+    ref + tol, and equals the rounding of ref wherever no boundary lies that close.  Returns
+    (mismatches, ambiguous entries)."""
+    r = rounding(ref)
+    lo, hi = rounding(ref - tol), rounding(ref + tol)
+    ambiguous = (lo != r) | (hi != r)
+    mism = got != r
+    assert not np.any(mism & ~ambiguous)
+    assert np.all((got >= lo) & (got <= hi))
+    return int(mism.sum()), int(ambiguous.sum())
+
+
+def rounded_variants(folded_blocks, rounding, K, shift, limit=4):
+    """Every low-precision folded matrix the device may hold: the oracle's rounding of its
+    M_j R_j^{-1}, with each entry that lies within fold_tolerance of a rounding boundary taking
+    either neighbour (at most `limit` such entries, so 2^limit variants)."""
+    base = [rounding(b.M) for b in folded_blocks]
+    amb = []
+    for bi, b in enumerate(folded_blocks):
+        tol = fold_tolerance(b.M, K, shift)
+        lo, hi = rounding(b.M - tol), rounding(b.M + tol)
+        r = base[bi]
+        for idx in zip(*np.nonzero((lo != r) | (hi != r))):
+            amb.append((bi, idx, lo[idx] if lo[idx] != r[idx] else hi[idx]))
+    assert len(amb) <= limit, f"{len(amb)} entries lie within the fold tolerance of a boundary"
+    out = []
+    for mask in range(2 ** len(amb)):
+        Ms = list(base)
+        for t, (bi, idx, alt) in enumerate(amb):
+            if mask >> t & 1:
+                if Ms[bi] is base[bi]:
+                    Ms[bi] = base[bi].copy()
+                Ms[bi][idx] = alt
+        out.append(Ms)
+    return out

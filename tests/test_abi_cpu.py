@@ -45,7 +45,7 @@ def _spec_desc(**over):
 
 @pytest.mark.parametrize("field,value", [
     ("abi_version", 99), ("dim", 3), ("op", 1), ("op", 7), ("ansatz", 5), ("delta", 0.9),
-    ("delta", 7.5), ("K", 0), ("K", 257), ("n_levels", 0), ("n_levels", 9), ("store_prec", 3),
+    ("delta", 7.5), ("K", 0), ("K", 257), ("n_levels", 0), ("n_levels", 9), ("store_prec", 4),
 ])
 def test_invalid_descriptors_are_rejected(field, value):
     from paper_2409_01949_amd import elmfb

@@ -8,7 +8,7 @@ from inputs import configs, feature_params
 from oracle import assemble as asm
 from oracle import linalg, lowprec
 
-from gpu_util import dev, torch_mod
+from gpu_util import check_rounded_fold, dev, fold_tolerance, rounded_variants, torch_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -28,9 +28,9 @@ def _forcing(spec, r):
     return np.stack([base * (1.0 + 0.5 * j) for j in range(r)])
 
 
-def _make(store_prec):
+def _make(store_prec, specs=None):
     from paper_2409_01949_amd import Batch
-    specs = _batch_specs()
+    specs = _batch_specs() if specs is None else specs
     feats = [feature_params(s) for s in specs]
     B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R, store_prec=store_prec)
     fs = [_forcing(s, R) for s in specs]
@@ -221,9 +221,30 @@ def test_batch_mixed_refinement_matches_oracle(batch32):
     inner steps every pair equals the oracle's refinement on its folded blocks, mapped back by
     R^{-1}.  The FP32 copies come from FP64 products summed in different orders, so an entry
     next to a rounding boundary may round differently: tolerance 1e-7."""
-    B, oracle = batch32
+    _mixed_vs_oracle(*batch32, lowprec.to_f32)
+
+
+def test_batch_mixed_refinement_fp16_matches_oracle():
+    """The same refinement on the IEEE binary16 rounding of the folded M R^{-1}; refinement on
+    the unfolded FP16 copy is refused.  An FP16 entry that rounds differently moves the
+    coefficients by 1e-6 to 1e-4 (measured on the oracle), so the shift is 1e-3, which leaves few
+    entries within fold_tolerance of a boundary, and the device result must match the oracle's
+    refinement on one of the admissible roundings.  small2d (many such entries) is left out."""
+    B, oracle = _make("fp16", [s for s in _batch_specs() if s.name != "small2d"])
     torch = torch_mod()
-    shift = 1e-6
+    coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception, match="FP16"):
+        B.solve(coef, method="mixed_ir", inner_iters=5, outer_lim=1, precond=False, atol=0.0,
+                btol=0.0)
+    _mixed_vs_oracle(B, oracle, lowprec.to_fp16, shift=1e-3)
+    B.destroy()
+
+
+def _mixed_vs_oracle(B, oracle, rounding, shift=1e-6):
+    """After 1 and 2 outer steps of 5 inner steps every pair equals the oracle's refinement on
+    its folded blocks (for FP16: on one of the admissible roundings, rounded_variants), mapped
+    back by R^{-1}, to 1e-7 in the coefficients."""
+    torch = torch_mod()
     B.precondition(shift)
     inner = 5
     for outer in (1, 2):
@@ -233,23 +254,79 @@ def test_batch_mixed_refinement_matches_oracle(batch32):
         cs = _coefs(B, coef, oracle)
         worst = 0.0
         for i, (s, bl, h) in enumerate(oracle):
+            wi = 0.0
             n = len(bl) * s.K
             facs = linalg.block_jacobi_factors(bl, shift)
             fb = linalg.fold_blocks(bl, facs)
-            lo = [asm.Block(blk.sd, blk.rows, lowprec.to_f32(blk.M)) for blk in fb]
+            if rounding is lowprec.to_fp16:
+                variants = rounded_variants(fb, rounding, s.K, shift)
+            else:
+                variants = [[rounding(blk.M) for blk in fb]]
+            los = [[asm.Block(blk.sd, blk.rows, Mv) for blk, Mv in zip(fb, Ms)] for Ms in variants]
             for j in range(R):
-                cy, hist = linalg.refine_lsqr(
-                    lambda v: asm.matvec(fb, v, s.n_rows), lambda u: asm.rmatvec(fb, u, n),
-                    lambda v: asm.matvec(lo, v, s.n_rows), lambda u: asm.rmatvec(lo, u, n), h[j],
-                    n, outer, inner)
-                c = linalg.block_apply(bl, facs, cy)
                 info = infos[i * R + j]
                 assert info["outer_iters"] == outer and info["iters"] == outer * inner
-                worst = max(worst, np.linalg.norm(cs[i][j] - c) / np.linalg.norm(c))
+                best = np.inf
+                for lo in los:
+                    cy, hist = linalg.refine_lsqr(
+                        lambda v: asm.matvec(fb, v, s.n_rows), lambda u: asm.rmatvec(fb, u, n),
+                        lambda v: asm.matvec(lo, v, s.n_rows), lambda u: asm.rmatvec(lo, u, n),
+                        h[j], n, outer, inner)
+                    c = linalg.block_apply(bl, facs, cy)
+                    best = min(best, np.linalg.norm(cs[i][j] - c) / np.linalg.norm(c))
+                wi = max(wi, best)
                 r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j])
                 assert abs(info["rnorm"] - r) <= 1e-9 * np.linalg.norm(h[j])
+            print(f"  instance {i} ({s.name}): coefficient rel diff {wi:.2e} "
+                  f"({len(los)} admissible roundings)")
+            worst = max(worst, wi)
         print(f"mixed outer={outer}: worst coefficient rel diff {worst:.2e}")
         assert worst <= 1e-7
+
+
+@pytest.mark.parametrize("store", ["fp32", "fp16"])
+def test_batch_folded_copies_match_oracle(store):
+    """elmfb_batch_precondition forms M_b R_b^{-1} for every block of every instance: the FP64
+    folded blocks equal the oracle's within the sensitivity of the shifted Cholesky factor
+    (fold_tolerance) and the low-precision copy is their rounding to nearest even (entries within
+    that distance of a boundary may round either way); the copy of M in that precision is no
+    longer held."""
+    B, oracle = _make(store)
+    torch = torch_mod()
+    shift = 1e-4
+    B.precondition(shift)
+    nnz = B.sizes["nnz"]
+    b64 = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    blo = torch.empty(nnz, dtype={"fp32": torch.float32, "fp16": torch.float16}[store],
+                      device="cuda")
+    table = B.copy_blocks(b64, "fp64", folded=True)
+    B.copy_blocks(blo, store, folded=True)
+    with pytest.raises(Exception):
+        B.copy_blocks(blo, store, folded=False)
+    torch.cuda.synchronize()
+    h64, hlo = b64.cpu().numpy(), blo.double().cpu().numpy()
+    rounding = lowprec.to_f32 if store == "fp32" else lowprec.to_fp16
+    k, worst, nm, na = 0, 0.0, 0, 0
+    for i, (s, bl, _) in enumerate(oracle):
+        fb = linalg.fold_blocks(bl, linalg.block_jacobi_factors(bl, shift))
+        for blk in fb:
+            inst, lvl, ix0, nx, iy0, ny, K, off = (int(v) for v in table[k])
+            k += 1
+            npt = nx * ny
+            assert inst == i and K == s.K and npt == blk.M.shape[0]
+            A64 = h64[off:off + K * npt].reshape(K, npt).T
+            Alo = hlo[off:off + K * npt].reshape(K, npt).T
+            tol = fold_tolerance(blk.M, K, shift)
+            err = np.abs(A64 - blk.M).max()
+            worst = max(worst, err / tol)
+            assert err <= tol
+            m, a = check_rounded_fold(Alo, blk.M, rounding, tol)
+            nm += m
+            na += a
+    assert k == len(table)
+    print(f"batch {store}: FP64 fold worst {worst:.2f} of its tolerance; rounded copy {nm} entries "
+          f"off the oracle's rounding, {na} within tolerance of a boundary")
+    B.destroy()
 
 
 def test_batch_mixed_solve_to_tolerance(batch32):

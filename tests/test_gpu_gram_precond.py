@@ -1,4 +1,4 @@
-"""GPU parity of the Gram blocks (matrix cores, FP64 / FP32 / BF16 inputs), the low-precision
+"""GPU parity of the Gram blocks (matrix cores, FP64 / FP32 / BF16 / FP16 inputs), the low-precision
 stored copies, block-Jacobi preconditioned LSQR and FP64 refinement around low-precision inner
 LSQR, against the CPU oracle."""
 import numpy as np
@@ -12,7 +12,8 @@ from oracle import geometry as geo
 from oracle import linalg
 from oracle import lowprec
 
-from gpu_util import build, dev, device_blocks, torch_mod
+from gpu_util import (build, check_rounded_fold, dev, device_blocks, fold_tolerance, n_ambiguous,
+                      torch_mod)
 
 pytestmark = pytest.mark.gpu
 
@@ -188,3 +189,102 @@ def test_mixed_refinement_matches_oracle(case32):
               f"(oracle last {hist[-1]:.4e}), inner iters {info['iters']}")
         assert info["outer_iters"] == outer and info["iters"] == outer * inner
         assert du <= 1e-7
+
+
+def test_fp16_copy_and_gram_blocks():
+    """The IEEE binary16 stored copy equals the oracle's entries rounded to nearest even (one
+    unit in the last place where the FP64 values differ in their last bits), and the FP16 Gram
+    blocks (v_mfma_f32_16x16x32_f16, FP32 accumulation) match the oracle's products of the
+    rounded entries to 1e-5 of the block max."""
+    spec = configs.small2d()
+    P, W, b, f = build(spec, store_prec="fp16")
+    blocks = asm.assemble_blocks(spec, W, b)
+    bad = total = 0
+    for (row, Mg), blk in zip(device_blocks(P, spec.K, "fp16"), blocks):
+        ref = lowprec.to_fp16(blk.M)
+        ulp = np.maximum(np.abs(ref) * 2.0 ** -10, 2.0 ** -24)
+        assert np.all(np.abs(Mg - ref) <= ulp)
+        bad += int(np.sum(Mg != ref))
+        total += ref.size
+    print(f"small2d fp16 copy: {bad} of {total} entries one ulp off RNE(oracle)")
+    assert bad <= max(2, total * 1e-5)
+    pairs = geo.overlap_pairs(spec, [blk.rows for blk in blocks])
+    ref = linalg.gram_blocks(blocks, pairs, entry_map=lowprec.to_fp16)
+    got = _gram_dense(P, spec, "fp16")
+    assert set(got.keys()) == set(ref.keys())
+    worst = max(np.abs(got[k] - R).max() / max(np.abs(R).max(), 1e-300) for k, R in ref.items())
+    print(f"small2d fp16 Gram: worst blockwise rel err {worst:.2e}")
+    assert worst <= 1e-5
+    P.destroy()
+
+
+def test_mixed_refinement_fp16_folded_matches_oracle():
+    """FP64 refinement around inner LSQR on the IEEE binary16 rounding of the folded matrix
+    M R^{-1}: GPU and oracle agree after each of the first outer steps (the same protocol as the
+    FP32 case); the refinement without the folded copy is refused.  An FP16 entry that rounds
+    differently moves the result by far more than the tolerance, so the shift is 1e-2: no entry
+    of the oracle's FP16 rounding then lies within fold_tolerance of a boundary (checked), and
+    both sides run the same inner matrix."""
+    spec = configs.small2d()
+    torch = torch_mod()
+    P, W, b, f = build(spec, store_prec="fp16")
+    n = P.sizes["n_phi"]
+    coef = torch.empty(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception, match="FP16"):
+        P.solve(coef, method="mixed_ir", inner_iters=5, outer_lim=1, precond=False, atol=0, btol=0)
+    blocks = asm.assemble_blocks(spec, W, b)
+    h = asm.rhs(spec, f)
+    shift = 1e-2
+    assert P.precondition(shift) == 0
+    N = spec.n_rows
+    facs = linalg.block_jacobi_factors(blocks, shift)
+    fb = linalg.fold_blocks(blocks, facs)
+    assert max(np.abs(blk.M).max() for blk in fb) <= 1.0 + 1e-12   # columns of norm <= 1
+    for blk in fb:
+        assert n_ambiguous(blk.M, lowprec.to_fp16, fold_tolerance(blk.M, spec.K, shift)) == 0
+    lo = [asm.Block(blk.sd, blk.rows, lowprec.to_fp16(blk.M)) for blk in fb]
+    xt = grid_points(spec, spec.meta["n_test"])
+    inner = 5
+    for outer in (1, 2):
+        info = P.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, check_every=5,
+                       precond=True, atol=0, btol=0)
+        cy, hist = linalg.refine_lsqr(lambda v: asm.matvec(fb, v, N),
+                                      lambda u: asm.rmatvec(fb, u, n),
+                                      lambda v: asm.matvec(lo, v, N),
+                                      lambda u: asm.rmatvec(lo, u, n), h, n, outer, inner)
+        c = linalg.block_apply(blocks, facs, cy)
+        du = ev.rel_l2(ev.evaluate(spec, W, b, coef.cpu().numpy(), xt), ev.evaluate(spec, W, b, c, xt))
+        print(f"{spec.name} fp16 mixed outer={outer}: u diff {du:.2e}, outer ||r|| "
+              f"{info['rnorm']:.4e} (oracle last {hist[-1]:.4e})")
+        assert info["outer_iters"] == outer and info["iters"] == outer * inner
+        assert du <= 1e-7
+    P.destroy()
+
+
+@pytest.mark.parametrize("store", ["fp32", "fp16"])
+@pytest.mark.parametrize("spec", [configs.small2d(), configs.medium2d()], ids=lambda s: s.name)
+def test_folded_copies_match_oracle(spec, store):
+    """elmfb_precondition forms M R^{-1} once: the FP64 folded blocks equal the oracle's
+    M_j R_j^{-1} within the sensitivity of the shifted Cholesky factor (fold_tolerance), and the
+    low-precision folded copy is their rounding to nearest even (an entry within that distance
+    of a rounding boundary may round either way)."""
+    P, W, b, f = build(spec, store_prec=store)
+    blocks = asm.assemble_blocks(spec, W, b)
+    shift = 1e-4
+    P.precondition(shift)
+    fb = linalg.fold_blocks(blocks, linalg.block_jacobi_factors(blocks, shift))
+    rounding = lowprec.to_f32 if store == "fp32" else lowprec.to_fp16
+    g64 = device_blocks(P, spec.K, "fp64", folded=True)
+    glo = device_blocks(P, spec.K, store, folded=True)
+    worst, nm, na = 0.0, 0, 0
+    for (_, A64), (_, Alo), blk in zip(g64, glo, fb):
+        tol = fold_tolerance(blk.M, spec.K, shift)
+        err = np.abs(A64 - blk.M).max()
+        worst = max(worst, err / tol)
+        assert err <= tol
+        m, a = check_rounded_fold(Alo, blk.M, rounding, tol)
+        nm += m
+        na += a
+    print(f"{spec.name} {store}: FP64 fold worst {worst:.2f} of its tolerance; rounded copy "
+          f"{nm} entries off the oracle's rounding, {na} within tolerance of a boundary")
+    P.destroy()

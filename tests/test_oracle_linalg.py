@@ -177,6 +177,24 @@ def test_bf16_rounding_against_torch_and_ties():
     assert lowprec.to_f32(np.array([1.0 + 2.0 ** -24]))[0] == 1.0
 
 
+def test_fp16_rounding_against_numpy_and_ties():
+    """IEEE binary16 rounding: numpy's one-step float64 -> float16 cast (a separate
+    implementation) on a wide random sample, and the tie, double-rounding, subnormal and
+    overflow cases by hand."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(1, 2, 200000) * 2.0 ** rng.integers(-30, 17, 200000) * rng.choice([-1, 1], 200000)
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(lowprec.to_fp16(x), ref)
+    f = lambda v: lowprec.to_fp16(np.array([v]))[0]
+    assert f(1.0 + 2.0 ** -11) == 1.0                          # tie -> even (down)
+    assert f(1.0 + 3 * 2.0 ** -11) == 1.0 + 2.0 ** -9          # tie -> even (up)
+    assert f(1.0 + 2.0 ** -11 + 2.0 ** -40) == 1.0 + 2.0 ** -10  # no double rounding via FP32
+    assert f(2.0 ** -25) == 0.0 and f(3 * 2.0 ** -26) == 2.0 ** -24   # subnormal spacing 2^-24
+    assert f(2.0 ** -14 - 2.0 ** -26) == 2.0 ** -14           # rounds up into the normal range
+    assert f(65519.0) == 65504.0 and np.isinf(f(65520.0))      # largest finite, overflow tie
+
+
 def test_evaluate_single_feature_closed_form():
     """One level, one subdomain, one feature: u = C(x) a tanh(W xbar + b)."""
     spec = configs.tiny1d(K=1, J=1, n=10)
