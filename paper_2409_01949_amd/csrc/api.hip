@@ -211,7 +211,7 @@ std::string plan_impl(elmfb_problem h) {
   h->tiles.clear();
   h->chunks.clear();
   h->chunk_start.clear();
-  int64_t a_off = 0, p_off = 0;
+  int64_t a_off = 0, p_off = 0, nnz = 0;
   for (int l = 0; l < d.n_levels; ++l)
     for (int jx = 0; jx < g.J[l][0]; ++jx)
       for (int jy = 0; jy < g.J[l][1]; ++jy) {
@@ -226,6 +226,7 @@ std::string plan_impl(elmfb_problem h) {
         const int64_t n = (int64_t)B.nx * B.ny;
         if (n > (int64_t)1 << 30) return "block too large";
         B.n = (int32_t)n;
+        B.ld = (int32_t)((n + kRowAlign - 1) / kRowAlign * kRowAlign);
         B.tabx = segoff[l][0][jx];
         B.taby = segoff[l][1][jy];
         B.level = l;
@@ -234,11 +235,13 @@ std::string plan_impl(elmfb_problem h) {
         h->chunk_start.push_back((int32_t)h->chunks.size());
         for (int64_t p0 = 0; p0 < n; p0 += kChunkPts) h->chunks.push_back(Tile{b, (int32_t)p0});
         h->blocks.push_back(B);
-        a_off += n * d.K;
+        a_off += (int64_t)B.ld * d.K;
+        nnz += n * d.K;
         p_off += n;
       }
   h->chunk_start.push_back((int32_t)h->chunks.size());
-  h->nnz = a_off;
+  h->nnz = nnz;
+  h->n_store = a_off;
   h->n_block_points = p_off;
 
   // overlapping pairs (i <= j) over all levels: on level l the subdomains meeting a box are the
@@ -282,8 +285,8 @@ int64_t footprint(elmfb_problem h) {
   const Geo& g = h->geo;
   int64_t b = 0;
   auto add = [&](int64_t n) { b += (n + 255) / 256 * 256; };
-  add(h->nnz * 8);                                        // FP64 matrix
-  if (h->lo_prec != ELMFB_FP64) add(h->nnz * elem_size(h->lo_prec));   // low-precision copy
+  add(h->n_store * 8);                                    // FP64 matrix
+  if (h->lo_prec != ELMFB_FP64) add(h->n_store * elem_size(h->lo_prec));   // low-precision copy
   add(h->n_block_points * 8);                             // tpart
   add((int64_t)h->chunks.size() * g.K * 8);               // part
   add(4 * 2 * kRedBlocks * 8);                            // reductions
@@ -379,8 +382,8 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
                                               hipGetErrorString(e_));      \
     }                                                                       \
   } while (0)
-  ALLOC(h->d_A, h->nnz * 8);
-  if (h->lo_prec != ELMFB_FP64) ALLOC(h->d_A_lo, h->nnz * elem_size(h->lo_prec));
+  ALLOC(h->d_A, h->n_store * 8);
+  if (h->lo_prec != ELMFB_FP64) ALLOC(h->d_A_lo, h->n_store * elem_size(h->lo_prec));
   ALLOC(h->d_tpart, h->n_block_points * 8);
   ALLOC(h->d_part, (int64_t)h->chunks.size() * g.K * 8);
   ALLOC(h->d_red, 4 * 2 * kRedBlocks * 8);
@@ -435,6 +438,17 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   if (!h->cov.empty()) H2D(h->d_cov, h->cov.data(), h->cov.size() * 4);
   if (!h->segs.empty()) H2D(h->d_segs, h->segs.data(), h->segs.size() * sizeof(AxisSeg));
 #undef H2D
+  // the row padding of the stored blocks is never assembled; the vector loads of the matrix
+  // passes read it with zero weights, so it must hold finite values
+  {
+    hipError_t ez = hipMemset(h->d_A, 0, (size_t)h->n_store * 8);
+    if (ez == hipSuccess && h->d_A_lo)
+      ez = hipMemset(h->d_A_lo, 0, (size_t)(h->n_store * elem_size(h->lo_prec)));
+    if (ez != hipSuccess) {
+      elmfb_destroy(h);
+      return fail(nullptr, ELMFB_E_DEVICE, std::string("hipMemset: ") + hipGetErrorString(ez));
+    }
+  }
   h->desc.W_host = nullptr;
   h->desc.b_host = nullptr;
 
@@ -536,6 +550,7 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
                                void* stream) {
   if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
   if (table_host) {
+    int64_t dense = 0;
     for (size_t b = 0; b < h->blocks.size(); ++b) {
       const DevBlock& B = h->blocks[b];
       int64_t* t = table_host + 8 * b;
@@ -546,7 +561,8 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
       t[4] = B.nx;
       t[5] = B.iy0;
       t[6] = B.ny;
-      t[7] = B.a_off;
+      t[7] = dense;
+      dense += (int64_t)B.n * h->geo.K;
     }
   }
   if (dst_dev) {
@@ -566,8 +582,17 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
     } else {
       return fail(h, ELMFB_E_STATE, "no stored copy in that precision");
     }
-    HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, src, (size_t)(h->nnz * elem_size(prec)),
-                                  hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    // stored rows are padded to ld; the copy drops the padding
+    const int64_t es = elem_size(prec);
+    int64_t dense = 0;
+    for (const DevBlock& B : h->blocks) {
+      if (B.n == 0) continue;
+      HIP_OR_FAIL(h, hipMemcpy2DAsync(static_cast<char*>(dst_dev) + dense * es, (size_t)(B.n * es),
+                                      static_cast<const char*>(src) + B.a_off * es,
+                                      (size_t)(B.ld * es), (size_t)(B.n * es), (size_t)h->geo.K,
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream));
+      dense += (int64_t)B.n * h->geo.K;
+    }
   }
   return ELMFB_OK;
 }

@@ -29,6 +29,7 @@ struct elmfb_batch_s {
   std::vector<ColTile> ctiles;
   std::vector<int64_t> foff, goff;   // per block: packed-factor and square Gram offsets
   int64_t n_rows = 0, n_phi = 0, nnz = 0, n_bp = 0, n_tab = 0, n_fac = 0, n_gsq = 0, bytes = 0;
+  int64_t n_store = 0;               // stored elements per matrix copy, row padding included
   int tp[4] = {32, 32, 32, 32};      // points per LDS stage of A^T U, per matrix precision
   bool tuned[4] = {false, false, false, false};
   bool lo_unsafe = false;            // FP16 fold over an identity-fallback block: not used
@@ -114,7 +115,7 @@ void brelease(elmfb_batch b) {
 }
 
 std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
-  int64_t row_off = 0, col_off = 0, a_off = 0, p_off = 0, f_off = 0, g_off = 0;
+  int64_t row_off = 0, col_off = 0, a_off = 0, p_off = 0, f_off = 0, g_off = 0, nnz = 0;
   int32_t blk_off = 0, tab_off = 0, cov_off = 0;
   for (int i = 0; i < B->n; ++i) {
     elmfb_problem_s hp;
@@ -168,7 +169,8 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
     B->cov.insert(B->cov.end(), hp.cov.begin(), hp.cov.end());
     row_off += g.n_rows;
     col_off += g.n_phi;
-    a_off += hp.nnz;
+    a_off += hp.n_store;
+    nnz += hp.nnz;
     p_off += hp.n_block_points;
     blk_off += (int32_t)hp.blocks.size();
     tab_off += (int32_t)hp.n_tab;
@@ -177,7 +179,8 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
   }
   B->n_rows = row_off;
   B->n_phi = col_off;
-  B->nnz = a_off;
+  B->nnz = nnz;
+  B->n_store = a_off;
   B->n_bp = p_off;
   B->n_tab = tab_off;
   B->n_fac = f_off;
@@ -334,7 +337,7 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   const int R = n_rhs;
   const int64_t es_lo = B->lo_prec == ELMFB_FP64 ? 0 : elem_size(B->lo_prec);
   const int64_t nblk = (int64_t)B->blocks.size();
-  int64_t bytes = B->nnz * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
+  int64_t bytes = B->n_store * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
                   B->n_phi * R * 8 * 4 + B->n_phi * 24 + B->n_tab * 24 +
                   (int64_t)(B->rtiles.size() * 3 + B->ctiles.size() + nblk) * kMaxRhs * 8 +
                   nblk * ((int64_t)sizeof(DevBlock) + 16) +
@@ -382,8 +385,8 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_tab, B->n_tab * 24);
   BALLOC(B->d_W, B->n_phi * 16);
   BALLOC(B->d_b, B->n_phi * 8);
-  BALLOC(B->d_A, B->nnz * 8);
-  if (es_lo) BALLOC(B->d_A_lo, B->nnz * es_lo);
+  BALLOC(B->d_A, B->n_store * 8);
+  if (es_lo) BALLOC(B->d_A_lo, B->n_store * es_lo);
   BALLOC(B->d_h, B->n_rows * R * 8);
   BALLOC(B->d_u, B->n_rows * R * 8);
   BALLOC(B->d_v, B->n_phi * R * 8);
@@ -430,6 +433,10 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   up(B->d_ctiles, B->ctiles.data(), B->ctiles.size() * sizeof(ColTile));
   up(B->d_W, W2.data(), W2.size() * 8);
   up(B->d_b, bb.data(), bb.size() * 8);
+  // the row padding of the stored blocks is never assembled; the matrix passes may read it with
+  // zero weights, so it must hold finite values
+  if (e == hipSuccess) e = hipMemset(B->d_A, 0, (size_t)B->n_store * 8);
+  if (e == hipSuccess && B->d_A_lo) e = hipMemset(B->d_A_lo, 0, (size_t)(B->n_store * es_lo));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming);
@@ -472,6 +479,7 @@ elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
                                      int64_t* table_host, void* stream) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
   if (table_host) {
+    int64_t dense = 0;
     for (size_t i = 0; i < B->blocks.size(); ++i) {
       const DevBlock& d = B->blocks[i];
       int64_t* t = table_host + 8 * i;
@@ -482,7 +490,8 @@ elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
       t[4] = d.iy0;
       t[5] = d.ny;
       t[6] = B->geos[d.inst].K;
-      t[7] = d.a_off;
+      t[7] = dense;
+      dense += (int64_t)d.n * B->geos[d.inst].K;
     }
   }
   if (dst_dev) {
@@ -497,8 +506,18 @@ elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
       src = folded == B->lo_hat ? B->d_A_lo : nullptr;
     }
     if (!src) return bfail(B, ELMFB_E_STATE, "no stored copy of that kind and precision");
-    BHIP(B, hipMemcpyAsync(dst_dev, src, (size_t)(B->nnz * elem_size(prec)),
-                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    // stored rows are padded to ld; the copy drops the padding
+    const int64_t es = elem_size(prec);
+    int64_t dense = 0;
+    for (const DevBlock& d : B->blocks) {
+      const int64_t K = B->geos[d.inst].K;
+      if (d.n == 0) continue;
+      BHIP(B, hipMemcpy2DAsync(static_cast<char*>(dst_dev) + dense * es, (size_t)(d.n * es),
+                               static_cast<const char*>(src) + d.a_off * es, (size_t)(d.ld * es),
+                               (size_t)(d.n * es), (size_t)K, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+      dense += (int64_t)d.n * K;
+    }
   }
   return ELMFB_OK;
 }
@@ -563,13 +582,14 @@ elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fa
   const int64_t nb = (int64_t)B->blocks.size();
   if (!B->d_rc) {
     hipError_t e1 = balloc(B, &B->d_rc, B->n_fac * 8);
-    hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_Ahat, B->nnz * 8) : e1;
+    hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_Ahat, B->n_store * 8) : e1;
+    if (e2 == hipSuccess) e2 = hipMemsetAsync(B->d_Ahat, 0, (size_t)B->n_store * 8, s);  // padding
     if (e2 != hipSuccess) {
       bfree(B, B->d_rc);
       B->d_rc = nullptr;
       return bfail(B, ELMFB_E_NOMEM, std::string("factor storage: ") + hipGetErrorString(e2));
     }
-    B->bytes += B->n_fac * 8 + B->nnz * 8;
+    B->bytes += B->n_fac * 8 + B->n_store * 8;
   }
   double *G = nullptr, *work = nullptr;
   hipError_t e1 = balloc(B, &G, B->n_gsq * 8);

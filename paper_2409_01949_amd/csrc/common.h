@@ -10,15 +10,18 @@ namespace elmfb {
 
 constexpr int kMaxLevels = ELMFB_MAX_LEVELS;
 constexpr int kTile = 256;          // points per assembly / A.v tile (one per thread)
+constexpr int kRowAlign = 8;        // stored rows start on 8-element boundaries (16 B in FP16)
 constexpr int kChunkPts = 2048;     // points per A^T u chunk (8 per thread of 256)
 constexpr int kRedBlocks = 1024;    // upper bound on per-workgroup partial sums of a reduction
 
 // One subdomain's block of the matrix: K rows (features) x n points of its box, feature-major.
 struct DevBlock {
-  int64_t a_off;    // element offset of the block in the stored matrix
+  int64_t a_off;    // element offset of the block in the stored matrix (a multiple of kRowAlign)
   int64_t p_off;    // offset of the block's points in the per-block-point arrays
   int32_t q0;       // first global column
   int32_t n;        // points in the box = nx * ny
+  int32_t ld;       // row stride of the stored block [K][ld]: n rounded up to kRowAlign; the
+                    // padding entries hold zeros
   int32_t ix0, nx;  // box along x (grid indices)
   int32_t iy0, ny;  // box along y
   int32_t tabx;     // offset of the x-axis envelope table entries for ix0..ix0+nx-1

@@ -22,6 +22,7 @@ struct elmfb_problem_s {
   std::vector<int32_t> chunk_start, cov;
   std::vector<AxisSeg> segs;
   int64_t nnz = 0, n_block_points = 0, n_tab = 0;
+  int64_t n_store = 0;          // stored elements per matrix copy, row padding included
   int64_t bytes_device = 0;
 
   // device memory

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
   const double yb = (g.dim == 2) ? (grid_coord(g, 1, B.iy0 + ly) - centre(g, l, 1, jy)) / sy : 0.0;
   const double scale = g.inv_scale;
   const int64_t base = B.a_off + p;
-  const int n = B.n;
+  const int ld = B.ld;
   for (int k = 0; k < K; ++k) {
     const double z = w1s[k] * xb + w2s[k] * yb + bs[k];
     const double ph = tanh(z);
@@ -133,8 +133,8 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
       v = P * ph;
     }
     const double e = v * scale;
-    A[base + (int64_t)k * n] = e;
-    if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * n, e);
+    A[base + (int64_t)k * ld] = e;
+    if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * ld, e);
   }
 }
 

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
   const double yb = (g.dim == 2) ? (grid_coord(g, 1, B.iy0 + ly) - centre(g, l, 1, jy)) / sy : 0.0;
   const double scale = g.inv_scale;
   const int64_t base = B.a_off + p;
-  const int n = B.n;
+  const int ld = B.ld;
   const int op = g.op;
   for (int k = 0; k < K; ++k) {
     const double z = w1s[k] * xb + w2s[k] * yb + bs[k];
@@ -118,12 +118,12 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
     else
       v = P * ph;
     const double e = v * scale;
-    A[base + (int64_t)k * n] = e;
-    if constexpr (LO == ELMFB_FP32) static_cast<float*>(A_lo)[base + (int64_t)k * n] = (float)e;
+    A[base + (int64_t)k * ld] = e;
+    if constexpr (LO == ELMFB_FP32) static_cast<float*>(A_lo)[base + (int64_t)k * ld] = (float)e;
     if constexpr (LO == ELMFB_BF16)
-      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * n] = f64_to_bf16_rne(e);
+      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * ld] = f64_to_bf16_rne(e);
     if constexpr (LO == ELMFB_FP16)
-      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * n] = f64_to_fp16_rne(e);
+      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * ld] = f64_to_fp16_rne(e);
   }
 }
 
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int n = B.n;
+  const int n = B.n, ld = B.ld;
   for (int p0 = wid * 64; p0 < n; p0 += 256) {
     const int p = p0 + lane;
     if (p < n) {
@@ -277,14 +277,14 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
       for (; k + 8 <= K; k += 8) {
         double a[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] = load_entry<PREC>(A, base + (int64_t)(k + q) * n);
+        for (int q = 0; q < 8; ++q) a[q] = load_entry<PREC>(A, base + (int64_t)(k + q) * ld);
 #pragma unroll
         for (int q = 0; q < 8; ++q)
 #pragma unroll
           for (int j = 0; j < kMaxRhs; ++j) acc[j] += a[q] * cs[k + q][j];
       }
       for (; k < K; ++k) {
-        const double a = load_entry<PREC>(A, base + (int64_t)k * n);
+        const double a = load_entry<PREC>(A, base + (int64_t)k * ld);
 #pragma unroll
         for (int j = 0; j < kMaxRhs; ++j) acc[j] += a * cs[k][j];
       }
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
       const int e = threadIdx.x + 256 * m;
       const int k = e / TP, c = e - (e / TP) * TP;
       const int p = p0 + c;
-      ra[m] = (k < K && p < n) ? Ab[(int64_t)k * n + p] : in_t(0);
+      ra[m] = (k < K && p < n) ? Ab[(int64_t)k * B.ld + p] : in_t(0);
     }
 #pragma unroll
     for (int m = 0; m < NU; ++m) {

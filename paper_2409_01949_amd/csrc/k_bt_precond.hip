@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_bt_gram_diag(const Geo* __restrict__ ge
   for (int p0 = 0; p0 < n; p0 += kGdStage) {
     for (int e = threadIdx.x; e < Kp * kGdStage; e += 256) {
       const int k = e / kGdStage, c = e - (e / kGdStage) * kGdStage;
-      X[k * STR + c] = (k < K && p0 + c < n) ? Ab[(int64_t)k * n + p0 + c] : 0.0;
+      X[k * STR + c] = (k < K && p0 + c < n) ? Ab[(int64_t)k * B.ld + p0 + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
     for (int e = threadIdx.x; e < kFoldK * kFoldP; e += 256) {
       const int kk = e / kFoldP, c = e - (e / kFoldP) * kFoldP;
       const int k = k0 + kk, p = p0 + c;
-      At[kk][c] = (k < K && p < n) ? Ab[(int64_t)k * n + p] : 0.0;
+      At[kk][c] = (k < K && p < n) ? Ab[(int64_t)k * B.ld + p] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
       for (int v = 0; v < 4; ++v) {
         const int kp = 16 * I + lq + 4 * v;
         if (kp < K && p < n) {
-          const int64_t o = B.a_off + (int64_t)kp * n + p;
+          const int64_t o = B.a_off + (int64_t)kp * B.ld + p;
           const double val = acc[a][b][v];
           if (Ahat) Ahat[o] = val;
           if constexpr (LO == ELMFB_FP32) static_cast<float*>(Ahat_lo)[o] = (float)val;

@@ -104,8 +104,8 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
       const int pi = pidx[s], pj = pidx[kStage + s];
       in_t xv = in_t(0.0f), yv = in_t(0.0f);
       if (k < K && pi >= 0) {
-        xv = load_in<PREC>(A, Bi.a_off + (int64_t)k * Bi.n + pi);
-        yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.n + pj);
+        xv = load_in<PREC>(A, Bi.a_off + (int64_t)k * Bi.ld + pi);
+        yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.ld + pj);
       }
       X[k * STR + s] = xv;
       Y[k * STR + s] = yv;

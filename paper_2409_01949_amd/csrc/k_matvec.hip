@@ -34,17 +34,17 @@ __global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __rest
   if (p >= B.n) return;
   const double* vb = v + B.q0;
   const int K = g.K;
-  const int n = B.n;
+  const int ld = B.ld;
   const int64_t base = B.a_off + p;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   int k = 0;
   for (; k + 4 <= K; k += 4) {
-    acc0 += load_entry<PREC>(A, base + (int64_t)(k + 0) * n) * vb[k + 0];
-    acc1 += load_entry<PREC>(A, base + (int64_t)(k + 1) * n) * vb[k + 1];
-    acc2 += load_entry<PREC>(A, base + (int64_t)(k + 2) * n) * vb[k + 2];
-    acc3 += load_entry<PREC>(A, base + (int64_t)(k + 3) * n) * vb[k + 3];
+    acc0 += load_entry<PREC>(A, base + (int64_t)(k + 0) * ld) * vb[k + 0];
+    acc1 += load_entry<PREC>(A, base + (int64_t)(k + 1) * ld) * vb[k + 1];
+    acc2 += load_entry<PREC>(A, base + (int64_t)(k + 2) * ld) * vb[k + 2];
+    acc3 += load_entry<PREC>(A, base + (int64_t)(k + 3) * ld) * vb[k + 3];
   }
-  for (; k < K; ++k) acc0 += load_entry<PREC>(A, base + (int64_t)k * n) * vb[k];
+  for (; k < K; ++k) acc0 += load_entry<PREC>(A, base + (int64_t)k * ld) * vb[k];
   const double sc = vscale ? *vscale : 1.0;
   tpart[B.p_off + p] = ((acc0 + acc1) + (acc2 + acc3)) * sc;
 }
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int n = B.n;
+  const int ld = B.ld;
   const int K8 = (K + 7) & ~7;
   for (int k0 = 0; k0 < K8; k0 += 8) {
     double acc[8];
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
       acc[j] = 0.0;
       const int k = k0 + j < K ? k0 + j : K - 1;     // padded features reread the last one
 #pragma unroll
-      for (int i = 0; i < PPT; ++i) acc[j] += load_entry<PREC>(A, idx[i] + (int64_t)k * n) * uv[i];
+      for (int i = 0; i < PPT; ++i) acc[j] += load_entry<PREC>(A, idx[i] + (int64_t)k * ld) * uv[i];
     }
     int f;
     const double v = butterfly8(acc, lane, &f);

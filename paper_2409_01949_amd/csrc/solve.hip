@@ -380,9 +380,14 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
       size_t free_b = 0, total_b = 0;
       return hipMemGetInfo(&free_b, &total_b) == hipSuccess && (int64_t)free_b > bytes + margin;
     };
-    if (es_lo && !h->d_Ahat_lo && fits(h->nnz * es_lo))
-      HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->nnz * es_lo));
-    if (!h->d_Ahat && fits(h->nnz * 8)) HIP_OR_FAIL(h, dalloc(h, &h->d_Ahat, h->nnz * 8));
+    if (es_lo && !h->d_Ahat_lo && fits(h->n_store * es_lo)) {
+      HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->n_store * es_lo));
+      HIP_OR_FAIL(h, hipMemsetAsync(h->d_Ahat_lo, 0, (size_t)(h->n_store * es_lo), s));  // padding
+    }
+    if (!h->d_Ahat && fits(h->n_store * 8)) {
+      HIP_OR_FAIL(h, dalloc(h, &h->d_Ahat, h->n_store * 8));
+      HIP_OR_FAIL(h, hipMemsetAsync(h->d_Ahat, 0, (size_t)h->n_store * 8, s));           // padding
+    }
     const bool lo_ok = es_lo && h->d_Ahat_lo;
     if ((lo_ok || h->d_Ahat) && !h->d_ftiles) {
       std::vector<Tile> ft;
@@ -448,7 +453,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   HIP_OR_FAIL(h, hipStreamWaitEvent(s, h->ev_in, 0));
 
   if (method == ELMFB_CGLS && h->anorm_f < 0.0) {
-    HIP_OR_FAIL(h, launch_sumsq_entries(ELMFB_FP64, h->d_A, h->nnz, h->d_red, kRedBlocks, s));
+    HIP_OR_FAIL(h, launch_sumsq_entries(ELMFB_FP64, h->d_A, h->n_store, h->d_red, kRedBlocks, s));
     HIP_OR_FAIL(h, launch_reduce_to(h->d_red, kRedBlocks, h->d_scalar, s));
     double ss = 0.0;
     HIP_OR_FAIL(h, hipMemcpyAsync(&ss, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
