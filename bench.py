@@ -41,9 +41,12 @@ def parse():
     p.add_argument("--method", default="mixed_ir", choices=["lsqr", "cgls", "mixed_ir"])
     p.add_argument("--no-precond", action="store_true", help="no block-Jacobi preconditioning")
     p.add_argument("--shift", type=float, default=1e-12)
-    p.add_argument("--store", default="fp32", choices=["fp64", "fp32", "bf16", "fp16"],
-                   help="low-precision stored copy for the inner solves of mixed_ir")
-    p.add_argument("--inner", type=int, default=2500)
+    p.add_argument("--store", default=None, choices=["fp64", "fp32", "bf16", "fp16"],
+                   help="low-precision stored copy for the inner solves of mixed_ir (default: "
+                        "fp16 for single problems, fp32 for the batched workloads)")
+    p.add_argument("--inner", type=int, default=None,
+                   help="inner LSQR steps per refinement step (default: 500 on a 16-bit copy, "
+                        "2500 on fp32)")
     p.add_argument("--no-compare", action="store_true",
                    help="skip the FP64 comparison solves")
     p.add_argument("--iters", type=int, default=15000)
@@ -58,7 +61,12 @@ def parse():
     p.add_argument("--epochs", type=int, default=100, help="warm workload: MLP training epochs")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run device copies of this many bytes (traffic-counter reference)")
-    return p.parse_args()
+    args = p.parse_args()
+    if args.store is None:
+        args.store = "fp16" if args.workload in ("poisson3l", "poisson5l") else "fp32"
+    if args.inner is None:
+        args.inner = 500 if args.store in ("fp16", "bf16") else 2500
+    return args
 
 
 def cpu_baseline(spec, W, b, f, n_iters_solve, budget_s=20.0):
@@ -399,7 +407,7 @@ def main():
     rel_test = float(np.linalg.norm(u - ut_np) / np.linalg.norm(ut_np))
 
     # roofline of the dominant kernel: the per-chunk pass of x = M^T u over the matrix copy the
-    # inner iterations stream (the FP32 copy for the mixed path)
+    # inner iterations stream (the low-precision copy for the mixed path)
     kprec = args.store if args.method == "mixed_ir" else "fp64"
     es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kprec]
     ms_mv, ms_rmv = P.time_kernels(args.kernel_reps, prec=kprec)

@@ -130,4 +130,54 @@ __device__ __forceinline__ double load_entry<ELMFB_FP16>(const void* A, int64_t 
   return (double)(float)static_cast<const _Float16*>(A)[i];
 }
 
+// Exact FP64 value of a 16-bit stored entry given as the low 16 bits of w.
+template <int PREC>
+__device__ __forceinline__ double half_bits_to_f64(uint32_t w) {
+  if constexpr (PREC == ELMFB_BF16) return (double)__uint_as_float(w << 16);
+  else return (double)(float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+
+// VEC consecutive stored entries from element i in one vector load (i a multiple of VEC; stored
+// rows start on kRowAlign-element boundaries, so the load is naturally aligned), as FP64.
+template <int PREC, int VEC>
+__device__ __forceinline__ void load_vec(const void* A, int64_t i, double (&out)[VEC]) {
+  static_assert(VEC == 1 || VEC == 2 || VEC == 4 || VEC == 8, "vector width");
+  static_assert(kRowAlign % VEC == 0, "rows must be aligned to the vector width");
+  if constexpr (VEC == 1) {
+    out[0] = load_entry<PREC>(A, i);
+  } else if constexpr (PREC == ELMFB_FP64) {
+    static_assert(VEC == 2, "FP64 vectors hold 2 entries");
+    const double2 x = *reinterpret_cast<const double2*>(static_cast<const double*>(A) + i);
+    out[0] = x.x;
+    out[1] = x.y;
+  } else if constexpr (PREC == ELMFB_FP32) {
+    const float* p = static_cast<const float*>(A) + i;
+    if constexpr (VEC == 2) {
+      const float2 x = *reinterpret_cast<const float2*>(p);
+      out[0] = x.x; out[1] = x.y;
+    } else {
+      static_assert(VEC == 4, "FP32 vectors hold 2 or 4 entries");
+      const float4 x = *reinterpret_cast<const float4*>(p);
+      out[0] = x.x; out[1] = x.y; out[2] = x.z; out[3] = x.w;
+    }
+  } else {
+    const uint16_t* p = static_cast<const uint16_t*>(A) + i;
+    uint32_t w[VEC / 2];
+    if constexpr (VEC == 2) {
+      w[0] = *reinterpret_cast<const uint32_t*>(p);
+    } else if constexpr (VEC == 4) {
+      const uint2 x = *reinterpret_cast<const uint2*>(p);
+      w[0] = x.x; w[1] = x.y;
+    } else {
+      const uint4 x = *reinterpret_cast<const uint4*>(p);
+      w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+    }
+#pragma unroll
+    for (int h = 0; h < VEC / 2; ++h) {
+      out[2 * h] = half_bits_to_f64<PREC>(w[h]);
+      out[2 * h + 1] = half_bits_to_f64<PREC>(w[h] >> 16);
+    }
+  }
+}
+
 }  // namespace elmfb

@@ -1,15 +1,17 @@
 // Block-sparse products with the assembled matrix M = sum_j V_j^T M_j W_j (Sec. 3
-// eq. multilevel_domain_decomp), each block M_j stored feature-major [K][n_j].
+// eq. multilevel_domain_decomp), each block M_j stored feature-major [K][ld_j] (rows padded with
+// zeros to a multiple of 8 entries, so vector loads stay aligned).
 //
 // y = M v runs in two passes that stream the matrix exactly once:
-//   1. per block point (one thread each, consecutive points on consecutive lanes):
-//      t_j[p] = sum_k M_j[k][p] v[q0_j + k] -- the K coefficients of the block are
-//      wavefront-uniform, so they come from the scalar cache;
+//   1. per block point (consecutive points on consecutive lanes; 16-bit copies take two points
+//      per lane in one 4-byte load): t_j[p] = sum_k M_j[k][p] v[q0_j + k] -- the K coefficients
+//      of the block are wavefront-uniform, so they come from the scalar cache;
 //   2. per row (grid point): y_r = sum over the blocks covering it of t_j[p_j(r)], the covering
 //      blocks found arithmetically from per-axis index ranges; no atomics, fixed order.
 // x = M^T u also streams the matrix once:
 //   1. per chunk of <= 2048 consecutive points of one block: each thread holds 8 gathered
-//      u values; for every group of 8 features the 256 lanes form their dot products, a
+//      u values (in vector-load groups of 2 or 4 consecutive points for FP32 and 16-bit
+//      copies); for every group of 8 features the 256 lanes form their dot products, a
 //      transposing butterfly across the wavefront reduces the 8 features at once (10 cross-lane
 //      shuffles) and a 4-wave LDS sum gives the chunk partials;
 //   2. per column: sum of the chunk partials of its block in chunk order.
@@ -19,7 +21,9 @@
 
 namespace elmfb {
 
-template <int PREC>
+// PTS consecutive points per thread (one vector load per feature row); a tile of 256 points
+// runs on 256 / PTS threads.  Per point the sum order does not depend on PTS.
+template <int PREC, int PTS>
 __global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __restrict__ blocks,
                                                    const Tile* __restrict__ tiles,
                                                    const void* __restrict__ A,
@@ -30,23 +34,38 @@ __global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __rest
   if (st && st->done) return;
   const Tile t = tiles[blockIdx.x];
   const DevBlock B = blocks[t.blk];
-  const int p = t.p0 + threadIdx.x;
+  const int p = t.p0 + threadIdx.x * PTS;
   if (p >= B.n) return;
   const double* vb = v + B.q0;
   const int K = g.K;
   const int ld = B.ld;
   const int64_t base = B.a_off + p;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  double acc[4][PTS];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) acc[u][q] = 0.0;
   int k = 0;
   for (; k + 4 <= K; k += 4) {
-    acc0 += load_entry<PREC>(A, base + (int64_t)(k + 0) * ld) * vb[k + 0];
-    acc1 += load_entry<PREC>(A, base + (int64_t)(k + 1) * ld) * vb[k + 1];
-    acc2 += load_entry<PREC>(A, base + (int64_t)(k + 2) * ld) * vb[k + 2];
-    acc3 += load_entry<PREC>(A, base + (int64_t)(k + 3) * ld) * vb[k + 3];
+    double a[4][PTS];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_vec<PREC, PTS>(A, base + (int64_t)(k + u) * ld, a[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < PTS; ++q) acc[u][q] += a[u][q] * vb[k + u];
   }
-  for (; k < K; ++k) acc0 += load_entry<PREC>(A, base + (int64_t)k * ld) * vb[k];
+  for (; k < K; ++k) {
+    double a[PTS];
+    load_vec<PREC, PTS>(A, base + (int64_t)k * ld, a);
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) acc[0][q] += a[q] * vb[k];
+  }
   const double sc = vscale ? *vscale : 1.0;
-  tpart[B.p_off + p] = ((acc0 + acc1) + (acc2 + acc3)) * sc;
+#pragma unroll
+  for (int q = 0; q < PTS; ++q)
+    if (p + q < B.n)
+      tpart[B.p_off + p + q] = ((acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q])) * sc;
 }
 
 __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __restrict__ blocks,
@@ -118,7 +137,9 @@ __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __re
   }
 }
 
-template <int PREC>
+// VEC consecutive points per vector load; each thread holds NG groups of them, the groups of a
+// chunk interleaved across the workgroup (group i of thread t starts at i*256*VEC + t*VEC).
+template <int PREC, int VEC>
 __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __restrict__ blocks,
                                                     const Tile* __restrict__ chunks,
                                                     const void* __restrict__ A,
@@ -126,26 +147,32 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
                                                     const double* __restrict__ uscale,
                                                     double* __restrict__ part,
                                                     const SolveState* __restrict__ st) {
-  constexpr int PPT = kChunkPts / 256;
+  constexpr int NG = kChunkPts / (256 * VEC);
+  static_assert(NG * 256 * VEC == kChunkPts, "chunk size");
   __shared__ double sred[4][264];
   if (st && st->done) return;
   const Tile c = chunks[blockIdx.x];
   const DevBlock B = blocks[c.blk];
   const int K = g.K;
   const double sc = uscale ? *uscale : 1.0;
-  double uv[PPT];
-  int64_t idx[PPT];
+  double uv[NG][VEC];
+  int64_t idx[NG];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int p = c.p0 + i * 256 + threadIdx.x;
-    if (p < B.n) {
-      const int lx = p / B.ny, ly = p - lx * B.ny;
-      const int64_t r = (int64_t)(B.ix0 + lx) * g.ny + (B.iy0 + ly);
-      uv[i] = u[r] * sc;
-      idx[i] = B.a_off + p;
-    } else {
-      uv[i] = 0.0;
-      idx[i] = B.a_off;   // in bounds; multiplied by a zero weight
+  for (int i = 0; i < NG; ++i) {
+    const int p0 = c.p0 + i * 256 * VEC + threadIdx.x * VEC;
+    // a group past the block reads the block's first entries with zero weights (in bounds);
+    // a group that straddles the end reads padding (zeros, p0 + VEC <= ld) with zero weights
+    idx[i] = B.a_off + (p0 < B.n ? p0 : 0);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      const int p = p0 + q;
+      if (p < B.n) {
+        const int lx = p / B.ny, ly = p - lx * B.ny;
+        const int64_t r = (int64_t)(B.ix0 + lx) * g.ny + (B.iy0 + ly);
+        uv[i][q] = u[r] * sc;
+      } else {
+        uv[i][q] = 0.0;
+      }
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -158,7 +185,12 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
       acc[j] = 0.0;
       const int k = k0 + j < K ? k0 + j : K - 1;     // padded features reread the last one
 #pragma unroll
-      for (int i = 0; i < PPT; ++i) acc[j] += load_entry<PREC>(A, idx[i] + (int64_t)k * ld) * uv[i];
+      for (int i = 0; i < NG; ++i) {
+        double a[VEC];
+        load_vec<PREC, VEC>(A, idx[i] + (int64_t)k * ld, a);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[j] += a[q] * uv[i][q];
+      }
     }
     int f;
     const double v = butterfly8(acc, lane, &f);
@@ -227,19 +259,30 @@ int cols_wg(const Geo& g) {
   return (int)(nb < kRedBlocks ? nb : kRedBlocks);
 }
 
+// Points per thread of the y = M v pass and points per vector load of the M^T u pass, per
+// stored precision (16-bit rows are read 4 or 8 bytes per lane).
+template <int PREC> struct MvShape { static constexpr int pts = 1, vec = 1; };
+template <> struct MvShape<ELMFB_FP32> { static constexpr int pts = 1, vec = 2; };
+template <> struct MvShape<ELMFB_BF16> { static constexpr int pts = 2, vec = 4; };
+template <> struct MvShape<ELMFB_FP16> { static constexpr int pts = 2, vec = 4; };
+
+template <int PREC>
+static void mv_launch(const Geo& g, const DevBlock* blocks, const Tile* tiles, int64_t n_tiles,
+                      const void* A, const double* v, const double* vscale, double* tpart,
+                      const SolveState* st, hipStream_t s) {
+  constexpr int P = MvShape<PREC>::pts;
+  hipLaunchKernelGGL((k_mv_blocks<PREC, P>), dim3((unsigned)n_tiles), dim3(kTile / P), 0, s, g,
+                     blocks, tiles, A, v, vscale, tpart, st);
+}
+
 hipError_t launch_mv_blocks(const Geo& g, int prec, const DevBlock* blocks, const Tile* tiles,
                             int64_t n_tiles, const void* A, const double* v, const double* vscale,
                             double* tpart, const SolveState* st, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_tiles), blk(256);
-  if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
-  else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_mv_blocks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
-  else if (prec == ELMFB_FP16)
-    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP16>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
-  else
-    hipLaunchKernelGGL(k_mv_blocks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, tiles, A, v, vscale, tpart, st);
+  if (prec == ELMFB_FP32) mv_launch<ELMFB_FP32>(g, blocks, tiles, n_tiles, A, v, vscale, tpart, st, s);
+  else if (prec == ELMFB_BF16) mv_launch<ELMFB_BF16>(g, blocks, tiles, n_tiles, A, v, vscale, tpart, st, s);
+  else if (prec == ELMFB_FP16) mv_launch<ELMFB_FP16>(g, blocks, tiles, n_tiles, A, v, vscale, tpart, st, s);
+  else mv_launch<ELMFB_FP64>(g, blocks, tiles, n_tiles, A, v, vscale, tpart, st, s);
   return hipGetLastError();
 }
 
@@ -251,20 +294,23 @@ hipError_t launch_gather_rows(const Geo& g, const DevBlock* blocks, const int32_
   return hipGetLastError();
 }
 
+template <int PREC>
+static void rmv_launch(const Geo& g, const DevBlock* blocks, const Tile* chunks, int64_t n_chunks,
+                       const void* A, const double* u, const double* uscale, double* part,
+                       const SolveState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_rmv_chunks<PREC, MvShape<PREC>::vec>), dim3((unsigned)n_chunks), dim3(256),
+                     0, s, g, blocks, chunks, A, u, uscale, part, st);
+}
+
 hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, const Tile* chunks,
                              int64_t n_chunks, const void* A, const double* u,
                              const double* uscale, double* part, const SolveState* st,
                              hipStream_t s) {
   if (n_chunks == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_chunks), blk(256);
-  if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP32>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
-  else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_BF16>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
-  else if (prec == ELMFB_FP16)
-    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP16>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
-  else
-    hipLaunchKernelGGL(k_rmv_chunks<ELMFB_FP64>, grid, blk, 0, s, g, blocks, chunks, A, u, uscale, part, st);
+  if (prec == ELMFB_FP32) rmv_launch<ELMFB_FP32>(g, blocks, chunks, n_chunks, A, u, uscale, part, st, s);
+  else if (prec == ELMFB_BF16) rmv_launch<ELMFB_BF16>(g, blocks, chunks, n_chunks, A, u, uscale, part, st, s);
+  else if (prec == ELMFB_FP16) rmv_launch<ELMFB_FP16>(g, blocks, chunks, n_chunks, A, u, uscale, part, st, s);
+  else rmv_launch<ELMFB_FP64>(g, blocks, chunks, n_chunks, A, u, uscale, part, st, s);
   return hipGetLastError();
 }
 

@@ -547,7 +547,11 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
             hit = true;
             break;
           }
+        } else if (left > 0) {
+          HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
+          HIP_OR_FAIL(h, hipStreamSynchronize(s));
         }
+        if (left > 0 && st.done) break;   // the inner LSQR met its own stopping test
       }
       if (!hit) {
         if (bj)
