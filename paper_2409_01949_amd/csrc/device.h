@@ -109,6 +109,17 @@ __device__ __forceinline__ double butterfly8(const double a[8], int lane, int* f
   return v;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b to XCD b mod 8), and each XCD
+// has its own L2.  Map workgroup b to a logical tile so that every XCD takes one contiguous range
+// of tiles, in order: neighbouring tiles, which share the cache lines at their boundary, then
+// run on the same L2 one after the other.  A bijection of 0..n-1 for any n.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, i = b / kXcd;
+  const int q = n / kXcd, r = n % kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <int PREC>
 __device__ __forceinline__ double load_entry(const void* A, int64_t i);
 

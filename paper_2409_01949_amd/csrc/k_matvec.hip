@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __rest
                                                    double* __restrict__ tpart,
                                                    const SolveState* __restrict__ st) {
   if (st && st->done) return;
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const DevBlock B = blocks[t.blk];
   const int p = t.p0 + threadIdx.x * PTS;
   if (p >= B.n) return;
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
   static_assert(NG * 256 * VEC == kChunkPts, "chunk size");
   __shared__ double sred[4][264];
   if (st && st->done) return;
-  const Tile c = chunks[blockIdx.x];
+  const int ci = xcd_tile(blockIdx.x, gridDim.x);
+  const Tile c = chunks[ci];
   const DevBlock B = blocks[c.blk];
   const int K = g.K;
   const double sc = uscale ? *uscale : 1.0;
@@ -198,7 +199,7 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
   }
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += 256)
-    part[(int64_t)blockIdx.x * K + k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
+    part[(int64_t)ci * K + k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
 }
 
 __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __restrict__ cstart,
