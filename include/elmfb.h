@@ -77,9 +77,15 @@ enum { ELMFB_FP64 = 0, ELMFB_FP32 = 1, ELMFB_BF16 = 2, ELMFB_FP16 = 3 };
 enum {
   ELMFB_LSQR = 0,       /* Paige-Saunders LSQR on block-sparse A v / A^T u, FP64 recurrences  */
   ELMFB_CGLS = 1,       /* CG on the normal equations in factored form, FP64                 */
-  ELMFB_MIXED_IR = 2    /* FP64 iterative refinement: r = h - A c with the FP64 matrix, the
-                           correction from inner_iters LSQR steps on the stored FP32/BF16 copy
-                           (FP64 vectors and recurrences), c += d in FP64                     */
+  ELMFB_MIXED_IR = 2,   /* FP64 iterative refinement: r = h - A c with the FP64 matrix, the
+                           correction from inner_iters LSQR steps on the stored FP32/BF16/FP16
+                           copy (FP64 vectors and recurrences), c += d in FP64                */
+  ELMFB_NORMAL_CG = 3,  /* CG on the normal equations G a = M^T h with G the Gram blocks of
+                           elmfb_gram(h, prec, 1) (FP64 or FP32 entries; FP64 vectors and
+                           scalars); precond = 1: block-Jacobi PCG, z = R^{-1} R^{-T} r        */
+  ELMFB_MIXED_IR_CG = 4 /* FP64 iterative refinement with the correction d from inner_iters CG
+                           steps on the stored Gram blocks: r = h - M c, g = M^T r (FP64),
+                           G d = g, c += d                                                    */
 };
 
 typedef struct elmfb_problem_s* elmfb_problem;
@@ -196,6 +202,12 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
 /* Solve min ||M x - h|| (Sec. 3 eq. multilevel_ls) into coef_dev [n_phi].  LSQR follows
  * Paige & Saunders (damp 0, no condition limit, stop tests on ||r|| and ||A^T r||), as the
  * method's reference solver does (Sec. 4.1).  Non-convergence is not an error: istop = 7.
+ * ELMFB_NORMAL_CG and ELMFB_MIXED_IR_CG solve the normal equations G a = M^T h (the least-squares
+ * minimiser when M has full column rank) on the Gram blocks of the last elmfb_gram(h, prec, 1)
+ * call (ELMFB_E_STATE without it); CG stops when ||g - G a|| <= btol ||g|| (istop 1), on a
+ * breakdown p.Gp <= 0 (istop 3: G is not positive definite in its stored precision) or after
+ * iter_lim (inner_iters) steps (istop 7); rnorm then reports ||g - G a||, except for the
+ * refinements, which report the FP64 residual ||h - M c||.  x0_dev warm-starts ELMFB_NORMAL_CG.
  * info_host may be NULL. */
 elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
                          elmfb_solve_info* info_host, void* stream);

@@ -262,6 +262,46 @@ def normal_cg(apply_G, g, n_iter, dtype=np.float64):
     return d
 
 
+def normal_pcg(apply_G, g, n_iter, apply_Minv=None, x0=None):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel, with a symmetric positive definite
+    preconditioner M) on G d = g for n_iter steps from x0 (or zero), float64 throughout:
+        r = g - G d, z = M^{-1} r, p = z;
+        each step: q = G p, a = (r.z)/(p.q), d += a p, r -= a q, z = M^{-1} r,
+                   p = z + ((r.z)_new / (r.z)) p.
+    apply_Minv None means M = I (plain CG).  Stops early when r.z = 0 or p.q <= 0."""
+    d = np.zeros(g.shape) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = np.array(g, dtype=np.float64, copy=True) - (apply_G(d) if x0 is not None else 0.0)
+    z = r.copy() if apply_Minv is None else np.asarray(apply_Minv(r), dtype=np.float64)
+    p = z.copy()
+    rz = r @ z
+    for _ in range(n_iter):
+        if rz == 0:
+            break
+        q = np.asarray(apply_G(p), dtype=np.float64)
+        pq = p @ q
+        if not pq > 0:
+            break
+        a = rz / pq
+        d = d + a * p
+        r = r - a * q
+        z = r.copy() if apply_Minv is None else np.asarray(apply_Minv(r), dtype=np.float64)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return d
+
+
+def block_jacobi_inverse_apply(blocks, factors, r):
+    """z = (R^T R)^{-1} r per block (R upper, R^T R = G_jj + lambda I): the block-Jacobi
+    preconditioner of the normal equations, by two triangular solves per block."""
+    z = np.zeros_like(r)
+    for blk, R in zip(blocks, factors):
+        K = R.shape[0]
+        sl = slice(blk.sd.q0, blk.sd.q0 + K)
+        z[sl] = np.linalg.solve(R, np.linalg.solve(R.T, r[sl]))
+    return z
+
+
 def refine(matvec, rmatvec, h, n, apply_G_lo, n_outer, n_inner, x0=None, lo_dtype=np.float32,
            callback=None):
     """Iterative refinement (BJ-style mixed precision): per outer step

@@ -74,6 +74,16 @@ struct elmfb_problem_s {
   int32_t* d_gmulti = nullptr;
   int64_t gmulti_cap = 0;
   std::vector<GramPair> gram_pairs_host;   // the pairs of the last elmfb_gram call
+  int64_t gram_gen = 0;                    // counts elmfb_gram calls
+
+  // CG on the Gram blocks: device copy of the stored pairs, per block-row tables of partials,
+  // partials [2 n_pairs][K], and one extra coefficient vector for the preconditioner
+  int64_t gcg_gen = -1;                    // gram_gen the tables were built for
+  GramPair* d_gcg_pairs = nullptr;
+  int32_t* d_gcg_rowptr = nullptr;
+  int32_t* d_gcg_idx = nullptr;
+  double* d_gcg_part = nullptr;
+  double* d_gcg_tmp = nullptr;
 
   // block-Jacobi factors
   double* d_bj_work = nullptr;

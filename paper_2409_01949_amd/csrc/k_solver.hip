@@ -392,4 +392,145 @@ hipError_t launch_cgls_update_p(const Geo& g, double* p, const double* sv, const
   return hipGetLastError();
 }
 
+// ---- CG on the assembled Gram blocks, G a = g (g = M^T h), optionally preconditioned by the
+// block-Jacobi factors (z = R^{-1} R^{-T} r, R^T R = G_jj + lambda I): Hestenes-Stiefel CG with
+// FP64 vectors and scalars.  gamma holds r.z (r.r without preconditioning), cg_a / cg_b the
+// step sizes, bnorm ||g||, rnorm ||r||.
+
+// Start: bnorm = ||g||, rnorm = ||r0||, gamma = r0.z0; done at once when r0 = 0 or iter_lim = 0.
+__global__ void __launch_bounds__(256) k_gcg_init(SolveState* st, const double* red_b, int nb,
+                                                  const double* red_r, int nr,
+                                                  const double* red_z, int nz) {
+  __shared__ double sh[4];
+  const double bb = reduce_partials(red_b, nb, sh);
+  const double rr = reduce_partials(red_r, nr, sh);
+  const double rz = red_z ? reduce_partials(red_z, nz, sh) : rr;
+  if (threadIdx.x == 0) {
+    st->bnorm = sqrt(bb);
+    st->rnorm = sqrt(rr);
+    st->gamma = rz;
+    st->cg_a = st->cg_b = 0.0;
+    st->itn = 0;
+    st->istop = 0;
+    st->done = 0;
+    st->rel_l2 = -1.0;
+    if (rr == 0.0) st->done = 1;                                   // exact at the start
+    else if (st->iter_lim <= 0) { st->istop = 7; st->done = 1; }
+  }
+}
+
+// cg_a = gamma / (p . q); a breakdown (p . q <= 0: G not positive definite in this precision)
+// stops with istop 3.
+__global__ void __launch_bounds__(256) k_gcg_alpha(SolveState* st, const double* red, int n) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double pq = reduce_partials(red, n, sh);
+  if (threadIdx.x == 0) {
+    if (pq > 0.0) {
+      st->cg_a = st->gamma / pq;
+    } else {
+      st->cg_a = 0.0;
+      st->istop = 3;
+      st->done = 1;
+    }
+  }
+}
+
+// a += cg_a p ; r -= cg_a q ; partial r . r.
+__global__ void __launch_bounds__(256) k_gcg_update(Geo g, double* __restrict__ a,
+                                                    double* __restrict__ r,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ q,
+                                                    const SolveState* __restrict__ st,
+                                                    double* __restrict__ red) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double al = st->cg_a;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.n_phi;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    a[t] += al * p[t];
+    const double rt = r[t] - al * q[t];
+    r[t] = rt;
+    acc += rt * rt;
+  }
+  const double sum = block_sum256(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = sum;
+}
+
+// partial x . y (skipped once the solve is done; st may be NULL).
+__global__ void __launch_bounds__(256) k_dot(const double* __restrict__ x,
+                                             const double* __restrict__ y, int64_t n,
+                                             const SolveState* __restrict__ st,
+                                             double* __restrict__ red) {
+  __shared__ double sh[4];
+  if (st && st->done) return;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    acc += x[t] * y[t];
+  const double sum = block_sum256(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = sum;
+}
+
+// rnorm = ||r||, gamma' = r.z, cg_b = gamma'/gamma; stop on ||r|| <= btol ||g|| (istop 1) or
+// the iteration limit (istop 7).
+__global__ void __launch_bounds__(256) k_gcg_beta(SolveState* st, const double* red_r, int nr,
+                                                  const double* red_z, int nz) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double rr = reduce_partials(red_r, nr, sh);
+  const double rz = red_z ? reduce_partials(red_z, nz, sh) : rr;
+  if (threadIdx.x == 0) {
+    st->itn += 1;
+    st->rnorm = sqrt(rr);
+    st->cg_b = st->gamma > 0.0 ? rz / st->gamma : 0.0;
+    st->gamma = rz;
+    int istop = 0;
+    if (st->rnorm <= st->btol * st->bnorm) istop = 1;
+    else if (st->itn >= st->iter_lim) istop = 7;
+    if (istop) { st->istop = istop; st->done = 1; }
+  }
+}
+
+// p = z + cg_b p (p = z at the start: cg_b = 0 with init = 1).
+__global__ void k_gcg_pupdate(Geo g, double* __restrict__ p, const double* __restrict__ z,
+                              const SolveState* __restrict__ st, int init) {
+  if (!init && st->done) return;
+  const double b = init ? 0.0 : st->cg_b;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.n_phi;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = z[t] + (init ? 0.0 : b * p[t]);
+}
+
+hipError_t launch_gcg_init(SolveState* st, const double* red_b, int nb, const double* red_r,
+                           int nr, const double* red_z, int nz, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcg_init, dim3(1), dim3(256), 0, s, st, red_b, nb, red_r, nr, red_z, nz);
+  return hipGetLastError();
+}
+hipError_t launch_gcg_alpha(SolveState* st, const double* red, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcg_alpha, dim3(1), dim3(256), 0, s, st, red, n);
+  return hipGetLastError();
+}
+hipError_t launch_gcg_update(const Geo& g, double* a, double* r, const double* p, const double* q,
+                             const SolveState* st, double* red, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcg_update, dim3(n_wg), dim3(256), 0, s, g, a, r, p, q, st, red);
+  return hipGetLastError();
+}
+hipError_t launch_dot(const double* x, const double* y, int64_t n, const SolveState* st,
+                      double* red, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(n_wg), dim3(256), 0, s, x, y, n, st, red);
+  return hipGetLastError();
+}
+hipError_t launch_gcg_beta(SolveState* st, const double* red_r, int nr, const double* red_z,
+                           int nz, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcg_beta, dim3(1), dim3(256), 0, s, st, red_r, nr, red_z, nz);
+  return hipGetLastError();
+}
+hipError_t launch_gcg_pupdate(const Geo& g, double* p, const double* z, const SolveState* st,
+                              int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_gcg_pupdate, grid_for(g.n_phi), dim3(256), 0, s, g, p, z, st, init);
+  return hipGetLastError();
+}
+
 }  // namespace elmfb

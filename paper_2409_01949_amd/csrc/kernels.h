@@ -75,6 +75,24 @@ hipError_t launch_reduce_to(const double* red, int n, double* out, hipStream_t s
 hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 
 // ---- Gram blocks (k_gram.hip)
+// y = G p from the stored upper Gram blocks (pass 1 per stored block into part [2 n_pairs][K],
+// pass 2 per output coefficient with its block-row table row_ptr/idx); red gets p . y partials.
+hipError_t launch_gram_mv(const Geo& g, int gram_prec, const GramPair* pairs, int64_t n_pairs,
+                          const void* G, const int32_t* row_ptr, const int32_t* idx,
+                          const double* p, double* part, double* y, const SolveState* st,
+                          double* red, int n_wg, hipStream_t s);
+// CG on the Gram blocks (FP64 vectors and scalars).
+hipError_t launch_gcg_init(SolveState* st, const double* red_b, int nb, const double* red_r,
+                           int nr, const double* red_z, int nz, hipStream_t s);
+hipError_t launch_gcg_alpha(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_gcg_update(const Geo& g, double* a, double* r, const double* p, const double* q,
+                             const SolveState* st, double* red, int n_wg, hipStream_t s);
+hipError_t launch_dot(const double* x, const double* y, int64_t n, const SolveState* st,
+                      double* red, int n_wg, hipStream_t s);
+hipError_t launch_gcg_beta(SolveState* st, const double* red_r, int nr, const double* red_z,
+                           int nz, hipStream_t s);
+hipError_t launch_gcg_pupdate(const Geo& g, double* p, const double* z, const SolveState* st,
+                              int init, hipStream_t s);
 hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const GramPair* pairs,
                        const GramChunk* chunks, int64_t n_chunks, const int32_t* multi,
                        int64_t n_multi, const void* A, void* G, void* part, hipStream_t s);

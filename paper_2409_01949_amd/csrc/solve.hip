@@ -153,9 +153,119 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
   return hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s);
 }
 
+// y = G p on the stored Gram blocks (all pairs), p . y partials into red.
+hipError_t gram_mv(elmfb_problem h, const double* p, double* y, const SolveState* st, double* red,
+                   hipStream_t s) {
+  return launch_gram_mv(h->geo, h->gram_prec, h->d_gcg_pairs, h->gram_npairs, h->d_G,
+                        h->d_gcg_rowptr, h->d_gcg_idx, p, h->d_gcg_part, y, st, red,
+                        cols_wg(h->geo), s);
+}
+
+// z = (R^T R)^{-1} r = R^{-1} R^{-T} r per block (block-Jacobi of the normal equations).
+hipError_t gcg_precond(elmfb_problem h, const double* r, double* z, const SolveState* st,
+                       hipStream_t s) {
+  hipError_t e = launch_bj_apply_t(h->geo, h->d_rinv, r, COL_STORE, h->d_gcg_tmp, st, nullptr, s);
+  if (e != hipSuccess) return e;
+  return launch_bj_apply(h->geo, h->d_rinvT, h->d_gcg_tmp, nullptr, z, st, s);
+}
+
+// One CG step on G a = g.  a = d_x, r = d_v, p = d_w, q = d_vt, z = d_xt (c.bj) or r.
+hipError_t gcg_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
+  const Geo& g = h->geo;
+  SolveState* st = h->d_state;
+  double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
+  const int cw = cols_wg(g);
+  hipError_t e;
+  if ((e = gram_mv(h, h->d_w, h->d_vt, st, red1, s))) return e;
+  if ((e = launch_gcg_alpha(st, red1, cw, s))) return e;
+  if ((e = launch_gcg_update(g, h->d_x, h->d_v, h->d_w, h->d_vt, st, red2, cw, s))) return e;
+  const double* z = h->d_v;
+  if (c.bj) {
+    if ((e = gcg_precond(h, h->d_v, h->d_xt, st, s))) return e;
+    if ((e = launch_dot(h->d_v, h->d_xt, g.n_phi, st, red3, cw, s))) return e;
+    z = h->d_xt;
+  }
+  if ((e = launch_gcg_beta(st, red2, cw, c.bj ? red3 : nullptr, cw, s))) return e;
+  return launch_gcg_pupdate(g, h->d_w, z, st, 0, s);
+}
+
+// Start CG on G a = M^T rhs (rhs = c.rhs over the rows), from x0 or zero.
+hipError_t gcg_start(elmfb_problem h, const KCtx& c, const double* x0, hipStream_t s) {
+  const Geo& g = h->geo;
+  double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
+  const int cw = cols_wg(g);
+  hipError_t e;
+  // r = g = M^T rhs (FP64 products), ||g||^2 partials in red1
+  if ((e = launch_rmv_chunks(g, ELMFB_FP64, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(),
+                             h->d_A, c.rhs, nullptr, h->d_part, nullptr, s)))
+    return e;
+  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red1, cw,
+                             s)))
+    return e;
+  if (x0) {
+    if ((e = launch_copy(x0, h->d_x, g.n_phi, s))) return e;
+    if ((e = gram_mv(h, h->d_x, h->d_vt, nullptr, red2, s))) return e;
+    if ((e = launch_axpy(-1.0, h->d_vt, h->d_v, g.n_phi, s))) return e;
+  } else {
+    if ((e = hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s))) return e;
+  }
+  if ((e = launch_dot(h->d_v, h->d_v, g.n_phi, nullptr, red2, cw, s))) return e;
+  const double* z = h->d_v;
+  if (c.bj) {
+    if ((e = gcg_precond(h, h->d_v, h->d_xt, nullptr, s))) return e;
+    if ((e = launch_dot(h->d_v, h->d_xt, g.n_phi, nullptr, red3, cw, s))) return e;
+    z = h->d_xt;
+  }
+  if ((e = launch_gcg_init(h->d_state, red1, cw, red2, cw, c.bj ? red3 : nullptr, cw, s))) return e;
+  return launch_gcg_pupdate(g, h->d_w, z, h->d_state, 1, s);
+}
+
+// Device tables of the stored Gram pairs for CG, rebuilt after every elmfb_gram call.
+elmfb_status gcg_prepare(elmfb_problem h) {
+  if (h->gcg_gen == h->gram_gen) return ELMFB_OK;
+  const Geo& g = h->geo;
+  const int64_t np = h->gram_npairs;
+  std::vector<std::vector<int32_t>> rows(g.n_blocks);
+  for (int64_t p = 0; p < np; ++p) {
+    const GramPair& P = h->gram_pairs_host[p];
+    rows[P.bi].push_back((int32_t)(2 * p));
+    if (P.bi != P.bj) rows[P.bj].push_back((int32_t)(2 * p + 1));
+  }
+  std::vector<int32_t> row_ptr(g.n_blocks + 1, 0), idx;
+  for (int b = 0; b < g.n_blocks; ++b) {
+    row_ptr[b] = (int32_t)idx.size();
+    idx.insert(idx.end(), rows[b].begin(), rows[b].end());
+  }
+  row_ptr[g.n_blocks] = (int32_t)idx.size();
+  dfree(h, h->d_gcg_pairs);
+  dfree(h, h->d_gcg_rowptr);
+  dfree(h, h->d_gcg_idx);
+  dfree(h, h->d_gcg_part);
+  h->d_gcg_pairs = nullptr;
+  h->d_gcg_rowptr = h->d_gcg_idx = nullptr;
+  h->d_gcg_part = nullptr;
+  h->gcg_gen = -1;
+  HIP_OR_FAIL(h, dalloc(h, &h->d_gcg_pairs, np * (int64_t)sizeof(GramPair)));
+  HIP_OR_FAIL(h, dalloc(h, &h->d_gcg_rowptr, (int64_t)row_ptr.size() * 4));
+  HIP_OR_FAIL(h, dalloc(h, &h->d_gcg_idx, (int64_t)idx.size() * 4 + 4));
+  HIP_OR_FAIL(h, dalloc(h, &h->d_gcg_part, 2 * np * g.K * 8));
+  if (!h->d_gcg_tmp) HIP_OR_FAIL(h, dalloc(h, &h->d_gcg_tmp, g.n_phi * 8));
+  if (np > 0)
+    HIP_OR_FAIL(h, hipMemcpy(h->d_gcg_pairs, h->gram_pairs_host.data(), np * sizeof(GramPair),
+                             hipMemcpyHostToDevice));
+  HIP_OR_FAIL(h, hipMemcpy(h->d_gcg_rowptr, row_ptr.data(), row_ptr.size() * 4,
+                           hipMemcpyHostToDevice));
+  if (!idx.empty())
+    HIP_OR_FAIL(h, hipMemcpy(h->d_gcg_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+  h->gcg_gen = h->gram_gen;
+  return ELMFB_OK;
+}
+
 hipError_t enqueue_iterations(elmfb_problem h, const KCtx& c, int method, int n, hipStream_t s) {
   for (int i = 0; i < n; ++i) {
-    hipError_t e = method == ELMFB_LSQR ? lsqr_iteration(h, c, s) : cgls_iteration(h, c, s);
+    hipError_t e = method == ELMFB_LSQR        ? lsqr_iteration(h, c, s)
+                   : method == ELMFB_NORMAL_CG ? gcg_iteration(h, c, s)
+                                               : cgls_iteration(h, c, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -163,7 +273,7 @@ hipError_t enqueue_iterations(elmfb_problem h, const KCtx& c, int method, int n,
 
 hipError_t get_graph(elmfb_problem h, const KCtx& c, int method, int n, hipGraphExec_t* out) {
   const std::vector<int64_t> key = {method, n, (int64_t)c.A, c.prec, (int64_t)c.rhs, c.bj,
-                                    c.apply};
+                                    c.apply, method == ELMFB_NORMAL_CG ? h->gram_gen : 0};
   auto it = h->graphs.find(key);
   if (it != h->graphs.end()) {
     *out = it->second;
@@ -296,6 +406,7 @@ elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stre
   if (st != ELMFB_OK) return st;
   h->gram_prec = prec;
   h->gram_which = which;
+  h->gram_gen += 1;
   h->gram_npairs = (int64_t)pairs.size();
   h->gram_pairs_host = pairs;
   return ELMFB_OK;
@@ -426,8 +537,11 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
   const int method = opts->method;
-  if (method != ELMFB_LSQR && method != ELMFB_CGLS && method != ELMFB_MIXED_IR)
+  if (method != ELMFB_LSQR && method != ELMFB_CGLS && method != ELMFB_MIXED_IR &&
+      method != ELMFB_NORMAL_CG && method != ELMFB_MIXED_IR_CG)
     return fail(h, ELMFB_E_UNSUPPORTED, "unknown solve method");
+  const bool mixed = method == ELMFB_MIXED_IR || method == ELMFB_MIXED_IR_CG;
+  const bool on_gram = method == ELMFB_NORMAL_CG || method == ELMFB_MIXED_IR_CG;
   if (opts->iter_lim < 0 || opts->check_every < 1 || opts->check_every > 100000)
     return fail(h, ELMFB_E_INVALID, "iter_lim >= 0 and 1 <= check_every <= 100000 required");
   if (!(opts->atol >= 0.0) || !(opts->btol >= 0.0))
@@ -437,9 +551,15 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   const bool bj = opts->precond != 0;
   if (bj && method == ELMFB_CGLS) return fail(h, ELMFB_E_UNSUPPORTED, "CGLS has no preconditioner");
   if (bj && !h->bj_ready) return fail(h, ELMFB_E_STATE, "precondition before solving with it");
+  if (mixed && (opts->inner_iters < 1 || opts->outer_lim < 0))
+    return fail(h, ELMFB_E_INVALID, "refinement needs inner_iters >= 1 and outer_lim >= 0");
+  if (on_gram) {
+    if (h->gram_prec < 0 || h->gram_which != 1)
+      return fail(h, ELMFB_E_STATE, "CG on the Gram blocks needs elmfb_gram(h, prec, 1) first");
+    const elmfb_status e = gcg_prepare(h);
+    if (e != ELMFB_OK) return e;
+  }
   if (method == ELMFB_MIXED_IR) {
-    if (opts->inner_iters < 1 || opts->outer_lim < 0)
-      return fail(h, ELMFB_E_INVALID, "MIXED_IR needs inner_iters >= 1 and outer_lim >= 0");
     if (!h->d_A_lo) return fail(h, ELMFB_E_STATE, "MIXED_IR needs a low-precision stored copy");
     if (h->lo_prec == ELMFB_FP16 && !(bj && h->folded_lo))
       return fail(h, ELMFB_E_UNSUPPORTED,
@@ -471,7 +591,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   SolveState init{};
   init.atol = opts->atol;
   init.btol = opts->btol;
-  init.iter_lim = method == ELMFB_MIXED_IR ? opts->inner_iters : opts->iter_lim;
+  init.iter_lim = mixed ? opts->inner_iters : opts->iter_lim;
   init.target = opts->n_check > 0 ? opts->target_rel_l2 : 0.0;
   init.rel_l2 = -1.0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_state, &init, sizeof(init), hipMemcpyHostToDevice, s));
@@ -480,18 +600,24 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   int total_iters = 0, outer = 0;
   double outer_rnorm = -1.0;
   const double* result = h->d_x;
-  if (method != ELMFB_MIXED_IR) {
+  if (!mixed) {
     const bool fold = bj && h->folded64;
-    const KCtx c{fold ? (const void*)h->d_Ahat : (const void*)h->d_A, ELMFB_FP64, h->d_h, bj,
-                 bj && !fold, h->d_A};
-    HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
+    const KCtx c = on_gram ? KCtx{h->d_G, h->gram_prec, h->d_h, bj, false, h->d_A}
+                           : KCtx{fold ? (const void*)h->d_Ahat : (const void*)h->d_A, ELMFB_FP64,
+                                  h->d_h, bj, bj && !fold, h->d_A};
+    // CG on G works on the coefficients themselves; LSQR with block-Jacobi on R x
+    const bool recover = bj && !on_gram;
+    if (on_gram)
+      HIP_OR_FAIL(h, gcg_start(h, c, opts->x0_dev, s));
+    else
+      HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
     HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(h, hipStreamSynchronize(s));
     while (!st.done) {
       HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
       if (opts->n_check > 0) {
         const double* xcur = h->d_x;
-        if (bj) {
+        if (recover) {
           HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, opts->x0_dev, h->d_c, s));
           xcur = h->d_c;
         }
@@ -500,7 +626,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
       HIP_OR_FAIL(h, hipStreamSynchronize(s));
     }
-    if (bj) {
+    if (recover) {
       HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, opts->x0_dev, h->d_c, s));
       result = h->d_c;
     }
@@ -512,9 +638,14 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, launch_copy(opts->x0_dev, h->d_c, g.n_phi, s));
     else
       HIP_OR_FAIL(h, hipMemsetAsync(h->d_c, 0, (size_t)g.n_phi * 8, s));
+    // the inner solve: LSQR on the low-precision copy (MIXED_IR), in preconditioned coordinates
+    // with block-Jacobi, or CG on the stored Gram blocks with rhs M^T r (MIXED_IR_CG)
     const bool fold = bj && h->folded_lo;
-    const KCtx inner{fold ? (const void*)h->d_Ahat_lo : (const void*)h->d_A_lo, h->lo_prec, h->d_r,
-                     bj, bj && !fold, h->d_A};
+    const KCtx inner = on_gram ? KCtx{h->d_G, h->gram_prec, h->d_r, bj, false, h->d_A}
+                               : KCtx{fold ? (const void*)h->d_Ahat_lo : (const void*)h->d_A_lo,
+                                      h->lo_prec, h->d_r, bj, bj && !fold, h->d_A};
+    const int inner_method = on_gram ? ELMFB_NORMAL_CG : ELMFB_LSQR;
+    const bool recover = bj && !on_gram;
     const int rw = rows_wg(g);
     int istop = 7;
     for (outer = 0; outer < opts->outer_lim; ++outer) {
@@ -524,16 +655,19 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_r,
                                         h->d_h, nullptr, red_slot(h, 3), rw, s));
       HIP_OR_FAIL(h, launch_reduce_to(red_slot(h, 3), rw, h->d_scalar, s));
-      HIP_OR_FAIL(h, solve_init(h, inner, ELMFB_LSQR, nullptr, s));
+      if (on_gram)
+        HIP_OR_FAIL(h, gcg_start(h, inner, nullptr, s));
+      else
+        HIP_OR_FAIL(h, solve_init(h, inner, ELMFB_LSQR, nullptr, s));
       int left = opts->inner_iters;
       bool hit = false;
       while (left > 0) {
         const int n = std::min(left, opts->check_every);
-        HIP_OR_FAIL(h, run_iterations(h, inner, ELMFB_LSQR, n, opts->use_graph != 0, s));
+        HIP_OR_FAIL(h, run_iterations(h, inner, inner_method, n, opts->use_graph != 0, s));
         left -= n;
         if (opts->n_check > 0 && left > 0) {
           // trial solution c + d after this part of the inner solve
-          if (bj)
+          if (recover)
             HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_xt, s));
           else {
             HIP_OR_FAIL(h, launch_copy(h->d_c, h->d_xt, g.n_phi, s));
@@ -554,7 +688,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
         if (left > 0 && st.done) break;   // the inner LSQR met its own stopping test
       }
       if (!hit) {
-        if (bj)
+        if (recover)
           HIP_OR_FAIL(h, launch_bj_recover(g, h->d_rinvT, h->d_x, h->d_c, h->d_c, s));
         else
           HIP_OR_FAIL(h, launch_axpy(1.0, h->d_x, h->d_c, g.n_phi, s));
@@ -590,7 +724,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
     info->istop = st.istop;
     info->iters = total_iters;
     info->outer_iters = outer;
-    info->rnorm = method == ELMFB_MIXED_IR ? outer_rnorm : st.rnorm;
+    info->rnorm = mixed ? outer_rnorm : st.rnorm;
     info->arnorm = st.arnorm;
     info->anorm = st.anorm;
     info->xnorm = st.xnorm;

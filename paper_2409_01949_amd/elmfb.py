@@ -24,12 +24,13 @@ OP_D1, OP_NEG_LAPLACE, OP_IDENTITY = 1, 2, 3
 ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 COPY_FOLDED = 0x100
-LSQR, CGLS, MIXED_IR = 0, 1, 2
+LSQR, CGLS, MIXED_IR, NORMAL_CG, MIXED_IR_CG = 0, 1, 2, 3, 4
 
 _OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY}
 _ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
-_METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR}
+_METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR, "normal_cg": NORMAL_CG,
+           "mixed_ir_cg": MIXED_IR_CG}
 
 
 class ProblemDesc(ctypes.Structure):

@@ -150,6 +150,49 @@ def test_normal_cg_solves_spd():
     assert np.allclose(d, np.linalg.solve(G, g), rtol=1e-10)
 
 
+def test_pcg_reduces_to_cg_and_exact_preconditioner_solves_in_one_step():
+    """Preconditioned CG with M = I is plain CG step for step; with M = G the first step is
+    exact; with a block-diagonal M it still terminates in n steps (n = 12); a warm start at the
+    solution leaves it there."""
+    A, _ = _well_conditioned(m=50, n=12, cond=30.0, seed=16)
+    G = A.T @ A
+    g = np.random.default_rng(17).standard_normal(12)
+    ref = np.linalg.solve(G, g)
+    for k in (1, 3, 7):
+        assert np.array_equal(linalg.normal_pcg(lambda p: G @ p, g, k),
+                              linalg.normal_cg(lambda p: G @ p, g, k))
+    d1 = linalg.normal_pcg(lambda p: G @ p, g, 1, apply_Minv=lambda r: np.linalg.solve(G, r))
+    assert np.allclose(d1, ref, rtol=1e-12, atol=0)
+    Mb = np.zeros_like(G)
+    for s0 in (0, 5):
+        Mb[s0:s0 + 5 + 2 * (s0 > 0), s0:s0 + 5 + 2 * (s0 > 0)] = \
+            G[s0:s0 + 5 + 2 * (s0 > 0), s0:s0 + 5 + 2 * (s0 > 0)]
+    dn = linalg.normal_pcg(lambda p: G @ p, g, 12, apply_Minv=lambda r: np.linalg.solve(Mb, r))
+    assert np.allclose(dn, ref, rtol=1e-9, atol=0)
+    d0 = linalg.normal_pcg(lambda p: G @ p, g, 5, x0=ref)
+    assert np.allclose(d0, ref, rtol=1e-12, atol=0)
+
+
+def test_block_jacobi_inverse_apply_inverts_the_shifted_diagonal_blocks():
+    """z = (R^T R)^{-1} r per block equals solving with G_jj + lambda I."""
+    from oracle import assemble as asm
+    spec = configs.small1d_multilevel()
+    W, b = feature_params(spec)
+    blocks = asm.assemble_blocks(spec, W, b)
+    shift = 1e-6
+    facs = linalg.block_jacobi_factors(blocks, shift)
+    n = len(blocks) * spec.K
+    r = np.random.default_rng(18).standard_normal(n)
+    z = linalg.block_jacobi_inverse_apply(blocks, facs, r)
+    for blk in blocks:
+        K = spec.K
+        G = blk.M.T @ blk.M
+        lam = shift * np.trace(G) / K
+        sl = slice(blk.sd.q0, blk.sd.q0 + K)
+        assert np.allclose((G + lam * np.eye(K)) @ z[sl], r[sl], rtol=0,
+                           atol=1e-8 * np.abs(r[sl]).max())
+
+
 def test_refinement_reaches_working_precision():
     """With kappa(G) u_32 << 1, refinement around a float32 inner solve converges to the float64
     least-squares solution (classical iterative refinement)."""
