@@ -38,7 +38,10 @@ def parse():
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="poisson3l")
-    p.add_argument("--method", default="mixed_ir", choices=["lsqr", "cgls", "mixed_ir"])
+    p.add_argument("--method", default="mixed_ir",
+                   choices=["lsqr", "cgls", "mixed_ir", "normal_cg", "mixed_ir_cg"])
+    p.add_argument("--gram-prec", default=None, choices=["fp64", "fp32"],
+                   help="Gram blocks for normal_cg / mixed_ir_cg (default fp64 / fp32)")
     p.add_argument("--no-precond", action="store_true", help="no block-Jacobi preconditioning")
     p.add_argument("--shift", type=float, default=1e-12)
     p.add_argument("--store", default=None, choices=["fp64", "fp32", "bf16", "fp16"],
@@ -62,8 +65,14 @@ def parse():
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run device copies of this many bytes (traffic-counter reference)")
     args = p.parse_args()
+    gram_method = args.method in ("normal_cg", "mixed_ir_cg")
+    if args.gram_prec is None:
+        args.gram_prec = "fp32" if args.method == "mixed_ir_cg" else "fp64"
     if args.store is None:
-        args.store = "fp16" if args.workload in ("poisson3l", "poisson5l") else "fp32"
+        if gram_method:
+            args.store = "fp32" if args.gram_prec == "fp32" else "fp64"
+        else:
+            args.store = "fp16" if args.workload in ("poisson3l", "poisson5l") else "fp32"
     if args.inner is None:
         args.inner = 500 if args.store in ("fp16", "bf16") else 2500
     return args
@@ -371,12 +380,16 @@ def main():
     coef = torch.empty(n, dtype=torch.float64, device="cuda")
     u_test = torch.empty(xt.shape[0], dtype=torch.float64, device="cuda")
 
+    gram_method = args.method in ("normal_cg", "mixed_ir_cg")
+
     def step(method=args.method, pre=precond, iters=args.iters):
         P.assemble(fd)
         if pre:
             P.precondition(args.shift)
-        if method == "mixed_ir":
-            info = P.solve(coef, method="mixed_ir", inner_iters=args.inner,
+        if method in ("normal_cg", "mixed_ir_cg"):
+            P.gram(args.gram_prec, "all")
+        if method in ("mixed_ir", "mixed_ir_cg"):
+            info = P.solve(coef, method=method, inner_iters=args.inner,
                            outer_lim=max(1, iters // args.inner), atol=0.0, btol=0.0,
                            check_every=min(args.check_every, args.inner), check_pts=xc,
                            check_ref=uc, target_rel_l2=args.target, precond=pre)
@@ -418,6 +431,36 @@ def main():
     mv_bytes = lambda e: nnz * e + nbp * 8
     achieved = rmv_bytes(es) / (ms_rmv * 1e-3) / 1e9
     kname = {"fp64": "FP64", "fp32": "FP32", "bf16": "BF16", "fp16": "FP16"}[kprec]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"k_rmv_chunks_{kprec}", spec.name),
+                "kernel": f"k_rmv_chunks<{kname}> (x = M^T u, per-chunk pass)",
+                "ms_per_launch": ms_rmv, "algorithmic_bytes_per_launch": rmv_bytes(es),
+                "also": [
+                    {"kernel": f"k_mv_blocks<{kname}> (y = M v, per-block-point pass)",
+                     "ms_per_launch": ms_mv,
+                     "achieved_GBs": mv_bytes(es) / (ms_mv * 1e-3) / 1e9},
+                    {"kernel": "k_rmv_chunks<FP64>", "ms_per_launch": ms_rmv64,
+                     "achieved_GBs": rmv_bytes(8) / (ms_rmv64 * 1e-3) / 1e9},
+                    {"kernel": "k_mv_blocks<FP64>", "ms_per_launch": ms_mv64,
+                     "achieved_GBs": mv_bytes(8) / (ms_mv64 * 1e-3) / 1e9}]}
+    if gram_method:
+        # CG on the Gram blocks: the per-block pass of y = G p reads every stored block once
+        # and writes two K-vectors of partials per block
+        ms_pairs, ms_gmv = P.time_gram_mv(args.kernel_reps)
+        n_pairs = P.sizes["n_pairs"]
+        esg = 8 if args.gram_prec == "fp64" else 4
+        g_bytes = n_pairs * spec.K * spec.K * esg + 2 * n_pairs * spec.K * 8
+        gname = "FP64" if esg == 8 else "FP32"
+        lsqr_roof = roofline
+        roofline = {"bound": "hbm", "achieved": g_bytes / (ms_pairs * 1e-3) / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": g_bytes / (ms_pairs * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": f"k_gmv_pairs<{gname}> (y = G p, per stored Gram block)",
+                    "ms_per_launch": ms_pairs, "algorithmic_bytes_per_launch": g_bytes,
+                    "also": [{"kernel": "G p, both passes", "ms_per_launch": ms_gmv}] +
+                            [{"kernel": lsqr_roof["kernel"], "ms_per_launch": ms_rmv,
+                              "achieved_GBs": achieved}] + lsqr_roof["also"]}
 
     compare = {}
     if not args.no_compare:
@@ -447,14 +490,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.method != "mixed_ir" else f"f64+{args.store}",
+        "dtype": (f"f64+{args.store}" if args.method == "mixed_ir" else
+                  f"f64+{args.gram_prec}" if gram_method else "f64"),
         "data": "synthetic",
         "config": {"workload": spec.name, "rows": spec.n_rows, "cols": n, "nnz": nnz,
                    "levels": [list(J) for J in spec.levels], "K": spec.K,
                    "grid": list(spec.n_points),
                    "method": (f"{args.method}" + ("+block-jacobi" if precond else "") +
                               (f" (inner {args.store} x{args.inner})" if args.method == "mixed_ir"
-                               else "-fp64")),
+                               else f" (gram {args.gram_prec}" +
+                               (f", inner x{args.inner})" if args.method == "mixed_ir_cg" else ")")
+                               if gram_method else "-fp64")),
                    "iter_budget": args.iters, "target_rel_l2": args.target,
                    "reference": "exact solution on the 128x128 check grid"},
         "time_to_solution_s": dt,
@@ -464,19 +510,7 @@ def main():
         "rel_l2_check_at_stop": info["rel_l2"],
         "rel_l2_test_vs_exact": rel_test,
         "e_l1_test": e_l1,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_rmv_chunks_{kprec}", spec.name),
-                     "kernel": f"k_rmv_chunks<{kname}> (x = M^T u, per-chunk pass)",
-                     "ms_per_launch": ms_rmv, "algorithmic_bytes_per_launch": rmv_bytes(es),
-                     "also": [
-                         {"kernel": f"k_mv_blocks<{kname}> (y = M v, per-block-point pass)",
-                          "ms_per_launch": ms_mv,
-                          "achieved_GBs": mv_bytes(es) / (ms_mv * 1e-3) / 1e9},
-                         {"kernel": "k_rmv_chunks<FP64>", "ms_per_launch": ms_rmv64,
-                          "achieved_GBs": rmv_bytes(8) / (ms_rmv64 * 1e-3) / 1e9},
-                         {"kernel": "k_mv_blocks<FP64>", "ms_per_launch": ms_mv64,
-                          "achieved_GBs": mv_bytes(8) / (ms_mv64 * 1e-3) / 1e9}]},
+        "roofline": roofline,
         "compare": compare,
     }
     if not args.no_cpu_baseline:

@@ -392,6 +392,12 @@ void elmfb_mlp_destroy(elmfb_mlp m);
 const char* elmfb_mlp_last_error(elmfb_mlp m);
 
 /* Release everything the handle owns.  NULL is a no-op. */
+/* Time y = G p on the Gram blocks of the last elmfb_gram(h, prec, 1) call (the operator of
+ * ELMFB_NORMAL_CG) with HIP events on `stream`, p = 1, `reps` times each: ms_host[0] = one
+ * launch of the per-block pass alone (reads every stored block once), ms_host[1] = both passes.
+ * Overwrites the solver's work vectors; blocks the host until the timing completes. */
+elmfb_status elmfb_time_gram_mv(elmfb_problem h, int32_t reps, double* ms_host, void* stream);
+
 void elmfb_destroy(elmfb_problem h);
 
 /* Message of the last failing call on this handle (NULL: of the calling thread). */

@@ -239,12 +239,15 @@ size_t gram_smem_bytes(int prec, int K) { return gram_smem(prec, K); }
 //
 // G = M^T M is symmetric; only the blocks G_ij (i <= j) are stored.  Pass 1, one workgroup per
 // stored block: the row products G_ij p_j (for block-row i) and, off the diagonal, the column
-// products G_ij^T p_i (for block-row j), each written as a K-vector of partials; G_ij is read
-// once, 16 rows at a time through LDS.  Pass 2 (k_gmv_rows): every output coefficient sums the
-// partials that belong to its block-row in a fixed order (a table built on the host), and the
-// workgroup adds its share of p . y.  Deterministic; no atomics.
-constexpr int kGmvRows = 16;
+// products G_ij^T p_i (for block-row j), each written as a K-vector of partials.  A group of 16
+// lanes owns one row at a time and reads it in 128-byte segments (lane s takes columns
+// s, s + 16, ...), so G_ij is read from memory exactly once: each loaded entry feeds the row
+// sum (a 16-lane butterfly) and the lane's running column sums, which are added over the 16
+// row groups through LDS at the end.  Pass 2 (k_gmv_rows): every output coefficient sums the
+// partials that belong to its block-row in a fixed order (a table built on the host), 4 lanes
+// per coefficient, and the workgroup adds its share of p . y.  Deterministic; no atomics.
 constexpr int kGmvMaxK = 256;
+constexpr int kGmvCols = kGmvMaxK / 16;   // columns per lane
 
 template <typename GT>
 __global__ void __launch_bounds__(256) k_gmv_pairs(int K, const GramPair* __restrict__ pairs,
@@ -252,8 +255,8 @@ __global__ void __launch_bounds__(256) k_gmv_pairs(int K, const GramPair* __rest
                                                    const double* __restrict__ p,
                                                    const SolveState* __restrict__ st,
                                                    double* __restrict__ part) {
-  __shared__ double tile[kGmvRows][kGmvMaxK + 1];
   __shared__ double pi_s[kGmvMaxK], pj_s[kGmvMaxK];
+  __shared__ double csum[16][kGmvMaxK];
   if (st && st->done) return;
   const int pr = blockIdx.x;
   const GramPair P = pairs[pr];
@@ -262,34 +265,49 @@ __global__ void __launch_bounds__(256) k_gmv_pairs(int K, const GramPair* __rest
     pi_s[t] = p[qi + t];
     pj_s[t] = p[qj + t];
   }
+  __syncthreads();
   const GT* Gb = G + P.g_off;
   const bool offd = P.bi != P.bj;
   const int r = threadIdx.x >> 4, s = threadIdx.x & 15;
-  double colsum = 0.0;     // (G_ij^T p_i)[threadIdx.x]
-  for (int k0 = 0; k0 < K; k0 += kGmvRows) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kGmvRows * K; e += 256) {
-      const int rr = e / K, c = e - rr * K;
-      tile[rr][c] = (k0 + rr < K) ? (double)Gb[(int64_t)(k0 + rr) * K + c] : 0.0;
-    }
-    __syncthreads();
-    // row k0 + r: 16 lanes each take every 16th column, then a 16-lane butterfly
+  const int nc = (K - s + 15) >> 4;          // columns s + 16 j < K of this lane
+  double pjr[kGmvCols], cs[kGmvCols];
+#pragma unroll
+  for (int j = 0; j < kGmvCols; ++j) {
+    pjr[j] = j < nc ? pj_s[s + 16 * j] : 0.0;
+    cs[j] = 0.0;
+  }
+  for (int k = r; k < K; k += 16) {
+    const GT* row = Gb + (int64_t)k * K + s;
+    double gv[kGmvCols];
+#pragma unroll
+    for (int j = 0; j < kGmvCols; ++j) gv[j] = j < nc ? (double)row[16 * j] : 0.0;
     double v = 0.0;
-    for (int c = s; c < K; c += 16) v += tile[r][c] * pj_s[c];
+#pragma unroll
+    for (int j = 0; j < kGmvCols; ++j) v += gv[j] * pjr[j];
     v += __shfl_xor(v, 8, 16);
     v += __shfl_xor(v, 4, 16);
     v += __shfl_xor(v, 2, 16);
     v += __shfl_xor(v, 1, 16);
-    if (s == 0 && k0 + r < K) part[(int64_t)(2 * pr) * K + k0 + r] = v;
-    if (offd && threadIdx.x < K) {
-      const int nr = K - k0 < kGmvRows ? K - k0 : kGmvRows;
-      for (int rr = 0; rr < nr; ++rr) colsum += tile[rr][threadIdx.x] * pi_s[k0 + rr];
-    }
+    if (s == 0) part[(int64_t)(2 * pr) * K + k] = v;
+    const double pk = pi_s[k];
+#pragma unroll
+    for (int j = 0; j < kGmvCols; ++j) cs[j] += gv[j] * pk;
   }
-  if (offd && threadIdx.x < K) part[(int64_t)(2 * pr + 1) * K + threadIdx.x] = colsum;
+  if (!offd) return;
+#pragma unroll
+  for (int j = 0; j < kGmvCols; ++j)
+    if (j < nc) csum[r][s + 16 * j] = cs[j];
+  __syncthreads();
+  for (int t = threadIdx.x; t < K; t += 256) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v += csum[q][t];
+    part[(int64_t)(2 * pr + 1) * K + t] = v;
+  }
 }
 
-// y[b K + k] = sum over the partials listed for block-row b (row_ptr / idx, in table order);
+// y[b K + k] = sum over the partials listed for block-row b (row_ptr / idx, in table order),
+// 4 lanes per coefficient taking every 4th partial, combined by a fixed butterfly;
 // red[workgroup] = its share of p . y.
 __global__ void __launch_bounds__(256) k_gmv_rows(int K, int64_t n_phi,
                                                   const int32_t* __restrict__ row_ptr,
@@ -301,26 +319,47 @@ __global__ void __launch_bounds__(256) k_gmv_rows(int K, int64_t n_phi,
                                                   double* __restrict__ red) {
   __shared__ double sh[4];
   if (st && st->done) return;
+  const int sub = threadIdx.x & 3;
   double acc = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_phi;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t n4 = n_phi * 4;
+  for (int64_t t4 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t4 < n4;
+       t4 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = t4 >> 2;
     const int b = (int)(t / K), k = (int)(t - (int64_t)b * K);
-    int e = row_ptr[b];
     const int e1 = row_ptr[b + 1];
     double v = 0.0;
-    for (; e + 8 <= e1; e += 8) {   // 8 partials in flight, summed in table order
-      double tv[8];
+    int e = row_ptr[b] + sub;
+    for (; e + 12 < e1; e += 16) {   // 4 partials of this lane in flight
+      double tv[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tv[q] = part[(int64_t)idx[e + q] * K + k];
+      for (int q = 0; q < 4; ++q) tv[q] = part[(int64_t)idx[e + 4 * q] * K + k];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v += tv[q];
+      for (int q = 0; q < 4; ++q) v += tv[q];
     }
-    for (; e < e1; ++e) v += part[(int64_t)idx[e] * K + k];
-    y[t] = v;
-    acc += p[t] * v;
+    for (; e < e1; e += 4) v += part[(int64_t)idx[e] * K + k];
+    v += __shfl_xor(v, 1, 4);
+    v += __shfl_xor(v, 2, 4);
+    if (sub == 0) {
+      y[t] = v;
+      acc += p[t] * v;
+    }
   }
   const double sum = block_sum256(acc, sh);
   if (threadIdx.x == 0) red[blockIdx.x] = sum;
+}
+
+hipError_t launch_gram_mv_pairs_only(const Geo& g, int gram_prec, const GramPair* pairs,
+                                     int64_t n_pairs, const void* G, const double* p, double* part,
+                                     hipStream_t s) {
+  if (g.K > kGmvMaxK) return hipErrorInvalidValue;
+  if (n_pairs == 0) return hipSuccess;
+  if (gram_prec == ELMFB_FP64)
+    hipLaunchKernelGGL(k_gmv_pairs<double>, dim3((unsigned)n_pairs), dim3(256), 0, s, g.K, pairs,
+                       (const double*)G, p, nullptr, part);
+  else
+    hipLaunchKernelGGL(k_gmv_pairs<float>, dim3((unsigned)n_pairs), dim3(256), 0, s, g.K, pairs,
+                       (const float*)G, p, nullptr, part);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_mv(const Geo& g, int gram_prec, const GramPair* pairs, int64_t n_pairs,
@@ -339,7 +378,7 @@ hipError_t launch_gram_mv(const Geo& g, int gram_prec, const GramPair* pairs, in
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_gmv_rows, dim3(n_wg), dim3(256), 0, s, g.K, g.n_phi, row_ptr, idx, part,
-                     p, y, st, red);
+                     p, y, st, red);   // n_wg <= kRedBlocks partials
   return hipGetLastError();
 }
 

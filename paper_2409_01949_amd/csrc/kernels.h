@@ -81,6 +81,9 @@ hipError_t launch_gram_mv(const Geo& g, int gram_prec, const GramPair* pairs, in
                           const void* G, const int32_t* row_ptr, const int32_t* idx,
                           const double* p, double* part, double* y, const SolveState* st,
                           double* red, int n_wg, hipStream_t s);
+hipError_t launch_gram_mv_pairs_only(const Geo& g, int gram_prec, const GramPair* pairs,
+                                     int64_t n_pairs, const void* G, const double* p, double* part,
+                                     hipStream_t s);
 // CG on the Gram blocks (FP64 vectors and scalars).
 hipError_t launch_gcg_init(SolveState* st, const double* red_b, int nb, const double* red_r,
                            int nr, const double* red_z, int nz, hipStream_t s);

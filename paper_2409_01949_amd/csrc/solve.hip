@@ -153,12 +153,18 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
   return hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s);
 }
 
-// y = G p on the stored Gram blocks (all pairs), p . y partials into red.
+// Workgroups (and p . y partials) of the second pass of y = G p: 4 lanes per coefficient.
+int gmv_wg(const Geo& g) {
+  const int64_t nb = (4 * g.n_phi + 255) / 256;
+  return (int)(nb < kRedBlocks ? nb : kRedBlocks);
+}
+
+// y = G p on the stored Gram blocks (all pairs), gmv_wg p . y partials into red.
 hipError_t gram_mv(elmfb_problem h, const double* p, double* y, const SolveState* st, double* red,
                    hipStream_t s) {
   return launch_gram_mv(h->geo, h->gram_prec, h->d_gcg_pairs, h->gram_npairs, h->d_G,
                         h->d_gcg_rowptr, h->d_gcg_idx, p, h->d_gcg_part, y, st, red,
-                        cols_wg(h->geo), s);
+                        gmv_wg(h->geo), s);
 }
 
 // z = (R^T R)^{-1} r = R^{-1} R^{-T} r per block (block-Jacobi of the normal equations).
@@ -177,7 +183,7 @@ hipError_t gcg_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
   const int cw = cols_wg(g);
   hipError_t e;
   if ((e = gram_mv(h, h->d_w, h->d_vt, st, red1, s))) return e;
-  if ((e = launch_gcg_alpha(st, red1, cw, s))) return e;
+  if ((e = launch_gcg_alpha(st, red1, gmv_wg(g), s))) return e;
   if ((e = launch_gcg_update(g, h->d_x, h->d_v, h->d_w, h->d_vt, st, red2, cw, s))) return e;
   const double* z = h->d_v;
   if (c.bj) {
@@ -732,6 +738,42 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
     info->ms_solve =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_time_gram_mv(elmfb_problem h, int32_t reps, double* ms_host, void* stream) {
+  if (!h || !ms_host || reps < 1) return fail(h, ELMFB_E_INVALID, "bad argument");
+  if (h->gram_prec < 0 || h->gram_which != 1)
+    return fail(h, ELMFB_E_STATE, "time_gram_mv needs elmfb_gram(h, prec, 1) first");
+  const elmfb_status es = gcg_prepare(h);
+  if (es != ELMFB_OK) return es;
+  hipStream_t s = (hipStream_t)stream;
+  const Geo& g = h->geo;
+  std::vector<double> ones((size_t)g.n_phi, 1.0);
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_w, ones.data(), (size_t)g.n_phi * 8, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1, e2;
+  HIP_OR_FAIL(h, hipEventCreate(&e0));
+  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  HIP_OR_FAIL(h, hipEventCreate(&e2));
+  // pass 1 alone (pairs), then both passes (pairs + rows)
+  hipError_t e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = launch_gram_mv_pairs_only(g, h->gram_prec, h->d_gcg_pairs, h->gram_npairs, h->d_G,
+                                  h->d_w, h->d_gcg_part, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = gram_mv(h, h->d_w, h->d_vt, nullptr, red_slot(h, 0), s);
+  if (e == hipSuccess) e = hipEventRecord(e2, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e2);
+  float t01 = 0.f, t12 = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t01, e0, e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&t12, e1, e2);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipEventDestroy(e2);
+  HIP_OR_FAIL(h, e);
+  ms_host[0] = (double)t01 / reps;
+  ms_host[1] = (double)t12 / reps;
   return ELMFB_OK;
 }
 

@@ -138,6 +138,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
         "elmfb_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(dbl), P]),
+        "elmfb_time_gram_mv": (i32, [P, i32, ctypes.POINTER(dbl), P]),
         "elmfb_define_batch": (i32, [ctypes.POINTER(ProblemDesc), i32, i32, ctypes.POINTER(P)]),
         "elmfb_batch_query": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(Sizes)]),
         "elmfb_batch_assemble": (i32, [P, P, P]),
@@ -344,6 +345,12 @@ class Problem:
         out = (ctypes.c_double * 2)()
         pr = _PREC[prec] if isinstance(prec, str) else int(prec)
         _check(_lib.elmfb_time_kernels(self.h, pr, int(reps), out, _stream(stream)), self.h)
+        return float(out[0]), float(out[1])
+
+    def time_gram_mv(self, reps=20, stream=None):
+        """Average duration (ms) of the per-block pass of y = G p alone and of both passes."""
+        out = (ctypes.c_double * 2)()
+        _check(_lib.elmfb_time_gram_mv(self.h, int(reps), out, _stream(stream)), self.h)
         return float(out[0]), float(out[1])
 
     def destroy(self):

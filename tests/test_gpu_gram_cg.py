@@ -169,3 +169,18 @@ def test_normal_cg_stops_on_its_test_and_needs_all_pairs():
     # the recursively updated residual the test reads may drift from g - G a by rounding
     assert rr <= 2 * btol * np.linalg.norm(g)
     P.destroy()
+
+
+def test_time_gram_mv_runs_and_leaves_products_valid(case):
+    """The timing entry point runs both passes on the stored blocks and reports positive
+    durations; a CG solve afterwards still matches the oracle's first step."""
+    spec, P, blocks, h, pairs = case
+    n = P.sizes["n_phi"]
+    P.gram("fp64", "all")
+    ms = P.time_gram_mv(3)
+    assert ms[0] > 0 and ms[1] >= ms[0] * 0.5
+    G = linalg.gram_blocks(blocks, pairs)
+    g = asm.rmatvec(blocks, h, n)
+    a, _ = _solve(P, n, method="normal_cg", iter_lim=1, atol=0, btol=0)
+    ref = linalg.normal_pcg(lambda p: linalg.gram_apply(G, blocks, p), g, 1)
+    assert _rel(a, ref) <= 1e-9
