@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("time-to-solution at rel-L2 1e-6 (s) and collocation rows/s; "
           "mixed/batched vs plain FP64")
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X (TFLOP/s), per input type
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
 
 def parse():
@@ -50,6 +52,7 @@ def parse():
     p.add_argument("--inner", type=int, default=None,
                    help="inner LSQR steps per refinement step (default: 500 on a 16-bit copy, "
                         "2500 on fp32)")
+    p.add_argument("--no-gram", action="store_true", help="skip the Gram-phase MFMA timing")
     p.add_argument("--no-compare", action="store_true",
                    help="skip the FP64 comparison solves")
     p.add_argument("--iters", type=int, default=15000)
@@ -462,6 +465,18 @@ def main():
                             [{"kernel": lsqr_roof["kernel"], "ms_per_launch": ms_rmv,
                               "achieved_GBs": achieved}] + lsqr_roof["also"]}
 
+    # the Gram phase on the matrix cores: all overlapping pairs, FP64 and the stored copy's type
+    gram_mfma = []
+    if not args.no_gram:
+        for gp in ["fp64"] + ([args.store] if args.store in ("fp32", "bf16", "fp16") else []):
+            ms_g, fl = P.time_gram(gp, "all", reps=3)
+            tf = fl / (ms_g * 1e-3) / 1e12
+            gram_mfma.append({"kernel": f"k_gram<{gp.upper()}> (+ chunk reduction), "
+                                        f"{P.sizes['n_pairs']} pairs", "ms": ms_g, "flops": fl,
+                              "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[gp],
+                              "frac": tf / MFMA_PEAK_TFLOPS[gp]})
+            note(f"gram {gp}: {ms_g:.2f} ms, {tf:.1f} TFLOP/s")
+
     compare = {}
     if not args.no_compare:
         for label, meth, pre in (("fp64_block_jacobi_lsqr", "lsqr", True),
@@ -511,6 +526,7 @@ def main():
         "rel_l2_test_vs_exact": rel_test,
         "e_l1_test": e_l1,
         "roofline": roofline,
+        "gram_mfma": gram_mfma,
         "compare": compare,
     }
     if not args.no_cpu_baseline:

@@ -220,6 +220,14 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
  * the handle (FP64 or FP32) until the next elmfb_gram call. */
 elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stream);
 
+/* elmfb_gram, then the same Gram computation `reps` more times between HIP events on `stream`:
+ * ms_host = the average duration of one computation (all its kernels), flops_host (may be NULL)
+ * = 2 K^2 times the shared points summed over the computed pairs (the useful MFMA work; K is
+ * padded to 16 on the matrix cores).  The stored blocks are those of elmfb_gram afterwards.
+ * Blocks the host until the timing completes. */
+elmfb_status elmfb_time_gram(elmfb_problem h, int32_t prec, int32_t which, int32_t reps,
+                             double* ms_host, double* flops_host, void* stream);
+
 /* Copy the Gram blocks of the last elmfb_gram call (n_pairs x K x K values, FP64 for
  * prec = FP64 else FP32, row index = feature of i) into dst_dev and the pair table
  * [n_pairs][3] (bi, bj, element offset) into pairs_host; *n_pairs_host receives the count.

@@ -75,6 +75,7 @@ struct elmfb_problem_s {
   int64_t gmulti_cap = 0;
   std::vector<GramPair> gram_pairs_host;   // the pairs of the last elmfb_gram call
   int64_t gram_gen = 0;                    // counts elmfb_gram calls
+  int64_t gram_nchunks = 0, gram_nmulti = 0;   // tables of the last Gram launch
 
   // CG on the Gram blocks: device copy of the stored pairs, per block-row tables of partials,
   // partials [2 n_pairs][K], and one extra coefficient vector for the preconditioner

@@ -373,6 +373,8 @@ elmfb_status run_gram(elmfb_problem h, int prec, std::vector<GramPair>& pairs, v
   HIP_OR_FAIL(h, launch_gram(g, prec, h->d_blocks, h->d_gpairs, h->d_gchunks,
                              (int64_t)chunks.size(), h->d_gmulti, (int64_t)multi.size(), A, G,
                              h->d_gpart, s));
+  h->gram_nchunks = (int64_t)chunks.size();
+  h->gram_nmulti = (int64_t)multi.size();
   // the host tables above must outlive the asynchronous copies
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
   return ELMFB_OK;
@@ -415,6 +417,38 @@ elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stre
   h->gram_gen += 1;
   h->gram_npairs = (int64_t)pairs.size();
   h->gram_pairs_host = pairs;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_time_gram(elmfb_problem h, int32_t prec, int32_t which, int32_t reps,
+                             double* ms_host, double* flops_host, void* stream) {
+  if (!h || !ms_host || reps < 1) return fail(h, ELMFB_E_INVALID, "bad argument");
+  const elmfb_status st = elmfb_gram(h, prec, which, stream);
+  if (st != ELMFB_OK) return st;
+  const Geo& g = h->geo;
+  if (flops_host) {
+    double shared = 0.0;
+    for (const GramPair& P : h->gram_pairs_host) shared += (double)P.nx * P.ny;
+    *flops_host = 2.0 * g.K * g.K * shared;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const void* A = prec == ELMFB_FP64 ? (const void*)h->d_A : h->d_A_lo;
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(h, hipEventCreate(&e0));
+  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  // the tables of the call above are still on the device; relaunch the same computation
+  hipError_t e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = launch_gram(g, prec, h->d_blocks, h->d_gpairs, h->d_gchunks, h->gram_nchunks,
+                    h->d_gmulti, h->gram_nmulti, A, h->d_G, h->d_gpart, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIP_OR_FAIL(h, e);
+  *ms_host = (double)t / reps;
   return ELMFB_OK;
 }
 

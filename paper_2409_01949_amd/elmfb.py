@@ -139,6 +139,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
         "elmfb_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(dbl), P]),
         "elmfb_time_gram_mv": (i32, [P, i32, ctypes.POINTER(dbl), P]),
+        "elmfb_time_gram": (i32, [P, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]),
         "elmfb_define_batch": (i32, [ctypes.POINTER(ProblemDesc), i32, i32, ctypes.POINTER(P)]),
         "elmfb_batch_query": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(Sizes)]),
         "elmfb_batch_assemble": (i32, [P, P, P]),
@@ -346,6 +347,15 @@ class Problem:
         pr = _PREC[prec] if isinstance(prec, str) else int(prec)
         _check(_lib.elmfb_time_kernels(self.h, pr, int(reps), out, _stream(stream)), self.h)
         return float(out[0]), float(out[1])
+
+    def time_gram(self, prec="fp64", which="all", reps=5, stream=None):
+        """(ms per Gram computation, useful flops) after computing the blocks as gram() does."""
+        ms, fl = ctypes.c_double(), ctypes.c_double()
+        pr = _PREC[prec] if isinstance(prec, str) else int(prec)
+        w = {"diag": 0, "all": 1}[which] if isinstance(which, str) else int(which)
+        _check(_lib.elmfb_time_gram(self.h, pr, w, int(reps), ctypes.byref(ms), ctypes.byref(fl),
+                                    _stream(stream)), self.h)
+        return ms.value, fl.value
 
     def time_gram_mv(self, reps=20, stream=None):
         """Average duration (ms) of the per-block pass of y = G p alone and of both passes."""

@@ -184,3 +184,17 @@ def test_time_gram_mv_runs_and_leaves_products_valid(case):
     a, _ = _solve(P, n, method="normal_cg", iter_lim=1, atol=0, btol=0)
     ref = linalg.normal_pcg(lambda p: linalg.gram_apply(G, blocks, p), g, 1)
     assert _rel(a, ref) <= 1e-9
+
+
+def test_time_gram_counts_the_useful_flops(case):
+    """elmfb_time_gram leaves the blocks of elmfb_gram behind and counts 2 K^2 times the shared
+    points summed over the oracle's overlapping pairs."""
+    spec, P, blocks, h, pairs = case
+    ms, flops = P.time_gram("fp64", "all", reps=2)
+    shared = sum(np.intersect1d(blocks[i].rows, blocks[j].rows).size for i, j in pairs)
+    assert ms > 0 and flops == 2.0 * spec.K * spec.K * shared
+    G = linalg.gram_blocks(blocks, pairs)
+    n = P.sizes["n_phi"]
+    g = asm.rmatvec(blocks, h, n)
+    a, _ = _solve(P, n, method="normal_cg", iter_lim=1, atol=0, btol=0)
+    assert _rel(a, linalg.normal_pcg(lambda p: linalg.gram_apply(G, blocks, p), g, 1)) <= 1e-9
