@@ -1,9 +1,12 @@
 // Evaluation of the fitted solution at arbitrary points (Sec. 3 eq. multilevel_solution, times
 // the hard-constraint factor of Sec. 4.3):
 //   u(x) = C(x) (1/L) sum_l sum_{j : x in supp omega_j} omega_j(x) sum_k a_q tanh(W_q xbar + b_q).
-// One thread per point.  Per level the covering subdomains along each axis are found from the
-// centre spacing and checked with the support test |x - mu| < sigma; the per-axis window sums
-// give the partition-of-unity normalisation.  This kernel is bound by the FP64 tanh throughput.
+// One wavefront per point: the lanes take the features of each covering subdomain (64 at a time)
+// and the point's sum is reduced across the wavefront at the end in a fixed order (a sum over
+// ~16 subdomains x K features per point, so one thread per point left most of the device idle on
+// check grids of 16,384 points).  Per level the covering subdomains along each axis are found
+// from the centre spacing and checked with the support test |x - mu| < sigma; the per-axis
+// window sums give the partition-of-unity normalisation.  Bound by the FP64 tanh throughput.
 #include "device.h"
 #include "kernels.h"
 
@@ -46,8 +49,10 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
                                                   const double* __restrict__ coef,
                                                   const double* __restrict__ pts, int64_t n_pts,
                                                   double* __restrict__ u) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_pts;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; i < n_pts;
+       i += nwaves) {
     const double x = pts[i * g.dim];
     const double y = (g.dim == 2) ? pts[i * g.dim + 1] : 0.0;
     double total = 0.0;
@@ -64,7 +69,7 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
           const double yb = (g.dim == 2) ? (y - centre(g, l, 1, jys[ay])) / sy : 0.0;
           const int64_t q0 = (int64_t)(g.bbase[l] + jxs[ax] * g.J[l][1] + jys[ay]) * g.K;
           double acc = 0.0;
-          for (int k = 0; k < g.K; ++k) {
+          for (int k = lane; k < g.K; k += 64) {
             const int64_t q = q0 + k;
             const double z = W[2 * q] * xb + ((g.dim == 2) ? W[2 * q + 1] * yb : 0.0) + bias[q];
             acc += coef[q] * tanh(z);
@@ -74,10 +79,11 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
       }
       total += lev;
     }
+    total = wave_sum(total);
     double cx, c1, c2, cy;
     ansatz_axis(g, 0, x, cx, c1, c2);
     ansatz_axis(g, 1, y, cy, c1, c2);
-    u[i] = total * (cx * cy) * g.inv_levels;
+    if (lane == 0) u[i] = total * (cx * cy) * g.inv_levels;
   }
 }
 
@@ -124,7 +130,7 @@ __global__ void __launch_bounds__(256) k_rel_l2_final(const double* __restrict__
 hipError_t launch_evaluate(const Geo& g, const double* W, const double* b, const double* coef,
                            const double* pts, int64_t n_pts, double* u, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
-  int64_t nb = (n_pts + 255) / 256;
+  int64_t nb = (n_pts + 3) / 4;   // 4 points (wavefronts) per workgroup
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_evaluate, dim3((unsigned)nb), dim3(256), 0, s, g, W, b, coef, pts, n_pts, u);
   return hipGetLastError();
