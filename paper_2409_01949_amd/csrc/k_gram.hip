@@ -23,7 +23,7 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kStage = 32;        // points per LDS stage
-constexpr int kTilesPerGroup = 64; // 16 per wave
+constexpr int kGramPf = 16;       // register-prefetched entries per thread (K <= 128)
 
 template <int PREC> struct GramTypes;
 template <> struct GramTypes<ELMFB_FP64> { typedef double in_t; typedef double acc_t; typedef d4_t v4; };
@@ -51,7 +51,9 @@ __device__ __forceinline__ _Float16 load_in<ELMFB_FP16>(const void* A, int64_t i
   return static_cast<const _Float16*>(A)[i];
 }
 
-template <int PREC>
+// TPW output tiles of 16 x 16 per wave (4 TPW per workgroup): 4 for K <= 64, 9 for K <= 96,
+// 16 above, so that the accumulators of small K leave room for the prefetch registers.
+template <int PREC, int TPW>
 __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict__ blocks,
                                               const GramPair* __restrict__ pairs,
                                               const GramChunk* __restrict__ chunks,
@@ -68,7 +70,6 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
   const int Kp = (K + 15) & ~15;
   in_t* X = reinterpret_cast<in_t*>(smem);
   in_t* Y = X + (size_t)Kp * STR;
-  int* pidx = reinterpret_cast<int*>(Y + (size_t)Kp * STR);   // [2][kStage]
 
   const GramChunk ck = chunks[blockIdx.x];
   const GramPair pr = pairs[ck.pair];
@@ -77,47 +78,83 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
   const int s_end = min(ck.s0 + kGramChunk, nshared);
   const int nT = Kp / 16;
   const int ntiles = nT * nT;
-  const int t_base = blockIdx.y * kTilesPerGroup;
+  const int t_base = blockIdx.y * 4 * TPW;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
+  // a diagonal block G_jj multiplies the staged rows by themselves: stage them once
+  const bool diag = pr.bi == pr.bj;
+  const in_t* Yop = diag ? X : Y;
 
-  v4 acc[kTilesPerGroup / 4];
+  v4 acc[TPW];
 #pragma unroll
-  for (int i = 0; i < kTilesPerGroup / 4; ++i) acc[i] = v4{0, 0, 0, 0};
+  for (int i = 0; i < TPW; ++i) acc[i] = v4{0, 0, 0, 0};
 
-  for (int s0 = ck.s0; s0 < s_end; s0 += kStage) {
-    if (threadIdx.x < kStage) {
-      const int s = s0 + threadIdx.x;
-      int pi = -1, pj = -1;
-      if (s < s_end) {
-        const int sx = s / pr.ny, sy = s - sx * pr.ny;
-        const int ix = pr.ix0 + sx, iy = pr.iy0 + sy;
-        pi = (ix - Bi.ix0) * Bi.ny + (iy - Bi.iy0);
-        pj = (ix - Bj.ix0) * Bj.ny + (iy - Bj.iy0);
-      }
-      pidx[threadIdx.x] = pi;
-      pidx[kStage + threadIdx.x] = pj;
+  // every thread stages one point slot (s_l) of the stage for features k_l, k_l + 8, ...; the
+  // next stage's entries are loaded into registers while the matrix cores work on this one
+  const int s_l = threadIdx.x & (kStage - 1), k_l = threadIdx.x >> 5;
+  constexpr int kRows = 256 / kStage;            // feature rows per pass (8)
+  in_t rx[kGramPf], ry[kGramPf];
+  const int npf = Kp / kRows;                    // passes (<= kGramPf when prefetching)
+  auto point_idx = [&](int s0, int& pi, int& pj) {
+    const int s = s0 + s_l;
+    pi = pj = -1;
+    if (s < s_end) {
+      const int sx = s / pr.ny, sy = s - sx * pr.ny;
+      const int ix = pr.ix0 + sx, iy = pr.iy0 + sy;
+      pi = (ix - Bi.ix0) * Bi.ny + (iy - Bi.iy0);
+      pj = (ix - Bj.ix0) * Bj.ny + (iy - Bj.iy0);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < Kp * kStage; e += 256) {
-      const int k = e / kStage, s = e - k * kStage;
-      const int pi = pidx[s], pj = pidx[kStage + s];
+  };
+  auto fetch = [&](int s0) {
+    int pi, pj;
+    point_idx(s0, pi, pj);
+#pragma unroll
+    for (int m = 0; m < kGramPf; ++m) {
+      const int k = k_l + kRows * m;
       in_t xv = in_t(0.0f), yv = in_t(0.0f);
-      if (k < K && pi >= 0) {
+      if (m < npf && k < K && pi >= 0) {
         xv = load_in<PREC>(A, Bi.a_off + (int64_t)k * Bi.ld + pi);
-        yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.ld + pj);
+        if (!diag) yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.ld + pj);
       }
-      X[k * STR + s] = xv;
-      Y[k * STR + s] = yv;
+      rx[m] = xv;
+      ry[m] = yv;
+    }
+  };
+  const bool pf = npf <= kGramPf;
+  if (pf) fetch(ck.s0);
+  for (int s0 = ck.s0; s0 < s_end; s0 += kStage) {
+    __syncthreads();   // the previous stage's products are done with X and Y
+    if (pf) {
+#pragma unroll
+      for (int m = 0; m < kGramPf; ++m) {
+        if (m < npf) {
+          const int k = k_l + kRows * m;
+          X[k * STR + s_l] = rx[m];
+          if (!diag) Y[k * STR + s_l] = ry[m];
+        }
+      }
+    } else {
+      int pi, pj;
+      point_idx(s0, pi, pj);
+      for (int k = k_l; k < Kp; k += kRows) {
+        in_t xv = in_t(0.0f), yv = in_t(0.0f);
+        if (k < K && pi >= 0) {
+          xv = load_in<PREC>(A, Bi.a_off + (int64_t)k * Bi.ld + pi);
+          if (!diag) yv = load_in<PREC>(A, Bj.a_off + (int64_t)k * Bj.ld + pj);
+        }
+        X[k * STR + s_l] = xv;
+        if (!diag) Y[k * STR + s_l] = yv;
+      }
     }
     __syncthreads();
+    if (pf && s0 + kStage < s_end) fetch(s0 + kStage);
 #pragma unroll
-    for (int i = 0; i < kTilesPerGroup / 4; ++i) {
+    for (int i = 0; i < TPW; ++i) {
       const int t = t_base + wid + 4 * i;
       if (t < ntiles) {
         const int I = t / nT, J = t - (t / nT) * nT;
         const in_t* xr = X + (I * 16 + li) * STR;
-        const in_t* yr = Y + (J * 16 + li) * STR;
+        const in_t* yr = Yop + (J * 16 + li) * STR;
         if constexpr (PREC == ELMFB_BF16) {
           bf8_t a, b;
 #pragma unroll
@@ -146,7 +183,7 @@ __global__ void __launch_bounds__(256) k_gram(Geo g, const DevBlock* __restrict_
   acc_t* out = (pr.nchunks == 1) ? G + pr.g_off
                                  : part + (int64_t)(blockIdx.x - pr.c0 + pr.p_off) * K * K;
 #pragma unroll
-  for (int i = 0; i < kTilesPerGroup / 4; ++i) {
+  for (int i = 0; i < TPW; ++i) {
     const int t = t_base + wid + 4 * i;
     if (t < ntiles) {
       const int I = t / nT, J = t - (t / nT) * nT;
@@ -182,46 +219,48 @@ static size_t gram_smem(int prec, int K) {
   return 2 * (size_t)Kp * str * es + 2 * kStage * sizeof(int) + 16;
 }
 
+template <int PREC, int TPW>
+static hipError_t gram_launch(const Geo& g, const DevBlock* blocks, const GramPair* pairs,
+                              const GramChunk* chunks, int64_t n_chunks, const void* A, void* G,
+                              void* part, size_t sm, hipStream_t s) {
+  typedef typename GramTypes<PREC>::acc_t acc_t;
+  const int Kp = (g.K + 15) & ~15;
+  const int nT = Kp / 16;
+  const int groups = (nT * nT + 4 * TPW - 1) / (4 * TPW);
+  if (sm > 64 * 1024) {
+    const hipError_t ea = hipFuncSetAttribute((const void*)k_gram<PREC, TPW>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (ea != hipSuccess) return ea;
+  }
+  hipLaunchKernelGGL((k_gram<PREC, TPW>), dim3((unsigned)n_chunks, (unsigned)groups), dim3(256),
+                     sm, s, g, blocks, pairs, chunks, A, (acc_t*)G, (acc_t*)part);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t gram_launch_k(const Geo& g, const DevBlock* blocks, const GramPair* pairs,
+                                const GramChunk* chunks, int64_t n_chunks, const void* A, void* G,
+                                void* part, size_t sm, hipStream_t s) {
+  if (g.K <= 64) return gram_launch<PREC, 4>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+  if (g.K <= 96) return gram_launch<PREC, 9>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+  return gram_launch<PREC, 16>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+}
+
 hipError_t launch_gram(const Geo& g, int prec, const DevBlock* blocks, const GramPair* pairs,
                        const GramChunk* chunks, int64_t n_chunks, const int32_t* multi,
                        int64_t n_multi, const void* A, void* G, void* part, hipStream_t s) {
   if (n_chunks == 0) return hipSuccess;
-  const int Kp = (g.K + 15) & ~15;
-  const int nT = Kp / 16;
-  const int groups = (nT * nT + kTilesPerGroup - 1) / kTilesPerGroup;
-  const dim3 grid((unsigned)n_chunks, (unsigned)groups), blk(256);
   const size_t sm = gram_smem(prec, g.K);
   if (sm > 160 * 1024) return hipErrorInvalidValue;
-  if (sm > 64 * 1024) {
-    hipError_t ea = hipSuccess;
-    if (prec == ELMFB_FP64)
-      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP64>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    else if (prec == ELMFB_FP32)
-      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP32>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    else if (prec == ELMFB_BF16)
-      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_BF16>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    else
-      ea = hipFuncSetAttribute((const void*)k_gram<ELMFB_FP16>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (ea != hipSuccess) return ea;
-  }
-  if (prec == ELMFB_FP64) {
-    hipLaunchKernelGGL(k_gram<ELMFB_FP64>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
-                       (double*)G, (double*)part);
-  } else if (prec == ELMFB_FP32) {
-    hipLaunchKernelGGL(k_gram<ELMFB_FP32>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
-                       (float*)G, (float*)part);
-  } else if (prec == ELMFB_BF16) {
-    hipLaunchKernelGGL(k_gram<ELMFB_BF16>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
-                       (float*)G, (float*)part);
-  } else {
-    hipLaunchKernelGGL(k_gram<ELMFB_FP16>, grid, blk, sm, s, g, blocks, pairs, chunks, A,
-                       (float*)G, (float*)part);
-  }
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (prec == ELMFB_FP64)
+    e = gram_launch_k<ELMFB_FP64>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+  else if (prec == ELMFB_FP32)
+    e = gram_launch_k<ELMFB_FP32>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+  else if (prec == ELMFB_BF16)
+    e = gram_launch_k<ELMFB_BF16>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
+  else
+    e = gram_launch_k<ELMFB_FP16>(g, blocks, pairs, chunks, n_chunks, A, G, part, sm, s);
   if (e != hipSuccess || n_multi == 0) return e;
   const dim3 rgrid((unsigned)n_multi, (unsigned)((g.K * g.K + 255) / 256 < 16 ? (g.K * g.K + 255) / 256 : 16));
   if (prec == ELMFB_FP64)
