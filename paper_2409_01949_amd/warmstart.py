@@ -132,10 +132,11 @@ def family_batch(omegas, C, store_prec="fp32"):
     return B, specs, hn
 
 
-def solve_batch(B, x0=None, btol=1e-4, inner=1000, outer=8, shift=1e-12, precondition=True):
-    """Refined block-Jacobi solve of every pair to ||h - M c|| <= btol ||h||, coefficients in
-    block-Jacobi coordinates (x0 and result); returns (coefficients on the host, infos,
-    seconds)."""
+def solve_batch(B, x0=None, btol=1e-4, inner=1000, outer=8, shift=1e-12, precondition=True,
+                atol=0.0):
+    """Refined block-Jacobi solve of every pair to ||h - M c|| <= btol ||h|| (or, with atol > 0,
+    to least-squares optimality ||M^T r|| <= atol ||M|| ||r||), coefficients in block-Jacobi
+    coordinates (x0 and result); returns (coefficients on the host, infos, seconds)."""
     import torch
 
     if precondition:
@@ -144,7 +145,7 @@ def solve_batch(B, x0=None, btol=1e-4, inner=1000, outer=8, shift=1e-12, precond
     coef = torch.empty(B.n_rhs * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = B.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, atol=0.0,
+    infos = B.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer, atol=atol,
                     btol=btol, check_every=50, precond=True, x0=x0)
     torch.cuda.synchronize()
     return coef.cpu().numpy(), infos, time.perf_counter() - t0
