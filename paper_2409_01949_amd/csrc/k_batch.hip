@@ -476,6 +476,11 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
   const int K = g.K, n = B.n, gny = g.ny;
   const in_t* Ab = static_cast<const in_t*>(A) + B.a_off;
 
+  // every U entry a thread stages has right-hand side threadIdx.x & 7: its pair scale is read
+  // once, and applied when the tile is written to LDS, so the loads of the next tile stay in
+  // flight while the current one is reduced
+  const int ju = threadIdx.x & 7;
+  const double usc = ju < R ? pair_scale(st, B.inst * R + ju, false) : 0.0;
   in_t ra[NA];
   double ru[NU];
   auto fetch = [&](int p0) {
@@ -495,7 +500,7 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
       if (c < TP && j < R && p < n) {
         const int lx = p / B.ny, ly = p - (p / B.ny) * B.ny;
         const int64_t r = row0 + (int64_t)(B.ix0 + lx) * gny + (B.iy0 + ly);
-        val = u[r * R + j] * pair_scale(st, B.inst * R + j, false);
+        val = u[r * R + j];
       }
       ru[m] = val;
     }
@@ -515,7 +520,7 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       const int e = threadIdx.x + 256 * m;
-      if ((e >> 3) < TP) us[e >> 3][e & 7] = ru[m];
+      if ((e >> 3) < TP) us[e >> 3][e & 7] = ru[m] * usc;
     }
     __syncthreads();
     if (p0 + TP < n) fetch(p0 + TP);
