@@ -79,7 +79,9 @@ enum {
   ELMFB_CGLS = 1,       /* CG on the normal equations in factored form, FP64                 */
   ELMFB_MIXED_IR = 2,   /* FP64 iterative refinement: r = h - A c with the FP64 matrix, the
                            correction from inner_iters LSQR steps on the stored FP32/BF16/FP16
-                           copy (FP64 vectors and recurrences), c += d in FP64                */
+                           copy (FP64 vectors and recurrences), c += d in FP64; outer_lim
+                           steps (istop 7), fewer when the inner solve stops before its first
+                           step (r = 0 or A^T r = 0: istop 0)                                 */
   ELMFB_NORMAL_CG = 3,  /* CG on the normal equations G a = M^T h with G the Gram blocks of
                            elmfb_gram(h, prec, 1) (FP64 or FP32 entries; FP64 vectors and
                            scalars); precond = 1: block-Jacobi PCG, z = R^{-1} R^{-T} r        */
@@ -161,9 +163,10 @@ typedef struct {
 } elmfb_solve_info;
 
 /* Validate the descriptor, plan the decomposition (subdomain boxes on the grid, offsets),
- * check the device footprint against free memory (ELMFB_E_NOMEM before any allocation),
- * allocate the handle's device memory and upload W, b and the tables.  Needs a gfx950
- * device (ELMFB_E_DEVICE otherwise).  Sec. 3, Sec. 4.1. */
+ * check the device footprint against free memory and against the environment variable
+ * ELMFB_MEM_CAP (bytes, if set and > 0; ELMFB_E_NOMEM before any allocation), allocate the
+ * handle's device memory and upload W, b and the tables.  Needs a gfx950 device
+ * (ELMFB_E_DEVICE otherwise).  Sec. 3, Sec. 4.1. */
 elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out);
 
 /* Sizes of the planned system. */
@@ -241,7 +244,8 @@ elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host
  * times, then replaced by the identity; *n_fallback_host (may be NULL) receives that count.
  * The preconditioned matrix M R^{-1} is also formed once (FP64 matrix cores): its store_prec
  * rounding (4 or 2 nnz bytes) for the inner solves of ELMFB_MIXED_IR and the FP64 matrix (8 nnz
- * bytes) for FP64 solves, each when it fits in free device memory with an 8 GB margin;
+ * bytes) for FP64 solves, each when it fits in free device memory with an 8 GB margin and,
+ * under the ELMFB_MEM_CAP of the definition, within the cap with the footprint;
  * preconditioned steps on a folded copy need no per-step R^{-1} products, the others apply R^{-1}
  * in every step.  M and its copy are unchanged.
  * A later elmfb_assemble discards the factors.  shift must be > 0.  Blocks until done. */

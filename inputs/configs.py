@@ -92,6 +92,17 @@ def small2d(seed=4) -> ProblemSpec:
     )
 
 
+def wide2d(K: int, seed: int = 6) -> ProblemSpec:
+    """A small 2D problem with many features per subdomain (K up to 256): 3 levels, non-square
+    grid, so every block is wider than it is tall in points at the finest level."""
+    return ProblemSpec(
+        name=f"wide2d_K{K}", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=6.0,
+        lo=(0.0, 0.0), hi=(1.0, 1.2), n_points=(45, 52), levels=((1, 1), (2, 2), (3, 2)),
+        delta=2.9, K=K, w_range=(-2.0, 2.0), b_range=(-1.0, 1.0), seed=seed + K,
+        meta={"family": "sines", "freqs": (1.0, 2.0), "amps": (1.0, 0.5), "n_test": (53, 59)},
+    )
+
+
 def medium2d(seed=5) -> ProblemSpec:
     """A multilevel case big enough to span many workgroups, small enough for the oracle."""
     return ProblemSpec(

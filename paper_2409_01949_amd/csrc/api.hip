@@ -340,6 +340,7 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   h->bytes_device = footprint(h);
   if (const char* cap = std::getenv("ELMFB_MEM_CAP")) {
     const long long c = std::atoll(cap);
+    if (c > 0) h->mem_cap = c;
     if (c > 0 && h->bytes_device > c) {
       const std::string m = "device footprint " + std::to_string(h->bytes_device) +
                             " B exceeds ELMFB_MEM_CAP";

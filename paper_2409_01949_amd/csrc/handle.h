@@ -24,6 +24,7 @@ struct elmfb_problem_s {
   int64_t nnz = 0, n_block_points = 0, n_tab = 0;
   int64_t n_store = 0;          // stored elements per matrix copy, row padding included
   int64_t bytes_device = 0;
+  int64_t mem_cap = 0;          // ELMFB_MEM_CAP at definition (0: no cap)
 
   // device memory
   std::vector<void*> allocs;

@@ -522,14 +522,20 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
                                   h->d_flag, s));
   // fold the preconditioner into the matrix: the store_prec rounding of M R^{-1} (inner solves of
   // the refinement) and M R^{-1} in FP64 (FP64 Krylov solves), each when it fits in free device
-  // memory with an 8 GB margin; otherwise those solves apply R^{-1} in every step
+  // memory with an 8 GB margin and, under ELMFB_MEM_CAP, within the cap together with the
+  // footprint; otherwise those solves apply R^{-1} in every step
   h->folded64 = h->folded_lo = false;
   {
     const int64_t es_lo = h->lo_prec == ELMFB_FP64 ? 0 : elem_size(h->lo_prec);
     const int64_t margin = (int64_t)8 << 30;
+    int64_t folded_bytes = (h->d_Ahat_lo ? h->n_store * es_lo : 0) + (h->d_Ahat ? h->n_store * 8 : 0);
     auto fits = [&](int64_t bytes) {
       size_t free_b = 0, total_b = 0;
-      return hipMemGetInfo(&free_b, &total_b) == hipSuccess && (int64_t)free_b > bytes + margin;
+      if (h->mem_cap > 0 && h->bytes_device + folded_bytes + bytes > h->mem_cap) return false;
+      const bool ok =
+          hipMemGetInfo(&free_b, &total_b) == hipSuccess && (int64_t)free_b > bytes + margin;
+      if (ok) folded_bytes += bytes;
+      return ok;
     };
     if (es_lo && !h->d_Ahat_lo && fits(h->n_store * es_lo)) {
       HIP_OR_FAIL(h, dalloc_bytes(h, &h->d_Ahat_lo, h->n_store * es_lo));
@@ -739,6 +745,13 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       total_iters += st.itn;
       if (st.target_hit) {
         istop = 8;
+        ++outer;
+        break;
+      }
+      if (st.done && st.itn == 0 && st.istop == 0) {
+        // the inner solve stopped before its first step: the FP64 residual is zero or
+        // orthogonal to the range (M^T r = 0), so c already solves the least-squares problem
+        istop = 0;
         ++outer;
         break;
       }
