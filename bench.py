@@ -319,16 +319,20 @@ def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
     (profiles/<kernel>_<workload>_traffic.json: FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
     the same counters on a plain copy of known size), or None when there is none or the kernel's
-    source changed since the counters were taken (its SHA-256 is recorded there)."""
+    sources changed since the counters were taken (the SHA-256 of the listed source files, read
+    in order and concatenated, is recorded there)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
-        with open(os.path.join(ROOT, d["source"]), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != d["source_sha256"]:
-                return None
+        h = hashlib.sha256()
+        for src in d.get("sources", [d.get("source")]):
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != d["source_sha256"]:
+            return None
         return float(d["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
