@@ -94,3 +94,11 @@ def test_no_device_gives_device_error():
     d, keep = _spec_desc()
     h = ctypes.c_void_p()
     assert lib.elmfb_define_problem(ctypes.byref(d), ctypes.byref(h)) == elmfb.E_DEVICE
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises; there is no fallback path."""
+    from paper_2409_01949_amd import elmfb
+    monkeypatch.setattr(elmfb, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        elmfb.load_library(str(tmp_path / "libelmfb.so"))
