@@ -479,10 +479,19 @@ def main():
         for gp in ["fp64"] + ([args.store] if args.store in ("fp32", "bf16", "fp16") else []):
             ms_g, fl = P.time_gram(gp, "all", reps=3)
             tf = fl / (ms_g * 1e-3) / 1e12
+            # a pair's 2 K^2 S flops read both blocks' S shared rows (2 K S entries): K / es flop
+            # per input byte, so the pass is bound by the matrix cores (FP64) or by reading its
+            # inputs (16-bit entries) when no row is shared between pairs in cache
+            es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[gp]
+            in_bytes = fl * es / spec.K
+            bw_tf = fl / (in_bytes / (HBM_PEAK_GBS * 1e9)) / 1e12
+            ceiling = min(MFMA_PEAK_TFLOPS[gp], bw_tf)
             gram_mfma.append({"kernel": f"k_gram<{gp.upper()}> (+ chunk reduction), "
                                         f"{P.sizes['n_pairs']} pairs", "ms": ms_g, "flops": fl,
                               "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[gp],
-                              "frac": tf / MFMA_PEAK_TFLOPS[gp]})
+                              "frac": tf / MFMA_PEAK_TFLOPS[gp], "input_bytes": in_bytes,
+                              "bound": "mfma" if MFMA_PEAK_TFLOPS[gp] <= bw_tf else "hbm",
+                              "ceiling_tflops": ceiling, "frac_of_ceiling": tf / ceiling})
             note(f"gram {gp}: {ms_g:.2f} ms, {tf:.1f} TFLOP/s")
 
     compare = {}

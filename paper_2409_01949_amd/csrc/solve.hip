@@ -415,6 +415,21 @@ elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stre
   h->gram_prec = prec;
   h->gram_which = which;
   h->gram_gen += 1;
+  // CG loops captured on the previous Gram blocks are keyed to the old generation and never
+  // replayed again: release them once the stream has drained
+  bool synced = false;
+  for (auto it = h->graphs.begin(); it != h->graphs.end();) {
+    if (it->first[0] == ELMFB_NORMAL_CG) {
+      if (!synced) {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        synced = true;
+      }
+      hipGraphExecDestroy(it->second);
+      it = h->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
   h->gram_npairs = (int64_t)pairs.size();
   h->gram_pairs_host = pairs;
   return ELMFB_OK;
