@@ -315,6 +315,16 @@ def run_warm(args):
     print(json.dumps(out), flush=True)
 
 
+def krylov_sigma(P):
+    """Extreme singular values of the bidiagonal the last solve's LSQR built (a lower bound on
+    the condition number of the operator it ran on), or None."""
+    try:
+        smax, smin, k = P.condition_estimate()
+    except Exception:
+        return None
+    return {"sigma_max": smax, "sigma_min": smin, "kappa_lower_bound": smax / smin, "steps": k}
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
     (profiles/<kernel>_<workload>_traffic.json: FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
@@ -426,6 +436,8 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     info = infos[-1]
+    # the operator of the timed solve's last LSQR run (for the refinement: its last inner solve)
+    main_sigma = krylov_sigma(P)
     u = u_test.cpu().numpy()
     e_l1 = float(np.mean(np.abs(u - ut_np)) / np.std(ut_np))
     rel_test = float(np.linalg.norm(u - ut_np) / np.linalg.norm(ut_np))
@@ -505,7 +517,8 @@ def main():
             compare[label] = {"time_to_solution_s": time.perf_counter() - t1,
                               "reached_target": bool(ci["istop"] == 8), "iters": ci["iters"],
                               "iter_budget": args.compare_iters,
-                              "rel_l2_check_at_stop": ci["rel_l2"]}
+                              "rel_l2_check_at_stop": ci["rel_l2"],
+                              "krylov_sigma": krylov_sigma(P)}
             note(f"{label}: {compare[label]['time_to_solution_s']:.2f} s, {ci['iters']} iterations")
         compare["speedup_vs_fp64_block_jacobi"] = \
             compare["fp64_block_jacobi_lsqr"]["time_to_solution_s"] / dt
@@ -544,6 +557,7 @@ def main():
         "e_l1_test": e_l1,
         "roofline": roofline,
         "gram_mfma": gram_mfma,
+        "krylov_sigma": main_sigma,
         "compare": compare,
     }
     if not args.no_cpu_baseline:

@@ -252,6 +252,28 @@ elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host
 elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback_host,
                                 void* stream);
 
+/* Conditioning of the system from the last solve's Krylov process (the paper reports kappa(M)
+ * of its systems from the SVD, Sec. 4): LSQR's Golub-Kahan bidiagonalisation builds the
+ * (k+1) x k lower bidiagonal B_k = U_{k+1}^T A V_k (alpha_1..alpha_k on the diagonal,
+ * beta_2..beta_{k+1} below), whose singular values lie within those of the operator A it ran
+ * on: sigma_max(B_k) grows toward sigma_max(A) and sigma_min(B_k) falls toward sigma_min(A), so
+ * sigma_max / sigma_min is a lower bound on kappa(A) that tightens with k (in floating point
+ * without reorthogonalisation the extreme values still converge; interior ones repeat).
+ * A is M for ELMFB_LSQR, M R^{-1} with precond = 1, and for ELMFB_MIXED_IR the low-precision
+ * operator of the last inner solve.  Every LSQR run records its first kHistCap = 32768 steps.
+ * Writes sigma_max and sigma_min of B_k and k (may be NULL); ELMFB_E_STATE if the last solve
+ * ran no LSQR step.  Blocks until done. */
+elmfb_status elmfb_condition_estimate(elmfb_problem h, double* sigma_max_host,
+                                      double* sigma_min_host, int32_t* k_host);
+
+/* The same for a bidiagonal given on the host (no device work): ab_host[2i] = alpha_{i+1},
+ * ab_host[2i + 1] = beta_{i+1} for i = 0..k (beta_1 is not used).  Extreme singular values by
+ * bisection on the (2k+1) x (2k+1) Golub-Kahan matrix [0 B; B^T 0] in tridiagonal form, whose
+ * eigenvalues are 0 and +-sigma_i: relative accuracy also for tiny sigma_min (Demmel and Kahan
+ * 1990), down to 1e-300 sigma_max.  ELMFB_E_NUMERIC for an all-zero or non-finite input. */
+elmfb_status elmfb_bidiag_sigma(const double* ab_host, int32_t k, double* sigma_max_host,
+                                double* sigma_min_host);
+
 /* u_dev [n_pts] = C(x) (1/L) sum_l sum_j omega_j(x) sum_k coef_q phi_q(x) at arbitrary points
  * pts_dev [n_pts][dim] (Sec. 3 eq. multilevel_solution with the hard-constraint factor). */
 elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,

@@ -59,6 +59,9 @@ class LsqrResult:
     xnorm: float
     snapshots: Dict[int, np.ndarray] = field(default_factory=dict)
     history: List[tuple] = field(default_factory=list)
+    # (alpha_{i+1}, beta_{i+1}) of the bidiagonalisation: entry 0 from the start, entry i after
+    # step i
+    bidiag: List[tuple] = field(default_factory=list)
 
 
 def lsqr(matvec: Callable, rmatvec: Callable, h: np.ndarray, n: int, atol=1e-8, btol=1e-8,
@@ -95,8 +98,10 @@ def lsqr(matvec: Callable, rmatvec: Callable, h: np.ndarray, n: int, atol=1e-8, 
     phibar, rhobar = beta, alpha
     anorm = 0.0
     rnorm, arnorm = beta, alpha * beta
+    bidiag = [(alpha, beta)]
     if arnorm == 0.0:
-        return LsqrResult(x, 0, 0, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist)
+        return LsqrResult(x, 0, 0, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist,
+                          bidiag)
     if bnorm == 0.0:
         bnorm = beta
     istop, itn = 0, 0
@@ -111,6 +116,7 @@ def lsqr(matvec: Callable, rmatvec: Callable, h: np.ndarray, n: int, atol=1e-8, 
             alpha = np.linalg.norm(v)
             if alpha > 0:
                 v = v / alpha
+        bidiag.append((alpha, beta))
         rho = np.sqrt(rhobar * rhobar + beta * beta)
         c = rhobar / rho
         s = beta / rho
@@ -146,7 +152,20 @@ def lsqr(matvec: Callable, rmatvec: Callable, h: np.ndarray, n: int, atol=1e-8, 
             break
     else:
         istop = 7
-    return LsqrResult(x, istop, itn, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist)
+    return LsqrResult(x, istop, itn, rnorm, arnorm, anorm, float(np.linalg.norm(x)), snaps, hist,
+                      bidiag)
+
+
+def bidiag_singular_values(bidiag, k):
+    """Singular values (descending) of the (k+1) x k lower bidiagonal B_k of the Golub-Kahan
+    process: alpha_1 .. alpha_k on the diagonal, beta_2 .. beta_{k+1} below it.  B_k = U^T M V
+    with orthonormal U (k+1 columns) and V (k columns), so its singular values lie between the
+    extreme singular values of M, and equal them once the process has spanned M's row space."""
+    B = np.zeros((k + 1, k))
+    for i in range(k):
+        B[i, i] = bidiag[i][0]
+        B[i + 1, i] = bidiag[i + 1][1]
+    return np.linalg.svd(B, compute_uv=False)
 
 
 # ---------------------------------------------------------------- CGLS

@@ -299,6 +299,8 @@ int64_t footprint(elmfb_problem h) {
   add((int64_t)(h->chunk_start.size() + h->cov.size()) * 4);
   add((int64_t)h->segs.size() * sizeof(AxisSeg));
   add(sizeof(SolveState) + 64);
+  add(64);                                                // flag
+  add((int64_t)kHistCap * 2 * 8);                         // bidiagonal of the last LSQR run
   return b;
 }
 
@@ -410,6 +412,7 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_state, sizeof(SolveState));
   ALLOC(h->d_scalar, 64);
   ALLOC(h->d_flag, 64);
+  ALLOC(h->d_hist, (int64_t)kHistCap * 2 * 8);
 #undef ALLOC
 
   // W padded to two columns

@@ -12,6 +12,7 @@ constexpr int kMaxLevels = ELMFB_MAX_LEVELS;
 constexpr int kTile = 256;          // points per assembly / A.v tile (one per thread)
 constexpr int kRowAlign = 8;        // stored rows start on 8-element boundaries (16 B in FP16)
 constexpr int kChunkPts = 2048;     // points per A^T u chunk (8 per thread of 256)
+constexpr int kHistCap = 32768;     // bidiagonalisation steps an LSQR run records
 constexpr int kRedBlocks = 1024;    // upper bound on per-workgroup partial sums of a reduction
 
 // One subdomain's block of the matrix: K rows (features) x n points of its box, feature-major.

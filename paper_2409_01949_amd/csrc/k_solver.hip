@@ -72,13 +72,18 @@ __global__ void __launch_bounds__(256) k_lsqr_init(SolveState* st, const double*
 }
 
 // alpha = ||A^T u||, phibar = beta, rhobar = alpha; stop at once if x0 is exact (istop 0).
+// hist (may be NULL) receives (alpha_1, beta_1).
 __global__ void __launch_bounds__(256) k_lsqr_init_alpha(SolveState* st, const double* red,
-                                                         int n) {
+                                                         int n, double* hist) {
   __shared__ double sh[4];
   const double s = reduce_partials(red, n, sh);
   if (threadIdx.x == 0) {
     const double beta = st->beta;
     const double alpha = beta > 0.0 ? sqrt(s) : 0.0;
+    if (hist) {
+      hist[0] = alpha;
+      hist[1] = beta;
+    }
     st->alpha = alpha;
     st->sv = alpha > 0.0 ? 1.0 / alpha : 0.0;
     st->phibar = beta;
@@ -104,13 +109,17 @@ __global__ void k_init_xw(Geo g, const double* __restrict__ x0, double* __restri
 }
 
 // beta = ||A v - alpha u||; su = 1/beta; anorm = sqrt(anorm^2 + alpha^2 + beta^2).
-__global__ void __launch_bounds__(256) k_lsqr_beta(SolveState* st, const double* red, int n) {
+// hist (may be NULL) receives beta_{i+1} of step i = itn + 1.
+__global__ void __launch_bounds__(256) k_lsqr_beta(SolveState* st, const double* red, int n,
+                                                   double* hist) {
   __shared__ double sh[4];
   if (st->done) return;
   const double s = reduce_partials(red, n, sh);
   if (threadIdx.x == 0) {
     const double beta = sqrt(s);
     st->beta = beta;
+    const int i = st->itn + 1;
+    if (hist && i < kHistCap) hist[2 * i + 1] = beta;
     if (beta > 0.0) {
       st->su = 1.0 / beta;
       const double a = st->alpha;
@@ -120,7 +129,9 @@ __global__ void __launch_bounds__(256) k_lsqr_beta(SolveState* st, const double*
 }
 
 // alpha = ||A^T u - beta v||, sv = 1/alpha, then the plane rotation of this step.
-__global__ void __launch_bounds__(256) k_lsqr_alpha(SolveState* st, const double* red, int n) {
+// hist (may be NULL) receives alpha_{i+1} of step i = itn + 1.
+__global__ void __launch_bounds__(256) k_lsqr_alpha(SolveState* st, const double* red, int n,
+                                                    double* hist) {
   __shared__ double sh[4];
   if (st->done) return;
   const double s = reduce_partials(red, n, sh);
@@ -132,6 +143,8 @@ __global__ void __launch_bounds__(256) k_lsqr_alpha(SolveState* st, const double
       st->alpha = alpha;
       if (alpha > 0.0) st->sv = 1.0 / alpha;
     }
+    const int i = st->itn + 1;
+    if (hist && i < kHistCap) hist[2 * i] = alpha;
     const double rhobar = st->rhobar;
     const double rho = sqrt(rhobar * rhobar + beta * beta);
     const double c = rhobar / rho, sn = beta / rho;
@@ -327,8 +340,9 @@ hipError_t launch_lsqr_init(SolveState* st, const double* red_b, int nb, const d
   hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(256), 0, s, st, red_b, nb, red_u, nu);
   return hipGetLastError();
 }
-hipError_t launch_lsqr_init_alpha(SolveState* st, const double* red, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_init_alpha, dim3(1), dim3(256), 0, s, st, red, n);
+hipError_t launch_lsqr_init_alpha(SolveState* st, const double* red, int n, double* hist,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_init_alpha, dim3(1), dim3(256), 0, s, st, red, n, hist);
   return hipGetLastError();
 }
 hipError_t launch_init_xw(const Geo& g, const double* x0, double* x, double* w, const double* v,
@@ -336,12 +350,14 @@ hipError_t launch_init_xw(const Geo& g, const double* x0, double* x, double* w, 
   hipLaunchKernelGGL(k_init_xw, grid_for(g.n_phi), dim3(256), 0, s, g, x0, x, w, v, st);
   return hipGetLastError();
 }
-hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(256), 0, s, st, red, n);
+hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, double* hist,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_beta, dim3(1), dim3(256), 0, s, st, red, n, hist);
   return hipGetLastError();
 }
-hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_alpha, dim3(1), dim3(256), 0, s, st, red, n);
+hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, double* hist,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_alpha, dim3(1), dim3(256), 0, s, st, red, n, hist);
   return hipGetLastError();
 }
 hipError_t launch_lsqr_update(const Geo& g, double* x, double* w, const double* v,

@@ -49,11 +49,15 @@ int cols_wg(const Geo& g);
 hipError_t launch_sumsq(const double* x, int64_t n, double* red, int n_wg, hipStream_t s);
 hipError_t launch_lsqr_init(SolveState* st, const double* red_b, int nb, const double* red_u,
                             int nu, hipStream_t s);
-hipError_t launch_lsqr_init_alpha(SolveState* st, const double* red, int n, hipStream_t s);
+// hist (may be NULL): the (alpha, beta) pairs of the bidiagonalisation, kHistCap of them
+hipError_t launch_lsqr_init_alpha(SolveState* st, const double* red, int n, double* hist,
+                                  hipStream_t s);
 hipError_t launch_init_xw(const Geo& g, const double* x0, double* x, double* w, const double* v,
                           const SolveState* st, hipStream_t s);
-hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, hipStream_t s);
-hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, hipStream_t s);
+hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, double* hist,
+                            hipStream_t s);
+hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, double* hist,
+                             hipStream_t s);
 hipError_t launch_lsqr_update(const Geo& g, double* x, double* w, const double* v,
                               const SolveState* st, double* red, int n_wg, hipStream_t s);
 hipError_t launch_lsqr_stop(SolveState* st, const double* red, int n, hipStream_t s);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -55,7 +56,7 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
   if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
                               st, red1, rw, s)))
     return e;
-  if ((e = launch_lsqr_beta(st, red1, rw, s))) return e;
+  if ((e = launch_lsqr_beta(st, red1, rw, h->d_hist, s))) return e;
   if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, nc, c.A, h->d_u,
                              state_field(h, offsetof(SolveState, su)), h->d_part, st, s)))
     return e;
@@ -69,7 +70,7 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
     if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw, s)))
       return e;
   }
-  if ((e = launch_lsqr_alpha(st, red2, na, s))) return e;
+  if ((e = launch_lsqr_alpha(st, red2, na, h->d_hist, s))) return e;
   if ((e = launch_lsqr_update(g, h->d_x, h->d_w, h->d_v, st, red3, cw, s))) return e;
   return launch_lsqr_stop(st, red3, cw, s);
 }
@@ -137,7 +138,7 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
                                  cw, s)))
         return e;
     }
-    if ((e = launch_lsqr_init_alpha(h->d_state, red3, na, s))) return e;
+    if ((e = launch_lsqr_init_alpha(h->d_state, red3, na, h->d_hist, s))) return e;
     return launch_init_xw(g, c.bj ? nullptr : x0, h->d_x, h->d_w, h->d_v, h->d_state, s);
   }
   // CGLS: s = A^T r, p = s, x = x0
@@ -380,9 +381,77 @@ elmfb_status run_gram(elmfb_problem h, int prec, std::vector<GramPair>& pairs, v
   return ELMFB_OK;
 }
 
+// Eigenvalues below x of the symmetric tridiagonal matrix with zero diagonal and off-diagonal
+// e (Sturm count: the negative pivots of the LDL^T factorisation of T - x I).  For the
+// Golub-Kahan matrix of a (k+1) x k bidiagonal B its eigenvalues are 0 and +-sigma_i(B), and
+// bisection on it finds small singular values to high relative accuracy (Demmel and Kahan 1990).
+int64_t tgk_count(const std::vector<double>& e, double x) {
+  const double tiny = std::numeric_limits<double>::min();
+  int64_t c = 0;
+  double d = -x;
+  for (size_t i = 0;; ++i) {
+    if (d < 0.0) ++c;
+    if (i == e.size()) break;
+    if (d == 0.0) d = -tiny;
+    d = -x - e[i] * (e[i] / d);
+  }
+  return c;
+}
+
 }  // namespace
 
 extern "C" {
+
+elmfb_status elmfb_bidiag_sigma(const double* ab_host, int32_t k, double* sigma_max_host,
+                                double* sigma_min_host) {
+  if (!ab_host || k < 1 || !sigma_max_host || !sigma_min_host)
+    return fail(nullptr, ELMFB_E_INVALID, "bad argument");
+  // off-diagonal of the Golub-Kahan matrix of B_k: alpha_1, beta_2, alpha_2, ..., alpha_k, beta_{k+1}
+  std::vector<double> e((size_t)2 * k);
+  double emax = 0.0;
+  for (int i = 0; i < k; ++i) {
+    e[2 * i] = ab_host[2 * i];
+    e[2 * i + 1] = ab_host[2 * (i + 1) + 1];
+    emax = std::max(emax, std::max(std::fabs(e[2 * i]), std::fabs(e[2 * i + 1])));
+  }
+  if (!(emax > 0.0) || !std::isfinite(emax))
+    return fail(nullptr, ELMFB_E_NUMERIC, "degenerate bidiagonal");
+  const int64_t n_all = 2 * (int64_t)k + 1;
+  // largest eigenvalue: all 2k+1 lie below x
+  double lo = 0.0, hi = 2.0 * emax;
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (tgk_count(e, mid) >= n_all) hi = mid;
+    else lo = mid;
+  }
+  const double smax = hi;
+  // smallest singular value: the (k+2)-th smallest eigenvalue (k negative ones and a zero below
+  // it), by bisection on a logarithmic scale down to 1e-300 of sigma_max
+  lo = smax * 1e-300;
+  hi = smax;
+  for (int it = 0; it < 400 && hi > lo * (1.0 + 1e-14); ++it) {
+    const double mid = std::sqrt(lo * hi);
+    if (tgk_count(e, mid) >= (int64_t)k + 2) hi = mid;
+    else lo = mid;
+  }
+  *sigma_max_host = smax;
+  *sigma_min_host = hi;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_condition_estimate(elmfb_problem h, double* sigma_max_host,
+                                      double* sigma_min_host, int32_t* k_host) {
+  if (!h || !sigma_max_host || !sigma_min_host) return fail(h, ELMFB_E_INVALID, "bad argument");
+  const int k = std::min(h->hist_k, kHistCap - 1);
+  if (k < 1) return fail(h, ELMFB_E_STATE, "the last solve recorded no LSQR step");
+  std::vector<double> hist((size_t)2 * (k + 1));
+  HIP_OR_FAIL(h, hipMemcpy(hist.data(), h->d_hist, hist.size() * 8, hipMemcpyDeviceToHost));
+  const elmfb_status es = elmfb_bidiag_sigma(hist.data(), k, sigma_max_host, sigma_min_host);
+  if (es != ELMFB_OK) return fail(h, es, "degenerate bidiagonal");
+  if (k_host) *k_host = k;
+  return ELMFB_OK;
+}
+
 
 elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stream) {
   if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
@@ -788,6 +857,8 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   HIP_OR_FAIL(h, hipMemcpyAsync(coef_dev, result, (size_t)g.n_phi * 8, hipMemcpyDeviceToDevice, s));
   HIP_OR_FAIL(h, hipEventRecord(h->ev_out, s));
   HIP_OR_FAIL(h, hipStreamWaitEvent(caller, h->ev_out, 0));
+  // the bidiagonalisation kept in d_hist belongs to the last LSQR run of this solve
+  h->hist_k = (method == ELMFB_LSQR || method == ELMFB_MIXED_IR) ? st.itn : -1;
   if (info) {
     info->istop = st.istop;
     info->iters = total_iters;

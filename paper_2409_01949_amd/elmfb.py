@@ -137,6 +137,9 @@ def load_library(path: Optional[str] = None):
         "elmfb_precondition": (i32, [P, dbl, ctypes.POINTER(i32), P]),
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
         "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
+        "elmfb_condition_estimate": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                           ctypes.POINTER(i32)]),
+        "elmfb_bidiag_sigma": (i32, [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "elmfb_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(dbl), P]),
         "elmfb_time_gram_mv": (i32, [P, i32, ctypes.POINTER(dbl), P]),
         "elmfb_time_gram": (i32, [P, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]),
@@ -174,6 +177,18 @@ def load_library(path: Optional[str] = None):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def bidiag_sigma(ab):
+    """(sigma_max, sigma_min) of the lower bidiagonal given as (alpha_{i+1}, beta_{i+1}) pairs,
+    i = 0..k, computed by the library on the host."""
+    lib = load_library()
+    a = np.ascontiguousarray(np.asarray(ab, dtype=np.float64).reshape(-1))
+    k = a.size // 2 - 1
+    smax, smin = ctypes.c_double(), ctypes.c_double()
+    _check(lib.elmfb_bidiag_sigma(a.ctypes.data_as(ctypes.c_void_p), k, ctypes.byref(smax),
+                                  ctypes.byref(smin)))
+    return smax.value, smin.value
 
 
 def _ptr(t) -> int:
@@ -340,6 +355,13 @@ class Problem:
         n = pts.shape[0]
         _check(_lib.elmfb_evaluate(self.h, _ptr(coef), _ptr(pts), int(n), _ptr(u),
                                    _stream(stream)), self.h)
+
+    def condition_estimate(self):
+        """(sigma_max, sigma_min, k) of the bidiagonal B_k that the last solve's LSQR built."""
+        smax, smin, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(_lib.elmfb_condition_estimate(self.h, ctypes.byref(smax), ctypes.byref(smin),
+                                             ctypes.byref(k)), self.h)
+        return smax.value, smin.value, k.value
 
     def time_kernels(self, reps=20, prec="fp64", stream=None):
         """Average duration (ms) of one launch of the M v and M^T u streaming kernels."""

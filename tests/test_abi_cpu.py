@@ -102,3 +102,25 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(elmfb, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         elmfb.load_library(str(tmp_path / "libelmfb.so"))
+
+
+def test_bidiagonal_sigma_host_bisection():
+    """elmfb_bidiag_sigma (host arithmetic): a diagonal B has sigma = |alpha_i| exactly, also at
+    1e-14 relative (the bisection keeps relative accuracy); random bidiagonals agree with the
+    oracle's dense SVD of B_k."""
+    from oracle import linalg
+    from paper_2409_01949_amd import elmfb
+    alphas = np.array([3.0, 1e-14, 0.5, 2.0, 1e-3])
+    ab = [(a, 0.0) for a in alphas] + [(0.0, 0.0)]
+    smax, smin = elmfb.bidiag_sigma(ab)
+    assert smax == pytest.approx(3.0, rel=1e-14)
+    assert smin == pytest.approx(1e-14, rel=1e-12)
+    rng = np.random.default_rng(0)
+    for k in (1, 2, 7, 40):
+        ab = [tuple(p) for p in rng.uniform(0.1, 2.0, size=(k + 1, 2))]
+        smax, smin = elmfb.bidiag_sigma(ab)
+        s = linalg.bidiag_singular_values(ab, k)
+        assert smax == pytest.approx(s[0], rel=1e-13)
+        assert smin == pytest.approx(s[-1], rel=1e-10)
+    with pytest.raises(elmfb.ElmfbError):
+        elmfb.bidiag_sigma([(0.0, 0.0), (0.0, 0.0)])

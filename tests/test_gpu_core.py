@@ -141,6 +141,49 @@ def test_krylov_iterates_match(case, method, ks):
         assert dr <= tol_r
 
 
+def test_condition_estimate_from_the_bidiagonal(case):
+    """elmfb_condition_estimate after k LSQR steps: sigma_max and sigma_min of the Golub-Kahan
+    bidiagonal B_k the device built equal those of the oracle's B_k (dense SVD) within
+    max(1e-10, 50x the oracle's own spread under row permutations), and lie within the dense
+    SVD's extreme singular values of M; after CGLS there is no bidiagonal (ELMFB_E_STATE)."""
+    from paper_2409_01949_amd import elmfb
+    spec, P, W, b, f, blocks, h = case
+    torch = torch_mod()
+    n = P.sizes["n_phi"]
+    N = spec.n_rows
+    M = asm.dense_from_blocks(blocks, N, n)
+    sv = np.linalg.svd(M, compute_uv=False)
+    for k in (5, 15):
+        coef = torch.empty(n, dtype=torch.float64, device="cuda")
+        P.solve(coef, method="lsqr", iter_lim=k, atol=0.0, btol=0.0, check_every=5)
+        smax, smin, kk = P.condition_estimate()
+        ref = linalg.lsqr(lambda v: asm.matvec(blocks, v, N), lambda u: asm.rmatvec(blocks, u, n),
+                          h, n, atol=0, btol=0, iter_lim=k)
+        kr = min(k, ref.itn)
+        s = linalg.bidiag_singular_values(ref.bidiag, kr)
+        spread_max = spread_min = 0.0
+        for seed in range(3):
+            perm = np.random.default_rng(seed).permutation(N)
+            Mp, hp = M[perm], h[perm]
+            rp = linalg.lsqr(lambda v: Mp @ v, lambda u: Mp.T @ u, hp, n, atol=0, btol=0,
+                             iter_lim=kr)
+            sp = linalg.bidiag_singular_values(rp.bidiag, kr)
+            spread_max = max(spread_max, abs(sp[0] - s[0]) / s[0])
+            spread_min = max(spread_min, abs(sp[-1] - s[-1]) / s[-1])
+        print(f"{spec.name} k={k}: sigma_max {smax:.6e} vs {s[0]:.6e}, sigma_min {smin:.6e} vs "
+              f"{s[-1]:.6e} (spreads {spread_max:.1e}, {spread_min:.1e}); M: {sv[0]:.6e}, "
+              f"{sv[-1]:.3e}")
+        assert kk == kr
+        assert abs(smax - s[0]) / s[0] <= max(1e-10, 50 * spread_max)
+        assert abs(smin - s[-1]) / s[-1] <= max(1e-10, 50 * spread_min)
+        assert smax <= sv[0] * (1 + 1e-10)
+        assert smin >= sv[-1] * (1 - 1e-10)
+    coef = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.solve(coef, method="cgls", iter_lim=3, atol=0.0, btol=0.0, check_every=3)
+    with pytest.raises(elmfb.ElmfbError):
+        P.condition_estimate()
+
+
 def test_lsqr_converges_to_least_squares_solution():
     """On a well-conditioned system (kappa ~ 2e4) LSQR runs to its stopping test and returns
     the least-squares minimiser: u equal to the QR solution's to 1e-10."""

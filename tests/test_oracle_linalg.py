@@ -340,3 +340,32 @@ def test_refine_lsqr_fp32_inner_fixed_points():
     ref = np.linalg.lstsq(A, h, rcond=None)[0]
     r_opt = np.linalg.norm(h - A @ ref)
     assert np.linalg.norm(A @ (c - ref)) <= 1e-5 * r_opt
+
+
+def test_bidiagonal_singular_values_interlace_and_terminate():
+    """The Golub-Kahan bidiagonal recorded by LSQR: its extreme singular values stay inside M's
+    (sigma_max(B_k) grows toward sigma_max(M), sigma_min(B_k) shrinks toward sigma_min(M)); for M
+    with three distinct singular values the Krylov space has dimension 3, so B_3's singular values
+    are exactly those three; the recorded alpha_1, beta_1 are ||M^T h|| / ||h|| and ||h||."""
+    M, _ = _well_conditioned(m=60, n=20, cond=30.0, seed=3)
+    h = np.random.default_rng(4).standard_normal(60)
+    sv = np.linalg.svd(M, compute_uv=False)
+    res = linalg.lsqr(lambda v: M @ v, lambda u: M.T @ u, h, 20, atol=0, btol=0, iter_lim=20)
+    assert res.bidiag[0][1] == pytest.approx(np.linalg.norm(h), rel=1e-15)
+    assert res.bidiag[0][0] == pytest.approx(np.linalg.norm(M.T @ h) / np.linalg.norm(h), rel=1e-14)
+    prev_max, prev_min = 0.0, np.inf
+    for k in (1, 2, 5, 10, 15, 20):
+        s = linalg.bidiag_singular_values(res.bidiag, k)
+        assert len(s) == k
+        assert s[0] <= sv[0] * (1 + 1e-12) and s[-1] >= sv[-1] * (1 - 1e-12)
+        assert s[0] >= prev_max * (1 - 1e-12) and s[-1] <= prev_min * (1 + 1e-12)
+        prev_max, prev_min = s[0], s[-1]
+    assert prev_max == pytest.approx(sv[0], rel=1e-12)
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.standard_normal((40, 12)))
+    V, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    M3 = (U * np.repeat([2.0, 1.0, 0.5], 4)) @ V.T
+    h3 = rng.standard_normal(40)
+    res3 = linalg.lsqr(lambda v: M3 @ v, lambda u: M3.T @ u, h3, 12, atol=0, btol=0, iter_lim=3)
+    assert np.allclose(linalg.bidiag_singular_values(res3.bidiag, 3), [2.0, 1.0, 0.5],
+                       rtol=1e-12, atol=0)
