@@ -667,6 +667,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
   const int method = opts->method;
+  h->hist_k = -1;   // the recorded bidiagonal is valid only after a solve that completes
   if (method != ELMFB_LSQR && method != ELMFB_CGLS && method != ELMFB_MIXED_IR &&
       method != ELMFB_NORMAL_CG && method != ELMFB_MIXED_IR_CG)
     return fail(h, ELMFB_E_UNSUPPORTED, "unknown solve method");
