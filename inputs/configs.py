@@ -92,6 +92,22 @@ def small2d(seed=4) -> ProblemSpec:
     )
 
 
+def oscillator(omega0: float = 80.0, J: int = 20, K: int = 12, n: int = 260, delta: float = 2.9,
+               levels=None, seed: int = 7) -> ProblemSpec:
+    """m u'' + mu u' + k u = 0 on [0, 1] with m = 1, mu = 4, k = omega0^2, u(0) = 1, u'(0) = 0
+    imposed by two soft-constraint rows with weights sqrt(lambda_u0) = omega0^2 and
+    sqrt(lambda_v0) = omega0; no hard-constraint factor; one level of J subdomains."""
+    k = omega0 ** 2
+    return ProblemSpec(
+        name=f"osc{int(omega0)}", dim=1, op="oscillator", ansatz="none", ansatz_omega=0.0,
+        lo=(0.0,), hi=(1.0,), n_points=(n,), levels=levels or ((J,),), delta=delta, K=K,
+        w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=seed,
+        meta={"family": "oscillator", "omega0": omega0, "osc": (1.0, 4.0, k),
+              # (x, derivative order, weight sqrt(lambda), value): u(0) = 1, u'(0) = 0
+              "bc": ((0.0, 0, k, 1.0), (0.0, 1, omega0, 0.0)), "n_test": (1000,)},
+    )
+
+
 def wide2d(K: int, seed: int = 6) -> ProblemSpec:
     """A small 2D problem with many features per subdomain (K up to 256): 3 levels, non-square
     grid, so every block is wider than it is tall in points at the finest level."""
@@ -125,6 +141,8 @@ def forcing(spec: ProblemSpec, pts=None) -> np.ndarray:
         return fam.ode_modes_forcing(pts, m["freqs"], m["amps"])
     if m["family"] == "sines":
         return fam.sines_forcing(pts, m["freqs"], m["amps"])
+    if m["family"] == "oscillator":   # homogeneous equation
+        return np.zeros(len(pts))
     raise ValueError(m["family"])
 
 
@@ -134,6 +152,8 @@ def exact(spec: ProblemSpec, pts) -> np.ndarray:
         return fam.ode_cos_exact(pts, m["omega"])
     if m["family"] == "ode_modes":
         return fam.ode_modes_exact(pts, m["freqs"], m["amps"])
+    if m["family"] == "oscillator":
+        return fam.oscillator_exact(np.asarray(pts)[:, 0], m["omega0"])
     if m["family"] == "sines":
         return fam.sines_exact(pts, m["freqs"], m["amps"])
     raise ValueError(m["family"])

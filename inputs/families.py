@@ -47,3 +47,16 @@ def sines_forcing(x: np.ndarray, freqs, amps) -> np.ndarray:
         kp = k * np.pi
         f = f + a * 2.0 * kp * kp * np.sin(kp * x[:, 0]) * np.sin(kp * x[:, 1])
     return f
+
+
+def oscillator_exact(t: np.ndarray, omega0: float, mu: float = 4.0, m: float = 1.0,
+                     u0: float = 1.0, v0: float = 0.0) -> np.ndarray:
+    """Under-damped m u'' + mu u' + k u = 0, k = m omega0^2, u(0) = u0, u'(0) = v0:
+    u = exp(-d t) 2A cos(phi + w t), d = mu/(2m), w = sqrt(omega0^2 - d^2),
+    phi = arctan(-(v0/u0 + d)/w), A = u0/(2 cos phi)."""
+    d = mu / (2.0 * m)
+    w = np.sqrt(omega0 ** 2 - d ** 2)
+    phi = np.arctan(-(v0 / u0 + d) / w)
+    A = u0 / (2.0 * np.cos(phi))
+    return np.exp(-d * t) * 2.0 * A * np.cos(phi + w * t)
+

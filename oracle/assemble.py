@@ -47,9 +47,37 @@ def assemble_blocks(prob, W, b, x=None):
 
 
 def rhs(prob, f):
-    """h = f(x_n) / sqrt(N_I)."""
+    """h = f(x_n) / sqrt(N_I), followed by the soft-constraint rows' sqrt(lambda_b) g_b."""
     N = int(np.prod(prob.n_points))
-    return np.asarray(f, dtype=np.float64) / np.sqrt(float(N))
+    h = np.asarray(f, dtype=np.float64) / np.sqrt(float(N))
+    bcs = prob.meta.get("bc", ())
+    if bcs:
+        h = np.concatenate([h, [wgt * val for (_, _, wgt, val) in bcs]])
+    return h
+
+
+def bc_rows(prob, W, b):
+    """The soft-constraint rows B (Sec. 3 "Definition of the system matrices"), dense [N_B, N_Phi]:
+    B_{p,q} = sqrt(lambda_b / N_B^(b)) (1/L) B_b[omega_j phi_q C](x_p) with one point per
+    condition (N_B^(b) = 1), B_b the value (order 0) or the first derivative (order 1) at x_p,
+    and weight sqrt(lambda_b) given per condition.  Zero rows when there are none."""
+    bcs = prob.meta.get("bc", ())
+    subs = geo.subdomains(prob)
+    L = len(prob.levels)
+    B = np.zeros((len(bcs), len(subs) * prob.K))
+    for i, (xb, order, wgt, _) in enumerate(bcs):
+        x = np.array([[float(xb)]])
+        ans = basis.ansatz(x, prob)
+        for l in range(L):
+            level = [sd for sd in subs if sd.level == l]
+            sums = basis.level_sum(x, level)
+            for sd in level:
+                if not geo.in_support(x, sd)[0]:
+                    continue
+                q = slice(sd.q0, sd.q0 + prob.K)
+                val, grad, _ = basis.localized_function(x, prob, sd, W[q], b[q], sums, ans)
+                B[i, q] = wgt / L * (val[0] if order == 0 else grad[0, :, 0])
+    return B
 
 
 def dense_from_blocks(blocks, n_rows, n_cols):
