@@ -36,8 +36,9 @@
 extern "C" {
 #endif
 
-#define ELMFB_ABI_VERSION 1
+#define ELMFB_ABI_VERSION 2
 #define ELMFB_MAX_LEVELS 8
+#define ELMFB_MAX_BC 4
 
 typedef int32_t elmfb_status;
 enum {
@@ -54,7 +55,9 @@ enum {
 enum {
   ELMFB_OP_D1 = 1,          /* du/dx, dim = 1                                                */
   ELMFB_OP_NEG_LAPLACE = 2, /* -Laplace(u), dim = 2                                          */
-  ELMFB_OP_IDENTITY = 3     /* u itself (evaluation / projection matrices), dim 1 or 2       */
+  ELMFB_OP_IDENTITY = 3,    /* u itself (evaluation / projection matrices), dim 1 or 2       */
+  ELMFB_OP_OSCILLATOR = 4   /* m u'' + mu u' + k u, (m, mu, k) = op_coef, dim 1 (Sec. 5.1
+                               eq. harm_oscillator)                                        */
 };
 
 /* Hard-constraint factor C(x) multiplying the network (Sec. 4.3 "Hard boundary constraints"). */
@@ -116,6 +119,18 @@ typedef struct {
                                         matrix is always stored.                            */
   const double* W_host;              /* [n_phi][dim]                                         */
   const double* b_host;              /* [n_phi]                                              */
+  double op_coef[3];                 /* ELMFB_OP_OSCILLATOR: (m, mu, k); ignored otherwise    */
+  /* Soft-constraint rows (Sec. 3 "Definition of the system matrices", matrix B), dim 1 only:
+   * condition b adds the row sqrt(lambda_b) (1/L) D^order_b[omega_j phi_q C](x_b) with right-hand
+   * side sqrt(lambda_b) g_b (one point per condition, N_B^(b) = 1).  They follow the N_I
+   * collocation rows: rows N_I .. N_I + n_bc - 1 of every row-space vector.  Only the FP64
+   * LSQR and CGLS solves accept them (the Gram, block-Jacobi and refinement paths return
+   * ELMFB_E_UNSUPPORTED). */
+  int32_t n_bc;                      /* 0..ELMFB_MAX_BC                                      */
+  int32_t bc_order[ELMFB_MAX_BC];    /* 0: the value, 1: the first derivative at x_b         */
+  double bc_x[ELMFB_MAX_BC];         /* x_b, inside [lo, hi]                                 */
+  double bc_weight[ELMFB_MAX_BC];    /* sqrt(lambda_b) > 0                                   */
+  double bc_value[ELMFB_MAX_BC];     /* g_b                                                  */
 } elmfb_problem_desc;
 
 typedef struct {
@@ -126,6 +141,7 @@ typedef struct {
   int64_t n_block_points;  /* sum_j |I_j|                                                   */
   int64_t bytes_device;    /* device memory held by the handle                              */
   int64_t n_pairs;         /* overlapping subdomain pairs (i <= j), all levels               */
+  int64_t n_bc;            /* soft-constraint rows; row-space vectors hold n_rows + n_bc      */
 } elmfb_sizes;
 
 typedef struct {
@@ -184,14 +200,18 @@ elmfb_status elmfb_points(elmfb_problem h, double* xy_dev, void* stream);
  * call then synchronises the stream). */
 elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream);
 
-/* y_dev [n_rows] = M v_dev [n_phi] (block-sparse, Sec. 3 eq. multilevel_domain_decomp). */
+/* y_dev [n_rows + n_bc] = M v_dev [n_phi] (block-sparse, Sec. 3 eq. multilevel_domain_decomp;
+ * the soft-constraint rows follow the collocation rows). */
 elmfb_status elmfb_matvec(elmfb_problem h, const double* v_dev, double* y_dev, void* stream);
 
-/* x_dev [n_phi] = M^T u_dev [n_rows]. */
+/* x_dev [n_phi] = M^T u_dev [n_rows + n_bc]. */
 elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, void* stream);
 
-/* Copy the assembled right-hand side h [n_rows] (FP64). */
+/* Copy the assembled right-hand side h [n_rows + n_bc] (FP64). */
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
+
+/* Copy the soft-constraint rows B [n_bc][n_phi] (FP64, dense; nothing when n_bc = 0). */
+elmfb_status elmfb_copy_bc(elmfb_problem h, double* dst_dev, void* stream);
 
 /* Copy the stored blocks of the FP64 matrix (prec = ELMFB_FP64) or of its low-precision copy
  * (prec = the descriptor's store_prec) as raw values, blocks in column order, each [K][|I_j|]

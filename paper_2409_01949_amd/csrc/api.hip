@@ -72,8 +72,24 @@ std::string validate_impl(const elmfb_problem_desc* d) {
   if (d->dim != 1 && d->dim != 2) return "dim must be 1 or 2";
   if (d->op == ELMFB_OP_D1 && d->dim != 1) return "ELMFB_OP_D1 needs dim = 1";
   if (d->op == ELMFB_OP_NEG_LAPLACE && d->dim != 2) return "ELMFB_OP_NEG_LAPLACE needs dim = 2";
-  if (d->op != ELMFB_OP_D1 && d->op != ELMFB_OP_NEG_LAPLACE && d->op != ELMFB_OP_IDENTITY)
+  if (d->op == ELMFB_OP_OSCILLATOR && d->dim != 1) return "ELMFB_OP_OSCILLATOR needs dim = 1";
+  if (d->op != ELMFB_OP_D1 && d->op != ELMFB_OP_NEG_LAPLACE && d->op != ELMFB_OP_IDENTITY &&
+      d->op != ELMFB_OP_OSCILLATOR)
     return "unknown operator";
+  if (d->op == ELMFB_OP_OSCILLATOR &&
+      !(std::isfinite(d->op_coef[0]) && std::isfinite(d->op_coef[1]) &&
+        std::isfinite(d->op_coef[2])))
+    return "op_coef must be finite";
+  if (d->n_bc < 0 || d->n_bc > ELMFB_MAX_BC) return "n_bc out of range";
+  if (d->n_bc > 0 && d->dim != 1) return "soft-constraint rows need dim = 1";
+  for (int i = 0; i < d->n_bc; ++i) {
+    if (d->bc_order[i] != 0 && d->bc_order[i] != 1) return "bc_order must be 0 or 1";
+    if (!(std::isfinite(d->bc_x[i]) && d->bc_x[i] >= d->lo[0] && d->bc_x[i] <= d->hi[0]))
+      return "bc_x must lie in [lo, hi]";
+    if (!(std::isfinite(d->bc_weight[i]) && d->bc_weight[i] > 0.0))
+      return "bc_weight must be finite and > 0";
+    if (!std::isfinite(d->bc_value[i])) return "bc_value must be finite";
+  }
   if (d->ansatz != ELMFB_ANSATZ_NONE && d->ansatz != ELMFB_ANSATZ_TANH_ORIGIN &&
       d->ansatz != ELMFB_ANSATZ_TANH_BOX)
     return "unknown ansatz";
@@ -108,6 +124,15 @@ std::string plan_impl(elmfb_problem h) {
   g.ny = d.dim == 2 ? d.n_points[1] : 1;
   g.n_levels = d.n_levels;
   g.K = d.K;
+  g.n_bc = d.n_bc;
+  for (int i = 0; i < 3; ++i) g.op_coef[i] = d.op_coef[i];
+  h->bcs.n = d.n_bc;
+  for (int i = 0; i < d.n_bc; ++i) {
+    h->bcs.order[i] = d.bc_order[i];
+    h->bcs.x[i] = d.bc_x[i];
+    h->bcs.w[i] = d.bc_weight[i];
+    h->bcs.val[i] = d.bc_value[i];
+  }
   g.op = d.op;
   g.ansatz = d.ansatz;
   g.ansatz_omega = d.ansatz_omega;
@@ -290,7 +315,8 @@ int64_t footprint(elmfb_problem h) {
   add(h->n_block_points * 8);                             // tpart
   add((int64_t)h->chunks.size() * g.K * 8);               // part
   add(4 * 2 * kRedBlocks * 8);                            // reductions
-  add(4 * g.n_rows * 8);                                  // h, u, t, r
+  add(4 * (g.n_rows + g.n_bc) * 8);                       // h, u, t, r
+  add((int64_t)g.n_bc * g.n_phi * 8);                     // soft-constraint rows
   add(7 * g.n_phi * 8);                                   // v, w, x, vt, xt, c
   add(g.n_phi * 2 * 8 + g.n_phi * 8);                     // W, b
   add(h->n_tab * 3 * 8);
@@ -390,16 +416,17 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_tpart, h->n_block_points * 8);
   ALLOC(h->d_part, (int64_t)h->chunks.size() * g.K * 8);
   ALLOC(h->d_red, 4 * 2 * kRedBlocks * 8);
-  ALLOC(h->d_h, g.n_rows * 8);
-  ALLOC(h->d_u, g.n_rows * 8);
-  ALLOC(h->d_t, g.n_rows * 8);
+  ALLOC(h->d_h, (g.n_rows + g.n_bc) * 8);
+  ALLOC(h->d_u, (g.n_rows + g.n_bc) * 8);
+  ALLOC(h->d_t, (g.n_rows + g.n_bc) * 8);
+  if (g.n_bc > 0) ALLOC(h->d_bc, (int64_t)g.n_bc * g.n_phi * 8);
   ALLOC(h->d_v, g.n_phi * 8);
   ALLOC(h->d_w, g.n_phi * 8);
   ALLOC(h->d_x, g.n_phi * 8);
   ALLOC(h->d_vt, g.n_phi * 8);
   ALLOC(h->d_xt, g.n_phi * 8);
   ALLOC(h->d_c, g.n_phi * 8);
-  ALLOC(h->d_r, g.n_rows * 8);
+  ALLOC(h->d_r, (g.n_rows + g.n_bc) * 8);
   ALLOC(h->d_W, g.n_phi * 2 * 8);
   ALLOC(h->d_b, g.n_phi * 8);
   ALLOC(h->d_tab, h->n_tab * 3 * 8);
@@ -483,6 +510,7 @@ elmfb_status elmfb_query(elmfb_problem h, elmfb_sizes* out) {
   out->n_block_points = h->n_block_points;
   out->bytes_device = h->bytes_device;
   out->n_pairs = (int64_t)h->pairs_all.size();
+  out->n_bc = h->geo.n_bc;
   return ELMFB_OK;
 }
 
@@ -503,6 +531,9 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
   HIP_OR_FAIL(h, launch_assemble(g, h->lo_prec, h->d_blocks, h->d_tiles,
                                  (int64_t)h->tiles.size(), h->d_tab, h->d_W, h->d_b, h->d_A,
                                  h->d_A_lo, s));
+  if (g.n_bc > 0)
+    HIP_OR_FAIL(h, launch_bc_assemble(g, h->bcs, h->d_blocks, h->d_W, h->d_b, h->d_bc, h->d_h,
+                                      s));
   int32_t bad = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&bad, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
@@ -526,6 +557,9 @@ elmfb_status elmfb_matvec(elmfb_problem h, const double* v_dev, double* y_dev, v
                                   h->d_A, v_dev, nullptr, h->d_tpart, nullptr, s));
   HIP_OR_FAIL(h, launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE, y_dev,
                                     nullptr, nullptr, h->d_red, rows_wg(g), s));
+  if (g.n_bc > 0)
+    HIP_OR_FAIL(h, launch_bc_rows(g, h->d_bc, v_dev, nullptr, ROW_STORE, y_dev, nullptr, nullptr,
+                                  h->d_red + rows_wg(g), s));
   return ELMFB_OK;
 }
 
@@ -538,14 +572,23 @@ elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, 
                                    (int64_t)h->chunks.size(), h->d_A, u_dev, nullptr, h->d_part,
                                    nullptr, s));
   HIP_OR_FAIL(h, launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE, x_dev, nullptr,
-                                   h->d_red, cols_wg(g), s));
+                                   h->d_red, cols_wg(g), h->d_bc, u_dev, nullptr, s));
   return ELMFB_OK;
 }
 
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream) {
   if (!h || !h_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "copy_rhs before assemble");
-  HIP_OR_FAIL(h, hipMemcpyAsync(h_dev, h->d_h, (size_t)h->geo.n_rows * 8,
+  HIP_OR_FAIL(h, hipMemcpyAsync(h_dev, h->d_h, (size_t)(h->geo.n_rows + h->geo.n_bc) * 8,
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_copy_bc(elmfb_problem h, double* dst_dev, void* stream) {
+  if (!h || !dst_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
+  if (!h->assembled) return fail(h, ELMFB_E_STATE, "copy_bc before assemble");
+  if (h->geo.n_bc == 0) return ELMFB_OK;
+  HIP_OR_FAIL(h, hipMemcpyAsync(dst_dev, h->d_bc, (size_t)h->geo.n_bc * h->geo.n_phi * 8,
                                 hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return ELMFB_OK;
 }

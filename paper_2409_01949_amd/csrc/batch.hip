@@ -321,6 +321,9 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
     const std::string v = validate_desc(&descs[i]);
     if (!v.empty()) return bfail(nullptr, ELMFB_E_INVALID, "instance " + std::to_string(i) + ": " + v);
     if (descs[i].K > kBatchMaxK) return bfail(nullptr, ELMFB_E_INVALID, "batched instances need K <= 128");
+    if (descs[i].n_bc != 0 || descs[i].op == ELMFB_OP_OSCILLATOR)
+      return bfail(nullptr, ELMFB_E_UNSUPPORTED,
+                   "batched instances: no soft-constraint rows and no oscillator operator");
     if (descs[i].store_prec != descs[0].store_prec)
       return bfail(nullptr, ELMFB_E_INVALID, "all instances need the same store_prec");
   }

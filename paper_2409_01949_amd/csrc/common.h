@@ -97,6 +97,17 @@ struct Geo {
   double sigma[kMaxLevels][2];    // half-width
   double mid[kMaxLevels][2];      // centre for J == 1
   int32_t cov_off[kMaxLevels][2]; // offset into the covering table (per grid index: jlo, jhi)
+  int32_t n_bc;                   // soft-constraint rows after the n_rows collocation rows
+  int32_t pad_bc_;
+  double op_coef[3];              // (m, mu, k) of the oscillator operator
+};
+
+// Soft-constraint conditions of a 1D problem: row b = w[b] (1/L) D^order[b][psi_q](x[b]),
+// right-hand side w[b] val[b].
+struct BcSpec {
+  int32_t n;
+  int32_t order[4];
+  double x[4], w[4], val[4];
 };
 
 // Device-side scalar state of one Krylov solve (LSQR or CGLS), FP64 throughout.

@@ -56,6 +56,8 @@ struct elmfb_problem_s {
   double* d_scalar = nullptr;   // scratch scalar
   SolveState* d_state = nullptr;
   int32_t* d_flag = nullptr;
+  double* d_bc = nullptr;       // soft-constraint rows, dense [n_bc][n_phi]
+  BcSpec bcs{};                 // their conditions
   double* d_hist = nullptr;     // (alpha_{i+1}, beta_{i+1}) of the last LSQR run, i < kHistCap
   int32_t hist_k = -1;          // steps of that run (-1: the last solve ran no LSQR)
   double* d_eval = nullptr;     // solution-check buffer

@@ -12,6 +12,7 @@
 //   -Lap(P phi) = -(Lap P phi + 2 (1-phi^2)(P_x W1/sx + P_y W2/sy)
 //                   - 2 P phi (1-phi^2)((W1/sx)^2 + (W2/sy)^2)),
 //   d/dx(P phi) = P_x phi + P (1-phi^2) W1/sx,    identity: P phi,
+//   1D m (P phi)'' + mu (P phi)' + k P phi (the damped oscillator, Sec. 5.1),
 // scaled by 1/(sqrt(N) L), in FP64, stored feature-major per block (A_blk[k][p]) so that a
 // wavefront writes 64 consecutive points of one feature.
 #include "device.h"
@@ -129,6 +130,11 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
       v = -(LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k]);
     } else if (OP == ELMFB_OP_D1) {
       v = Px * ph + P * sd * c1s[k];
+    } else if (OP == ELMFB_OP_OSCILLATOR) {
+      // m (P phi)'' + mu (P phi)' + k P phi in 1D (LP = P'', c3 = (W/sigma)^2)
+      const double d2 = LP * ph + 2.0 * sd * Px * c1s[k] - 2.0 * P * ph * sd * c3s[k];
+      const double d1 = Px * ph + P * sd * c1s[k];
+      v = g.op_coef[0] * d2 + g.op_coef[1] * d1 + g.op_coef[2] * P * ph;
     } else {
       v = P * ph;
     }
@@ -178,6 +184,10 @@ static hipError_t launch_assemble_p(const Geo& g, const DevBlock* blocks, const 
     case ELMFB_OP_D1:
       hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_D1>), grid, blk, 0, s, g, blocks, tiles, tab,
                          W, b, A, A_lo);
+      break;
+    case ELMFB_OP_OSCILLATOR:
+      hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_OSCILLATOR>), grid, blk, 0, s, g, blocks,
+                         tiles, tab, W, b, A, A_lo);
       break;
     default:
       hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_IDENTITY>), grid, blk, 0, s, g, blocks, tiles,

@@ -202,11 +202,17 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
     part[(int64_t)ci * K + k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
 }
 
+// bc (may be NULL): the dense soft-constraint rows [n_bc][n_phi]; their part of column q,
+// sum_b bc[b][q] u[n_rows + b] (u scaled by *uscale when given), is added after the chunk
+// partials.
 __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __restrict__ cstart,
                                                     const double* __restrict__ part, int mode,
                                                     double* __restrict__ out,
                                                     const SolveState* __restrict__ st,
-                                                    double* __restrict__ red) {
+                                                    double* __restrict__ red,
+                                                    const double* __restrict__ bc,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ uscale) {
   __shared__ double sh[4];
   if (st && st->done) return;
   const int K = g.K;
@@ -231,6 +237,10 @@ __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __rest
       for (int q = 0; q < 8; ++q) x += t[q];
     }
     for (; c < ce; ++c) x += part[(int64_t)c * K + k];
+    if (bc) {
+      const double usc = uscale ? *uscale : 1.0;
+      for (int r = 0; r < g.n_bc; ++r) x += bc[(int64_t)r * g.n_phi + q] * (u[g.n_rows + r] * usc);
+    }
     if (mode == COL_STORE) {
       out[q] = x;
     } else if (mode == COL_LSQR_V) {
@@ -317,10 +327,17 @@ hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, con
 
 hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
                              int mode, double* out, const SolveState* st, double* red, int n_wg,
+                             const double* bc, const double* u, const double* uscale,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_rmv_finish, dim3(n_wg), dim3(256), 0, s, g, chunk_start, part, mode, out,
-                     st, red);
+                     st, red, g.n_bc > 0 ? bc : nullptr, u, uscale);
   return hipGetLastError();
+}
+hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
+                             int mode, double* out, const SolveState* st, double* red, int n_wg,
+                             hipStream_t s) {
+  return launch_rmv_finish(g, chunk_start, part, mode, out, st, red, n_wg, nullptr, nullptr,
+                           nullptr, s);
 }
 
 }  // namespace elmfb

@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256) k_cgls_update_r(Geo g, double* __restrict
   if (st->done) return;
   const double a = st->cg_a;
   double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n_rows;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n_rows + g.n_bc;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double v = r[i] - a * t[i];
     r[i] = v;

@@ -42,6 +42,21 @@ hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, con
 hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
                              int mode, double* out, const SolveState* st, double* red, int n_wg,
                              hipStream_t s);
+// the same with the soft-constraint rows bc [n_bc][n_phi] (NULL: none) applied to the rows
+// n_rows.. of u, scaled by *uscale when given
+hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,
+                             int mode, double* out, const SolveState* st, double* red, int n_wg,
+                             const double* bc, const double* u, const double* uscale,
+                             hipStream_t s);
+// Soft-constraint rows (k_bc.hip): assemble them (and their right-hand side entries h[n_rows..]),
+// and their part of y = M v: rows n_rows.. of out in the given RowMode, one partial squared norm
+// to *red (not for ROW_STORE)
+hipError_t launch_bc_assemble(const Geo& g, const BcSpec& bc, const DevBlock* blocks,
+                              const double* W, const double* b, double* Bm, double* h,
+                              hipStream_t s);
+hipError_t launch_bc_rows(const Geo& g, const double* Bm, const double* v, const double* vscale,
+                          int mode, double* out, const double* bvec, const SolveState* st,
+                          double* red, hipStream_t s);
 int rows_wg(const Geo& g);
 int cols_wg(const Geo& g);
 

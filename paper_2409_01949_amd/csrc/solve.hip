@@ -29,6 +29,9 @@ struct KCtx {
 
 double* red_slot(elmfb_problem h, int i) { return h->d_red + (int64_t)2 * kRedBlocks * i; }
 
+// norm partials the soft-constraint rows add after the row gather's
+int bc_parts(const Geo& g) { return g.n_bc > 0 ? 1 : 0; }
+
 const double* state_field(elmfb_problem h, size_t off) {
   return reinterpret_cast<const double*>(reinterpret_cast<const char*>(h->d_state) + off);
 }
@@ -56,7 +59,12 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
   if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
                               st, red1, rw, s)))
     return e;
-  if ((e = launch_lsqr_beta(st, red1, rw, h->d_hist, s))) return e;
+  // soft-constraint rows: their u entries and one more norm partial
+  if ((e = launch_bc_rows(g, h->d_bc, c.apply ? h->d_vt : h->d_v,
+                          c.apply ? nullptr : state_field(h, offsetof(SolveState, sv)), ROW_LSQR_U,
+                          h->d_u, nullptr, st, red1 + rw, s)))
+    return e;
+  if ((e = launch_lsqr_beta(st, red1, rw + bc_parts(g), h->d_hist, s))) return e;
   if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, nc, c.A, h->d_u,
                              state_field(h, offsetof(SolveState, su)), h->d_part, st, s)))
     return e;
@@ -67,7 +75,8 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
     if ((e = launch_bj_apply_t(g, h->d_rinv, h->d_xt, COL_LSQR_V, h->d_v, st, red2, s))) return e;
     na = bj_wg(g);
   } else {
-    if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw, s)))
+    if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw,
+                               h->d_bc, h->d_u, state_field(h, offsetof(SolveState, su)), s)))
       return e;
   }
   if ((e = launch_lsqr_alpha(st, red2, na, h->d_hist, s))) return e;
@@ -87,13 +96,17 @@ hipError_t cgls_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
   if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE_SQ, h->d_t, nullptr,
                               st, red1, rw, s)))
     return e;
-  if ((e = launch_cgls_step_a(st, red1, rw, s))) return e;
+  if ((e = launch_bc_rows(g, h->d_bc, h->d_w, nullptr, ROW_STORE_SQ, h->d_t, nullptr, st,
+                          red1 + rw, s)))
+    return e;
+  if ((e = launch_cgls_step_a(st, red1, rw + bc_parts(g), s))) return e;
   if ((e = launch_cgls_update_x(g, h->d_x, h->d_w, st, s))) return e;
   if ((e = launch_cgls_update_r(g, h->d_u, h->d_t, st, red2, rw, s))) return e;
   if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), c.A,
                              h->d_u, nullptr, h->d_part, st, s)))
     return e;
-  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, st, red3, cw, s)))
+  if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, st, red3, cw,
+                             h->d_bc, h->d_u, nullptr, s)))
     return e;
   if ((e = launch_cgls_step_b(st, red2, rw, red3, cw, s))) return e;
   return launch_cgls_update_p(g, h->d_w, h->d_v, st, s);
@@ -106,6 +119,8 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
   const Geo& g = h->geo;
   double *red1 = red_slot(h, 0), *red2 = red_slot(h, 1), *red3 = red_slot(h, 2);
   const int rw = rows_wg(g), cw = cols_wg(g);
+  const int64_t nrt = g.n_rows + g.n_bc;   // collocation rows, then the soft-constraint rows
+  int n2 = rw;
   hipError_t e;
   if (x0) {   // x0 is in the coordinates of M
     if ((e = launch_mv_blocks(g, ELMFB_FP64, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(),
@@ -114,13 +129,17 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
     if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_RESID, h->d_u, c.rhs,
                                 nullptr, red2, rw, s)))
       return e;
+    if ((e = launch_bc_rows(g, h->d_bc, x0, nullptr, ROW_RESID, h->d_u, c.rhs, nullptr,
+                            red2 + rw, s)))
+      return e;
+    n2 = rw + bc_parts(g);
   } else {
-    if ((e = launch_copy(c.rhs, h->d_u, g.n_rows, s))) return e;
-    if ((e = launch_sumsq(h->d_u, g.n_rows, red2, rw, s))) return e;
+    if ((e = launch_copy(c.rhs, h->d_u, nrt, s))) return e;
+    if ((e = launch_sumsq(h->d_u, nrt, red2, rw, s))) return e;
   }
-  if ((e = launch_sumsq(c.rhs, g.n_rows, red1, rw, s))) return e;
+  if ((e = launch_sumsq(c.rhs, nrt, red1, rw, s))) return e;
   if (method == ELMFB_LSQR) {
-    if ((e = launch_lsqr_init(h->d_state, red1, rw, red2, rw, s))) return e;
+    if ((e = launch_lsqr_init(h->d_state, red1, rw, red2, n2, s))) return e;
     if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), c.A,
                                h->d_u, state_field(h, offsetof(SolveState, su)), h->d_part,
                                nullptr, s)))
@@ -135,7 +154,8 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
       na = bj_wg(g);
     } else {
       if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3,
-                                 cw, s)))
+                                 cw, h->d_bc, h->d_u, state_field(h, offsetof(SolveState, su)),
+                                 s)))
         return e;
     }
     if ((e = launch_lsqr_init_alpha(h->d_state, red3, na, h->d_hist, s))) return e;
@@ -146,9 +166,9 @@ hipError_t solve_init(elmfb_problem h, const KCtx& c, int method, const double* 
                              h->d_u, nullptr, h->d_part, nullptr, s)))
     return e;
   if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_v, nullptr, red3, cw,
-                             s)))
+                             h->d_bc, h->d_u, nullptr, s)))
     return e;
-  if ((e = launch_cgls_init(h->d_state, red1, rw, red2, rw, red3, cw, h->anorm_f, s))) return e;
+  if ((e = launch_cgls_init(h->d_state, red1, rw, red2, n2, red3, cw, h->anorm_f, s))) return e;
   if ((e = launch_copy(h->d_v, h->d_w, g.n_phi, s))) return e;
   if (x0) return launch_copy(x0, h->d_x, g.n_phi, s);
   return hipMemsetAsync(h->d_x, 0, (size_t)g.n_phi * 8, s);
@@ -456,6 +476,8 @@ elmfb_status elmfb_condition_estimate(elmfb_problem h, double* sigma_max_host,
 elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stream) {
   if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "gram before assemble");
+  if (h->geo.n_bc > 0)
+    return fail(h, ELMFB_E_UNSUPPORTED, "Gram blocks of a system with soft-constraint rows");
   if (which != 0 && which != 1) return fail(h, ELMFB_E_INVALID, "which must be 0 or 1");
   if (prec != ELMFB_FP64 && !(prec == h->lo_prec && h->d_A_lo))
     return fail(h, ELMFB_E_STATE, "no stored matrix copy in that precision");
@@ -559,6 +581,8 @@ elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host
 elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallback, void* stream) {
   if (!h) return fail(h, ELMFB_E_INVALID, "NULL handle");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "precondition before assemble");
+  if (h->geo.n_bc > 0)
+    return fail(h, ELMFB_E_UNSUPPORTED, "block-Jacobi for a system with soft-constraint rows");
   if (!(shift > 0.0) || !std::isfinite(shift)) return fail(h, ELMFB_E_INVALID, "shift must be > 0");
   const Geo& g = h->geo;
   const int64_t KK = (int64_t)g.K * g.K;
@@ -680,6 +704,9 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   if (opts->n_check < 0 || (opts->n_check > 0 && (!opts->check_pts_dev || !opts->check_ref_dev)))
     return fail(h, ELMFB_E_INVALID, "check points need check_pts_dev and check_ref_dev");
   const bool bj = opts->precond != 0;
+  if (h->geo.n_bc > 0 && (mixed || on_gram || bj))
+    return fail(h, ELMFB_E_UNSUPPORTED,
+                "soft-constraint rows: FP64 LSQR and CGLS without preconditioning only");
   if (bj && method == ELMFB_CGLS) return fail(h, ELMFB_E_UNSUPPORTED, "CGLS has no preconditioner");
   if (bj && !h->bj_ready) return fail(h, ELMFB_E_STATE, "precondition before solving with it");
   if (mixed && (opts->inner_iters < 1 || opts->outer_lim < 0))
@@ -706,10 +733,14 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
   if (method == ELMFB_CGLS && h->anorm_f < 0.0) {
     HIP_OR_FAIL(h, launch_sumsq_entries(ELMFB_FP64, h->d_A, h->n_store, h->d_red, kRedBlocks, s));
     HIP_OR_FAIL(h, launch_reduce_to(h->d_red, kRedBlocks, h->d_scalar, s));
-    double ss = 0.0;
+    double ss = 0.0, sb = 0.0;
     HIP_OR_FAIL(h, hipMemcpyAsync(&ss, h->d_scalar, 8, hipMemcpyDeviceToHost, s));
+    if (g.n_bc > 0) {   // ||[N; B]||_F^2 = ||N||_F^2 + ||B||_F^2
+      HIP_OR_FAIL(h, launch_sumsq(h->d_bc, (int64_t)g.n_bc * g.n_phi, h->d_red, 1, s));
+      HIP_OR_FAIL(h, hipMemcpyAsync(&sb, h->d_red, 8, hipMemcpyDeviceToHost, s));
+    }
     HIP_OR_FAIL(h, hipStreamSynchronize(s));
-    h->anorm_f = std::sqrt(ss);
+    h->anorm_f = std::sqrt(ss + sb);
   }
   if (opts->n_check > h->eval_cap) {
     dfree(h, h->d_eval);

@@ -16,17 +16,19 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libelmfb.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
+MAX_BC = 4
 MAX_LEVELS = 8
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = range(7)
-OP_D1, OP_NEG_LAPLACE, OP_IDENTITY = 1, 2, 3
+OP_D1, OP_NEG_LAPLACE, OP_IDENTITY, OP_OSCILLATOR = 1, 2, 3, 4
 ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 COPY_FOLDED = 0x100
 LSQR, CGLS, MIXED_IR, NORMAL_CG, MIXED_IR_CG = 0, 1, 2, 3, 4
 
-_OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY}
+_OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY,
+        "oscillator": OP_OSCILLATOR}
 _ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
 _METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR, "normal_cg": NORMAL_CG,
@@ -50,13 +52,19 @@ class ProblemDesc(ctypes.Structure):
         ("store_prec", ctypes.c_int32),
         ("W_host", ctypes.POINTER(ctypes.c_double)),
         ("b_host", ctypes.POINTER(ctypes.c_double)),
+        ("op_coef", ctypes.c_double * 3),
+        ("n_bc", ctypes.c_int32),
+        ("bc_order", ctypes.c_int32 * MAX_BC),
+        ("bc_x", ctypes.c_double * MAX_BC),
+        ("bc_weight", ctypes.c_double * MAX_BC),
+        ("bc_value", ctypes.c_double * MAX_BC),
     ]
 
 
 class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_rows", "n_phi", "nnz", "n_blocks", "n_block_points", "bytes_device",
-                 "n_pairs")]
+                 "n_pairs", "n_bc")]
 
 
 class SolveOpts(ctypes.Structure):
@@ -131,6 +139,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_matvec": (i32, [P, P, P, P]),
         "elmfb_rmatvec": (i32, [P, P, P, P]),
         "elmfb_copy_rhs": (i32, [P, P, P]),
+        "elmfb_copy_bc": (i32, [P, P, P]),
         "elmfb_copy_blocks": (i32, [P, i32, P, ctypes.POINTER(i64), P]),
         "elmfb_gram": (i32, [P, i32, i32, P]),
         "elmfb_copy_gram": (i32, [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P]),
@@ -217,9 +226,10 @@ def _check(code, handle=None):
 
 
 def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K, W, b,
-              store_prec="fp64"):
+              store_prec="fp64", op_coef=(0.0, 0.0, 0.0), bc=()):
     """Descriptor from plain values.  W [n_phi, dim] and b [n_phi] are float64 host arrays;
-    the returned tuple keeps them alive for the duration of the define call."""
+    the returned tuple keeps them alive for the duration of the define call.  bc: soft
+    constraints as (x, derivative order, weight sqrt(lambda), value) tuples."""
     d = ProblemDesc()
     d.abi_version = ABI_VERSION
     d.dim = int(dim)
@@ -237,6 +247,12 @@ def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K,
     d.delta = float(delta)
     d.K = int(K)
     d.store_prec = _PREC[store_prec] if isinstance(store_prec, str) else int(store_prec)
+    for i, c in enumerate(op_coef):
+        d.op_coef[i] = float(c)
+    d.n_bc = len(bc)
+    for i, (x, order, wgt, val) in enumerate(bc[:MAX_BC]):
+        d.bc_x[i], d.bc_order[i], d.bc_weight[i], d.bc_value[i] = float(x), int(order), \
+            float(wgt), float(val)
     W = np.ascontiguousarray(W, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
     d.W_host = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -246,8 +262,10 @@ def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K,
 
 def desc_from_spec(spec, W, b, store_prec="fp64"):
     """Descriptor from any object with the problem-specification attributes."""
+    meta = getattr(spec, "meta", {}) or {}
     return make_desc(spec.dim, spec.op, spec.ansatz, spec.ansatz_omega, spec.lo, spec.hi,
-                     spec.n_points, spec.levels, spec.delta, spec.K, W, b, store_prec)
+                     spec.n_points, spec.levels, spec.delta, spec.K, W, b, store_prec,
+                     op_coef=meta.get("osc", (0.0, 0.0, 0.0)), bc=tuple(meta.get("bc", ())))
 
 
 def define_problem(desc_and_keep) -> "Problem":
@@ -292,6 +310,10 @@ class Problem:
 
     def copy_rhs(self, hvec, stream=None):
         _check(_lib.elmfb_copy_rhs(self.h, _ptr(hvec), _stream(stream)), self.h)
+
+    def copy_bc(self, dst, stream=None):
+        """The soft-constraint rows [n_bc, n_phi] into dst (FP64)."""
+        _check(_lib.elmfb_copy_bc(self.h, _ptr(dst), _stream(stream)), self.h)
 
     def copy_blocks(self, dst=None, prec="fp64", folded=False, stream=None):
         """Returns the block table [n_blocks, 8] (int64); copies raw blocks into dst if given
