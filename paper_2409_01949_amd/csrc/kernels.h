@@ -60,6 +60,16 @@ hipError_t launch_bc_rows(const Geo& g, const double* Bm, const double* v, const
 int rows_wg(const Geo& g);
 int cols_wg(const Geo& g);
 
+// ---- LSQR in one workgroup for systems that fit in LDS (k_persistent.hip): up to n_iter
+// steps on the FP64 matrix, the state carried in st and the vectors u, v, w, x
+constexpr size_t kPersistMaxLds = 65536;
+constexpr int64_t kPersistMaxEntries = 1 << 17;   // stored entries the one CU re-reads per step
+size_t persistent_lds_bytes(const Geo& g, int64_t n_pts);
+hipError_t launch_lsqr_persistent(const Geo& g, const DevBlock* blocks, const int32_t* cov,
+                                  const double* A, const double* bc, double* u, double* v,
+                                  double* w, double* x, SolveState* st, double* hist, int n_iter,
+                                  int64_t n_pts, hipStream_t s);
+
 // ---- Krylov recurrences (k_solver.hip)
 hipError_t launch_sumsq(const double* x, int64_t n, double* red, int n_wg, hipStream_t s);
 hipError_t launch_lsqr_init(SolveState* st, const double* red_b, int nb, const double* red_u,

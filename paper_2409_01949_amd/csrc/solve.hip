@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -34,6 +35,15 @@ int bc_parts(const Geo& g) { return g.n_bc > 0 ? 1 : 0; }
 
 const double* state_field(elmfb_problem h, size_t off) {
   return reinterpret_cast<const double*>(reinterpret_cast<const char*>(h->d_state) + off);
+}
+
+// The one-workgroup LSQR takes the system when its vectors fit in LDS and its matrix is small
+// enough to re-read from one CU's caches every step; ELMFB_PERSISTENT=0 turns it off.
+bool one_workgroup_fits(elmfb_problem h) {
+  if (const char* e = std::getenv("ELMFB_PERSISTENT"))
+    if (e[0] == '0' && e[1] == 0) return false;
+  return persistent_lds_bytes(h->geo, h->n_block_points) <= kPersistMaxLds &&
+         h->n_store <= kPersistMaxEntries;
 }
 
 hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
@@ -773,10 +783,17 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       HIP_OR_FAIL(h, gcg_start(h, c, opts->x0_dev, s));
     else
       HIP_OR_FAIL(h, solve_init(h, c, method, opts->x0_dev, s));
+    // FP64 LSQR on a system that fits in one CU's LDS runs whole steps in one workgroup
+    const bool one_wg = method == ELMFB_LSQR && !on_gram && !bj && one_workgroup_fits(h);
     HIP_OR_FAIL(h, hipMemcpyAsync(&st, h->d_state, sizeof(st), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(h, hipStreamSynchronize(s));
     while (!st.done) {
-      HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
+      if (one_wg)
+        HIP_OR_FAIL(h, launch_lsqr_persistent(g, h->d_blocks, h->d_cov, h->d_A, h->d_bc, h->d_u,
+                                              h->d_v, h->d_w, h->d_x, h->d_state, h->d_hist,
+                                              opts->check_every, h->n_block_points, s));
+      else
+        HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
       if (opts->n_check > 0) {
         const double* xcur = h->d_x;
         if (recover) {
