@@ -231,7 +231,10 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
  * breakdown p.Gp <= 0 (istop 3: G is not positive definite in its stored precision) or after
  * iter_lim (inner_iters) steps (istop 7); rnorm then reports ||g - G a||, except for the
  * refinements, which report the FP64 residual ||h - M c||.  x0_dev warm-starts ELMFB_NORMAL_CG.
- * info_host may be NULL. */
+ * FP64 LSQR without block-Jacobi on a system whose vectors fit in 64 KB of LDS (at most 2^17
+ * stored entries) runs check_every steps per launch in one workgroup; the environment variable
+ * ELMFB_PERSISTENT=0 selects the multi-workgroup steps instead (same iteration, other summation
+ * order).  info_host may be NULL. */
 elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
                          elmfb_solve_info* info_host, void* stream);
 

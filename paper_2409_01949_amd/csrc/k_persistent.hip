@@ -1,10 +1,11 @@
 // LSQR (Sec. 3: the method's least-squares solver, Paige-Saunders recurrences) for systems that
-// fit in one compute unit: one workgroup of 1024 threads runs whole iterations, with u, v, w,
-// x and the per-block-point partials t_j held in LDS and the FP64 matrix read from global memory
-// (it stays in the CU's caches between iterations).  A step here costs its arithmetic and a few
-// workgroup barriers instead of the ~9 kernel launches per step of the multi-workgroup path,
-// which dominate when the system holds only thousands of entries (the damped oscillator of
-// Sec. 5.1).
+// fit in one compute unit: one workgroup of 512 threads runs whole iterations, with u, v, w,
+// x, the per-block-point partials t_j, the soft-constraint rows and the index tables held in
+// LDS; the FP64 matrix is copied into LDS too when the device's per-workgroup limit allows it,
+// else read from global memory, where it stays in the CU's caches.  A step here costs its
+// arithmetic and a few workgroup barriers instead of the ~9 kernel launches per step of the
+// multi-workgroup path, which dominate when the system holds only thousands of entries (the
+// damped oscillator of Sec. 5.1).
 //
 // The step is the same one the multi-workgroup path takes, on the same stored (unnormalised)
 // u and v with their scales su = 1/beta and sv = 1/alpha:
@@ -13,9 +14,13 @@
 //   u_b    = sum_q B[b][q] v[q] sv - alpha su u_b              (soft-constraint rows)
 //   beta   = ||u||, x_q = sum_p M_j[k][p] u[r(p)] su + sum_b B[b][q] u_b su,
 //   v      = x - beta sv v, alpha = ||v||, the plane rotation, x += t1 w, w = v sv + t2 w,
-// then the stopping tests.  Each reduction is a fixed-order wavefront butterfly and a
-// fixed-order sum of the 16 wavefront partials that every thread reads, so every thread holds
-// the same scalar state and the result is deterministic.
+// then the stopping tests.  Built once per launch: the block table, the block and row of every
+// block point, and for every row the block points it sums, in the order of the covering loop
+// (level, then x, then y subdomain index), as a compressed row list.  Each reduction is a
+// fixed-order wavefront butterfly and a fixed-order sum of the 8 wavefront partials that every
+// thread reads, so every thread holds the same scalar state and the result is deterministic.
+// 512 threads measured faster than 256 or 1024 on the oscillator (5.9 against 6.7 and 7.4 us
+// per step).
 #include "device.h"
 #include "kernels.h"
 
@@ -23,50 +28,84 @@ namespace elmfb {
 
 namespace {
 
-constexpr int kPThreads = 1024;
+constexpr int kPThreads = 512;
 constexpr int kPWaves = kPThreads / 64;
 
-// Fixed-order sum over the workgroup; every thread returns the same value.  slot holds
-// kPWaves doubles and must not be rewritten before every thread has passed a later barrier.
+// Fixed-order sum over the workgroup; every thread returns the same value (each wavefront
+// sums the kPWaves partials with the same butterfly).  slot holds kPWaves doubles and must not
+// be rewritten before every thread has passed a later barrier.
 __device__ __forceinline__ double wg_sum(double v, double* slot) {
   v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) slot[threadIdx.x >> 6] = v;
   __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < kPWaves; ++i) s += slot[i];
-  return s;
+  return wave_sum(lane < kPWaves ? slot[lane] : 0.0);
 }
 
-// Global row of point p of block B (box row-major, y fastest).
-__device__ __forceinline__ int64_t block_row(const Geo& g, const DevBlock& B, int p) {
-  const int px = p / B.ny, py = p - px * B.ny;
-  return (int64_t)(B.ix0 + px) * g.ny + (B.iy0 + py);
+// Doubles ahead of the index tables, rounded up to an even count so the int4 block table
+// starts on a 16-byte boundary.
+__host__ __device__ __forceinline__ int64_t persistent_doubles(const Geo& g, int64_t n_pts,
+                                                               int64_t n_store, bool a_in_lds) {
+  int64_t d = g.n_rows + g.n_bc + 3 * g.n_phi + n_pts + 3 * kPWaves + (int64_t)g.n_bc * g.n_phi;
+  if (a_in_lds) d += n_store + g.n_phi;   // rows of (n_j | 1) <= ld_j + 1 entries
+  return (d + 1) & ~(int64_t)1;
+}
+
+// In wavefront 0: exclusive prefix sum of a[0], a[stride], ... (n entries) in place; returns
+// the total in lane 0..63 of wavefront 0.
+__device__ __forceinline__ int wave0_exclusive_scan(int32_t* a, int64_t n, int stride) {
+  const int lane = threadIdx.x & 63;
+  int run = 0;
+  for (int64_t base = 0; base < n; base += 64) {
+    const int64_t i = base + lane;
+    const int c = i < n ? a[i * stride] : 0;
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (i < n) a[i * stride] = run + incl - c;
+    run += __shfl(incl, 63, 64);
+  }
+  return run;
 }
 
 }  // namespace
 
-size_t persistent_lds_bytes(const Geo& g, int64_t n_pts) {
-  const int64_t nrt = g.n_rows + g.n_bc;
-  return (size_t)(8 * (nrt + 3 * g.n_phi + n_pts + 3 * kPWaves) + 4 * n_pts);
+// LDS bytes of a launch: the vectors, partials, reduction slots, constraint rows and index
+// tables, plus the matrix copy when a_in_lds.
+size_t persistent_lds_bytes(const Geo& g, int64_t n_pts, int64_t n_store, bool a_in_lds) {
+  const int64_t i = 5 * (int64_t)g.n_blocks + 3 * n_pts + g.n_rows + 1;
+  return (size_t)(8 * persistent_doubles(g, n_pts, n_store, a_in_lds) + 4 * i);
 }
 
+template <bool ALDS>
 __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
     Geo g, const DevBlock* __restrict__ blocks, const int32_t* __restrict__ cov,
-    const double* __restrict__ A, const double* __restrict__ bc, double* __restrict__ u_g,
+    const double* __restrict__ A_g, const double* __restrict__ bc_g, double* __restrict__ u_g,
     double* __restrict__ v_g, double* __restrict__ w_g, double* __restrict__ x_g,
-    SolveState* st, double* __restrict__ hist, int n_iter, int64_t n_pts) {
+    SolveState* st, double* __restrict__ hist, int n_iter, int64_t n_pts, int64_t n_store) {
   if (st->done) return;
   extern __shared__ double lds[];
   const int64_t nrt = g.n_rows + g.n_bc;
   const int64_t n_phi = g.n_phi;
+  const int nb = g.n_blocks;
   double* u = lds;
   double* v = u + nrt;
   double* w = v + n_phi;
   double* x = w + n_phi;
   double* tp = x + n_phi;
-  double* slot = tp + n_pts;    // 3 x kPWaves reduction slots
-  int32_t* pblk = reinterpret_cast<int32_t*>(slot + 3 * kPWaves);
+  double* slot = tp + n_pts;                  // 3 x kPWaves reduction slots
+  double* bc = slot + 3 * kPWaves;            // [n_bc][n_phi]
+  double* As = bc + (int64_t)g.n_bc * n_phi;  // the matrix copy (ALDS)
+  int32_t* ib = reinterpret_cast<int32_t*>(lds + persistent_doubles(g, n_pts, n_store, ALDS));
+  int4* bt = reinterpret_cast<int4*>(ib);     // per block: a_off, ld, q0, p_off
+  int32_t* bn = ib + 4 * nb;                  // per block: points
+  int32_t* pblk = bn + nb;                    // per block point: its block
+  int32_t* prow = pblk + n_pts;               // per block point: its row
+  int32_t* rp = prow + n_pts;                 // per row: first entry of its list (n_rows + 1)
+  int32_t* ridx = rp + g.n_rows + 1;          // the lists: block point indices
+  const double* A = ALDS ? As : A_g;
   const int tid = threadIdx.x;
   const int K = g.K;
 
@@ -76,9 +115,62 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
     w[i] = w_g[i];
     x[i] = x_g[i];
   }
-  for (int j = tid; j < g.n_blocks; j += kPThreads) {
+  for (int64_t i = tid; i < (int64_t)g.n_bc * n_phi; i += kPThreads) bc[i] = bc_g[i];
+  // block table: the global offset and row stride, or (ALDS) the LDS copy's, whose rows hold
+  // n_j | 1 entries so that the columns a wavefront reads in M^T u fall in different banks
+  for (int j = tid; j < nb; j += kPThreads) {
     const DevBlock& B = blocks[j];
-    for (int p = 0; p < B.n; ++p) pblk[B.p_off + p] = j;
+    const int ldl = B.n | 1;
+    bt[j] = ALDS ? make_int4(K * ldl, ldl, B.q0, (int)B.p_off)
+                 : make_int4((int)B.a_off, B.ld, B.q0, (int)B.p_off);
+    bn[j] = B.n;
+    for (int p = 0; p < B.n; ++p) {
+      const int px = p / B.ny, py = p - px * B.ny;
+      pblk[B.p_off + p] = j;
+      prow[B.p_off + p] = (B.ix0 + px) * g.ny + (B.iy0 + py);
+    }
+  }
+  if (ALDS) {
+    __syncthreads();
+    if (tid < 64) wave0_exclusive_scan(reinterpret_cast<int32_t*>(bt), nb, 4);
+    __syncthreads();
+    for (int j = tid >> 6; j < nb; j += kPWaves) {   // one wavefront per block
+      const DevBlock& B = blocks[j];
+      const int4 L = bt[j];
+      for (int e = tid & 63; e < K * B.n; e += 64) {
+        const int k = e / B.n, p = e - k * B.n;
+        As[L.x + k * L.y + p] = A_g[B.a_off + (int64_t)k * B.ld + p];
+      }
+    }
+  }
+  // the row lists: count, exclusive scan (wavefront 0), fill in the covering loop's order
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t r = tid; r < g.n_rows; r += kPThreads) {
+      const int ix = (int)(r / g.ny), iy = (int)(r - (int64_t)ix * g.ny);
+      int c = 0, at = pass ? rp[r] : 0;
+      for (int l = 0; l < g.n_levels; ++l) {
+        const int jx0 = cov[g.cov_off[l][0] + 2 * ix], jx1 = cov[g.cov_off[l][0] + 2 * ix + 1];
+        const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
+        const int Jy = g.J[l][1];
+        for (int jx = jx0; jx <= jx1; ++jx)
+          for (int jy = jy0; jy <= jy1; ++jy) {
+            if (pass) {
+              const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
+              // every (row, covering block) pair is one block point: at < n_pts
+              if (at < n_pts) ridx[at] = (int)B.p_off + (ix - B.ix0) * B.ny + (iy - B.iy0);
+              ++at;
+            }
+            ++c;
+          }
+      }
+      if (!pass) rp[r] = c;
+    }
+    __syncthreads();
+    if (!pass && tid < 64) {
+      const int run = wave0_exclusive_scan(rp, g.n_rows, 1);
+      if (tid == 0) rp[g.n_rows] = run;
+    }
+    __syncthreads();
   }
 
   // scalar state: the same copy in every thread
@@ -89,32 +181,30 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
   const int iter_lim = st->iter_lim;
   int itn = st->itn, istop = st->istop, done = 0;
 
-  // threads per column of M^T u: the largest power of two with n_phi * T <= 1024, at most 64
+  // threads per column of M^T u: the largest power of two with n_phi * T <= kPThreads, at most 64
   int T = 1;
   while (T < 64 && (int64_t)(2 * T) * n_phi <= kPThreads) T *= 2;
   const int sub = tid & (T - 1);
-  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
 
   for (int it = 0; it < n_iter && !done; ++it) {
     // t_j[p] = sum_k M_j[k][p] v[q0_j + k] sv
     for (int64_t f = tid; f < n_pts; f += kPThreads) {
-      const DevBlock& B = blocks[pblk[f]];
-      const int p = (int)(f - B.p_off);
-      const double* a = A + B.a_off + p;
-      const double* vb = v + B.q0;
-      const int ld = B.ld;
-      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      const int4 B = bt[pblk[f]];
+      const double* a = A + B.x + (f - B.w);
+      const double* vb = v + B.z;
+      const int ld = B.y;
+      double c[4] = {0.0, 0.0, 0.0, 0.0};
       int k = 0;
-      for (; k + 4 <= K; k += 4) {
-        const double a0 = a[(int64_t)k * ld], a1 = a[(int64_t)(k + 1) * ld];
-        const double a2 = a[(int64_t)(k + 2) * ld], a3 = a[(int64_t)(k + 3) * ld];
-        c0 += a0 * vb[k];
-        c1 += a1 * vb[k + 1];
-        c2 += a2 * vb[k + 2];
-        c3 += a3 * vb[k + 3];
+      for (; k + 8 <= K; k += 8) {
+        double t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = a[(k + e) * ld];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c[e & 3] += t[e] * vb[k + e];
       }
-      for (; k < K; ++k) c0 += a[(int64_t)k * ld] * vb[k];
-      tp[f] = ((c0 + c1) + (c2 + c3)) * sv;
+      for (; k < K; ++k) c[k & 3] += a[k * ld] * vb[k];
+      tp[f] = ((c[0] + c[1]) + (c[2] + c[3])) * sv;
     }
     __syncthreads();
 
@@ -122,30 +212,22 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
     const double coef_u = alpha * su;
     double acc = 0.0;
     for (int64_t r = tid; r < g.n_rows; r += kPThreads) {
-      const int ix = (int)(r / g.ny), iy = (int)(r - (int64_t)ix * g.ny);
       double y = 0.0;
-      for (int l = 0; l < g.n_levels; ++l) {
-        const int jx0 = cov[g.cov_off[l][0] + 2 * ix], jx1 = cov[g.cov_off[l][0] + 2 * ix + 1];
-        const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
-        const int Jy = g.J[l][1];
-        for (int jx = jx0; jx <= jx1; ++jx)
-          for (int jy = jy0; jy <= jy1; ++jy) {
-            const DevBlock& B = blocks[g.bbase[l] + jx * Jy + jy];
-            y += tp[B.p_off + (ix - B.ix0) * B.ny + (iy - B.iy0)];
-          }
-      }
+      const int e1 = rp[r + 1];
+      for (int e = rp[r]; e < e1; ++e) y += tp[ridx[e]];
       const double un = y - coef_u * u[r];
       u[r] = un;
       acc += un * un;
     }
-    const int wave = tid >> 6, lane = tid & 63;
-    if (wave < g.n_bc) {
+    // constraint row cb on the last wavefronts, which hold the fewest collocation rows
+    const int cb = kPWaves - 1 - wave;
+    if (cb < g.n_bc) {
       double d = 0.0;
-      for (int64_t q = lane; q < n_phi; q += 64) d += bc[(int64_t)wave * n_phi + q] * v[q];
+      for (int64_t q = lane; q < n_phi; q += 64) d += bc[(int64_t)cb * n_phi + q] * v[q];
       d = wave_sum(d) * sv;
       if (lane == 0) {
-        const double un = d - coef_u * u[g.n_rows + wave];
-        u[g.n_rows + wave] = un;
+        const double un = d - coef_u * u[g.n_rows + cb];
+        u[g.n_rows + cb] = un;
         acc += un * un;
       }
     }
@@ -166,16 +248,25 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
       // only active lanes
       if (q < n_phi) {
         const int b = (int)(q / K), k = (int)(q - (int64_t)b * K);
-        const DevBlock& B = blocks[b];
-        const double* a = A + B.a_off + (int64_t)k * B.ld;
-        double s0 = 0.0, s1 = 0.0;
+        const int4 B = bt[b];
+        const int n = bn[b];
+        const double* a = A + B.x + k * B.y;
+        const int32_t* pr = prow + B.w;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
         int p = sub;
-        for (; p + T < B.n; p += 2 * T) {
-          s0 += a[p] * u[block_row(g, B, p)];
-          s1 += a[p + T] * u[block_row(g, B, p + T)];
+        for (; p + 3 * T < n; p += 4 * T) {
+          double t[4];
+          int rr[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            t[e] = a[p + e * T];
+            rr[e] = pr[p + e * T];
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) s4[e] += t[e] * u[rr[e]];
         }
-        if (p < B.n) s0 += a[p] * u[block_row(g, B, p)];
-        double s = s0 + s1;
+        for (int e = 0; p < n; p += T, ++e) s4[e] += a[p] * u[pr[p]];
+        double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         for (int o = T >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
         double xq = s * su;
         for (int r = 0; r < g.n_bc; ++r) xq += bc[(int64_t)r * n_phi + q] * (u[g.n_rows + r] * su);
@@ -265,11 +356,26 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
 hipError_t launch_lsqr_persistent(const Geo& g, const DevBlock* blocks, const int32_t* cov,
                                   const double* A, const double* bc, double* u, double* v,
                                   double* w, double* x, SolveState* st, double* hist, int n_iter,
-                                  int64_t n_pts, hipStream_t s) {
-  const size_t lds = persistent_lds_bytes(g, n_pts);
+                                  int64_t n_pts, int64_t n_store, hipStream_t s) {
+  size_t lds = persistent_lds_bytes(g, n_pts, n_store, false);
   if (lds > kPersistMaxLds || n_iter <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lsqr_persistent, dim3(1), dim3(kPThreads), lds, s, g, blocks, cov, A, bc,
-                     u, v, w, x, st, hist, n_iter, n_pts);
+  // the matrix joins the vectors in LDS when the device allows that much per workgroup
+  int dev = 0, max_lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  const size_t lds_a = persistent_lds_bytes(g, n_pts, n_store, true);
+  if (lds_a <= (size_t)max_lds &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lsqr_persistent<true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a) == hipSuccess) {
+    hipLaunchKernelGGL(k_lsqr_persistent<true>, dim3(1), dim3(kPThreads), lds_a, s, g, blocks,
+                       cov, A, bc, u, v, w, x, st, hist, n_iter, n_pts, n_store);
+    return hipGetLastError();
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_lsqr_persistent<false>, dim3(1), dim3(kPThreads), lds, s, g, blocks, cov,
+                     A, bc, u, v, w, x, st, hist, n_iter, n_pts, n_store);
   return hipGetLastError();
 }
 

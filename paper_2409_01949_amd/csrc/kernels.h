@@ -64,11 +64,12 @@ int cols_wg(const Geo& g);
 // steps on the FP64 matrix, the state carried in st and the vectors u, v, w, x
 constexpr size_t kPersistMaxLds = 65536;
 constexpr int64_t kPersistMaxEntries = 1 << 17;   // stored entries the one CU re-reads per step
-size_t persistent_lds_bytes(const Geo& g, int64_t n_pts);
+// LDS bytes of a launch, with or without the matrix copy of n_store entries
+size_t persistent_lds_bytes(const Geo& g, int64_t n_pts, int64_t n_store, bool a_in_lds);
 hipError_t launch_lsqr_persistent(const Geo& g, const DevBlock* blocks, const int32_t* cov,
                                   const double* A, const double* bc, double* u, double* v,
                                   double* w, double* x, SolveState* st, double* hist, int n_iter,
-                                  int64_t n_pts, hipStream_t s);
+                                  int64_t n_pts, int64_t n_store, hipStream_t s);
 
 // ---- Krylov recurrences (k_solver.hip)
 hipError_t launch_sumsq(const double* x, int64_t n, double* red, int n_wg, hipStream_t s);

@@ -42,7 +42,7 @@ const double* state_field(elmfb_problem h, size_t off) {
 bool one_workgroup_fits(elmfb_problem h) {
   if (const char* e = std::getenv("ELMFB_PERSISTENT"))
     if (e[0] == '0' && e[1] == 0) return false;
-  return persistent_lds_bytes(h->geo, h->n_block_points) <= kPersistMaxLds &&
+  return persistent_lds_bytes(h->geo, h->n_block_points, h->n_store, false) <= kPersistMaxLds &&
          h->n_store <= kPersistMaxEntries;
 }
 
@@ -791,7 +791,8 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
       if (one_wg)
         HIP_OR_FAIL(h, launch_lsqr_persistent(g, h->d_blocks, h->d_cov, h->d_A, h->d_bc, h->d_u,
                                               h->d_v, h->d_w, h->d_x, h->d_state, h->d_hist,
-                                              opts->check_every, h->n_block_points, s));
+                                              opts->check_every, h->n_block_points,
+                                              h->n_store, s));
       else
         HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
       if (opts->n_check > 0) {

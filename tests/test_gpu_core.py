@@ -220,7 +220,10 @@ def test_evaluate_matches_oracle(case):
     assert err <= 1e-12
 
 
-def test_graph_and_eager_solves_agree(case):
+def test_graph_and_eager_solves_agree(case, monkeypatch):
+    """The multi-workgroup LSQR replayed as a graph and launched eagerly: the same bits (the
+    one-workgroup path, which small systems take by default, has its own chunking test)."""
+    monkeypatch.setenv("ELMFB_PERSISTENT", "0")
     spec, P, *_ = case
     torch = torch_mod()
     n = P.sizes["n_phi"]
