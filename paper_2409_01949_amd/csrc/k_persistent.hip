@@ -31,15 +31,49 @@ namespace {
 constexpr int kPThreads = 512;
 constexpr int kPWaves = kPThreads / 64;
 
+// A double moved across lanes by a DPP control (both halves); lanes without a source get 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Fixed-order sum over a full wavefront, the same value in every lane: a scan by row shifts of
+// 1, 2, 4 and 8 leaves each 16-lane row's sum in its last lane, and the four row sums are added
+// as (r0 + r1) + (r2 + r3).  DPP moves and lane reads stay in the vector unit, where the LDS
+// permutes of a shuffle butterfly cost a round trip each.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_move<0x111>(v);   // row_shr:1
+  v += dpp_move<0x112>(v);   // row_shr:2
+  v += dpp_move<0x114>(v);   // row_shr:4
+  v += dpp_move<0x118>(v);   // row_shr:8
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
+}
+
+// Sum over aligned groups of T lanes (T a power of two <= 64), the same value in each lane of
+// a group: quad permutes for the first two steps, shuffles beyond.
+__device__ __forceinline__ double group_sum(double s, int T) {
+  if (T >= 2) s += dpp_move<0xB1>(s);   // quad_perm [1,0,3,2]: lane ^ 1
+  if (T >= 4) s += dpp_move<0x4E>(s);   // quad_perm [2,3,0,1]: lane ^ 2
+  for (int o = 4; o < T; o <<= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
 // Fixed-order sum over the workgroup; every thread returns the same value (each wavefront
-// sums the kPWaves partials with the same butterfly).  slot holds kPWaves doubles and must not
-// be rewritten before every thread has passed a later barrier.
+// sums the kPWaves partials the same way).  slot holds kPWaves doubles and must not be
+// rewritten before every thread has passed a later barrier.
 __device__ __forceinline__ double wg_sum(double v, double* slot) {
-  v = wave_sum(v);
+  v = wave_sum_dpp(v);
   const int lane = threadIdx.x & 63;
   if (lane == 0) slot[threadIdx.x >> 6] = v;
   __syncthreads();
-  return wave_sum(lane < kPWaves ? slot[lane] : 0.0);
+  return wave_sum_dpp(lane < kPWaves ? slot[lane] : 0.0);
 }
 
 // Doubles ahead of the index tables, rounded up to an even count so the int4 block table
@@ -224,7 +258,7 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
     if (cb < g.n_bc) {
       double d = 0.0;
       for (int64_t q = lane; q < n_phi; q += 64) d += bc[(int64_t)cb * n_phi + q] * v[q];
-      d = wave_sum(d) * sv;
+      d = wave_sum_dpp(d) * sv;
       if (lane == 0) {
         const double un = d - coef_u * u[g.n_rows + cb];
         u[g.n_rows + cb] = un;
@@ -267,7 +301,7 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
         }
         for (int e = 0; p < n; p += T, ++e) s4[e] += a[p] * u[pr[p]];
         double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        for (int o = T >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        s = group_sum(s, T);
         double xq = s * su;
         for (int r = 0; r < g.n_bc; ++r) xq += bc[(int64_t)r * n_phi + q] * (u[g.n_rows + r] * su);
         if (sub == 0) {
