@@ -1,6 +1,8 @@
-"""LSQR in one workgroup (systems whose vectors fit in LDS: the damped oscillator of Sec. 5.1 and
-the small 1D problems) against the multi-workgroup LSQR on the same system (ELMFB_PERSISTENT=0)
-and against the oracle's LSQR.  Every call goes through the C ABI."""
+"""LSQR in one workgroup (systems whose vectors fit in LDS: the damped oscillator of Sec. 5.1, the
+small 1D problems and a small 2D one) against the multi-workgroup LSQR on the same system
+(ELMFB_PERSISTENT=0) and against the oracle's LSQR.  Every call goes through the C ABI."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -14,7 +16,16 @@ from gpu_util import build, torch_mod
 pytestmark = pytest.mark.gpu
 
 SPECS = [configs.oscillator(), configs.oscillator(omega0=30.0, J=6, K=5, n=120, levels=((1,), (6,))),
-         configs.small1d_multilevel(), configs.tiny1d()]
+         configs.small1d_multilevel(), configs.tiny1d(),
+         # a 2D system small enough for one workgroup: rows covered along both axes
+         dataclasses.replace(configs.small2d(), name="tiny2d", n_points=(15, 13),
+                             levels=((1, 1), (2, 3)), K=6)]
+
+
+def _test_points(spec):
+    if spec.dim == 1:
+        return np.linspace(spec.lo[0], spec.hi[0], 1000)[:, None]
+    return np.random.default_rng(5).uniform(spec.lo, spec.hi, (1000, 2))
 
 
 @pytest.fixture(scope="module", params=SPECS, ids=lambda s: s.name + f"_L{len(s.levels)}")
@@ -66,7 +77,7 @@ def test_iterates_match_the_multi_workgroup_path_and_the_oracle(case, monkeypatc
     dozen steps, and row order alone then moves ||r|| by ~1e-3)."""
     spec, P, W, b, M, h = case
     n = M.shape[1]
-    xt = np.linspace(spec.lo[0], spec.hi[0], 1000)[:, None]
+    xt = _test_points(spec)
     ref = linalg.lsqr(lambda vv: M @ vv, lambda uu: M.T @ uu, h, n, atol=0, btol=0, iter_lim=k)
     uref = ev.evaluate(spec, W, b, ref.x, xt)
     spread = rspread = 0.0
