@@ -56,7 +56,7 @@ enum {
   ELMFB_OP_D1 = 1,          /* du/dx, dim = 1                                                */
   ELMFB_OP_NEG_LAPLACE = 2, /* -Laplace(u), dim = 2                                          */
   ELMFB_OP_IDENTITY = 3,    /* u itself (evaluation / projection matrices), dim 1 or 2       */
-  ELMFB_OP_OSCILLATOR = 4   /* m u'' + mu u' + k u, (m, mu, k) = op_coef, dim 1 (Sec. 5.1
+  ELMFB_OP_OSCILLATOR = 4   /* m u'' + mu u' + k u, (m, mu, k) = op_coef, dim 1 (Sec. 4.2
                                eq. harm_oscillator)                                        */
 };
 

@@ -191,7 +191,7 @@ def apply_operator(prob, val, grad, lap):
     if prob.op == "identity":
         return val
     if prob.op == "oscillator":
-        # m u'' + mu u' + k u in 1D (Sec. 5.1 eq. harm_oscillator): lap is the second derivative
+        # m u'' + mu u' + k u in 1D (Sec. 4.2 eq. harm_oscillator): lap is the second derivative
         m, mu, k = prob.meta["osc"]
         return m * lap + mu * grad[:, :, 0] + k * val
     raise ValueError(prob.op)

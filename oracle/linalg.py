@@ -168,6 +168,29 @@ def bidiag_singular_values(bidiag, k):
     return np.linalg.svd(B, compute_uv=False)
 
 
+def bidiag_extreme_singular_values(bidiag, k):
+    """(sigma_max, sigma_min) of the same B_k without forming it, for long runs (k in the
+    thousands, where the dense SVD costs O(k^3)).  The symmetric matrix [0 B_k; B_k^T 0] of
+    order 2k+1 has eigenvalues +-sigma_i and one 0 (Golub and Kahan 1965); reordering its rows
+    and columns as (e_1, f_1, e_2, f_2, ..., e_{k+1}) makes it tridiagonal with zero diagonal and
+    off-diagonal alpha_1, beta_2, alpha_2, beta_3, ..., alpha_k, beta_{k+1}.  Its largest
+    eigenvalue is sigma_max and its (k+1)-th smallest (index k+1 from 0, after the k negative
+    ones and the zero) is sigma_min, found by LAPACK bisection (stebz) with the tightest
+    absolute tolerance."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    e = np.empty(2 * k)
+    for i in range(k):
+        e[2 * i] = bidiag[i][0]
+        e[2 * i + 1] = bidiag[i + 1][1]
+    d = np.zeros(2 * k + 1)
+    tol = 2.0 * np.finfo(np.float64).tiny
+    top = eigvalsh_tridiagonal(d, e, select="i", select_range=(2 * k, 2 * k), tol=tol,
+                               lapack_driver="stebz")
+    low = eigvalsh_tridiagonal(d, e, select="i", select_range=(k + 1, k + 1), tol=tol,
+                               lapack_driver="stebz")
+    return float(top[0]), float(low[0])
+
+
 # ---------------------------------------------------------------- CGLS
 
 @dataclass

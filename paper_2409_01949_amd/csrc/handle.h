@@ -107,6 +107,7 @@ struct elmfb_problem_s {
   int64_t n_ftiles = 0;
 
   bool assembled = false;
+  int persist_lds_mode = -1;    // one-workgroup LSQR: 1 matrix in LDS, 0 vectors only, -1 undecided
   double anorm_f = -1.0;        // exact Frobenius norm of the stored matrix (lazy)
   hipStream_t stream = nullptr; // internal stream for captured solves
   hipEvent_t ev_in = nullptr, ev_out = nullptr;

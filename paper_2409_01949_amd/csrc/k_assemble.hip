@@ -12,7 +12,7 @@
 //   -Lap(P phi) = -(Lap P phi + 2 (1-phi^2)(P_x W1/sx + P_y W2/sy)
 //                   - 2 P phi (1-phi^2)((W1/sx)^2 + (W2/sy)^2)),
 //   d/dx(P phi) = P_x phi + P (1-phi^2) W1/sx,    identity: P phi,
-//   1D m (P phi)'' + mu (P phi)' + k P phi (the damped oscillator, Sec. 5.1),
+//   1D m (P phi)'' + mu (P phi)' + k P phi (the damped oscillator, Sec. 4.2 eq. harm_oscillator),
 // scaled by 1/(sqrt(N) L), in FP64, stored feature-major per block (A_blk[k][p]) so that a
 // wavefront writes 64 consecutive points of one feature.
 #include "device.h"

@@ -5,7 +5,7 @@
 // else read from global memory, where it stays in the CU's caches.  A step here costs its
 // arithmetic and a few workgroup barriers instead of the ~9 kernel launches per step of the
 // multi-workgroup path, which dominate when the system holds only thousands of entries (the
-// damped oscillator of Sec. 5.1).
+// damped oscillator of Sec. 4.2, eq. harm_oscillator).
 //
 // The step is the same one the multi-workgroup path takes, on the same stored (unnormalised)
 // u and v with their scales su = 1/beta and sv = 1/alpha:
@@ -390,26 +390,33 @@ __global__ void __launch_bounds__(kPThreads) k_lsqr_persistent(
 hipError_t launch_lsqr_persistent(const Geo& g, const DevBlock* blocks, const int32_t* cov,
                                   const double* A, const double* bc, double* u, double* v,
                                   double* w, double* x, SolveState* st, double* hist, int n_iter,
-                                  int64_t n_pts, int64_t n_store, hipStream_t s) {
+                                  int64_t n_pts, int64_t n_store, int* lds_mode, hipStream_t s) {
   size_t lds = persistent_lds_bytes(g, n_pts, n_store, false);
   if (lds > kPersistMaxLds || n_iter <= 0) return hipErrorInvalidValue;
-  // the matrix joins the vectors in LDS when the device allows that much per workgroup
-  int dev = 0, max_lds = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess)
-    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e != hipSuccess) return e;
   const size_t lds_a = persistent_lds_bytes(g, n_pts, n_store, true);
-  if (lds_a <= (size_t)max_lds &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lsqr_persistent<true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a) == hipSuccess) {
+  // The matrix joins the vectors in LDS when the device allows that much per workgroup.  The
+  // decision (device query and kernel attribute) is taken on the first launch for this system
+  // and kept by the caller in *lds_mode: 1 matrix in LDS, 0 vectors only, -1 not decided yet.
+  if (*lds_mode < 0) {
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    // the attribute is the kernel's, shared by every handle: raise it to the device limit so a
+    // later system with a smaller matrix never lowers it under an earlier one's launches
+    *lds_mode = lds_a <= (size_t)max_lds &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lsqr_persistent<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    max_lds) == hipSuccess;
+    (void)hipGetLastError();
+  }
+  if (*lds_mode == 1)
     hipLaunchKernelGGL(k_lsqr_persistent<true>, dim3(1), dim3(kPThreads), lds_a, s, g, blocks,
                        cov, A, bc, u, v, w, x, st, hist, n_iter, n_pts, n_store);
-    return hipGetLastError();
-  }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_lsqr_persistent<false>, dim3(1), dim3(kPThreads), lds, s, g, blocks, cov,
-                     A, bc, u, v, w, x, st, hist, n_iter, n_pts, n_store);
+  else
+    hipLaunchKernelGGL(k_lsqr_persistent<false>, dim3(1), dim3(kPThreads), lds, s, g, blocks,
+                       cov, A, bc, u, v, w, x, st, hist, n_iter, n_pts, n_store);
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ size_t persistent_lds_bytes(const Geo& g, int64_t n_pts, int64_t n_store, bool a
 hipError_t launch_lsqr_persistent(const Geo& g, const DevBlock* blocks, const int32_t* cov,
                                   const double* A, const double* bc, double* u, double* v,
                                   double* w, double* x, SolveState* st, double* hist, int n_iter,
-                                  int64_t n_pts, int64_t n_store, hipStream_t s);
+                                  int64_t n_pts, int64_t n_store, int* lds_mode, hipStream_t s);
 
 // ---- Krylov recurrences (k_solver.hip)
 hipError_t launch_sumsq(const double* x, int64_t n, double* red, int n_wg, hipStream_t s);

@@ -792,7 +792,7 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
         HIP_OR_FAIL(h, launch_lsqr_persistent(g, h->d_blocks, h->d_cov, h->d_A, h->d_bc, h->d_u,
                                               h->d_v, h->d_w, h->d_x, h->d_state, h->d_hist,
                                               opts->check_every, h->n_block_points,
-                                              h->n_store, s));
+                                              h->n_store, &h->persist_lds_mode, s));
       else
         HIP_OR_FAIL(h, run_iterations(h, c, method, opts->check_every, opts->use_graph != 0, s));
       if (opts->n_check > 0) {

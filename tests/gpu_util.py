@@ -115,3 +115,71 @@ def rounded_variants(folded_blocks, rounding, K, shift, limit=4):
                 Ms[bi][idx] = alt
         out.append(Ms)
     return out
+
+
+# ---------------------------------------------------------------- converged-solve tolerances
+#
+# Two correct LSQR implementations that sum in different orders drift apart once the Golub-Kahan
+# vectors lose orthogonality, so a converged solve cannot be compared with the oracle's to a
+# fixed precision.  The yardstick is the oracle against itself: the same LSQR on row-permuted
+# copies of the system (the same computation in exact arithmetic, other rounding).  A GPU result
+# must lie within ITERATE_MULTIPLE times the oracle's largest deviation under those permutations
+# (u on the test points, ||r||, the extreme singular values of the recorded bidiagonal), as the
+# matched-iterate tests require; a step count, a single integer whose spread over three
+# permutations is a few percent, within COUNT_MULTIPLE times its spread plus COUNT_SLACK steps
+# (50x its spread would admit any count).
+
+ITERATE_MULTIPLE = 50.0
+COUNT_MULTIPLE = 3.0
+COUNT_SLACK = 2
+
+
+class OracleSpread:
+    """The oracle's LSQR on M and on `seeds` row-permuted copies, to the same stopping test.
+
+    ref: the unpermuted run; u_ref: evaluate(ref.x); sigma_ref: (sigma_max, sigma_min) of its
+    bidiagonal; itn, u, rnorm, sigma_max, sigma_min, err: the largest deviation of the permuted
+    runs from ref (absolute in steps, relative otherwise; err: |error vs exact| when `exact` is
+    given, absolute)."""
+
+    def __init__(self, M, h, n, evaluate, exact=None, error=None, seeds=3, x_map=None,
+                 **lsqr_kw):
+        from oracle import evaluate as ev
+        from oracle import linalg
+        x_map = x_map or (lambda x: x)
+
+        def run(A, rhs):
+            r = linalg.lsqr(lambda v: A @ v, lambda u: A.T @ u, rhs, n, **lsqr_kw)
+            k = r.itn
+            s = linalg.bidiag_extreme_singular_values(r.bidiag, k) if k > 0 else (0.0, 0.0)
+            return r, evaluate(x_map(r.x)), s
+
+        error = error or (lambda u, ue: ev.rel_l2(u, ue))
+        self.ref, self.u_ref, self.sigma_ref = run(M, h)
+        self.err_ref = error(self.u_ref, exact) if exact is not None else None
+        self.itn = self.u = self.rnorm = self.sigma_max = self.sigma_min = self.err = 0.0
+        self.runs = []
+        for seed in range(seeds):
+            perm = np.random.default_rng(seed).permutation(M.shape[0])
+            r, u, s = run(M[perm], h[perm])
+            self.runs.append(r)
+            self.itn = max(self.itn, abs(r.itn - self.ref.itn))
+            self.u = max(self.u, ev.rel_l2(u, self.u_ref))
+            self.rnorm = max(self.rnorm, abs(r.rnorm - self.ref.rnorm) / max(self.ref.rnorm, 1e-300))
+            if self.sigma_ref[0] > 0:
+                self.sigma_max = max(self.sigma_max, abs(s[0] - self.sigma_ref[0]) / self.sigma_ref[0])
+                self.sigma_min = max(self.sigma_min, abs(s[1] - self.sigma_ref[1]) / self.sigma_ref[1])
+            if exact is not None:
+                self.err = max(self.err, abs(error(u, exact) - self.err_ref))
+
+    def tol(self, spread, floor=1e-10):
+        return max(floor, ITERATE_MULTIPLE * spread)
+
+    def count_tol(self):
+        return COUNT_MULTIPLE * self.itn + COUNT_SLACK
+
+    def describe(self):
+        return (f"oracle {self.ref.itn} steps (istop {self.ref.istop}), spreads: steps {self.itn}, "
+                f"u {self.u:.1e}, ||r|| {self.rnorm:.1e}, sigma_max {self.sigma_max:.1e}, "
+                f"sigma_min {self.sigma_min:.1e}" +
+                (f", error {self.err:.1e}" if self.err_ref is not None else ""))

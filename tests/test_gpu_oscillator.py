@@ -1,4 +1,4 @@
-"""GPU parity of the damped oscillator (Sec. 5.1): the second-order operator rows
+"""GPU parity of the damped oscillator (Sec. 4.2, eq. harm_oscillator): the second-order operator rows
 m u'' + mu u' + k u, the two soft initial-condition rows (matrix B of Sec. 3), products over
 [N; B], LSQR and CGLS iterates, and LSQR to its stopping test against the oracle and the exact
 solution.  Every call goes through the C ABI."""
@@ -10,7 +10,7 @@ from oracle import assemble as asm
 from oracle import evaluate as ev
 from oracle import linalg
 
-from gpu_util import build, dev, device_blocks, torch_mod
+from gpu_util import OracleSpread, build, dev, device_blocks, torch_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -98,32 +98,49 @@ def test_krylov_iterates(case, method, ks):
         assert du <= tol
 
 
-def test_lsqr_to_its_stopping_test(case):
-    """LSQR with atol = btol = 1e-8 (the method's solver): it stops on its residual test within
-    20,000 steps, the reported ||r|| is the oracle's ||h - [N; B] c|| of the returned
-    coefficients to 1e-6, the iteration count is within 30% of the oracle's LSQR on the same
-    system, and u approaches the exact solution as the oracle's LSQR does (rel-L2 within 3x of
-    the oracle's, measured 7e-4 for the paper's baseline)."""
+def _e_l1(u, ue):
+    """Sec. 4.1 eq. l1_error: mean absolute error over the test points divided by the
+    (population) standard deviation of the exact solution."""
+    return float(np.mean(np.abs(u - ue)) / np.std(ue))
+
+
+def test_lsqr_full_budget_as_in_the_paper(case):
+    """The paper's solver protocol (Sec. 4.1: LSQR runs its whole budget of 15,000 iterations,
+    no early stop; atol = btol = 0 here, so only the machine-precision tests could end it) on the
+    GPU and in the oracle, and in the oracle on three row-permuted copies (OracleSpread): the same
+    stop reason (the baseline runs all 15,000 steps; the two-level case meets the machine-precision
+    test on ||A^T r|| after 2,500-2,800 steps, a count that moves with rounding), the step count
+    within 3x the oracle's step-count spread plus 2; u on 1,000 test points, the reported ||r|| and e_L1 against the
+    exact solution each within 50x the oracle's spread of that quantity (floor 1e-10); the
+    reported ||r|| equal to ||h - [N; B] c|| of the returned coefficients to 1e-6.  The dense QR
+    solution of the same system is printed beside it (its e_L1 is what the features can reach;
+    15,000 LSQR steps stop short of it on these kappa ~ 1e18 systems)."""
     spec, P, W, b, blocks, B, h, M = case
     torch = torch_mod()
     n = M.shape[1]
-    coef = torch.empty(n, dtype=torch.float64, device="cuda")
-    info = P.solve(coef, method="lsqr", iter_lim=20000, atol=1e-8, btol=1e-8, check_every=100)
-    c = coef.cpu().numpy()
-    ref = linalg.lsqr(lambda vv: M @ vv, lambda uu: M.T @ uu, h, n, atol=1e-8, btol=1e-8,
-                      iter_lim=20000)
     xt = np.linspace(0.0, 1.0, 1000)[:, None]
     ue = configs.exact(spec, xt)
-    err = ev.rel_l2(ev.evaluate(spec, W, b, c, xt), ue)
-    err_ref = ev.rel_l2(ev.evaluate(spec, W, b, ref.x, xt), ue)
+    sp = OracleSpread(M, h, n, lambda x: ev.evaluate(spec, W, b, x, xt), exact=ue, error=_e_l1,
+                      atol=0.0, btol=0.0, iter_lim=15000)
+    coef = torch.empty(n, dtype=torch.float64, device="cuda")
+    info = P.solve(coef, method="lsqr", iter_lim=15000, atol=0.0, btol=0.0, check_every=5000)
+    c = coef.cpu().numpy()
+    u = ev.evaluate(spec, W, b, c, xt)
+    e = _e_l1(u, ue)
+    du = ev.rel_l2(u, sp.u_ref)
     r = np.linalg.norm(h - M @ c)
-    print(f"{spec.name}: istop {info['istop']} after {info['iters']} (oracle {ref.istop} after "
-          f"{ref.itn}), rel-L2 vs exact {err:.2e} (oracle {err_ref:.2e}), ||r|| {info['rnorm']:.6e} "
-          f"vs {r:.6e}")
-    assert info["istop"] in (1, 2)
+    dr = abs(info["rnorm"] - sp.ref.rnorm) / sp.ref.rnorm
+    xq = linalg.householder_lstsq(M, h)
+    e_qr = _e_l1(ev.evaluate(spec, W, b, xq, xt), ue)
+    print(f"{spec.name}: istop {info['istop']} after {info['iters']}; {sp.describe()}; u {du:.2e} "
+          f"(tol {sp.tol(sp.u):.1e}), ||r|| {dr:.2e} (tol {sp.tol(sp.rnorm):.1e}), e_L1 {e:.3e} "
+          f"vs oracle {sp.err_ref:.3e} (tol {sp.tol(sp.err):.1e}); dense QR e_L1 {e_qr:.3e}")
+    assert info["istop"] == sp.ref.istop
+    assert abs(info["iters"] - sp.ref.itn) <= sp.count_tol()
     assert abs(info["rnorm"] - r) <= 1e-6 * r
-    assert abs(info["iters"] - ref.itn) <= 0.3 * ref.itn
-    assert err <= 3 * err_ref
+    assert du <= sp.tol(sp.u)
+    assert dr <= sp.tol(sp.rnorm)
+    assert abs(e - sp.err_ref) <= sp.tol(sp.err)
 
 
 def test_constraint_rows_refuse_the_other_paths(case):

@@ -269,7 +269,7 @@ def test_grid_definition_matches_inputs():
 
 
 def test_oscillator_exact_solution():
-    """The damped oscillator's closed form (Sec. 5.1 eq. harm_u_exact) solves
+    """The damped oscillator's closed form (Sec. 4.2 eq. harm_u_exact) solves
     m u'' + mu u' + k u = 0 (complex step for u', central second differences for u'') and meets
     u(0) = 1, u'(0) = 0."""
     spec = configs.oscillator(omega0=80.0)

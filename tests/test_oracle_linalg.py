@@ -369,3 +369,24 @@ def test_bidiagonal_singular_values_interlace_and_terminate():
     res3 = linalg.lsqr(lambda v: M3 @ v, lambda u: M3.T @ u, h3, 12, atol=0, btol=0, iter_lim=3)
     assert np.allclose(linalg.bidiag_singular_values(res3.bidiag, 3), [2.0, 1.0, 0.5],
                        rtol=1e-12, atol=0)
+
+
+def test_bidiagonal_extreme_values_by_bisection():
+    """The extreme singular values of B_k from bisection on the Golub-Kahan tridiagonal equal the
+    dense SVD's on a recorded LSQR bidiagonal (every k up to 60); and on a hand-built bidiagonal
+    with known singular values (a diagonal B_k padded with a zero last row: alpha_i on the
+    diagonal, beta = 0 below, so sigma_i = alpha_i) they are exact also when sigma_min is 1e-13
+    of sigma_max, where squaring (B^T B) would lose every digit."""
+    M, _ = _well_conditioned(m=90, n=60, cond=1e4, seed=7)
+    h = np.random.default_rng(8).standard_normal(90)
+    res = linalg.lsqr(lambda v: M @ v, lambda u: M.T @ u, h, 60, atol=0, btol=0, iter_lim=60)
+    for k in (1, 2, 7, 30, 60):
+        s = linalg.bidiag_singular_values(res.bidiag, k)
+        smax, smin = linalg.bidiag_extreme_singular_values(res.bidiag, k)
+        assert smax == pytest.approx(s[0], rel=1e-13)
+        assert smin == pytest.approx(s[-1], rel=1e-10)
+    alphas = [3.0, 1.0, 2.5e-13, 0.7]
+    bid = [(alphas[0], 1.0)] + [(alphas[i], 0.0) for i in range(1, 4)] + [(0.0, 0.0)]
+    smax, smin = linalg.bidiag_extreme_singular_values(bid, 4)
+    assert smax == pytest.approx(3.0, rel=1e-15)
+    assert smin == pytest.approx(2.5e-13, rel=1e-12)
