@@ -207,6 +207,19 @@ elmfb_status elmfb_matvec(elmfb_problem h, const double* v_dev, double* y_dev, v
 /* x_dev [n_phi] = M^T u_dev [n_rows + n_bc]. */
 elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, void* stream);
 
+/* x_dev [n_phi] = M^T u_dev [n_rows + n_bc] exactly as elmfb_rmatvec computes it (the same
+ * kernels and summation order: bit-identical results), for callers that cannot allocate device
+ * memory -- code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The call allocates nothing: its per-chunk partial sums (one double per feature and per chunk
+ * of <= 2048 points of a subdomain) live in a fixed scratch array of 2^18 doubles (2 MiB) that
+ * the library holds on every device it runs on until the process ends (its address on a device
+ * is looked up by elmfb_define_problem).  A problem needing more partials than that is refused
+ * with ELMFB_E_UNSUPPORTED before any device work (use elmfb_rmatvec).  Every call on one device
+ * shares that device's array: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller.  Asynchronous on `stream`. */
+elmfb_status elmfb_rmatvec_noalloc(elmfb_problem h, const double* u_dev, double* x_dev,
+                                   void* stream);
+
 /* Copy the assembled right-hand side h [n_rows + n_bc] (FP64). */
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
 

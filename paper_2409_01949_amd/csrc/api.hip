@@ -392,6 +392,11 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
     delete h;
     return fail(nullptr, ELMFB_E_DEVICE, m);
   }
+  if (hipError_t e = noalloc_init_device(); e != hipSuccess) {
+    delete h;
+    return fail(nullptr, ELMFB_E_DEVICE, std::string("scratch array address: ") +
+                                             hipGetErrorString(e));
+  }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)h->bytes_device > free_b) {
     const std::string m = "device footprint " + std::to_string(h->bytes_device) +

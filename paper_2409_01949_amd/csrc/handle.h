@@ -138,6 +138,10 @@ hipError_t dalloc(elmfb_problem h, T** p, int64_t bytes) {
 }
 void dfree(elmfb_problem h, void* p);
 
+// Looks up this device's address of the fixed scratch array of elmfb_rmatvec_noalloc (once per
+// device; the current device must be the handle's).
+hipError_t noalloc_init_device();
+
 // Descriptor checks and the host-side decomposition plan of one problem (no device work).
 std::string validate_desc(const elmfb_problem_desc* d);
 std::string plan_problem(elmfb_problem h);
