@@ -315,12 +315,15 @@ elmfb_status elmfb_bidiag_sigma(const double* ab_host, int32_t k, double* sigma_
 elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,
                             int64_t n_pts, double* u_dev, void* stream);
 
-/* Time the two matrix-streaming kernels of one LSQR/CGLS iteration on `stream` with HIP
- * events: the per-block-point pass of y = M v and the per-chunk pass of x = M^T u, each
- * launched `reps` times back to back on the stored matrix copy of precision `prec`
- * (ELMFB_FP64 or the descriptor's store_prec), with v = 1, u = 1.  Writes the average duration
- * of one launch in milliseconds to ms_host[0] (M v) and ms_host[1] (M^T u).  Blocks the host
- * until the timing completes. */
+/* Time the kernels of the two products of one LSQR/CGLS iteration on `stream` with HIP events:
+ * the per-block-point pass of y = M v, the per-chunk pass of x = M^T u, then the row gather that
+ * completes y and the column pass that completes x (each writing its vector and its norm
+ * partials, as in an LSQR step), each launched `reps` times back to back on the stored matrix
+ * copy of precision `prec` (ELMFB_FP64 or the descriptor's store_prec), with v = 1, u = 1.
+ * Writes the average duration of one launch in milliseconds to ms_host[0] (M v, first pass),
+ * ms_host[1] (M^T u, first pass), ms_host[2] (gather) and ms_host[3] (column pass): ms_host
+ * holds 4 doubles.  Overwrites the solver's work vectors.  Blocks the host until the timing
+ * completes.  (Measurement support for the products of Sec. 3 eq. multilevel_domain_decomp.) */
 elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t prec, int32_t reps, double* ms_host,
                                 void* stream);
 
@@ -380,6 +383,16 @@ elmfb_status elmfb_batch_precondition(elmfb_batch b, double shift, int32_t* n_fa
  * Overwrites the solver's work vectors; synchronises. */
 elmfb_status elmfb_batch_autotune(elmfb_batch b, int32_t prec, int32_t reps, double* ms_host,
                                   int32_t* chosen_host, void* stream);
+
+/* Time the three matrix passes of one batched Krylov step on `stream` with HIP events, each
+ * launched `reps` times (1..1000) back to back on the assembled matrix copy of precision `prec`
+ * (ELMFB_FP64 or the batch's store_prec), with V = 1, U = 1: ms_host[0] the per-block pass of
+ * Y = M V, ms_host[1] the row gather that completes Y (with its norm partials), ms_host[2] the
+ * per-block pass of X = M^T U at the current point tile (with its norm partials); ms_host holds
+ * 3 doubles.  Overwrites the solver's work vectors; blocks the host until the timing
+ * completes.  (Measurement support for the products of Sec. 3 eq. multilevel_domain_decomp.) */
+elmfb_status elmfb_batch_time_kernels(elmfb_batch b, int32_t prec, int32_t reps, double* ms_host,
+                                      void* stream);
 
 /* Set the point tile of the batched M^T U pass for matrix precision `prec` by hand (16, 32, or
  * 64 except for ELMFB_FP64), as elmfb_batch_autotune would keep it. */

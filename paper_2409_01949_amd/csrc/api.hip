@@ -673,29 +673,34 @@ elmfb_status elmfb_time_kernels(elmfb_problem h, int32_t prec, int32_t reps, dou
   std::vector<double> ones((size_t)(g.n_rows > g.n_phi ? g.n_rows : g.n_phi), 1.0);
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_x, ones.data(), (size_t)g.n_phi * 8, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_t, ones.data(), (size_t)g.n_rows * 8, hipMemcpyHostToDevice, s));
-  hipEvent_t e0, e1, e2;
-  HIP_OR_FAIL(h, hipEventCreate(&e0));
-  HIP_OR_FAIL(h, hipEventCreate(&e1));
-  HIP_OR_FAIL(h, hipEventCreate(&e2));
-  hipError_t e = hipEventRecord(e0, s);
+  // four timed groups: the two matrix-streaming passes, then the row gather that completes
+  // y = M v and the column pass that completes x = M^T u (both with their norm partials, as in
+  // an LSQR step)
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) HIP_OR_FAIL(h, hipEventCreate(&ev[i]));
+  hipError_t e = hipEventRecord(ev[0], s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
     e = launch_mv_blocks(g, prec, h->d_blocks, h->d_tiles, (int64_t)h->tiles.size(), A, h->d_x,
                          nullptr, h->d_tpart, nullptr, s);
-  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   for (int i = 0; i < reps && e == hipSuccess; ++i)
     e = launch_rmv_chunks(g, prec, h->d_blocks, h->d_chunks, (int64_t)h->chunks.size(), A,
                           h->d_t, nullptr, h->d_part, nullptr, s);
-  if (e == hipSuccess) e = hipEventRecord(e2, s);
-  if (e == hipSuccess) e = hipEventSynchronize(e2);
-  float t01 = 0.f, t12 = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&t01, e0, e1);
-  if (e == hipSuccess) e = hipEventElapsedTime(&t12, e1, e2);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipEventDestroy(e2);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_STORE_SQ, h->d_r, nullptr,
+                           nullptr, h->d_red, rows_wg(g), s);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_STORE_SQ, h->d_xt, nullptr, h->d_red,
+                          cols_wg(g), s);
+  if (e == hipSuccess) e = hipEventRecord(ev[4], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+  float t[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
+  for (int i = 0; i < 5; ++i) hipEventDestroy(ev[i]);
   HIP_OR_FAIL(h, e);
-  ms_host[0] = (double)t01 / reps;
-  ms_host[1] = (double)t12 / reps;
+  for (int i = 0; i < 4; ++i) ms_host[i] = (double)t[i] / reps;
   return ELMFB_OK;
 }
 

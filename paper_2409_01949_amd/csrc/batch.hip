@@ -677,6 +677,45 @@ elmfb_status elmfb_batch_autotune(elmfb_batch B, int32_t prec, int32_t reps, dou
   return ELMFB_OK;
 }
 
+elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps, double* ms_host,
+                                      void* stream) {
+  if (!B || !ms_host) return bfail(B, ELMFB_E_INVALID, "NULL argument");
+  if (!B->assembled) return bfail(B, ELMFB_E_STATE, "time_kernels before assemble");
+  if (prec != ELMFB_FP64 && prec != B->lo_prec)
+    return bfail(B, ELMFB_E_INVALID, "no stored matrix copy of that precision");
+  if (reps < 1 || reps > 1000) return bfail(B, ELMFB_E_INVALID, "reps must be in 1..1000");
+  hipStream_t s = (hipStream_t)stream;
+  const int R = B->R;
+  const int64_t nb = (int64_t)B->blocks.size();
+  const void* A = matrix_of(B, prec, false);
+  // V = 1 and U = 1 on every column, row and right-hand side (timing inputs only)
+  std::vector<double> ones((size_t)std::max(B->n_rows, B->n_phi) * R, 1.0);
+  BHIP(B, hipMemcpyAsync(B->d_v, ones.data(), (size_t)B->n_phi * R * 8, hipMemcpyHostToDevice, s));
+  BHIP(B, hipMemcpyAsync(B->d_u, ones.data(), (size_t)B->n_rows * R * 8, hipMemcpyHostToDevice, s));
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) BHIP(B, hipEventCreate(&ev[i]));
+  hipError_t e = hipEventRecord(ev[0], s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+                         (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_c, nullptr,
+                         nullptr, B->d_red_r, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
+                       B->d_u, R, nullptr, COL_STORE_SQ, B->d_w, B->d_red_c, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+  float t[3] = {0.f, 0.f, 0.f};
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
+  for (int i = 0; i < 4; ++i) hipEventDestroy(ev[i]);
+  BHIP(B, e);
+  for (int i = 0; i < 3; ++i) ms_host[i] = (double)t[i] / reps;
+  return ELMFB_OK;
+}
+
 elmfb_status elmfb_batch_set_tile(elmfb_batch B, int32_t prec, int32_t tile) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
   if (prec != ELMFB_FP64 && prec != ELMFB_FP32 && prec != ELMFB_BF16 && prec != ELMFB_FP16)

@@ -162,6 +162,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_autotune": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i32), P]),
         "elmfb_batch_set_tile": (i32, [P, i32, i32]),
+        "elmfb_batch_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double), P]),
         "elmfb_batch_set_coords": (i32, [P, i32]),
         "elmfb_batch_from_coords": (i32, [P, P, P, P]),
         "elmfb_batch_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
@@ -386,11 +387,12 @@ class Problem:
         return smax.value, smin.value, k.value
 
     def time_kernels(self, reps=20, prec="fp64", stream=None):
-        """Average duration (ms) of one launch of the M v and M^T u streaming kernels."""
-        out = (ctypes.c_double * 2)()
+        """Average duration (ms) of one launch of the M v and M^T u streaming kernels, then of
+        the row gather and the column pass that complete them."""
+        out = (ctypes.c_double * 4)()
         pr = _PREC[prec] if isinstance(prec, str) else int(prec)
         _check(_lib.elmfb_time_kernels(self.h, pr, int(reps), out, _stream(stream)), self.h)
-        return float(out[0]), float(out[1])
+        return tuple(float(v) for v in out)
 
     def time_gram(self, prec="fp64", which="all", reps=5, stream=None):
         """(ms per Gram computation, useful flops) after computing the blocks as gram() does."""
@@ -497,6 +499,13 @@ class Batch:
 
     def set_tile(self, prec, tile):
         self._check(_lib.elmfb_batch_set_tile(self.h, _PREC[prec], int(tile)))
+
+    def time_kernels(self, prec, reps=10, stream=None):
+        """Average ms per launch of the batched M V pass, the row gather and the M^T U pass."""
+        ms = (ctypes.c_double * 3)()
+        self._check(_lib.elmfb_batch_time_kernels(self.h, _PREC[prec], int(reps), ms,
+                                                  _stream(stream)))
+        return tuple(float(v) for v in ms)
 
     def solve(self, coef, iter_lim=15000, atol=0.0, btol=1e-6, check_every=50, use_graph=True,
               method="lsqr", precond=False, inner_iters=500, outer_lim=20, x0=None, stream=None):
