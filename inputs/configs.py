@@ -10,7 +10,7 @@ import math
 
 import numpy as np
 
-from .problems import ProblemSpec, grid_points
+from .problems import ProblemSpec, grid_points, l_shape_boundary
 from . import families as fam
 
 
@@ -59,6 +59,24 @@ def laplace_baseline(levels=((16, 16),), seed=0) -> ProblemSpec:
         w_range=(-a, a), b_range=(-a, a), seed=seed,
         meta={"family": "sines", "freqs": (4.0, 8.0, 12.0, 16.0), "amps": (0.25,) * 4,
               "n_test": (96, 96)},
+    )
+
+
+def helmholtz(omega: float = 8.0, levels=((16, 16),), K: int = 16, n: int = 80, k: float = 1.0,
+              seed: int = 0) -> ProblemSpec:
+    """Lap u + k^2 u = f on the L-shaped domain [0,1]^2 without [0.5,1]^2, u = g on the boundary
+    (Sec. 4.4): the manufactured solution of eq. helmholtz_exact, k = 1; the baseline has
+    omega = 8, one level of 16 x 16 subdomains (those outside the L discarded), K = 16, width
+    ratio 2.9, R = 1 (W, b ~ U(-1/sqrt(2), 1/sqrt(2))), the 80 x 80 grid's points inside the L as
+    interior rows, 80 boundary points per unit length with lambda_bc = 25 omega^4, and the
+    96 x 96 grid's points inside the L as test points."""
+    a = 1.0 / math.sqrt(2.0)
+    return ProblemSpec(
+        name=f"helmholtz{int(omega)}_L{len(levels)}", dim=2, op="helmholtz", ansatz="none",
+        ansatz_omega=0.0, lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(n, n), levels=tuple(levels),
+        delta=2.9, K=K, w_range=(-a, a), b_range=(-a, a), seed=seed, domain="l_shape",
+        meta={"family": "helmholtz", "omega": float(omega), "k": float(k), "n_test": (96, 96),
+              "bc_per_unit": 80, "lambda_bc": 25.0 * float(omega) ** 4},
     )
 
 
@@ -143,6 +161,8 @@ def forcing(spec: ProblemSpec, pts=None) -> np.ndarray:
         return fam.sines_forcing(pts, m["freqs"], m["amps"])
     if m["family"] == "oscillator":   # homogeneous equation
         return np.zeros(len(pts))
+    if m["family"] == "helmholtz":
+        return fam.helmholtz_forcing(pts, m["omega"], m["k"])
     raise ValueError(m["family"])
 
 
@@ -156,6 +176,8 @@ def exact(spec: ProblemSpec, pts) -> np.ndarray:
         return fam.oscillator_exact(np.asarray(pts)[:, 0], m["omega0"])
     if m["family"] == "sines":
         return fam.sines_exact(pts, m["freqs"], m["amps"])
+    if m["family"] == "helmholtz":
+        return fam.helmholtz_exact(np.asarray(pts), m["omega"])
     raise ValueError(m["family"])
 
 
@@ -229,3 +251,16 @@ def warm_batch_forcing(spec: ProblemSpec, C) -> np.ndarray:
     """[n_rhs, N] forcing of one warm-family instance for each coefficient vector C[r]."""
     pts = grid_points(spec)
     return np.stack([fam.ode_modes_forcing(pts, spec.meta["freqs"], c) for c in C])
+
+
+def boundary_points(spec: ProblemSpec) -> np.ndarray:
+    """Boundary collocation points of an L-shaped problem [N_B, 2]."""
+    return l_shape_boundary(spec, spec.meta["bc_per_unit"])
+
+
+def in_l_shape(spec: ProblemSpec, pts) -> np.ndarray:
+    """Points of a grid that belong to the L-shaped domain (not strictly inside the removed
+    upper-right quarter): the problem's domain, used to pick test points."""
+    pts = np.asarray(pts)
+    mid = 0.5 * (np.asarray(spec.lo) + np.asarray(spec.hi))
+    return ~((pts[:, 0] > mid[0]) & (pts[:, 1] > mid[1]))

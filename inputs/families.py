@@ -60,3 +60,18 @@ def oscillator_exact(t: np.ndarray, omega0: float, mu: float = 4.0, m: float = 1
     A = u0 / (2.0 * np.cos(phi))
     return np.exp(-d * t) * 2.0 * A * np.cos(phi + w * t)
 
+
+
+def helmholtz_exact(x: np.ndarray, omega: float) -> np.ndarray:
+    """u = sin(w pi x) sin(2 w pi y) + sin(3 w pi x y) (Sec. 4.4 eq. helmholtz_exact)."""
+    wp = omega * np.pi
+    return np.sin(wp * x[:, 0]) * np.sin(2 * wp * x[:, 1]) + np.sin(3 * wp * x[:, 0] * x[:, 1])
+
+
+def helmholtz_forcing(x: np.ndarray, omega: float, k: float) -> np.ndarray:
+    """f = Lap u + k^2 u for that u (Sec. 4.4 eq. helmholtz_f)."""
+    wp = omega * np.pi
+    a = np.sin(wp * x[:, 0]) * np.sin(2 * wp * x[:, 1])
+    c = np.sin(3 * wp * x[:, 0] * x[:, 1])
+    return (-5.0 * wp * wp * a - 9.0 * wp * wp * (x[:, 0] ** 2 + x[:, 1] ** 2) * c
+            + k * k * (a + c))

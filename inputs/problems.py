@@ -31,6 +31,9 @@ class ProblemSpec:
     b_range: Tuple[float, float] = (-1.0, 1.0)
     seed: int = 0
     meta: dict = field(default_factory=dict, compare=False, hash=False)
+    # "box": the whole box [lo, hi]; "l_shape" (dim 2): the box without its upper-right quarter
+    # [mid_x, hi_x] x [mid_y, hi_y], mid = (lo + hi)/2 (Sec. 4.4 eq. helmholtz_problem)
+    domain: str = "box"
 
     @property
     def n_levels(self) -> int:
@@ -45,7 +48,9 @@ class ProblemSpec:
 
 
 def n_phi(spec: ProblemSpec) -> int:
-    """Total number of random features over all levels (N_Phi = sum_l J_l K)."""
+    """Random-feature parameters drawn for a problem: K for every subdomain of every level's full
+    J_x x J_y grid (N_Phi = sum_l J_l K on a box; on an L-shaped domain the draw also covers the
+    subdomains the method discards, whose parameters are then not used)."""
     return spec.n_subdomains() * spec.K
 
 
@@ -53,7 +58,8 @@ def feature_params(spec: ProblemSpec):
     """Seeded uniform draws of the fixed hidden weights W [N_Phi, dim] and biases b [N_Phi].
 
     Rows follow the global column order q (level, then subdomain j in x-major
-    order, then feature k).  W is drawn first, then b, from one PCG64 stream.
+    order, then feature k) of each level's full subdomain grid.  W is drawn first, then b, from
+    one PCG64 stream.
     """
     rng = np.random.Generator(np.random.PCG64(spec.seed))
     n = n_phi(spec)
@@ -104,3 +110,22 @@ def mlp_init(dims, seed):
         parts.append(rng.uniform(-a, a, size=n_out * n_in))
         parts.append(np.zeros(n_out))
     return np.concatenate(parts).astype(np.float32)
+
+
+def l_shape_boundary(spec: ProblemSpec, per_unit: int):
+    """Boundary collocation points of the L-shaped domain (Sec. 4.4 baseline: points spread
+    evenly along each boundary segment, 80 on the long segments and 40 on the short ones of the
+    unit square's L): the six segments counter-clockwise from (lo_x, lo_y), each of length s
+    holding round(per_unit s) points at the centres of equal sub-intervals (so no corner is
+    taken twice and every segment has the same spacing).  Returns [N_B, 2]."""
+    lo, hi = np.asarray(spec.lo, float), np.asarray(spec.hi, float)
+    mid = 0.5 * (lo + hi)
+    corners = [(lo[0], lo[1]), (hi[0], lo[1]), (hi[0], mid[1]), (mid[0], mid[1]),
+               (mid[0], hi[1]), (lo[0], hi[1]), (lo[0], lo[1])]
+    out = []
+    for (x0, y0), (x1, y1) in zip(corners[:-1], corners[1:]):
+        length = abs(x1 - x0) + abs(y1 - y0)
+        n = int(round(per_unit * length))
+        t = (np.arange(n, dtype=np.float64) + 0.5) / n
+        out.append(np.stack([x0 + t * (x1 - x0), y0 + t * (y1 - y0)], axis=1))
+    return np.concatenate(out)

@@ -46,14 +46,50 @@ def assemble_blocks(prob, W, b, x=None):
     return blocks
 
 
-def rhs(prob, f):
-    """h = f(x_n) / sqrt(N_I), followed by the soft-constraint rows' sqrt(lambda_b) g_b."""
-    N = int(np.prod(prob.n_points))
+def rhs(prob, f, g=None):
+    """h = f(x_n) / sqrt(N_I) over the collocation points, followed by the soft-constraint rows'
+    right-hand sides: sqrt(lambda_b) g_b of the 1D conditions, or on an L-shaped domain
+    sqrt(lambda_bc / N_B) g(x_b) at the N_B boundary points (g given there)."""
+    N = geo.points(prob).shape[0]
     h = np.asarray(f, dtype=np.float64) / np.sqrt(float(N))
     bcs = prob.meta.get("bc", ())
     if bcs:
         h = np.concatenate([h, [wgt * val for (_, _, wgt, val) in bcs]])
+    if g is not None:
+        g = np.asarray(g, dtype=np.float64)
+        h = np.concatenate([h, dirichlet_weight(prob, g.size) * g])
     return h
+
+
+def dirichlet_weight(prob, n_b):
+    """Row weight of the boundary term lambda_bc (1/N_B) sum_b (u(x_b) - g_b)^2 of the
+    Helmholtz loss (Sec. 4.4): sqrt(lambda_bc / N_B)."""
+    return float(np.sqrt(prob.meta["lambda_bc"] / n_b))
+
+
+def dirichlet_rows(prob, W, b, xb):
+    """The boundary rows B [N_B, N_Phi] of the Helmholtz loss (Sec. 3 matrix B, Sec. 4.4 with
+    lambda_bc): B_{p,q} = sqrt(lambda_bc / N_B) (1/L) omega_j(x_p) phi_q(x_p), each subdomain's
+    window normalised over the kept subdomains of its level at x_p."""
+    xb = np.asarray(xb, dtype=np.float64)
+    subs = geo.subdomains(prob)
+    L = len(prob.levels)
+    wgt = dirichlet_weight(prob, xb.shape[0])
+    B = np.zeros((xb.shape[0], len(subs) * prob.K))
+    ans = basis.ansatz(xb, prob)
+    for l in range(L):
+        level = [sd for sd in subs if sd.level == l]
+        sums = basis.level_sum(xb, level)
+        for sd in level:
+            m = geo.in_support(xb, sd)
+            if not m.any():
+                continue
+            q = slice(sd.q0, sd.q0 + prob.K)
+            val, _, _ = basis.localized_function(xb[m], prob, sd, W[q], b[q],
+                                                 tuple(s[m] for s in sums),
+                                                 tuple(a[m] for a in ans))
+            B[m, q] = wgt / L * val
+    return B
 
 
 def bc_rows(prob, W, b):

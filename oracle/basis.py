@@ -190,6 +190,10 @@ def apply_operator(prob, val, grad, lap):
         return -lap
     if prob.op == "identity":
         return val
+    if prob.op == "helmholtz":
+        # Lap u + k^2 u (Sec. 4.4 eq. helmholtz_problem)
+        k = float(prob.meta["k"])
+        return lap + k * k * val
     if prob.op == "oscillator":
         # m u'' + mu u' + k u in 1D (Sec. 4.2 eq. harm_oscillator): lap is the second derivative
         m, mu, k = prob.meta["osc"]

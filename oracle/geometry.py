@@ -13,7 +13,13 @@ Readings of the paper used here:
     domain boundary;
   * a single subdomain along an axis (J = 1) is the whole axis: mu = midpoint,
     sigma = (hi-lo)/2, and its window factor along that axis is identically one;
-  * a point belongs to the support I_j when |x_i - mu_i| < sigma_i on every axis (strict).
+  * a point belongs to the support I_j when |x_i - mu_i| < sigma_i on every axis (strict);
+  * an L-shaped domain (Sec. 4.4 eq. helmholtz_problem) is the box without its upper-right
+    quarter Q = (mid_x, hi_x] x (mid_y, hi_y], mid = (lo + hi)/2: its collocation points are the
+    grid points not in Q (x > mid_x and y > mid_y both strict), and a subdomain is discarded
+    when its centre lies in Q (Sec. 4.1: the rectangular subdomains outside the L are dropped;
+    16 x 16 keeps 192, 8 x 8 keeps 48 as the paper counts them); the kept subdomains are
+    numbered in the same level-then-x-major order.
 """
 from __future__ import annotations
 
@@ -34,14 +40,33 @@ def axis_coords(lo: float, hi: float, n: int) -> np.ndarray:
     return out
 
 
-def points(prob, n_points=None) -> np.ndarray:
-    """Collocation points [N, dim] in x-major order."""
+def is_l_shape(prob) -> bool:
+    return getattr(prob, "domain", "box") == "l_shape"
+
+
+def in_removed_quarter(prob, x) -> np.ndarray:
+    """Points (rows of x [N, 2]) strictly inside the quarter an L-shaped domain removes."""
+    mx = 0.5 * (float(prob.lo[0]) + float(prob.hi[0]))
+    my = 0.5 * (float(prob.lo[1]) + float(prob.hi[1]))
+    return (np.real(x[:, 0]) > mx) & (np.real(x[:, 1]) > my)
+
+
+def grid(prob, n_points=None) -> np.ndarray:
+    """Every point of the regular grid [N_grid, dim] in x-major order."""
     n_points = prob.n_points if n_points is None else n_points
     ax = [axis_coords(prob.lo[a], prob.hi[a], int(n_points[a])) for a in range(prob.dim)]
     if prob.dim == 1:
         return ax[0][:, None]
     X, Y = np.meshgrid(ax[0], ax[1], indexing="ij")
     return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def points(prob, n_points=None) -> np.ndarray:
+    """Collocation points [N, dim] in x-major order: the grid points of the domain."""
+    x = grid(prob, n_points)
+    if is_l_shape(prob):
+        x = x[~in_removed_quarter(prob, x)]
+    return x
 
 
 def axis_centres(lo: float, hi: float, J: int, delta: float):
@@ -64,24 +89,39 @@ class Subdomain:
     q0: int               # first global column: sum_{m<l} J_m K + j K
     single: bool          # level with a single subdomain (window == 1)
     single_axes: tuple = ()   # per axis: the level has one subdomain along that axis
+    pidx: int = -1        # index among all subdomains of the full per-level grids (parameters)
 
 
 def subdomains(prob) -> List[Subdomain]:
     """All subdomains in global column order q = sum_{m<l} J_m K + j K + k."""
     out = []
     q0 = 0
+    pidx = 0
+    lshape = is_l_shape(prob)
     for l, J in enumerate(prob.levels):
         per_axis = [axis_centres(prob.lo[a], prob.hi[a], int(J[a]), prob.delta)
                     for a in range(prob.dim)]
         single = all(int(J[a]) == 1 for a in range(prob.dim))
+        j = 0
         for jj in np.ndindex(*[int(J[a]) for a in range(prob.dim)]):
             mu = np.array([per_axis[a][0][jj[a]] for a in range(prob.dim)])
             sig = np.array([per_axis[a][1] for a in range(prob.dim)])
-            j = int(np.ravel_multi_index(jj, [int(J[a]) for a in range(prob.dim)]))
+            pidx += 1
+            if lshape and in_removed_quarter(prob, mu[None, :])[0]:
+                continue
             out.append(Subdomain(l, j, tuple(int(v) for v in jj), mu, sig, q0, single,
-                                 tuple(int(J[a]) == 1 for a in range(prob.dim))))
+                                 tuple(int(J[a]) == 1 for a in range(prob.dim)), pidx - 1))
             q0 += prob.K
+            j += 1
     return out
+
+
+def kept_parameters(prob, W, b):
+    """The random-feature parameters of the kept subdomains in column order, from a draw over
+    every subdomain of the full per-level grids (the identity on a box)."""
+    K = prob.K
+    idx = np.concatenate([np.arange(sd.pidx * K, sd.pidx * K + K) for sd in subdomains(prob)])
+    return np.ascontiguousarray(W[idx]), np.ascontiguousarray(b[idx])
 
 
 def in_support(x: np.ndarray, sd: Subdomain) -> np.ndarray:
