@@ -64,7 +64,7 @@ def parse():
                    help="iteration budget of the FP64 comparison solves")
     p.add_argument("--ref-iters", type=int, default=15000,
                    help="iteration budget of the FP64 reference solution (atol = btol = 1e-10)")
-    p.add_argument("--secondary", default="ode1d,batch,poisson5l",
+    p.add_argument("--secondary", default="ode1d,helmholtz,batch,poisson5l",
                    help="workloads measured after the headline in the default run, each with a "
                         "fixed budget (empty: none)")
     p.add_argument("--secondary-deadline", type=float, default=300.0,
@@ -869,6 +869,148 @@ def ode1d_cpu_baseline(spec, W, b, f, n_iters, n_lsqr=1000):
             "value_1_thread": spec.n_rows / float(np.median(t1s))}
 
 
+def run_helmholtz(args, steps, warmup, levels=((16, 16),)):
+    """The L-shaped Helmholtz problem of Sec. 4.4 at the paper's baseline: omega = 8, k = 1, one
+    level of 16 x 16 subdomains less the 8 x 8 outside the L (192), K = 16, width ratio 2.9,
+    R = 1, the 80 x 80 grid's 4,800 points inside the L as interior rows, 320 Dirichlet rows at
+    the boundary points with lambda_bc = 25 omega^4.  Solved as the paper does (Sec. 4.1): FP64
+    LSQR for its whole 15,000-iteration budget (atol = btol = 0).  A step is assembly (interior
+    and boundary rows) and that solve; the error is e_L1 against the exact solution on the
+    96 x 96 grid's points inside the L (the paper's ELM-FBPINN: 1.3 +- 0.8e-2, context only)."""
+    import numpy as np
+    import torch
+
+    from inputs import configs, feature_params
+    from paper_2409_01949_amd import Problem
+
+    budget = 15000
+    spec = configs.helmholtz(levels=levels)
+    Wf, bf = feature_params(spec)
+    f = configs.forcing(spec)
+    xb = configs.boundary_points(spec)
+    g = configs.exact(spec, xb)
+    wgt = float(np.sqrt(spec.meta["lambda_bc"] / xb.shape[0]))
+    P = Problem.from_spec(spec, Wf, bf, "fp64", bc_pts=xb, bc_vals=g, bc_weight=wgt)
+    fd = torch.as_tensor(f).cuda()
+    n = P.sizes["n_phi"]
+    rows = P.sizes["n_interior"] + P.sizes["n_bc"]
+    coef = torch.empty(n, dtype=torch.float64, device="cuda")
+    from inputs.problems import grid_points
+    xt_all = grid_points(spec, spec.meta["n_test"])
+    xt = xt_all[configs.in_l_shape(spec, xt_all)]
+    ue = configs.exact(spec, xt)
+    xt_d = torch.as_tensor(xt).cuda()
+    u_d = torch.empty(xt.shape[0], dtype=torch.float64, device="cuda")
+
+    def step():
+        P.assemble(fd)
+        return P.solve(coef, method="lsqr", iter_lim=budget, atol=0.0, btol=0.0,
+                       check_every=1000)
+
+    print(f"# {spec.name}: {P.sizes}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    info = infos[-1]
+    print(f"# {spec.name}: {dt:.3f} s per step, {info['iters']} iterations", file=sys.stderr,
+          flush=True)
+    P.evaluate(coef, xt_d, u_d)
+    u = u_d.cpu().numpy()
+    e_l1 = float(np.mean(np.abs(u - ue)) / np.std(ue))
+    rel = float(np.linalg.norm(u - ue) / np.linalg.norm(ue))
+    sigma = krylov_sigma(P)
+    reps = max(2, args.kernel_reps // 10)
+    ms_l, us_step = _multi_wg_us_per_step(P, coef, 2000, reps)
+    tiny = configs.tiny1d()
+    Wt, bt = feature_params(tiny)
+    Pt = Problem.from_spec(tiny, Wt, bt, "fp64")
+    Pt.assemble(torch.as_tensor(configs.forcing(tiny)).cuda())
+    ct = torch.empty(Pt.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    old = os.environ.get("ELMFB_PERSISTENT")
+    os.environ["ELMFB_PERSISTENT"] = "0"
+    try:
+        _, us_floor = _multi_wg_us_per_step(Pt, ct, 2000, reps)
+    finally:
+        if old is None:
+            del os.environ["ELMFB_PERSISTENT"]
+        else:
+            os.environ["ELMFB_PERSISTENT"] = old
+    Pt.destroy()
+    out = {
+        "metric": METRIC, "value": rows / dt, "unit": "rows/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": spec.name, "omega": spec.meta["omega"], "k": spec.meta["k"],
+                   "levels": [list(J) for J in spec.levels], "K": spec.K,
+                   "subdomains": P.sizes["n_blocks"], "interior_rows": P.sizes["n_interior"],
+                   "boundary_rows": P.sizes["n_bc"], "lambda_bc": spec.meta["lambda_bc"],
+                   "method": "lsqr fp64", "atol": 0.0, "btol": 0.0, "iter_budget": budget},
+        "time_to_solution_s": dt, "iters": info["iters"], "istop": info["istop"],
+        "rnorm": info["rnorm"], "e_l1_test": e_l1, "rel_l2_test_vs_exact": rel,
+        "paper_e_l1_context": "1.3 +- 0.8e-2 (ELM-FBPINN, 37 s on one CPU core)",
+        "krylov_sigma": sigma,
+        "roofline": {"bound": "latency", "achieved": us_step, "peak": us_floor,
+                     "unit": "us/step", "frac": us_floor / us_step, "traffic": None,
+                     "kernel": "multi-workgroup LSQR step (the product passes, the row gather, "
+                               "the boundary rows, the column pass and the scalar kernels)",
+                     "peak_meaning": "the same graph of kernels on the 200-point 3-subdomain 1D "
+                                     "system (ELMFB_PERSISTENT=0)",
+                     "ms_per_2000_steps": ms_l},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = helmholtz_cpu_baseline(spec, Wf, bf, f, xb, g, info["iters"],
+                                                     rows)
+    P.destroy()
+    return out
+
+
+def helmholtz_cpu_baseline(spec, Wf, bf, f_grid, xb, g, n_iters, rows, n_lsqr=1000):
+    """The oracle on the Helmholtz problem: assembly of the interior blocks and the Dirichlet
+    rows, then n_lsqr LSQR iterations on the sparse [N; B], scaled to the GPU step's n_iters;
+    1 warm-up + 2 repeats at the BLAS's threads, 1 warm-up + 1 repeat at 1 thread."""
+    import numpy as np
+    import scipy.sparse as sp
+    from inputs import configs
+    from oracle import assemble as asm
+    from oracle import geometry as geo
+    from oracle import linalg
+    from threadpoolctl import threadpool_limits
+
+    inside = configs.in_l_shape(spec, geo.grid(spec))
+
+    def once():
+        t0 = time.perf_counter()
+        W, b = geo.kept_parameters(spec, Wf, bf)
+        blocks = asm.assemble_blocks(spec, W, b)
+        N, n = int(inside.sum()), len(blocks) * spec.K
+        S = sp.csr_matrix(np.vstack([asm.dense_from_blocks(blocks, N, n),
+                                     asm.dirichlet_rows(spec, W, b, xb)]))
+        h = asm.rhs(spec, f_grid[inside], g)
+        t1 = time.perf_counter()
+        linalg.lsqr(lambda v: S @ v, lambda u: S.T @ u, h, n, atol=0.0, btol=0.0,
+                    iter_lim=n_lsqr)
+        return (t1 - t0) + (time.perf_counter() - t1) * n_iters / n_lsqr
+
+    def series(k):
+        return [t for i, t in enumerate(once() for _ in range(k + 1)) if i > 0]
+
+    ts = series(2)
+    threads = _threads()
+    with threadpool_limits(limits=1, user_api="blas"):
+        t1s = series(1)
+    t_med = float(np.median(ts))
+    return {"value": rows / t_med, "unit": "rows/s", "cores": threads, "kind": "oracle",
+            "sample": (f"assembly and {n_lsqr} LSQR iterations on the sparse [N; B], scaled to "
+                       f"the step's {n_iters}; 1 warm-up + 2 repeats at {threads} BLAS threads, "
+                       f"median {t_med:.2f} s per step (min {min(ts):.2f}, max {max(ts):.2f}); "
+                       f"1 thread {t1s[0]:.2f} s"),
+            "value_1_thread": rows / t1s[0]}
+
+
 def _kname(prec):
     return {"fp64": "FP64", "fp32": "FP32", "bf16": "BF16", "fp16": "FP16"}[prec]
 
@@ -1146,6 +1288,10 @@ def main():
     if args.workload == "ode1d":
         print(json.dumps(run_ode1d(args, args.steps, args.warmup)), flush=True)
         return
+    if args.workload in ("helmholtz", "helmholtz_ml"):
+        lv = ((16, 16),) if args.workload == "helmholtz" else ((1, 1), (8, 8), (16, 16))
+        print(json.dumps(run_helmholtz(args, args.steps, args.warmup, lv)), flush=True)
+        return
     t_start = time.perf_counter()
     out = run_single(args, args.workload, args.steps, args.warmup)
     # the other workloads, each one step with a fixed budget after a short warm-up, reported
@@ -1164,6 +1310,8 @@ def main():
             a = _args_for(args, w)
             if w == "ode1d":
                 r = run_ode1d(a, 3, 1)
+            elif w == "helmholtz":
+                r = run_helmholtz(a, 2, 1)
             elif w == "batch":
                 r = run_batch(a, 1, 1, args.secondary_iters)
             else:

@@ -36,9 +36,10 @@
 extern "C" {
 #endif
 
-#define ELMFB_ABI_VERSION 2
+#define ELMFB_ABI_VERSION 3
 #define ELMFB_MAX_LEVELS 8
 #define ELMFB_MAX_BC 4
+#define ELMFB_MAX_BC_PTS 4096
 
 typedef int32_t elmfb_status;
 enum {
@@ -56,9 +57,24 @@ enum {
   ELMFB_OP_D1 = 1,          /* du/dx, dim = 1                                                */
   ELMFB_OP_NEG_LAPLACE = 2, /* -Laplace(u), dim = 2                                          */
   ELMFB_OP_IDENTITY = 3,    /* u itself (evaluation / projection matrices), dim 1 or 2       */
-  ELMFB_OP_OSCILLATOR = 4   /* m u'' + mu u' + k u, (m, mu, k) = op_coef, dim 1 (Sec. 4.2
+  ELMFB_OP_OSCILLATOR = 4,  /* m u'' + mu u' + k u, (m, mu, k) = op_coef, dim 1 (Sec. 4.2
                                eq. harm_oscillator)                                        */
+  ELMFB_OP_HELMHOLTZ = 5    /* Laplace(u) + k^2 u, k^2 = op_coef[0], dim 2 (Sec. 4.4
+                               eq. helmholtz_problem)                                      */
 };
+
+/* Domains (dim 2).  ELMFB_DOMAIN_L is the box without its upper-right quarter
+ * Q = (mid_x, hi_x] x (mid_y, hi_y], mid = (lo + hi)/2 (Sec. 4.4 eq. helmholtz_problem):
+ *   - the collocation rows are the grid points outside Q; row-space vectors keep the full grid
+ *     (row n = ix*ny + iy), and the rows of grid points in Q are identically zero (matrix and
+ *     right-hand side), so they do not change the least-squares problem; the row scale is
+ *     1/sqrt(N_I) with N_I the number of grid points outside Q;
+ *   - a subdomain whose centre lies in Q is discarded (Sec. 4.1: rectangular subdomains outside
+ *     the L are dropped; 16 x 16 keeps 192, 8 x 8 keeps 48); the kept ones are numbered in level,
+ *     then x-major order, and each window is normalised over the kept subdomains of its level;
+ *   - W_host / b_host still hold the parameters of every subdomain of each level's full
+ *     J_x x J_y grid (in that full order); the library takes the kept subdomains' rows. */
+enum { ELMFB_DOMAIN_BOX = 0, ELMFB_DOMAIN_L = 1 };
 
 /* Hard-constraint factor C(x) multiplying the network (Sec. 4.3 "Hard boundary constraints"). */
 enum {
@@ -131,17 +147,30 @@ typedef struct {
   double bc_x[ELMFB_MAX_BC];         /* x_b, inside [lo, hi]                                 */
   double bc_weight[ELMFB_MAX_BC];    /* sqrt(lambda_b) > 0                                   */
   double bc_value[ELMFB_MAX_BC];     /* g_b                                                  */
+  /* ABI 3 */
+  int32_t domain;                    /* ELMFB_DOMAIN_BOX or ELMFB_DOMAIN_L (dim 2)           */
+  /* Dirichlet rows at given points of a 2D problem (Sec. 3 matrix B; the boundary term
+   * lambda_bc (1/N_B) sum_b (u(x_b) - g_b)^2 of the Helmholtz loss, Sec. 4.4): row b is
+   * bc_pts_weight (1/L) omega_j(x_b) phi_q(x_b) C(x_b) with right-hand side bc_pts_weight g_b
+   * (bc_pts_weight = sqrt(lambda_bc / N_B) reproduces that loss).  They follow the collocation
+   * rows like the 1D conditions and take the same paths (FP64 LSQR and CGLS only). */
+  int32_t n_bc_pts;                  /* 0..ELMFB_MAX_BC_PTS (dim 2, with n_bc = 0)          */
+  const double* bc_pts_host;         /* [n_bc_pts][2], inside the box                       */
+  const double* bc_pts_val_host;     /* [n_bc_pts] g_b                                      */
+  double bc_pts_weight;              /* > 0                                                 */
 } elmfb_problem_desc;
 
 typedef struct {
-  int64_t n_rows;          /* collocation points N_I                                        */
+  int64_t n_rows;          /* grid points (row-space length before the soft-constraint rows) */
   int64_t n_phi;           /* columns N_Phi = K * sum_l prod_a J[l][a]                       */
   int64_t nnz;             /* stored entries = K * sum_j |I_j|                               */
   int64_t n_blocks;        /* subdomains over all levels                                    */
   int64_t n_block_points;  /* sum_j |I_j|                                                   */
   int64_t bytes_device;    /* device memory held by the handle                              */
   int64_t n_pairs;         /* overlapping subdomain pairs (i <= j), all levels               */
-  int64_t n_bc;            /* soft-constraint rows; row-space vectors hold n_rows + n_bc      */
+  int64_t n_bc;            /* soft-constraint rows (the 1D conditions or the Dirichlet rows at
+                              points); row-space vectors hold n_rows + n_bc                    */
+  int64_t n_interior;      /* collocation rows that belong to the domain (n_rows on a box)   */
 } elmfb_sizes;
 
 typedef struct {

@@ -73,9 +73,30 @@ std::string validate_impl(const elmfb_problem_desc* d) {
   if (d->op == ELMFB_OP_D1 && d->dim != 1) return "ELMFB_OP_D1 needs dim = 1";
   if (d->op == ELMFB_OP_NEG_LAPLACE && d->dim != 2) return "ELMFB_OP_NEG_LAPLACE needs dim = 2";
   if (d->op == ELMFB_OP_OSCILLATOR && d->dim != 1) return "ELMFB_OP_OSCILLATOR needs dim = 1";
+  if (d->op == ELMFB_OP_HELMHOLTZ && d->dim != 2) return "ELMFB_OP_HELMHOLTZ needs dim = 2";
   if (d->op != ELMFB_OP_D1 && d->op != ELMFB_OP_NEG_LAPLACE && d->op != ELMFB_OP_IDENTITY &&
-      d->op != ELMFB_OP_OSCILLATOR)
+      d->op != ELMFB_OP_OSCILLATOR && d->op != ELMFB_OP_HELMHOLTZ)
     return "unknown operator";
+  if (d->op == ELMFB_OP_HELMHOLTZ && !std::isfinite(d->op_coef[0]))
+    return "op_coef[0] (k^2) must be finite";
+  if (d->domain != ELMFB_DOMAIN_BOX && d->domain != ELMFB_DOMAIN_L) return "unknown domain";
+  if (d->domain == ELMFB_DOMAIN_L && d->dim != 2) return "ELMFB_DOMAIN_L needs dim = 2";
+  if (d->n_bc_pts < 0 || d->n_bc_pts > ELMFB_MAX_BC_PTS) return "n_bc_pts out of range";
+  if (d->n_bc_pts > 0) {
+    if (d->dim != 2) return "Dirichlet rows at points need dim = 2";
+    if (d->n_bc > 0) return "n_bc and n_bc_pts cannot both be set";
+    if (!d->bc_pts_host || !d->bc_pts_val_host) return "bc_pts_host and bc_pts_val_host are required";
+    if (!(std::isfinite(d->bc_pts_weight) && d->bc_pts_weight > 0.0))
+      return "bc_pts_weight must be finite and > 0";
+    for (int i = 0; i < d->n_bc_pts; ++i) {
+      for (int a = 0; a < 2; ++a) {
+        const double x = d->bc_pts_host[2 * i + a];
+        if (!(std::isfinite(x) && x >= d->lo[a] && x <= d->hi[a]))
+          return "bc_pts must lie in the box";
+      }
+      if (!std::isfinite(d->bc_pts_val_host[i])) return "bc_pts_val must be finite";
+    }
+  }
   if (d->op == ELMFB_OP_OSCILLATOR &&
       !(std::isfinite(d->op_coef[0]) && std::isfinite(d->op_coef[1]) &&
         std::isfinite(d->op_coef[2])))
@@ -124,7 +145,9 @@ std::string plan_impl(elmfb_problem h) {
   g.ny = d.dim == 2 ? d.n_points[1] : 1;
   g.n_levels = d.n_levels;
   g.K = d.K;
-  g.n_bc = d.n_bc;
+  g.n_bc = d.n_bc + d.n_bc_pts;
+  g.domain = d.domain;
+  g.bc_w = d.n_bc_pts > 0 ? d.bc_pts_weight : 0.0;
   for (int i = 0; i < 3; ++i) g.op_coef[i] = d.op_coef[i];
   h->bcs.n = d.n_bc;
   for (int i = 0; i < d.n_bc; ++i) {
@@ -145,16 +168,25 @@ std::string plan_impl(elmfb_problem h) {
     g.step[a] = npts[a] > 1 ? (hi[a] - lo[a]) / (double)(npts[a] - 1) : 0.0;
   }
   g.n_rows = (int64_t)g.nx * g.ny;
-  const double sqn = std::sqrt((double)g.n_rows);
-  g.inv_scale = 1.0 / (sqn * (double)d.n_levels);
-  g.inv_sqrt_n = 1.0 / sqn;
-  g.inv_levels = 1.0 / (double)d.n_levels;
-
   std::vector<double> xs[2];
   for (int a = 0; a < 2; ++a) {
     xs[a].resize(npts[a]);
     for (int m = 0; m < npts[a]; ++m) xs[a][m] = grid_x(lo[a], hi[a], npts[a], m);
   }
+  // L-shaped domain: grid points with x > mid_x and y > mid_y are not collocation points
+  const bool lshape = d.domain == ELMFB_DOMAIN_L;
+  for (int a = 0; a < 2; ++a) g.lmid[a] = 0.5 * (lo[a] + hi[a]);
+  g.n_int = g.n_rows;
+  if (lshape) {
+    int64_t cx = 0, cy = 0;
+    for (int m = 0; m < npts[0]; ++m) cx += xs[0][m] > g.lmid[0];
+    for (int m = 0; m < npts[1]; ++m) cy += xs[1][m] > g.lmid[1];
+    g.n_int = g.n_rows - cx * cy;
+  }
+  const double sqn = std::sqrt((double)g.n_int);
+  g.inv_scale = 1.0 / (sqn * (double)d.n_levels);
+  g.inv_sqrt_n = 1.0 / sqn;
+  g.inv_levels = 1.0 / (double)d.n_levels;
 
   // per level, per axis: centres, half-width, per-subdomain ranges, per-point cover ranges
   std::vector<int> m0s[kMaxLevels][2], m1s[kMaxLevels][2];
@@ -212,8 +244,37 @@ std::string plan_impl(elmfb_problem h) {
     }
     nb += g.J[l][0] * g.J[l][1];
   }
-  g.n_blocks = nb;
-  g.n_phi = (int64_t)nb * d.K;
+  // kept subdomains: all of them on a box; on an L-shaped domain those whose centre is not in
+  // the removed quarter.  bmap[bmap_off[l] + jx*Jy + jy] = block index or -1; pidx = index of
+  // the block among all subdomains of the full grids (its parameters in W_host, b_host).
+  h->bmap.clear();
+  h->block_pidx.clear();
+  int nkept = 0, nfull = 0;
+  for (int l = 0; l < d.n_levels; ++l) {
+    g.bmap_off[l] = (int32_t)h->bmap.size();
+    g.bbase[l] = nkept;
+    for (int jx = 0; jx < g.J[l][0]; ++jx)
+      for (int jy = 0; jy < g.J[l][1]; ++jy, ++nfull) {
+        const bool drop = lshape && centre_x(lo[0], hi[0], g.J[l][0], jx) > g.lmid[0] &&
+                          centre_x(lo[1], hi[1], g.J[l][1], jy) > g.lmid[1];
+        h->bmap.push_back(drop ? -1 : nkept);
+        if (!drop) {
+          h->block_pidx.push_back(nfull);
+          ++nkept;
+        }
+      }
+  }
+  h->n_sub_full = nfull;
+  g.n_blocks = nkept;
+  g.n_phi = (int64_t)nkept * d.K;
+  // per-axis window sums of an L-shaped domain: 6 doubles per (level, axis, grid index)
+  int32_t nls = 0;
+  for (int l = 0; l < d.n_levels; ++l)
+    for (int a = 0; a < 2; ++a) {
+      g.lsum_off[l][a] = nls;
+      if (lshape) nls += npts[a];
+    }
+  h->n_lsum = nls;
 
   // axis segments and the envelope table layout
   h->segs.clear();
@@ -240,7 +301,10 @@ std::string plan_impl(elmfb_problem h) {
   for (int l = 0; l < d.n_levels; ++l)
     for (int jx = 0; jx < g.J[l][0]; ++jx)
       for (int jy = 0; jy < g.J[l][1]; ++jy) {
+        if (h->bmap[g.bmap_off[l] + jx * g.J[l][1] + jy] < 0) continue;
         DevBlock B{};
+        B.jx = jx;
+        B.jy = jy;
         B.a_off = a_off;
         B.p_off = p_off;
         B.q0 = (int32_t)(h->blocks.size() * (size_t)d.K);
@@ -284,8 +348,8 @@ std::string plan_impl(elmfb_problem h) {
       const int jy1 = h->cov[g.cov_off[l][1] + 2 * (iy1 - 1) + 1];
       for (int jx = jx0; jx <= jx1; ++jx)
         for (int jy = jy0; jy <= jy1; ++jy) {
-          const int j = g.bbase[l] + jx * g.J[l][1] + jy;
-          if (j < (int)i) continue;
+          const int j = h->bmap[g.bmap_off[l] + jx * g.J[l][1] + jy];
+          if (j < (int)i) continue;   // discarded (-1) or already paired
           const DevBlock& Bj = h->blocks[j];
           if (Bj.n == 0) continue;
           const int ox0 = std::max(Bi.ix0, Bj.ix0), ox1 = std::min(ix1, Bj.ix0 + Bj.nx);
@@ -317,6 +381,9 @@ int64_t footprint(elmfb_problem h) {
   add(4 * 2 * kRedBlocks * 8);                            // reductions
   add(4 * (g.n_rows + g.n_bc) * 8);                       // h, u, t, r
   add((int64_t)g.n_bc * g.n_phi * 8);                     // soft-constraint rows
+  add((int64_t)g.n_bc * 3 * 8);                           // their points and values
+  add((int64_t)h->bmap.size() * 4);                       // block map
+  add(h->n_lsum * 6 * 8);                                 // per-axis window sums (L domain)
   add(7 * g.n_phi * 8);                                   // v, w, x, vt, xt, c
   add(g.n_phi * 2 * 8 + g.n_phi * 8);                     // W, b
   add(h->n_tab * 3 * 8);
@@ -425,6 +492,12 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_u, (g.n_rows + g.n_bc) * 8);
   ALLOC(h->d_t, (g.n_rows + g.n_bc) * 8);
   if (g.n_bc > 0) ALLOC(h->d_bc, (int64_t)g.n_bc * g.n_phi * 8);
+  if (desc->n_bc_pts > 0) ALLOC(h->d_bcpts, (int64_t)desc->n_bc_pts * 3 * 8);
+  ALLOC(h->d_bmap, (int64_t)h->bmap.size() * 4);
+  if (h->n_lsum > 0) ALLOC(h->d_lsum, h->n_lsum * 6 * 8);
+  h->geo.bmap = h->d_bmap;
+  h->geo.lsum = h->d_lsum;
+  h->geo.bcpts = h->d_bcpts;
   ALLOC(h->d_v, g.n_phi * 8);
   ALLOC(h->d_w, g.n_phi * 8);
   ALLOC(h->d_x, g.n_phi * 8);
@@ -447,13 +520,18 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_hist, (int64_t)kHistCap * 2 * 8);
 #undef ALLOC
 
-  // W padded to two columns
-  std::vector<double> W2((size_t)g.n_phi * 2, 0.0);
-  for (int64_t q = 0; q < g.n_phi; ++q)
-    for (int a = 0; a < desc->dim; ++a) W2[2 * q + a] = desc->W_host[q * desc->dim + a];
-  for (int64_t q = 0; q < g.n_phi * desc->dim; ++q)
+  // W padded to two columns; the parameters of kept block j are rows pidx_j K .. of W_host
+  std::vector<double> W2((size_t)g.n_phi * 2, 0.0), b1((size_t)g.n_phi, 0.0);
+  for (int j = 0; j < g.n_blocks; ++j)
+    for (int k = 0; k < g.K; ++k) {
+      const int64_t q = (int64_t)j * g.K + k;
+      const int64_t src = (int64_t)h->block_pidx[j] * g.K + k;
+      for (int a = 0; a < desc->dim; ++a) W2[2 * q + a] = desc->W_host[src * desc->dim + a];
+      b1[q] = desc->b_host[src];
+    }
+  for (int64_t q = 0; q < (int64_t)h->n_sub_full * g.K * desc->dim; ++q)
     if (!std::isfinite(desc->W_host[q])) { elmfb_destroy(h); return fail(nullptr, ELMFB_E_NUMERIC, "W has non-finite values"); }
-  for (int64_t q = 0; q < g.n_phi; ++q)
+  for (int64_t q = 0; q < (int64_t)h->n_sub_full * g.K; ++q)
     if (!std::isfinite(desc->b_host[q])) { elmfb_destroy(h); return fail(nullptr, ELMFB_E_NUMERIC, "b has non-finite values"); }
 
 #define H2D(dst, src, bytes)                                                          \
@@ -466,7 +544,15 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
     }                                                                                 \
   } while (0)
   H2D(h->d_W, W2.data(), W2.size() * 8);
-  H2D(h->d_b, desc->b_host, g.n_phi * 8);
+  H2D(h->d_b, b1.data(), g.n_phi * 8);
+  H2D(h->d_bmap, h->bmap.data(), h->bmap.size() * 4);
+  if (desc->n_bc_pts > 0) {
+    // Dirichlet points [n][2] then their values [n]
+    std::vector<double> bp((size_t)desc->n_bc_pts * 3);
+    std::memcpy(bp.data(), desc->bc_pts_host, (size_t)desc->n_bc_pts * 2 * 8);
+    std::memcpy(bp.data() + 2 * desc->n_bc_pts, desc->bc_pts_val_host, (size_t)desc->n_bc_pts * 8);
+    H2D(h->d_bcpts, bp.data(), bp.size() * 8);
+  }
   if (!h->blocks.empty()) H2D(h->d_blocks, h->blocks.data(), h->blocks.size() * sizeof(DevBlock));
   if (!h->tiles.empty()) H2D(h->d_tiles, h->tiles.data(), h->tiles.size() * sizeof(Tile));
   if (!h->chunks.empty()) H2D(h->d_chunks, h->chunks.data(), h->chunks.size() * sizeof(Tile));
@@ -487,6 +573,8 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   }
   h->desc.W_host = nullptr;
   h->desc.b_host = nullptr;
+  h->desc.bc_pts_host = nullptr;
+  h->desc.bc_pts_val_host = nullptr;
 
   if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -496,6 +584,7 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   }
   // envelope tables depend only on the geometry: build them once here
   hipError_t e = launch_axis_tables(g, h->d_segs, (int)h->segs.size(), h->d_cov, h->d_tab, h->stream);
+  if (e == hipSuccess && h->n_lsum > 0) e = launch_axis_sums(g, h->d_cov, h->d_lsum, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     const std::string m = std::string("axis tables: ") + hipGetErrorString(e);
@@ -516,6 +605,7 @@ elmfb_status elmfb_query(elmfb_problem h, elmfb_sizes* out) {
   out->bytes_device = h->bytes_device;
   out->n_pairs = (int64_t)h->pairs_all.size();
   out->n_bc = h->geo.n_bc;
+  out->n_interior = h->geo.n_int;
   return ELMFB_OK;
 }
 
@@ -536,9 +626,11 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
   HIP_OR_FAIL(h, launch_assemble(g, h->lo_prec, h->d_blocks, h->d_tiles,
                                  (int64_t)h->tiles.size(), h->d_tab, h->d_W, h->d_b, h->d_A,
                                  h->d_A_lo, s));
-  if (g.n_bc > 0)
+  if (g.n_bc > 0 && g.dim == 1)
     HIP_OR_FAIL(h, launch_bc_assemble(g, h->bcs, h->d_blocks, h->d_W, h->d_b, h->d_bc, h->d_h,
                                       s));
+  if (g.n_bc > 0 && g.dim == 2)
+    HIP_OR_FAIL(h, launch_bc_assemble_pts(g, h->d_blocks, h->d_W, h->d_b, h->d_bc, h->d_h, s));
   int32_t bad = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&bad, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
@@ -607,8 +699,8 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
       const DevBlock& B = h->blocks[b];
       int64_t* t = table_host + 8 * b;
       t[0] = B.level;
-      t[1] = (b - (size_t)h->geo.bbase[B.level]) / h->geo.J[B.level][1];
-      t[2] = (b - (size_t)h->geo.bbase[B.level]) % h->geo.J[B.level][1];
+      t[1] = B.jx;
+      t[2] = B.jy;
       t[3] = B.ix0;
       t[4] = B.nx;
       t[5] = B.iy0;

@@ -274,29 +274,35 @@ elmfb_status bt_run(elmfb_batch B, int prec, bool bj, int chunk, bool use_graph,
   BHIP(B, launch_bt_count_active(B->d_state, nR, B->d_count, s));
   BHIP(B, hipMemcpyAsync(&active, B->d_count, 4, hipMemcpyDeviceToHost, s));
   BHIP(B, hipStreamSynchronize(s));
-  const int64_t key = ((int64_t)chunk << 16) | (prec << 8) | (bj ? 128 : 0) | B->tp[prec_index(prec)];
   while (active > 0) {
     if (use_graph) {
-      auto it = B->graphs.find(key);
-      hipGraphExec_t exec = nullptr;
-      if (it != B->graphs.end()) {
-        exec = it->second;
-      } else {
-        hipGraph_t graph = nullptr;
-        BHIP(B, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e2 = hipSuccess;
-        for (int i = 0; i < chunk && e2 == hipSuccess; ++i) e2 = bt_iteration(B, prec, bj, s);
-        hipError_t e3 = hipStreamEndCapture(s, &graph);
-        if (e2 != hipSuccess || e3 != hipSuccess) {
-          if (graph) hipGraphDestroy(graph);
-          BHIP(B, e2 != hipSuccess ? e2 : e3);
+      // graphs of at most kGraphMaxSteps steps, replayed until `chunk` steps are enqueued
+      for (int left = chunk; left > 0;) {
+        const int m = left > kGraphMaxSteps ? kGraphMaxSteps : left;
+        const int64_t key =
+            ((int64_t)m << 16) | (prec << 8) | (bj ? 128 : 0) | B->tp[prec_index(prec)];
+        auto it = B->graphs.find(key);
+        hipGraphExec_t exec = nullptr;
+        if (it != B->graphs.end()) {
+          exec = it->second;
+        } else {
+          hipGraph_t graph = nullptr;
+          BHIP(B, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          hipError_t e2 = hipSuccess;
+          for (int i = 0; i < m && e2 == hipSuccess; ++i) e2 = bt_iteration(B, prec, bj, s);
+          hipError_t e3 = hipStreamEndCapture(s, &graph);
+          if (e2 != hipSuccess || e3 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            BHIP(B, e2 != hipSuccess ? e2 : e3);
+          }
+          hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          hipGraphDestroy(graph);
+          BHIP(B, e4);
+          B->graphs[key] = exec;
         }
-        hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        BHIP(B, e4);
-        B->graphs[key] = exec;
+        BHIP(B, hipGraphLaunch(exec, s));
+        left -= m;
       }
-      BHIP(B, hipGraphLaunch(exec, s));
     } else {
       for (int i = 0; i < chunk; ++i) BHIP(B, bt_iteration(B, prec, bj, s));
     }
@@ -321,9 +327,11 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
     const std::string v = validate_desc(&descs[i]);
     if (!v.empty()) return bfail(nullptr, ELMFB_E_INVALID, "instance " + std::to_string(i) + ": " + v);
     if (descs[i].K > kBatchMaxK) return bfail(nullptr, ELMFB_E_INVALID, "batched instances need K <= 128");
-    if (descs[i].n_bc != 0 || descs[i].op == ELMFB_OP_OSCILLATOR)
+    if (descs[i].n_bc != 0 || descs[i].n_bc_pts != 0 || descs[i].op == ELMFB_OP_OSCILLATOR ||
+        descs[i].op == ELMFB_OP_HELMHOLTZ || descs[i].domain != ELMFB_DOMAIN_BOX)
       return bfail(nullptr, ELMFB_E_UNSUPPORTED,
-                   "batched instances: no soft-constraint rows and no oscillator operator");
+                   "batched instances: box domains only, no soft-constraint rows, no oscillator "
+                   "or Helmholtz operator");
     if (descs[i].store_prec != descs[0].store_prec)
       return bfail(nullptr, ELMFB_E_INVALID, "all instances need the same store_prec");
   }

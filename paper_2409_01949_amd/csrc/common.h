@@ -14,6 +14,10 @@ constexpr int kRowAlign = 8;        // stored rows start on 8-element boundaries
 constexpr int kChunkPts = 2048;     // points per A^T u chunk (8 per thread of 256)
 constexpr int kHistCap = 32768;     // bidiagonalisation steps an LSQR run records
 constexpr int kRedBlocks = 1024;    // upper bound on per-workgroup partial sums of a reduction
+// Iterations per captured graph: a graph of a Krylov loop is one chain of ~10 kernels per step,
+// and instantiating very long chains exhausts the runtime (a 15,000-step capture ended the
+// process); a longer run between host checks replays graphs of at most this many steps.
+constexpr int kGraphMaxSteps = 1000;
 
 // One subdomain's block of the matrix: K rows (features) x n points of its box, feature-major.
 struct DevBlock {
@@ -29,6 +33,7 @@ struct DevBlock {
   int32_t taby;     // offset of the y-axis envelope table entries for iy0..iy0+ny-1
   int32_t level;
   int32_t inst;     // instance of a batch (0 for a single problem)
+  int32_t jx, jy;   // subdomain indices along the axes within the level
 };
 
 constexpr int kGramChunk = 4096;  // shared points per Gram chunk
@@ -98,8 +103,22 @@ struct Geo {
   double mid[kMaxLevels][2];      // centre for J == 1
   int32_t cov_off[kMaxLevels][2]; // offset into the covering table (per grid index: jlo, jhi)
   int32_t n_bc;                   // soft-constraint rows after the n_rows collocation rows
-  int32_t pad_bc_;
-  double op_coef[3];              // (m, mu, k) of the oscillator operator
+  int32_t domain;                 // ELMFB_DOMAIN_BOX or ELMFB_DOMAIN_L
+  double op_coef[3];              // (m, mu, k) of the oscillator operator; k^2 of Helmholtz
+  // L-shaped domain: the removed quarter starts at mid (points x > mid_x and y > mid_y); per
+  // level the first entry of the block map (kept block index or -1 for every (jx, jy) of the
+  // full grid) and of the per-axis window-sum tables (6 doubles per grid index: the sum over
+  // every subdomain along the axis and over those with centre above mid, each with two
+  // derivatives)
+  double lmid[2];
+  int64_t n_int;                  // grid points of the domain (interior rows)
+  int32_t bmap_off[kMaxLevels];
+  int32_t lsum_off[kMaxLevels][2];
+  double bc_w;                    // weight of the Dirichlet rows at points
+  // device tables of a single problem (unused by batches)
+  const int32_t* bmap;            // block map
+  const double* lsum;             // per-axis window sums (L domain)
+  const double* bcpts;            // Dirichlet points [n_bc][2], then their values [n_bc]
 };
 
 // Soft-constraint conditions of a 1D problem: row b = w[b] (1/L) D^order[b][psi_q](x[b]),

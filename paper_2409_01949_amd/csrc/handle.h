@@ -21,6 +21,10 @@ struct elmfb_problem_s {
   std::vector<Tile> tiles, chunks;
   std::vector<int32_t> chunk_start, cov;
   std::vector<AxisSeg> segs;
+  std::vector<int32_t> bmap;    // per level, (jx, jy) of the full grid -> kept block or -1
+  std::vector<int32_t> block_pidx;   // per kept block: index among all subdomains (parameters)
+  int n_sub_full = 0;           // subdomains of the full per-level grids
+  int64_t n_lsum = 0;           // grid indices of the per-axis window-sum tables (L domain)
   int64_t nnz = 0, n_block_points = 0, n_tab = 0;
   int64_t n_store = 0;          // stored elements per matrix copy, row padding included
   int64_t bytes_device = 0;
@@ -57,6 +61,9 @@ struct elmfb_problem_s {
   SolveState* d_state = nullptr;
   int32_t* d_flag = nullptr;
   double* d_bc = nullptr;       // soft-constraint rows, dense [n_bc][n_phi]
+  double* d_bcpts = nullptr;    // Dirichlet points [n][2], then their values [n]
+  int32_t* d_bmap = nullptr;    // block map
+  double* d_lsum = nullptr;     // per-axis window sums of an L-shaped domain
   BcSpec bcs{};                 // their conditions
   double* d_hist = nullptr;     // (alpha_{i+1}, beta_{i+1}) of the last LSQR run, i < kHistCap
   int32_t hist_k = -1;          // steps of that run (-1: the last solve ran no LSQR)

@@ -13,6 +13,7 @@
 //                   - 2 P phi (1-phi^2)((W1/sx)^2 + (W2/sy)^2)),
 //   d/dx(P phi) = P_x phi + P (1-phi^2) W1/sx,    identity: P phi,
 //   1D m (P phi)'' + mu (P phi)' + k P phi (the damped oscillator, Sec. 4.2 eq. harm_oscillator),
+//   Lap(P phi) + k^2 P phi (the Helmholtz problem, Sec. 4.4 eq. helmholtz_problem),
 // scaled by 1/(sqrt(N) L), in FP64, stored feature-major per block (A_blk[k][p]) so that a
 // wavefront writes 64 consecutive points of one feature.
 #include "device.h"
@@ -45,9 +46,17 @@ __global__ void __launch_bounds__(256) k_axis_tables(Geo g, const AxisSeg* __res
           raw_window(x, centre(g, l, a, jj), sigma, v, v1, v2);
           S += v; S1 += v1; S2 += v2;
         }
-        gv = w / S;
-        g1 = (w1 - gv * S1) / S;
-        g2 = (w2 - 2.0 * g1 * S1 - gv * S2) / S;
+        if (g.domain == ELMFB_DOMAIN_L) {
+          // L-shaped domain: the level sum of the kept 2D windows does not factor per axis, so
+          // the table holds the raw factor and the entry kernel divides by the 2D sum
+          gv = w;
+          g1 = w1;
+          g2 = w2;
+        } else {
+          gv = w / S;
+          g1 = (w1 - gv * S1) / S;
+          g2 = (w2 - 2.0 * g1 * S1 - gv * S2) / S;
+        }
       }
       double c, c1, c2;
       ansatz_axis(g, a, x, c, c1, c2);
@@ -60,6 +69,66 @@ __global__ void __launch_bounds__(256) k_axis_tables(Geo g, const AxisSeg* __res
     tab[o + 1] = e1;
     tab[o + 2] = e2;
   }
+}
+
+// L-shaped domain: per (level, axis, grid index) the sum of the raw window factors of every
+// subdomain along the axis covering that index, S_a, and of those whose centre lies above the
+// domain's midpoint, D_a, each with two derivatives.  The discarded subdomains of a level are
+// the product set {jx: mu_x > mid_x} x {jy: mu_y > mid_y}, so the level sum of the kept 2D
+// windows is S = S_x S_y - D_x D_y (and its derivatives follow from the product rule).  An axis
+// with a single subdomain has factor 1: S_a = 1, D_a = 0.
+__global__ void __launch_bounds__(256) k_axis_sums(Geo g, const int32_t* __restrict__ cov,
+                                                   double* __restrict__ lsum) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int l = 0; l < g.n_levels; ++l)
+    for (int a = 0; a < 2; ++a) {
+      const int n = a == 0 ? g.nx : g.ny;
+      if (i >= n) {
+        i -= n;
+        continue;
+      }
+      const int m = (int)i;
+      double S = 1.0, S1 = 0.0, S2 = 0.0, D = 0.0, D1 = 0.0, D2 = 0.0;
+      if (g.J[l][a] > 1) {
+        const double x = grid_coord(g, a, m);
+        const double sigma = g.sigma[l][a];
+        const int jlo = cov[g.cov_off[l][a] + 2 * m], jhi = cov[g.cov_off[l][a] + 2 * m + 1];
+        S = 0.0;
+        for (int jj = jlo; jj <= jhi; ++jj) {
+          const double mu = centre(g, l, a, jj);
+          double v, v1, v2;
+          raw_window(x, mu, sigma, v, v1, v2);
+          S += v; S1 += v1; S2 += v2;
+          if (mu > g.lmid[a]) { D += v; D1 += v1; D2 += v2; }
+        }
+      }
+      double* o = lsum + 6 * (int64_t)(g.lsum_off[l][a] + m);
+      o[0] = S; o[1] = S1; o[2] = S2; o[3] = D; o[4] = D1; o[5] = D2;
+      return;
+    }
+}
+
+// Envelope P = P_hat / S of a point on an L-shaped domain from the raw product P_hat = X Y (X, Y
+// the per-axis table entries, ansatz included) and the 2D level sum S = Sx Sy - Dx Dy, by the
+// quotient rule: P_a = (P_hat_a - P S_a)/S, P_aa = (P_hat_aa - 2 P_a S_a - P S_aa)/S.
+__device__ __forceinline__ void l_envelope(const Geo& g, int l, int ix, int iy, const double* tx,
+                                           const double* ty, double& P, double& Px, double& Py,
+                                           double& LP) {
+  const double* sx = g.lsum + 6 * (int64_t)(g.lsum_off[l][0] + ix);
+  const double* sy = g.lsum + 6 * (int64_t)(g.lsum_off[l][1] + iy);
+  const double S = sx[0] * sy[0] - sx[3] * sy[3];
+  const double Sx = sx[1] * sy[0] - sx[4] * sy[3];
+  const double Sy = sx[0] * sy[1] - sx[3] * sy[4];
+  const double Sxx = sx[2] * sy[0] - sx[5] * sy[3];
+  const double Syy = sx[0] * sy[2] - sx[3] * sy[5];
+  const double H = tx[0] * ty[0], Hx = tx[1] * ty[0], Hy = tx[0] * ty[1];
+  const double Hxx = tx[2] * ty[0], Hyy = tx[0] * ty[2];
+  P = H / S;
+  Px = (Hx - P * Sx) / S;
+  Py = (Hy - P * Sy) / S;
+  const double Pxx = (Hxx - 2.0 * Px * Sx - P * Sxx) / S;
+  const double Pyy = (Hyy - 2.0 * Py * Sy - P * Syy) / S;
+  LP = Pxx + Pyy;
 }
 
 template <int PREC>
@@ -110,12 +179,21 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
   const int lx = p / B.ny, ly = p - lx * B.ny;
   const double* tx = tab + 3 * (int64_t)(B.tabx + lx);
   const double* ty = tab + 3 * (int64_t)(B.taby + ly);
-  const double X0 = tx[0], X1 = tx[1], X2 = tx[2];
-  const double Y0 = ty[0], Y1 = ty[1], Y2 = ty[2];
-  const double P = X0 * Y0, Px = X1 * Y0, Py = X0 * Y1, LP = X2 * Y0 + X0 * Y2;
+  double P, Px, Py, LP;
+  bool outside = false;   // a grid point of the removed quarter of an L-shaped domain
+  if (g.domain == ELMFB_DOMAIN_L) {
+    l_envelope(g, l, B.ix0 + lx, B.iy0 + ly, tx, ty, P, Px, Py, LP);
+    outside = grid_coord(g, 0, B.ix0 + lx) > g.lmid[0] && grid_coord(g, 1, B.iy0 + ly) > g.lmid[1];
+  } else {
+    const double X0 = tx[0], X1 = tx[1], X2 = tx[2];
+    const double Y0 = ty[0], Y1 = ty[1], Y2 = ty[2];
+    P = X0 * Y0;
+    Px = X1 * Y0;
+    Py = X0 * Y1;
+    LP = X2 * Y0 + X0 * Y2;
+  }
   // subdomain-local inputs xbar = (x - mu)/sigma
-  const int jx = (t.blk - g.bbase[l]) / g.J[l][1];
-  const int jy = (t.blk - g.bbase[l]) - jx * g.J[l][1];
+  const int jx = B.jx, jy = B.jy;
   const double xb = (grid_coord(g, 0, B.ix0 + lx) - centre(g, l, 0, jx)) / sx;
   const double yb = (g.dim == 2) ? (grid_coord(g, 1, B.iy0 + ly) - centre(g, l, 1, jy)) / sy : 0.0;
   const double scale = g.inv_scale;
@@ -135,20 +213,33 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
       const double d2 = LP * ph + 2.0 * sd * Px * c1s[k] - 2.0 * P * ph * sd * c3s[k];
       const double d1 = Px * ph + P * sd * c1s[k];
       v = g.op_coef[0] * d2 + g.op_coef[1] * d1 + g.op_coef[2] * P * ph;
+    } else if (OP == ELMFB_OP_HELMHOLTZ) {
+      // Lap(P phi) + k^2 P phi (k^2 = op_coef[0])
+      v = LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k] +
+          g.op_coef[0] * P * ph;
     } else {
       v = P * ph;
     }
-    const double e = v * scale;
+    const double e = outside ? 0.0 : v * scale;
     A[base + (int64_t)k * ld] = e;
     if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * ld, e);
   }
 }
 
+// h = f / sqrt(N_I); on an L-shaped domain the rows of grid points in the removed quarter are
+// zero (f is not read there).
 __global__ void k_rhs(Geo g, const double* __restrict__ f, double* __restrict__ h,
                       int32_t* __restrict__ bad) {
-  const double sq = sqrt((double)g.n_rows);
+  const double sq = sqrt((double)g.n_int);
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < g.n_rows;
        r += (int64_t)gridDim.x * blockDim.x) {
+    if (g.domain == ELMFB_DOMAIN_L) {
+      const int ix = (int)(r / g.ny), iy = (int)(r - (int64_t)ix * g.ny);
+      if (grid_coord(g, 0, ix) > g.lmid[0] && grid_coord(g, 1, iy) > g.lmid[1]) {
+        h[r] = 0.0;
+        continue;
+      }
+    }
     const double v = f[r];
     if (!isfinite(v)) atomicOr(bad, 1);
     h[r] = v / sq;
@@ -189,6 +280,10 @@ static hipError_t launch_assemble_p(const Geo& g, const DevBlock* blocks, const 
       hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_OSCILLATOR>), grid, blk, 0, s, g, blocks,
                          tiles, tab, W, b, A, A_lo);
       break;
+    case ELMFB_OP_HELMHOLTZ:
+      hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_HELMHOLTZ>), grid, blk, 0, s, g, blocks,
+                         tiles, tab, W, b, A, A_lo);
+      break;
     default:
       hipLaunchKernelGGL((k_assemble<LO, ELMFB_OP_IDENTITY>), grid, blk, 0, s, g, blocks, tiles,
                          tab, W, b, A, A_lo);
@@ -208,6 +303,13 @@ hipError_t launch_assemble(const Geo& g, int lo_prec, const DevBlock* blocks, co
   if (lo_prec == ELMFB_FP16)
     return launch_assemble_p<ELMFB_FP16>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
   return launch_assemble_p<-1>(g, blocks, tiles, n_tiles, tab, W, b, A, A_lo, s);
+}
+
+hipError_t launch_axis_sums(const Geo& g, const int32_t* cov, double* lsum, hipStream_t s) {
+  int64_t n = 0;
+  for (int l = 0; l < g.n_levels; ++l) n += g.nx + g.ny;
+  hipLaunchKernelGGL(k_axis_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, cov, lsum);
+  return hipGetLastError();
 }
 
 hipError_t launch_rhs(const Geo& g, const double* f, double* h, int32_t* bad, hipStream_t s) {

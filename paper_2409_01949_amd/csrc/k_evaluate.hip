@@ -44,6 +44,41 @@ __device__ __forceinline__ int cover_axis(const Geo& g, int l, int a, double x, 
   return n;
 }
 
+// The same covering subdomains with their raw window factors (not normalised), the sum S of
+// those factors and the sum D over the ones whose centre lies above the domain's midpoint (the
+// discarded subdomains of an L-shaped domain are the products of such centres on both axes).
+__device__ __forceinline__ int cover_axis_raw(const Geo& g, int l, int a, double x, int* js,
+                                              double* ws, double& S, double& D) {
+  S = 1.0;
+  D = 0.0;
+  const int J = g.J[l][a];
+  if (J == 1 || a >= g.dim) {
+    js[0] = 0;
+    ws[0] = 1.0;
+    return 1;
+  }
+  const double h = g.cen_h[l][a], sigma = g.sigma[l][a];
+  int j0 = (int)floor((x - g.lo[a] - sigma) / h) - 1;
+  int j1 = (int)ceil((x - g.lo[a] + sigma) / h) + 1;
+  if (j0 < 0) j0 = 0;
+  if (j1 > J - 1) j1 = J - 1;
+  int n = 0;
+  S = 0.0;
+  for (int j = j0; j <= j1 && n < kMaxCover; ++j) {
+    const double mu = centre(g, l, a, j);
+    if (fabs(x - mu) < sigma) {
+      double w, w1, w2;
+      raw_window(x, mu, sigma, w, w1, w2);
+      js[n] = j;
+      ws[n] = w;
+      S += w;
+      if (mu > g.lmid[a]) D += w;
+      ++n;
+    }
+  }
+  return n;
+}
+
 __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restrict__ W,
                                                   const double* __restrict__ bias,
                                                   const double* __restrict__ coef,
@@ -56,18 +91,34 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
     const double x = pts[i * g.dim];
     const double y = (g.dim == 2) ? pts[i * g.dim + 1] : 0.0;
     double total = 0.0;
+    const bool lshape = g.domain == ELMFB_DOMAIN_L;
     for (int l = 0; l < g.n_levels; ++l) {
       int jxs[kMaxCover], jys[kMaxCover];
       double wxs[kMaxCover], wys[kMaxCover];
-      const int nxc = cover_axis(g, l, 0, x, jxs, wxs);
-      const int nyc = cover_axis(g, l, 1, y, jys, wys);
+      int nxc, nyc;
+      double inv_s = 1.0;
+      if (lshape) {
+        // windows normalised over the kept subdomains: S = Sx Sy - Dx Dy
+        double Sx, Dx, Sy, Dy;
+        nxc = cover_axis_raw(g, l, 0, x, jxs, wxs, Sx, Dx);
+        nyc = cover_axis_raw(g, l, 1, y, jys, wys, Sy, Dy);
+        inv_s = 1.0 / (Sx * Sy - Dx * Dy);
+      } else {
+        nxc = cover_axis(g, l, 0, x, jxs, wxs);
+        nyc = cover_axis(g, l, 1, y, jys, wys);
+      }
       const double sx = g.sigma[l][0], sy = g.sigma[l][1];
       double lev = 0.0;
       for (int ax = 0; ax < nxc; ++ax) {
         const double xb = (x - centre(g, l, 0, jxs[ax])) / sx;
         for (int ay = 0; ay < nyc; ++ay) {
           const double yb = (g.dim == 2) ? (y - centre(g, l, 1, jys[ay])) / sy : 0.0;
-          const int64_t q0 = (int64_t)(g.bbase[l] + jxs[ax] * g.J[l][1] + jys[ay]) * g.K;
+          int bi = g.bbase[l] + jxs[ax] * g.J[l][1] + jys[ay];
+          if (lshape) {
+            bi = g.bmap[g.bmap_off[l] + jxs[ax] * g.J[l][1] + jys[ay]];
+            if (bi < 0) continue;   // discarded subdomain
+          }
+          const int64_t q0 = (int64_t)bi * g.K;
           double acc = 0.0;
           for (int k = lane; k < g.K; k += 64) {
             const int64_t q = q0 + k;
@@ -77,7 +128,7 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
           lev += (wxs[ax] * wys[ay]) * acc;
         }
       }
-      total += lev;
+      total += lshape ? lev * inv_s : lev;
     }
     total = wave_sum(total);
     double cx, c1, c2, cy;

@@ -89,7 +89,16 @@ __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __re
       const int jy0 = cov[g.cov_off[l][1] + 2 * iy], jy1 = cov[g.cov_off[l][1] + 2 * iy + 1];
       const int Jy = g.J[l][1];
       const int ncx = jx1 - jx0 + 1, ncy = jy1 - jy0 + 1;
-      if (ncx <= 3 && ncy <= 3) {
+      if (g.domain == ELMFB_DOMAIN_L) {
+        // an L-shaped domain discards subdomains: covering blocks through the block map
+        for (int jx = jx0; jx <= jx1; ++jx)
+          for (int jy = jy0; jy <= jy1; ++jy) {
+            const int bi = g.bmap[g.bmap_off[l] + jx * Jy + jy];
+            if (bi < 0) continue;
+            const DevBlock& B = blocks[bi];
+            y += tpart[B.p_off + (ix - B.ix0) * B.ny + (iy - B.iy0)];
+          }
+      } else if (ncx <= 3 && ncy <= 3) {
         // up to 3 x 3 covering blocks (width ratio < 3): every load issued before the sums,
         // which keep the order jx-major, jy-minor; absent slots read the first block and add 0
         double tv[9];

@@ -11,6 +11,7 @@ struct AxisSeg {
 };
 
 // ---- assembly (k_assemble.hip)
+hipError_t launch_axis_sums(const Geo& g, const int32_t* cov, double* lsum, hipStream_t s);
 hipError_t launch_axis_tables(const Geo& g, const AxisSeg* segs, int n_segs, const int32_t* cov,
                               double* tab, hipStream_t s);
 // writes the FP64 matrix into A and, if lo_prec is FP32 or BF16, its rounded copy into A_lo
@@ -54,6 +55,10 @@ hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const dou
 hipError_t launch_bc_assemble(const Geo& g, const BcSpec& bc, const DevBlock* blocks,
                               const double* W, const double* b, double* Bm, double* h,
                               hipStream_t s);
+hipError_t launch_bc_assemble_pts(const Geo& g, const DevBlock* blocks, const double* W,
+                                  const double* b, double* Bm, double* h, hipStream_t s);
+// workgroups of launch_bc_rows, each writing one norm partial
+int bc_row_wgs(const Geo& g);
 hipError_t launch_bc_rows(const Geo& g, const double* Bm, const double* v, const double* vscale,
                           int mode, double* out, const double* bvec, const SolveState* st,
                           double* red, hipStream_t s);

@@ -31,7 +31,7 @@ struct KCtx {
 double* red_slot(elmfb_problem h, int i) { return h->d_red + (int64_t)2 * kRedBlocks * i; }
 
 // norm partials the soft-constraint rows add after the row gather's
-int bc_parts(const Geo& g) { return g.n_bc > 0 ? 1 : 0; }
+int bc_parts(const Geo& g) { return g.n_bc > 0 ? bc_row_wgs(g) : 0; }
 
 const double* state_field(elmfb_problem h, size_t off) {
   return reinterpret_cast<const double*>(reinterpret_cast<const char*>(h->d_state) + off);
@@ -42,6 +42,9 @@ const double* state_field(elmfb_problem h, size_t off) {
 bool one_workgroup_fits(elmfb_problem h) {
   if (const char* e = std::getenv("ELMFB_PERSISTENT"))
     if (e[0] == '0' && e[1] == 0) return false;
+  // the one-workgroup kernel finds covering blocks arithmetically on a full tensor grid of
+  // subdomains and keeps its handful of constraint rows in LDS
+  if (h->geo.domain != ELMFB_DOMAIN_BOX || h->geo.n_bc > ELMFB_MAX_BC) return false;
   return persistent_lds_bytes(h->geo, h->n_block_points, h->n_store, false) <= kPersistMaxLds &&
          h->n_store <= kPersistMaxEntries;
 }
@@ -338,10 +341,15 @@ hipError_t get_graph(elmfb_problem h, const KCtx& c, int method, int n, hipGraph
 hipError_t run_iterations(elmfb_problem h, const KCtx& c, int method, int n, bool graph,
                           hipStream_t s) {
   if (!graph) return enqueue_iterations(h, c, method, n, s);
-  hipGraphExec_t exec = nullptr;
-  hipError_t e = get_graph(h, c, method, n, &exec);
-  if (e != hipSuccess) return e;
-  return hipGraphLaunch(exec, s);
+  while (n > 0) {
+    const int m = n > kGraphMaxSteps ? kGraphMaxSteps : n;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = get_graph(h, c, method, m, &exec);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return e;
+    n -= m;
+  }
+  return hipSuccess;
 }
 
 // Evaluate the current solution at the check points and update the rel-L2 stop state.

@@ -16,19 +16,22 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libelmfb.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_BC = 4
+MAX_BC_PTS = 4096
 MAX_LEVELS = 8
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = range(7)
-OP_D1, OP_NEG_LAPLACE, OP_IDENTITY, OP_OSCILLATOR = 1, 2, 3, 4
+OP_D1, OP_NEG_LAPLACE, OP_IDENTITY, OP_OSCILLATOR, OP_HELMHOLTZ = 1, 2, 3, 4, 5
+DOMAIN_BOX, DOMAIN_L = 0, 1
 ANSATZ_NONE, ANSATZ_TANH_ORIGIN, ANSATZ_TANH_BOX = 0, 1, 2
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 COPY_FOLDED = 0x100
 LSQR, CGLS, MIXED_IR, NORMAL_CG, MIXED_IR_CG = 0, 1, 2, 3, 4
 
 _OPS = {"d1": OP_D1, "neg_laplace": OP_NEG_LAPLACE, "identity": OP_IDENTITY,
-        "oscillator": OP_OSCILLATOR}
+        "oscillator": OP_OSCILLATOR, "helmholtz": OP_HELMHOLTZ}
+_DOMAINS = {"box": DOMAIN_BOX, "l_shape": DOMAIN_L}
 _ANSATZ = {"none": ANSATZ_NONE, "tanh_origin": ANSATZ_TANH_ORIGIN, "tanh_box": ANSATZ_TANH_BOX}
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16}
 _METHOD = {"lsqr": LSQR, "cgls": CGLS, "mixed_ir": MIXED_IR, "normal_cg": NORMAL_CG,
@@ -58,13 +61,18 @@ class ProblemDesc(ctypes.Structure):
         ("bc_x", ctypes.c_double * MAX_BC),
         ("bc_weight", ctypes.c_double * MAX_BC),
         ("bc_value", ctypes.c_double * MAX_BC),
+        ("domain", ctypes.c_int32),
+        ("n_bc_pts", ctypes.c_int32),
+        ("bc_pts_host", ctypes.POINTER(ctypes.c_double)),
+        ("bc_pts_val_host", ctypes.POINTER(ctypes.c_double)),
+        ("bc_pts_weight", ctypes.c_double),
     ]
 
 
 class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_rows", "n_phi", "nnz", "n_blocks", "n_block_points", "bytes_device",
-                 "n_pairs", "n_bc")]
+                 "n_pairs", "n_bc", "n_interior")]
 
 
 class SolveOpts(ctypes.Structure):
@@ -227,10 +235,13 @@ def _check(code, handle=None):
 
 
 def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K, W, b,
-              store_prec="fp64", op_coef=(0.0, 0.0, 0.0), bc=()):
-    """Descriptor from plain values.  W [n_phi, dim] and b [n_phi] are float64 host arrays;
-    the returned tuple keeps them alive for the duration of the define call.  bc: soft
-    constraints as (x, derivative order, weight sqrt(lambda), value) tuples."""
+              store_prec="fp64", op_coef=(0.0, 0.0, 0.0), bc=(), domain="box", bc_pts=None,
+              bc_vals=None, bc_weight=0.0):
+    """Descriptor from plain values.  W [n_phi, dim] and b [n_phi] are float64 host arrays
+    (on an L-shaped domain: for every subdomain of each level's full grid); the returned tuple
+    keeps them alive for the duration of the define call.  bc: 1D soft constraints as
+    (x, derivative order, weight sqrt(lambda), value) tuples; bc_pts [n, 2], bc_vals [n],
+    bc_weight: 2D Dirichlet rows at points."""
     d = ProblemDesc()
     d.abi_version = ABI_VERSION
     d.dim = int(dim)
@@ -258,15 +269,31 @@ def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K,
     b = np.ascontiguousarray(b, dtype=np.float64)
     d.W_host = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     d.b_host = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    return d, (W, b)
+    d.domain = _DOMAINS[domain] if isinstance(domain, str) else int(domain)
+    keep = [W, b]
+    if bc_pts is not None:
+        P = np.ascontiguousarray(bc_pts, dtype=np.float64).reshape(-1, 2)
+        G = np.ascontiguousarray(bc_vals, dtype=np.float64).reshape(-1)
+        d.n_bc_pts = P.shape[0]
+        d.bc_pts_host = P.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.bc_pts_val_host = G.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.bc_pts_weight = float(bc_weight)
+        keep += [P, G]
+    return d, tuple(keep)
 
 
-def desc_from_spec(spec, W, b, store_prec="fp64"):
-    """Descriptor from any object with the problem-specification attributes."""
+def desc_from_spec(spec, W, b, store_prec="fp64", bc_pts=None, bc_vals=None, bc_weight=0.0):
+    """Descriptor from any object with the problem-specification attributes (Helmholtz: the
+    operator's k^2 from meta["k"]; the Dirichlet points, values and weight from the caller)."""
     meta = getattr(spec, "meta", {}) or {}
+    coef = meta.get("osc", (0.0, 0.0, 0.0))
+    if spec.op == "helmholtz":
+        coef = (float(meta["k"]) ** 2, 0.0, 0.0)
     return make_desc(spec.dim, spec.op, spec.ansatz, spec.ansatz_omega, spec.lo, spec.hi,
                      spec.n_points, spec.levels, spec.delta, spec.K, W, b, store_prec,
-                     op_coef=meta.get("osc", (0.0, 0.0, 0.0)), bc=tuple(meta.get("bc", ())))
+                     op_coef=coef, bc=tuple(meta.get("bc", ())),
+                     domain=getattr(spec, "domain", "box"), bc_pts=bc_pts, bc_vals=bc_vals,
+                     bc_weight=bc_weight)
 
 
 def define_problem(desc_and_keep) -> "Problem":
@@ -289,8 +316,8 @@ class Problem:
         self.sizes = self.query()
 
     @classmethod
-    def from_spec(cls, spec, W, b, store_prec="fp64"):
-        return define_problem(desc_from_spec(spec, W, b, store_prec))
+    def from_spec(cls, spec, W, b, store_prec="fp64", **bc):
+        return define_problem(desc_from_spec(spec, W, b, store_prec, **bc))
 
     def query(self):
         s = Sizes()
