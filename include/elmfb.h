@@ -183,14 +183,20 @@ typedef struct {
   int32_t inner_iters;     /* MIXED_IR: LSQR steps per refinement step (>= 1)               */
   int32_t outer_lim;       /* MIXED_IR: maximum refinement steps (>= 0)                     */
   double atol, btol;       /* Paige-Saunders stopping tolerances (>= 0); conlim is off      */
-  const double* x0_dev;    /* optional warm start [n_phi] (NULL: zero)                      */
+  const double* x0_dev;    /* optional warm start [n_rhs][n_phi] (NULL: zero)               */
   /* optional stop on the solution error: every check_every iterations u_tilde is evaluated
    * at check_pts_dev [n_check][dim] and the solve stops once
-   * ||u - check_ref|| / ||check_ref|| <= target_rel_l2.  n_check = 0 disables it. */
+   * ||u - check_ref|| / ||check_ref|| <= target_rel_l2 (check_ref_dev [n_rhs][n_check]).
+   * n_check = 0 disables it. */
   const double* check_pts_dev;
   const double* check_ref_dev;
   int64_t n_check;
   double target_rel_l2;
+  /* ABI 3 */
+  int32_t n_rhs;           /* right-hand sides solved with the assembled matrix, 1 (also for
+                              0) up to the n_rhs of the last elmfb_assemble                  */
+  int32_t estimate_cond;   /* 1: fill info.acond (host bisection on the recorded bidiagonal,
+                              O(60 k) operations for k LSQR steps)                          */
 } elmfb_solve_opts;
 
 typedef struct {
@@ -204,7 +210,13 @@ typedef struct {
   double anorm;            /* LSQR Frobenius-norm estimate; CGLS: exact ||A||_F              */
   double xnorm;            /* ||x||                                                          */
   double rel_l2;           /* last rel-L2 check value (-1 if none ran)                      */
-  double ms_solve;         /* host wall time of the call                                    */
+  double ms_solve;         /* host wall time of this right-hand side's solve                 */
+  /* ABI 3 */
+  double acond;            /* with opts.estimate_cond: sigma_max / sigma_min of the Golub-Kahan
+                              bidiagonal of the last LSQR run (a lower bound on the condition
+                              number of the operator it ran on; see elmfb_condition_estimate);
+                              otherwise, or without an LSQR step, -1                         */
+  double ms_assemble;      /* host wall time of the last elmfb_assemble                      */
 } elmfb_solve_info;
 
 /* Validate the descriptor, plan the decomposition (subdomain boxes on the grid, offsets),
@@ -214,20 +226,24 @@ typedef struct {
  * (ELMFB_E_DEVICE otherwise).  Sec. 3, Sec. 4.1. */
 elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out);
 
-/* Sizes of the planned system. */
+/* Sizes of the planned system: rows (Sec. 3 "Problem and model definition", the collocation
+ * points), columns N_Phi = K sum_l J_l (Sec. 3 "Indexing conventions"), stored entries of the
+ * blocks M_j over I_j x K_j (Sec. 3 eq. multilevel_domain_decomp), overlapping pairs. */
 elmfb_status elmfb_query(elmfb_problem h, elmfb_sizes* out_host);
 
-/* Collocation points [n_rows][dim] in row order, computed on the device. */
+/* The regular collocation grid [n_rows][dim] in row order, computed on the device (Sec. 4.1:
+ * regularly spaced collocation points; both endpoints included). */
 elmfb_status elmfb_points(elmfb_problem h, double* xy_dev, void* stream);
 
 /* Assemble every block M_j [K][|I_j|] (feature-major) of the system matrix in the stored
- * precision and the right-hand side h = f/sqrt(N_I) from f_dev [n_rows] (Sec. 3 "Definition
- * of the vectors" and "Definition of the system matrices"):
+ * precision and the right-hand sides h_r = f_r/sqrt(N_I) from f_dev [n_rhs][n_rows] (Sec. 3
+ * "Definition of the vectors" and "Definition of the system matrices"):
  *     M_{n,q} = Op[C omega_j phi_q](x_n) / (sqrt(N_I) L).
- * Entries are computed in FP64 and rounded once (round-to-nearest-even) to the stored
- * precision.  ELMFB_E_NUMERIC if f holds a non-finite value (checked on the device; the
- * call then synchronises the stream). */
-elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream);
+ * The matrix is assembled once for all n_rhs (1..1024) right-hand sides, which elmfb_solve
+ * then solves with it.  Entries are computed in FP64 and rounded once (round-to-nearest-even)
+ * to the stored precision.  ELMFB_E_NUMERIC if f holds a non-finite value (checked on the
+ * device).  Synchronises the stream (its wall time is reported as info.ms_assemble). */
+elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, int32_t n_rhs, void* stream);
 
 /* y_dev [n_rows + n_bc] = M v_dev [n_phi] (block-sparse, Sec. 3 eq. multilevel_domain_decomp;
  * the soft-constraint rows follow the collocation rows). */
@@ -249,10 +265,12 @@ elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, 
 elmfb_status elmfb_rmatvec_noalloc(elmfb_problem h, const double* u_dev, double* x_dev,
                                    void* stream);
 
-/* Copy the assembled right-hand side h [n_rows + n_bc] (FP64). */
+/* Copy the assembled right-hand sides h [n_rhs][n_rows + n_bc] (FP64; Sec. 3 "Definition of
+ * the vectors": f/sqrt(N_I), then the soft-constraint values). */
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream);
 
-/* Copy the soft-constraint rows B [n_bc][n_phi] (FP64, dense; nothing when n_bc = 0). */
+/* Copy the soft-constraint rows B [n_bc][n_phi] (FP64, dense; nothing when n_bc = 0; Sec. 3
+ * "Definition of the system matrices", the matrix B). */
 elmfb_status elmfb_copy_bc(elmfb_problem h, double* dst_dev, void* stream);
 
 /* Copy the stored blocks of the FP64 matrix (prec = ELMFB_FP64) or of its low-precision copy
@@ -260,7 +278,8 @@ elmfb_status elmfb_copy_bc(elmfb_problem h, double* dst_dev, void* stream);
  * with the block's points in row-major order of its box, into dst_dev; and the block table
  * into table_host [n_blocks][8] as int64: level, jx, jy, ix0, nx, iy0, ny, element offset.
  * prec | ELMFB_COPY_FOLDED copies the folded M R^{-1} of elmfb_precondition in that precision
- * instead (ELMFB_E_STATE if it was not formed).  Either pointer may be NULL. */
+ * instead (ELMFB_E_STATE if it was not formed).  Either pointer may be NULL.  (The blocks M_j of
+ * Sec. 3 eq. multilevel_domain_decomp, M = sum_j V_j^T M_j W_j.) */
 elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int64_t* table_host,
                                void* stream);
 
@@ -292,14 +311,16 @@ elmfb_status elmfb_gram(elmfb_problem h, int32_t prec, int32_t which, void* stre
  * ms_host = the average duration of one computation (all its kernels), flops_host (may be NULL)
  * = 2 K^2 times the shared points summed over the computed pairs (the useful MFMA work; K is
  * padded to 16 on the matrix cores).  The stored blocks are those of elmfb_gram afterwards.
- * Blocks the host until the timing completes. */
+ * Blocks the host until the timing completes.  (Measurement support for the Gram blocks of the
+ * normal equations of Sec. 3 eq. multilevel_ls.) */
 elmfb_status elmfb_time_gram(elmfb_problem h, int32_t prec, int32_t which, int32_t reps,
                              double* ms_host, double* flops_host, void* stream);
 
 /* Copy the Gram blocks of the last elmfb_gram call (n_pairs x K x K values, FP64 for
  * prec = FP64 else FP32, row index = feature of i) into dst_dev and the pair table
  * [n_pairs][3] (bi, bj, element offset) into pairs_host; *n_pairs_host receives the count.
- * Either pointer may be NULL. */
+ * Either pointer may be NULL.  (G_ij = M_i^T M_j over the shared rows, Sec. 3
+ * eq. multilevel_domain_decomp.) */
 elmfb_status elmfb_copy_gram(elmfb_problem h, void* dst_dev, int64_t* pairs_host,
                              int64_t* n_pairs_host, void* stream);
 
@@ -339,10 +360,11 @@ elmfb_status elmfb_condition_estimate(elmfb_problem h, double* sigma_max_host,
 elmfb_status elmfb_bidiag_sigma(const double* ab_host, int32_t k, double* sigma_max_host,
                                 double* sigma_min_host);
 
-/* u_dev [n_pts] = C(x) (1/L) sum_l sum_j omega_j(x) sum_k coef_q phi_q(x) at arbitrary points
- * pts_dev [n_pts][dim] (Sec. 3 eq. multilevel_solution with the hard-constraint factor). */
-elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,
-                            int64_t n_pts, double* u_dev, void* stream);
+/* u_dev [n_rhs][n_pts] = C(x) (1/L) sum_l sum_j omega_j(x) sum_k coef_q phi_q(x) at arbitrary
+ * points pts_dev [n_pts][dim] for each of the n_rhs (>= 1) coefficient vectors coef_dev
+ * [n_rhs][n_phi] (Sec. 3 eq. multilevel_solution with the hard-constraint factor). */
+elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, int32_t n_rhs,
+                            const double* pts_dev, int64_t n_pts, double* u_dev, void* stream);
 
 /* Time the kernels of the two products of one LSQR/CGLS iteration on `stream` with HIP events:
  * the per-block-point pass of y = M v, the per-chunk pass of x = M^T u, then the row gather that
@@ -369,8 +391,14 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
                                 elmfb_batch* out);
 
 /* offsets_host [n+1][2]: first global row and column of every instance, then the totals;
- * totals_host: summed sizes (n_pairs = 0).  Either may be NULL. */
+ * totals_host: summed sizes (n_pairs = 0).  Either may be NULL.  (The sizes of Sec. 3 per
+ * instance, concatenated.) */
 elmfb_status elmfb_batch_query(elmfb_batch b, int64_t* offsets_host, elmfb_sizes* totals_host);
+
+/* Sizes of every instance: per_instance_host [n] (n_rows, n_phi, nnz, n_blocks, n_block_points,
+ * n_interior as for a single problem; bytes_device = the instance's share of the stored matrix
+ * entries and vectors; n_pairs = n_bc = 0). */
+elmfb_status elmfb_batch_query_instances(elmfb_batch b, elmfb_sizes* per_instance_host);
 
 /* Copy the stored blocks of every instance into dst_dev: prec = ELMFB_FP64 (M) or the batch's
  * store_prec (its rounded copy, until elmfb_batch_precondition replaces it), or either or'd with
@@ -456,6 +484,9 @@ elmfb_status elmfb_batch_from_coords(elmfb_batch b, const double* y_dev, double*
 elmfb_status elmfb_batch_solve(elmfb_batch b, const elmfb_solve_opts* opts, double* coef_dev,
                                elmfb_solve_info* info_host, void* stream);
 
+/* Release everything the batch handle owns (NULL: no-op); the message of its last failing call
+ * (NULL handle: of the calling thread).  Resource management of the handles above; no
+ * computation of the paper. */
 void elmfb_batch_destroy(elmfb_batch b);
 const char* elmfb_batch_last_error(elmfb_batch b);
 
@@ -483,6 +514,7 @@ typedef struct {
  * with elmfb_mlp_set_params. */
 elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_t n_mod,
                               int32_t max_batch, elmfb_mlp* out);
+/* Number of flat parameters (sum over layers of dims[l+1] (dims[l] + 1)). */
 elmfb_status elmfb_mlp_query(elmfb_mlp m, int64_t* n_params_host);
 /* Copy the flat parameters in (also resets the Adam moments and step count) or out. */
 elmfb_status elmfb_mlp_set_params(elmfb_mlp m, const float* params_host);
@@ -500,19 +532,24 @@ elmfb_status elmfb_mlp_forward(elmfb_mlp m, const float* x_dev, const float* f_d
 elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* f_dev,
                                   const float* t_dev, int32_t batch, const elmfb_adam* opt,
                                   double* loss_host, void* stream);
+/* Release the network (NULL: no-op); the message of its last failing call (NULL: of the calling
+ * thread).  Resource management; no computation of the paper. */
 void elmfb_mlp_destroy(elmfb_mlp m);
 const char* elmfb_mlp_last_error(elmfb_mlp m);
 
-/* Release everything the handle owns.  NULL is a no-op. */
 /* Time y = G p on the Gram blocks of the last elmfb_gram(h, prec, 1) call (the operator of
  * ELMFB_NORMAL_CG) with HIP events on `stream`, p = 1, `reps` times each: ms_host[0] = one
  * launch of the per-block pass alone (reads every stored block once), ms_host[1] = both passes.
- * Overwrites the solver's work vectors; blocks the host until the timing completes. */
+ * Overwrites the solver's work vectors; blocks the host until the timing completes.
+ * (Measurement support for CG on the normal equations of Sec. 3 eq. multilevel_ls.) */
 elmfb_status elmfb_time_gram_mv(elmfb_problem h, int32_t reps, double* ms_host, void* stream);
 
+/* Release everything the handle owns (device memory, graphs, streams).  NULL is a no-op.
+ * Resource management; no computation of the paper. */
 void elmfb_destroy(elmfb_problem h);
 
-/* Message of the last failing call on this handle (NULL: of the calling thread). */
+/* Message of the last failing call on this handle (NULL: of the calling thread).  Error
+ * reporting; no computation of the paper. */
 const char* elmfb_last_error(elmfb_problem h);
 
 #ifdef __cplusplus

@@ -615,10 +615,20 @@ elmfb_status elmfb_points(elmfb_problem h, double* xy_dev, void* stream) {
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) {
+elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, int32_t n_rhs, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
   if (!h || !f_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
+  if (n_rhs < 1 || n_rhs > 1024) return fail(h, ELMFB_E_INVALID, "n_rhs must be in 1..1024");
   hipStream_t s = (hipStream_t)stream;
   const Geo& g = h->geo;
+  const int64_t nrt = g.n_rows + g.n_bc;
+  if (n_rhs > 1 && (int64_t)n_rhs * nrt > h->hs_cap) {
+    dfree(h, h->d_hs);
+    h->d_hs = nullptr;
+    h->hs_cap = 0;
+    HIP_OR_FAIL(h, dalloc(h, &h->d_hs, (int64_t)n_rhs * nrt * 8));
+    h->hs_cap = (int64_t)n_rhs * nrt;
+  }
   h->bj_ready = false;   // factors and the folded matrix belong to the previous assembly
   h->folded64 = h->folded_lo = false;
   HIP_OR_FAIL(h, hipMemsetAsync(h->d_flag, 0, 4, s));
@@ -631,9 +641,27 @@ elmfb_status elmfb_assemble(elmfb_problem h, const double* f_dev, void* stream) 
                                       s));
   if (g.n_bc > 0 && g.dim == 2)
     HIP_OR_FAIL(h, launch_bc_assemble_pts(g, h->d_blocks, h->d_W, h->d_b, h->d_bc, h->d_h, s));
+  if (n_rhs > 1) {
+    // every right-hand side: its h_r = f_r/sqrt(N_I), then the constraint values of h (the same
+    // for all of them); d_h keeps the first
+    for (int r = 0; r < n_rhs; ++r) {
+      double* dst = h->d_hs + (int64_t)r * nrt;
+      if (r == 0) {
+        HIP_OR_FAIL(h, hipMemcpyAsync(dst, h->d_h, (size_t)nrt * 8, hipMemcpyDeviceToDevice, s));
+        continue;
+      }
+      HIP_OR_FAIL(h, launch_rhs(g, f_dev + (int64_t)r * g.n_rows, dst, h->d_flag, s));
+      if (g.n_bc > 0)
+        HIP_OR_FAIL(h, hipMemcpyAsync(dst + g.n_rows, h->d_h + g.n_rows, (size_t)g.n_bc * 8,
+                                      hipMemcpyDeviceToDevice, s));
+    }
+  }
   int32_t bad = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(&bad, h->d_flag, 4, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(h, hipStreamSynchronize(s));
+  h->n_rhs = n_rhs;
+  h->ms_assemble =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (bad) {
     h->assembled = false;
     return fail(h, ELMFB_E_NUMERIC, "f holds non-finite values");
@@ -676,8 +704,13 @@ elmfb_status elmfb_rmatvec(elmfb_problem h, const double* u_dev, double* x_dev, 
 elmfb_status elmfb_copy_rhs(elmfb_problem h, double* h_dev, void* stream) {
   if (!h || !h_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "copy_rhs before assemble");
-  HIP_OR_FAIL(h, hipMemcpyAsync(h_dev, h->d_h, (size_t)(h->geo.n_rows + h->geo.n_bc) * 8,
-                                hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  const int64_t nrt = h->geo.n_rows + h->geo.n_bc;
+  if (h->n_rhs > 1)
+    HIP_OR_FAIL(h, hipMemcpyAsync(h_dev, h->d_hs, (size_t)(h->n_rhs * nrt) * 8,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  else
+    HIP_OR_FAIL(h, hipMemcpyAsync(h_dev, h->d_h, (size_t)nrt * 8, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream));
   return ELMFB_OK;
 }
 
@@ -742,12 +775,14 @@ elmfb_status elmfb_copy_blocks(elmfb_problem h, int32_t prec, void* dst_dev, int
 }
 
 
-elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, const double* pts_dev,
-                            int64_t n_pts, double* u_dev, void* stream) {
-  if (!h || n_pts < 0 || (n_pts > 0 && (!coef_dev || !pts_dev || !u_dev)))
+elmfb_status elmfb_evaluate(elmfb_problem h, const double* coef_dev, int32_t n_rhs,
+                            const double* pts_dev, int64_t n_pts, double* u_dev, void* stream) {
+  if (!h || n_pts < 0 || n_rhs < 1 || (n_pts > 0 && (!coef_dev || !pts_dev || !u_dev)))
     return fail(h, ELMFB_E_INVALID, "bad argument");
-  HIP_OR_FAIL(h, launch_evaluate(h->geo, h->d_W, h->d_b, coef_dev, pts_dev, n_pts, u_dev,
-                                 (hipStream_t)stream));
+  for (int r = 0; r < n_rhs; ++r)
+    HIP_OR_FAIL(h, launch_evaluate(h->geo, h->d_W, h->d_b, coef_dev + (int64_t)r * h->geo.n_phi,
+                                   pts_dev, n_pts, u_dev + (int64_t)r * n_pts,
+                                   (hipStream_t)stream));
   return ELMFB_OK;
 }
 

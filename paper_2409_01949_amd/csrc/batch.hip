@@ -482,6 +482,36 @@ elmfb_status elmfb_batch_query(elmfb_batch B, int64_t* offsets_host, elmfb_sizes
     totals_host->n_block_points = B->n_bp;
     totals_host->bytes_device = B->bytes;
     totals_host->n_pairs = 0;
+    totals_host->n_bc = 0;
+    totals_host->n_interior = B->n_rows;
+  }
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_query_instances(elmfb_batch B, elmfb_sizes* out) {
+  if (!B || !out) return bfail(B, ELMFB_E_INVALID, "NULL argument");
+  for (int i = 0; i < B->n; ++i) {
+    elmfb_sizes& z = out[i];
+    z = elmfb_sizes{};
+    z.n_rows = B->nrows[i];
+    z.n_phi = B->nphis[i];
+    z.n_interior = B->nrows[i];
+  }
+  // stored entries, blocks and block points per instance from the block table
+  int64_t stored = 0;
+  for (const DevBlock& b : B->blocks) {
+    elmfb_sizes& z = out[b.inst];
+    z.nnz += (int64_t)b.n * B->geos[b.inst].K;
+    z.n_blocks += 1;
+    z.n_block_points += b.n;
+    stored += (int64_t)b.ld * B->geos[b.inst].K;
+  }
+  // the instance's share of the device footprint, by its share of the stored entries
+  for (int i = 0; i < B->n; ++i) {
+    int64_t mine = 0;
+    for (int64_t j = B->insts[i].b0; j < B->insts[i].b1; ++j)
+      mine += (int64_t)B->blocks[j].ld * B->geos[i].K;
+    out[i].bytes_device = stored > 0 ? (int64_t)((double)B->bytes * mine / stored) : 0;
   }
   return ELMFB_OK;
 }

@@ -114,6 +114,10 @@ struct elmfb_problem_s {
   int64_t n_ftiles = 0;
 
   bool assembled = false;
+  int n_rhs = 1;                // right-hand sides of the last assembly
+  double* d_hs = nullptr;       // [n_rhs][n_rows + n_bc] when n_rhs > 1
+  int64_t hs_cap = 0;           // doubles held by d_hs
+  double ms_assemble = 0.0;     // host wall time of the last assembly
   int persist_lds_mode = -1;    // one-workgroup LSQR: 1 matrix in LDS, 0 vectors only, -1 undecided
   double anorm_f = -1.0;        // exact Frobenius norm of the stored matrix (lazy)
   hipStream_t stream = nullptr; // internal stream for captured solves

@@ -703,8 +703,9 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
   return ELMFB_OK;
 }
 
-elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
-                         elmfb_solve_info* info, void* stream) {
+// One right-hand side: the one held in d_h.
+static elmfb_status solve_one(elmfb_problem h, const elmfb_solve_opts* opts, double* coef_dev,
+                              elmfb_solve_info* info, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
   if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
@@ -928,6 +929,41 @@ elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts, double* 
     info->rel_l2 = st.rel_l2;
     info->ms_solve =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return ELMFB_OK;
+}
+
+extern "C" elmfb_status elmfb_solve(elmfb_problem h, const elmfb_solve_opts* opts,
+                                    double* coef_dev, elmfb_solve_info* info, void* stream) {
+  if (!h || !opts || !coef_dev) return fail(h, ELMFB_E_INVALID, "NULL argument");
+  if (!h->assembled) return fail(h, ELMFB_E_STATE, "solve before assemble");
+  const int R = opts->n_rhs > 1 ? opts->n_rhs : 1;
+  if (R > h->n_rhs)
+    return fail(h, ELMFB_E_INVALID, "n_rhs exceeds the right-hand sides of the last assembly");
+  const Geo& g = h->geo;
+  const int64_t nrt = g.n_rows + g.n_bc;
+  for (int r = 0; r < R; ++r) {
+    // the r-th right-hand side into d_h, ordered before the solve on the caller's stream
+    if (h->n_rhs > 1)
+      HIP_OR_FAIL(h, hipMemcpyAsync(h->d_h, h->d_hs + (int64_t)r * nrt, (size_t)nrt * 8,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    elmfb_solve_opts o = *opts;
+    o.n_rhs = 1;
+    if (o.x0_dev) o.x0_dev += (int64_t)r * g.n_phi;
+    if (o.n_check > 0) o.check_ref_dev += (int64_t)r * o.n_check;
+    elmfb_solve_info* inf = info ? info + r : nullptr;
+    const elmfb_status e = solve_one(h, &o, coef_dev + (int64_t)r * g.n_phi, inf, stream);
+    if (e != ELMFB_OK) return e;
+    if (inf) {
+      inf->ms_assemble = h->ms_assemble;
+      inf->acond = -1.0;
+      if (opts->estimate_cond && h->hist_k > 0) {
+        double smax = 0.0, smin = 0.0;
+        int32_t k = 0;
+        if (elmfb_condition_estimate(h, &smax, &smin, &k) == ELMFB_OK && smin > 0.0)
+          inf->acond = smax / smin;
+      }
+    }
   }
   return ELMFB_OK;
 }

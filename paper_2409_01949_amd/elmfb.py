@@ -91,6 +91,8 @@ class SolveOpts(ctypes.Structure):
         ("check_ref_dev", ctypes.c_void_p),
         ("n_check", ctypes.c_int64),
         ("target_rel_l2", ctypes.c_double),
+        ("n_rhs", ctypes.c_int32),
+        ("estimate_cond", ctypes.c_int32),
     ]
 
 
@@ -105,6 +107,8 @@ class SolveInfo(ctypes.Structure):
         ("xnorm", ctypes.c_double),
         ("rel_l2", ctypes.c_double),
         ("ms_solve", ctypes.c_double),
+        ("acond", ctypes.c_double),
+        ("ms_assemble", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -143,7 +147,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_define_problem": (i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]),
         "elmfb_query": (i32, [P, ctypes.POINTER(Sizes)]),
         "elmfb_points": (i32, [P, P, P]),
-        "elmfb_assemble": (i32, [P, P, P]),
+        "elmfb_assemble": (i32, [P, P, i32, P]),
         "elmfb_matvec": (i32, [P, P, P, P]),
         "elmfb_rmatvec": (i32, [P, P, P, P]),
         "elmfb_copy_rhs": (i32, [P, P, P]),
@@ -153,7 +157,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_copy_gram": (i32, [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64), P]),
         "elmfb_precondition": (i32, [P, dbl, ctypes.POINTER(i32), P]),
         "elmfb_solve": (i32, [P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P]),
-        "elmfb_evaluate": (i32, [P, P, P, i64, P, P]),
+        "elmfb_evaluate": (i32, [P, P, i32, P, i64, P, P]),
         "elmfb_condition_estimate": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                            ctypes.POINTER(i32)]),
         "elmfb_bidiag_sigma": (i32, [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
@@ -162,6 +166,7 @@ def load_library(path: Optional[str] = None):
         "elmfb_time_gram": (i32, [P, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]),
         "elmfb_define_batch": (i32, [ctypes.POINTER(ProblemDesc), i32, i32, ctypes.POINTER(P)]),
         "elmfb_batch_query": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(Sizes)]),
+        "elmfb_batch_query_instances": (i32, [P, ctypes.POINTER(Sizes)]),
         "elmfb_batch_assemble": (i32, [P, P, P]),
         "elmfb_batch_copy_blocks": (i32, [P, i32, P, ctypes.POINTER(i64), P]),
         "elmfb_batch_matvec": (i32, [P, P, P, P]),
@@ -327,8 +332,12 @@ class Problem:
     def points(self, xy, stream=None):
         _check(_lib.elmfb_points(self.h, _ptr(xy), _stream(stream)), self.h)
 
-    def assemble(self, f, stream=None):
-        _check(_lib.elmfb_assemble(self.h, _ptr(f), _stream(stream)), self.h)
+    def assemble(self, f, stream=None, n_rhs=None):
+        """M and the right-hand sides of f [n_rhs, n_rows] (n_rhs from f's size by default)."""
+        if n_rhs is None:
+            n_rhs = max(1, int(f.numel()) // int(self.sizes["n_rows"]))
+        _check(_lib.elmfb_assemble(self.h, _ptr(f), int(n_rhs), _stream(stream)), self.h)
+        self.n_rhs = int(n_rhs)
 
     def matvec(self, v, y, stream=None):
         _check(_lib.elmfb_matvec(self.h, _ptr(v), _ptr(y), _stream(stream)), self.h)
@@ -380,7 +389,10 @@ class Problem:
 
     def solve(self, coef, method="lsqr", iter_lim=15000, atol=1e-8, btol=1e-8, check_every=50,
               use_graph=True, x0=None, check_pts=None, check_ref=None, target_rel_l2=0.0,
-              precond=False, inner_iters=100, outer_lim=10, stream=None):
+              precond=False, inner_iters=100, outer_lim=10, stream=None, n_rhs=1,
+              estimate_cond=False):
+        """Solve for n_rhs assembled right-hand sides into coef [n_rhs, n_phi]; returns the
+        info dict (a list of them when n_rhs > 1)."""
         o = SolveOpts()
         o.method = _METHOD[method] if isinstance(method, str) else int(method)
         o.iter_lim = int(iter_lim)
@@ -394,16 +406,22 @@ class Problem:
         o.x0_dev = _ptr(x0)
         o.check_pts_dev = _ptr(check_pts)
         o.check_ref_dev = _ptr(check_ref)
-        o.n_check = int(check_ref.numel()) if check_ref is not None else 0
+        o.n_check = int(check_pts.shape[0]) if check_ref is not None else 0
         o.target_rel_l2 = float(target_rel_l2)
-        info = SolveInfo()
-        _check(_lib.elmfb_solve(self.h, ctypes.byref(o), _ptr(coef), ctypes.byref(info),
-                                _stream(stream)), self.h)
-        return info.as_dict()
+        o.n_rhs = int(n_rhs)
+        o.estimate_cond = 1 if estimate_cond else 0
+        infos = (SolveInfo * max(1, int(n_rhs)))()
+        _check(_lib.elmfb_solve(self.h, ctypes.byref(o), _ptr(coef), infos, _stream(stream)),
+               self.h)
+        out = [i.as_dict() for i in infos]
+        return out[0] if n_rhs <= 1 else out
 
-    def evaluate(self, coef, pts, u, stream=None):
+    def evaluate(self, coef, pts, u, stream=None, n_rhs=None):
+        """u [n_rhs, n_pts] at pts [n_pts, dim] for coef [n_rhs, n_phi]."""
         n = pts.shape[0]
-        _check(_lib.elmfb_evaluate(self.h, _ptr(coef), _ptr(pts), int(n), _ptr(u),
+        if n_rhs is None:
+            n_rhs = max(1, int(coef.numel()) // int(self.sizes["n_phi"]))
+        _check(_lib.elmfb_evaluate(self.h, _ptr(coef), int(n_rhs), _ptr(pts), int(n), _ptr(u),
                                    _stream(stream)), self.h)
 
     def condition_estimate(self):
@@ -482,6 +500,12 @@ class Batch:
 
     def assemble(self, f, stream=None):
         self._check(_lib.elmfb_batch_assemble(self.h, _ptr(f), _stream(stream)))
+
+    def query_instances(self):
+        """Per-instance sizes: a list of dicts like Problem.query()."""
+        arr = (Sizes * self.n)()
+        self._check(_lib.elmfb_batch_query_instances(self.h, arr))
+        return [{n: getattr(z, n) for n, _ in Sizes._fields_} for z in arr]
 
     def copy_blocks(self, dst=None, prec="fp64", folded=False, stream=None):
         """Block table [n_blocks, 8] (instance, level, ix0, nx, iy0, ny, K, element offset);
