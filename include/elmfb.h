@@ -451,6 +451,34 @@ elmfb_status elmfb_batch_autotune(elmfb_batch b, int32_t prec, int32_t reps, dou
 elmfb_status elmfb_batch_time_kernels(elmfb_batch b, int32_t prec, int32_t reps, double* ms_host,
                                       void* stream);
 
+/* Launch shapes of the three matrix passes of a batched Krylov step (the batching of the
+ * method's products, Sec. 3 eq. multilevel_domain_decomp, per instance and right-hand side). */
+typedef struct {
+  int32_t rmvb_tile;       /* points per LDS stage of the M^T U pass: 16, 32, 64 (not FP64)   */
+  int32_t mvb_ahead;       /* feature entries each lane loads ahead in the M V pass: 4, 8, 16 */
+  int32_t gather_rows;     /* rows per thread of the row gather completing M V: 1 or 2       */
+  int32_t from_cache;      /* set by elmfb_batch_tune: 1 = taken from the cache, nothing timed */
+  double ms_rmvb[3];       /* ms per launch of each M^T U tile (16, 32, 64); -1 not timed     */
+  double ms_mvb[3];        /* of each M V look-ahead (4, 8, 16)                                */
+  double ms_gather[2];     /* of each gather shape (1, 2 rows per thread)                      */
+} elmfb_batch_shape;
+
+/* Time every candidate shape of the three matrix passes on the assembled matrix copy of
+ * precision `prec` (ELMFB_FP64 or the batch's store_prec), `reps` launches each (1..1000)
+ * after a warm-up launch, keep the fastest of each for later solves of that precision and
+ * write them with the timings to out (may be NULL).  The choice is also cached for the process
+ * under (operator, precision, largest K rounded up to a multiple of 16, stored entries rounded
+ * down to a power of two, right-hand sides); with use_cache = 1 a batch of a cached class takes
+ * the cached shapes without timing (out->from_cache = 1).  Shapes change only launch
+ * configurations: M^T U tiles and gather shapes change summation order within rounding, the
+ * M V look-ahead does not.  Overwrites the solver's work vectors; synchronises. */
+elmfb_status elmfb_batch_tune(elmfb_batch b, int32_t prec, int32_t reps, int32_t use_cache,
+                              elmfb_batch_shape* out, void* stream);
+
+/* Set the three shapes for matrix precision `prec` by hand (the gather shape is shared by all
+ * precisions); ELMFB_E_INVALID for a shape outside the candidates. */
+elmfb_status elmfb_batch_set_shape(elmfb_batch b, int32_t prec, const elmfb_batch_shape* shape);
+
 /* Set the point tile of the batched M^T U pass for matrix precision `prec` by hand (16, 32, or
  * 64 except for ELMFB_FP64), as elmfb_batch_autotune would keep it. */
 elmfb_status elmfb_batch_set_tile(elmfb_batch b, int32_t prec, int32_t tile);

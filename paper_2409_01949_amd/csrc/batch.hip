@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,8 @@ struct elmfb_batch_s {
   int64_t n_rows = 0, n_phi = 0, nnz = 0, n_bp = 0, n_tab = 0, n_fac = 0, n_gsq = 0, bytes = 0;
   int64_t n_store = 0;               // stored elements per matrix copy, row padding included
   int tp[4] = {32, 32, 32, 32};      // points per LDS stage of A^T U, per matrix precision
+  int fa[4] = {8, 8, 8, 8};          // features loaded ahead per lane in A V, per precision
+  int rpt = 1;                       // rows per thread of the row gather
   bool tuned[4] = {false, false, false, false};
   bool lo_unsafe = false;            // FP16 fold over an identity-fallback block: not used
 
@@ -208,11 +211,11 @@ hipError_t bt_iteration(elmfb_batch B, int prec, bool bj, hipStream_t s) {
   const void* A = matrix_of(B, prec, bj);
   hipError_t e;
   if ((e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, B->d_state, B->d_tpart,
-                         s)))
+                         s, B->fa[prec_index(prec)])))
     return e;
   if ((e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                             (int64_t)B->rtiles.size(), B->d_tpart, ROW_LSQR_U, R, B->d_u, nullptr,
-                            B->d_state, B->d_red_r, s)))
+                            B->d_state, B->d_red_r, s, B->rpt)))
     return e;
   if ((e = launch_bt_lsqr_beta(B->d_state, B->d_insts, n, R, B->d_red_r, s))) return e;
   if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
@@ -256,14 +259,14 @@ hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s,
   hipError_t e;
   if (c) {
     if ((e = launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(),
-                           matrix_of(B, ELMFB_FP64, bj), c, R, nullptr, B->d_tpart, s)))
+                           matrix_of(B, ELMFB_FP64, bj), c, R, nullptr, B->d_tpart, s, B->fa[0])))
       return e;
   } else if ((e = hipMemsetAsync(B->d_tpart, 0, (size_t)(B->n_bp * R * 8), s))) {
     return e;
   }
   return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                           (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u,
-                          b ? b : B->d_h, nullptr, B->d_red_r, s);
+                          b ? b : B->d_h, nullptr, B->d_red_r, s, B->rpt);
 }
 
 // Run LSQR steps until every pair has stopped: replays of a captured graph of `chunk` steps (or
@@ -279,8 +282,10 @@ elmfb_status bt_run(elmfb_batch B, int prec, bool bj, int chunk, bool use_graph,
       // graphs of at most kGraphMaxSteps steps, replayed until `chunk` steps are enqueued
       for (int left = chunk; left > 0;) {
         const int m = left > kGraphMaxSteps ? kGraphMaxSteps : left;
-        const int64_t key =
-            ((int64_t)m << 16) | (prec << 8) | (bj ? 128 : 0) | B->tp[prec_index(prec)];
+        // the captured kernels depend on the tuned shapes as well
+        const int64_t key = ((int64_t)m << 24) | ((int64_t)B->rpt << 20) |
+                            ((int64_t)B->fa[prec_index(prec)] << 15) | (prec << 8) |
+                            (bj ? 128 : 0) | B->tp[prec_index(prec)];
         auto it = B->graphs.find(key);
         hipGraphExec_t exec = nullptr;
         if (it != B->graphs.end()) {
@@ -593,10 +598,10 @@ elmfb_status elmfb_batch_matvec(elmfb_batch B, const double* v_dev, double* y_de
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, v_dev, B->d_w, 1, 1, s));
   BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(), B->d_A,
-                        B->d_w, R, nullptr, B->d_tpart, s));
+                        B->d_w, R, nullptr, B->d_tpart, s, B->fa[0]));
   BHIP(B, launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                            (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE, R, B->d_u, nullptr,
-                           nullptr, B->d_red_r, s));
+                           nullptr, B->d_red_r, s, B->rpt));
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nrows, B->n, R, B->n_rows, B->d_u, y_dev, 0, 0, s));
   return ELMFB_OK;
 }
@@ -734,12 +739,13 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   for (int i = 0; i < 4; ++i) BHIP(B, hipEventCreate(&ev[i]));
   hipError_t e = hipEventRecord(ev[0], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart, s);
+    e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart, s,
+                      B->fa[prec_index(prec)]);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                          (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_c, nullptr,
-                         nullptr, B->d_red_r, s);
+                         nullptr, B->d_red_r, s, B->rpt);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
@@ -751,6 +757,139 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   for (int i = 0; i < 4; ++i) hipEventDestroy(ev[i]);
   BHIP(B, e);
   for (int i = 0; i < 3; ++i) ms_host[i] = (double)t[i] / reps;
+  return ELMFB_OK;
+}
+
+namespace {
+
+// Shapes chosen by elmfb_batch_tune, kept for the process and keyed by (operator, precision,
+// largest K in 16s, stored entries in powers of two, right-hand sides): a later batch of the same
+// class takes them without timing.
+struct ShapeKey {
+  int op, prec, kclass, sclass, rhs;
+  bool operator<(const ShapeKey& o) const {
+    if (op != o.op) return op < o.op;
+    if (prec != o.prec) return prec < o.prec;
+    if (kclass != o.kclass) return kclass < o.kclass;
+    if (sclass != o.sclass) return sclass < o.sclass;
+    return rhs < o.rhs;
+  }
+};
+std::mutex g_shape_mu;
+std::map<ShapeKey, elmfb_batch_shape> g_shapes;
+
+ShapeKey shape_key(elmfb_batch B, int prec) {
+  int kmax = 0;
+  for (const Geo& g : B->geos) kmax = std::max(kmax, (int)g.K);
+  int sc = 0;
+  for (int64_t n = B->nnz; n > 1; n >>= 1) ++sc;
+  return ShapeKey{B->geos.empty() ? 0 : B->geos[0].op, prec, (kmax + 15) / 16, sc, B->R};
+}
+
+bool valid_shape(int prec, const elmfb_batch_shape& sh) {
+  const bool tile = sh.rmvb_tile == 16 || sh.rmvb_tile == 32 ||
+                    (sh.rmvb_tile == 64 && prec != ELMFB_FP64);
+  return tile && (sh.mvb_ahead == 4 || sh.mvb_ahead == 8 || sh.mvb_ahead == 16) &&
+         (sh.gather_rows == 1 || sh.gather_rows == 2);
+}
+
+}  // namespace
+
+elmfb_status elmfb_batch_tune(elmfb_batch B, int32_t prec, int32_t reps, int32_t use_cache,
+                              elmfb_batch_shape* out, void* stream) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (!B->assembled) return bfail(B, ELMFB_E_STATE, "tune before assemble");
+  if (prec != ELMFB_FP64 && prec != B->lo_prec)
+    return bfail(B, ELMFB_E_INVALID, "no stored matrix copy of that precision");
+  if (reps < 1 || reps > 1000) return bfail(B, ELMFB_E_INVALID, "reps must be in 1..1000");
+  const ShapeKey key = shape_key(B, prec);
+  elmfb_batch_shape sh{};
+  for (int i = 0; i < 3; ++i) sh.ms_rmvb[i] = sh.ms_mvb[i] = -1.0;
+  sh.ms_gather[0] = sh.ms_gather[1] = -1.0;
+  if (use_cache) {
+    std::lock_guard<std::mutex> lock(g_shape_mu);
+    auto it = g_shapes.find(key);
+    if (it != g_shapes.end()) {
+      sh = it->second;
+      sh.from_cache = 1;
+    }
+  }
+  if (!sh.from_cache) {
+    hipStream_t s = (hipStream_t)stream;
+    const int R = B->R;
+    const int64_t nb = (int64_t)B->blocks.size();
+    const void* A = matrix_of(B, prec, false);
+    std::vector<double> ones((size_t)std::max(B->n_rows, B->n_phi) * R, 1.0);
+    BHIP(B, hipMemcpyAsync(B->d_v, ones.data(), (size_t)B->n_phi * R * 8, hipMemcpyHostToDevice, s));
+    BHIP(B, hipMemcpyAsync(B->d_u, ones.data(), (size_t)B->n_rows * R * 8, hipMemcpyHostToDevice, s));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    BHIP(B, hipEventCreate(&t0));
+    BHIP(B, hipEventCreate(&t1));
+    hipError_t e = hipSuccess;
+    // one warm-up launch, then `reps` timed launches of a candidate
+    auto timed = [&](auto&& launch) -> double {
+      if (e == hipSuccess) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(t0, s);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(t1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float f = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
+      return e == hipSuccess ? (double)f / reps : -1.0;
+    };
+    const int tiles[3] = {16, 32, 64}, aheads[3] = {4, 8, 16};
+    double best = 1e300;
+    for (int c = 0; c < 3; ++c) {
+      if (prec == ELMFB_FP64 && tiles[c] == 64) continue;
+      sh.ms_rmvb[c] = timed([&] {
+        return launch_bt_rmvb(prec, tiles[c], B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u,
+                              R, nullptr, COL_STORE, B->d_w, B->d_red_c, s);
+      });
+      if (sh.ms_rmvb[c] >= 0 && sh.ms_rmvb[c] < best) { best = sh.ms_rmvb[c]; sh.rmvb_tile = tiles[c]; }
+    }
+    best = 1e300;
+    for (int c = 0; c < 3; ++c) {
+      sh.ms_mvb[c] = timed([&] {
+        return launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart,
+                             s, aheads[c]);
+      });
+      if (sh.ms_mvb[c] >= 0 && sh.ms_mvb[c] < best) { best = sh.ms_mvb[c]; sh.mvb_ahead = aheads[c]; }
+    }
+    best = 1e300;
+    for (int c = 0; c < 2; ++c) {
+      sh.ms_gather[c] = timed([&] {
+        return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+                                (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_c,
+                                nullptr, nullptr, B->d_red_r, s, c + 1);
+      });
+      if (sh.ms_gather[c] >= 0 && sh.ms_gather[c] < best) { best = sh.ms_gather[c]; sh.gather_rows = c + 1; }
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    BHIP(B, e);
+    std::lock_guard<std::mutex> lock(g_shape_mu);
+    g_shapes[key] = sh;
+  }
+  const int pi = prec_index(prec);
+  B->tp[pi] = sh.rmvb_tile;
+  B->fa[pi] = sh.mvb_ahead;
+  B->rpt = sh.gather_rows;
+  B->tuned[pi] = true;
+  if (out) *out = sh;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_set_shape(elmfb_batch B, int32_t prec, const elmfb_batch_shape* shape) {
+  if (!B || !shape) return bfail(B, ELMFB_E_INVALID, "NULL argument");
+  if (prec != ELMFB_FP64 && prec != ELMFB_FP32 && prec != ELMFB_BF16 && prec != ELMFB_FP16)
+    return bfail(B, ELMFB_E_INVALID, "bad precision");
+  if (!valid_shape(prec, *shape))
+    return bfail(B, ELMFB_E_INVALID,
+                 "tile 16/32/64 (not 64 in FP64), ahead 4/8/16 and gather rows 1/2 required");
+  const int pi = prec_index(prec);
+  B->tp[pi] = shape->rmvb_tile;
+  B->fa[pi] = shape->mvb_ahead;
+  B->rpt = shape->gather_rows;
   return ELMFB_OK;
 }
 

@@ -162,9 +162,10 @@ __device__ __forceinline__ double pair_scale(const SolveState* st, int idx, bool
   return use_v ? s.sv : s.su;
 }
 
-// Sum 8 per-thread values over the 256 threads: transposing butterfly in each wave, then the
-// four wave sums in fixed order.  Value j is returned in thread j (j < 8); every thread must
-// call it.
+// Sum 8 per-thread values over the NW waves of a workgroup: transposing butterfly in each wave,
+// then the NW wave sums in fixed order.  Value j is returned in thread j (j < 8); every thread
+// must call it.
+template <int NW = 4>
 __device__ __forceinline__ double block_sum8(const double a[kMaxRhs], double (*sh)[kMaxRhs]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int f;
@@ -174,7 +175,9 @@ __device__ __forceinline__ double block_sum8(const double a[kMaxRhs], double (*s
   double r = 0.0;
   if (threadIdx.x < kMaxRhs) {
     const int j = threadIdx.x;
-    r = (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
+    if constexpr (NW == 4) r = (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
+    else if constexpr (NW == 2) r = sh[0][j] + sh[1][j];
+    else r = sh[0][j];
   }
   __syncthreads();
   return r;
@@ -247,9 +250,10 @@ __device__ __forceinline__ void bj_apply_lds(const double* __restrict__ rc, int 
 constexpr int kFacStage = 2048;   // doubles of a packed factor staged per round in A.v
 
 // Partial rows of Y = A V: per block point, the block's contribution for every right-hand side,
-// tpart[(p_off + p) * R + rhs] (V scaled per pair by 1/alpha, or 0 once the pair is done).  The waves take 64-point runs of the block in
-// turn; each lane loads 8 feature entries ahead of their products.
-template <int PREC>
+// tpart[(p_off + p) * R + rhs] (V scaled per pair by 1/alpha, or 0 once the pair is done).  The
+// waves take 64-point runs of the block in turn; each lane loads FA feature entries ahead of
+// their products (the autotuner's choice; the sum order over features does not depend on it).
+template <int PREC, int FA>
 __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
                                                 const DevBlock* __restrict__ blocks,
                                                 const void* __restrict__ A,
@@ -274,12 +278,12 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
       for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
       const int64_t base = B.a_off + p;
       int k = 0;
-      for (; k + 8 <= K; k += 8) {
-        double a[8];
+      for (; k + FA <= K; k += FA) {
+        double a[FA];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] = load_entry<PREC>(A, base + (int64_t)(k + q) * ld);
+        for (int q = 0; q < FA; ++q) a[q] = load_entry<PREC>(A, base + (int64_t)(k + q) * ld);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < FA; ++q)
 #pragma unroll
           for (int j = 0; j < kMaxRhs; ++j) acc[j] += a[q] * cs[k + q][j];
       }
@@ -293,6 +297,10 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
   }
 }
 
+// One workgroup per row tile of 256 rows, RPT rows per thread (the autotuner's choice: 256/RPT
+// threads); the rows' own sums do not depend on RPT, the per-tile norm partial adds its rows in
+// another order when RPT changes.
+template <int RPT>
 __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
                                                    const InstInfo* __restrict__ insts,
                                                    const DevBlock* __restrict__ blocks,
@@ -303,15 +311,20 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
                                                    const double* __restrict__ bvec,
                                                    const SolveState* __restrict__ st,
                                                    double* __restrict__ red) {
+  constexpr int NT = 256 / RPT;
   __shared__ double sh[4][kMaxRhs];
   const RowTile t = rtiles[blockIdx.x];
   const Geo& g = geos[t.inst];
   const InstInfo I = insts[t.inst];
-  const int64_t r = t.r0 + threadIdx.x;
-  const bool valid = r < I.row_off + g.n_rows;
-  double y[kMaxRhs], acc[kMaxRhs];
+  double acc[kMaxRhs];
 #pragma unroll
-  for (int j = 0; j < kMaxRhs; ++j) { y[j] = 0.0; acc[j] = 0.0; }
+  for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
+  for (int ri = 0; ri < RPT; ++ri) {
+  const int64_t r = t.r0 + threadIdx.x + ri * NT;
+  const bool valid = r < I.row_off + g.n_rows;
+  double y[kMaxRhs];
+#pragma unroll
+  for (int j = 0; j < kMaxRhs; ++j) y[j] = 0.0;
   if (valid) {
     const int64_t rl = r - I.row_off;
     const int ix = (int)(rl / g.ny), iy = (int)(rl - (int64_t)ix * g.ny);
@@ -365,7 +378,7 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
           const SolveState& s = st[t.inst * R + j];
           const double u = s.done ? 0.0 : y[j] - s.alpha * s.su * o[j];
           o[j] = u;
-          acc[j] = u * u;
+          acc[j] += u * u;
         }
       }
     } else if (mode == ROW_RESID) {
@@ -375,7 +388,7 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
         if (j < R) {
           const double u = bv[j] - y[j];
           o[j] = u;
-          acc[j] = u * u;
+          acc[j] += u * u;
         }
       }
     } else {
@@ -383,13 +396,14 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
       for (int j = 0; j < kMaxRhs; ++j) {
         if (j < R) {
           o[j] = y[j];
-          acc[j] = y[j] * y[j];
+          acc[j] += y[j] * y[j];
         }
       }
     }
   }
+  }   // rows of this thread
   if (mode != ROW_STORE) {
-    const double sum = block_sum8(acc, sh);
+    const double sum = block_sum8<NT / 64>(acc, sh);
     if (threadIdx.x < kMaxRhs) red[(int64_t)blockIdx.x * kMaxRhs + threadIdx.x] = sum;
   }
 }
@@ -869,28 +883,44 @@ hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* 
   return hipGetLastError();
 }
 
+template <int FA>
+static void mvb_fa(int prec, dim3 grid, const Geo* geos, const DevBlock* blocks, const void* A,
+                   const double* v, int R, const SolveState* st, double* tpart, hipStream_t s) {
+  const dim3 blk(256);
+  if (prec == ELMFB_FP32)
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP32, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+  else if (prec == ELMFB_BF16)
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_BF16, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+  else if (prec == ELMFB_FP16)
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP16, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+  else
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP64, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+}
+
 hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
                          const void* A, const double* v, int R, const SolveState* st,
-                         double* tpart, hipStream_t s) {
+                         double* tpart, hipStream_t s, int fa) {
   if (n_blocks == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_blocks), blk(256);
-  if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP32>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
-  else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL(k_bt_mvb<ELMFB_BF16>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
-  else if (prec == ELMFB_FP16)
-    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP16>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
-  else
-    hipLaunchKernelGGL(k_bt_mvb<ELMFB_FP64>, grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+  const dim3 grid((unsigned)n_blocks);
+  if (fa == 4) mvb_fa<4>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
+  else if (fa == 8) mvb_fa<8>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
+  else if (fa == 16) mvb_fa<16>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
                             const int32_t* cov, const RowTile* rt, int64_t n_rt,
                             const double* tpart, int mode, int R, double* out, const double* bvec,
-                            const SolveState* st, double* red, hipStream_t s) {
-  hipLaunchKernelGGL(k_bt_gather, dim3((unsigned)n_rt), dim3(256), 0, s, geos, insts, blocks, cov,
-                     rt, tpart, mode, R, out, bvec, st, red);
+                            const SolveState* st, double* red, hipStream_t s, int rpt) {
+  if (rpt == 1)
+    hipLaunchKernelGGL(k_bt_gather<1>, dim3((unsigned)n_rt), dim3(256), 0, s, geos, insts, blocks,
+                       cov, rt, tpart, mode, R, out, bvec, st, red);
+  else if (rpt == 2)
+    hipLaunchKernelGGL(k_bt_gather<2>, dim3((unsigned)n_rt), dim3(128), 0, s, geos, insts, blocks,
+                       cov, rt, tpart, mode, R, out, bvec, st, red);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -164,11 +164,11 @@ hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* 
                          int R, const double* f, double* h, int32_t* bad, hipStream_t s);
 hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
                          const void* A, const double* v, int R, const SolveState* st,
-                         double* tpart, hipStream_t s);
+                         double* tpart, hipStream_t s, int fa = 8);
 hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
                             const int32_t* cov, const RowTile* rt, int64_t n_rt,
                             const double* tpart, int mode, int R, double* out, const double* bvec,
-                            const SolveState* st, double* red, hipStream_t s);
+                            const SolveState* st, double* red, hipStream_t s, int rpt = 1);
 // tp: points per LDS stage, one of kBtTileChoices (64 not for FP64)
 hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* insts,
                           const DevBlock* blocks, int64_t n_blocks, const void* A,

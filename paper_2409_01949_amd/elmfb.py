@@ -115,6 +115,23 @@ class SolveInfo(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class BatchShape(ctypes.Structure):
+    _fields_ = [("rmvb_tile", ctypes.c_int32), ("mvb_ahead", ctypes.c_int32),
+                ("gather_rows", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ms_rmvb", ctypes.c_double * 3), ("ms_mvb", ctypes.c_double * 3),
+                ("ms_gather", ctypes.c_double * 2)]
+
+    def as_dict(self):
+        return {"rmvb_tile": self.rmvb_tile, "mvb_ahead": self.mvb_ahead,
+                "gather_rows": self.gather_rows, "from_cache": bool(self.from_cache),
+                "ms_rmvb": {t: self.ms_rmvb[i] for i, t in enumerate((16, 32, 64))
+                            if self.ms_rmvb[i] >= 0},
+                "ms_mvb": {a: self.ms_mvb[i] for i, a in enumerate((4, 8, 16))
+                           if self.ms_mvb[i] >= 0},
+                "ms_gather": {r: self.ms_gather[i] for i, r in enumerate((1, 2))
+                              if self.ms_gather[i] >= 0}}
+
+
 class Adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double)]
@@ -175,6 +192,8 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_autotune": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i32), P]),
         "elmfb_batch_set_tile": (i32, [P, i32, i32]),
+        "elmfb_batch_tune": (i32, [P, i32, i32, i32, ctypes.POINTER(BatchShape), P]),
+        "elmfb_batch_set_shape": (i32, [P, i32, ctypes.POINTER(BatchShape)]),
         "elmfb_batch_time_kernels": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double), P]),
         "elmfb_batch_set_coords": (i32, [P, i32]),
         "elmfb_batch_from_coords": (i32, [P, P, P, P]),
@@ -550,6 +569,19 @@ class Batch:
 
     def set_tile(self, prec, tile):
         self._check(_lib.elmfb_batch_set_tile(self.h, _PREC[prec], int(tile)))
+
+    def tune(self, prec, reps=3, use_cache=True, stream=None):
+        """Time the shapes of the M^T U, M V and gather passes and keep the fastest (or take
+        them from the process's cache); returns the shapes and timings as a dict."""
+        sh = BatchShape()
+        self._check(_lib.elmfb_batch_tune(self.h, _PREC[prec], int(reps), 1 if use_cache else 0,
+                                          ctypes.byref(sh), _stream(stream)))
+        return sh.as_dict()
+
+    def set_shape(self, prec, rmvb_tile=32, mvb_ahead=8, gather_rows=1):
+        sh = BatchShape()
+        sh.rmvb_tile, sh.mvb_ahead, sh.gather_rows = int(rmvb_tile), int(mvb_ahead), int(gather_rows)
+        self._check(_lib.elmfb_batch_set_shape(self.h, _PREC[prec], ctypes.byref(sh)))
 
     def time_kernels(self, prec, reps=10, stream=None):
         """Average ms per launch of the batched M V pass, the row gather and the M^T U pass."""

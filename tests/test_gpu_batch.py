@@ -407,3 +407,40 @@ def test_batch_warm_start(batch32):
             if c["istop"] == 1:
                 assert w["istop"] == 1 and w["iters"] == 0 and w["outer_iters"] == 0
                 assert r <= btol * (1 + 1e-2)
+
+
+@pytest.mark.parametrize("ahead,rows", [(4, 1), (16, 2), (8, 2)])
+def test_batch_shapes_products_and_iterates(batch, ahead, rows):
+    """Every launch shape the tuner can choose for the M V look-ahead and the row gather: products
+    per instance and right-hand side to 1e-12 and 5 LSQR steps to 1e-9 against the oracle (the
+    shape is restored afterwards)."""
+    B, oracle = batch
+    torch = torch_mod()
+    B.set_shape("fp64", rmvb_tile=32, mvb_ahead=ahead, gather_rows=rows)
+    try:
+        test_batch_products(batch)
+        test_batch_lsqr_iterates(batch)
+    finally:
+        B.set_shape("fp64", rmvb_tile=32, mvb_ahead=8, gather_rows=1)
+
+
+def test_batch_tuner_and_its_cache(batch32):
+    """The tuner times every candidate of the three passes and keeps the fastest of each; the
+    same batch class then takes the cached choice without timing; a shape outside the candidates
+    is refused."""
+    from paper_2409_01949_amd import elmfb
+    B, oracle = batch32
+    t = B.tune("fp32", reps=2, use_cache=False)
+    print(t)
+    assert not t["from_cache"]
+    assert set(t["ms_rmvb"]) == {16, 32, 64} and set(t["ms_mvb"]) == {4, 8, 16}
+    assert set(t["ms_gather"]) == {1, 2}
+    assert t["rmvb_tile"] == min(t["ms_rmvb"], key=t["ms_rmvb"].get)
+    assert t["mvb_ahead"] == min(t["ms_mvb"], key=t["ms_mvb"].get)
+    assert t["gather_rows"] == min(t["ms_gather"], key=t["ms_gather"].get)
+    c = B.tune("fp32", reps=2, use_cache=True)
+    assert c["from_cache"] and all(c[k] == t[k] for k in ("rmvb_tile", "mvb_ahead", "gather_rows"))
+    with pytest.raises(elmfb.ElmfbError):
+        B.set_shape("fp64", rmvb_tile=64)
+    with pytest.raises(elmfb.ElmfbError):
+        B.set_shape("fp32", mvb_ahead=5)
