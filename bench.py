@@ -341,8 +341,9 @@ def run_batch(args, steps=None, warmup=None, iters=None):
     es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kp]
     ms_mv, ms_g, ms_rmv = B.time_kernels(kp, reps=5)
     R = 8
-    prods = {f"k_bt_mvb<{_kname(kp)}>": (ms_mv, nnz * es + 8 * R * (n_phi + nbp)),
-             "k_bt_gather": (ms_g, 8 * R * (nbp + N)),
+    prods = {f"k_bt_mvb<{_kname(kp)},{tune[kp]['mvb_ahead']}>": (ms_mv, nnz * es
+                                                                 + 8 * R * (n_phi + nbp)),
+             f"k_bt_gather<{tune[kp]['gather_rows']}>": (ms_g, 8 * R * (nbp + N)),
              f"k_bt_rmvb<{_kname(kp)},{tune[kp]['rmvb_tile']}>": (ms_rmv,
                                                                  nnz * es + 8 * R * (nbp + n_phi))}
     dom = max(prods, key=lambda k: prods[k][0])
@@ -352,7 +353,8 @@ def run_batch(args, steps=None, warmup=None, iters=None):
             "ms_per_launch": prods[dom][0], "algorithmic_bytes_per_launch": prods[dom][1],
             "also": [{"kernel": k, "ms_per_launch": t, "algorithmic_bytes_per_launch": a,
                       "achieved_GBs": a / (t * 1e-3) / 1e9, "frac": a / (t * 1e-3) / 1e9 /
-                      HBM_PEAK_GBS} for k, (t, a) in prods.items() if k != dom]}
+                      HBM_PEAK_GBS, "traffic": measured_traffic(k, "batch512x8")}
+                     for k, (t, a) in prods.items() if k != dom]}
     roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
     n_ok = int(np.sum((stops == 1) | (stops == 2)))
     out = {
