@@ -230,6 +230,26 @@ def warm_family_1d(omega: float, coeffs) -> ProblemSpec:
     )
 
 
+def warm_modes_2d(omega: float):
+    """Mode numbers of the 2D warm-start family: n_m = max(1, round(m omega / 15)), m = 1..3
+    (halves rounded up)."""
+    return tuple(max(1, int(math.floor(m * float(omega) / 15.0 + 0.5))) for m in (1, 2, 3))
+
+
+def warm_family_2d(omega: float, coeffs=(1.0, 1.0, 1.0), n: int = 200, J: int = 16,
+                   K: int = 48) -> ProblemSpec:
+    """-Lap u = f on [0,1]^2, u = sum_{m=1..3} c_m sin(n_m pi x) sin(n_m pi y) with
+    n_m = max(1, round(m omega / 15)); hard constraint tanh(omega s) tanh(omega (1 - s)) per axis;
+    one level of 16 x 16 subdomains, K = 48, width ratio 2.9, 200^2 points."""
+    return ProblemSpec(
+        name="warm2d", dim=2, op="neg_laplace", ansatz="tanh_box", ansatz_omega=float(omega),
+        lo=(0.0, 0.0), hi=(1.0, 1.0), n_points=(n, n), levels=((J, J),), delta=2.9, K=K,
+        w_range=(-1.0, 1.0), b_range=(-1.0, 1.0), seed=0,
+        meta={"family": "sines", "freqs": tuple(float(v) for v in warm_modes_2d(omega)),
+              "amps": tuple(coeffs), "n_test": (240, 240)},
+    )
+
+
 def warm_draws(n, seed):
     """Problem parameters (omega ~ U[5,50], c ~ N(0,1)^3) for n instances."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -248,9 +268,17 @@ def warm_groups(n_groups, seed, n_rhs=8):
 
 
 def warm_batch_forcing(spec: ProblemSpec, C) -> np.ndarray:
-    """[n_rhs, N] forcing of one warm-family instance for each coefficient vector C[r]."""
+    """[n_rhs, N] forcing of one warm-family instance (1D or 2D) for each coefficient vector
+    C[r]."""
     pts = grid_points(spec)
-    return np.stack([fam.ode_modes_forcing(pts, spec.meta["freqs"], c) for c in C])
+    f = fam.sines_forcing if spec.dim == 2 else fam.ode_modes_forcing
+    return np.stack([f(pts, spec.meta["freqs"], c) for c in C])
+
+
+def warm_exact(spec: ProblemSpec, c, pts) -> np.ndarray:
+    """Exact solution of a warm-family instance with coefficient vector c at points pts."""
+    f = fam.sines_exact if spec.dim == 2 else fam.ode_modes_exact
+    return f(np.asarray(pts), spec.meta["freqs"], c)
 
 
 def boundary_points(spec: ProblemSpec) -> np.ndarray:

@@ -117,6 +117,32 @@ void brelease(elmfb_batch b) {
   b->stream = nullptr;
 }
 
+// Workgroups of a launch go to the 8 XCDs in turn (workgroup w to XCD w mod 8), and each XCD has
+// its own L2.  The 64-point runs of one block all read the block's packed factor, so they are
+// ordered to land on one XCD: whole blocks are dealt to the XCD with the fewest runs so far, and
+// the runs are interleaved by XCD, with empty runs (blk = -1) where an XCD's list is shorter.
+constexpr int kXcds = 8;
+
+std::vector<Tile> xcd_grouped(const std::vector<Tile>& runs) {
+  std::vector<std::vector<Tile>> q(kXcds);
+  for (size_t a = 0; a < runs.size();) {
+    size_t b = a;
+    while (b < runs.size() && runs[b].blk == runs[a].blk) ++b;
+    size_t x = 0;
+    for (size_t y = 1; y < q.size(); ++y)
+      if (q[y].size() < q[x].size()) x = y;
+    q[x].insert(q[x].end(), runs.begin() + a, runs.begin() + b);
+    a = b;
+  }
+  size_t len = 0;
+  for (const auto& v : q) len = std::max(len, v.size());
+  std::vector<Tile> out;
+  out.reserve(len * kXcds);
+  for (size_t r = 0; r < len; ++r)
+    for (int x = 0; x < kXcds; ++x) out.push_back(r < q[x].size() ? q[x][r] : Tile{-1, 0});
+  return out;
+}
+
 std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
   int64_t row_off = 0, col_off = 0, a_off = 0, p_off = 0, f_off = 0, g_off = 0, nnz = 0;
   int32_t blk_off = 0, tab_off = 0, cov_off = 0;
@@ -180,6 +206,7 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
     cov_off += (int32_t)hp.cov.size();
     if (row_off > ((int64_t)1 << 31) || col_off > ((int64_t)1 << 31)) return "batch too large";
   }
+  B->ftiles = xcd_grouped(B->ftiles);
   B->n_rows = row_off;
   B->n_phi = col_off;
   B->nnz = nnz;
@@ -637,19 +664,18 @@ elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fa
     }
     B->bytes += B->n_fac * 8 + B->n_store * 8;
   }
-  double *G = nullptr, *work = nullptr;
+  double* G = nullptr;
   hipError_t e1 = balloc(B, &G, B->n_gsq * 8);
-  hipError_t e2 = e1 == hipSuccess ? balloc(B, &work, B->n_gsq * 8) : e1;
-  if (e2 != hipSuccess) {
-    bfree(B, G);
-    return bfail(B, ELMFB_E_NOMEM, std::string("Gram scratch: ") + hipGetErrorString(e2));
-  }
+  if (e1 != hipSuccess)
+    return bfail(B, ELMFB_E_NOMEM, std::string("Gram scratch: ") + hipGetErrorString(e1));
+  int kmax = 1;
+  for (const Geo& g : B->geos) kmax = std::max(kmax, (int)g.K);
   B->bj_ready = false;
   hipError_t e = hipMemsetAsync(B->d_flag, 0, 4, s);
   if (e == hipSuccess)
     e = launch_bt_gram_diag(B->d_geos, B->d_blocks, nb, B->d_A, B->d_goff, G, s);
   if (e == hipSuccess)
-    e = launch_bt_bj_factor(B->d_geos, B->d_blocks, nb, G, B->d_goff, work, B->d_foff, shift,
+    e = launch_bt_bj_factor(B->d_geos, B->d_blocks, nb, G, B->d_goff, B->d_foff, kmax, shift,
                             B->d_rc, B->d_flag, s);
   // M R^{-1} in FP64, and its rounded copy in place of the low-precision M
   if (e == hipSuccess)
@@ -659,7 +685,6 @@ elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fa
   int32_t nfail = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&nfail, B->d_flag, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  bfree(B, work);
   bfree(B, G);
   BHIP(B, e);
   if (n_fallback_host) *n_fallback_host = nfail;

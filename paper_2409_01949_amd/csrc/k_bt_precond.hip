@@ -76,85 +76,108 @@ __global__ void __launch_bounds__(256) k_bt_gram_diag(const Geo* __restrict__ ge
   }
 }
 
-// One workgroup per block: Cholesky of G_b + lambda I (upper factor, in work), the inverse
-// Ri = R^{-1} (one column per thread, into G_b's storage once the factor exists), then the
-// column-packed copy (Ri[i][k], i <= k, at k(k+1)/2 + i).  A failed factorisation is retried with a 100x larger shift up to 8 times; after
-// that, or for an all-zero block, the block gets the identity and nfail counts it.
-__global__ void __launch_bounds__(256) k_bt_bj_factor(const Geo* __restrict__ geos,
-                                                      const DevBlock* __restrict__ blocks,
-                                                      double* __restrict__ G,
-                                                      const int64_t* __restrict__ goff,
-                                                      double* __restrict__ work,
-                                                      const int64_t* __restrict__ foff,
-                                                      double shift, double* __restrict__ rc,
-                                                      int32_t* __restrict__ nfail) {
-  __shared__ int bad;
-  __shared__ double lam_s;
+// One workgroup of 1,024 threads per block, everything in LDS (two packed upper triangles of
+// K(K+1)/2 doubles, (i, j) at j(j+1)/2 + i, and one row vector): the upper Cholesky factor R of
+// G_b + lambda I by right-looking elimination (step k: the pivot row R[k][j] = G'[k][j] / sqrt of
+// the pivot, kept in the row vector, then the trailing update R[i][j] -= R[k][i] R[k][j] for
+// k < i <= j), then X = R^{-1} by the same elimination from the bottom row (row i of X is row i of
+// the running right-hand side over R[i][i]; rows r < i then lose R[r][i] X[i][j]), written out in
+// the same column-packed layout.  Each update is spread as 8 threads per column j over its rows,
+// which are contiguous in the packed layout, so a thread's updates are independent of each
+// other.  A failed factorisation is retried with a 100x larger shift up to 8 times; after that,
+// or for an all-zero block, the block gets the identity and nfail counts it.
+constexpr int kFacThreads = 1024;
+
+__global__ void __launch_bounds__(kFacThreads) k_bt_bj_factor(const Geo* __restrict__ geos,
+                                                              const DevBlock* __restrict__ blocks,
+                                                              const double* __restrict__ G,
+                                                              const int64_t* __restrict__ goff,
+                                                              const int64_t* __restrict__ foff,
+                                                              double shift,
+                                                              double* __restrict__ rc,
+                                                              int32_t* __restrict__ nfail) {
+  extern __shared__ double lds[];
+  __shared__ double part[kFacThreads / 64];
+  __shared__ double row[kBatchMaxK];
   const DevBlock B = blocks[blockIdx.x];
   const int K = geos[B.inst].K;
-  double* Gj = G + goff[blockIdx.x];
-  double* R = work + goff[blockIdx.x];
+  const int np = K * (K + 1) / 2;
+  double* Rp = lds;
+  double* Xp = lds + np;
+  const double* Gj = G + goff[blockIdx.x];
   double* Pc = rc + foff[blockIdx.x];
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < K; ++i) tr += Gj[i * K + i];
-    lam_s = shift * tr / K;
-  }
+  const int t = threadIdx.x, tc = t >> 3, ts = t & 7;   // column offset, row phase
+  // trace of G_b
+  double tr = 0.0;
+  for (int i = t; i < K; i += kFacThreads) tr += Gj[(int64_t)i * K + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o);
+  if ((t & 63) == 0) part[t >> 6] = tr;
   __syncthreads();
-  double lam = lam_s;
+  tr = 0.0;
+  for (int w = 0; w < kFacThreads / 64; ++w) tr += part[w];
+  double lam = shift * tr / K;
   bool ok = lam > 0.0;
+  bool bad = true;
   for (int attempt = 0; attempt < 8 && ok; ++attempt) {
-    for (int e = threadIdx.x; e < K * K; e += 256) {
-      const int i = e / K, j = e - i * K;
-      R[e] = (j >= i) ? Gj[e] + (i == j ? lam : 0.0) : 0.0;
+    for (int e = t; e < K * K; e += kFacThreads) {
+      const int i = e / K, j = e - (e / K) * K;
+      if (i <= j) Rp[j * (j + 1) / 2 + i] = Gj[e] + (i == j ? lam : 0.0);
     }
-    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
+    bad = false;
     for (int k = 0; k < K; ++k) {
-      if (threadIdx.x == 0) {
-        const double d = R[k * K + k];
-        if (!(d > 0.0)) bad = 1;
-        R[k * K + k] = d > 0.0 ? sqrt(d) : 1.0;
+      const double d = Rp[k * (k + 1) / 2 + k];
+      if (!(d > 0.0)) { bad = true; break; }    // every thread reads the same value
+      const double rk = sqrt(d);
+      for (int j = k + 1 + t; j < K; j += kFacThreads) {
+        const double v = Rp[j * (j + 1) / 2 + k] / rk;
+        Rp[j * (j + 1) / 2 + k] = v;
+        row[j] = v;
       }
       __syncthreads();
-      if (bad) break;
-      const double dk = R[k * K + k];
-      for (int j = k + 1 + threadIdx.x; j < K; j += 256) R[k * K + j] /= dk;
-      __syncthreads();
-      const int m = K - k - 1;
-      for (int e = threadIdx.x; e < m * m; e += 256) {
-        const int i = k + 1 + e / m, j = k + 1 + (e - (e / m) * m);
-        if (j >= i) R[i * K + j] -= R[k * K + i] * R[k * K + j];
+      if (t == 0) Rp[k * (k + 1) / 2 + k] = rk;
+      const int j = k + 1 + tc;
+      if (j < K) {
+        double* cj = Rp + j * (j + 1) / 2;
+        const double rkj = row[j];
+        for (int i = k + 1 + ts; i <= j; i += 8) cj[i] -= row[i] * rkj;
       }
       __syncthreads();
     }
     if (!bad) break;
-    lam *= 100.0;
     __syncthreads();
-    if (threadIdx.x == 0 && attempt == 7) atomicAdd(nfail, 1);
+    lam *= 100.0;
     ok = attempt < 7;
   }
+  if (bad) {
+    if (t == 0) atomicAdd(nfail, 1);
+    for (int e = t; e < np; e += kFacThreads) Pc[e] = 0.0;
+    for (int i = t; i < K; i += kFacThreads) Pc[i * (i + 1) / 2 + i] = 1.0;
+    return;
+  }
+  for (int e = t; e < np; e += kFacThreads) Xp[e] = 0.0;
   __syncthreads();
-  const bool ident = !ok || bad;
-  if (!ident) {
-    // Ri (upper) into Gj's storage: R Ri = I, one column per thread
-    for (int j = threadIdx.x; j < K; j += 256) {
-      Gj[j * K + j] = 1.0 / R[j * K + j];
-      for (int i = j - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int m = i + 1; m <= j; ++m) s += R[i * K + m] * Gj[m * K + j];
-        Gj[i * K + j] = -s / R[i * K + i];
-      }
+  for (int i = t; i < K; i += kFacThreads) Xp[i * (i + 1) / 2 + i] = 1.0;
+  __syncthreads();
+  for (int i = K - 1; i >= 0; --i) {
+    const int ci = i * (i + 1) / 2;
+    const double rii = Rp[ci + i];
+    for (int j = i + t; j < K; j += kFacThreads) {
+      const double v = Xp[j * (j + 1) / 2 + i] / rii;
+      Xp[j * (j + 1) / 2 + i] = v;
+      row[j] = v;
+    }
+    __syncthreads();
+    const int j = i + tc;
+    if (j < K) {
+      double* xj = Xp + j * (j + 1) / 2;
+      const double xij = row[j];
+      for (int r = ts; r < i; r += 8) xj[r] -= Rp[ci + r] * xij;
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < K * K; e += 256) {
-    const int i = e / K, k = e - i * K;
-    if (i <= k) {
-      const double v = ident ? (i == k ? 1.0 : 0.0) : Gj[i * K + k];
-      Pc[(int64_t)k * (k + 1) / 2 + i] = v;
-    }
-  }
+  for (int e = t; e < np; e += kFacThreads) Pc[e] = Xp[e];
 }
 
 // Fold the preconditioner into the matrix: Mhat_b = M_b R_b^{-1}, i.e. in the feature-major
@@ -180,6 +203,7 @@ __global__ void __launch_bounds__(256) k_bt_fold(const Geo* __restrict__ geos,
   __shared__ double Rt[KMAX][kFoldK + 1];         // Rt[k'][kk] = Ri[k0 + kk][k']
   __shared__ double At[kFoldK][kFoldP + 1];       // At[kk][c] = M_b[k0 + kk][p0 + c]
   const Tile t = ftiles[blockIdx.x];
+  if (t.blk < 0) return;                          // an empty run (launch order padding)
   const DevBlock B = blocks[t.blk];
   const int K = geos[B.inst].K;
   const int n = B.n, p0 = t.p0;
@@ -276,11 +300,16 @@ hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t 
 }
 
 hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
-                               double* G, const int64_t* goff, double* work, const int64_t* foff,
+                               const double* G, const int64_t* goff, const int64_t* foff, int kmax,
                                double shift, double* rc, int32_t* nfail, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bt_bj_factor, dim3((unsigned)n_blocks), dim3(256), 0, s, geos, blocks, G,
-                     goff, work, foff, shift, rc, nfail);
+  if (kmax < 1 || kmax > kBatchMaxK) return hipErrorInvalidValue;
+  const size_t lds = (size_t)kmax * (kmax + 1) * sizeof(double);    // two packed triangles
+  hipError_t e = hipFuncSetAttribute((const void*)k_bt_bj_factor,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bt_bj_factor, dim3((unsigned)n_blocks), dim3(kFacThreads), lds, s, geos,
+                     blocks, G, goff, foff, shift, rc, nfail);
   return hipGetLastError();
 }
 

@@ -182,8 +182,9 @@ hipError_t launch_bt_recover_plain(int64_t n, const double* y, const double* x0,
                                    hipStream_t s);
 hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
                                const double* A, const int64_t* goff, double* G, hipStream_t s);
+// kmax: largest K of the blocks (<= kBatchMaxK; sets the dynamic LDS of two packed triangles)
 hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
-                               double* G, const int64_t* goff, double* work, const int64_t* foff,
+                               const double* G, const int64_t* goff, const int64_t* foff, int kmax,
                                double shift, double* rc, int32_t* nfail, hipStream_t s);
 // full: rc holds R^{-1} as K x K row-major per block (foff unused); else column-packed at foff
 // kmax: largest K of the blocks (<= 256); Ahat may be NULL (low-precision result only)
