@@ -75,12 +75,26 @@ def parse():
     p.add_argument("--secondary-iters", type=int, default=3000,
                    help="inner-iteration budget of the secondary multilevel and batched steps")
     p.add_argument("--batch-n", type=int, default=512)
-    p.add_argument("--batch-btol", type=float, default=1e-6)
-    p.add_argument("--epochs", type=int, default=100, help="warm workload: MLP training epochs")
+    p.add_argument("--batch-btol", type=float, default=None,
+                   help="batched workloads: residual tolerance (default 1e-6 for batch, 1e-4 "
+                        "for warm, 1e-3 for warm2d)")
+    p.add_argument("--epochs", type=int, default=None,
+                   help="warm workloads: MLP training epochs (default 100 for warm, 30 for warm2d)")
+    p.add_argument("--warm-inner", type=int, default=None,
+                   help="warm workloads: inner LSQR steps per refinement step")
+    p.add_argument("--warm-outer", type=int, default=None,
+                   help="warm workloads: refinement steps")
+    p.add_argument("--warm-train-groups", type=int, default=512,
+                   help="warm workloads: training omegas (8 coefficient vectors each)")
+    p.add_argument("--warm-test-groups", type=int, default=128,
+                   help="warm workloads: held-out omegas (8 coefficient vectors each)")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run device copies of this many bytes (traffic-counter reference)")
     args = p.parse_args()
     args.store_given, args.inner_given = args.store, args.inner
+    args.batch_btol_given = args.batch_btol
+    if args.batch_btol is None:
+        args.batch_btol = 1e-6
     return _defaults(args)
 
 
@@ -338,24 +352,8 @@ def run_batch(args, steps=None, warmup=None, iters=None):
               + (f"mixed-ir ({store} inner)" if mixed else "lsqr-fp64"))
     # rooflines of the three matrix passes of a step, on the matrix the inner steps stream
     kp = store if mixed else "fp64"
-    es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kp]
-    ms_mv, ms_g, ms_rmv = B.time_kernels(kp, reps=5)
-    R = 8
-    prods = {f"k_bt_mvb<{_kname(kp)},{tune[kp]['mvb_ahead']}>": (ms_mv, nnz * es
-                                                                 + 8 * R * (n_phi + nbp)),
-             f"k_bt_gather<{tune[kp]['gather_rows']}>": (ms_g, 8 * R * (nbp + N)),
-             f"k_bt_rmvb<{_kname(kp)},{tune[kp]['rmvb_tile']}>": (ms_rmv,
-                                                                 nnz * es + 8 * R * (nbp + n_phi))}
-    dom = max(prods, key=lambda k: prods[k][0])
-    roof = {"bound": "hbm", "achieved": prods[dom][1] / (prods[dom][0] * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": measured_traffic(dom, "batch512x8"),
-            "kernel": f"{dom} (the longest matrix pass of a batched Krylov step, 8 rhs)",
-            "ms_per_launch": prods[dom][0], "algorithmic_bytes_per_launch": prods[dom][1],
-            "also": [{"kernel": k, "ms_per_launch": t, "algorithmic_bytes_per_launch": a,
-                      "achieved_GBs": a / (t * 1e-3) / 1e9, "frac": a / (t * 1e-3) / 1e9 /
-                      HBM_PEAK_GBS, "traffic": measured_traffic(k, "batch512x8")}
-                     for k, (t, a) in prods.items() if k != dom]}
-    roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
+    roof = _batch_pass_roofline(B, kp, tune[kp], "batch512x8",
+                                "the longest matrix pass of a batched Krylov step, 8 rhs")
     n_ok = int(np.sum((stops == 1) | (stops == 2)))
     out = {
         "metric": METRIC, "value": rows_rhs / dt, "unit": "rows/s", "n_gpus": 1,
@@ -384,7 +382,8 @@ def run_batch(args, steps=None, warmup=None, iters=None):
     return out
 
 
-def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n_lsqr=20):
+def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n_lsqr=20,
+                       forcing=None):
     """The oracle on a sample of the batch: the smallest, the largest and two seeded instances,
     each assembled (FP64 blocks) and n_lsqr LSQR iterations run for each of its 8 right-hand
     sides; scaled by entry count to the whole batch and the step's iterations.  1 warm-up + 2
@@ -410,7 +409,7 @@ def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n
             t_asm += time.perf_counter() - t0
             n = len(blocks) * spec.K
             ent += sum(blk.M.size for blk in blocks)
-            F = configs.batch_forcing(spec)
+            F = configs.batch_forcing(spec) if forcing is None else forcing(i)
             t1 = time.perf_counter()
             for r in range(F.shape[0]):
                 h = asm.rhs(spec, F[r])
@@ -442,69 +441,171 @@ def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n
             "value_1_thread": rows_rhs / t1s[0]}
 
 
-def run_warm(args):
-    """Learned warm start on the 1D parameterised family (omega ~ U[5,50], c ~ N(0,1)^3, J=64,
-    K=32, 6000 points): 4,096 training solves (512 omega x 8 c) by the batched solver, the MLP
-    (3 x 512 tanh, BF16 products) trained on them, then the 1,024 held-out pairs (128 x 8) solved
-    to ||h - M c|| <= btol ||h|| from its prediction.  A step is prediction + warm solve; the cold
-    solve of the same batch is reported beside it."""
+def _batch_pass_roofline(B, kp, shape, workload, label):
+    """HBM roofline of the longest of the three matrix passes of a batched Krylov step (8 right-
+    hand sides) on the stored copy of precision kp, with the other two under "also"."""
+    es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kp]
+    nnz, nbp = B.sizes["nnz"], B.sizes["n_block_points"]
+    N, n_phi = B.sizes["n_rows"], B.sizes["n_phi"]
+    ms_mv, ms_g, ms_rmv = B.time_kernels(kp, reps=5)
+    R = 8
+    prods = {f"k_bt_mvb<{_kname(kp)},{shape['mvb_ahead']}>": (ms_mv, nnz * es + 8 * R * (n_phi + nbp)),
+             f"k_bt_gather<{shape['gather_rows']}>": (ms_g, 8 * R * (nbp + N)),
+             f"k_bt_rmvb<{_kname(kp)},{shape['rmvb_tile']}>": (ms_rmv,
+                                                            nnz * es + 8 * R * (nbp + n_phi))}
+    dom = max(prods, key=lambda k: prods[k][0])
+    roof = {"bound": "hbm", "achieved": prods[dom][1] / (prods[dom][0] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": measured_traffic(dom, workload),
+            "kernel": f"{dom} ({label})", "ms_per_launch": prods[dom][0],
+            "algorithmic_bytes_per_launch": prods[dom][1],
+            "also": [{"kernel": k, "ms_per_launch": t, "algorithmic_bytes_per_launch": a,
+                      "achieved_GBs": a / (t * 1e-3) / 1e9,
+                      "frac": a / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "traffic": measured_traffic(k, workload)}
+                     for k, (t, a) in prods.items() if k != dom]}
+    roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
+    return roof
+
+
+def _warm_errors(specs, om, C, coef_y, B, groups):
+    """rel-L2 of u against the exact solution on each sampled group's test grid, for every
+    right-hand side, from batch coefficients in block-Jacobi coordinates (mapped back by the
+    batch, evaluated by a single-problem handle of the instance)."""
     import numpy as np
     import torch
 
-    from inputs import configs
+    from inputs import configs, feature_params
+    from inputs.problems import grid_points
+    from paper_2409_01949_amd import Problem
+
+    x = torch.empty(B.n_rhs * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    B.from_coords(torch.as_tensor(coef_y).cuda(), x)
+    xh = x.cpu().numpy()
+    R = C.shape[1]
+    out = []
+    o = 0
+    offs = []
+    for s in specs:
+        offs.append(o)
+        o += R * int(np.prod(s.levels[0])) * s.K
+    for g in groups:
+        s = specs[g]
+        n = int(np.prod(s.levels[0])) * s.K
+        W, b = feature_params(s)
+        P = Problem.from_spec(s, W, b)
+        tp = grid_points(s, s.meta["n_test"])
+        u = torch.empty(R * tp.shape[0], dtype=torch.float64, device="cuda")
+        P.evaluate(torch.as_tensor(xh[offs[g]:offs[g] + R * n]).cuda(),
+                   torch.as_tensor(tp).cuda(), u, n_rhs=R)
+        uh = u.cpu().numpy().reshape(R, -1)
+        for r in range(R):
+            ue = configs.warm_exact(s, C[g, r], tp)
+            out.append(float(np.linalg.norm(uh[r] - ue) / np.linalg.norm(ue)))
+        P.destroy()
+    return np.array(out)
+
+
+def run_warm(args):
+    """Learned warm start on a parameterised family (omega ~ U[5,50], c ~ N(0,1)^3): 1D
+    (`warm`, J=64, K=32, 6000 points) or 2D (`warm2d`, -Lap u = f on [0,1]^2, 16 x 16
+    subdomains, K=48, 200^2 points).  4,096 training solves (512 omega x 8 c) by the batched
+    solver, the MLP (3 x 512 tanh, BF16 products) trained on them, then the 1,024 held-out pairs
+    (128 x 8) solved to ||h - M c|| <= btol ||h|| (or least-squares optimality at atol = btol)
+    from its prediction.  A step is prediction + warm solve; the cold solve of the same batch is
+    reported beside it, with both solutions' rel-L2 against the exact solution on sampled
+    groups."""
+    import numpy as np
+    import torch
+
+    from inputs import configs, feature_params
     from paper_2409_01949_amd import warmstart as ws
 
     def log(m):
         print("# " + m, file=sys.stderr, flush=True)
 
-    om, C = configs.warm_groups(512, 5)
-    B, specs, _ = ws.family_batch(om, C)
-    coef, infos, t_data = ws.solve_batch(B, btol=args.batch_btol * 0.1, inner=2000, outer=6)
-    X, F = ws.family_inputs(specs, om, C)
-    Y = ws.coef_blocks(coef, specs, C.shape[1])
-    B.destroy()
+    dim = 2 if args.workload == "warm2d" else 1
+    inner = args.warm_inner or (2000 if dim == 1 else 4000)
+    outer = args.warm_outer or (10 if dim == 1 else 4)
+    btol = args.batch_btol_given if args.batch_btol_given else (1e-4 if dim == 1 else 1e-3)
+    epochs = args.epochs or (100 if dim == 1 else 30)
+    chunk = 512 if dim == 1 else 128
+    store = "fp32"
+    om, C = configs.warm_groups(args.warm_train_groups, 5)
+    parts, infos, t_data = [], [], 0.0
+    for c0 in range(0, len(om), chunk):
+        B, specs, _ = ws.family_batch(om[c0:c0 + chunk], C[c0:c0 + chunk], dim=dim)
+        B.tune(store, reps=3)
+        coef, inf, t = ws.solve_batch(B, btol=btol * 0.1, atol=btol * 0.1, inner=inner,
+                                      outer=outer)
+        X, F = ws.family_inputs(specs, om[c0:c0 + chunk], C[c0:c0 + chunk])
+        parts.append((X.astype(np.float32), F.astype(np.float32),
+                      ws.coef_blocks(coef, specs, C.shape[1])))
+        infos += inf
+        t_data += t
+        B.destroy()
+        torch.cuda.empty_cache()
+    X = np.concatenate([p[0] for p in parts])
+    F = np.concatenate([p[1] for p in parts])
+    Y = np.concatenate([p[2] for p in parts])
+    parts = None
     log(f"training data: {len(X)} samples from {len(infos)} solves in {t_data:.1f} s")
-    W = ws.WarmStart(n_in=X.shape[1], K=Y.shape[1], max_batch=4096, seed=0)
+    Wn = ws.WarmStart(n_in=X.shape[1], K=Y.shape[1], max_batch=4096, seed=0,
+                      n_mod=F.shape[1])
     t0 = time.perf_counter()
-    hist = W.fit(X, F, Y, epochs=args.epochs, lr=1e-3, seed=0, log=log)
+    hist = Wn.fit(X, F, Y, epochs=epochs, lr=1e-3, seed=0, log=log)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    om2, C2 = configs.warm_groups(128, 6)
-    B2, specs2, hn2 = ws.family_batch(om2, C2)
+    n_steps = epochs * (len(X) // 4096)
+    flop_step = sum(6 * 4096 * a * b for a, b in zip(Wn.dims[:-1], Wn.dims[1:]))
+    X = F = Y = None
+    om2, C2 = configs.warm_groups(args.warm_test_groups, 6)
+    B2, specs2, hn2 = ws.family_batch(om2, C2, dim=dim)
+    shape = B2.tune(store, reps=3)
     X2, F2 = ws.family_inputs(specs2, om2, C2)
-    btol = args.batch_btol
     # a pair is solved at ||r|| <= btol ||h|| or, for the pairs whose optimal residual lies above
     # that, at least-squares optimality with atol = btol
-    _, cold, t_cold = ws.solve_batch(B2, btol=btol, inner=2000, outer=10, atol=btol)
+    yc, cold, t_cold = ws.solve_batch(B2, btol=btol, inner=inner, outer=outer, atol=btol)
 
     def step():
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        x0 = torch.as_tensor(np.ascontiguousarray(W.predict(X2, F2)).reshape(-1)).cuda()
-        _, warm, _ = ws.solve_batch(B2, x0=x0, btol=btol, inner=2000, outer=10,
-                                    precondition=False, atol=btol)
+        x0 = torch.as_tensor(np.ascontiguousarray(Wn.predict(X2, F2)).reshape(-1)).cuda()
+        yw, warm, _ = ws.solve_batch(B2, x0=x0, btol=btol, inner=inner, outer=outer,
+                                     precondition=False, atol=btol)
         torch.cuda.synchronize()
-        return warm, time.perf_counter() - ta
+        return yw, warm, time.perf_counter() - ta
 
     for _ in range(args.warmup):
         step()
     ts = []
     for _ in range(args.steps):
-        warm, dt = step()
+        yw, warm, dt = step()
         ts.append(dt)
     dt = float(np.mean(ts))
     itc = np.array([i["iters"] for i in cold])
     itw = np.array([i["iters"] for i in warm])
+    groups = sorted({0, len(om2) // 2, len(om2) - 1})
+    ec = _warm_errors(specs2, om2, C2, yc, B2, groups)
+    ew = _warm_errors(specs2, om2, C2, yw, B2, groups)
     rows_rhs = B2.sizes["n_rows"] * C2.shape[1]
+    name = f"warm{dim}d_{len(om2)}x{C2.shape[1]}"
+    roof = _batch_pass_roofline(B2, store, shape, name,
+                                "the longest matrix pass of the warm-started solve")
+    roof["also"].append({"kernel": "k_mlp_gemm (training, whole Adam step)",
+                         "ms_per_step": t_train / max(1, n_steps) * 1e3,
+                         "achieved_TFLOPs": flop_step * n_steps / t_train / 1e12,
+                         "peak_TFLOPs": 2500.0, "bound": "mfma"})
+    mlp = "-".join(str(d) for d in Wn.dims) + f" tanh, bf16, output modulated by {F2.shape[1]}"
     out = {
         "metric": METRIC, "value": rows_rhs / dt, "unit": "rows/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+fp32",
         "data": "synthetic",
-        "config": {"workload": "warm1d_128x8", "instances": 128, "n_rhs": 8,
+        "config": {"workload": name, "instances": len(om2), "n_rhs": C2.shape[1],
                    "train_solves": len(infos), "rows": B2.sizes["n_rows"],
                    "cols": B2.sizes["n_phi"], "method": "bj-mixed-ir (fp32 inner), MLP x0",
-                   "btol": btol, "epochs": args.epochs,
-                   "mlp": "65-512-512-512-192 tanh, bf16, output modulated by 6 weights"},
+                   "btol": btol, "atol": btol, "inner": inner, "outer": outer,
+                   "epochs": epochs, "mlp": mlp},
         "warm_s": dt, "cold_s": t_cold, "speedup_vs_cold": t_cold / dt,
         "iters_mean": {"cold": float(itc.mean()), "warm": float(itw.mean())},
         "iters_max": {"cold": int(itc.max()), "warm": int(itw.max())},
@@ -512,13 +613,21 @@ def run_warm(args):
                       "warm": int(sum(i["istop"] == 1 for i in warm)), "pairs": len(cold)},
         "ls_optimal": {"cold": int(sum(i["istop"] == 2 for i in cold)),
                        "warm": int(sum(i["istop"] == 2 for i in warm))},
-        "training": {"data_s": t_data, "train_s": t_train, "loss_first": hist[0],
-                     "loss_last": hist[-1]},
+        "rel_l2_vs_exact": {"groups": groups, "cold_median": float(np.median(ec)),
+                            "cold_max": float(ec.max()), "warm_median": float(np.median(ew)),
+                            "warm_max": float(ew.max())},
+        "training": {"data_s": t_data, "train_s": t_train, "adam_steps": n_steps,
+                     "loss_first": hist[0], "loss_last": hist[-1]},
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        feats2 = [feature_params(s) for s in specs2]
+        out["cpu_baseline"] = batch_cpu_baseline(
+            specs2, feats2, int(itw.max()), B2.sizes["nnz"], rows_rhs,
+            forcing=lambda i: configs.warm_batch_forcing(specs2[i], C2[i]))
     B2.destroy()
-    W.destroy()
-    print(json.dumps(out), flush=True)
-
+    Wn.destroy()
+    return out
 
 def krylov_sigma(P):
     """Extreme singular values of the bidiagonal the last solve's LSQR built (a lower bound on
@@ -1282,8 +1391,8 @@ def main():
     if args.workload.startswith("batch"):
         print(json.dumps(run_batch(args)), flush=True)
         return
-    if args.workload == "warm":
-        run_warm(args)
+    if args.workload in ("warm", "warm2d"):
+        print(json.dumps(run_warm(args)), flush=True)
         return
     if args.workload == "oscillator":
         run_oscillator(args)

@@ -756,7 +756,8 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   const int R = B->R;
   const int64_t nb = (int64_t)B->blocks.size();
   const void* A = matrix_of(B, prec, false);
-  // V = 1 and U = 1 on every column, row and right-hand side (timing inputs only)
+  // V = 1 and U = 1 on every column, row and right-hand side (timing inputs only); the row
+  // gather writes its rows into the row-sized work vector U, which the M^T U timing then reads
   std::vector<double> ones((size_t)std::max(B->n_rows, B->n_phi) * R, 1.0);
   BHIP(B, hipMemcpyAsync(B->d_v, ones.data(), (size_t)B->n_phi * R * 8, hipMemcpyHostToDevice, s));
   BHIP(B, hipMemcpyAsync(B->d_u, ones.data(), (size_t)B->n_rows * R * 8, hipMemcpyHostToDevice, s));
@@ -769,7 +770,7 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
-                         (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_c, nullptr,
+                         (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_u, nullptr,
                          nullptr, B->d_red_r, s, B->rpt);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
@@ -884,7 +885,7 @@ elmfb_status elmfb_batch_tune(elmfb_batch B, int32_t prec, int32_t reps, int32_t
     for (int c = 0; c < 2; ++c) {
       sh.ms_gather[c] = timed([&] {
         return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
-                                (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_c,
+                                (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_u,
                                 nullptr, nullptr, B->d_red_r, s, c + 1);
       });
       if (sh.ms_gather[c] >= 0 && sh.ms_gather[c] < best) { best = sh.ms_gather[c]; sh.gather_rows = c + 1; }

@@ -233,11 +233,18 @@ struct MlpGemm {
   uint16_t* out_bf16;      // BIAS_TANH, DTANH
   int64_t ldo;
 };
-hipError_t launch_mlp_gemm(const MlpGemm& p, hipStream_t s);
+// ws: FP32 workspace of mlp_gemm_ws_floats(M, N, K) floats for split-k products (F32 epilogue
+// only; NULL: no split)
+int mlp_gemm_splits(int M, int N, int K);
+int64_t mlp_gemm_ws_floats(int M, int N, int K);
+hipError_t launch_mlp_gemm(const MlpGemm& p, float* ws, hipStream_t s);
 hipError_t launch_mlp_to_bf16(int64_t n, const float* x, uint16_t* y, hipStream_t s);
 hipError_t launch_mlp_loss(int64_t n, const float* y, const float* t, uint16_t* g, double* part,
                            int n_part, double* loss, hipStream_t s);
-hipError_t launch_mlp_colsum(int M, int N, const uint16_t* g, float* db, hipStream_t s);
+// part: mlp_colsum_chunks(M) x N floats of partial sums
+int mlp_colsum_chunks(int M);
+hipError_t launch_mlp_colsum(int M, int N, const uint16_t* g, float* part, float* db,
+                             hipStream_t s);
 hipError_t launch_mlp_modulate(int64_t n, int K, int n_mod, const float* z, const float* f,
                                float* y, hipStream_t s);
 hipError_t launch_mlp_mod_loss(int64_t n, int K, int n_mod, const float* z, const float* f,

@@ -28,6 +28,8 @@ struct elmfb_mlp_s {
   uint16_t *d_pb = nullptr, *d_x = nullptr, *d_g1 = nullptr, *d_g2 = nullptr;
   std::vector<uint16_t*> d_act;          // a_l, l = 1..L-1 (bfloat16)
   double *d_part = nullptr, *d_loss = nullptr;
+  float* d_ws = nullptr;                 // split-k partial products of the weight gradients
+  float* d_colpart = nullptr;            // partial column sums of the bias gradients
 };
 
 namespace {
@@ -92,7 +94,7 @@ hipError_t run_forward(elmfb_mlp m, const float* x, int batch, float* y, hipStre
       g.epi = MLP_EPI_BIAS;
       g.out_f32 = y;
     }
-    e = launch_mlp_gemm(g, s);
+    e = launch_mlp_gemm(g, nullptr, s);
   }
   return e;
 }
@@ -149,6 +151,11 @@ elmfb_status elmfb_mlp_create(int32_t n_layers, const int32_t* dims_host, int32_
   for (int l = 1; l < n_layers; ++l) A(&m->d_act[l], B * m->dims[l] * 2);
   A(&m->d_part, kLossParts * 8);
   A(&m->d_loss, 8);
+  int64_t ws = 0;
+  for (int l = 0; l < n_layers; ++l)
+    ws = std::max(ws, mlp_gemm_ws_floats(m->dims[l + 1], m->dims[l], max_batch));
+  A(&m->d_ws, ws * 4);
+  A(&m->d_colpart, (int64_t)mlp_colsum_chunks(max_batch) * m->max_dim * 4);
   if (e == hipSuccess) e = hipMemset(m->d_p, 0, (size_t)o * 4);
   if (e == hipSuccess) e = hipMemset(m->d_pb, 0, (size_t)o * 2);
   if (e == hipSuccess) e = hipMemset(m->d_m, 0, (size_t)o * 4);
@@ -251,8 +258,8 @@ elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* 
     gw.epi = MLP_EPI_F32;
     gw.out_f32 = m->d_g + m->offW[l];
     gw.ldo = n_in;
-    MHIP(m, launch_mlp_gemm(gw, s));
-    MHIP(m, launch_mlp_colsum(batch, n_out, g, m->d_g + m->offb[l], s));
+    MHIP(m, launch_mlp_gemm(gw, m->d_ws, s));
+    MHIP(m, launch_mlp_colsum(batch, n_out, g, m->d_colpart, m->d_g + m->offb[l], s));
     if (l > 0) {
       // g_prev[m][k] = (sum_n g[m][n] W[n][k]) (1 - a_in[m][k]^2)
       MlpGemm gb{};
@@ -269,7 +276,7 @@ elmfb_status elmfb_mlp_train_step(elmfb_mlp m, const float* x_dev, const float* 
       gb.act = a_in;
       gb.out_bf16 = g_next;
       gb.ldo = n_in;
-      MHIP(m, launch_mlp_gemm(gb, s));
+      MHIP(m, launch_mlp_gemm(gb, nullptr, s));
       std::swap(g, g_next);
     }
   }

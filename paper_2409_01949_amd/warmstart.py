@@ -6,17 +6,25 @@ plus a subdomain's position to that subdomain's K coefficients; its prediction i
 later batched solves.  Coefficients are taken in block-Jacobi coordinates y_j = R_j x_j (the
 subdomain's features orthonormalised over its support): there they are of the size of the
 local solution, whereas the raw coefficients of the redundant random features carry large,
-cancelling components that no regression reproduces.  This module only prepares inputs and standardises targets on the host;
-solves, training and inference run in the library.
+cancelling components that no regression reproduces.  This module only prepares inputs and
+standardises targets on the host; solves, training and inference run in the library.
 
-Family (1D, single level): du/dx = sum_{m=1..3} c_m cos(m omega x / 3) on [-2 pi, 2 pi] with the
-hard constraint tanh(omega x) (u(0) = 0), J subdomains of K features.  The solution is linear in
-c, and near a centre mu_j each mode is a combination of sin and cos of its phase
-phi_m = m omega mu_j / 3.  The model uses that structure: the network maps (omega / 50, one-hot
-subdomain index) to six K-vectors G_i, and the prediction is sum_i f_i G_i with the per-sample
-weights f = (c_m sin phi_m, c_m cos phi_m), m = 1..3 (the library's modulated MLP output).  The
-subdomains have their own random features, so each needs its own function of omega: the one-hot
-index lets the first layer hold them.
+The solution of each family is linear in the source coefficients c, so the network's output is
+modulated: it maps (parameters, one-hot subdomain index) to N_MOD K-vectors G_i and the
+prediction is sum_i f_i G_i with per-sample weights f that are linear in c (the library's
+modulated MLP output).  The subdomains have their own random features, so each needs its own
+function of the parameters: the one-hot index lets the first layer hold them.
+
+1D family: du/dx = sum_{m=1..3} c_m cos(m omega x / 3) on [-2 pi, 2 pi] with the hard constraint
+tanh(omega x) (u(0) = 0), J subdomains of K features.  Near a centre mu_j each mode is a
+combination of sin and cos of its phase phi_m = m omega mu_j / 3, so the weights are
+f = (c_m sin phi_m, c_m cos phi_m), m = 1..3, and the inputs (omega / 50, one-hot j).
+
+2D family: -Lap u = f on [0, 1]^2, u = sum_{m=1..3} c_m sin(n_m pi x) sin(n_m pi y) with
+n_m = max(1, round(m omega / 15)) and the hard constraint tanh(omega s) tanh(omega (1 - s)) per
+axis, 16 x 16 subdomains of K features.  Each mode's contribution is one fixed function of
+(omega, n_m, subdomain), so the weights are f = c and the inputs
+(omega / 50, n_1 / 10, n_2 / 10, n_3 / 10, one-hot j).
 """
 from __future__ import annotations
 
@@ -29,9 +37,16 @@ from .elmfb import MLP, Batch
 N_MOD = 6
 
 
+def _n_sub(spec):
+    n = 1
+    for v in spec.levels[0]:
+        n *= int(v)
+    return n
+
+
 def subdomain_inputs(spec, omega, coeffs):
-    """Network inputs [J, 1 + J] and modulation weights [J, N_MOD] of one instance (single
-    level, 1D) for one coefficient vector."""
+    """Network inputs [J, 1 + J] and modulation weights [J, 6] of one instance of the 1D family
+    (single level) for one coefficient vector."""
     lo, hi = spec.lo[0], spec.hi[0]
     J = spec.levels[0][0]
     mu = lo + (hi - lo) * np.arange(J) / (J - 1) if J > 1 else np.array([(lo + hi) / 2])
@@ -45,9 +60,25 @@ def subdomain_inputs(spec, omega, coeffs):
     return X, F
 
 
+def subdomain_inputs_2d(spec, omega, coeffs):
+    """Network inputs [J, 4 + J] and modulation weights [J, 3] of one instance of the 2D family
+    (J = Jx Jy subdomains of one level) for one coefficient vector."""
+    J = _n_sub(spec)
+    modes = np.asarray(spec.meta["freqs"], dtype=np.float64)
+    head = np.concatenate([[omega / 50.0], modes / 10.0])
+    X = np.concatenate([np.tile(head, (J, 1)), np.eye(J)], axis=1)
+    F = np.tile(np.asarray(coeffs, dtype=np.float64), (J, 1))
+    return X, F
+
+
+def n_mod_of(spec):
+    return 3 if spec.dim == 2 else N_MOD
+
+
 def family_inputs(specs, omegas, C):
     """(X, F) for every (instance, rhs, subdomain), in the coefficient order of a batch solve."""
-    parts = [subdomain_inputs(s, om, c) for s, om, Cg in zip(specs, omegas, C) for c in Cg]
+    fn = subdomain_inputs_2d if specs[0].dim == 2 else subdomain_inputs
+    parts = [fn(s, om, c) for s, om, Cg in zip(specs, omegas, C) for c in Cg]
     return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
 
@@ -55,8 +86,8 @@ def coef_blocks(coef, specs, n_rhs):
     """Batch coefficients (per instance [n_rhs][J K]) as [(instance, rhs, subdomain), K]."""
     out, o = [], 0
     for s in specs:
-        n = s.levels[0][0] * s.K
-        out.append(coef[o:o + n_rhs * n].reshape(n_rhs * s.levels[0][0], s.K))
+        n = _n_sub(s) * s.K
+        out.append(coef[o:o + n_rhs * n].reshape(n_rhs * _n_sub(s), s.K))
         o += n_rhs * n
     return np.concatenate(out)
 
@@ -64,37 +95,37 @@ def coef_blocks(coef, specs, n_rhs):
 class WarmStart:
     """Modulated MLP from subdomain inputs to coefficient blocks (targets scaled per column)."""
 
-    def __init__(self, n_in, K, hidden=512, depth=3, max_batch=4096, seed=0):
+    def __init__(self, n_in, K, hidden=512, depth=3, max_batch=4096, seed=0, n_mod=N_MOD):
         from inputs import mlp_init
 
-        self.dims = [n_in] + [hidden] * depth + [N_MOD * K]
-        self.net = MLP(self.dims, max_batch, n_mod=N_MOD)
+        self.dims = [n_in] + [hidden] * depth + [n_mod * K]
+        self.net = MLP(self.dims, max_batch, n_mod=n_mod)
         self.net.set_params(mlp_init(self.dims, seed))
         self.max_batch = max_batch
         self.scale = np.ones(K)
 
     def fit(self, X, F, Y, epochs, lr=1e-3, seed=0, log=None):
         """Adam on the mean-squared error of the scaled targets (scaling only, so the model stays
-        linear in F); returns the loss history (the last mini-batch's loss of every epoch)."""
+        linear in F); returns the loss history (the last mini-batch's loss of every epoch).  The
+        samples are copied to the device once; each epoch visits them in a seeded random order."""
         import torch
 
         self.scale = Y.std(axis=0) + 1e-12
-        T = (Y / self.scale).astype(np.float32)
-        Xf, Ff = X.astype(np.float32), F.astype(np.float32)
+        xs = torch.as_tensor(X.astype(np.float32)).cuda()
+        fs = torch.as_tensor(F.astype(np.float32)).cuda()
+        ts = torch.as_tensor((Y / self.scale).astype(np.float32)).cuda()
         rng = np.random.default_rng(seed)
         hist = []
         bs = min(self.max_batch, len(X))
         t0 = time.perf_counter()
         for ep in range(epochs):
-            perm = rng.permutation(len(X))
-            xd = torch.as_tensor(Xf[perm]).cuda()
-            fd = torch.as_tensor(Ff[perm]).cuda()
-            td = torch.as_tensor(T[perm]).cuda()
+            perm = torch.as_tensor(rng.permutation(len(X))).cuda()
             nb = len(X) // bs
             loss = None
             for b in range(nb):
-                sl = slice(b * bs, (b + 1) * bs)
-                loss = self.net.train_step(xd[sl], td[sl], f=fd[sl], lr=lr, want_loss=b == nb - 1)
+                idx = perm[b * bs:(b + 1) * bs]
+                loss = self.net.train_step(xs[idx], ts[idx], f=fs[idx], lr=lr,
+                                           want_loss=b == nb - 1)
             hist.append(loss)
             if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
                 log(f"epoch {ep}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
@@ -114,14 +145,15 @@ class WarmStart:
         self.net.destroy()
 
 
-def family_batch(omegas, C, store_prec="fp32"):
-    """Batch of warm-family instances (one per omega, its rows of C as right-hand sides),
-    assembled, with their specs and per-pair ||h||."""
+def family_batch(omegas, C, store_prec="fp32", dim=1):
+    """Batch of warm-family instances of the 1D or 2D family (one per omega, its rows of C as
+    right-hand sides), assembled, with their specs and per-pair ||h||."""
     import torch
 
     from inputs import configs, feature_params
 
-    specs = [configs.warm_family_1d(om, Cg[0]) for om, Cg in zip(omegas, C)]
+    make = configs.warm_family_2d if dim == 2 else configs.warm_family_1d
+    specs = [make(om, Cg[0]) for om, Cg in zip(omegas, C)]
     feats = [feature_params(s) for s in specs]
     R = C.shape[1]
     B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R, store_prec=store_prec)

@@ -80,6 +80,27 @@ def test_mlp_gradients_match_oracle(net):
     assert abs(float(g @ d) - fd) <= 3e-2 * abs(fd) + 1e-6
 
 
+def test_mlp_gradients_split_k_match_oracle(net):
+    """A batch long enough that the weight gradients are summed over k in several parts (1,500
+    rows: 4 parts of 384 rows for the 512 x 512 layers, the last one ragged, 5 for the first
+    layer) and then in order: the same bound against the oracle as a single pass."""
+    torch = torch_mod()
+    p = mlp_init(DIMS, 6)
+    net.set_params(p)
+    X, T = _data(1500, 13)
+    loss = net.train_step(torch.as_tensor(X).cuda(), torch.as_tensor(T).cuda(), update=False)
+    g = net.get_grads()
+    params = omlp.unflatten(p.astype(np.float64), DIMS)
+    y, acts = omlp.forward(params, X.astype(np.float64), bf16=True)
+    lo, dy = omlp.mse(y, T.astype(np.float64))
+    go = omlp.unflatten(omlp.flatten(omlp.backward(params, acts, dy, bf16=True)), DIMS)
+    assert abs(loss - lo) <= 1e-3 * lo
+    for l, ((gW, gb), (oW, ob)) in enumerate(zip(omlp.unflatten(g.astype(np.float64), DIMS), go)):
+        eW, eb = _rel(gW, oW), _rel(gb, ob)
+        print(f"layer {l}: dW rel diff {eW:.2e}, db rel diff {eb:.2e}")
+        assert eW <= 5e-3 and eb <= 5e-3
+
+
 def test_mlp_adam_step_matches_formula(net):
     """One Adam step from the GPU's own gradient: the FP32 update equals the float64 formula."""
     torch = torch_mod()
