@@ -22,9 +22,13 @@ f = (c_m sin phi_m, c_m cos phi_m), m = 1..3, and the inputs (omega / 50, one-ho
 
 2D family: -Lap u = f on [0, 1]^2, u = sum_{m=1..3} c_m sin(n_m pi x) sin(n_m pi y) with
 n_m = max(1, round(m omega / 15)) and the hard constraint tanh(omega s) tanh(omega (1 - s)) per
-axis, 16 x 16 subdomains of K features.  Each mode's contribution is one fixed function of
-(omega, n_m, subdomain), so the weights are f = c and the inputs
-(omega / 50, n_1 / 10, n_2 / 10, n_3 / 10, one-hot j).
+axis, 16 x 16 subdomains of K features.  Each mode's contribution is one function G(omega, n, j)
+of the frequency, the mode number and the subdomain, the same for every m: the network is not
+modulated but learns G from inputs (omega / 50, n / 10, one-hot j), and the prediction is
+sum_u c'_u G(omega, u, j) over the distinct mode numbers u (c'_u the sum of the c_m with
+n_m = u).  Its targets come from the training solves themselves: the 8 right-hand sides of an
+omega share the matrix, so their coefficient blocks are, up to the solves' accuracy, the same
+combinations of the per-mode blocks, which a least-squares fit per omega recovers.
 """
 from __future__ import annotations
 
@@ -71,8 +75,66 @@ def subdomain_inputs_2d(spec, omega, coeffs):
     return X, F
 
 
-def n_mod_of(spec):
-    return 3 if spec.dim == 2 else N_MOD
+def distinct_modes(spec, C):
+    """Distinct mode numbers u of a 2D instance and the coefficient of each, c'_u = sum of the
+    c_m with n_m = u, for every coefficient vector in C: (modes, [len(C), len(modes)])."""
+    freqs = list(spec.meta["freqs"])
+    um = sorted(set(freqs))
+    A = np.array([[sum(c[m] for m in range(len(freqs)) if freqs[m] == u) for u in um]
+                  for c in np.atleast_2d(C)])
+    return um, A
+
+
+def mode_inputs(spec, omega, n):
+    """Network inputs [J, 2 + J] of the per-mode model: (omega / 50, n / 10, one-hot j)."""
+    J = _n_sub(spec)
+    return np.concatenate([np.tile([omega / 50.0, n / 10.0], (J, 1)), np.eye(J)], axis=1)
+
+
+def mode_targets(specs, omegas, C, Y):
+    """Per-mode training set of the 2D family: for each omega, the blocks G_u [J, K] of every
+    distinct mode from a least-squares fit of its right-hand sides' blocks Y_r = sum_u A_ru G_u;
+    returns (inputs, targets) with one row per (omega, mode, subdomain)."""
+    X, T = [], []
+    o = 0
+    for s, om, Cg in zip(specs, omegas, C):
+        J, R = _n_sub(s), Cg.shape[0]
+        Yg = Y[o:o + R * J].reshape(R, J * s.K)
+        o += R * J
+        um, A = distinct_modes(s, Cg)
+        G = np.linalg.lstsq(A, Yg, rcond=None)[0]
+        for i, u in enumerate(um):
+            X.append(mode_inputs(s, om, u))
+            T.append(G[i].reshape(J, s.K))
+    return np.concatenate(X), np.concatenate(T)
+
+
+def training_set(specs, omegas, C, Y):
+    """(inputs, modulation weights or None, targets) of the family's model from the training
+    solves' coefficient blocks Y [(instance, rhs, subdomain), K]."""
+    if specs[0].dim == 2:
+        X, T = mode_targets(specs, omegas, C, Y)
+        return X, None, T
+    X, F = family_inputs(specs, omegas, C)
+    return X, F, Y
+
+
+def predict(model, specs, omegas, C):
+    """Predicted coefficient blocks [(instance, rhs, subdomain), K] for every pair."""
+    if specs[0].dim != 2:
+        return model.predict(*family_inputs(specs, omegas, C))
+    rows, combos = [], []
+    for s, om, Cg in zip(specs, omegas, C):
+        um, A = distinct_modes(s, Cg)
+        rows += [mode_inputs(s, om, u) for u in um]
+        combos.append((A, _n_sub(s), len(um)))
+    G = model.predict(np.concatenate(rows))
+    out, o = [], 0
+    for A, J, U in combos:
+        Gi = G[o:o + U * J].reshape(U, J, -1)
+        o += U * J
+        out.append(np.einsum("ru,ujk->rjk", A, Gi).reshape(-1, Gi.shape[2]))
+    return np.concatenate(out)
 
 
 def family_inputs(specs, omegas, C):
@@ -112,7 +174,7 @@ class WarmStart:
 
         self.scale = Y.std(axis=0) + 1e-12
         xs = torch.as_tensor(X.astype(np.float32)).cuda()
-        fs = torch.as_tensor(F.astype(np.float32)).cuda()
+        fs = None if F is None else torch.as_tensor(F.astype(np.float32)).cuda()
         ts = torch.as_tensor((Y / self.scale).astype(np.float32)).cuda()
         rng = np.random.default_rng(seed)
         hist = []
@@ -124,20 +186,21 @@ class WarmStart:
             loss = None
             for b in range(nb):
                 idx = perm[b * bs:(b + 1) * bs]
-                loss = self.net.train_step(xs[idx], ts[idx], f=fs[idx], lr=lr,
-                                           want_loss=b == nb - 1)
+                loss = self.net.train_step(xs[idx], ts[idx], f=None if fs is None else fs[idx],
+                                           lr=lr, want_loss=b == nb - 1)
             hist.append(loss)
             if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
                 log(f"epoch {ep}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
         return hist
 
-    def predict(self, X, F):
+    def predict(self, X, F=None):
         import torch
 
         out = []
         for o in range(0, len(X), self.max_batch):
             xd = torch.as_tensor(X[o:o + self.max_batch].astype(np.float32)).cuda()
-            fd = torch.as_tensor(F[o:o + self.max_batch].astype(np.float32)).cuda()
+            fd = (None if F is None else
+                  torch.as_tensor(F[o:o + self.max_batch].astype(np.float32)).cuda())
             out.append(self.net.forward(xd, fd).cpu().numpy().astype(np.float64))
         return np.concatenate(out) * self.scale
 
