@@ -79,7 +79,7 @@ def parse():
                    help="batched workloads: residual tolerance (default 1e-6 for batch, 1e-4 "
                         "for warm, 1e-3 for warm2d)")
     p.add_argument("--epochs", type=int, default=None,
-                   help="warm workloads: MLP training epochs (default 100)")
+                   help="warm workloads: MLP training epochs (default 100 for warm, 300 for warm2d)")
     p.add_argument("--warm-inner", type=int, default=None,
                    help="warm workloads: inner LSQR steps per refinement step")
     p.add_argument("--warm-outer", type=int, default=None,
@@ -527,16 +527,18 @@ def run_warm(args):
     inner = args.warm_inner or (2000 if dim == 1 else 4000)
     outer = args.warm_outer or (10 if dim == 1 else 4)
     btol = args.batch_btol_given if args.batch_btol_given else (1e-4 if dim == 1 else 1e-3)
-    epochs = args.epochs or 100
-    chunk = 512 if dim == 1 else 128
+    epochs = args.epochs or (100 if dim == 1 else 300)
+    chunk = 512 if dim == 1 else 64
     store = "fp32"
     om, C = configs.warm_groups(args.warm_train_groups, 5)
     parts, infos, t_data = [], [], 0.0
     for c0 in range(0, len(om), chunk):
         B, specs, _ = ws.family_batch(om[c0:c0 + chunk], C[c0:c0 + chunk], dim=dim)
         B.tune(store, reps=3)
+        log(f"training omegas {c0}..{c0 + len(specs) - 1}: batch assembled")
         coef, inf, t = ws.solve_batch(B, btol=btol * 0.1, atol=btol * 0.1, inner=inner,
                                       outer=outer)
+        log(f"training omegas {c0}..{c0 + len(specs) - 1}: solved in {t:.1f} s")
         X, F, T = ws.training_set(specs, om[c0:c0 + chunk], C[c0:c0 + chunk],
                                   ws.coef_blocks(coef, specs, C.shape[1]))
         parts.append((X.astype(np.float32), None if F is None else F.astype(np.float32), T))
@@ -561,9 +563,11 @@ def run_warm(args):
     om2, C2 = configs.warm_groups(args.warm_test_groups, 6)
     B2, specs2, hn2 = ws.family_batch(om2, C2, dim=dim)
     shape = B2.tune(store, reps=3)
+    log("held-out batch assembled")
     # a pair is solved at ||r|| <= btol ||h|| or, for the pairs whose optimal residual lies above
     # that, at least-squares optimality with atol = btol
     yc, cold, t_cold = ws.solve_batch(B2, btol=btol, inner=inner, outer=outer, atol=btol)
+    log(f"cold solve {t_cold:.2f} s")
 
     def step():
         torch.cuda.synchronize()

@@ -129,6 +129,16 @@ __device__ __forceinline__ double pair_scale(const SolveState* st, int idx, bool
   return use_v ? s.sv : s.su;
 }
 
+// True when every right-hand side of the instance has stopped: the Krylov kernels then skip the
+// instance's blocks, rows and columns (their values are read only for pairs still iterating),
+// so a batch costs what its active instances cost.
+__device__ __forceinline__ bool inst_all_done(const SolveState* st, int inst, int R) {
+  if (!st) return false;
+  for (int j = 0; j < R; ++j)
+    if (!st[inst * R + j].done) return false;
+  return true;
+}
+
 // Sum 8 per-thread values over the NW waves of a workgroup: transposing butterfly in each wave,
 // then the NW wave sums in fixed order.  Value j is returned in thread j (j < 8); every thread
 // must call it.
@@ -229,6 +239,7 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
                                                 double* __restrict__ tpart) {
   __shared__ double cs[kBatchMaxK][kMaxRhs];
   const DevBlock B = blocks[blockIdx.x];
+  if (inst_all_done(st, B.inst, R)) return;
   const int K = geos[B.inst].K;
   for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
     const int k = e >> 3, j = e & 7;
@@ -281,6 +292,7 @@ __global__ void __launch_bounds__(256) k_bt_gather(const Geo* __restrict__ geos,
   constexpr int NT = 256 / RPT;
   __shared__ double sh[4][kMaxRhs];
   const RowTile t = rtiles[blockIdx.x];
+  if (mode == ROW_LSQR_U && inst_all_done(st, t.inst, R)) return;
   const Geo& g = geos[t.inst];
   const InstInfo I = insts[t.inst];
   double acc[kMaxRhs];
@@ -452,6 +464,7 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
   __shared__ double xs[kBatchMaxK][kMaxRhs];
   __shared__ double sh[4][kMaxRhs];
   const DevBlock B = blocks[blockIdx.x];
+  if (inst_all_done(st, B.inst, R)) return;
   const Geo& g = geos[B.inst];
   const int64_t row0 = insts[B.inst].row_off;
   const int K = g.K, n = B.n, gny = g.ny;
@@ -710,6 +723,7 @@ __global__ void __launch_bounds__(256) k_bt_update(const Geo* __restrict__ geos,
                                                    double* __restrict__ red) {
   __shared__ double sh[4][kMaxRhs];
   const ColTile t = ctiles[blockIdx.x];
+  if (inst_all_done(st, t.inst, R)) return;
   const InstInfo I = insts[t.inst];
   const int64_t q_end = I.col_off + geos[t.inst].n_phi;
   const int64_t ncol = (q_end - t.q0) < 256 ? (q_end - t.q0) : 256;

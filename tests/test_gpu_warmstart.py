@@ -82,7 +82,7 @@ def test_learned_warm_start_2d_gains():
     B.destroy()
     assert F is None and X.shape[1] == 2 + 256 and T.shape[1] == 48
     W = ws.WarmStart(n_in=X.shape[1], K=T.shape[1], max_batch=4096, seed=0, n_mod=1)
-    hist = W.fit(X, None, T, epochs=200, lr=1e-3, seed=0)
+    hist = W.fit(X, None, T, epochs=1000, lr=1e-3, seed=0)
     print(f"data {t_data:.1f} s ({len(X)} samples); loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     assert hist[-1] < 0.5 * hist[0]
 
