@@ -457,8 +457,12 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
                                                  double* __restrict__ out,
                                                  double* __restrict__ red) {
   typedef typename StoreT<PREC>::t in_t;
-  constexpr int NA = kBatchMaxK * TP / 256;          // A entries per thread per tile
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  constexpr int VEC = 16 / (int)sizeof(in_t);        // entries per 16-byte load
+  constexpr int NV = kBatchMaxK * TP / VEC / 256;    // 16-byte loads of A per thread per tile
+  constexpr int TV = TP / VEC;                       // loads per feature row of a tile
   constexpr int NU = (TP * kMaxRhs + 255) / 256;     // U entries per thread per tile
+  static_assert(NV >= 1 && NV * 256 * VEC == kBatchMaxK * TP, "tile shape");
   __shared__ __align__(16) in_t At[kBatchMaxK][TP + 1];
   __shared__ double us[TP][kMaxRhs];
   __shared__ double xs[kBatchMaxK][kMaxRhs];
@@ -475,15 +479,19 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
   // flight while the current one is reduced
   const int ju = threadIdx.x & 7;
   const double usc = ju < R ? pair_scale(st, B.inst * R + ju, false) : 0.0;
-  in_t ra[NA];
+  // A is read 16 bytes at a time: VEC consecutive points of one feature row (rows start on
+  // 8-entry boundaries and ld is a multiple of 8, so a load lies wholly before or after ld; the
+  // row padding between n and ld holds zeros)
+  u32x4_t ra[NV];
   double ru[NU];
   auto fetch = [&](int p0) {
 #pragma unroll
-    for (int m = 0; m < NA; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      const int k = e / TP, c = e - (e / TP) * TP;
-      const int p = p0 + c;
-      ra[m] = (k < K && p < n) ? Ab[(int64_t)k * B.ld + p] : in_t(0);
+    for (int m = 0; m < NV; ++m) {
+      const int g4 = threadIdx.x + 256 * m;
+      const int k = g4 / TV, p = p0 + (g4 - (g4 / TV) * TV) * VEC;
+      ra[m] = (k < K && p + VEC <= B.ld)
+                  ? *reinterpret_cast<const u32x4_t*>(Ab + (int64_t)k * B.ld + p)
+                  : u32x4_t{0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
@@ -507,9 +515,13 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
   fetch(0);
   for (int p0 = 0; p0 < n; p0 += TP) {
 #pragma unroll
-    for (int m = 0; m < NA; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      At[e / TP][e - (e / TP) * TP] = ra[m];
+    for (int m = 0; m < NV; ++m) {
+      const int g4 = threadIdx.x + 256 * m;
+      const int k = g4 / TV, c = (g4 - (g4 / TV) * TV) * VEC;
+      in_t v[VEC];
+      __builtin_memcpy(v, &ra[m], 16);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) At[k][c + i] = v[i];
     }
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
