@@ -580,25 +580,33 @@ __global__ void __launch_bounds__(256) k_bt_bj_recover(const Geo* __restrict__ g
 
 // ---------------------------------------------------------------- recurrences
 
-// sum of an instance's tile partials for one right-hand side, in tile order
+// The per-pair scalar kernels run one wavefront per (instance, rhs) pair: pair
+// blockIdx.x * 4 + wave.  Sum of an instance's tile partials for one right-hand side: each lane
+// sums tiles lane, lane + 64, ..., then a fixed butterfly over the wavefront (lane 0's value is
+// the one used).
 __device__ __forceinline__ double seg_sum(const double* red, int t0, int t1, int j) {
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int t = t0; t < t1; ++t) s += red[(int64_t)t * kMaxRhs + j];
-  return s;
+  for (int t = t0 + lane; t < t1; t += 64) s += red[(int64_t)t * kMaxRhs + j];
+  return wave_sum(s);
 }
+
+__device__ __forceinline__ int pair_index() { return blockIdx.x * 4 + (threadIdx.x >> 6); }
 
 // bnorm = ||h||, beta = ||u||, su = 1/beta  (row partials)
 __global__ void k_bt_lsqr_init(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
                                int R, const double* __restrict__ red_b,
                                const double* __restrict__ red_u, double atol, double btol,
                                int iter_lim, const BtOuter* __restrict__ ot, double inner_rel) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   const int i = idx / R, j = idx - (idx / R) * R;
   const InstInfo I = insts[i];
+  const double su2 = seg_sum(red_u, I.rt0, I.rt1, j), sb2 = seg_sum(red_b, I.rt0, I.rt1, j);
+  if ((threadIdx.x & 63) != 0) return;
   SolveState s{};
-  const double beta = sqrt(seg_sum(red_u, I.rt0, I.rt1, j));
-  s.bnorm = sqrt(seg_sum(red_b, I.rt0, I.rt1, j));
+  const double beta = sqrt(su2);
+  s.bnorm = sqrt(sb2);
   s.beta = beta;
   s.su = beta > 0.0 ? 1.0 / beta : 0.0;
   s.atol = atol;
@@ -628,10 +636,13 @@ __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
                                  const double* __restrict__ red_r,
                                  const double* __restrict__ red_a, double atol, int mode,
                                  double btol, int outer_lim) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   const InstInfo I = insts[idx / R];
   const double rn = sqrt(seg_sum(red_r, I.rt0, I.rt1, idx - (idx / R) * R));
+  const bool use_a = mode == 0 && red_a && atol > 0.0;
+  const double an = use_a ? sqrt(seg_sum(red_a, I.b0, I.b1, idx - (idx / R) * R)) : 0.0;
+  if ((threadIdx.x & 63) != 0) return;
   BtOuter o = mode == 1 ? BtOuter{} : ot[idx];
   if (mode == 1) {
     o.hnorm = rn;
@@ -648,9 +659,7 @@ __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
     } else if (rn <= o.btol * o.hnorm) {
       o.done = 1;
       o.istop = 1;
-    } else if (mode == 0 && red_a && atol > 0.0 &&
-               sqrt(seg_sum(red_a, I.b0, I.b1, idx - (idx / R) * R)) <=
-                   atol * st[idx].anorm * rn) {
+    } else if (use_a && an <= atol * st[idx].anorm * rn) {
       o.done = 1;
       o.istop = 2;
     } else if (o.outer >= outer_lim) {
@@ -664,13 +673,15 @@ __global__ void k_bt_outer_check(BtOuter* ot, const SolveState* __restrict__ st,
 // alpha = ||A^T u||, phibar = beta, rhobar = alpha  (column partials)
 __global__ void k_bt_lsqr_init_alpha(SolveState* st, const InstInfo* __restrict__ insts,
                                      int n_inst, int R, const double* __restrict__ red) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   const int i = idx / R, j = idx - (idx / R) * R;
   const InstInfo I = insts[i];
+  const double sa2 = seg_sum(red, I.b0, I.b1, j);
+  if ((threadIdx.x & 63) != 0) return;
   SolveState& s = st[idx];
   const double beta = s.beta;
-  const double alpha = beta > 0.0 ? sqrt(seg_sum(red, I.b0, I.b1, j)) : 0.0;
+  const double alpha = beta > 0.0 ? sqrt(sa2) : 0.0;
   s.alpha = alpha;
   s.sv = alpha > 0.0 ? 1.0 / alpha : 0.0;
   s.phibar = beta;
@@ -684,12 +695,13 @@ __global__ void k_bt_lsqr_init_alpha(SolveState* st, const InstInfo* __restrict_
 
 __global__ void k_bt_lsqr_beta(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
                                int R, const double* __restrict__ red) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   SolveState& s = st[idx];
   if (s.done) return;
   const InstInfo I = insts[idx / R];
   const double beta = sqrt(seg_sum(red, I.rt0, I.rt1, idx - (idx / R) * R));
+  if ((threadIdx.x & 63) != 0) return;
   s.beta = beta;
   if (beta > 0.0) {
     s.su = 1.0 / beta;
@@ -699,15 +711,17 @@ __global__ void k_bt_lsqr_beta(SolveState* st, const InstInfo* __restrict__ inst
 
 __global__ void k_bt_lsqr_alpha(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
                                 int R, const double* __restrict__ red) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   SolveState& s = st[idx];
   if (s.done) return;
   const InstInfo I = insts[idx / R];
+  const double sa2 = seg_sum(red, I.b0, I.b1, idx - (idx / R) * R);
+  if ((threadIdx.x & 63) != 0) return;
   const double beta = s.beta;
   double alpha = s.alpha;
   if (beta > 0.0) {
-    alpha = sqrt(seg_sum(red, I.b0, I.b1, idx - (idx / R) * R));
+    alpha = sqrt(sa2);
     s.alpha = alpha;
     if (alpha > 0.0) s.sv = 1.0 / alpha;
   }
@@ -765,13 +779,14 @@ __global__ void __launch_bounds__(256) k_bt_update(const Geo* __restrict__ geos,
 
 __global__ void k_bt_lsqr_stop(SolveState* st, const InstInfo* __restrict__ insts, int n_inst,
                                int R, const double* __restrict__ red) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = pair_index();
   if (idx >= n_inst * R) return;
   SolveState& s = st[idx];
   if (s.done) return;
   const InstInfo I = insts[idx / R];
   const double eps = 2.220446049250313e-16;
   const double xnorm = sqrt(seg_sum(red, I.ct0, I.ct1, idx - (idx / R) * R));
+  if ((threadIdx.x & 63) != 0) return;
   s.xnorm = xnorm;
   s.itn += 1;
   const double test1 = s.rnorm / s.bnorm;
@@ -970,7 +985,7 @@ hipError_t launch_bt_axpy(int64_t n, const double* y, double* x, hipStream_t s) 
   return hipGetLastError();
 }
 
-static dim3 pairs_grid(int n) { return dim3((unsigned)((n + 255) / 256)); }
+static dim3 pairs_grid(int n) { return dim3((unsigned)((n + 3) / 4)); }   // a wavefront per pair
 
 hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,
                                const double* red_b, const double* red_u, double atol, double btol,
