@@ -513,7 +513,6 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   ALLOC(h->d_chunks, (int64_t)h->chunks.size() * sizeof(Tile));
   ALLOC(h->d_cstart, (int64_t)h->chunk_start.size() * 4);
   ALLOC(h->d_cov, (int64_t)h->cov.size() * 4);
-  ALLOC(h->d_sync, 3 * sizeof(unsigned int));
   ALLOC(h->d_segs, (int64_t)h->segs.size() * sizeof(AxisSeg));
   ALLOC(h->d_state, sizeof(SolveState));
   ALLOC(h->d_scalar, 64);
@@ -565,9 +564,6 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
   // passes read it with zero weights, so it must hold finite values
   {
     hipError_t ez = hipMemset(h->d_A, 0, (size_t)h->n_store * 8);
-    // arrival counters of the fused LSQR scalar steps start at zero (each launch's last
-    // workgroup resets its counter)
-    if (ez == hipSuccess) ez = hipMemset(h->d_sync, 0, 3 * sizeof(unsigned int));
     if (ez == hipSuccess && h->d_A_lo)
       ez = hipMemset(h->d_A_lo, 0, (size_t)(h->n_store * elem_size(h->lo_prec)));
     if (ez != hipSuccess) {
@@ -575,8 +571,6 @@ elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem*
       return fail(nullptr, ELMFB_E_DEVICE, std::string("hipMemset: ") + hipGetErrorString(ez));
     }
   }
-  if (const char* fz = std::getenv("ELMFB_FUSE_SCALARS"))
-    h->fuse_scalars = !(fz[0] == '0' && fz[1] == 0);
   h->desc.W_host = nullptr;
   h->desc.b_host = nullptr;
   h->desc.bc_pts_host = nullptr;

@@ -118,8 +118,6 @@ struct elmfb_problem_s {
   double* d_hs = nullptr;       // [n_rhs][n_rows + n_bc] when n_rhs > 1
   int64_t hs_cap = 0;           // doubles held by d_hs
   double ms_assemble = 0.0;     // host wall time of the last assembly
-  bool fuse_scalars = true;     // LSQR scalar steps in the last workgroup of their producers
-  unsigned int* d_sync = nullptr;  // 3 arrival counters of those kernels (zero between launches)
   int persist_lds_mode = -1;    // one-workgroup LSQR: 1 matrix in LDS, 0 vectors only, -1 undecided
   double anorm_f = -1.0;        // exact Frobenius norm of the stored matrix (lazy)
   hipStream_t stream = nullptr; // internal stream for captured solves

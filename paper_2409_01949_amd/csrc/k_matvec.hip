@@ -18,7 +18,6 @@
 // All reductions are deterministic (fixed order, no floating-point atomics).
 #include "device.h"
 #include "kernels.h"
-#include "lsqr_scalar.h"
 
 namespace elmfb {
 
@@ -69,17 +68,13 @@ __global__ void __launch_bounds__(256) k_mv_blocks(Geo g, const DevBlock* __rest
       tpart[B.p_off + p + q] = ((acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q])) * sc;
 }
 
-// With sync (not NULL; mode ROW_LSQR_U, no constraint rows) the last workgroup also computes
-// beta from the partials (the step of k_lsqr_beta, bit-identical) into fst, which is st.
 __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __restrict__ blocks,
                                                      const int32_t* __restrict__ cov,
                                                      const double* __restrict__ tpart, int mode,
                                                      double* __restrict__ out,
                                                      const double* __restrict__ bvec,
                                                      const SolveState* __restrict__ st,
-                                                     double* __restrict__ red, SolveState* fst,
-                                                     unsigned int* __restrict__ sync,
-                                                     double* __restrict__ hist) {
+                                                     double* __restrict__ red) {
   __shared__ double sh[4];
   if (st && st->done) return;
   double coef_u = 0.0;
@@ -148,10 +143,6 @@ __global__ void __launch_bounds__(256) k_gather_rows(Geo g, const DevBlock* __re
   if (mode != ROW_STORE) {
     const double s = block_sum256(acc, sh);
     if (threadIdx.x == 0) red[blockIdx.x] = s;
-    if (sync && last_workgroup(sync)) {
-      const double tot = sum_partials_device(red, gridDim.x, sh);
-      if (threadIdx.x == 0) lsqr_beta_scalar(fst, tot, hist);
-    }
   }
 }
 
@@ -223,8 +214,6 @@ __global__ void __launch_bounds__(256) k_rmv_chunks(Geo g, const DevBlock* __res
 // bc (may be NULL): the dense soft-constraint rows [n_bc][n_phi]; their part of column q,
 // sum_b bc[b][q] u[n_rows + b] (u scaled by *uscale when given), is added after the chunk
 // partials.
-// With sync (not NULL; mode COL_LSQR_V) the last workgroup also computes alpha and the plane
-// rotation from the partials (the step of k_lsqr_alpha, bit-identical) into fst, which is st.
 __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __restrict__ cstart,
                                                     const double* __restrict__ part, int mode,
                                                     double* __restrict__ out,
@@ -232,10 +221,7 @@ __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __rest
                                                     double* __restrict__ red,
                                                     const double* __restrict__ bc,
                                                     const double* __restrict__ u,
-                                                    const double* __restrict__ uscale,
-                                                    SolveState* fst,
-                                                    unsigned int* __restrict__ sync,
-                                                    double* __restrict__ hist) {
+                                                    const double* __restrict__ uscale) {
   __shared__ double sh[4];
   if (st && st->done) return;
   const int K = g.K;
@@ -281,10 +267,6 @@ __global__ void __launch_bounds__(256) k_rmv_finish(Geo g, const int32_t* __rest
   if (mode != COL_STORE) {
     const double s = block_sum256(acc, sh);
     if (threadIdx.x == 0) red[blockIdx.x] = s;
-    if (sync && last_workgroup(sync)) {
-      const double tot = sum_partials_device(red, gridDim.x, sh);
-      if (threadIdx.x == 0) lsqr_alpha_scalar(fst, tot, hist);
-    }
   }
 }
 
@@ -328,15 +310,7 @@ hipError_t launch_gather_rows(const Geo& g, const DevBlock* blocks, const int32_
                               const double* tpart, int mode, double* out, const double* bvec,
                               const SolveState* st, double* red, int n_wg, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_rows, dim3(n_wg), dim3(256), 0, s, g, blocks, cov, tpart, mode, out,
-                     bvec, st, red, nullptr, nullptr, nullptr);
-  return hipGetLastError();
-}
-hipError_t launch_gather_rows_beta(const Geo& g, const DevBlock* blocks, const int32_t* cov,
-                                   const double* tpart, double* out, SolveState* st, double* red,
-                                   int n_wg, unsigned int* sync, double* hist, hipStream_t s) {
-  if (g.n_bc > 0 || !sync) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gather_rows, dim3(n_wg), dim3(256), 0, s, g, blocks, cov, tpart,
-                     (int)ROW_LSQR_U, out, nullptr, st, red, st, sync, hist);
+                     bvec, st, red);
   return hipGetLastError();
 }
 
@@ -365,17 +339,7 @@ hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const dou
                              const double* bc, const double* u, const double* uscale,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_rmv_finish, dim3(n_wg), dim3(256), 0, s, g, chunk_start, part, mode, out,
-                     st, red, g.n_bc > 0 ? bc : nullptr, u, uscale, nullptr, nullptr, nullptr);
-  return hipGetLastError();
-}
-hipError_t launch_rmv_finish_alpha(const Geo& g, const int32_t* chunk_start, const double* part,
-                                   double* out, SolveState* st, double* red, int n_wg,
-                                   const double* bc, const double* u, const double* uscale,
-                                   unsigned int* sync, double* hist, hipStream_t s) {
-  if (!sync) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rmv_finish, dim3(n_wg), dim3(256), 0, s, g, chunk_start, part,
-                     (int)COL_LSQR_V, out, st, red, g.n_bc > 0 ? bc : nullptr, u, uscale, st, sync,
-                     hist);
+                     st, red, g.n_bc > 0 ? bc : nullptr, u, uscale);
   return hipGetLastError();
 }
 hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const double* part,

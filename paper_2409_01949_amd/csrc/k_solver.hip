@@ -6,7 +6,6 @@
 // the scale as they read.
 #include "device.h"
 #include "kernels.h"
-#include "lsqr_scalar.h"
 
 namespace elmfb {
 
@@ -116,7 +115,17 @@ __global__ void __launch_bounds__(256) k_lsqr_beta(SolveState* st, const double*
   __shared__ double sh[4];
   if (st->done) return;
   const double s = reduce_partials(red, n, sh);
-  if (threadIdx.x == 0) lsqr_beta_scalar(st, s, hist);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(s);
+    st->beta = beta;
+    const int i = st->itn + 1;
+    if (hist && i < kHistCap) hist[2 * i + 1] = beta;
+    if (beta > 0.0) {
+      st->su = 1.0 / beta;
+      const double a = st->alpha;
+      st->anorm = sqrt(st->anorm * st->anorm + a * a + beta * beta);
+    }
+  }
 }
 
 // alpha = ||A^T u - beta v||, sv = 1/alpha, then the plane rotation of this step.
@@ -126,17 +135,37 @@ __global__ void __launch_bounds__(256) k_lsqr_alpha(SolveState* st, const double
   __shared__ double sh[4];
   if (st->done) return;
   const double s = reduce_partials(red, n, sh);
-  if (threadIdx.x == 0) lsqr_alpha_scalar(st, s, hist);
+  if (threadIdx.x == 0) {
+    const double beta = st->beta;
+    double alpha = st->alpha;
+    if (beta > 0.0) {
+      alpha = sqrt(s);
+      st->alpha = alpha;
+      if (alpha > 0.0) st->sv = 1.0 / alpha;
+    }
+    const int i = st->itn + 1;
+    if (hist && i < kHistCap) hist[2 * i] = alpha;
+    const double rhobar = st->rhobar;
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double c = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    st->rhobar = -c * alpha;
+    const double phi = c * st->phibar;
+    const double phibar = sn * st->phibar;
+    st->phibar = phibar;
+    st->t1 = phi / rho;
+    st->t2 = -theta / rho;
+    st->rnorm = phibar;
+    st->arnorm = alpha * fabs(c) * phibar;
+  }
 }
 
-// x += t1 w ; w = v/alpha + t2 w ; partial ||x||^2.  With sync (not NULL) the last workgroup
-// also runs the stopping tests (the step of k_lsqr_stop, bit-identical).
+// x += t1 w ; w = v/alpha + t2 w ; partial ||x||^2.
 __global__ void __launch_bounds__(256) k_lsqr_update(Geo g, double* __restrict__ x,
                                                      double* __restrict__ w,
                                                      const double* __restrict__ v,
-                                                     SolveState* __restrict__ st,
-                                                     double* __restrict__ red,
-                                                     unsigned int* __restrict__ sync) {
+                                                     const SolveState* __restrict__ st,
+                                                     double* __restrict__ red) {
   __shared__ double sh[4];
   if (st->done) return;
   const double t1 = st->t1, t2 = st->t2, sv = st->sv;
@@ -151,10 +180,6 @@ __global__ void __launch_bounds__(256) k_lsqr_update(Geo g, double* __restrict__
   }
   const double s = block_sum256(acc, sh);
   if (threadIdx.x == 0) red[blockIdx.x] = s;
-  if (sync && last_workgroup(sync)) {
-    const double tot = sum_partials_device(red, gridDim.x, sh);
-    if (threadIdx.x == 0) lsqr_stop_scalar(st, tot);
-  }
 }
 
 // Paige-Saunders stopping tests (conlim off).
@@ -162,7 +187,24 @@ __global__ void __launch_bounds__(256) k_lsqr_stop(SolveState* st, const double*
   __shared__ double sh[4];
   if (st->done) return;
   const double s = reduce_partials(red, n, sh);
-  if (threadIdx.x == 0) lsqr_stop_scalar(st, s);
+  if (threadIdx.x == 0) {
+    const double eps = 2.220446049250313e-16;
+    const double xnorm = sqrt(s);
+    st->xnorm = xnorm;
+    st->itn += 1;
+    const double anorm = st->anorm, rnorm = st->rnorm, bnorm = st->bnorm;
+    const double test1 = rnorm / bnorm;
+    const double test2 = st->arnorm / (anorm * rnorm + eps);
+    const double t1 = test1 / (1.0 + anorm * xnorm / bnorm);
+    const double rtol = st->btol + st->atol * anorm * xnorm / bnorm;
+    int istop = 0;
+    if (1.0 + test2 <= 1.0) istop = 5;
+    if (1.0 + t1 <= 1.0) istop = 4;
+    if (test2 <= st->atol) istop = 2;
+    if (test1 <= rtol) istop = 1;
+    if (istop == 0 && st->itn >= st->iter_lim) istop = 7;
+    if (istop != 0) { st->istop = istop; st->done = 1; }
+  }
 }
 
 // ---- CGLS
@@ -319,9 +361,8 @@ hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, double* h
   return hipGetLastError();
 }
 hipError_t launch_lsqr_update(const Geo& g, double* x, double* w, const double* v,
-                              SolveState* st, double* red, int n_wg, hipStream_t s,
-                              unsigned int* sync) {
-  hipLaunchKernelGGL(k_lsqr_update, dim3(n_wg), dim3(256), 0, s, g, x, w, v, st, red, sync);
+                              const SolveState* st, double* red, int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_update, dim3(n_wg), dim3(256), 0, s, g, x, w, v, st, red);
   return hipGetLastError();
 }
 hipError_t launch_lsqr_stop(SolveState* st, const double* red, int n, hipStream_t s) {

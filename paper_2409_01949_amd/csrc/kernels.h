@@ -34,11 +34,6 @@ hipError_t launch_mv_blocks(const Geo& g, int prec, const DevBlock* blocks, cons
 hipError_t launch_gather_rows(const Geo& g, const DevBlock* blocks, const int32_t* cov,
                               const double* tpart, int mode, double* out, const double* bvec,
                               const SolveState* st, double* red, int n_wg, hipStream_t s);
-// the same in mode ROW_LSQR_U whose last workgroup also computes beta into st (sync: a zeroed
-// counter; no constraint rows)
-hipError_t launch_gather_rows_beta(const Geo& g, const DevBlock* blocks, const int32_t* cov,
-                                   const double* tpart, double* out, SolveState* st, double* red,
-                                   int n_wg, unsigned int* sync, double* hist, hipStream_t s);
 // stage 1 of x = A^T u: per chunk partial dot products [n_chunks][K]
 hipError_t launch_rmv_chunks(const Geo& g, int prec, const DevBlock* blocks, const Tile* chunks,
                              int64_t n_chunks, const void* A, const double* u,
@@ -54,12 +49,6 @@ hipError_t launch_rmv_finish(const Geo& g, const int32_t* chunk_start, const dou
                              int mode, double* out, const SolveState* st, double* red, int n_wg,
                              const double* bc, const double* u, const double* uscale,
                              hipStream_t s);
-// the same in mode COL_LSQR_V whose last workgroup also computes alpha and the plane rotation
-// into st (sync: a zeroed counter)
-hipError_t launch_rmv_finish_alpha(const Geo& g, const int32_t* chunk_start, const double* part,
-                                   double* out, SolveState* st, double* red, int n_wg,
-                                   const double* bc, const double* u, const double* uscale,
-                                   unsigned int* sync, double* hist, hipStream_t s);
 // Soft-constraint rows (k_bc.hip): assemble them (and their right-hand side entries h[n_rows..]),
 // and their part of y = M v: rows n_rows.. of out in the given RowMode, one partial squared norm
 // to *red (not for ROW_STORE)
@@ -100,10 +89,8 @@ hipError_t launch_lsqr_beta(SolveState* st, const double* red, int n, double* hi
                             hipStream_t s);
 hipError_t launch_lsqr_alpha(SolveState* st, const double* red, int n, double* hist,
                              hipStream_t s);
-// sync (may be NULL): a zeroed counter; the last workgroup then also runs the stopping tests
 hipError_t launch_lsqr_update(const Geo& g, double* x, double* w, const double* v,
-                              SolveState* st, double* red, int n_wg, hipStream_t s,
-                              unsigned int* sync = nullptr);
+                              const SolveState* st, double* red, int n_wg, hipStream_t s);
 hipError_t launch_lsqr_stop(SolveState* st, const double* red, int n, hipStream_t s);
 hipError_t launch_cgls_init(SolveState* st, const double* red_b, int nb, const double* red_r,
                             int nr, const double* red_s, int ns, double anorm_f, hipStream_t s);

@@ -69,24 +69,15 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
                               state_field(h, offsetof(SolveState, sv)), h->d_tpart, st, s)))
       return e;
   }
-  // beta, alpha and the stopping tests run in the last workgroup of the kernel that produces
-  // their partials (bit-identical to separate launches) unless ELMFB_FUSE_SCALARS=0
-  const bool fuse = h->fuse_scalars;
-  if (fuse && g.n_bc == 0) {
-    if ((e = launch_gather_rows_beta(g, h->d_blocks, h->d_cov, h->d_tpart, h->d_u, st, red1, rw,
-                                     h->d_sync, h->d_hist, s)))
-      return e;
-  } else {
-    if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
-                                st, red1, rw, s)))
-      return e;
-    // soft-constraint rows: their u entries and one more norm partial
-    if ((e = launch_bc_rows(g, h->d_bc, c.apply ? h->d_vt : h->d_v,
-                            c.apply ? nullptr : state_field(h, offsetof(SolveState, sv)),
-                            ROW_LSQR_U, h->d_u, nullptr, st, red1 + rw, s)))
-      return e;
-    if ((e = launch_lsqr_beta(st, red1, rw + bc_parts(g), h->d_hist, s))) return e;
-  }
+  if ((e = launch_gather_rows(g, h->d_blocks, h->d_cov, h->d_tpart, ROW_LSQR_U, h->d_u, nullptr,
+                              st, red1, rw, s)))
+    return e;
+  // soft-constraint rows: their u entries and one more norm partial
+  if ((e = launch_bc_rows(g, h->d_bc, c.apply ? h->d_vt : h->d_v,
+                          c.apply ? nullptr : state_field(h, offsetof(SolveState, sv)), ROW_LSQR_U,
+                          h->d_u, nullptr, st, red1 + rw, s)))
+    return e;
+  if ((e = launch_lsqr_beta(st, red1, rw + bc_parts(g), h->d_hist, s))) return e;
   if ((e = launch_rmv_chunks(g, c.prec, h->d_blocks, h->d_chunks, nc, c.A, h->d_u,
                              state_field(h, offsetof(SolveState, su)), h->d_part, st, s)))
     return e;
@@ -96,21 +87,14 @@ hipError_t lsqr_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {
       return e;
     if ((e = launch_bj_apply_t(g, h->d_rinv, h->d_xt, COL_LSQR_V, h->d_v, st, red2, s))) return e;
     na = bj_wg(g);
-  } else if (fuse) {
-    if ((e = launch_rmv_finish_alpha(g, h->d_cstart, h->d_part, h->d_v, st, red2, cw, h->d_bc,
-                                     h->d_u, state_field(h, offsetof(SolveState, su)),
-                                     h->d_sync + 1, h->d_hist, s)))
-      return e;
   } else {
     if ((e = launch_rmv_finish(g, h->d_cstart, h->d_part, COL_LSQR_V, h->d_v, st, red2, cw,
                                h->d_bc, h->d_u, state_field(h, offsetof(SolveState, su)), s)))
       return e;
   }
-  if ((c.apply || !fuse) && (e = launch_lsqr_alpha(st, red2, na, h->d_hist, s))) return e;
-  if ((e = launch_lsqr_update(g, h->d_x, h->d_w, h->d_v, st, red3, cw, s,
-                              fuse ? h->d_sync + 2 : nullptr)))
-    return e;
-  return fuse ? hipSuccess : launch_lsqr_stop(st, red3, cw, s);
+  if ((e = launch_lsqr_alpha(st, red2, na, h->d_hist, s))) return e;
+  if ((e = launch_lsqr_update(g, h->d_x, h->d_w, h->d_v, st, red3, cw, s))) return e;
+  return launch_lsqr_stop(st, red3, cw, s);
 }
 
 hipError_t cgls_iteration(elmfb_problem h, const KCtx& c, hipStream_t s) {

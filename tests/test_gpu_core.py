@@ -235,33 +235,6 @@ def test_graph_and_eager_solves_agree(case, monkeypatch):
     assert torch.equal(a, c)   # deterministic reductions: bit-identical
 
 
-def test_fused_scalar_steps_bit_identical(case, monkeypatch):
-    """beta, alpha and the stopping tests computed by the last workgroup of the kernels that
-    produce their partials (the default) and by separate launches (ELMFB_FUSE_SCALARS=0): the
-    same bits for x, the recurrence scalars, the recorded bidiagonal and the stopping step."""
-    monkeypatch.setenv("ELMFB_PERSISTENT", "0")
-    spec, P, *_ = case
-    torch = torch_mod()
-    monkeypatch.setenv("ELMFB_FUSE_SCALARS", "0")
-    Q, *_ = build(spec)
-    monkeypatch.delenv("ELMFB_FUSE_SCALARS")
-    n = P.sizes["n_phi"]
-    try:
-        for kw in (dict(iter_lim=40, atol=0, btol=0, check_every=7),
-                   dict(iter_lim=3000, atol=1e-7, btol=1e-7, check_every=50)):
-            a = torch.empty(n, dtype=torch.float64, device="cuda")
-            c = torch.empty(n, dtype=torch.float64, device="cuda")
-            ia = P.solve(a, **kw)
-            ic = Q.solve(c, **kw)
-            print(spec.name, kw["iter_lim"], ia["iters"], ia["istop"], ic["iters"], ic["istop"])
-            assert torch.equal(a, c)
-            for k in ("iters", "istop", "rnorm", "arnorm", "anorm", "xnorm"):
-                assert ia[k] == ic[k], k
-            assert P.condition_estimate() == Q.condition_estimate()
-    finally:
-        Q.destroy()
-
-
 def test_warm_start_and_zero_iterations(case):
     spec, P, *_ = case
     torch = torch_mod()
