@@ -34,6 +34,8 @@ class ProblemSpec:
     # "box": the whole box [lo, hi]; "l_shape" (dim 2): the box without its upper-right quarter
     # [mid_x, hi_x] x [mid_y, hi_y], mid = (lo + hi)/2 (Sec. 4.4 eq. helmholtz_problem)
     domain: str = "box"
+    # feature inputs: "local" xbar = (x - mu_j)/sigma_l (the default reading), "global" xbar = x
+    input_norm: str = "local"
 
     @property
     def n_levels(self) -> int:

@@ -4,7 +4,8 @@
     on the support and zero outside, normalised per level by the sum over all subdomains of that
     level, so sum_j omega_j = 1 (Sec. 3 "Problem and model definition");
   * random features (Sec. 3, the shallow network with h = 1; Sec. 4.1 initialisation):
-    phi_q(x) = tanh(W_q . xbar + b_q), xbar = (x - mu_j)/sigma_l (subdomain-local inputs);
+    phi_q(x) = tanh(W_q . xbar + b_q), xbar = (x - mu_j)/sigma_l (subdomain-local inputs, the
+    default reading); with a problem's input_norm "global" the raw coordinates, xbar = x;
   * hard-constraint ansatz (Sec. 4.3 "Hard boundary constraints"):
     C(x) = prod_i tanh(w (x_i - lo_i)) tanh(w (hi_i - x_i)); for the 1D ODE C = tanh(w x);
   * operator rows (Sec. 3 "Definition of the system matrices"):
@@ -106,16 +107,24 @@ def window(x, sd: geo.Subdomain, level_sums):
 
 # ---------------------------------------------------------------- random features
 
-def features(x, sd: geo.Subdomain, W, b):
+def global_inputs(prob) -> bool:
+    return getattr(prob, "input_norm", "local") == "global"
+
+
+def features(x, sd: geo.Subdomain, W, b, global_in=False):
     """phi, grad phi [N,K,d] and Laplacian of phi [N,K] for the K features of one subdomain.
 
-    W [K, d] and b [K] are the subdomain's fixed hidden parameters."""
+    W [K, d] and b [K] are the subdomain's fixed hidden parameters; global_in: xbar = x."""
     N, d = x.shape
-    xbar = (x - sd.mu[None, :]) / sd.sigma[None, :]
+    if global_in:
+        xbar = x
+        c = W                                     # d xbar / dx = 1
+    else:
+        xbar = (x - sd.mu[None, :]) / sd.sigma[None, :]
+        c = W / sd.sigma[None, :]                 # chain rule factor W_i / sigma_i, [K, d]
     z = xbar @ W.T + b[None, :]
     phi = np.tanh(z)
     s = 1.0 - phi * phi
-    c = W / sd.sigma[None, :]                     # chain rule factor W_i / sigma_i, [K, d]
     grad = s[:, :, None] * c[None, :, :]
     lap = -2.0 * phi * s * np.sum(c * c, axis=1)[None, :]
     return phi, grad, lap
@@ -175,7 +184,7 @@ def localized_function(x, prob, sd, W, b, level_sums, ans=None):
     P = C * w
     gP = gC * w[:, None] + C[:, None] * gw
     lP = lC * w + 2.0 * np.sum(gC * gw, axis=1) + C * lw
-    phi, gphi, lphi = features(x, sd, W, b)
+    phi, gphi, lphi = features(x, sd, W, b, global_inputs(prob))
     val = P[:, None] * phi
     grad = gP[:, None, :] * phi[:, :, None] + P[:, None, None] * gphi
     lap = lP[:, None] * phi + 2.0 * np.einsum("nd,nkd->nk", gP, gphi) + P[:, None] * lphi

@@ -37,7 +37,7 @@ def evaluate(prob, W, b, coef, x):
                 v, _, _ = basis.window_hat(xs, sd)
                 w = v / S[m]
             q = slice(sd.q0, sd.q0 + prob.K)
-            phi, _, _ = basis.features(xs, sd, W[q], b[q])
+            phi, _, _ = basis.features(xs, sd, W[q], b[q], basis.global_inputs(prob))
             out[:, m] += w[None, :] * (C2[:, q] @ phi.T)
     out = out * C[None, :] / L
     return out[0] if single else out
