@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define ELMFB_ABI_VERSION 3
+#define ELMFB_ABI_VERSION 4
 #define ELMFB_MAX_LEVELS 8
 #define ELMFB_MAX_BC 4
 #define ELMFB_MAX_BC_PTS 4096
@@ -75,6 +75,11 @@ enum {
  *   - W_host / b_host still hold the parameters of every subdomain of each level's full
  *     J_x x J_y grid (in that full order); the library takes the kept subdomains' rows. */
 enum { ELMFB_DOMAIN_BOX = 0, ELMFB_DOMAIN_L = 1 };
+
+/* Inputs of the random features (Sec. 3: a shallow network per subdomain; the paper does not
+ * state how its inputs are scaled).  LOCAL: xbar = (x - mu_j)/sigma_l, the subdomain's own
+ * coordinates; GLOBAL: xbar = x. */
+enum { ELMFB_INPUT_LOCAL = 0, ELMFB_INPUT_GLOBAL = 1 };
 
 /* Hard-constraint factor C(x) multiplying the network (Sec. 4.3 "Hard boundary constraints"). */
 enum {
@@ -116,7 +121,8 @@ typedef struct elmfb_problem_s* elmfb_problem;
  * with centres lo + j*h, h = (hi-lo)/(J-1), and half-width delta*h/2 (J = 1: the whole axis,
  * window factor 1).  For dim = 1 the second entries of lo/hi/n_points/J are ignored.
  * W_host [n_phi][dim] and b_host [n_phi] are the fixed hidden weights and biases of the
- * random features tanh(W_q . xbar + b_q), xbar = (x - mu_j)/sigma_l, in column order q. */
+ * random features tanh(W_q . xbar + b_q) (xbar per input_norm), in column order q; with both
+ * NULL the library draws them from `seed` (elmfb_draw_features). */
 typedef struct {
   int32_t abi_version;               /* must be ELMFB_ABI_VERSION                            */
   int32_t dim;                       /* 1 or 2                                               */
@@ -158,6 +164,11 @@ typedef struct {
   const double* bc_pts_host;         /* [n_bc_pts][2], inside the box                       */
   const double* bc_pts_val_host;     /* [n_bc_pts] g_b                                      */
   double bc_pts_weight;              /* > 0                                                 */
+  /* ABI 4 */
+  int32_t input_norm;                /* ELMFB_INPUT_LOCAL or ELMFB_INPUT_GLOBAL              */
+  uint64_t seed;                     /* stream of the drawn W, b (W_host = b_host = NULL)    */
+  double w_range[2], b_range[2];     /* W ~ U[w_range[0], w_range[1]), b ~ U[b_range...)
+                                        when drawn; lo <= hi, finite                         */
 } elmfb_problem_desc;
 
 typedef struct {
@@ -225,6 +236,17 @@ typedef struct {
  * handle's device memory and upload W, b and the tables.  Needs a gfx950 device
  * (ELMFB_E_DEVICE otherwise).  Sec. 3, Sec. 4.1. */
 elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out);
+
+/* The random-feature parameters the library draws for `desc` (Sec. 3: W and b fixed at random;
+ * the generator is not stated): for parameter q of the full per-level subdomain grids (level,
+ * then subdomain in x-major order, then feature k; the layout of W_host and b_host),
+ * W[q][a] = U(4q + a) over w_range and b[q] = U(4q + 3) over b_range, where U(c) is
+ * lo + (hi - lo) ((z >> 11) 2^-53) and z the SplitMix64 output (Steele, Lea and Flood 2014)
+ * of state seed + (c + 1) 0x9e3779b97f4a7c15 (mod 2^64), each operation rounded on its own.
+ * W_host [n_params][dim] and b_host [n_params] are caller-owned host arrays with
+ * n_params = K sum_l prod_a J[l][a]; only the geometry fields, seed and ranges of desc are read.
+ * Returns ELMFB_E_INVALID for NULL pointers, bad levels or ranges. */
+elmfb_status elmfb_draw_features(const elmfb_problem_desc* desc, double* W_host, double* b_host);
 
 /* Sizes of the planned system: rows (Sec. 3 "Problem and model definition", the collocation
  * points), columns N_Phi = K sum_l J_l (Sec. 3 "Indexing conventions"), stored entries of the

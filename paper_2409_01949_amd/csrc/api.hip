@@ -131,8 +131,56 @@ std::string validate_impl(const elmfb_problem_desc* d) {
   if (d->store_prec != ELMFB_FP64 && d->store_prec != ELMFB_FP32 && d->store_prec != ELMFB_BF16 &&
       d->store_prec != ELMFB_FP16)
     return "unknown store precision";
-  if (!d->W_host || !d->b_host) return "W_host and b_host are required";
+  if (d->input_norm != ELMFB_INPUT_LOCAL && d->input_norm != ELMFB_INPUT_GLOBAL)
+    return "unknown input_norm";
+  if (!d->W_host != !d->b_host) return "W_host and b_host must both be given or both be NULL";
+  if (!d->W_host) {
+    for (int i = 0; i < 2; ++i)
+      if (!(std::isfinite(d->w_range[i]) && std::isfinite(d->b_range[i])))
+        return "w_range and b_range must be finite";
+    if (d->w_range[0] > d->w_range[1] || d->b_range[0] > d->b_range[1])
+      return "w_range and b_range must have lo <= hi";
+  }
   return "";
+}
+
+// ---- counter-based draws of the random-feature parameters (SplitMix64, Steele, Lea and
+// Flood 2014, in counter mode): value c of stream `seed` is the generator's finaliser of
+// seed + (c + 1) gamma (mod 2^64); U(c) = lo + (hi - lo) u with u the top 53 bits times 2^-53,
+// each operation rounded on its own.
+#pragma STDC FP_CONTRACT OFF
+uint64_t splitmix_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+double uniform_at(uint64_t seed, uint64_t c, double lo, double hi) {
+  const double u = (double)(splitmix_at(seed, c) >> 11) * 0x1p-53;
+  const double span = hi - lo;
+  const double t = span * u;
+  return lo + t;
+}
+
+int64_t full_params(const elmfb_problem_desc& d) {
+  int64_t n = 0;
+  for (int l = 0; l < d.n_levels; ++l) {
+    int64_t s = 1;
+    for (int a = 0; a < d.dim; ++a) s *= d.J[l][a];
+    n += s;
+  }
+  return n * d.K;
+}
+
+// W [n][dim], b [n] for parameter q at counters 4q + a and 4q + 3
+void draw_params(const elmfb_problem_desc& d, double* W, double* b) {
+  const int64_t n = full_params(d);
+  for (int64_t q = 0; q < n; ++q) {
+    for (int a = 0; a < d.dim; ++a)
+      W[q * d.dim + a] = uniform_at(d.seed, 4 * (uint64_t)q + (uint64_t)a, d.w_range[0], d.w_range[1]);
+    b[q] = uniform_at(d.seed, 4 * (uint64_t)q + 3, d.b_range[0], d.b_range[1]);
+  }
 }
 
 // Build every host table of the decomposition.
@@ -158,6 +206,7 @@ std::string plan_impl(elmfb_problem h) {
   }
   g.op = d.op;
   g.ansatz = d.ansatz;
+  g.input_norm = d.input_norm;
   g.ansatz_omega = d.ansatz_omega;
   const int npts[2] = {g.nx, g.ny};
   double lo[2] = {d.lo[0], d.dim == 2 ? d.lo[1] : 0.0};
@@ -414,15 +463,48 @@ void release(elmfb_problem h) {
 namespace elmfb {
 std::string validate_desc(const elmfb_problem_desc* d) { return validate_impl(d); }
 std::string plan_problem(elmfb_problem h) { return plan_impl(h); }
+int64_t feature_param_count(const elmfb_problem_desc& d) { return full_params(d); }
+void draw_feature_params(const elmfb_problem_desc& d, double* W, double* b) {
+  draw_params(d, W, b);
+}
 }  // namespace elmfb
 
 extern "C" {
 
-elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc, elmfb_problem* out) {
+elmfb_status elmfb_draw_features(const elmfb_problem_desc* desc, double* W_host, double* b_host) {
+  if (!desc || !W_host || !b_host) return fail(nullptr, ELMFB_E_INVALID, "NULL argument");
+  if (desc->dim != 1 && desc->dim != 2) return fail(nullptr, ELMFB_E_INVALID, "dim must be 1 or 2");
+  if (desc->n_levels < 1 || desc->n_levels > ELMFB_MAX_LEVELS || desc->K < 1 || desc->K > 256)
+    return fail(nullptr, ELMFB_E_INVALID, "bad levels or K");
+  for (int l = 0; l < desc->n_levels; ++l)
+    for (int a = 0; a < desc->dim; ++a)
+      if (desc->J[l][a] < 1 || desc->J[l][a] > 4096) return fail(nullptr, ELMFB_E_INVALID, "J out of range");
+  for (int i = 0; i < 2; ++i)
+    if (!(std::isfinite(desc->w_range[i]) && std::isfinite(desc->b_range[i])))
+      return fail(nullptr, ELMFB_E_INVALID, "w_range and b_range must be finite");
+  if (desc->w_range[0] > desc->w_range[1] || desc->b_range[0] > desc->b_range[1])
+    return fail(nullptr, ELMFB_E_INVALID, "w_range and b_range must have lo <= hi");
+  draw_params(*desc, W_host, b_host);
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_define_problem(const elmfb_problem_desc* desc_in, elmfb_problem* out) {
   if (!out) return fail(nullptr, ELMFB_E_INVALID, "out is NULL");
   *out = nullptr;
-  const std::string v = validate_impl(desc);
+  const std::string v = validate_impl(desc_in);
   if (!v.empty()) return fail(nullptr, ELMFB_E_INVALID, v);
+  // parameters drawn by the library when the caller passes none
+  elmfb_problem_desc dd = *desc_in;
+  std::vector<double> Wd, bd;
+  if (!dd.W_host) {
+    const int64_t np = full_params(dd);
+    Wd.resize((size_t)(np * dd.dim));
+    bd.resize((size_t)np);
+    draw_params(dd, Wd.data(), bd.data());
+    dd.W_host = Wd.data();
+    dd.b_host = bd.data();
+  }
+  const elmfb_problem_desc* desc = &dd;
   elmfb_problem h = new (std::nothrow) elmfb_problem_s();
   if (!h) return fail(nullptr, ELMFB_E_NOMEM, "host allocation failed");
   h->desc = *desc;

@@ -449,12 +449,23 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
 #undef BALLOC
   // features, W padded to two columns, instance by instance
   std::vector<double> W2((size_t)B->n_phi * 2, 0.0), bb((size_t)B->n_phi, 0.0);
+  std::vector<double> Wd, bd;   // parameters drawn by the library for instances without them
   for (int i = 0; i < n; ++i) {
     const elmfb_problem_desc& d = descs[i];
+    const double* Wi = d.W_host;
+    const double* bi = d.b_host;
+    if (!Wi) {
+      const int64_t np = feature_param_count(d);
+      Wd.assign((size_t)(np * d.dim), 0.0);
+      bd.assign((size_t)np, 0.0);
+      draw_feature_params(d, Wd.data(), bd.data());
+      Wi = Wd.data();
+      bi = bd.data();
+    }
     const int64_t c0 = B->insts[i].col_off;
     for (int64_t q = 0; q < B->nphis[i]; ++q) {
-      for (int a = 0; a < d.dim; ++a) W2[2 * (c0 + q) + a] = d.W_host[q * d.dim + a];
-      bb[c0 + q] = d.b_host[q];
+      for (int a = 0; a < d.dim; ++a) W2[2 * (c0 + q) + a] = Wi[q * d.dim + a];
+      bb[c0 + q] = bi[q];
     }
   }
   hipError_t e = hipSuccess;

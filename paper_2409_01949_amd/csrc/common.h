@@ -94,6 +94,7 @@ struct Geo {
   double inv_sqrt_n;              // 1 / sqrt(N)
   double inv_levels;              // 1 / L
   int32_t op, ansatz;
+  int32_t input_norm;             // ELMFB_INPUT_LOCAL or ELMFB_INPUT_GLOBAL
   double ansatz_omega;
   // per level and axis
   int32_t J[kMaxLevels][2];

@@ -24,6 +24,16 @@ __device__ __forceinline__ double centre(const Geo& g, int l, int a, int j) {
   return t + g.lo[a];
 }
 
+// Input of the random features along axis a of subdomain j of level l at coordinate x, and the
+// divisor of its derivative: subdomain-local (x - mu_j)/sigma_l (ELMFB_INPUT_LOCAL) or the
+// coordinate itself (ELMFB_INPUT_GLOBAL).
+__device__ __forceinline__ double feat_in(const Geo& g, int l, int a, int j, double x) {
+  return g.input_norm == ELMFB_INPUT_GLOBAL ? x : (x - centre(g, l, a, j)) / g.sigma[l][a];
+}
+__device__ __forceinline__ double feat_div(const Geo& g, int l, int a) {
+  return g.input_norm == ELMFB_INPUT_GLOBAL ? 1.0 : g.sigma[l][a];
+}
+
 // Raw window factor (1 + cos(pi t))^2, t = (x - mu)/sigma, and its first two x-derivatives.
 __device__ __forceinline__ void raw_window(double x, double mu, double sigma, double& w,
                                            double& w1, double& w2) {

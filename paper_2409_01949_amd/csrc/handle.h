@@ -156,5 +156,8 @@ hipError_t noalloc_init_device();
 // Descriptor checks and the host-side decomposition plan of one problem (no device work).
 std::string validate_desc(const elmfb_problem_desc* d);
 std::string plan_problem(elmfb_problem h);
+// the library's draw of W, b for a descriptor without them (elmfb_draw_features)
+int64_t feature_param_count(const elmfb_problem_desc& d);
+void draw_feature_params(const elmfb_problem_desc& d, double* W, double* b);
 
 }  // namespace elmfb

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
   const Geo& g = geos[B.inst];
   const int K = g.K;
   const int l = B.level;
-  const double sx = g.sigma[l][0], sy = g.sigma[l][1];
+  const double sx = feat_div(g, l, 0), sy = feat_div(g, l, 1);
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double w1 = W[2 * (int64_t)(B.q0 + k)];
     const double w2 = (g.dim == 2) ? W[2 * (int64_t)(B.q0 + k) + 1] : 0.0;
@@ -67,8 +67,8 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
   const int jl = t.blk - g.bbase[l];
   const int jx = jl / g.J[l][1];
   const int jy = jl - jx * g.J[l][1];
-  const double xb = (grid_coord(g, 0, B.ix0 + lx) - centre(g, l, 0, jx)) / sx;
-  const double yb = (g.dim == 2) ? (grid_coord(g, 1, B.iy0 + ly) - centre(g, l, 1, jy)) / sy : 0.0;
+  const double xb = feat_in(g, l, 0, jx, grid_coord(g, 0, B.ix0 + lx));
+  const double yb = (g.dim == 2) ? feat_in(g, l, 1, jy, grid_coord(g, 1, B.iy0 + ly)) : 0.0;
   const double scale = g.inv_scale;
   const int64_t base = B.a_off + p;
   const int ld = B.ld;

@@ -47,7 +47,8 @@ __global__ void __launch_bounds__(256) k_bc_assemble(Geo g, BcSpec bc,
   double c, c1, c2;
   ansatz_axis(g, 0, x, c, c1, c2);
   const double P = c * gv, P1 = c1 * gv + c * g1;
-  const double xb = (x - mu) / sigma;
+  const double xb = feat_in(g, l, 0, jj, x);
+  const double fd = feat_div(g, l, 0);
   const double scale = bc.w[b] * g.inv_levels;
   for (int k = threadIdx.x; k < g.K; k += blockDim.x) {
     double v = 0.0;
@@ -55,7 +56,7 @@ __global__ void __launch_bounds__(256) k_bc_assemble(Geo g, BcSpec bc,
       const int64_t q = B.q0 + k;
       const double w1 = W[2 * q];
       const double ph = tanh(w1 * xb + bias[q]);
-      v = bc.order[b] == 0 ? P * ph : P1 * ph + P * (1.0 - ph * ph) * (w1 / sigma);
+      v = bc.order[b] == 0 ? P * ph : P1 * ph + P * (1.0 - ph * ph) * (w1 / fd);
       v *= scale;
     }
     Bm[(int64_t)b * g.n_phi + B.q0 + k] = v;
@@ -110,8 +111,8 @@ __global__ void __launch_bounds__(256) k_bc_assemble_pts(Geo g, const DevBlock* 
     double v = 0.0;
     if (w != 0.0) {
       const int l = B.level;
-      const double xb = (p[0] - centre(g, l, 0, B.jx)) / g.sigma[l][0];
-      const double yb = (p[1] - centre(g, l, 1, B.jy)) / g.sigma[l][1];
+      const double xb = feat_in(g, l, 0, B.jx, p[0]);
+      const double yb = feat_in(g, l, 1, B.jy, p[1]);
       const double ph = tanh(W[2 * q] * xb + W[2 * q + 1] * yb + bias[q]);
       v = scale * (w * inv_s[l]) * ph;
     }

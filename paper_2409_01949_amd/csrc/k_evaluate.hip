@@ -107,12 +107,11 @@ __global__ void __launch_bounds__(256) k_evaluate(Geo g, const double* __restric
         nxc = cover_axis(g, l, 0, x, jxs, wxs);
         nyc = cover_axis(g, l, 1, y, jys, wys);
       }
-      const double sx = g.sigma[l][0], sy = g.sigma[l][1];
       double lev = 0.0;
       for (int ax = 0; ax < nxc; ++ax) {
-        const double xb = (x - centre(g, l, 0, jxs[ax])) / sx;
+        const double xb = feat_in(g, l, 0, jxs[ax], x);
         for (int ay = 0; ay < nyc; ++ay) {
-          const double yb = (g.dim == 2) ? (y - centre(g, l, 1, jys[ay])) / sy : 0.0;
+          const double yb = (g.dim == 2) ? feat_in(g, l, 1, jys[ay], y) : 0.0;
           int bi = g.bbase[l] + jxs[ax] * g.J[l][1] + jys[ay];
           if (lshape) {
             bi = g.bmap[g.bmap_off[l] + jxs[ax] * g.J[l][1] + jys[ay]];

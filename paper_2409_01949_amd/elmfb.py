@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libelmfb.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_BC = 4
 MAX_BC_PTS = 4096
 MAX_LEVELS = 8
@@ -66,6 +66,10 @@ class ProblemDesc(ctypes.Structure):
         ("bc_pts_host", ctypes.POINTER(ctypes.c_double)),
         ("bc_pts_val_host", ctypes.POINTER(ctypes.c_double)),
         ("bc_pts_weight", ctypes.c_double),
+        ("input_norm", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("w_range", ctypes.c_double * 2),
+        ("b_range", ctypes.c_double * 2),
     ]
 
 
@@ -162,6 +166,8 @@ def load_library(path: Optional[str] = None):
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "elmfb_define_problem": (i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]),
+        "elmfb_draw_features": (i32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(dbl),
+                                      ctypes.POINTER(dbl)]),
         "elmfb_query": (i32, [P, ctypes.POINTER(Sizes)]),
         "elmfb_points": (i32, [P, P, P]),
         "elmfb_assemble": (i32, [P, P, i32, P]),
@@ -260,12 +266,14 @@ def _check(code, handle=None):
 
 def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K, W, b,
               store_prec="fp64", op_coef=(0.0, 0.0, 0.0), bc=(), domain="box", bc_pts=None,
-              bc_vals=None, bc_weight=0.0):
+              bc_vals=None, bc_weight=0.0, input_norm="local", seed=0, w_range=(-1.0, 1.0),
+              b_range=(-1.0, 1.0)):
     """Descriptor from plain values.  W [n_phi, dim] and b [n_phi] are float64 host arrays
-    (on an L-shaped domain: for every subdomain of each level's full grid); the returned tuple
-    keeps them alive for the duration of the define call.  bc: 1D soft constraints as
-    (x, derivative order, weight sqrt(lambda), value) tuples; bc_pts [n, 2], bc_vals [n],
-    bc_weight: 2D Dirichlet rows at points."""
+    (on an L-shaped domain: for every subdomain of each level's full grid), or both None for the
+    library to draw them from seed over w_range and b_range; the returned tuple keeps them
+    alive for the duration of the define call.  bc: 1D soft constraints as (x, derivative
+    order, weight sqrt(lambda), value) tuples; bc_pts [n, 2], bc_vals [n], bc_weight: 2D
+    Dirichlet rows at points; input_norm "local" or "global" feature inputs."""
     d = ProblemDesc()
     d.abi_version = ABI_VERSION
     d.dim = int(dim)
@@ -289,12 +297,20 @@ def make_desc(dim, op, ansatz, ansatz_omega, lo, hi, n_points, levels, delta, K,
     for i, (x, order, wgt, val) in enumerate(bc[:MAX_BC]):
         d.bc_x[i], d.bc_order[i], d.bc_weight[i], d.bc_value[i] = float(x), int(order), \
             float(wgt), float(val)
-    W = np.ascontiguousarray(W, dtype=np.float64)
-    b = np.ascontiguousarray(b, dtype=np.float64)
-    d.W_host = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    d.b_host = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep = []
+    if W is not None or b is not None:
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        d.W_host = W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.b_host = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep = [W, b]
     d.domain = _DOMAINS[domain] if isinstance(domain, str) else int(domain)
-    keep = [W, b]
+    d.input_norm = {"local": 0, "global": 1}[input_norm] if isinstance(input_norm, str) \
+        else int(input_norm)
+    d.seed = int(seed) & ((1 << 64) - 1)
+    for i in range(2):
+        d.w_range[i] = float(w_range[i])
+        d.b_range[i] = float(b_range[i])
     if bc_pts is not None:
         P = np.ascontiguousarray(bc_pts, dtype=np.float64).reshape(-1, 2)
         G = np.ascontiguousarray(bc_vals, dtype=np.float64).reshape(-1)
@@ -317,7 +333,26 @@ def desc_from_spec(spec, W, b, store_prec="fp64", bc_pts=None, bc_vals=None, bc_
                      spec.n_points, spec.levels, spec.delta, spec.K, W, b, store_prec,
                      op_coef=coef, bc=tuple(meta.get("bc", ())),
                      domain=getattr(spec, "domain", "box"), bc_pts=bc_pts, bc_vals=bc_vals,
-                     bc_weight=bc_weight)
+                     bc_weight=bc_weight, input_norm=getattr(spec, "input_norm", "local"),
+                     seed=getattr(spec, "seed", 0), w_range=getattr(spec, "w_range", (-1.0, 1.0)),
+                     b_range=getattr(spec, "b_range", (-1.0, 1.0)))
+
+
+def draw_features(desc_and_keep):
+    """The library's draw of W [n_params, dim] and b [n_params] for a descriptor (host code)."""
+    lib = load_library()
+    desc, _ = desc_and_keep
+    n = desc.K * sum(int(np.prod([desc.J[l][a] for a in range(desc.dim)]))
+                     for l in range(desc.n_levels))
+    W = np.empty((n, desc.dim), dtype=np.float64)
+    b = np.empty(n, dtype=np.float64)
+    code = lib.elmfb_draw_features(ctypes.byref(desc),
+                                   W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if code != OK:
+        msg = lib.elmfb_last_error(None)
+        raise ElmfbError(code, msg.decode() if msg else "")
+    return W, b
 
 
 def define_problem(desc_and_keep) -> "Problem":
