@@ -409,6 +409,81 @@ def fold_blocks(blocks, factors):
     return out
 
 
+# ---------------------------------------------------------------- block-Jacobi over patches
+#
+# The redundancy that makes M ill-conditioned (Sec. 5 "Conditioning and redundancy") is not only
+# within one subdomain: neighbouring subdomains of a level overlap and their features describe
+# nearly the same functions on the shared points.  Taking P^d neighbouring subdomains of a level
+# as one block of the block-Jacobi preconditioner (a patch) orthonormalises their columns
+# together.  A patch block holds every column of its members on the union of their supports
+# (zero where a member's window vanishes); the preconditioner is then exactly the block-Jacobi
+# one above applied to the patch blocks, and P = 1 is the per-subdomain preconditioner.
+
+
+@dataclass
+class PatchBlock:
+    level: int
+    index: tuple            # patch index per axis (j // P for the members' per-axis indices j)
+    members: list           # the member subdomain blocks, per-axis indices in lexicographic order
+    rows: np.ndarray        # union of the members' rows, sorted
+    cols: np.ndarray        # global columns, member by member (features in order)
+    M: np.ndarray           # [len(rows), len(cols)], zero outside each member's rows
+
+
+def patch_blocks(blocks, P):
+    """Group the subdomain blocks of every level into patches of P consecutive subdomains per
+    axis (the last patch along an axis keeps what is left); patches in order of level, then
+    patch index (x-major), which is also the column order of the preconditioned system."""
+    groups = {}
+    for blk in blocks:
+        key = (blk.sd.level,) + tuple(int(j) // P for j in blk.sd.jj)
+        groups.setdefault(key, []).append(blk)
+    out = []
+    for key in sorted(groups):
+        mem = sorted(groups[key], key=lambda b: tuple(b.sd.jj))
+        rows = np.unique(np.concatenate([np.asarray(b.rows) for b in mem]))
+        cols = np.concatenate([np.arange(b.sd.q0, b.sd.q0 + b.M.shape[1]) for b in mem])
+        M = np.zeros((rows.size, cols.size))
+        c = 0
+        for b in mem:
+            M[np.searchsorted(rows, b.rows), c:c + b.M.shape[1]] = b.M
+            c += b.M.shape[1]
+        out.append(PatchBlock(key[0], key[1:], mem, rows, cols, M))
+    return out
+
+
+def patch_order(pblocks):
+    """Column permutation of the patch system: position i holds original column perm[i]."""
+    return np.concatenate([pb.cols for pb in pblocks])
+
+
+def patch_matvec(pblocks, y, n_rows):
+    """sum over patches of M_p y_p, y in patch column order."""
+    out = np.zeros(n_rows)
+    o = 0
+    for pb in pblocks:
+        k = pb.M.shape[1]
+        out[pb.rows] += pb.M @ y[o:o + k]
+        o += k
+    return out
+
+
+def patch_rmatvec(pblocks, u):
+    """(M_p^T u) for every patch, concatenated in patch column order."""
+    return np.concatenate([pb.M.T @ u[pb.rows] for pb in pblocks])
+
+
+def patch_recover(pblocks, factors, y):
+    """x = R^{-1} y patch by patch, returned in the original column order."""
+    x = np.zeros(y.size)
+    o = 0
+    for pb, R in zip(pblocks, factors):
+        k = pb.M.shape[1]
+        x[pb.cols] = np.linalg.solve(R, y[o:o + k])
+        o += k
+    return x
+
+
 def preconditioned_lsqr(matvec, rmatvec, blocks, factors, h, n, x0=None, **kw):
     """LSQR on M R^{-1} (right block-Jacobi preconditioning); returns (x, result) with
     x = x0 + R^{-1} y, y the LSQR solution for the residual h - M x0."""
