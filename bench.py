@@ -75,6 +75,9 @@ def parse():
     p.add_argument("--secondary-iters", type=int, default=3000,
                    help="inner-iteration budget of the secondary multilevel and batched steps")
     p.add_argument("--batch-n", type=int, default=512)
+    p.add_argument("--batch-patch", type=int, default=2,
+                   help="batched workload: block-Jacobi over patches of P x P neighbouring "
+                        "subdomains (1: per subdomain)")
     p.add_argument("--batch-btol", type=float, default=None,
                    help="batched workloads: residual tolerance (default 1e-6 for batch, 1e-4 "
                         "for warm, 1e-3 for warm2d)")
@@ -305,7 +308,11 @@ def run_batch(args, steps=None, warmup=None, iters=None):
     coef = torch.empty(8 * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
     btol = args.batch_btol
     precond = not args.no_precond
+    patch = args.batch_patch if precond else 1
     B.assemble(fd)
+    if precond:
+        # the passes run on the folded matrix (in the patch layout for patches): tune on it
+        B.precondition(args.shift, patch=patch)
     # launch shapes of the three matrix passes, timed per precision (or from the process's cache)
     tune = {p: B.tune(p, reps=3) for p in sorted({"fp64", store})}
     print(f"# tuned shapes: {tune}", file=sys.stderr, flush=True)
@@ -314,7 +321,7 @@ def run_batch(args, steps=None, warmup=None, iters=None):
         ta = time.perf_counter()
         B.assemble(fd)
         if precond:
-            B.precondition(args.shift)
+            B.precondition(args.shift, patch=patch)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         if mixed:
@@ -348,12 +355,15 @@ def run_batch(args, steps=None, warmup=None, iters=None):
     rows_rhs = B.sizes["n_rows"] * 8
     nnz, nbp = B.sizes["nnz"], B.sizes["n_block_points"]
     N, n_phi = B.sizes["n_rows"], B.sizes["n_phi"]
-    method = (f"batched {'bj-' if precond else ''}"
+    bj_name = f"bj{patch}x{patch}-" if patch > 1 else "bj-"
+    method = (f"batched {bj_name if precond else ''}"
               + (f"mixed-ir ({store} inner)" if mixed else "lsqr-fp64"))
     # rooflines of the three matrix passes of a step, on the matrix the inner steps stream
     kp = store if mixed else "fp64"
-    roof = _batch_pass_roofline(B, kp, tune[kp], "batch512x8",
-                                "the longest matrix pass of a batched Krylov step, 8 rhs")
+    label = f"batch{args.batch_n}x8" + (f"_p{patch}" if patch > 1 else "")
+    roof = _batch_pass_roofline(B, kp, tune[kp], label,
+                                "the longest matrix pass of a batched Krylov step, 8 rhs",
+                                folded=precond)
     n_ok = int(np.sum((stops == 1) | (stops == 2)))
     out = {
         "metric": METRIC, "value": rows_rhs / dt, "unit": "rows/s", "n_gpus": 1,
@@ -363,7 +373,8 @@ def run_batch(args, steps=None, warmup=None, iters=None):
         "config": {"workload": f"batch{args.batch_n}x8", "instances": args.batch_n, "n_rhs": 8,
                    "rows": N, "cols": n_phi, "nnz": nnz,
                    "method": method, "btol": btol, "iter_budget": iters,
-                   "inner": inner if mixed else None, "shift": args.shift if precond else None},
+                   "inner": inner if mixed else None, "shift": args.shift if precond else None,
+                   "patch": patch if precond else None},
         "define_s": t_define, "setup_ms": t_setup * 1e3, "solve_s": t_solve,
         "tuned_shapes": tune,
         "pairs_meeting_stop_test": n_ok, "pairs": int(len(stops)),
@@ -378,16 +389,20 @@ def run_batch(args, steps=None, warmup=None, iters=None):
     }
     B.destroy()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = batch_cpu_baseline(specs, feats, int(its.max()), nnz, rows_rhs)
+        out["cpu_baseline"] = batch_cpu_baseline(specs, feats, int(its.max()), nnz, rows_rhs,
+                                                 patch=patch if precond else None,
+                                                 shift=args.shift)
     return out
 
 
 def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n_lsqr=20,
-                       forcing=None):
+                       forcing=None, patch=None, shift=1e-12):
     """The oracle on a sample of the batch: the smallest, the largest and two seeded instances,
     each assembled (FP64 blocks) and n_lsqr LSQR iterations run for each of its 8 right-hand
-    sides; scaled by entry count to the whole batch and the step's iterations.  1 warm-up + 2
-    repeats at the BLAS's threads, 1 warm-up + 1 repeat at 1 thread."""
+    sides (with patch: on the oracle's block-Jacobi fold over patches of patch^2 subdomains,
+    factors and fold included in the assembly time); scaled by entry count to the whole batch
+    and the step's iterations.  1 warm-up + 2 repeats at the BLAS's threads, 1 warm-up + 1
+    repeat at 1 thread."""
     import numpy as np
     from inputs import configs
     from oracle import assemble as asm
@@ -406,16 +421,22 @@ def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n
             spec, (W, b) = specs[i], feats[i]
             t0 = time.perf_counter()
             blocks = asm.assemble_blocks(spec, W, b)
-            t_asm += time.perf_counter() - t0
             n = len(blocks) * spec.K
+            if patch is not None:
+                pb = linalg.patch_blocks(blocks, patch)
+                fold = linalg.fold_blocks(pb, linalg.block_jacobi_factors(pb, shift))
+                mv = lambda v: linalg.patch_matvec(fold, v, spec.n_rows)
+                rmv = lambda u: linalg.patch_rmatvec(fold, u)
+            else:
+                mv = lambda v: asm.matvec(blocks, v, spec.n_rows)
+                rmv = lambda u: asm.rmatvec(blocks, u, n)
+            t_asm += time.perf_counter() - t0
             ent += sum(blk.M.size for blk in blocks)
             F = configs.batch_forcing(spec) if forcing is None else forcing(i)
             t1 = time.perf_counter()
             for r in range(F.shape[0]):
                 h = asm.rhs(spec, F[r])
-                linalg.lsqr(lambda v: asm.matvec(blocks, v, spec.n_rows),
-                            lambda u: asm.rmatvec(blocks, u, n), h, n, atol=0, btol=0,
-                            iter_lim=n_lsqr)
+                linalg.lsqr(mv, rmv, h, n, atol=0, btol=0, iter_lim=n_lsqr)
             t_it += (time.perf_counter() - t1) / n_lsqr
         return (t_asm + t_it * n_iters) * nnz_total / ent, ent
 
@@ -433,7 +454,9 @@ def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n
         t1s, _ = series(1)
     t_med = float(np.median(ts))
     return {"value": rows_rhs / t_med, "unit": "rows/s", "cores": threads, "kind": "oracle",
-            "sample": (f"instances {pick} ({ent} of {nnz_total} entries): oracle assembly and "
+            "sample": (f"instances {pick} ({ent} of {nnz_total} entries): oracle assembly"
+                       + (f", block-Jacobi factors and fold over {patch} x {patch} patches"
+                          if patch is not None else "") + " and "
                        f"{n_lsqr} LSQR iterations per right-hand side (8 each), scaled by entry "
                        f"count to the batch and the step's {n_iters} iterations; 1 warm-up + 2 "
                        f"repeats at {threads} BLAS threads, median {t_med:.0f} s per step (min "
@@ -441,11 +464,17 @@ def batch_cpu_baseline(specs, feats, n_iters, nnz_total, rows_rhs, n_sample=4, n
             "value_1_thread": rows_rhs / t1s[0]}
 
 
-def _batch_pass_roofline(B, kp, shape, workload, label):
+def _batch_pass_roofline(B, kp, shape, workload, label, folded=False):
     """HBM roofline of the longest of the three matrix passes of a batched Krylov step (8 right-
-    hand sides) on the stored copy of precision kp, with the other two under "also"."""
+    hand sides) on the stored copy of precision kp, with the other two under "also".  With
+    folded, the entries and block points are those of the folded matrix the solves stream (the
+    patch blocks when the factors are of patches)."""
     es = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}[kp]
     nnz, nbp = B.sizes["nnz"], B.sizes["n_block_points"]
+    if folded:
+        tab = B.copy_blocks(folded=True)
+        nnz = int((tab[:, 3] * tab[:, 5] * tab[:, 6]).sum())
+        nbp = int((tab[:, 3] * tab[:, 5]).sum())
     N, n_phi = B.sizes["n_rows"], B.sizes["n_phi"]
     ms_mv, ms_g, ms_rmv = B.time_kernels(kp, reps=5)
     R = 8

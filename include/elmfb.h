@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define ELMFB_ABI_VERSION 4
+#define ELMFB_ABI_VERSION 5
 #define ELMFB_MAX_LEVELS 8
 #define ELMFB_MAX_BC 4
 #define ELMFB_MAX_BC_PTS 4096
@@ -425,10 +425,12 @@ elmfb_status elmfb_batch_query_instances(elmfb_batch b, elmfb_sizes* per_instanc
 /* Copy the stored blocks of every instance into dst_dev: prec = ELMFB_FP64 (M) or the batch's
  * store_prec (its rounded copy, until elmfb_batch_precondition replaces it), or either or'd with
  * ELMFB_COPY_FOLDED for the folded M_b R_b^{-1} in FP64 or its rounding (after
- * elmfb_batch_precondition); ELMFB_E_STATE when that copy is not held.  Each block is
+ * elmfb_batch_precondition; with patch factors, the patch blocks of
+ * elmfb_batch_precondition_patches); ELMFB_E_STATE when that copy is not held.  Each block is
  * [K][nx*ny], points in row-major order of its box.  The block table goes into table_host
- * [n_blocks][8] as int64: instance, level, ix0, nx, iy0, ny, K, element offset; blocks are
- * ordered by instance, then by column.  Either pointer may be NULL. */
+ * [n_blocks][8] as int64: instance, level, ix0, nx, iy0, ny, K (the block's columns), element
+ * offset; blocks are ordered by instance, then by column; a folded copy of patch factors has
+ * elmfb_batch_patch_info's block count.  Either pointer may be NULL. */
 elmfb_status elmfb_batch_copy_blocks(elmfb_batch b, int32_t prec, void* dst_dev,
                                      int64_t* table_host, void* stream);
 
@@ -453,6 +455,34 @@ elmfb_status elmfb_batch_rmatvec(elmfb_batch b, const double* u_dev, double* x_d
  * the stream. */
 elmfb_status elmfb_batch_precondition(elmfb_batch b, double shift, int32_t* n_fallback_host,
                                       void* stream);
+
+/* Block-Jacobi over patches: as elmfb_batch_precondition, with the blocks of the preconditioner
+ * formed by `patch` (1..4) consecutive subdomains along each axis of a level (patch^d
+ * neighbouring subdomains; the last patch along an axis keeps what is left), so the columns of
+ * neighbouring subdomains, whose features nearly coincide on the shared points (the redundancy of
+ * Sec. 5 "Conditioning and redundancy"), are orthonormalised together.  A patch block holds the
+ * columns of its members, member by member in x-major order, on the bounding box of their boxes
+ * (zero where a member's window vanishes); R_p is the Cholesky factor of
+ * M_p^T M_p + shift trace(M_p^T M_p)/nk_p I (nk_p = the patch's columns, at most 512:
+ * ELMFB_E_INVALID otherwise), and M_p R_p^{-1} is formed once in FP64 and in store_prec in the
+ * patch layout (the low-precision copy of M itself is kept).  Preconditioned solves then run on
+ * the patch blocks and return x = R^{-1} y; their coefficients y are in patch column order,
+ * which elmfb_batch_patch_info reports.  patch = 1 is elmfb_batch_precondition.  Factors of one
+ * patch size are held at a time.  Keeps 8 (dense + sum_p nk_p (nk_p+1)/2) bytes, plus the
+ * store_prec copy, on the device (dense: stored entries of the patch blocks); temporary: up to
+ * 4 GiB of Gram scratch, taken in chunks of patches.  Block-Jacobi coordinates
+ * (elmfb_batch_set_coords) need patch = 1 (ELMFB_E_UNSUPPORTED).  Synchronises the stream. */
+elmfb_status elmfb_batch_precondition_patches(elmfb_batch b, double shift, int32_t patch,
+                                              int32_t* n_fallback_host, void* stream);
+
+/* The patch size of the factors held (1 before any preconditioning) in patch_host, the number of
+ * blocks of their folded matrix (patch blocks, or the subdomain blocks for patch 1) in
+ * n_blocks_host, the entries elmfb_batch_copy_blocks copies of it in n_entries_host, and in
+ * perm_host [n_phi] (int32, may be NULL) for every column of the patch column order its column
+ * of x (the identity for patch 1).  Any pointer may be NULL.  (Bookkeeping of the preconditioner
+ * above.) */
+elmfb_status elmfb_batch_patch_info(elmfb_batch b, int32_t* patch_host, int64_t* n_blocks_host,
+                                    int64_t* n_entries_host, int32_t* perm_host);
 
 /* Time the candidate point-tile sizes (16, 32, 64 points per LDS stage) of the batched M^T U
  * pass on the assembled matrix copy of precision `prec` (ELMFB_FP64 or the batch's store_prec),

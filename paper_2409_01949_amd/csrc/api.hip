@@ -368,6 +368,7 @@ std::string plan_impl(elmfb_problem h) {
         B.tabx = segoff[l][0][jx];
         B.taby = segoff[l][1][jy];
         B.level = l;
+        B.nk = d.K;
         const int b = (int)h->blocks.size();
         for (int64_t p0 = 0; p0 < n; p0 += kTile) h->tiles.push_back(Tile{b, (int32_t)p0});
         h->chunk_start.push_back((int32_t)h->chunks.size());

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "handle.h"
@@ -53,6 +54,7 @@ struct elmfb_batch_s {
   double *d_h = nullptr, *d_u = nullptr, *d_v = nullptr, *d_w = nullptr, *d_x = nullptr,
          *d_c = nullptr;
   double* d_tpart = nullptr;
+  int64_t tpart_bp = 0;        // block points d_tpart holds (the subdomain or patch boxes)
   double *d_red_r = nullptr, *d_red_b = nullptr, *d_red_c = nullptr, *d_red_h = nullptr;
   double *d_x0 = nullptr, *d_h0 = nullptr;   // warm start and h - M x0 (allocated on first use)
   SolveState* d_state = nullptr;
@@ -61,6 +63,40 @@ struct elmfb_batch_s {
   double* d_rc = nullptr;      // block-Jacobi inverse factors R_b^{-1} (column-packed)
   double* d_Ahat = nullptr;    // preconditioned matrix M_b R_b^{-1} (FP64)
   Tile* d_ftiles = nullptr;    // 64-point runs of the blocks (forming M R^{-1})
+  std::vector<ColSlice> slices;    // one per subdomain block (the M^T U pass)
+  std::vector<GramTask> tasks;     // one per subdomain block (the diagonal Gram blocks)
+  ColSlice* d_slices = nullptr;
+  GramTask* d_tasks = nullptr;
+  int kmax = 1;                    // largest K
+
+  // Patches of the block-Jacobi preconditioner: P^d neighbouring subdomains of a level as one
+  // block (patch > 1).  Their tables are planned for one P at a time (patch_planned); the folded
+  // matrix M R^{-1} of the patches, FP64 and store_prec, lives in their own block layout, and y
+  // (the coefficients of M R^{-1}) in the patch column order: column q of that order is column
+  // pperm[q] of x.
+  int patch = 1;                   // P of the factors held
+  int patch_planned = 0;
+  std::vector<Geo> pgeos;
+  std::vector<InstInfo> pinsts;
+  std::vector<DevBlock> pblocks;
+  std::vector<int32_t> pcov, pmem, pmoff, pperm;
+  std::vector<ColSlice> pslices;
+  std::vector<Tile> pftiles, pruns;
+  std::vector<GramTask> ptasks;
+  std::vector<int64_t> pfoff, pgoff;
+  std::vector<int64_t> pchunk_blk, pchunk_task;   // factor chunks: first block and first task
+  int pkmax = 1;
+  int64_t pn_store = 0, pn_bp = 0, pn_fac = 0, pn_scratch = 0, pn_dense = 0;
+  Geo* d_pgeos = nullptr;
+  InstInfo* d_pinsts = nullptr;
+  DevBlock* d_pblocks = nullptr;
+  int32_t *d_pcov = nullptr, *d_pmem = nullptr, *d_pmoff = nullptr, *d_pperm = nullptr;
+  ColSlice* d_pslices = nullptr;
+  Tile *d_pftiles = nullptr, *d_pruns = nullptr;
+  GramTask* d_ptasks = nullptr;
+  int64_t *d_pfoff = nullptr, *d_pgoff = nullptr;
+  double *d_pAhat = nullptr, *d_prc = nullptr;
+  void* d_plo = nullptr;
   bool assembled = false, bj_ready = false;
   bool lo_hat = false;         // the low-precision copy holds M R^{-1} (else M)
   bool coords_y = false;       // solve in/out coefficients are y = R x (block-Jacobi coordinates)
@@ -186,9 +222,12 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
       for (int p0 = 0; p0 < D.n; p0 += 64) B->ftiles.push_back(Tile{blk_off + (int32_t)b, p0});
       B->foff.push_back(f_off);
       B->goff.push_back(g_off);
+      B->slices.push_back(ColSlice{blk_off + (int32_t)b, 0});
+      B->tasks.push_back(GramTask{blk_off + (int32_t)b, 0, 0});
       f_off += K * (K + 1) / 2;
       g_off += K * K;
     }
+    B->kmax = std::max(B->kmax, (int)K);
     for (const Tile& t : hp.tiles) B->tiles.push_back(Tile{t.blk + blk_off, t.p0});
     for (const AxisSeg& s : hp.segs) {
       AxisSeg s2 = s;
@@ -218,6 +257,170 @@ std::string plan_batch(elmfb_batch B, const elmfb_problem_desc* descs) {
   return "";
 }
 
+// Device bytes of the factors and folded matrices held (the subdomain or the patch ones).
+int64_t factor_bytes(elmfb_batch B) {
+  const int64_t es_lo = B->lo_prec == ELMFB_FP64 ? 0 : elem_size(B->lo_prec);
+  int64_t b = 0;
+  if (B->d_rc) b += B->n_fac * 8;
+  if (B->d_Ahat) b += B->n_store * 8;
+  if (B->d_prc) b += B->pn_fac * 8;
+  if (B->d_pAhat) b += B->pn_store * 8;
+  if (B->d_plo) b += B->pn_store * es_lo;
+  return b;
+}
+
+// Scratch for the Gram blocks and factors of the patches, per chunk of patches (two nk x nk
+// matrices per patch): the chunks are formed so that each needs at most this many doubles.
+constexpr int64_t kPatchScratch = (int64_t)1 << 28;   // 2 GiB of doubles per matrix set
+
+// Patch tables for P: per instance and level, patches of P consecutive subdomains along each
+// axis (the last along an axis keeps what is left), in x-major order; a patch block covers the
+// bounding box of its members' boxes (their union, as neighbouring supports overlap), holds their
+// columns member by member (members in x-major order) and is stored like a subdomain block,
+// [nk][ld] feature-major.  A grid index is covered by the patches of the subdomains covering it.
+std::string plan_patches(elmfb_batch B, int P) {
+  B->pgeos.clear(); B->pinsts.clear(); B->pblocks.clear(); B->pcov.clear(); B->pmem.clear();
+  B->pmoff.clear(); B->pperm.assign((size_t)B->n_phi, -1); B->pslices.clear();
+  B->pftiles.clear(); B->pruns.clear(); B->ptasks.clear(); B->pfoff.clear(); B->pgoff.clear();
+  B->pchunk_blk.clear(); B->pchunk_task.clear();
+  int64_t a_off = 0, p_off = 0, f_off = 0, dense = 0;
+  int kmax = 1;
+  for (int i = 0; i < B->n; ++i) {
+    const Geo& g = B->geos[i];
+    const InstInfo& I = B->insts[i];
+    const int K = g.K;
+    Geo pg = g;
+    InstInfo pi = I;
+    pi.b0 = (int32_t)B->pslices.size();
+    int64_t col = I.col_off;
+    int nb_i = 0;
+    for (int l = 0; l < g.n_levels; ++l) {
+      const int Jx = g.J[l][0], Jy = g.J[l][1];
+      const int PJx = (Jx + P - 1) / P, PJy = (Jy + P - 1) / P;
+      pg.J[l][0] = PJx;
+      pg.J[l][1] = PJy;
+      pg.bbase[l] = (int32_t)B->pblocks.size();
+      for (int a = 0; a < 2; ++a) {
+        const int np = a == 0 ? g.nx : g.ny;
+        pg.cov_off[l][a] = (int32_t)B->pcov.size();
+        for (int m = 0; m < np; ++m) {
+          const int jlo = B->cov[g.cov_off[l][a] + 2 * m], jhi = B->cov[g.cov_off[l][a] + 2 * m + 1];
+          B->pcov.push_back(jhi >= jlo ? jlo / P : 0);
+          B->pcov.push_back(jhi >= jlo ? jhi / P : -1);
+        }
+      }
+      for (int px = 0; px < PJx; ++px)
+        for (int py = 0; py < PJy; ++py) {
+          DevBlock D{};
+          int x0 = 1 << 30, x1 = -1, y0 = 1 << 30, y1 = -1, nm = 0;
+          B->pmoff.push_back((int32_t)B->pmem.size());
+          for (int jx = P * px; jx < std::min(P * px + P, Jx); ++jx)
+            for (int jy = P * py; jy < std::min(P * py + P, Jy); ++jy) {
+              const int mb = g.bbase[l] + jx * Jy + jy;
+              const DevBlock& M = B->blocks[mb];
+              B->pmem.push_back(mb);
+              for (int k = 0; k < K; ++k) B->pperm[col + (int64_t)nm * K + k] = M.q0 + k;
+              ++nm;
+              if (M.n == 0) continue;
+              x0 = std::min(x0, M.ix0); x1 = std::max(x1, M.ix0 + M.nx);
+              y0 = std::min(y0, M.iy0); y1 = std::max(y1, M.iy0 + M.ny);
+            }
+          if (x1 < 0) { x0 = x1 = y0 = y1 = 0; }
+          D.nk = nm * K;
+          if (D.nk > kPatchMaxK)
+            return "a patch holds more than 512 columns: take a smaller patch size";
+          D.ix0 = x0; D.nx = x1 - x0; D.iy0 = y0; D.ny = y1 - y0;
+          D.n = D.nx * D.ny;
+          D.ld = (D.n + kRowAlign - 1) / kRowAlign * kRowAlign;
+          D.a_off = a_off;
+          D.p_off = p_off;
+          D.q0 = (int32_t)col;
+          D.level = l;
+          D.inst = i;
+          D.jx = px;
+          D.jy = py;
+          const int b = (int)B->pblocks.size();
+          B->pblocks.push_back(D);
+          for (int k0 = 0; k0 < D.nk; k0 += kBatchMaxK) B->pslices.push_back(ColSlice{b, k0});
+          for (int p0 = 0; p0 < D.ld; p0 += 256) B->pruns.push_back(Tile{b, p0});
+          for (int i0 = 0; i0 < D.nk; i0 += kBatchMaxK)
+            for (int j0 = i0; j0 < D.nk; j0 += kBatchMaxK) B->ptasks.push_back(GramTask{b, i0, j0});
+          B->pfoff.push_back(f_off);
+          f_off += (int64_t)D.nk * (D.nk + 1) / 2;
+          a_off += (int64_t)D.nk * D.ld;
+          p_off += D.n;
+          dense += (int64_t)D.nk * D.n;
+          col += D.nk;
+          kmax = std::max(kmax, D.nk);
+          ++nb_i;
+        }
+    }
+    pg.n_blocks = nb_i;
+    pi.b1 = (int32_t)B->pslices.size();
+    B->pgeos.push_back(pg);
+    B->pinsts.push_back(pi);
+  }
+  // fold runs, dealt to the XCDs by block; factor chunks with their scratch offsets
+  const int run = fold_run_points(kmax);
+  std::vector<Tile> ft;
+  for (size_t b = 0; b < B->pblocks.size(); ++b)
+    for (int p0 = 0; p0 < B->pblocks[b].n; p0 += run) ft.push_back(Tile{(int32_t)b, p0});
+  B->pftiles = xcd_grouped(ft);
+  int64_t g_off = 0, scratch = 0;
+  size_t t = 0;
+  for (size_t b = 0; b < B->pblocks.size(); ++b) {
+    const int64_t sq = (int64_t)B->pblocks[b].nk * B->pblocks[b].nk;
+    if (b == 0 || g_off + sq > kPatchScratch) {
+      B->pchunk_blk.push_back((int64_t)b);
+      while (t < B->ptasks.size() && B->ptasks[t].blk < (int32_t)b) ++t;
+      B->pchunk_task.push_back((int64_t)t);
+      g_off = 0;
+    }
+    B->pgoff.push_back(g_off);
+    g_off += sq;
+    scratch = std::max(scratch, g_off);
+  }
+  B->pchunk_blk.push_back((int64_t)B->pblocks.size());
+  B->pchunk_task.push_back((int64_t)B->ptasks.size());
+  B->pkmax = kmax;
+  B->pn_store = a_off;
+  B->pn_bp = p_off;
+  B->pn_fac = f_off;
+  B->pn_scratch = scratch;
+  B->pn_dense = dense;
+  return "";
+}
+
+// The block structure a pass runs on: the subdomain blocks of the assembly, or the patch blocks
+// of the block-Jacobi preconditioner.
+struct BtLayout {
+  const Geo* geos;
+  const InstInfo* insts;
+  const DevBlock* blocks;
+  int64_t nb;
+  const int32_t* cov;
+  const ColSlice* slices;
+  int64_t ns;
+  int kmax;
+  int64_t n_bp;
+};
+
+BtLayout sub_layout(elmfb_batch B) {
+  return BtLayout{B->d_geos, B->d_insts, B->d_blocks, (int64_t)B->blocks.size(), B->d_cov,
+                  B->d_slices, (int64_t)B->slices.size(), B->kmax, B->n_bp};
+}
+
+BtLayout patch_layout(elmfb_batch B) {
+  return BtLayout{B->d_pgeos, B->d_pinsts, B->d_pblocks, (int64_t)B->pblocks.size(), B->d_pcov,
+                  B->d_pslices, (int64_t)B->pslices.size(), B->pkmax, B->pn_bp};
+}
+
+// Preconditioned passes run on the folded matrix, in the patch layout when the factors are of
+// patches; everything else on the subdomain blocks.
+BtLayout layout_of(elmfb_batch B, bool bj) {
+  return bj && B->patch > 1 ? patch_layout(B) : sub_layout(B);
+}
+
 int prec_index(int prec) {
   return prec == ELMFB_FP32 ? 1 : (prec == ELMFB_BF16 ? 2 : (prec == ELMFB_FP16 ? 3 : 0));
 }
@@ -225,8 +428,27 @@ int prec_index(int prec) {
 // The matrix the Krylov steps run on: M, or with block-Jacobi the folded M R^{-1}; FP64 or the
 // low-precision copy.
 const void* matrix_of(elmfb_batch B, int prec, bool bj) {
-  if (prec == ELMFB_FP64) return bj ? (const void*)B->d_Ahat : (const void*)B->d_A;
-  return (const void*)B->d_A_lo;
+  const bool pt = bj && B->patch > 1;
+  if (prec == ELMFB_FP64)
+    return bj ? (pt ? (const void*)B->d_pAhat : (const void*)B->d_Ahat) : (const void*)B->d_A;
+  return pt ? (const void*)B->d_plo : (const void*)B->d_A_lo;
+}
+
+// Factors, their offsets and the column order of the preconditioned coefficients.
+const double* factors_of(elmfb_batch B) { return B->patch > 1 ? B->d_prc : B->d_rc; }
+const int64_t* foff_of(elmfb_batch B) { return B->patch > 1 ? B->d_pfoff : B->d_foff; }
+const int32_t* perm_of(elmfb_batch B) { return B->patch > 1 ? B->d_pperm : nullptr; }
+
+// The matrix copy of precision prec that tuning and timing run on, with its layout: the folded
+// patch matrices while patch factors are held (the solves run on them), else the stored copy of
+// M (for P = 1 its low-precision buffer holds M R^{-1} after preconditioning).
+struct TimedTarget {
+  BtLayout L;
+  const void* A;
+};
+TimedTarget timed_target(elmfb_batch B, int prec) {
+  if (B->patch > 1 && B->bj_ready) return TimedTarget{patch_layout(B), matrix_of(B, prec, true)};
+  return TimedTarget{sub_layout(B), matrix_of(B, prec, false)};
 }
 
 // One LSQR step for every (instance, rhs) on the matrix of precision `prec` (M, or M R^{-1} with
@@ -234,25 +456,25 @@ const void* matrix_of(elmfb_batch B, int prec, bool bj) {
 // x, w update; stop tests.
 hipError_t bt_iteration(elmfb_batch B, int prec, bool bj, hipStream_t s) {
   const int n = B->n, R = B->R;
-  const int64_t nb = (int64_t)B->blocks.size();
+  const BtLayout L = layout_of(B, bj);
   const void* A = matrix_of(B, prec, bj);
   hipError_t e;
-  if ((e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, B->d_state, B->d_tpart,
-                         s, B->fa[prec_index(prec)])))
+  if ((e = launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, B->d_state, B->d_tpart, s,
+                         B->fa[prec_index(prec)])))
     return e;
-  if ((e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+  if ((e = launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles,
                             (int64_t)B->rtiles.size(), B->d_tpart, ROW_LSQR_U, R, B->d_u, nullptr,
                             B->d_state, B->d_red_r, s, B->rpt)))
     return e;
-  if ((e = launch_bt_lsqr_beta(B->d_state, B->d_insts, n, R, B->d_red_r, s))) return e;
-  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
-                          B->d_u, R, B->d_state, COL_LSQR_V, B->d_v, B->d_red_c, s)))
+  if ((e = launch_bt_lsqr_beta(B->d_state, L.insts, n, R, B->d_red_r, s))) return e;
+  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], L.geos, L.insts, L.blocks, L.slices, L.ns,
+                          A, B->d_u, R, B->d_state, COL_LSQR_V, B->d_v, B->d_red_c, s)))
     return e;
-  if ((e = launch_bt_lsqr_alpha(B->d_state, B->d_insts, n, R, B->d_red_c, s))) return e;
-  if ((e = launch_bt_update(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
+  if ((e = launch_bt_lsqr_alpha(B->d_state, L.insts, n, R, B->d_red_c, s))) return e;
+  if ((e = launch_bt_update(B->d_geos, L.insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
                             B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_b, s)))
     return e;
-  return launch_bt_lsqr_stop(B->d_state, B->d_insts, n, R, B->d_red_b, s);
+  return launch_bt_lsqr_stop(B->d_state, L.insts, n, R, B->d_red_b, s);
 }
 
 // LSQR start from the rows already in d_u (u = rhs) with their squared-norm partials in
@@ -262,19 +484,20 @@ hipError_t bt_lsqr_start(elmfb_batch B, int prec, bool bj, double atol, double b
                          const BtOuter* ot, double inner_rel, hipStream_t s,
                          const double* red_b = nullptr) {
   const int n = B->n, R = B->R;
+  const BtLayout L = layout_of(B, bj);
   hipError_t e;
-  if ((e = launch_bt_lsqr_init(B->d_state, B->d_insts, n, R, red_b ? red_b : B->d_red_r,
+  if ((e = launch_bt_lsqr_init(B->d_state, L.insts, n, R, red_b ? red_b : B->d_red_r,
                                B->d_red_r, atol, btol, iter_lim, ot, inner_rel, s)))
     return e;
-  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks,
-                          (int64_t)B->blocks.size(), matrix_of(B, prec, bj), B->d_u, R,
-                          B->d_state, COL_STORE_SQ, B->d_v, B->d_red_c, s)))
+  if ((e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], L.geos, L.insts, L.blocks, L.slices, L.ns,
+                          matrix_of(B, prec, bj), B->d_u, R, B->d_state, COL_STORE_SQ, B->d_v,
+                          B->d_red_c, s)))
     return e;
-  if ((e = launch_bt_lsqr_init_alpha(B->d_state, B->d_insts, n, R, B->d_red_c, s))) return e;
+  if ((e = launch_bt_lsqr_init_alpha(B->d_state, L.insts, n, R, B->d_red_c, s))) return e;
   if ((e = hipMemsetAsync(B->d_x, 0, (size_t)(B->n_phi * R * 8), s))) return e;
   if ((e = hipMemsetAsync(B->d_w, 0, (size_t)(B->n_phi * R * 8), s))) return e;
   // with t1 = t2 = 0 (fresh state) the update leaves x = 0 and sets w = v sv
-  return launch_bt_update(B->d_geos, B->d_insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
+  return launch_bt_update(B->d_geos, L.insts, B->d_ctiles, (int64_t)B->ctiles.size(), R,
                           B->d_x, B->d_w, B->d_v, B->d_state, B->d_red_b, s);
 }
 
@@ -283,15 +506,16 @@ hipError_t bt_lsqr_start(elmfb_batch B, int prec, bool bj, double atol, double b
 hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s,
                        const double* b = nullptr) {
   const int R = B->R;
+  const BtLayout L = layout_of(B, bj);
   hipError_t e;
   if (c) {
-    if ((e = launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(),
-                           matrix_of(B, ELMFB_FP64, bj), c, R, nullptr, B->d_tpart, s, B->fa[0])))
+    if ((e = launch_bt_mvb(ELMFB_FP64, L.blocks, L.nb, L.kmax, matrix_of(B, ELMFB_FP64, bj), c, R,
+                           nullptr, B->d_tpart, s, B->fa[0])))
       return e;
-  } else if ((e = hipMemsetAsync(B->d_tpart, 0, (size_t)(B->n_bp * R * 8), s))) {
+  } else if ((e = hipMemsetAsync(B->d_tpart, 0, (size_t)(L.n_bp * R * 8), s))) {
     return e;
   }
-  return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+  return launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles,
                           (int64_t)B->rtiles.size(), B->d_tpart, ROW_RESID, R, B->d_u,
                           b ? b : B->d_h, nullptr, B->d_red_r, s, B->rpt);
 }
@@ -311,7 +535,8 @@ elmfb_status bt_run(elmfb_batch B, int prec, bool bj, int chunk, bool use_graph,
         const int m = left > kGraphMaxSteps ? kGraphMaxSteps : left;
         // the captured kernels depend on the tuned shapes as well
         const int64_t key = ((int64_t)m << 24) | ((int64_t)B->rpt << 20) |
-                            ((int64_t)B->fa[prec_index(prec)] << 15) | (prec << 8) |
+                            ((int64_t)B->fa[prec_index(prec)] << 15) |
+                            ((int64_t)(bj ? B->patch : 0) << 10) | (prec << 8) |
                             (bj ? 128 : 0) | B->tp[prec_index(prec)];
         auto it = B->graphs.find(key);
         hipGraphExec_t exec = nullptr;
@@ -383,7 +608,8 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   int64_t bytes = B->n_store * (8 + es_lo) + B->n_bp * R * 8 + B->n_rows * R * 8 * 2 +
                   B->n_phi * R * 8 * 4 + B->n_phi * 24 + B->n_tab * 24 +
                   (int64_t)(B->rtiles.size() * 3 + B->ctiles.size() + nblk) * kMaxRhs * 8 +
-                  nblk * ((int64_t)sizeof(DevBlock) + 16) +
+                  nblk * ((int64_t)sizeof(DevBlock) + 16 + (int64_t)sizeof(ColSlice) +
+                          (int64_t)sizeof(GramTask)) +
                   (int64_t)(B->tiles.size() + B->ftiles.size()) * sizeof(Tile) +
                   (int64_t)n * R * ((int64_t)sizeof(SolveState) + (int64_t)sizeof(BtOuter));
   B->bytes = bytes;
@@ -420,6 +646,8 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_blocks, nblk * (int64_t)sizeof(DevBlock));
   BALLOC(B->d_foff, nblk * 8);
   BALLOC(B->d_goff, nblk * 8);
+  BALLOC(B->d_slices, nblk * (int64_t)sizeof(ColSlice));
+  BALLOC(B->d_tasks, nblk * (int64_t)sizeof(GramTask));
   BALLOC(B->d_tiles, (int64_t)B->tiles.size() * sizeof(Tile));
   BALLOC(B->d_cov, (int64_t)B->cov.size() * 4);
   BALLOC(B->d_segs, (int64_t)B->segs.size() * sizeof(BSeg));
@@ -438,6 +666,7 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   BALLOC(B->d_c, B->n_phi * R * 8);
   BALLOC(B->d_ftiles, (int64_t)B->ftiles.size() * sizeof(Tile));
   BALLOC(B->d_tpart, B->n_bp * R * 8);
+  B->tpart_bp = B->n_bp;
   BALLOC(B->d_red_r, (int64_t)B->rtiles.size() * kMaxRhs * 8);
   BALLOC(B->d_red_b, (int64_t)B->ctiles.size() * kMaxRhs * 8);
   BALLOC(B->d_red_c, nblk * kMaxRhs * 8);
@@ -479,6 +708,8 @@ elmfb_status elmfb_define_batch(const elmfb_problem_desc* descs, int32_t n, int3
   up(B->d_blocks, B->blocks.data(), B->blocks.size() * sizeof(DevBlock));
   up(B->d_foff, B->foff.data(), B->foff.size() * 8);
   up(B->d_goff, B->goff.data(), B->goff.size() * 8);
+  up(B->d_slices, B->slices.data(), B->slices.size() * sizeof(ColSlice));
+  up(B->d_tasks, B->tasks.data(), B->tasks.size() * sizeof(GramTask));
   up(B->d_tiles, B->tiles.data(), B->tiles.size() * sizeof(Tile));
   up(B->d_ftiles, B->ftiles.data(), B->ftiles.size() * sizeof(Tile));
   up(B->d_cov, B->cov.data(), B->cov.size() * 4);
@@ -562,10 +793,15 @@ elmfb_status elmfb_batch_query_instances(elmfb_batch B, elmfb_sizes* out) {
 elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
                                      int64_t* table_host, void* stream) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  const bool folded = (prec & ELMFB_COPY_FOLDED) != 0;
+  prec &= ~ELMFB_COPY_FOLDED;
+  // folded copies of patch factors are stored in the patch blocks
+  const bool pt = folded && B->patch > 1 && B->bj_ready;
+  const std::vector<DevBlock>& blocks = pt ? B->pblocks : B->blocks;
   if (table_host) {
     int64_t dense = 0;
-    for (size_t i = 0; i < B->blocks.size(); ++i) {
-      const DevBlock& d = B->blocks[i];
+    for (size_t i = 0; i < blocks.size(); ++i) {
+      const DevBlock& d = blocks[i];
       int64_t* t = table_host + 8 * i;
       t[0] = d.inst;
       t[1] = d.level;
@@ -573,34 +809,33 @@ elmfb_status elmfb_batch_copy_blocks(elmfb_batch B, int32_t prec, void* dst_dev,
       t[3] = d.nx;
       t[4] = d.iy0;
       t[5] = d.ny;
-      t[6] = B->geos[d.inst].K;
+      t[6] = d.nk;
       t[7] = dense;
-      dense += (int64_t)d.n * B->geos[d.inst].K;
+      dense += (int64_t)d.n * d.nk;
     }
   }
   if (dst_dev) {
     if (!B->assembled) return bfail(B, ELMFB_E_STATE, "copy_blocks before assemble");
-    const bool folded = (prec & ELMFB_COPY_FOLDED) != 0;
-    prec &= ~ELMFB_COPY_FOLDED;
     const void* src = nullptr;
     if (prec == ELMFB_FP64) {
-      src = folded ? (B->bj_ready ? (const void*)B->d_Ahat : nullptr) : (const void*)B->d_A;
+      src = folded ? (B->bj_ready ? matrix_of(B, ELMFB_FP64, true) : nullptr) : (const void*)B->d_A;
     } else if (prec == B->lo_prec && B->d_A_lo) {
-      // the low-precision buffer holds M until elmfb_batch_precondition, then M R^{-1}
-      src = folded == B->lo_hat ? B->d_A_lo : nullptr;
+      // the low-precision buffer holds M until elmfb_batch_precondition, then M R^{-1} (per
+      // subdomain); the folded copy of patch factors has its own buffer
+      if (pt) src = B->d_plo;
+      else src = folded == B->lo_hat ? B->d_A_lo : nullptr;
     }
     if (!src) return bfail(B, ELMFB_E_STATE, "no stored copy of that kind and precision");
     // stored rows are padded to ld; the copy drops the padding
     const int64_t es = elem_size(prec);
     int64_t dense = 0;
-    for (const DevBlock& d : B->blocks) {
-      const int64_t K = B->geos[d.inst].K;
+    for (const DevBlock& d : blocks) {
       if (d.n == 0) continue;
       BHIP(B, hipMemcpy2DAsync(static_cast<char*>(dst_dev) + dense * es, (size_t)(d.n * es),
                                static_cast<const char*>(src) + d.a_off * es, (size_t)(d.ld * es),
-                               (size_t)(d.n * es), (size_t)K, hipMemcpyDeviceToDevice,
+                               (size_t)(d.n * es), (size_t)d.nk, hipMemcpyDeviceToDevice,
                                (hipStream_t)stream));
-      dense += (int64_t)d.n * K;
+      dense += (int64_t)d.n * d.nk;
     }
   }
   return ELMFB_OK;
@@ -635,7 +870,7 @@ elmfb_status elmfb_batch_matvec(elmfb_batch B, const double* v_dev, double* y_de
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, v_dev, B->d_w, 1, 1, s));
-  BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_geos, B->d_blocks, (int64_t)B->blocks.size(), B->d_A,
+  BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_blocks, (int64_t)B->blocks.size(), B->kmax, B->d_A,
                         B->d_w, R, nullptr, B->d_tpart, s, B->fa[0]));
   BHIP(B, launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                            (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE, R, B->d_u, nullptr,
@@ -650,8 +885,8 @@ elmfb_status elmfb_batch_rmatvec(elmfb_batch B, const double* u_dev, double* x_d
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nrows, B->n, R, B->n_rows, u_dev, B->d_u, 1, 0, s));
-  BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], B->d_geos, B->d_insts, B->d_blocks,
-                         (int64_t)B->blocks.size(), B->d_A, B->d_u, R, nullptr, COL_STORE, B->d_w,
+  BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], B->d_geos, B->d_insts, B->d_blocks, B->d_slices,
+                         (int64_t)B->slices.size(), B->d_A, B->d_u, R, nullptr, COL_STORE, B->d_w,
                          B->d_red_c, s));
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, B->d_w, x_dev, 0, 1, s));
   return ELMFB_OK;
@@ -659,50 +894,168 @@ elmfb_status elmfb_batch_rmatvec(elmfb_batch B, const double* u_dev, double* x_d
 
 elmfb_status elmfb_batch_precondition(elmfb_batch B, double shift, int32_t* n_fallback_host,
                                       void* stream) {
+  return elmfb_batch_precondition_patches(B, shift, 1, n_fallback_host, stream);
+}
+
+elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32_t patch,
+                                              int32_t* n_fallback_host, void* stream) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
   if (!B->assembled) return bfail(B, ELMFB_E_STATE, "precondition before assemble");
   if (!(shift > 0.0) || !(shift < 1.0)) return bfail(B, ELMFB_E_INVALID, "shift must be in (0, 1)");
+  if (patch < 1 || patch > 4) return bfail(B, ELMFB_E_INVALID, "patch must be in 1..4");
+  if (patch > 1 && B->coords_y)
+    return bfail(B, ELMFB_E_UNSUPPORTED, "block-Jacobi coordinates are per subdomain (patch 1)");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t nb = (int64_t)B->blocks.size();
-  if (!B->d_rc) {
-    hipError_t e1 = balloc(B, &B->d_rc, B->n_fac * 8);
-    hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_Ahat, B->n_store * 8) : e1;
-    if (e2 == hipSuccess) e2 = hipMemsetAsync(B->d_Ahat, 0, (size_t)B->n_store * 8, s);  // padding
-    if (e2 != hipSuccess) {
-      bfree(B, B->d_rc);
-      B->d_rc = nullptr;
-      return bfail(B, ELMFB_E_NOMEM, std::string("factor storage: ") + hipGetErrorString(e2));
-    }
-    B->bytes += B->n_fac * 8 + B->n_store * 8;
+  auto release = [&](auto*& p) { bfree(B, p); p = nullptr; };
+  if (patch > 1 && B->patch_planned != patch) {
+    // patch tables (checked before anything held is released)
+    B->patch_planned = 0;
+    const std::string pe = plan_patches(B, patch);
+    if (!pe.empty()) return bfail(B, ELMFB_E_INVALID, pe);
   }
-  double* G = nullptr;
-  hipError_t e1 = balloc(B, &G, B->n_gsq * 8);
-  if (e1 != hipSuccess)
-    return bfail(B, ELMFB_E_NOMEM, std::string("Gram scratch: ") + hipGetErrorString(e1));
-  int kmax = 1;
-  for (const Geo& g : B->geos) kmax = std::max(kmax, (int)g.K);
   B->bj_ready = false;
-  hipError_t e = hipMemsetAsync(B->d_flag, 0, 4, s);
-  if (e == hipSuccess)
-    e = launch_bt_gram_diag(B->d_geos, B->d_blocks, nb, B->d_A, B->d_goff, G, s);
-  if (e == hipSuccess)
-    e = launch_bt_bj_factor(B->d_geos, B->d_blocks, nb, G, B->d_goff, B->d_foff, kmax, shift,
-                            B->d_rc, B->d_flag, s);
-  // M R^{-1} in FP64, and its rounded copy in place of the low-precision M
-  if (e == hipSuccess)
-    e = launch_bt_fold(B->lo_prec, false, kBatchMaxK, B->d_geos, B->d_blocks, B->d_ftiles,
-                       (int64_t)B->ftiles.size(), B->d_A, B->d_rc, B->d_foff, B->d_Ahat,
-                       B->d_A_lo, s);
+  B->bytes -= factor_bytes(B);
+  // the factors of one patch size at a time: release the other kind's storage
+  if (patch == 1) {
+    release(B->d_pAhat); release(B->d_prc); release(B->d_plo);
+  } else {
+    release(B->d_Ahat); release(B->d_rc);
+  }
+  for (auto& kv : B->graphs) hipGraphExecDestroy(kv.second);
+  B->graphs.clear();
   int32_t nfail = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&nfail, B->d_flag, 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  bfree(B, G);
-  BHIP(B, e);
+  hipError_t e = hipMemsetAsync(B->d_flag, 0, 4, s);
+  if (patch == 1) {
+    const int64_t nb = (int64_t)B->blocks.size();
+    if (!B->d_rc) {
+      hipError_t e1 = balloc(B, &B->d_rc, B->n_fac * 8);
+      hipError_t e2 = e1 == hipSuccess ? balloc(B, &B->d_Ahat, B->n_store * 8) : e1;
+      if (e2 == hipSuccess) e2 = hipMemsetAsync(B->d_Ahat, 0, (size_t)B->n_store * 8, s);  // padding
+      if (e2 != hipSuccess) {
+        release(B->d_rc);
+        release(B->d_Ahat);
+        return bfail(B, ELMFB_E_NOMEM, std::string("factor storage: ") + hipGetErrorString(e2));
+      }
+    }
+    double* G = nullptr;
+    hipError_t e1 = balloc(B, &G, B->n_gsq * 8);
+    if (e1 != hipSuccess)
+      return bfail(B, ELMFB_E_NOMEM, std::string("Gram scratch: ") + hipGetErrorString(e1));
+    if (e == hipSuccess)
+      e = launch_bt_gram_diag(B->d_blocks, B->d_tasks, nb, false, B->d_A, B->d_goff, G, s);
+    if (e == hipSuccess)
+      e = launch_bt_bj_factor(B->d_blocks, 0, nb, G, B->d_goff, B->d_foff, B->kmax, shift, B->d_rc,
+                              B->d_flag, s);
+    // M R^{-1} in FP64, and its rounded copy in place of the low-precision M
+    if (e == hipSuccess)
+      e = launch_bt_fold(B->lo_prec, false, B->kmax, B->d_blocks, B->d_ftiles,
+                         (int64_t)B->ftiles.size(), B->d_A, B->d_rc, B->d_foff, B->d_Ahat,
+                         B->d_A_lo, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nfail, B->d_flag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    bfree(B, G);
+    BHIP(B, e);
+    B->lo_hat = B->lo_prec != ELMFB_FP64;
+  } else {
+    if (B->patch_planned != patch) {
+      // device tables (replacing those of another patch size)
+      release(B->d_pgeos); release(B->d_pinsts); release(B->d_pblocks); release(B->d_pcov);
+      release(B->d_pmem); release(B->d_pmoff); release(B->d_pperm); release(B->d_pslices);
+      release(B->d_pftiles); release(B->d_pruns); release(B->d_ptasks); release(B->d_pfoff);
+      release(B->d_pgoff);
+      hipError_t ea = hipSuccess;
+      auto put = [&](auto*& dst, const auto& v) {
+        using T = typename std::remove_reference<decltype(v)>::type::value_type;
+        if (ea != hipSuccess) return;
+        ea = balloc(B, &dst, (int64_t)(v.size() * sizeof(T)));
+        if (ea == hipSuccess && !v.empty())
+          ea = hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+      };
+      put(B->d_pgeos, B->pgeos); put(B->d_pinsts, B->pinsts); put(B->d_pblocks, B->pblocks);
+      put(B->d_pcov, B->pcov); put(B->d_pmem, B->pmem); put(B->d_pmoff, B->pmoff);
+      put(B->d_pperm, B->pperm); put(B->d_pslices, B->pslices); put(B->d_pftiles, B->pftiles);
+      put(B->d_pruns, B->pruns); put(B->d_ptasks, B->ptasks); put(B->d_pfoff, B->pfoff);
+      put(B->d_pgoff, B->pgoff);
+      // the per-block-point partials of M V must hold the patch boxes as well
+      if (ea == hipSuccess && B->pn_bp > B->tpart_bp) {
+        release(B->d_tpart);
+        ea = balloc(B, &B->d_tpart, B->pn_bp * B->R * 8);
+        if (ea == hipSuccess) {
+          B->bytes += (B->pn_bp - B->tpart_bp) * B->R * 8;
+          B->tpart_bp = B->pn_bp;
+        }
+      }
+      release(B->d_pAhat); release(B->d_prc); release(B->d_plo);
+      if (ea != hipSuccess) return bfail(B, ELMFB_E_NOMEM, std::string("patch tables: ") + hipGetErrorString(ea));
+      B->patch_planned = patch;
+    }
+    const int64_t es_lo = B->lo_prec == ELMFB_FP64 ? 0 : elem_size(B->lo_prec);
+    if (!B->d_pAhat) {
+      hipError_t e1 = balloc(B, &B->d_pAhat, B->pn_store * 8);
+      if (e1 == hipSuccess) e1 = balloc(B, &B->d_prc, B->pn_fac * 8);
+      if (e1 == hipSuccess && es_lo) e1 = balloc(B, &B->d_plo, B->pn_store * es_lo);
+      // row padding of the low-precision copy: never written by the fold, read with zero weights
+      if (e1 == hipSuccess && es_lo) e1 = hipMemsetAsync(B->d_plo, 0, (size_t)(B->pn_store * es_lo), s);
+      if (e1 != hipSuccess) {
+        release(B->d_pAhat); release(B->d_prc); release(B->d_plo);
+        return bfail(B, ELMFB_E_NOMEM, std::string("patch storage: ") + hipGetErrorString(e1));
+      }
+    }
+    double *G = nullptr, *Wk = nullptr;
+    hipError_t e1 = balloc(B, &G, B->pn_scratch * 8);
+    if (e1 == hipSuccess && B->pkmax > kBatchMaxK) e1 = balloc(B, &Wk, B->pn_scratch * 8);
+    if (e1 != hipSuccess) {
+      bfree(B, G);
+      return bfail(B, ELMFB_E_NOMEM, std::string("patch Gram scratch: ") + hipGetErrorString(e1));
+    }
+    // patches of M in FP64, then per chunk their Gram blocks and factors, then M R^{-1} in place
+    if (e == hipSuccess)
+      e = launch_bt_expand(B->d_geos, B->d_pblocks, B->d_pruns, (int64_t)B->pruns.size(),
+                           B->d_blocks, B->d_pmem, B->d_pmoff, B->d_A, B->d_pAhat, s);
+    for (size_t c = 0; c + 1 < B->pchunk_blk.size() && e == hipSuccess; ++c) {
+      const int64_t b0 = B->pchunk_blk[c], b1 = B->pchunk_blk[c + 1];
+      const int64_t t0 = B->pchunk_task[c], t1 = B->pchunk_task[c + 1];
+      e = launch_bt_gram_diag(B->d_pblocks, B->d_ptasks + t0, t1 - t0, B->pkmax > kBatchMaxK,
+                              B->d_pAhat, B->d_pgoff, G, s);
+      if (e == hipSuccess) {
+        if (B->pkmax <= kBatchMaxK)
+          e = launch_bt_bj_factor(B->d_pblocks, (int)b0, b1 - b0, G, B->d_pgoff, B->d_pfoff,
+                                  B->pkmax, shift, B->d_prc, B->d_flag, s);
+        else
+          e = launch_bt_bj_factor_blocked(B->d_pblocks, (int)b0, b1 - b0, G, Wk, B->d_pgoff,
+                                          B->d_pfoff, shift, B->d_prc, B->d_flag, s);
+      }
+    }
+    if (e == hipSuccess)
+      e = launch_bt_fold(B->lo_prec, false, B->pkmax, B->d_pblocks, B->d_pftiles,
+                         (int64_t)B->pftiles.size(), B->d_pAhat, B->d_prc, B->d_pfoff, B->d_pAhat,
+                         B->d_plo, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nfail, B->d_flag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    bfree(B, G);
+    bfree(B, Wk);
+    BHIP(B, e);
+    B->lo_hat = false;   // the low-precision copy of M itself is untouched
+  }
+  B->bytes += factor_bytes(B);
   if (n_fallback_host) *n_fallback_host = nfail;
+  B->patch = patch;
   B->bj_ready = true;
-  B->lo_hat = B->lo_prec != ELMFB_FP64;
   // an identity fallback leaves that block's columns unscaled; their FP16 rounding may overflow
   B->lo_unsafe = B->lo_prec == ELMFB_FP16 && nfail > 0;
+  return ELMFB_OK;
+}
+
+elmfb_status elmfb_batch_patch_info(elmfb_batch B, int32_t* patch_host, int64_t* n_blocks_host,
+                                    int64_t* n_entries_host, int32_t* perm_host) {
+  if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  const bool pt = B->patch > 1 && B->patch_planned == B->patch;
+  if (patch_host) *patch_host = B->patch;
+  if (n_blocks_host) *n_blocks_host = pt ? (int64_t)B->pblocks.size() : (int64_t)B->blocks.size();
+  if (n_entries_host) *n_entries_host = pt ? B->pn_dense : B->nnz;
+  if (perm_host) {
+    for (int64_t q = 0; q < B->n_phi; ++q) perm_host[q] = pt ? B->pperm[q] : (int32_t)q;
+  }
   return ELMFB_OK;
 }
 
@@ -715,8 +1068,9 @@ elmfb_status elmfb_batch_autotune(elmfb_batch B, int32_t prec, int32_t reps, dou
   if (reps < 1 || reps > 1000) return bfail(B, ELMFB_E_INVALID, "reps must be in 1..1000");
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
-  const int64_t nb = (int64_t)B->blocks.size();
-  const void* A = matrix_of(B, prec, false);
+  const TimedTarget T = timed_target(B, prec);
+  const BtLayout& L = T.L;
+  const void* A = T.A;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   BHIP(B, hipEventCreate(&t0));
   BHIP(B, hipEventCreate(&t1));
@@ -729,11 +1083,11 @@ elmfb_status elmfb_batch_autotune(elmfb_batch B, int32_t prec, int32_t reps, dou
     const int tp = kBtTileChoices[c];
     double ms = -1.0;
     if (!(prec == ELMFB_FP64 && tp == 64)) {
-      e = launch_bt_rmvb(prec, tp, B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u, R, nullptr,
-                         COL_STORE, B->d_w, B->d_red_c, s);
+      e = launch_bt_rmvb(prec, tp, L.geos, L.insts, L.blocks, L.slices, L.ns, A, B->d_u, R,
+                         nullptr, COL_STORE, B->d_w, B->d_red_c, s);
       if (e == hipSuccess) e = hipEventRecord(t0, s);
       for (int r = 0; r < reps && e == hipSuccess; ++r)
-        e = launch_bt_rmvb(prec, tp, B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u, R,
+        e = launch_bt_rmvb(prec, tp, L.geos, L.insts, L.blocks, L.slices, L.ns, A, B->d_u, R,
                            nullptr, COL_STORE, B->d_w, B->d_red_c, s);
       if (e == hipSuccess) e = hipEventRecord(t1, s);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
@@ -765,8 +1119,9 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   if (reps < 1 || reps > 1000) return bfail(B, ELMFB_E_INVALID, "reps must be in 1..1000");
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
-  const int64_t nb = (int64_t)B->blocks.size();
-  const void* A = matrix_of(B, prec, false);
+  const TimedTarget T = timed_target(B, prec);
+  const BtLayout& L = T.L;
+  const void* A = T.A;
   // V = 1 and U = 1 on every column, row and right-hand side (timing inputs only); the row
   // gather writes its rows into the row-sized work vector U, which the M^T U timing then reads
   std::vector<double> ones((size_t)std::max(B->n_rows, B->n_phi) * R, 1.0);
@@ -776,16 +1131,16 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   for (int i = 0; i < 4; ++i) BHIP(B, hipEventCreate(&ev[i]));
   hipError_t e = hipEventRecord(ev[0], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart, s,
+    e = launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, nullptr, B->d_tpart, s,
                       B->fa[prec_index(prec)]);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
-                         (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_u, nullptr,
-                         nullptr, B->d_red_r, s, B->rpt);
+    e = launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles, (int64_t)B->rtiles.size(),
+                         B->d_tpart, ROW_STORE_SQ, R, B->d_u, nullptr, nullptr, B->d_red_r, s,
+                         B->rpt);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], B->d_geos, B->d_insts, B->d_blocks, nb, A,
+    e = launch_bt_rmvb(prec, B->tp[prec_index(prec)], L.geos, L.insts, L.blocks, L.slices, L.ns, A,
                        B->d_u, R, nullptr, COL_STORE_SQ, B->d_w, B->d_red_c, s);
   if (e == hipSuccess) e = hipEventRecord(ev[3], s);
   if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
@@ -800,11 +1155,12 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
 namespace {
 
 // Shapes chosen by elmfb_batch_tune, kept for the process and keyed by (operator, precision,
-// largest K in 16s, stored entries in powers of two, right-hand sides): a later batch of the same
-// class takes them without timing.
+// largest K in 16s, stored entries in powers of two, right-hand sides, patch size of the factors
+// whose folded matrix is timed): a later batch of the same class takes them without timing.
 struct ShapeKey {
-  int op, prec, kclass, sclass, rhs;
+  int op, prec, kclass, sclass, rhs, patch;
   bool operator<(const ShapeKey& o) const {
+    if (patch != o.patch) return patch < o.patch;
     if (op != o.op) return op < o.op;
     if (prec != o.prec) return prec < o.prec;
     if (kclass != o.kclass) return kclass < o.kclass;
@@ -820,7 +1176,8 @@ ShapeKey shape_key(elmfb_batch B, int prec) {
   for (const Geo& g : B->geos) kmax = std::max(kmax, (int)g.K);
   int sc = 0;
   for (int64_t n = B->nnz; n > 1; n >>= 1) ++sc;
-  return ShapeKey{B->geos.empty() ? 0 : B->geos[0].op, prec, (kmax + 15) / 16, sc, B->R};
+  const int pt = B->patch > 1 && B->bj_ready ? B->patch : 1;
+  return ShapeKey{B->geos.empty() ? 0 : B->geos[0].op, prec, (kmax + 15) / 16, sc, B->R, pt};
 }
 
 bool valid_shape(int prec, const elmfb_batch_shape& sh) {
@@ -854,8 +1211,9 @@ elmfb_status elmfb_batch_tune(elmfb_batch B, int32_t prec, int32_t reps, int32_t
   if (!sh.from_cache) {
     hipStream_t s = (hipStream_t)stream;
     const int R = B->R;
-    const int64_t nb = (int64_t)B->blocks.size();
-    const void* A = matrix_of(B, prec, false);
+    const TimedTarget T = timed_target(B, prec);
+    const BtLayout& L = T.L;
+    const void* A = T.A;
     std::vector<double> ones((size_t)std::max(B->n_rows, B->n_phi) * R, 1.0);
     BHIP(B, hipMemcpyAsync(B->d_v, ones.data(), (size_t)B->n_phi * R * 8, hipMemcpyHostToDevice, s));
     BHIP(B, hipMemcpyAsync(B->d_u, ones.data(), (size_t)B->n_rows * R * 8, hipMemcpyHostToDevice, s));
@@ -879,23 +1237,23 @@ elmfb_status elmfb_batch_tune(elmfb_batch B, int32_t prec, int32_t reps, int32_t
     for (int c = 0; c < 3; ++c) {
       if (prec == ELMFB_FP64 && tiles[c] == 64) continue;
       sh.ms_rmvb[c] = timed([&] {
-        return launch_bt_rmvb(prec, tiles[c], B->d_geos, B->d_insts, B->d_blocks, nb, A, B->d_u,
-                              R, nullptr, COL_STORE, B->d_w, B->d_red_c, s);
+        return launch_bt_rmvb(prec, tiles[c], L.geos, L.insts, L.blocks, L.slices, L.ns, A,
+                              B->d_u, R, nullptr, COL_STORE, B->d_w, B->d_red_c, s);
       });
       if (sh.ms_rmvb[c] >= 0 && sh.ms_rmvb[c] < best) { best = sh.ms_rmvb[c]; sh.rmvb_tile = tiles[c]; }
     }
     best = 1e300;
     for (int c = 0; c < 3; ++c) {
       sh.ms_mvb[c] = timed([&] {
-        return launch_bt_mvb(prec, B->d_geos, B->d_blocks, nb, A, B->d_v, R, nullptr, B->d_tpart,
-                             s, aheads[c]);
+        return launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, nullptr, B->d_tpart, s,
+                             aheads[c]);
       });
       if (sh.ms_mvb[c] >= 0 && sh.ms_mvb[c] < best) { best = sh.ms_mvb[c]; sh.mvb_ahead = aheads[c]; }
     }
     best = 1e300;
     for (int c = 0; c < 2; ++c) {
       sh.ms_gather[c] = timed([&] {
-        return launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
+        return launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles,
                                 (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE_SQ, R, B->d_u,
                                 nullptr, nullptr, B->d_red_r, s, c + 1);
       });
@@ -942,6 +1300,8 @@ elmfb_status elmfb_batch_set_tile(elmfb_batch B, int32_t prec, int32_t tile) {
 
 elmfb_status elmfb_batch_set_coords(elmfb_batch B, int32_t preconditioned) {
   if (!B) return bfail(B, ELMFB_E_INVALID, "NULL batch");
+  if (preconditioned && B->patch > 1)
+    return bfail(B, ELMFB_E_UNSUPPORTED, "block-Jacobi coordinates are per subdomain (patch 1)");
   B->coords_y = preconditioned != 0;
   return ELMFB_OK;
 }
@@ -950,11 +1310,13 @@ elmfb_status elmfb_batch_from_coords(elmfb_batch B, const double* y_dev, double*
                                      void* stream) {
   if (!B || !y_dev || !x_dev) return bfail(B, ELMFB_E_INVALID, "NULL argument");
   if (!B->bj_ready) return bfail(B, ELMFB_E_STATE, "no block-Jacobi factors");
+  if (B->patch > 1)
+    return bfail(B, ELMFB_E_UNSUPPORTED, "block-Jacobi coordinates are per subdomain (patch 1)");
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, y_dev, B->d_w, 1, 1, s));
-  BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, (int64_t)B->blocks.size(), B->d_rc,
-                               B->d_foff, R, B->d_w, nullptr, B->d_v, s));
+  BHIP(B, launch_bt_bj_recover(B->d_blocks, (int64_t)B->blocks.size(), B->d_rc, B->d_foff,
+                               nullptr, R, B->d_w, nullptr, B->d_v, s));
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, B->d_v, x_dev, 0, 1, s));
   return ELMFB_OK;
 }
@@ -988,8 +1350,8 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
       (mixed && (opts->inner_iters < 1 || opts->outer_lim < 0)))
     return bfail(B, ELMFB_E_INVALID, "bad solve options");
   const int n = B->n, R = B->R;
-  const int64_t nb = (int64_t)B->blocks.size();
   const bool bj = opts->precond != 0;
+  const BtLayout L = layout_of(B, bj);
   const bool warm = opts->x0_dev != nullptr;
   if (warm && !B->d_x0) {
     hipError_t e1 = balloc(B, &B->d_x0, B->n_phi * R * 8);
@@ -1024,8 +1386,8 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
     const elmfb_status st = bt_run(B, ELMFB_FP64, bj, opts->check_every, opts->use_graph != 0, s);
     if (st != ELMFB_OK) return st;
     if (bj && !B->coords_y)
-      BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_x,
-                                   warm ? B->d_x0 : nullptr, B->d_c, s));
+      BHIP(B, launch_bt_bj_recover(L.blocks, L.nb, factors_of(B), foff_of(B), perm_of(B), R,
+                                   B->d_x, warm ? B->d_x0 : nullptr, B->d_c, s));
     else if (warm)
       BHIP(B, launch_bt_recover_plain(B->n_phi * R, B->d_x, B->d_x0, B->d_c, s));
     else
@@ -1033,10 +1395,10 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
   } else {
     // FP64 refinement: r = rhs - A c, inner LSQR on the stored low-precision copy, c += d
     const int lo = B->lo_prec;
-    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_h, nullptr,
+    BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, L.insts, n, R, B->d_red_h, nullptr,
                                   0.0, 1, opts->btol, opts->outer_lim, s));
     if (warm)   // the residual of x0 (in d_red_r) may already meet the target
-      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r,
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, L.insts, n, R, B->d_red_r,
                                     nullptr, 0.0, 2, opts->btol, opts->outer_lim, s));
     BHIP(B, hipMemsetAsync(B->d_c, 0, (size_t)(B->n_phi * R * 8), s));
     for (;;) {
@@ -1053,20 +1415,20 @@ elmfb_status elmfb_batch_solve(elmfb_batch B, const elmfb_solve_opts* opts, doub
       BHIP(B, bt_residual(B, B->d_c, bj, s, rhs));
       const double* red_a = nullptr;
       if (opts->atol > 0.0) {   // ||A^T r|| per block with the FP64 matrix (v is free here)
-        BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], B->d_geos, B->d_insts, B->d_blocks, nb,
+        BHIP(B, launch_bt_rmvb(ELMFB_FP64, B->tp[0], L.geos, L.insts, L.blocks, L.slices, L.ns,
                                matrix_of(B, ELMFB_FP64, bj), B->d_u, R, nullptr, COL_STORE_SQ,
                                B->d_v, B->d_red_c, s));
         red_a = B->d_red_c;
       }
-      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, B->d_insts, n, R, B->d_red_r, red_a,
+      BHIP(B, launch_bt_outer_check(B->d_outer, B->d_state, L.insts, n, R, B->d_red_r, red_a,
                                     opts->atol, 0, opts->btol, opts->outer_lim, s));
     }
   }
   const double* fin = B->d_c;
   if (mixed) {   // coefficients x = x0 + R^{-1} c (or x0 + c; y = y0 + c in block-Jacobi coordinates)
     if (bj && !B->coords_y)
-      BHIP(B, launch_bt_bj_recover(B->d_geos, B->d_blocks, nb, B->d_rc, B->d_foff, R, B->d_c,
-                                   warm ? B->d_x0 : nullptr, B->d_x, s));
+      BHIP(B, launch_bt_bj_recover(L.blocks, L.nb, factors_of(B), foff_of(B), perm_of(B), R,
+                                   B->d_c, warm ? B->d_x0 : nullptr, B->d_x, s));
     else
       BHIP(B, launch_bt_recover_plain(B->n_phi * R, B->d_c, warm ? B->d_x0 : nullptr, B->d_x, s));
     fin = B->d_x;

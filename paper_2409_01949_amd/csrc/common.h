@@ -33,7 +33,10 @@ struct DevBlock {
   int32_t taby;     // offset of the y-axis envelope table entries for iy0..iy0+ny-1
   int32_t level;
   int32_t inst;     // instance of a batch (0 for a single problem)
-  int32_t jx, jy;   // subdomain indices along the axes within the level
+  int32_t jx, jy;   // subdomain indices along the axes within the level (patch indices for a
+                    // patch block)
+  int32_t nk;       // columns of the block: K for a subdomain; for a patch of the batched
+                    // block-Jacobi preconditioner, the columns of all its member subdomains
 };
 
 constexpr int kGramChunk = 4096;  // shared points per Gram chunk
@@ -55,6 +58,24 @@ struct GramChunk {
 // ---- batches of independent instances with several right-hand sides
 constexpr int kMaxRhs = 8;
 constexpr int kBatchMaxK = 128;      // features per subdomain in a batch
+// Columns of a patch block (P^d neighbouring subdomains of a level taken as one block of the
+// batched block-Jacobi preconditioner).
+constexpr int kPatchMaxK = 512;
+
+// <= kBatchMaxK consecutive columns of one block: the unit of work of the batched M^T U pass
+// (a subdomain block is one slice, a patch block several).
+struct ColSlice {
+  int32_t blk;
+  int32_t k0;       // first column of the slice within the block
+};
+
+// One tile of <= 128 x 128 entries of a block's diagonal Gram block G_b = M_b^T M_b: rows
+// [i0, i0 + 128) and columns [j0, j0 + 128), i0 <= j0 (the factorisation reads the upper
+// triangle only).
+struct GramTask {
+  int32_t blk;
+  int32_t i0, j0;
+};
 // Points per LDS stage of the batched A^T U pass; the autotuner picks one of these.
 constexpr int kBtTileChoices[3] = {16, 32, 64};
 

@@ -109,7 +109,6 @@ struct elmfb_problem_s {
   bool folded64 = false, folded_lo = false;
   double* d_Ahat = nullptr;
   void* d_Ahat_lo = nullptr;
-  Geo* d_geo1 = nullptr;
   Tile* d_ftiles = nullptr;
   int64_t n_ftiles = 0;
 

@@ -190,15 +190,17 @@ __device__ __forceinline__ void store_r(double* __restrict__ p, int R, const dou
   }
 }
 
-// y = R_b^{-1} c for the block's coefficients c in LDS (cs[k][rhs]); the result replaces cs.
-// The column-packed factor is streamed through LDS (fs, nfs doubles) in runs of whole columns
-// with coalesced loads; thread i < K accumulates output i over the staged columns k >= i.
+// y = R_b^{-1} c for the block's coefficients c in LDS (cs[k][rhs], K <= 512); the result
+// replaces cs.  The column-packed factor is streamed through LDS (fs, nfs doubles) in runs of
+// whole columns with coalesced loads; thread t accumulates outputs i = t and t + 256 (i < K) over
+// the staged columns k >= i.
 __device__ __forceinline__ void bj_apply_lds(const double* __restrict__ rc, int K,
                                              double (*cs)[kMaxRhs], double* fs, int nfs) {
-  const int i = threadIdx.x;
-  double acc[kMaxRhs];
+  double acc[2][kMaxRhs];
 #pragma unroll
-  for (int j = 0; j < kMaxRhs; ++j) acc[j] = 0.0;
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < kMaxRhs; ++j) acc[h][j] = 0.0;
   int k0 = 0;
   while (k0 < K) {
     const int64_t base = packed_col(0, k0);
@@ -207,19 +209,27 @@ __device__ __forceinline__ void bj_apply_lds(const double* __restrict__ rc, int 
     const int cnt = (int)(packed_col(0, k1) - base);
     for (int e = threadIdx.x; e < cnt; e += 256) fs[e] = rc[base + e];
     __syncthreads();
-    if (i < K) {
-      for (int k = (i > k0 ? i : k0); k < k1; ++k) {
-        const double r = fs[packed_col(i, k) - base];
 #pragma unroll
-        for (int j = 0; j < kMaxRhs; ++j) acc[j] += r * cs[k][j];
+    for (int h = 0; h < 2; ++h) {
+      const int i = threadIdx.x + 256 * h;
+      if (i < K) {
+        for (int k = (i > k0 ? i : k0); k < k1; ++k) {
+          const double r = fs[packed_col(i, k) - base];
+#pragma unroll
+          for (int j = 0; j < kMaxRhs; ++j) acc[h][j] += r * cs[k][j];
+        }
       }
     }
     __syncthreads();
     k0 = k1;
   }
-  if (i < K) {
 #pragma unroll
-    for (int j = 0; j < kMaxRhs; ++j) cs[i][j] = acc[j];
+  for (int h = 0; h < 2; ++h) {
+    const int i = threadIdx.x + 256 * h;
+    if (i < K) {
+#pragma unroll
+      for (int j = 0; j < kMaxRhs; ++j) cs[i][j] = acc[h][j];
+    }
   }
   __syncthreads();
 }
@@ -230,17 +240,19 @@ constexpr int kFacStage = 2048;   // doubles of a packed factor staged per round
 // tpart[(p_off + p) * R + rhs] (V scaled per pair by 1/alpha, or 0 once the pair is done).  The
 // waves take 64-point runs of the block in turn; each lane loads FA feature entries ahead of
 // their products (the autotuner's choice; the sum order over features does not depend on it).
+// The block's coefficients are staged in dynamic LDS, cs[k][rhs] for k < nk (the launch sizes it
+// for the largest block).
 template <int PREC, int FA>
-__global__ void __launch_bounds__(256) k_bt_mvb(const Geo* __restrict__ geos,
-                                                const DevBlock* __restrict__ blocks,
+__global__ void __launch_bounds__(256) k_bt_mvb(const DevBlock* __restrict__ blocks,
                                                 const void* __restrict__ A,
                                                 const double* __restrict__ v, int R,
                                                 const SolveState* __restrict__ st,
                                                 double* __restrict__ tpart) {
-  __shared__ double cs[kBatchMaxK][kMaxRhs];
+  extern __shared__ double cs_dyn[];
+  double (*cs)[kMaxRhs] = reinterpret_cast<double (*)[kMaxRhs]>(cs_dyn);
   const DevBlock B = blocks[blockIdx.x];
   if (inst_all_done(st, B.inst, R)) return;
-  const int K = geos[B.inst].K;
+  const int K = B.nk;
   for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
     const int k = e >> 3, j = e & 7;
     cs[k][j] = j < R ? v[(int64_t)(B.q0 + k) * R + j] * pair_scale(st, B.inst * R + j, true) : 0.0;
@@ -440,17 +452,20 @@ __device__ __forceinline__ void col_epilogue(int q0, int inst, int R, int kk,
   }
 }
 
-// X = A^T U for one block and every right-hand side.  Tiles of TP points
+// X = A^T U for one slice of <= 128 columns of a block and every right-hand side (a subdomain
+// block is one slice; a patch block of the block-Jacobi preconditioner has several, each reading
+// the patch's rows of U).  Tiles of TP points
 // are staged in LDS (the block's K feature rows, and U on the tile's rows gathered from the
 // grid), the next tile's loads in flight while the current one is reduced; thread (k, s) owns
 // feature k and half s of the tile's points, so no cross-lane reduction is needed.  The
 // epilogue stores the block's columns (COL_STORE), applies the LSQR step v = x - beta sv v
 // (COL_LSQR_V) or stores and squares (COL_STORE_SQ); per-block partial squared norms go to
-// red[block][rhs].
+// red[slice][rhs].
 template <int PREC, int TP>
 __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
                                                  const InstInfo* __restrict__ insts,
                                                  const DevBlock* __restrict__ blocks,
+                                                 const ColSlice* __restrict__ slices,
                                                  const void* __restrict__ A,
                                                  const double* __restrict__ u, int R,
                                                  const SolveState* __restrict__ st, int mode,
@@ -467,12 +482,13 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
   __shared__ double us[TP][kMaxRhs];
   __shared__ double xs[kBatchMaxK][kMaxRhs];
   __shared__ double sh[4][kMaxRhs];
-  const DevBlock B = blocks[blockIdx.x];
+  const ColSlice S = slices[blockIdx.x];
+  const DevBlock B = blocks[S.blk];
   if (inst_all_done(st, B.inst, R)) return;
   const Geo& g = geos[B.inst];
   const int64_t row0 = insts[B.inst].row_off;
-  const int K = g.K, n = B.n, gny = g.ny;
-  const in_t* Ab = static_cast<const in_t*>(A) + B.a_off;
+  const int K = min(kBatchMaxK, B.nk - S.k0), n = B.n, gny = g.ny;
+  const in_t* Ab = static_cast<const in_t*>(A) + B.a_off + (int64_t)S.k0 * B.ld;
 
   // every U entry a thread stages has right-hand side threadIdx.x & 7: its pair scale is read
   // once, and applied when the tile is written to LDS, so the loads of the next tile stay in
@@ -551,20 +567,22 @@ __global__ void __launch_bounds__(256) k_bt_rmvb(const Geo* __restrict__ geos,
 #pragma unroll
     for (int j = 0; j < kMaxRhs; ++j) acc[j] += xs[k][j];
   }
-  col_epilogue(B.q0, B.inst, R, s == 0 && k < K ? k : -1, acc, mode, st, out, red, sh);
+  col_epilogue(B.q0 + S.k0, B.inst, R, s == 0 && k < K ? k : -1, acc, mode, st, out, red, sh);
 }
 
-// x = x0 + R^{-1} y per block and right-hand side (x0 may be NULL; x may alias x0).
-__global__ void __launch_bounds__(256) k_bt_bj_recover(const Geo* __restrict__ geos,
-                                                       const DevBlock* __restrict__ blocks,
+// x = x0 + R^{-1} y per block and right-hand side (x0 may be NULL; x may alias x0).  y is in
+// the blocks' column order; with perm (patch blocks) column q of that order is column perm[q] of
+// x and x0, else the two orders agree.
+__global__ void __launch_bounds__(256) k_bt_bj_recover(const DevBlock* __restrict__ blocks,
                                                        const double* __restrict__ rc,
-                                                       const int64_t* __restrict__ foff, int R,
+                                                       const int64_t* __restrict__ foff,
+                                                       const int32_t* __restrict__ perm, int R,
                                                        const double* __restrict__ y,
                                                        const double* x0, double* x) {
-  __shared__ double cs[kBatchMaxK][kMaxRhs];
+  __shared__ double cs[kPatchMaxK][kMaxRhs];
   __shared__ double fs[kFacStage];
   const DevBlock B = blocks[blockIdx.x];
-  const int K = geos[B.inst].K;
+  const int K = B.nk;
   for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
     const int k = e >> 3, j = e & 7;
     cs[k][j] = j < R ? y[(int64_t)(B.q0 + k) * R + j] : 0.0;
@@ -573,7 +591,8 @@ __global__ void __launch_bounds__(256) k_bt_bj_recover(const Geo* __restrict__ g
   bj_apply_lds(rc + foff[blockIdx.x], K, cs, fs, kFacStage);
   for (int e = threadIdx.x; e < K * R; e += 256) {
     const int k = e / R, j = e - (e / R) * R;
-    const int64_t o = (int64_t)(B.q0 + k) * R + j;
+    const int64_t q = perm ? (int64_t)perm[B.q0 + k] : (int64_t)(B.q0 + k);
+    const int64_t o = q * R + j;
     x[o] = (x0 ? x0[o] : 0.0) + cs[k][j];
   }
 }
@@ -892,27 +911,29 @@ hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* 
 }
 
 template <int FA>
-static void mvb_fa(int prec, dim3 grid, const Geo* geos, const DevBlock* blocks, const void* A,
+static void mvb_fa(int prec, dim3 grid, size_t lds, const DevBlock* blocks, const void* A,
                    const double* v, int R, const SolveState* st, double* tpart, hipStream_t s) {
   const dim3 blk(256);
   if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP32, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP32, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
   else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_BF16, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_BF16, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
   else if (prec == ELMFB_FP16)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP16, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP16, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
   else
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP64, FA>), grid, blk, 0, s, geos, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP64, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
 }
 
-hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, int64_t n_blocks, int kmax,
                          const void* A, const double* v, int R, const SolveState* st,
                          double* tpart, hipStream_t s, int fa) {
   if (n_blocks == 0) return hipSuccess;
+  if (kmax < 1 || kmax > kPatchMaxK) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_blocks);
-  if (fa == 4) mvb_fa<4>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
-  else if (fa == 8) mvb_fa<8>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
-  else if (fa == 16) mvb_fa<16>(prec, grid, geos, blocks, A, v, R, st, tpart, s);
+  const size_t lds = (size_t)kmax * kMaxRhs * sizeof(double);
+  if (fa == 4) mvb_fa<4>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
+  else if (fa == 8) mvb_fa<8>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
+  else if (fa == 16) mvb_fa<16>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -933,14 +954,14 @@ hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlo
 }
 
 hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* insts,
-                          const DevBlock* blocks, int64_t n_blocks, const void* A,
-                          const double* u, int R, const SolveState* st, int mode, double* out,
-                          double* red, hipStream_t s) {
-  if (n_blocks == 0) return hipSuccess;
-  const dim3 grid((unsigned)n_blocks), blk(256);
+                          const DevBlock* blocks, const ColSlice* slices, int64_t n_slices,
+                          const void* A, const double* u, int R, const SolveState* st, int mode,
+                          double* out, double* red, hipStream_t s) {
+  if (n_slices == 0) return hipSuccess;
+  const dim3 grid((unsigned)n_slices), blk(256);
 #define RMVB(P, T)                                                                          \
-  hipLaunchKernelGGL((k_bt_rmvb<P, T>), grid, blk, 0, s, geos, insts, blocks, A, u, R, st, mode, \
-                     out, red)
+  hipLaunchKernelGGL((k_bt_rmvb<P, T>), grid, blk, 0, s, geos, insts, blocks, slices, A, u, R, st, \
+                     mode, out, red)
   if (prec == ELMFB_FP32) {
     if (tp == 16) RMVB(ELMFB_FP32, 16); else if (tp == 32) RMVB(ELMFB_FP32, 32);
     else if (tp == 64) RMVB(ELMFB_FP32, 64); else return hipErrorInvalidValue;
@@ -959,12 +980,12 @@ hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* ins
   return hipGetLastError();
 }
 
-hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
-                                const double* rc, const int64_t* foff, int R, const double* y,
+hipError_t launch_bt_bj_recover(const DevBlock* blocks, int64_t n_blocks, const double* rc,
+                                const int64_t* foff, const int32_t* perm, int R, const double* y,
                                 const double* x0, double* x, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bt_bj_recover, dim3((unsigned)n_blocks), dim3(256), 0, s, geos, blocks, rc,
-                     foff, R, y, x0, x);
+  hipLaunchKernelGGL(k_bt_bj_recover, dim3((unsigned)n_blocks), dim3(256), 0, s, blocks, rc,
+                     foff, perm, R, y, x0, x);
   return hipGetLastError();
 }
 

@@ -162,7 +162,8 @@ hipError_t launch_bt_assemble(int lo_prec, const Geo* geos, const DevBlock* bloc
                               hipStream_t s);
 hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* rt, int64_t n_rt,
                          int R, const double* f, double* h, int32_t* bad, hipStream_t s);
-hipError_t launch_bt_mvb(int prec, const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+// kmax: largest nk of the blocks (<= kPatchMaxK; sets the dynamic LDS of the coefficients)
+hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, int64_t n_blocks, int kmax,
                          const void* A, const double* v, int R, const SolveState* st,
                          double* tpart, hipStream_t s, int fa = 8);
 hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
@@ -170,28 +171,43 @@ hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlo
                             const double* tpart, int mode, int R, double* out, const double* bvec,
                             const SolveState* st, double* red, hipStream_t s, int rpt = 1);
 // tp: points per LDS stage, one of kBtTileChoices (64 not for FP64)
+// one workgroup per column slice; red receives per-slice partials
 hipError_t launch_bt_rmvb(int prec, int tp, const Geo* geos, const InstInfo* insts,
-                          const DevBlock* blocks, int64_t n_blocks, const void* A,
-                          const double* u, int R, const SolveState* st, int mode, double* out,
-                          double* red, hipStream_t s);
-hipError_t launch_bt_bj_recover(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
-                                const double* rc, const int64_t* foff, int R, const double* y,
+                          const DevBlock* blocks, const ColSlice* slices, int64_t n_slices,
+                          const void* A, const double* u, int R, const SolveState* st, int mode,
+                          double* out, double* red, hipStream_t s);
+// perm (may be NULL): original column of every column of the blocks' order (patch blocks)
+hipError_t launch_bt_bj_recover(const DevBlock* blocks, int64_t n_blocks, const double* rc,
+                                const int64_t* foff, const int32_t* perm, int R, const double* y,
                                 const double* x0, double* x, hipStream_t s);
 hipError_t launch_bt_axpy(int64_t n, const double* y, double* x, hipStream_t s);
 hipError_t launch_bt_recover_plain(int64_t n, const double* y, const double* x0, double* x,
                                    hipStream_t s);
-hipError_t launch_bt_gram_diag(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
-                               const double* A, const int64_t* goff, double* G, hipStream_t s);
-// kmax: largest K of the blocks (<= kBatchMaxK; sets the dynamic LDS of two packed triangles)
-hipError_t launch_bt_bj_factor(const Geo* geos, const DevBlock* blocks, int64_t n_blocks,
+// two_panels: some task lies off the diagonal (blocks of more than 128 columns)
+hipError_t launch_bt_gram_diag(const DevBlock* blocks, const GramTask* tasks, int64_t n_tasks,
+                               bool two_panels, const double* A, const int64_t* goff, double* G,
+                               hipStream_t s);
+// blocks blk0 .. blk0 + n_blocks - 1; kmax: their largest nk (<= kBatchMaxK; sets the dynamic
+// LDS of two packed triangles)
+hipError_t launch_bt_bj_factor(const DevBlock* blocks, int blk0, int64_t n_blocks,
                                const double* G, const int64_t* goff, const int64_t* foff, int kmax,
                                double shift, double* rc, int32_t* nfail, hipStream_t s);
+// blocks of up to kPatchMaxK columns: W scratch beside G (both nk x nk at goff); G is overwritten
+hipError_t launch_bt_bj_factor_blocked(const DevBlock* blocks, int blk0, int64_t n_blocks,
+                                       double* G, double* W, const int64_t* goff,
+                                       const int64_t* foff, double shift, double* rc,
+                                       int32_t* nfail, hipStream_t s);
+// patch blocks (FP64, their own layout) from the subdomain blocks of the assembled M
+hipError_t launch_bt_expand(const Geo* geos, const DevBlock* pblocks, const Tile* runs,
+                            int64_t n_runs, const DevBlock* blocks, const int32_t* members,
+                            const int32_t* moff, const double* A, double* Ap, hipStream_t s);
 // full: rc holds R^{-1} as K x K row-major per block (foff unused); else column-packed at foff
-// kmax: largest K of the blocks (<= 256); Ahat may be NULL (low-precision result only)
-hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const Geo* geos,
-                          const DevBlock* blocks, const Tile* ftiles, int64_t n_ftiles,
-                          const double* A, const double* rc, const int64_t* foff, double* Ahat,
-                          void* Ahat_lo, hipStream_t s);
+// kmax: largest nk of the blocks (<= kPatchMaxK, <= 256 with full); runs of
+// fold_run_points(kmax) points; Ahat may be NULL (low-precision result only) or A itself
+int fold_run_points(int kmax);
+hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const DevBlock* blocks,
+                          const Tile* ftiles, int64_t n_ftiles, const double* A, const double* rc,
+                          const int64_t* foff, double* Ahat, void* Ahat_lo, hipStream_t s);
 // ot (may be NULL): outer state of a refined solve; pairs it marks done are frozen, the others
 // stop their inner LSQR once its residual estimate is inner_rel times the outer target
 hipError_t launch_bt_lsqr_init(SolveState* st, const InstInfo* insts, int n_inst, int R,

@@ -676,18 +676,16 @@ elmfb_status elmfb_precondition(elmfb_problem h, double shift, int32_t* n_fallba
       std::vector<Tile> ft;
       for (size_t b = 0; b < h->blocks.size(); ++b)
         for (int p0 = 0; p0 < h->blocks[b].n; p0 += 64) ft.push_back(Tile{(int32_t)b, p0});
-      HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_geo1, (int64_t)sizeof(Geo)));
       HIP_OR_FAIL(h, dalloc_bytes(h, (void**)&h->d_ftiles, (int64_t)(ft.size() * sizeof(Tile)) + 16));
-      HIP_OR_FAIL(h, hipMemcpy(h->d_geo1, &h->geo, sizeof(Geo), hipMemcpyHostToDevice));
       if (!ft.empty())
         HIP_OR_FAIL(h, hipMemcpy(h->d_ftiles, ft.data(), ft.size() * sizeof(Tile),
                                  hipMemcpyHostToDevice));
       h->n_ftiles = (int64_t)ft.size();
     }
     if (lo_ok || h->d_Ahat) {
-      HIP_OR_FAIL(h, launch_bt_fold(lo_ok ? h->lo_prec : ELMFB_FP64, true, g.K, h->d_geo1,
-                                    h->d_blocks, h->d_ftiles, h->n_ftiles, h->d_A, h->d_rinv,
-                                    nullptr, h->d_Ahat, lo_ok ? h->d_Ahat_lo : nullptr, s));
+      HIP_OR_FAIL(h, launch_bt_fold(lo_ok ? h->lo_prec : ELMFB_FP64, true, g.K, h->d_blocks,
+                                    h->d_ftiles, h->n_ftiles, h->d_A, h->d_rinv, nullptr,
+                                    h->d_Ahat, lo_ok ? h->d_Ahat_lo : nullptr, s));
       h->folded64 = h->d_Ahat != nullptr;
       h->folded_lo = lo_ok;
     }

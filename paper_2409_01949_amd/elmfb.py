@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libelmfb.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAX_BC = 4
 MAX_BC_PTS = 4096
 MAX_LEVELS = 8
@@ -195,6 +195,10 @@ def load_library(path: Optional[str] = None):
         "elmfb_batch_matvec": (i32, [P, P, P, P]),
         "elmfb_batch_rmatvec": (i32, [P, P, P, P]),
         "elmfb_batch_precondition": (i32, [P, ctypes.c_double, ctypes.POINTER(i32), P]),
+        "elmfb_batch_precondition_patches": (i32, [P, ctypes.c_double, i32, ctypes.POINTER(i32),
+                                                   P]),
+        "elmfb_batch_patch_info": (i32, [P, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "elmfb_batch_autotune": (i32, [P, i32, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i32), P]),
         "elmfb_batch_set_tile": (i32, [P, i32, i32]),
@@ -563,8 +567,10 @@ class Batch:
 
     def copy_blocks(self, dst=None, prec="fp64", folded=False, stream=None):
         """Block table [n_blocks, 8] (instance, level, ix0, nx, iy0, ny, K, element offset);
-        copies the raw blocks of M (or, folded, of M R^-1) in precision prec into dst if given."""
-        table = np.zeros((self.sizes["n_blocks"], 8), dtype=np.int64)
+        copies the raw blocks of M (or, folded, of M R^-1: the patch blocks when the factors are
+        of patches) in precision prec into dst if given."""
+        nb = self.patch_info()["n_blocks"] if folded else self.sizes["n_blocks"]
+        table = np.zeros((nb, 8), dtype=np.int64)
         pr = _PREC[prec] if isinstance(prec, str) else int(prec)
         if folded:
             pr |= COPY_FOLDED
@@ -579,12 +585,32 @@ class Batch:
     def rmatvec(self, u, x, stream=None):
         self._check(_lib.elmfb_batch_rmatvec(self.h, _ptr(u), _ptr(x), _stream(stream)))
 
-    def precondition(self, shift=1e-12, stream=None):
-        """Block-Jacobi factors of every block; returns the number of identity fallbacks."""
+    def precondition(self, shift=1e-12, patch=1, stream=None):
+        """Block-Jacobi factors of every block (patch = 1) or of every patch of patch^d
+        neighbouring subdomains; returns the number of identity fallbacks."""
         nf = ctypes.c_int32(0)
-        self._check(_lib.elmfb_batch_precondition(self.h, float(shift), ctypes.byref(nf),
-                                                  _stream(stream)))
+        if patch == 1:
+            self._check(_lib.elmfb_batch_precondition(self.h, float(shift), ctypes.byref(nf),
+                                                      _stream(stream)))
+        else:
+            self._check(_lib.elmfb_batch_precondition_patches(self.h, float(shift), int(patch),
+                                                              ctypes.byref(nf), _stream(stream)))
         return int(nf.value)
+
+    def patch_info(self, perm=False):
+        """{'patch', 'n_blocks', 'n_entries'} of the factors held, and with perm=True the original
+        column of every column of the preconditioned coefficients' order ('perm', int32)."""
+        pt = ctypes.c_int32(0)
+        nb = ctypes.c_int64(0)
+        ne = ctypes.c_int64(0)
+        pv = np.zeros(self.sizes["n_phi"], dtype=np.int32) if perm else None
+        self._check(_lib.elmfb_batch_patch_info(
+            self.h, ctypes.byref(pt), ctypes.byref(nb), ctypes.byref(ne),
+            pv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if perm else None))
+        out = {"patch": int(pt.value), "n_blocks": int(nb.value), "n_entries": int(ne.value)}
+        if perm:
+            out["perm"] = pv
+        return out
 
     def autotune(self, prec="fp64", reps=5, stream=None):
         """Time the M^T U tile variants; returns ({tile: ms}, chosen tile)."""

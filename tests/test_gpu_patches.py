@@ -1,0 +1,290 @@
+"""GPU parity of the batched block-Jacobi preconditioner over patches of neighbouring subdomains
+(elmfb_batch_precondition_patches): the patch tables, column order and folded blocks M_p R_p^{-1}
+(FP64 and rounded) against the oracle's patch blocks, preconditioned LSQR iterates and FP64
+refinement against the oracle's solves on the folded patch system, the widest patches (512 and
+360 columns: the blocked factorisation and the widest fold), and the refusals.  Every call goes
+through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from inputs import configs, feature_params
+from oracle import assemble as asm
+from oracle import linalg, lowprec
+
+from gpu_util import check_rounded_fold, dev, fold_tolerance, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+R = 2
+
+
+def _specs():
+    specs, _ = configs.batch_instances(n=3, seed=11, n_rhs=R, J_range=(3, 6), K_range=(12, 30),
+                                       p_range=(10.0, 30.0))
+    return specs + [configs.small2d(), configs.small1d_multilevel()]
+
+
+def _forcing(spec):
+    if "rhs_amps" in spec.meta:
+        return configs.batch_forcing(spec)[:R]
+    base = configs.forcing(spec)
+    return np.stack([base * (1.0 + 0.5 * j) for j in range(R)])
+
+
+def _make(store, specs=None):
+    from paper_2409_01949_amd import Batch
+    specs = _specs() if specs is None else specs
+    feats = [feature_params(s) for s in specs]
+    B = Batch(specs, [w for w, _ in feats], [b for _, b in feats], R, store_prec=store)
+    fs = [_forcing(s) for s in specs]
+    B.assemble(dev(np.concatenate([f.ravel() for f in fs])))
+    oracle = []
+    for s, (W, b), f in zip(specs, feats, fs):
+        blocks = asm.assemble_blocks(s, W, b)
+        oracle.append((s, blocks, np.stack([asm.rhs(s, fj) for fj in f])))
+    return B, oracle
+
+
+def _coefs(B, coef, oracle):
+    ch = coef.cpu().numpy()
+    out = []
+    for i, (s, bl, _) in enumerate(oracle):
+        n = len(bl) * s.K
+        c0 = B.offsets[i][1]
+        out.append(ch[R * c0:R * (c0 + n)].reshape(R, n))
+    return out
+
+
+def _box_rows(spec, ix0, nx, iy0, ny):
+    ny_grid = spec.n_points[1] if spec.dim == 2 else 1
+    ix, iy = np.meshgrid(np.arange(ix0, ix0 + nx), np.arange(iy0, iy0 + ny), indexing="ij")
+    return (ix * ny_grid + iy).ravel()
+
+
+def _check_patches(B, oracle, P, store, shift):
+    """Tables, column order and folded blocks of patch size P against the oracle."""
+    torch = torch_mod()
+    B.precondition(shift, patch=P)
+    info = B.patch_info(perm=True)
+    pbs = [linalg.patch_blocks(bl, P) for _, bl, _ in oracle]
+    assert info["patch"] == P
+    assert info["n_blocks"] == sum(len(pb) for pb in pbs)
+    for i, ((s, bl, _), pb) in enumerate(zip(oracle, pbs)):
+        c0 = B.offsets[i][1]
+        n = len(bl) * s.K
+        np.testing.assert_array_equal(info["perm"][c0:c0 + n] - c0, linalg.patch_order(pb))
+    ne = info["n_entries"]
+    b64 = torch.empty(ne, dtype=torch.float64, device="cuda")
+    table = B.copy_blocks(b64, "fp64", folded=True)
+    hlo = None
+    if store != "fp64":
+        blo = torch.empty(ne, dtype={"fp32": torch.float32, "fp16": torch.float16}[store],
+                          device="cuda")
+        B.copy_blocks(blo, store, folded=True)
+        hlo = blo.double().cpu().numpy()
+    torch.cuda.synchronize()
+    h64 = b64.cpu().numpy()
+    rounding = {"fp32": lowprec.to_f32, "fp16": lowprec.to_fp16}.get(store)
+    k, worst = 0, 0.0
+    for i, ((s, bl, _), pb) in enumerate(zip(oracle, pbs)):
+        fold = linalg.fold_blocks(pb, linalg.block_jacobi_factors(pb, shift))
+        for p in fold:
+            inst, lvl, ix0, nx, iy0, ny, nk, off = (int(v) for v in table[k])
+            k += 1
+            assert inst == i and lvl == p.level and nk == p.M.shape[1]
+            # the patch box is the union of the members' supports
+            np.testing.assert_array_equal(_box_rows(s, ix0, nx, iy0, ny), p.rows)
+            npt = nx * ny
+            A64 = h64[off:off + nk * npt].reshape(nk, npt).T
+            tol = fold_tolerance(p.M, nk, shift)
+            err = np.abs(A64 - p.M).max()
+            worst = max(worst, err / tol)
+            assert err <= tol, (i, k, err, tol)
+            if hlo is not None:
+                Alo = hlo[off:off + nk * npt].reshape(nk, npt).T
+                check_rounded_fold(Alo, p.M, rounding, tol)
+    assert k == len(table)
+    print(f"patch {P}, {store}: {k} patch blocks, FP64 fold worst {worst:.2f} of its tolerance")
+    return pbs
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_patch_tables_and_folded_blocks(P):
+    B, oracle = _make("fp32")
+    try:
+        _check_patches(B, oracle, P, "fp32", 1e-4)
+    finally:
+        B.destroy()
+
+
+def test_patch_lsqr_iterates_and_back_to_subdomains():
+    """Preconditioned LSQR on the folded patch system equals the oracle's after 1 and 5 steps
+    (coefficients x = R^{-1} y in the original column order, and ||r||); factors of patch 1 taken
+    afterwards give the per-subdomain preconditioner again."""
+    B, oracle = _make("fp64")
+    torch = torch_mod()
+    shift = 1e-6
+    try:
+        pbs = _check_patches(B, oracle, 2, "fp64", shift)
+        for k in (1, 5):
+            coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+            infos = B.solve(coef, iter_lim=k, atol=0.0, btol=0.0, check_every=5, precond=True)
+            cs = _coefs(B, coef, oracle)
+            worst = 0.0
+            for i, ((s, bl, h), pb) in enumerate(zip(oracle, pbs)):
+                facs = linalg.block_jacobi_factors(pb, shift)
+                fold = linalg.fold_blocks(pb, facs)
+                n = len(bl) * s.K
+                for j in range(R):
+                    res = linalg.lsqr(lambda y: linalg.patch_matvec(fold, y, s.n_rows),
+                                      lambda u: linalg.patch_rmatvec(fold, u), h[j], n,
+                                      atol=0, btol=0, iter_lim=k)
+                    x_ref = linalg.patch_recover(pb, facs, res.x)
+                    worst = max(worst, np.linalg.norm(cs[i][j] - x_ref) / np.linalg.norm(x_ref))
+                    assert infos[i * R + j]["iters"] == k
+                    assert abs(infos[i * R + j]["rnorm"] - res.rnorm) <= 1e-8 * res.rnorm
+            print(f"patch 2 lsqr k={k}: worst coefficient rel diff {worst:.2e}")
+            assert worst <= 1e-8
+        # back to per-subdomain factors: the folded copy is in the subdomain blocks again
+        B.precondition(shift)
+        assert B.patch_info() == {"patch": 1, "n_blocks": B.sizes["n_blocks"],
+                                  "n_entries": B.sizes["nnz"]}
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        B.solve(coef, iter_lim=3, atol=0.0, btol=0.0, check_every=3, precond=True)
+        cs = _coefs(B, coef, oracle)
+        s, bl, h = oracle[0]
+        n = len(bl) * s.K
+        facs = linalg.block_jacobi_factors(bl, shift)
+        x_ref, _ = linalg.preconditioned_lsqr(lambda v: asm.matvec(bl, v, s.n_rows),
+                                              lambda u: asm.rmatvec(bl, u, n), bl, facs, h[0], n,
+                                              atol=0, btol=0, iter_lim=3)
+        assert np.linalg.norm(cs[0][0] - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    finally:
+        B.destroy()
+
+
+def test_patch_mixed_refinement_matches_oracle():
+    """FP64 refinement around inner LSQR on the FP32 rounding of the folded patch system: after
+    1 and 2 outer steps of 5 inner steps every pair equals the oracle's refinement on its folded
+    patch blocks, mapped back by R^{-1}, to 1e-7; the reported residual is the oracle's."""
+    B, oracle = _make("fp32")
+    torch = torch_mod()
+    shift = 1e-6
+    try:
+        B.precondition(shift, patch=2)
+        pbs = [linalg.patch_blocks(bl, 2) for _, bl, _ in oracle]
+        inner = 5
+        for outer in (1, 2):
+            coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+            infos = B.solve(coef, method="mixed_ir", inner_iters=inner, outer_lim=outer,
+                            check_every=5, precond=True, atol=0.0, btol=0.0)
+            cs = _coefs(B, coef, oracle)
+            worst = 0.0
+            for i, ((s, bl, h), pb) in enumerate(zip(oracle, pbs)):
+                facs = linalg.block_jacobi_factors(pb, shift)
+                fold = linalg.fold_blocks(pb, facs)
+                lo = [dataclasses.replace(p, M=lowprec.to_f32(p.M)) for p in fold]
+                n = len(bl) * s.K
+                for j in range(R):
+                    info = infos[i * R + j]
+                    assert info["outer_iters"] == outer and info["iters"] == outer * inner
+                    cy, _ = linalg.refine_lsqr(
+                        lambda y: linalg.patch_matvec(fold, y, s.n_rows),
+                        lambda u: linalg.patch_rmatvec(fold, u),
+                        lambda y: linalg.patch_matvec(lo, y, s.n_rows),
+                        lambda u: linalg.patch_rmatvec(lo, u), h[j], n, outer, inner)
+                    c = linalg.patch_recover(pb, facs, cy)
+                    worst = max(worst, np.linalg.norm(cs[i][j] - c) / np.linalg.norm(c))
+                    r = np.linalg.norm(asm.matvec(bl, cs[i][j], s.n_rows) - h[j])
+                    assert abs(info["rnorm"] - r) <= 1e-9 * np.linalg.norm(h[j])
+            print(f"patch 2 mixed outer={outer}: worst coefficient rel diff {worst:.2e}")
+            assert worst <= 1e-7
+    finally:
+        B.destroy()
+
+
+@pytest.mark.parametrize("K,P", [(128, 2), (40, 3)], ids=["nk512", "nk360"])
+def test_widest_patches(K, P):
+    """Patches of 512 columns (K = 128, 2 x 2 subdomains) and of 360 columns (K = 40, 3 x 3,
+    a ragged last panel of the blocked factorisation): folded blocks against the oracle, and five
+    preconditioned LSQR steps."""
+    spec = dataclasses.replace(configs.batch_instances(n=1, seed=5, n_rhs=R)[0][0],
+                               levels=((2 * P, 2 * P),), K=K, n_points=(7 * P, 7 * P))
+    B, oracle = _make("fp32", [spec])
+    torch = torch_mod()
+    shift = 1e-6
+    try:
+        pbs = _check_patches(B, oracle, P, "fp32", shift)
+        assert max(p.M.shape[1] for p in pbs[0]) == P * P * K
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        infos = B.solve(coef, iter_lim=5, atol=0.0, btol=0.0, check_every=5, precond=True)
+        cs = _coefs(B, coef, oracle)
+        s, bl, h = oracle[0]
+        facs = linalg.block_jacobi_factors(pbs[0], shift)
+        fold = linalg.fold_blocks(pbs[0], facs)
+        n = len(bl) * s.K
+        for j in range(R):
+            res = linalg.lsqr(lambda y: linalg.patch_matvec(fold, y, s.n_rows),
+                              lambda u: linalg.patch_rmatvec(fold, u), h[j], n, atol=0, btol=0,
+                              iter_lim=5)
+            x_ref = linalg.patch_recover(pbs[0], facs, res.x)
+            err = np.linalg.norm(cs[0][j] - x_ref) / np.linalg.norm(x_ref)
+            print(f"nk {P * P * K}: rhs {j} coefficient rel diff {err:.2e}")
+            assert err <= 1e-8
+            assert abs(infos[j]["rnorm"] - res.rnorm) <= 1e-8 * res.rnorm
+    finally:
+        B.destroy()
+
+
+def test_patches_beat_subdomain_blocks():
+    """On batch instances of the benchmark's family (smaller grids), 400 preconditioned steps
+    with 2 x 2 patches leave a smaller residual than with per-subdomain blocks on every pair, and
+    the oracle confirms the residual of the returned coefficients."""
+    specs, _ = configs.batch_instances(n=4, seed=9, n_rhs=R, J_range=(4, 8), K_range=(64, 96),
+                                       p_range=(20.0, 40.0))
+    B, oracle = _make("fp64", specs)
+    torch = torch_mod()
+    try:
+        out = {}
+        for P in (1, 2):
+            B.precondition(1e-12, patch=P)
+            coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+            out[P] = (B.solve(coef, iter_lim=400, atol=0.0, btol=0.0, check_every=100,
+                              precond=True), _coefs(B, coef, oracle))
+        for i, (s, bl, h) in enumerate(oracle):
+            for j in range(R):
+                r1, r2 = out[1][0][i * R + j]["rnorm"], out[2][0][i * R + j]["rnorm"]
+                r = np.linalg.norm(asm.matvec(bl, out[2][1][i][j], s.n_rows) - h[j])
+                hn = np.linalg.norm(h[j])
+                print(f"instance {i} rhs {j}: ||r||/||h|| subdomains {r1 / hn:.2e}, "
+                      f"patches {r2 / hn:.2e} (oracle {r / hn:.2e})")
+                assert abs(r - r2) <= 1e-6 * hn + 1e-3 * r
+                assert r2 < r1
+    finally:
+        B.destroy()
+
+
+def test_patch_refusals():
+    """Patch sizes outside 1..4, patches of more than 512 columns, and block-Jacobi coordinates
+    with patches are refused; the batch stays usable."""
+    spec = dataclasses.replace(configs.batch_instances(n=1, seed=5, n_rhs=R)[0][0],
+                               levels=((6, 6),), K=128, n_points=(30, 30))
+    B, oracle = _make("fp64", [spec])
+    try:
+        for bad in (0, 5):
+            with pytest.raises(Exception, match="patch"):
+                B.precondition(1e-8, patch=bad)
+        with pytest.raises(Exception, match="512"):
+            B.precondition(1e-8, patch=3)
+        B.precondition(1e-8, patch=2)
+        with pytest.raises(Exception, match="patch 1"):
+            B.set_coords(True)
+        B.precondition(1e-8)
+        B.set_coords(True)
+        with pytest.raises(Exception, match="patch 1"):
+            B.precondition(1e-8, patch=2)
+        B.set_coords(False)
+    finally:
+        B.destroy()
