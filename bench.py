@@ -282,9 +282,11 @@ def cpu_baseline(spec, W, b, f, n_iters_solve, total_nnz, rows_per_step=None, ma
 def run_batch(args, steps=None, warmup=None, iters=None):
     """The ragged batch: 512 independent 2D Poisson instances (J~U{4..24}^2, K~U{64..128},
     20..60 points per subdomain cell), 8 right-hand sides each, every kernel one launch over the
-    batch.  A step is assembly, block-Jacobi factors and the solve of every (instance, rhs) pair
-    until ||h - M c|| <= btol ||h|| (istop 1), least-squares optimality ||M^T r|| <= btol ||M|| ||r||
-    (istop 2; pairs whose features cannot represent the solution) or the iteration budget."""
+    batch.  A step is assembly, block-Jacobi factors (per subdomain, or over patches of
+    --batch-patch^2 neighbouring subdomains) and the solve of every (instance, rhs) pair until
+    ||h - M c|| <= btol ||h|| (istop 1), for the refinement also least-squares optimality
+    ||M^T r|| <= btol ||M|| ||r|| (istop 2; pairs whose features cannot represent the solution),
+    or the iteration budget."""
     import numpy as np
     import torch
 
@@ -329,7 +331,9 @@ def run_batch(args, steps=None, warmup=None, iters=None):
                           outer_lim=max(1, budget // inner), atol=btol, btol=btol,
                           check_every=args.check_every, precond=precond)
         else:
-            inf = B.solve(coef, iter_lim=budget, atol=btol, btol=btol,
+            # the refinement's residual test ||r|| <= btol ||h|| (atol = 0: Paige and Saunders'
+            # first test without its atol ||A|| ||x|| term, the second test off)
+            inf = B.solve(coef, iter_lim=budget, atol=0.0, btol=btol,
                           check_every=args.check_every, precond=precond)
         torch.cuda.synchronize()
         return inf, tb - ta, time.perf_counter() - tb
