@@ -81,7 +81,7 @@ struct elmfb_batch_s {
   std::vector<DevBlock> pblocks;
   std::vector<int32_t> pcov, pmem, pmoff, pperm;
   std::vector<ColSlice> pslices;
-  std::vector<Tile> pftiles, pruns;
+  std::vector<Tile> pftiles, pruns, pmvruns;
   std::vector<GramTask> ptasks;
   std::vector<int64_t> pfoff, pgoff;
   std::vector<int64_t> pchunk_blk, pchunk_task;   // factor chunks: first block and first task
@@ -92,7 +92,7 @@ struct elmfb_batch_s {
   DevBlock* d_pblocks = nullptr;
   int32_t *d_pcov = nullptr, *d_pmem = nullptr, *d_pmoff = nullptr, *d_pperm = nullptr;
   ColSlice* d_pslices = nullptr;
-  Tile *d_pftiles = nullptr, *d_pruns = nullptr;
+  Tile *d_pftiles = nullptr, *d_pruns = nullptr, *d_pmvruns = nullptr;
   GramTask* d_ptasks = nullptr;
   int64_t *d_pfoff = nullptr, *d_pgoff = nullptr;
   double *d_pAhat = nullptr, *d_prc = nullptr;
@@ -281,7 +281,8 @@ constexpr int64_t kPatchScratch = (int64_t)1 << 28;   // 2 GiB of doubles per ma
 std::string plan_patches(elmfb_batch B, int P) {
   B->pgeos.clear(); B->pinsts.clear(); B->pblocks.clear(); B->pcov.clear(); B->pmem.clear();
   B->pmoff.clear(); B->pperm.assign((size_t)B->n_phi, -1); B->pslices.clear();
-  B->pftiles.clear(); B->pruns.clear(); B->ptasks.clear(); B->pfoff.clear(); B->pgoff.clear();
+  B->pftiles.clear(); B->pruns.clear(); B->pmvruns.clear(); B->ptasks.clear(); B->pfoff.clear();
+  B->pgoff.clear();
   B->pchunk_blk.clear(); B->pchunk_task.clear();
   int64_t a_off = 0, p_off = 0, f_off = 0, dense = 0;
   int kmax = 1;
@@ -366,6 +367,10 @@ std::string plan_patches(elmfb_batch B, int P) {
   for (size_t b = 0; b < B->pblocks.size(); ++b)
     for (int p0 = 0; p0 < B->pblocks[b].n; p0 += run) ft.push_back(Tile{(int32_t)b, p0});
   B->pftiles = xcd_grouped(ft);
+  std::vector<Tile> mr;
+  for (size_t b = 0; b < B->pblocks.size(); ++b)
+    for (int p0 = 0; p0 < B->pblocks[b].n; p0 += 256) mr.push_back(Tile{(int32_t)b, p0});
+  B->pmvruns = xcd_grouped(mr);
   int64_t g_off = 0, scratch = 0;
   size_t t = 0;
   for (size_t b = 0; b < B->pblocks.size(); ++b) {
@@ -398,6 +403,8 @@ struct BtLayout {
   const InstInfo* insts;
   const DevBlock* blocks;
   int64_t nb;
+  const Tile* mv_runs;   // point runs of the M V pass (NULL: one workgroup per block)
+  int64_t n_mv;          // its grid: runs, or blocks
   const int32_t* cov;
   const ColSlice* slices;
   int64_t ns;
@@ -406,13 +413,15 @@ struct BtLayout {
 };
 
 BtLayout sub_layout(elmfb_batch B) {
-  return BtLayout{B->d_geos, B->d_insts, B->d_blocks, (int64_t)B->blocks.size(), B->d_cov,
-                  B->d_slices, (int64_t)B->slices.size(), B->kmax, B->n_bp};
+  return BtLayout{B->d_geos, B->d_insts, B->d_blocks, (int64_t)B->blocks.size(), nullptr,
+                  (int64_t)B->blocks.size(), B->d_cov, B->d_slices, (int64_t)B->slices.size(),
+                  B->kmax, B->n_bp};
 }
 
 BtLayout patch_layout(elmfb_batch B) {
-  return BtLayout{B->d_pgeos, B->d_pinsts, B->d_pblocks, (int64_t)B->pblocks.size(), B->d_pcov,
-                  B->d_pslices, (int64_t)B->pslices.size(), B->pkmax, B->pn_bp};
+  return BtLayout{B->d_pgeos, B->d_pinsts, B->d_pblocks, (int64_t)B->pblocks.size(),
+                  B->d_pmvruns, (int64_t)B->pmvruns.size(), B->d_pcov, B->d_pslices,
+                  (int64_t)B->pslices.size(), B->pkmax, B->pn_bp};
 }
 
 // Preconditioned passes run on the folded matrix, in the patch layout when the factors are of
@@ -459,8 +468,8 @@ hipError_t bt_iteration(elmfb_batch B, int prec, bool bj, hipStream_t s) {
   const BtLayout L = layout_of(B, bj);
   const void* A = matrix_of(B, prec, bj);
   hipError_t e;
-  if ((e = launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, B->d_state, B->d_tpart, s,
-                         B->fa[prec_index(prec)])))
+  if ((e = launch_bt_mvb(prec, L.blocks, L.mv_runs, L.n_mv, L.kmax, A, B->d_v, R, B->d_state,
+                         B->d_tpart, s, B->fa[prec_index(prec)])))
     return e;
   if ((e = launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles,
                             (int64_t)B->rtiles.size(), B->d_tpart, ROW_LSQR_U, R, B->d_u, nullptr,
@@ -509,8 +518,9 @@ hipError_t bt_residual(elmfb_batch B, const double* c, bool bj, hipStream_t s,
   const BtLayout L = layout_of(B, bj);
   hipError_t e;
   if (c) {
-    if ((e = launch_bt_mvb(ELMFB_FP64, L.blocks, L.nb, L.kmax, matrix_of(B, ELMFB_FP64, bj), c, R,
-                           nullptr, B->d_tpart, s, B->fa[0])))
+    if ((e = launch_bt_mvb(ELMFB_FP64, L.blocks, L.mv_runs, L.n_mv, L.kmax,
+                           matrix_of(B, ELMFB_FP64, bj), c, R, nullptr, B->d_tpart, s,
+                           B->fa[0])))
       return e;
   } else if ((e = hipMemsetAsync(B->d_tpart, 0, (size_t)(L.n_bp * R * 8), s))) {
     return e;
@@ -870,8 +880,8 @@ elmfb_status elmfb_batch_matvec(elmfb_batch B, const double* v_dev, double* y_de
   hipStream_t s = (hipStream_t)stream;
   const int R = B->R;
   BHIP(B, launch_bt_pack(B->d_insts, B->d_nphis, B->n, R, B->n_phi, v_dev, B->d_w, 1, 1, s));
-  BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_blocks, (int64_t)B->blocks.size(), B->kmax, B->d_A,
-                        B->d_w, R, nullptr, B->d_tpart, s, B->fa[0]));
+  BHIP(B, launch_bt_mvb(ELMFB_FP64, B->d_blocks, nullptr, (int64_t)B->blocks.size(), B->kmax,
+                        B->d_A, B->d_w, R, nullptr, B->d_tpart, s, B->fa[0]));
   BHIP(B, launch_bt_gather(B->d_geos, B->d_insts, B->d_blocks, B->d_cov, B->d_rtiles,
                            (int64_t)B->rtiles.size(), B->d_tpart, ROW_STORE, R, B->d_u, nullptr,
                            nullptr, B->d_red_r, s, B->rpt));
@@ -961,7 +971,8 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
       // device tables (replacing those of another patch size)
       release(B->d_pgeos); release(B->d_pinsts); release(B->d_pblocks); release(B->d_pcov);
       release(B->d_pmem); release(B->d_pmoff); release(B->d_pperm); release(B->d_pslices);
-      release(B->d_pftiles); release(B->d_pruns); release(B->d_ptasks); release(B->d_pfoff);
+      release(B->d_pftiles); release(B->d_pruns); release(B->d_pmvruns); release(B->d_ptasks);
+      release(B->d_pfoff);
       release(B->d_pgoff);
       hipError_t ea = hipSuccess;
       auto put = [&](auto*& dst, const auto& v) {
@@ -974,7 +985,8 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
       put(B->d_pgeos, B->pgeos); put(B->d_pinsts, B->pinsts); put(B->d_pblocks, B->pblocks);
       put(B->d_pcov, B->pcov); put(B->d_pmem, B->pmem); put(B->d_pmoff, B->pmoff);
       put(B->d_pperm, B->pperm); put(B->d_pslices, B->pslices); put(B->d_pftiles, B->pftiles);
-      put(B->d_pruns, B->pruns); put(B->d_ptasks, B->ptasks); put(B->d_pfoff, B->pfoff);
+      put(B->d_pruns, B->pruns); put(B->d_pmvruns, B->pmvruns); put(B->d_ptasks, B->ptasks);
+      put(B->d_pfoff, B->pfoff);
       put(B->d_pgoff, B->pgoff);
       // the per-block-point partials of M V must hold the patch boxes as well
       if (ea == hipSuccess && B->pn_bp > B->tpart_bp) {
@@ -1131,8 +1143,8 @@ elmfb_status elmfb_batch_time_kernels(elmfb_batch B, int32_t prec, int32_t reps,
   for (int i = 0; i < 4; ++i) BHIP(B, hipEventCreate(&ev[i]));
   hipError_t e = hipEventRecord(ev[0], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, nullptr, B->d_tpart, s,
-                      B->fa[prec_index(prec)]);
+    e = launch_bt_mvb(prec, L.blocks, L.mv_runs, L.n_mv, L.kmax, A, B->d_v, R, nullptr,
+                      B->d_tpart, s, B->fa[prec_index(prec)]);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     e = launch_bt_gather(L.geos, L.insts, L.blocks, L.cov, B->d_rtiles, (int64_t)B->rtiles.size(),
@@ -1245,8 +1257,8 @@ elmfb_status elmfb_batch_tune(elmfb_batch B, int32_t prec, int32_t reps, int32_t
     best = 1e300;
     for (int c = 0; c < 3; ++c) {
       sh.ms_mvb[c] = timed([&] {
-        return launch_bt_mvb(prec, L.blocks, L.nb, L.kmax, A, B->d_v, R, nullptr, B->d_tpart, s,
-                             aheads[c]);
+        return launch_bt_mvb(prec, L.blocks, L.mv_runs, L.n_mv, L.kmax, A, B->d_v, R, nullptr,
+                             B->d_tpart, s, aheads[c]);
       });
       if (sh.ms_mvb[c] >= 0 && sh.ms_mvb[c] < best) { best = sh.ms_mvb[c]; sh.mvb_ahead = aheads[c]; }
     }

@@ -241,16 +241,21 @@ constexpr int kFacStage = 2048;   // doubles of a packed factor staged per round
 // waves take 64-point runs of the block in turn; each lane loads FA feature entries ahead of
 // their products (the autotuner's choice; the sum order over features does not depend on it).
 // The block's coefficients are staged in dynamic LDS, cs[k][rhs] for k < nk (the launch sizes it
-// for the largest block).
+// for the largest block).  Without runs a workgroup takes a whole block; with runs (patch blocks,
+// several hundred points over up to 512 columns) it takes one run of at most 256 points, so its
+// four waves get one 64-point group each (runs of a block are dealt to one XCD; blk = -1 pads).
 template <int PREC, int FA>
 __global__ void __launch_bounds__(256) k_bt_mvb(const DevBlock* __restrict__ blocks,
+                                                const Tile* __restrict__ runs,
                                                 const void* __restrict__ A,
                                                 const double* __restrict__ v, int R,
                                                 const SolveState* __restrict__ st,
                                                 double* __restrict__ tpart) {
   extern __shared__ double cs_dyn[];
   double (*cs)[kMaxRhs] = reinterpret_cast<double (*)[kMaxRhs]>(cs_dyn);
-  const DevBlock B = blocks[blockIdx.x];
+  const Tile run = runs ? runs[blockIdx.x] : Tile{(int32_t)blockIdx.x, 0};
+  if (run.blk < 0) return;
+  const DevBlock B = blocks[run.blk];
   if (inst_all_done(st, B.inst, R)) return;
   const int K = B.nk;
   for (int e = threadIdx.x; e < K * kMaxRhs; e += 256) {
@@ -259,8 +264,8 @@ __global__ void __launch_bounds__(256) k_bt_mvb(const DevBlock* __restrict__ blo
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int n = B.n, ld = B.ld;
-  for (int p0 = wid * 64; p0 < n; p0 += 256) {
+  const int n = runs ? min(B.n, run.p0 + 256) : B.n, ld = B.ld;
+  for (int p0 = run.p0 + wid * 64; p0 < n; p0 += 256) {
     const int p = p0 + lane;
     if (p < n) {
       double acc[kMaxRhs];
@@ -911,29 +916,34 @@ hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* 
 }
 
 template <int FA>
-static void mvb_fa(int prec, dim3 grid, size_t lds, const DevBlock* blocks, const void* A,
-                   const double* v, int R, const SolveState* st, double* tpart, hipStream_t s) {
+static void mvb_fa(int prec, dim3 grid, size_t lds, const DevBlock* blocks, const Tile* runs,
+                   const void* A, const double* v, int R, const SolveState* st, double* tpart,
+                   hipStream_t s) {
   const dim3 blk(256);
   if (prec == ELMFB_FP32)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP32, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP32, FA>), grid, blk, lds, s, blocks, runs, A, v, R, st,
+                       tpart);
   else if (prec == ELMFB_BF16)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_BF16, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_BF16, FA>), grid, blk, lds, s, blocks, runs, A, v, R, st,
+                       tpart);
   else if (prec == ELMFB_FP16)
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP16, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP16, FA>), grid, blk, lds, s, blocks, runs, A, v, R, st,
+                       tpart);
   else
-    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP64, FA>), grid, blk, lds, s, blocks, A, v, R, st, tpart);
+    hipLaunchKernelGGL((k_bt_mvb<ELMFB_FP64, FA>), grid, blk, lds, s, blocks, runs, A, v, R, st,
+                       tpart);
 }
 
-hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, int64_t n_blocks, int kmax,
-                         const void* A, const double* v, int R, const SolveState* st,
+hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, const Tile* runs, int64_t n_grid,
+                         int kmax, const void* A, const double* v, int R, const SolveState* st,
                          double* tpart, hipStream_t s, int fa) {
-  if (n_blocks == 0) return hipSuccess;
+  if (n_grid == 0) return hipSuccess;
   if (kmax < 1 || kmax > kPatchMaxK) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)n_blocks);
+  const dim3 grid((unsigned)n_grid);
   const size_t lds = (size_t)kmax * kMaxRhs * sizeof(double);
-  if (fa == 4) mvb_fa<4>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
-  else if (fa == 8) mvb_fa<8>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
-  else if (fa == 16) mvb_fa<16>(prec, grid, lds, blocks, A, v, R, st, tpart, s);
+  if (fa == 4) mvb_fa<4>(prec, grid, lds, blocks, runs, A, v, R, st, tpart, s);
+  else if (fa == 8) mvb_fa<8>(prec, grid, lds, blocks, runs, A, v, R, st, tpart, s);
+  else if (fa == 16) mvb_fa<16>(prec, grid, lds, blocks, runs, A, v, R, st, tpart, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -323,6 +323,7 @@ hipError_t launch_bt_fold(int lo_prec, bool full, int kmax, const DevBlock* bloc
 // factorisation is retried with a 100x larger shift up to 8 times; after that, or for an all-zero
 // block, the block gets the identity and nfail counts it.
 constexpr int kPanel = 16;
+constexpr int kRows = 8;   // rows of a trailing update in flight per thread
 
 __global__ void __launch_bounds__(256) k_bt_bj_factor_blocked(const DevBlock* __restrict__ blocks,
                                                               int blk0, double* __restrict__ G,
@@ -393,16 +394,24 @@ __global__ void __launch_bounds__(256) k_bt_bj_factor_blocked(const DevBlock* __
         }
       }
       __syncthreads();
-      for (int i = j0; i < K; ++i) {
-        double pi[kPanel];
+      // trailing update, kRows rows at a time so that their loads are in flight together
+      for (int i0 = j0; i0 < K; i0 += kRows) {
+        for (int j = i0 + t; j < K; j += 256) {
+          double pj[kPanel], w[kRows];
 #pragma unroll
-        for (int r = 0; r < kPanel; ++r) pi[r] = r < nb ? Pn[r][i] : 0.0;
-        for (int j = i + t; j < K; j += 256) {
-          double acc = Wb[(int64_t)i * K + j];
+          for (int r = 0; r < kPanel; ++r) pj[r] = r < nb ? Pn[r][j] : 0.0;
 #pragma unroll
-          for (int r = 0; r < kPanel; ++r)
-            if (r < nb) acc -= pi[r] * Pn[r][j];
-          Wb[(int64_t)i * K + j] = acc;
+          for (int a = 0; a < kRows; ++a)
+            w[a] = i0 + a <= j ? Wb[(int64_t)(i0 + a) * K + j] : 0.0;
+#pragma unroll
+          for (int a = 0; a < kRows; ++a) {
+            if (i0 + a <= j) {
+#pragma unroll
+              for (int r = 0; r < kPanel; ++r)
+                if (r < nb) w[a] -= Pn[r][i0 + a] * pj[r];
+              Wb[(int64_t)(i0 + a) * K + j] = w[a];
+            }
+          }
         }
       }
       __syncthreads();
@@ -429,6 +438,7 @@ __global__ void __launch_bounds__(256) k_bt_bj_factor_blocked(const DevBlock* __
       double T[kPanel];
 #pragma unroll
       for (int r = 0; r < kPanel; ++r) T[r] = (r < nb && ib + r == j) ? 1.0 : 0.0;
+#pragma unroll 8
       for (int s2 = ib + nb; s2 <= j; ++s2) {
         const double x = Gb[(int64_t)s2 * K + j];
 #pragma unroll

@@ -162,9 +162,11 @@ hipError_t launch_bt_assemble(int lo_prec, const Geo* geos, const DevBlock* bloc
                               hipStream_t s);
 hipError_t launch_bt_rhs(const Geo* geos, const InstInfo* insts, const RowTile* rt, int64_t n_rt,
                          int R, const double* f, double* h, int32_t* bad, hipStream_t s);
-// kmax: largest nk of the blocks (<= kPatchMaxK; sets the dynamic LDS of the coefficients)
-hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, int64_t n_blocks, int kmax,
-                         const void* A, const double* v, int R, const SolveState* st,
+// runs NULL: one workgroup per block (n_grid blocks); else one per run of <= 256 points (n_grid
+// runs, blk = -1 for padding).  kmax: largest nk of the blocks (<= kPatchMaxK; sets the dynamic
+// LDS of the coefficients)
+hipError_t launch_bt_mvb(int prec, const DevBlock* blocks, const Tile* runs, int64_t n_grid,
+                         int kmax, const void* A, const double* v, int R, const SolveState* st,
                          double* tpart, hipStream_t s, int fa = 8);
 hipError_t launch_bt_gather(const Geo* geos, const InstInfo* insts, const DevBlock* blocks,
                             const int32_t* cov, const RowTile* rt, int64_t n_rt,
