@@ -165,6 +165,45 @@ def test_patch_lsqr_iterates_and_back_to_subdomains():
         B.destroy()
 
 
+def test_patch_warm_start_from_x():
+    """A preconditioned solve over patches from x0 (in the original column order): x = x0 +
+    R^{-1} y with y from LSQR on h - M x0 over the folded patch system, equal to the oracle's
+    after 4 steps."""
+    B, oracle = _make("fp64")
+    torch = torch_mod()
+    shift = 1e-6
+    try:
+        B.precondition(shift, patch=2)
+        rng = np.random.default_rng(7)
+        x0s = [rng.standard_normal((R, len(bl) * s.K)) * 1e-2 for s, bl, _ in oracle]
+        x0 = np.zeros(R * B.sizes["n_phi"])
+        for i, ((s, bl, _), xi) in enumerate(zip(oracle, x0s)):
+            c0 = B.offsets[i][1]
+            x0[R * c0:R * c0 + xi.size] = xi.ravel()
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        infos = B.solve(coef, iter_lim=4, atol=0.0, btol=0.0, check_every=4, precond=True,
+                        x0=dev(x0))
+        cs = _coefs(B, coef, oracle)
+        worst = 0.0
+        for i, ((s, bl, h), xi) in enumerate(zip(oracle, x0s)):
+            pb = linalg.patch_blocks(bl, 2)
+            facs = linalg.block_jacobi_factors(pb, shift)
+            fold = linalg.fold_blocks(pb, facs)
+            n = len(bl) * s.K
+            for j in range(R):
+                r0 = h[j] - asm.matvec(bl, xi[j], s.n_rows)
+                res = linalg.lsqr(lambda y: linalg.patch_matvec(fold, y, s.n_rows),
+                                  lambda u: linalg.patch_rmatvec(fold, u), r0, n, atol=0, btol=0,
+                                  iter_lim=4)
+                x_ref = xi[j] + linalg.patch_recover(pb, facs, res.x)
+                worst = max(worst, np.linalg.norm(cs[i][j] - x_ref) / np.linalg.norm(x_ref))
+                assert abs(infos[i * R + j]["rnorm"] - res.rnorm) <= 1e-8 * res.rnorm
+        print(f"patch 2 warm start: worst coefficient rel diff {worst:.2e}")
+        assert worst <= 1e-8
+    finally:
+        B.destroy()
+
+
 def test_patch_mixed_refinement_matches_oracle():
     """FP64 refinement around inner LSQR on the FP32 rounding of the folded patch system: after
     1 and 2 outer steps of 5 inner steps every pair equals the oracle's refinement on its folded
