@@ -915,12 +915,18 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
   if (patch < 1 || patch > 4) return bfail(B, ELMFB_E_INVALID, "patch must be in 1..4");
   if (patch > 1 && B->coords_y)
     return bfail(B, ELMFB_E_UNSUPPORTED, "block-Jacobi coordinates are per subdomain (patch 1)");
+  // the widest patch, checked before any table or factor held is touched
+  for (const Geo& g : B->geos)
+    for (int l = 0; l < g.n_levels; ++l)
+      if ((int64_t)std::min(patch, (int)g.J[l][0]) * std::min(patch, (int)g.J[l][1]) * g.K >
+          kPatchMaxK)
+        return bfail(B, ELMFB_E_INVALID,
+                     "a patch holds more than 512 columns: take a smaller patch size");
   hipStream_t s = (hipStream_t)stream;
   auto release = [&](auto*& p) { bfree(B, p); p = nullptr; };
   if (patch > 1 && B->patch_planned != patch) {
-    // patch tables (checked before anything held is released)
     B->patch_planned = 0;
-    const std::string pe = plan_patches(B, patch);
+    const std::string pe = plan_patches(B, patch);   // cannot fail after the check above
     if (!pe.empty()) return bfail(B, ELMFB_E_INVALID, pe);
   }
   B->bj_ready = false;
@@ -988,11 +994,14 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
       put(B->d_pruns, B->pruns); put(B->d_pmvruns, B->pmvruns); put(B->d_ptasks, B->ptasks);
       put(B->d_pfoff, B->pfoff);
       put(B->d_pgoff, B->pgoff);
-      // the per-block-point partials of M V must hold the patch boxes as well
+      // the per-block-point partials of M V must hold the patch boxes as well (the larger
+      // buffer replaces the old one only once it is allocated)
       if (ea == hipSuccess && B->pn_bp > B->tpart_bp) {
-        release(B->d_tpart);
-        ea = balloc(B, &B->d_tpart, B->pn_bp * B->R * 8);
+        double* t = nullptr;
+        ea = balloc(B, &t, B->pn_bp * B->R * 8);
         if (ea == hipSuccess) {
+          release(B->d_tpart);
+          B->d_tpart = t;
           B->bytes += (B->pn_bp - B->tpart_bp) * B->R * 8;
           B->tpart_bp = B->pn_bp;
         }

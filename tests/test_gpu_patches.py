@@ -307,7 +307,8 @@ def test_patches_beat_subdomain_blocks():
 
 def test_patch_refusals():
     """Patch sizes outside 1..4, patches of more than 512 columns, and block-Jacobi coordinates
-    with patches are refused; the batch stays usable."""
+    with patches are refused; the batch stays usable, and a refused patch size leaves the
+    factors held in place."""
     spec = dataclasses.replace(configs.batch_instances(n=1, seed=5, n_rhs=R)[0][0],
                                levels=((6, 6),), K=128, n_points=(30, 30))
     B, oracle = _make("fp64", [spec])
@@ -318,6 +319,19 @@ def test_patch_refusals():
         with pytest.raises(Exception, match="512"):
             B.precondition(1e-8, patch=3)
         B.precondition(1e-8, patch=2)
+        # a refused patch size leaves the factors held untouched: solves still run on them
+        with pytest.raises(Exception, match="512"):
+            B.precondition(1e-8, patch=3)
+        assert B.patch_info()["patch"] == 2
+        torch = torch_mod()
+        coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+        infos = B.solve(coef, iter_lim=20, atol=0.0, btol=0.0, check_every=10, precond=True)
+        s_, bl, h = oracle[0]
+        for j in range(R):
+            c = coef.cpu().numpy()[j * len(bl) * s_.K:(j + 1) * len(bl) * s_.K]
+            r = np.linalg.norm(asm.matvec(bl, c, s_.n_rows) - h[j])
+            assert abs(r - infos[j]["rnorm"]) <= 1e-6 * np.linalg.norm(h[j]) + 1e-3 * r
+            assert r < np.linalg.norm(h[j])
         with pytest.raises(Exception, match="patch 1"):
             B.set_coords(True)
         B.precondition(1e-8)
