@@ -720,22 +720,26 @@ def run_copy(args):
 
 
 def _one_wg_us_per_step(P, coef, n_it, reps):
-    """Microseconds per LSQR step of the one-workgroup solve on P: n_it steps in one launch, less
-    a solve of no steps (the set-up kernels), HIP events on the stream the solve runs on."""
+    """Microseconds per LSQR step of the one-workgroup solve on P: up to n_it steps in one launch,
+    less a solve of no steps (the set-up kernels), HIP events on the stream the solve runs on,
+    divided by the steps the solve actually took (at atol = btol = 0 a small system can still end
+    early on LSQR's machine-precision tests)."""
     import torch
     stream = torch.cuda.current_stream()
 
     def timed(k):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        P.solve(coef, method="lsqr", iter_lim=k, atol=0.0, btol=0.0, check_every=max(k, 1))
+        info = P.solve(coef, method="lsqr", iter_lim=k, atol=0.0, btol=0.0, check_every=max(k, 1))
         e1.record(stream)
         e1.synchronize()
-        return e0.elapsed_time(e1)
+        return e0.elapsed_time(e1), info["iters"]
 
-    timed(n_it)
-    ms = min(timed(n_it) for _ in range(reps)) - min(timed(0) for _ in range(reps))
-    return ms, ms * 1e3 / max(n_it, 1)
+    steps = timed(n_it)[1]
+    runs = [timed(n_it) for _ in range(reps)]
+    assert all(r[1] == steps for r in runs), "the solve's step count changed between repeats"
+    ms = min(r[0] for r in runs) - min(timed(0)[0] for _ in range(reps))
+    return ms, ms * 1e3 / max(steps, 1), steps
 
 
 def run_oscillator(args):
@@ -789,13 +793,13 @@ def run_oscillator(args):
     # 3-subdomain 1D problem, 200 block points) measured alongside.
     k = info["iters"]
     reps = max(2, args.kernel_reps // 10)
-    ms_launch, us_step = _one_wg_us_per_step(P, coef, k, reps)
+    ms_launch, us_step, _ = _one_wg_us_per_step(P, coef, k, reps)
     tiny = configs.tiny1d()
     Wt, bt = feature_params(tiny)
     Pt = Problem.from_spec(tiny, Wt, bt, "fp64")
     Pt.assemble(torch.as_tensor(configs.forcing(tiny)).cuda())
     ct = torch.empty(Pt.sizes["n_phi"], dtype=torch.float64, device="cuda")
-    _, us_floor = _one_wg_us_per_step(Pt, ct, 2000, reps)
+    _, us_floor, floor_steps = _one_wg_us_per_step(Pt, ct, 2000, reps)
     Pt.destroy()
     out = {
         "metric": METRIC,
@@ -813,7 +817,8 @@ def run_oscillator(args):
                      "kernel": f"k_lsqr_persistent ({k} LSQR steps in one workgroup, the "
                                f"system's {P.sizes['nnz']} entries in LDS)",
                      "peak_meaning": "fixed cost of one step: the same kernel on the 200-point "
-                                     "3-subdomain 1D system",
+                                     f"3-subdomain 1D system ({floor_steps} steps, where its "
+                                     "solve ends)",
                      "ms_per_launch": ms_launch},
     }
     if not args.no_cpu_baseline:
