@@ -93,6 +93,20 @@ def parse():
                    help="warm workloads: held-out omegas (8 coefficient vectors each)")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run device copies of this many bytes (traffic-counter reference)")
+    p.add_argument("--write-traffic", default=None, metavar="NAME",
+                   help="host only: write profiles/traffic_NAME.json from rocprofv3 counter runs "
+                        "(--pmc-fetch/--pmc-write of the workload, --copy-fetch/--copy-write of "
+                        "`--copy-bytes 1073741824` copies) for --traffic-kernels, hashing "
+                        "--traffic-sources")
+    p.add_argument("--pmc-fetch", default=None)
+    p.add_argument("--pmc-write", default=None)
+    p.add_argument("--copy-fetch", default=None)
+    p.add_argument("--copy-write", default=None)
+    p.add_argument("--copy-ref-bytes", type=int, default=1 << 30)
+    p.add_argument("--traffic-kernels", default="",
+                   help="';'-separated kernel names as bench.py reports them, e.g. k_bt_mvb<FP32,16>")
+    p.add_argument("--traffic-sources", default="",
+                   help="','-separated source files (from the repository root) of those kernels")
     args = p.parse_args()
     args.store_given, args.inner_given = args.store, args.inner
     args.batch_btol_given = args.batch_btol
@@ -702,6 +716,89 @@ def measured_traffic(kernel, workload):
         return float(d["kernels"][kernel]["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError, TypeError):
         return None
+
+
+_PREC_NAMES = {"0": "FP64", "1": "FP32", "2": "BF16", "3": "FP16"}
+
+
+def _kernel_label(name):
+    """A rocprofv3 kernel name in the form bench.py reports it: namespace and return type
+    dropped, the precision argument of the matrix-pass templates named (k_mv_blocks<FP16,2>)."""
+    s = name.strip()
+    if s.startswith("void "):
+        s = s[5:]
+    s = s.replace("elmfb::", "")
+    base, _, rest = s.partition("<")
+    base = base.split("(")[0]
+    if not rest or "(" in base:
+        return base
+    targs = [t.strip() for t in rest.split(">")[0].split(",")]
+    if base in ("k_mv_blocks", "k_bt_mvb", "k_bt_rmvb", "k_rmv_chunks"):
+        targs[0] = _PREC_NAMES.get(targs[0], targs[0])
+        if base == "k_rmv_chunks":
+            targs = targs[:1]
+    return f"{base}<{','.join(targs)}>"
+
+
+def _counter_values(run_dir, counter):
+    """Per kernel label, the counter's value (KiB) of every dispatch in a rocprofv3 --pmc run."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.setdefault(_kernel_label(r["Kernel_Name"]), []).append(
+                        float(r["Counter_Value"]))
+    return out
+
+
+def _copy_scale(run_dir, counter, nbytes):
+    """Bytes per counted KiB, from the copy kernel's dispatches of a plain copy of nbytes (the
+    runtime's copy kernel; dispatches below a fifth of nbytes, other copies, are left out)."""
+    vals = _counter_values(run_dir, counter)
+    name, v = max(((n, v) for n, v in vals.items() if "copy" in n.lower()),
+                  key=lambda kv: max(kv[1]))
+    big = [x for x in v if x * 1024 > 0.2 * nbytes]
+    return nbytes / (sum(big) / len(big) * 1024), name
+
+
+def write_traffic(args):
+    """profiles/traffic_<name>.json: HBM bytes per dispatch of the named kernels, FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch, averaged over the run's dispatches) each scaled by what the
+    same counter reads for a plain copy of known size, with the SHA-256 of the kernels' source
+    files (read in order and concatenated) so that measured_traffic() drops them once a source
+    changes."""
+    import hashlib
+    fs, fname = _copy_scale(args.copy_fetch, "FETCH_SIZE", args.copy_ref_bytes)
+    ws, _ = _copy_scale(args.copy_write, "WRITE_SIZE", args.copy_ref_bytes)
+    F = _counter_values(args.pmc_fetch, "FETCH_SIZE")
+    W = _counter_values(args.pmc_write, "WRITE_SIZE")
+    sources = [x for x in args.traffic_sources.split(",") if x]
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    out = {"workload": args.write_traffic, "sources": sources, "source_sha256": h.hexdigest(),
+           "scale": {"fetch": fs, "write": ws, "copy_kernel": fname},
+           "unit": "bytes per dispatch (FETCH_SIZE x scale.fetch + WRITE_SIZE x scale.write)",
+           "kernels": {}}
+    for k in [x for x in args.traffic_kernels.split(";") if x]:
+        if k not in F or k not in W:
+            raise SystemExit(f"{k}: not in both counter runs (kernels seen: {sorted(F)})")
+        rd = sum(F[k]) / len(F[k]) * 1024 * fs
+        wr = sum(W[k]) / len(W[k]) * 1024 * ws
+        out["kernels"][k] = {"hbm_bytes_per_launch": rd + wr, "read_bytes": rd,
+                             "write_bytes": wr, "dispatches_fetch": len(F[k]),
+                             "dispatches_write": len(W[k])}
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.write_traffic}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def run_copy(args):
@@ -1428,6 +1525,9 @@ def run_single(args, workload, steps, warmup, secondary=False):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: run with --gpus 1 (the multi-GPU "
                                    "sharding is a design only)"}))

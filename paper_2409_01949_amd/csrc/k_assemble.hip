@@ -89,21 +89,6 @@ __device__ __forceinline__ void l_envelope(const Geo& g, int l, int ix, int iy, 
   LP = Pxx + Pyy;
 }
 
-template <int PREC>
-__device__ __forceinline__ void store_entry(void* A, int64_t i, double v);
-template <>
-__device__ __forceinline__ void store_entry<ELMFB_FP32>(void* A, int64_t i, double v) {
-  static_cast<float*>(A)[i] = (float)v;   // IEEE round-to-nearest-even
-}
-template <>
-__device__ __forceinline__ void store_entry<ELMFB_BF16>(void* A, int64_t i, double v) {
-  static_cast<uint16_t*>(A)[i] = f64_to_bf16_rne(v);
-}
-template <>
-__device__ __forceinline__ void store_entry<ELMFB_FP16>(void* A, int64_t i, double v) {
-  static_cast<uint16_t*>(A)[i] = f64_to_fp16_rne(v);
-}
-
 // One workgroup per tile of <= 256 points of one block; one thread per point, looping over K.
 // LO < 0: FP64 matrix only; LO = FP32 / BF16 / FP16: also its rounded copy.
 template <int LO, int OP>
@@ -119,18 +104,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
   const DevBlock B = blocks[t.blk];
   const int K = g.K;
   const int l = B.level;
-  const double sx = feat_div(g, l, 0), sy = feat_div(g, l, 1);
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double w1 = W[2 * (int64_t)(B.q0 + k)];
-    const double w2 = (g.dim == 2) ? W[2 * (int64_t)(B.q0 + k) + 1] : 0.0;
-    const double c1 = w1 / sx, c2 = (g.dim == 2) ? w2 / sy : 0.0;
-    w1s[k] = w1;
-    w2s[k] = w2;
-    c1s[k] = c1;
-    c2s[k] = c2;
-    c3s[k] = c1 * c1 + c2 * c2;
-    bs[k] = bias[B.q0 + k];
-  }
+  stage_block_features(g, l, B.q0, K, W, bias, w1s, w2s, c1s, c2s, c3s, bs);
   __syncthreads();
   const int p = t.p0 + threadIdx.x;
   if (p >= B.n) return;
@@ -161,23 +135,7 @@ __global__ void __launch_bounds__(256) k_assemble(Geo g, const DevBlock* __restr
     const double z = w1s[k] * xb + w2s[k] * yb + bs[k];
     const double ph = tanh(z);
     const double sd = 1.0 - ph * ph;
-    double v;
-    if (OP == ELMFB_OP_NEG_LAPLACE) {
-      v = -(LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k]);
-    } else if (OP == ELMFB_OP_D1) {
-      v = Px * ph + P * sd * c1s[k];
-    } else if (OP == ELMFB_OP_OSCILLATOR) {
-      // m (P phi)'' + mu (P phi)' + k P phi in 1D (LP = P'', c3 = (W/sigma)^2)
-      const double d2 = LP * ph + 2.0 * sd * Px * c1s[k] - 2.0 * P * ph * sd * c3s[k];
-      const double d1 = Px * ph + P * sd * c1s[k];
-      v = g.op_coef[0] * d2 + g.op_coef[1] * d1 + g.op_coef[2] * P * ph;
-    } else if (OP == ELMFB_OP_HELMHOLTZ) {
-      // Lap(P phi) + k^2 P phi (k^2 = op_coef[0])
-      v = LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k] +
-          g.op_coef[0] * P * ph;
-    } else {
-      v = P * ph;
-    }
+    const double v = operator_entry(OP, g.op_coef, P, Px, Py, LP, ph, sd, c1s[k], c2s[k], c3s[k]);
     const double e = outside ? 0.0 : v * scale;
     A[base + (int64_t)k * ld] = e;
     if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * ld, e);

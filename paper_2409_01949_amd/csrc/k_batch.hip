@@ -43,18 +43,7 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
   const Geo& g = geos[B.inst];
   const int K = g.K;
   const int l = B.level;
-  const double sx = feat_div(g, l, 0), sy = feat_div(g, l, 1);
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double w1 = W[2 * (int64_t)(B.q0 + k)];
-    const double w2 = (g.dim == 2) ? W[2 * (int64_t)(B.q0 + k) + 1] : 0.0;
-    const double c1 = w1 / sx, c2 = (g.dim == 2) ? w2 / sy : 0.0;
-    w1s[k] = w1;
-    w2s[k] = w2;
-    c1s[k] = c1;
-    c2s[k] = c2;
-    c3s[k] = c1 * c1 + c2 * c2;
-    bs[k] = bias[B.q0 + k];
-  }
+  stage_block_features(g, l, B.q0, K, W, bias, w1s, w2s, c1s, c2s, c3s, bs);
   __syncthreads();
   const int p = t.p0 + threadIdx.x;
   if (p >= B.n) return;
@@ -77,20 +66,10 @@ __global__ void __launch_bounds__(256) k_bt_assemble(const Geo* __restrict__ geo
     const double z = w1s[k] * xb + w2s[k] * yb + bs[k];
     const double ph = tanh(z);
     const double sd = 1.0 - ph * ph;
-    double v;
-    if (op == ELMFB_OP_NEG_LAPLACE)
-      v = -(LP * ph + 2.0 * sd * (Px * c1s[k] + Py * c2s[k]) - 2.0 * P * ph * sd * c3s[k]);
-    else if (op == ELMFB_OP_D1)
-      v = Px * ph + P * sd * c1s[k];
-    else
-      v = P * ph;
-    const double e = v * scale;
+    const double e =
+        operator_entry(op, g.op_coef, P, Px, Py, LP, ph, sd, c1s[k], c2s[k], c3s[k]) * scale;
     A[base + (int64_t)k * ld] = e;
-    if constexpr (LO == ELMFB_FP32) static_cast<float*>(A_lo)[base + (int64_t)k * ld] = (float)e;
-    if constexpr (LO == ELMFB_BF16)
-      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * ld] = f64_to_bf16_rne(e);
-    if constexpr (LO == ELMFB_FP16)
-      static_cast<uint16_t*>(A_lo)[base + (int64_t)k * ld] = f64_to_fp16_rne(e);
+    if constexpr (LO >= 0) store_entry<LO>(A_lo, base + (int64_t)k * ld, e);
   }
 }
 
