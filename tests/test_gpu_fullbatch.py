@@ -140,3 +140,55 @@ def test_full_batch_block_jacobi_and_refinement(full_batch):
             r = np.linalg.norm(h[j] - asm.matvec(bl, ci[j], s.n_rows))
             assert abs(infos[i * R + j]["rnorm"] - r) <= 1e-9 * np.linalg.norm(h[j]), (i, j)
             assert r < np.linalg.norm(h[j])
+
+
+def test_full_batch_patches(full_batch):
+    """The benchmark's preconditioner: block-Jacobi over 2 x 2 patches of all 512 instances
+    (shift 1e-6).  For the sampled instances the column order of the patch system equals the
+    oracle's, 5 preconditioned LSQR steps on the FP64 folded patch matrix give the oracle's
+    coefficients (x = R^{-1} y in the original column order) to 1e-8 and its ||r|| to 1e-8, and
+    the FP64 refinement on the FP32 folded copy reports for every sampled pair the residual
+    ||h - M c|| that the oracle's products give for the returned coefficients (1e-9 of ||h||)."""
+    B, specs, oracle = full_batch
+    torch = torch_mod()
+    shift, P = 1e-6, 2
+    print("# full batch: 2 x 2 patch preconditioner", flush=True)
+    assert B.precondition(shift, patch=P) == 0
+    info = B.patch_info(perm=True)
+    assert info["patch"] == P
+    pbs = {}
+    for i, (s, bl, _) in oracle.items():
+        pbs[i] = linalg.patch_blocks(bl, P)
+        c0 = B.offsets[i][1]
+        n = len(bl) * s.K
+        np.testing.assert_array_equal(info["perm"][c0:c0 + n] - c0, linalg.patch_order(pbs[i]))
+    coef = torch.empty(R * B.sizes["n_phi"], dtype=torch.float64, device="cuda")
+    infos = B.solve(coef, iter_lim=5, atol=0.0, btol=0.0, check_every=5, precond=True)
+    ch = coef.cpu().numpy()
+    worst = 0.0
+    for i, (s, bl, h) in oracle.items():
+        n = len(bl) * s.K
+        pb = pbs[i]
+        facs = linalg.block_jacobi_factors(pb, shift)
+        fold = linalg.fold_blocks(pb, facs)
+        ci = _slice(B, ch, i, n)
+        for j in range(R):
+            res = linalg.lsqr(lambda y: linalg.patch_matvec(fold, y, s.n_rows),
+                              lambda u: linalg.patch_rmatvec(fold, u), h[j], n,
+                              atol=0, btol=0, iter_lim=5)
+            x_ref = linalg.patch_recover(pb, facs, res.x)
+            worst = max(worst, _rel(ci[j], x_ref))
+            assert infos[i * R + j]["iters"] == 5
+            assert abs(infos[i * R + j]["rnorm"] - res.rnorm) <= 1e-8 * res.rnorm, (i, j)
+    print(f"full batch patch-2 lsqr k=5: worst coefficient rel diff {worst:.2e}")
+    assert worst <= 1e-8
+    infos = B.solve(coef, method="mixed_ir", inner_iters=5, outer_lim=2, check_every=5,
+                    precond=True, atol=0.0, btol=0.0)
+    ch = coef.cpu().numpy()
+    for i, (s, bl, h) in oracle.items():
+        n = len(bl) * s.K
+        ci = _slice(B, ch, i, n)
+        for j in range(R):
+            r = np.linalg.norm(h[j] - asm.matvec(bl, ci[j], s.n_rows))
+            assert abs(infos[i * R + j]["rnorm"] - r) <= 1e-9 * np.linalg.norm(h[j]), (i, j)
+            assert r < np.linalg.norm(h[j])
