@@ -107,6 +107,8 @@ def parse():
                    help="';'-separated kernel names as bench.py reports them, e.g. k_bt_mvb<FP32,16>")
     p.add_argument("--traffic-sources", default="",
                    help="','-separated source files (from the repository root) of those kernels")
+    p.add_argument("--traffic-out", default=None,
+                   help="where --write-traffic writes (default profiles/traffic_NAME.json)")
     args = p.parse_args()
     args.store_given, args.inner_given = args.store, args.inner
     args.batch_btol_given = args.batch_btol
@@ -795,7 +797,7 @@ def write_traffic(args):
         out["kernels"][k] = {"hbm_bytes_per_launch": rd + wr, "read_bytes": rd,
                              "write_bytes": wr, "dispatches_fetch": len(F[k]),
                              "dispatches_write": len(W[k])}
-    path = os.path.join(ROOT, "profiles", f"traffic_{args.write_traffic}.json")
+    path = args.traffic_out or os.path.join(ROOT, "profiles", f"traffic_{args.write_traffic}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
