@@ -930,7 +930,13 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
     if (!pe.empty()) return bfail(B, ELMFB_E_INVALID, pe);
   }
   B->bj_ready = false;
-  B->bytes -= factor_bytes(B);
+  // device bytes held for factors and folded copies: settled on every exit, error returns
+  // included (storage may be released or allocated before a later step fails)
+  struct FactorBytes {
+    elmfb_batch b;
+    int64_t before;
+    ~FactorBytes() { b->bytes += factor_bytes(b) - before; }
+  } factor_guard{B, factor_bytes(B)};
   // the factors of one patch size at a time: release the other kind's storage
   if (patch == 1) {
     release(B->d_pAhat); release(B->d_prc); release(B->d_plo);
@@ -1058,7 +1064,6 @@ elmfb_status elmfb_batch_precondition_patches(elmfb_batch B, double shift, int32
     BHIP(B, e);
     B->lo_hat = false;   // the low-precision copy of M itself is untouched
   }
-  B->bytes += factor_bytes(B);
   if (n_fallback_host) *n_fallback_host = nfail;
   B->patch = patch;
   B->bj_ready = true;

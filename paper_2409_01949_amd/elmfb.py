@@ -556,6 +556,16 @@ class Batch:
             msg = _lib.elmfb_batch_last_error(self.h)
             raise ElmfbError(code, msg.decode() if msg else "")
 
+    def query(self):
+        """Totals over the batch as they stand (bytes_device changes as factors are formed);
+        also refreshes self.sizes."""
+        offs = np.zeros((self.n + 1, 2), dtype=np.int64)
+        tot = Sizes()
+        self._check(_lib.elmfb_batch_query(self.h, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           ctypes.byref(tot)))
+        self.sizes = {n: getattr(tot, n) for n, _ in Sizes._fields_}
+        return dict(self.sizes)
+
     def assemble(self, f, stream=None):
         self._check(_lib.elmfb_batch_assemble(self.h, _ptr(f), _stream(stream)))
 

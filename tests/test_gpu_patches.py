@@ -341,3 +341,33 @@ def test_patch_refusals():
         B.set_coords(False)
     finally:
         B.destroy()
+
+
+def test_patch_device_bytes():
+    """bytes_device follows the factors held: switching between patch sizes 1 and 2 returns the
+    same figure for the same size each time, each at least the folded copies' entries (FP64
+    plus the FP32 copy for patches; the per-subdomain fold rounds into the FP32 copy of M in
+    place), and a refused call leaves it unchanged."""
+    B, _ = _make("fp32")
+    try:
+        base = B.query()["bytes_device"]
+        B.precondition(1e-6, patch=2)   # the first patch plan also widens the M V partials
+        seen = {}
+        for P in (1, 2, 1, 2):
+            B.precondition(1e-6, patch=P)
+            b = B.query()["bytes_device"]
+            seen.setdefault(P, b)
+            assert b == seen[P], (P, b, seen)
+        with pytest.raises(Exception, match="patch"):
+            B.precondition(1e-6, patch=5)
+        assert B.query()["bytes_device"] == seen[2]
+        B.precondition(1e-6, patch=1)
+        e1 = B.patch_info()["n_entries"]
+        B.precondition(1e-6, patch=2)
+        e2 = B.patch_info()["n_entries"]
+        assert seen[1] - base >= 8 * e1
+        assert seen[2] - base >= 12 * e2
+        print(f"bytes_device: patch 1 {seen[1]:,}, patch 2 {seen[2]:,} "
+              f"({e1:,} / {e2:,} folded entries)")
+    finally:
+        B.destroy()
